@@ -1,0 +1,737 @@
+// ck_oracle.cpp -- reference model of a bucketized / d-ary cuckoo hash table
+// with the kick-out eviction schemes of Kuszmaul, "Fast Concurrent Cuckoo
+// Kick-out Eviction Schemes for High-Density Tables" (arXiv 1605.05236).
+//
+// TEST INFRASTRUCTURE ONLY.  This file is the oracle against which the GPU
+// library is checked.  It is plain, single-threaded and deliberately slow:
+// every algorithm is written as the paper states it, step by step, against a
+// copy-on-write "draft" of the bins it touches.  It shares no code, header,
+// constant table or helper with the GPU library, and the GPU library never
+// calls it.  Only the tests, the smoke check and the CPU-baseline leg of the
+// benchmark load it.
+//
+// Where the paper is silent or ambiguous the readings taken are listed in the
+// repository's design notes; each is also stated next to the code below.
+//
+// Paper map:
+//   Sec. 1  (Introduction)         two distinct bins per key, first-fit insert,
+//                                  kick-out chains, constant-time lookup/delete.
+//   Sec. 2  (Past work)            load balancing (insert into the less full bin).
+//   Sec. 3  (Experimental setup)   uniformly random hashes; inserted keys are
+//                                  assumed absent; cost = bins viewed per insert.
+//   Sec. 4  (Ghost insertions)     duplicates in both bins; Proposition 4.1.
+//   Sec. 5  (Sorted search)        BFS over records; spawn-count ordering with
+//                                  16 buckets; visited-bin set; Theorem 5.1.
+//   Sec. 6  (Queue-kicking)        FIFO victims via per-bin hit counters; hit
+//                                  balancing; fetch-and-add slot scheduling.
+//   Sec. 7  (Rattle-kicking)       d-ary tables, per-key rattle counters.
+//   Sec. 8.2 (Mechanisms)          reverse-order ("system transaction") kick-out
+//                                  chains; claims on every bin a plan writes.
+//
+// Parity status: every function here is pinned by the CPU tests (invariants,
+// brute force, textbook dictionary semantics, closed forms and the paper's
+// quoted statistics); see the test files for which pin covers which function.
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <set>
+#include <vector>
+
+namespace {
+
+constexpr uint64_t kEmpty = ~0ull;  // reserved key marking an empty slot
+constexpr int kBands = 200;         // 0.5 % density bands
+
+enum Scheme { RANDOM_WALK = 0, BFS = 1, SORTED = 2, QUEUE = 3, RATTLE = 4 };
+enum OpStatus { ST_NOT_FOUND = 0, ST_OK = 1, ST_FAIL = 2, ST_ABORTED = 3, ST_BAD_KEY = 4 };
+
+// ---------------------------------------------------------------------------
+// splitmix64 (Steele, Lea, Flood 2014): state advances by the golden-ratio
+// increment and each output is the state passed through the mixing function.
+// Used (a) to derive the hash multipliers from the hash seed and (b) as the
+// counter-based generator behind the random walk's choices.
+// ---------------------------------------------------------------------------
+uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+uint64_t splitmix_next(uint64_t& state) {
+  state += 0x9E3779B97F4A7C15ull;
+  return mix64(state);
+}
+
+// Uniform choice in [0, m) from a 64-bit word: floor(r * m / 2^64).
+uint64_t scale(uint64_t r, uint64_t m) {
+  return (uint64_t)(((unsigned __int128)r * m) >> 64);
+}
+
+struct Slot {
+  uint64_t key = kEmpty;
+  uint64_t val = 0;
+  uint16_t rattle = 0;  // rattle counter r(x) of the stored key (Sec. 7)
+};
+
+// The state of one bin: its B slots plus the per-bin metadata the schemes
+// keep: duplicate marks (Sec. 4), hit counter (Sec. 6), spawn count (Sec. 5).
+struct BinState {
+  Slot s[8];
+  uint8_t dup = 0;  // bit i set: slot i holds a ghost duplicate
+  uint8_t hc = 0;   // hit counter, one byte, wraps (Sec. 6 footnote)
+  uint8_t sc = 0;   // spawn count, capped at 15 (four bits, Sec. 5)
+};
+
+struct Params {
+  uint64_t n;        // bins
+  int B;             // slots per bin
+  int H;             // hash functions
+  int scheme;
+  int ghost;
+  int load_balance;  // fresh insert into the less full bin (Sec. 2)
+  uint32_t max_chain, max_search, max_rounds, batch_ops;
+  uint64_t hash_seed, rng_seed;
+};
+
+struct Stats {
+  uint64_t inserts_ok, inserts_failed, inserts_aborted, inserts_bad_key;
+  uint64_t views, views_all, kicks, max_kicks, retries, rounds, twin_updates;
+  uint64_t lookups, lookup_hits, lookup_probes;
+  uint64_t deletes, deletes_found, delete_probes, delete_retries;
+  uint64_t stored;
+  uint64_t band_inserts[kBands], band_views[kBands], band_kicks[kBands], band_fails[kBands];
+};
+
+struct Table {
+  Params p;
+  uint64_t a[4], c[4];          // hash multipliers and offsets
+  std::vector<BinState> bins;
+  uint64_t insert_count = 0;    // global index of the next insert op
+  Stats st;
+
+  BinState bin(uint64_t b) const { return bins[b]; }
+
+  // Bin indices of key x (reading of Sec. 1 / Sec. 3): H distinct bins.
+  // h_i(x) = floor(((a_i x + c_i) mod 2^64) * n / 2^64); a clash with an
+  // earlier h_j is resolved by stepping to the next bin modulo n.
+  void hash(uint64_t x, uint64_t* out) const {
+    for (int i = 0; i < p.H; ++i) {
+      uint64_t z = a[i] * x + c[i];
+      uint64_t h = scale(z, p.n);
+      bool clash = true;
+      while (clash) {
+        clash = false;
+        for (int j = 0; j < i; ++j)
+          if (out[j] == h) clash = true;
+        if (clash) h = (h + 1) % p.n;
+      }
+      out[i] = h;
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// A plan: the algorithm run against a copy-on-write draft of the table.
+// Reads see the draft where the plan has already written, else the table.
+// The set of drafted bins is the plan's write set W (every bin whose slots,
+// duplicate marks or hit counter the plan writes).  Spawn-count increments
+// are collected separately: they are not writes to W (they are applied by
+// every plan, including plans that fail or lose a claim).
+// ---------------------------------------------------------------------------
+struct Plan {
+  const Table& T;
+  uint64_t op;  // global insert index, keys the random choices
+  uint32_t draws = 0;
+  std::map<uint64_t, BinState> draft;
+  std::vector<uint64_t> spawns;
+  uint32_t views = 0, kicks = 0, twins = 0;
+  int status = ST_FAIL;
+
+  Plan(const Table& t, uint64_t op_) : T(t), op(op_) {}
+
+  BinState read(uint64_t b) const {
+    auto it = draft.find(b);
+    return it != draft.end() ? it->second : T.bin(b);
+  }
+  BinState& write(uint64_t b) {
+    auto it = draft.find(b);
+    if (it == draft.end()) it = draft.emplace(b, T.bin(b)).first;
+    return it->second;
+  }
+  // Reading a bin's slots to decide something: one bin viewed (Sec. 3).
+  BinState view(uint64_t b) {
+    ++views;
+    return read(b);
+  }
+
+  // Counter-based random draw t of this plan: mix64(seed ^ op*phi ^ (t+1)).
+  // A uniform choice among m > 1 options consumes one draw; m == 1 none.
+  uint64_t uniform(uint64_t m) {
+    if (m <= 1) return 0;
+    uint64_t r = mix64(T.p.rng_seed ^ (op * 0x9E3779B97F4A7C15ull) ^ (uint64_t)(draws + 1));
+    ++draws;
+    return scale(r, m);
+  }
+
+  int first_empty(const BinState& s) const {
+    for (int i = 0; i < T.p.B; ++i)
+      if (s.s[i].key == kEmpty) return i;
+    return -1;
+  }
+  int first_dup(const BinState& s) const {
+    for (int i = 0; i < T.p.B; ++i)
+      if (s.s[i].key != kEmpty && ((s.dup >> i) & 1)) return i;
+    return -1;
+  }
+  int occupancy(const BinState& s) const {
+    int o = 0;
+    for (int i = 0; i < T.p.B; ++i) o += s.s[i].key != kEmpty;
+    return o;
+  }
+  // A bin ends a kick-out chain if it has a free slot, or, with ghost
+  // insertions, a duplicate that can be dropped (Sec. 4).
+  bool terminal(const BinState& s) const {
+    return first_empty(s) >= 0 || (T.p.ghost && first_dup(s) >= 0);
+  }
+
+  // The key's bins other than `cur`, in hash order.
+  std::vector<uint64_t> others(uint64_t key, uint64_t cur) const {
+    uint64_t h[4];
+    T.hash(key, h);
+    std::vector<uint64_t> o;
+    for (int i = 0; i < T.p.H; ++i)
+      if (h[i] != cur) o.push_back(h[i]);
+    return o;
+  }
+
+  // Store `rec` in slot i of bin b.  `as_dup` marks a ghost copy.  With the
+  // queue scheme every insertion into a bin advances its hit counter (Sec. 6).
+  void put(uint64_t b, int i, const Slot& rec, bool as_dup) {
+    BinState& s = write(b);
+    s.s[i] = rec;
+    if (T.p.B == 1) s.s[i].val &= 0xFFFFFFFFull;  // single-slot bins keep 32-bit values
+    if (as_dup) s.dup |= (uint8_t)(1u << i);
+    else s.dup &= (uint8_t)~(1u << i);
+    if (T.p.scheme == QUEUE) s.hc = (uint8_t)(s.hc + 1);
+  }
+
+  // Overwrite the duplicate in slot i of bin b: the other copy of that key,
+  // in its other bin, stops being a duplicate (Sec. 4).  Reading the twin's
+  // bin to find the copy is bookkeeping, not a bin viewed.
+  void replace_dup(uint64_t b, int i, const Slot& rec) {
+    uint64_t k = read(b).s[i].key;
+    uint64_t tb = others(k, b)[0];
+    BinState tw = read(tb);
+    int ti = -1;
+    for (int j = 0; j < T.p.B; ++j)
+      if (tw.s[j].key == k) ti = j;
+    write(tb).dup &= (uint8_t)~(1u << ti);
+    ++twins;
+    put(b, i, rec, false);
+  }
+
+  // Place `rec` into a terminal bin: a free slot first, else a duplicate.
+  void place_terminal(uint64_t b, const Slot& rec) {
+    BinState s = read(b);
+    int e = first_empty(s);
+    if (e >= 0) put(b, e, rec, false);
+    else replace_dup(b, first_dup(s), rec);
+  }
+
+  // ---- The fresh insert, before any eviction (Sec. 1, 2, 4). -----------------
+  // Returns true when the record was placed without a kick-out.
+  bool place_fresh(const Slot& x, const uint64_t* h) {
+    const Params& P = T.p;
+    if (P.ghost) {
+      // Ghost insertion (Sec. 4): both bins viewed; room in both -> a
+      // duplicate copy in each; room in one -> there; else reuse a duplicate.
+      BinState s0 = view(h[0]), s1 = view(h[1]);
+      int e0 = first_empty(s0), e1 = first_empty(s1);
+      if (e0 >= 0 && e1 >= 0) {
+        put(h[0], e0, x, true);
+        put(h[1], e1, x, true);
+        return true;
+      }
+      if (e0 >= 0) { put(h[0], e0, x, false); return true; }
+      if (e1 >= 0) { put(h[1], e1, x, false); return true; }
+      int d0 = first_dup(s0);
+      if (d0 >= 0) { replace_dup(h[0], d0, x); return true; }
+      int d1 = first_dup(s1);
+      if (d1 >= 0) { replace_dup(h[1], d1, x); return true; }
+      return false;
+    }
+    if (P.load_balance || P.scheme == QUEUE) {
+      // Load balancing (Sec. 2): view both, insert into the less full one.
+      BinState s0 = view(h[0]), s1 = view(h[1]);
+      int o0 = occupancy(s0), o1 = occupancy(s1);
+      if (o0 < P.B || o1 < P.B) {
+        uint64_t t = o0 <= o1 ? h[0] : h[1];
+        put(t, first_empty(read(t)), x, false);
+        return true;
+      }
+      return false;
+    }
+    // First fit (Sec. 1): look through the bins in hash order.
+    for (int i = 0; i < P.H; ++i) {
+      BinState s = view(h[i]);
+      int e = first_empty(s);
+      if (e >= 0) { put(h[i], e, x, false); return true; }
+    }
+    return false;
+  }
+
+  // ---- Random kicking (Sec. 1, Sec. 6 opening) --------------------------------
+  void random_walk(const Slot& x, const uint64_t* h) {
+    if (place_fresh(x, h)) { status = ST_OK; return; }
+    uint64_t cur = h[uniform(T.p.H)];  // pick one of the key's bins
+    Slot carry = x;
+    for (;;) {
+      if (kicks == T.p.max_chain) { status = ST_FAIL; return; }
+      int i = (int)uniform(T.p.B);      // a random victim in it
+      Slot victim = read(cur).s[i];
+      put(cur, i, carry, false);
+      ++kicks;
+      carry = victim;
+      std::vector<uint64_t> o = others(carry.key, cur);
+      cur = o[uniform(o.size())];       // the victim goes to one of its other bins
+      if (terminal(view(cur))) {
+        place_terminal(cur, carry);
+        status = ST_OK;
+        return;
+      }
+    }
+  }
+
+  // ---- Queue-kicking with hit counters and hit balancing (Sec. 6) ---------------
+  void queue_kick(const Slot& x, const uint64_t* h) {
+    if (place_fresh(x, h)) { status = ST_OK; return; }
+    // Both bins full: hit balancing picks the bin with the smaller counter.
+    uint64_t t = read(h[0]).hc <= read(h[1]).hc ? h[0] : h[1];
+    Slot carry = x;
+    for (;;) {
+      if (kicks == T.p.max_chain) { status = ST_FAIL; return; }
+      // The record goes to slot (hit counter mod B), evicting the occupant;
+      // with no deletes that occupant is the bin's oldest record.
+      BinState s = read(t);
+      int i = s.hc % T.p.B;
+      Slot victim = s.s[i];
+      put(t, i, carry, false);
+      ++kicks;
+      carry = victim;
+      t = others(carry.key, t)[0];
+      if (terminal(view(t))) {
+        place_terminal(t, carry);
+        status = ST_OK;
+        return;
+      }
+    }
+  }
+
+  // ---- Breadth-first search and sorted search (Sec. 5) --------------------------
+  // The search state is a list of records viewed but not yet spawned.  BFS
+  // spawns them in FIFO order; sorted search spawns the one whose bin has the
+  // smallest spawn count, kept as 16 FIFO buckets (bucket sort) keyed by the
+  // capped spawn count read when the record enters the list.  Bins already
+  // visited by this search are never viewed again.
+  struct Entry {
+    uint64_t bin;
+    int slot;
+    int parent;  // index into `entries`, -1 for the records of the key's own bins
+  };
+  void search(const Slot& x, const uint64_t* h, bool sorted) {
+    if (place_fresh(x, h)) { status = ST_OK; return; }
+    std::vector<Entry> entries;
+    std::deque<int> bucket[16];
+    std::set<uint64_t> visited;
+    auto enqueue_bin = [&](uint64_t b, int parent) {
+      BinState s = read(b);
+      int key = sorted ? std::min<int>(15, s.sc) : 0;
+      for (int i = 0; i < T.p.B; ++i) {
+        entries.push_back({b, i, parent});
+        bucket[key].push_back((int)entries.size() - 1);
+      }
+    };
+    for (int i = 0; i < T.p.H; ++i) {
+      visited.insert(h[i]);
+      enqueue_bin(h[i], -1);
+    }
+    for (;;) {
+      int k = 0;
+      while (k < 16 && bucket[k].empty()) ++k;
+      if (k == 16) { status = ST_FAIL; return; }  // nothing left to spawn
+      int e = bucket[k].front();
+      bucket[k].pop_front();
+      Entry en = entries[e];
+      Slot rec = read(en.bin).s[en.slot];
+      bool spawned = false;
+      for (uint64_t child : others(rec.key, en.bin)) {
+        if (visited.count(child)) continue;
+        if (views == T.p.max_search) { status = ST_FAIL; return; }
+        if (!spawned && sorted) spawns.push_back(en.bin);
+        spawned = true;
+        visited.insert(child);
+        if (terminal(view(child))) {
+          // Found: shift each record on the path one hop toward the free
+          // slot, starting from the end of the chain (Sec. 8.2).
+          place_terminal(child, rec);
+          ++kicks;
+          int cur = e;
+          while (entries[cur].parent >= 0) {
+            int par = entries[cur].parent;
+            put(entries[cur].bin, entries[cur].slot, read(entries[par].bin).s[entries[par].slot], false);
+            ++kicks;
+            cur = par;
+          }
+          put(entries[cur].bin, entries[cur].slot, x, false);
+          status = ST_OK;
+          return;
+        }
+        enqueue_bin(child, e);
+      }
+    }
+  }
+
+  // ---- Rattle-kicking for d-ary tables with single-slot bins (Sec. 7) -----------
+  // A key x carries a counter r(x), incremented on every try; it tries bin
+  // h_{r mod d}.  Against an occupant y the larger counter keeps the bin (the
+  // occupant on a tie) and the other key moves on.
+  void rattle(const Slot& x, const uint64_t* h) {
+    (void)h;
+    Slot carry = x;
+    carry.rattle = 0;
+    uint32_t tries = 0;
+    for (;;) {
+      if (tries == T.p.max_chain) { status = ST_FAIL; return; }
+      uint64_t hh[4];
+      T.hash(carry.key, hh);
+      uint64_t b = hh[carry.rattle % T.p.H];
+      carry.rattle = (uint16_t)(carry.rattle + 1);
+      ++tries;
+      BinState s = view(b);
+      if (s.s[0].key == kEmpty) {
+        put(b, 0, carry, false);
+        status = ST_OK;
+        return;
+      }
+      Slot y = s.s[0];
+      if (carry.rattle > y.rattle) {
+        put(b, 0, carry, false);
+        ++kicks;
+        carry = y;
+      }
+    }
+  }
+};
+
+Plan plan_insert(const Table& T, uint64_t op, uint64_t key, uint64_t val) {
+  Plan pl(T, op);
+  Slot x;
+  x.key = key;
+  x.val = val;
+  uint64_t h[4];
+  T.hash(key, h);
+  switch (T.p.scheme) {
+    case RANDOM_WALK: pl.random_walk(x, h); break;
+    case BFS: pl.search(x, h, false); break;
+    case SORTED: pl.search(x, h, true); break;
+    case QUEUE: pl.queue_kick(x, h); break;
+    case RATTLE: pl.rattle(x, h); break;
+  }
+  if (pl.status != ST_OK) {  // a failed plan writes nothing (table unchanged)
+    pl.draft.clear();
+    pl.kicks = 0;
+    pl.twins = 0;
+  }
+  return pl;
+}
+
+// Delete (Sec. 1): find the key in its bins and empty every slot holding it,
+// both copies of a ghost duplicate included.  Counters are left unchanged.
+Plan plan_delete(const Table& T, uint64_t key, uint32_t* probes) {
+  Plan pl(T, 0);
+  uint64_t h[4];
+  T.hash(key, h);
+  pl.status = ST_NOT_FOUND;
+  *probes = 0;
+  for (int i = 0; i < T.p.H; ++i) {
+    BinState s = pl.read(h[i]);
+    ++*probes;
+    for (int j = 0; j < T.p.B; ++j) {
+      if (s.s[j].key != key) continue;
+      bool was_dup = (s.dup >> j) & 1;
+      BinState& w = pl.write(h[i]);
+      w.s[j] = Slot();
+      w.dup &= (uint8_t)~(1u << j);
+      if (was_dup) {
+        uint64_t tb = h[1 - i];
+        BinState t = pl.read(tb);
+        ++*probes;
+        for (int k = 0; k < T.p.B; ++k)
+          if (t.s[k].key == key) {
+            BinState& tw = pl.write(tb);
+            tw.s[k] = Slot();
+            tw.dup &= (uint8_t)~(1u << k);
+          }
+      }
+      pl.status = ST_OK;
+      return pl;
+    }
+  }
+  return pl;
+}
+
+// ---- Deterministic phased rounds ------------------------------------------------
+// Every pending op plans against the same snapshot; each plan claims the bins
+// it writes, lowest op index winning a bin; a plan that owns all its bins is
+// applied (its writes land on exactly the contents it read), the others try
+// again next round.  Spawn-count increments of all plans are added with
+// saturation at 15 after each round.  A sub-batch of one op is the serial
+// algorithm.
+struct OpResult {
+  int status = ST_FAIL;
+  uint32_t views = 0, kicks = 0, twins = 0, retries = 0, views_all = 0;
+};
+
+template <class PlanFn>
+uint32_t run_rounds(Table& T, const std::vector<uint64_t>& ids, PlanFn plan_fn,
+                    std::vector<OpResult>& res) {
+  std::vector<uint64_t> pending = ids;  // batch-relative op indices in op order
+  uint32_t round = 0;
+  while (!pending.empty()) {
+    std::vector<Plan> plans;
+    plans.reserve(pending.size());
+    for (uint64_t i : pending) plans.push_back(plan_fn(i));
+    // Claims: the lowest op index that writes a bin owns it this round.
+    std::map<uint64_t, uint64_t> owner;
+    for (size_t k = 0; k < plans.size(); ++k)
+      for (auto& kv : plans[k].draft) {
+        auto it = owner.find(kv.first);
+        if (it == owner.end() || pending[k] < it->second) owner[kv.first] = pending[k];
+      }
+    std::vector<uint64_t> next;
+    for (size_t k = 0; k < plans.size(); ++k) {
+      uint64_t i = pending[k];
+      bool wins = true;
+      for (auto& kv : plans[k].draft)
+        if (owner[kv.first] != i) wins = false;
+      res[i].views_all += plans[k].views;
+      if (wins) {
+        for (auto& kv : plans[k].draft) {
+          BinState nb = kv.second;
+          nb.sc = T.bins[kv.first].sc;  // spawn counts are merged below
+          T.bins[kv.first] = nb;
+        }
+        res[i].status = plans[k].status;
+        res[i].views = plans[k].views;
+        res[i].kicks = plans[k].kicks;
+        res[i].twins = plans[k].twins;
+      } else {
+        ++res[i].retries;
+        if (T.p.max_rounds && res[i].retries >= T.p.max_rounds) res[i].status = ST_ABORTED;
+        else next.push_back(i);
+      }
+    }
+    for (auto& pl : plans)
+      for (uint64_t b : pl.spawns) T.bins[b].sc = (uint8_t)std::min(15, T.bins[b].sc + 1);
+    ++round;
+    pending.swap(next);
+  }
+  return round;
+}
+
+}  // namespace
+
+// ============================================================================
+// C interface for the test harness (ctypes).
+// ============================================================================
+extern "C" {
+
+struct ck_oracle_stats_t {
+  uint64_t inserts_ok, inserts_failed, inserts_aborted, inserts_bad_key;
+  uint64_t views, views_all, kicks, max_kicks, retries, rounds, twin_updates;
+  uint64_t lookups, lookup_hits, lookup_probes;
+  uint64_t deletes, deletes_found, delete_probes, delete_retries;
+  uint64_t stored;
+  uint64_t band_inserts[kBands], band_views[kBands], band_kicks[kBands], band_fails[kBands];
+};
+
+void* ck_oracle_create(uint64_t n, int B, int H, int scheme, int ghost, int load_balance,
+                       uint32_t max_chain, uint32_t max_search, uint32_t max_rounds,
+                       uint32_t batch_ops, uint64_t hash_seed, uint64_t rng_seed) {
+  if (n < (uint64_t)H || B < 1 || B > 8 || H < 2 || H > 4 || batch_ops == 0) return nullptr;
+  if (scheme < RANDOM_WALK || scheme > RATTLE) return nullptr;
+  if (H > 2 && B != 1) return nullptr;                 // d-ary tables use single-slot bins
+  if (ghost && H != 2) return nullptr;                 // ghosts need exactly two bins
+  if (scheme == RATTLE && (B != 1 || ghost)) return nullptr;
+  if (scheme == QUEUE && H != 2) return nullptr;
+  Table* T = new Table();
+  T->p = Params{n, B, H, scheme, ghost, load_balance, max_chain, max_search, max_rounds,
+                batch_ops, hash_seed, rng_seed};
+  uint64_t s = hash_seed;
+  for (int i = 0; i < 4; ++i) {
+    T->a[i] = splitmix_next(s) | 1ull;
+    T->c[i] = splitmix_next(s);
+  }
+  T->bins.assign(n, BinState());
+  std::memset(&T->st, 0, sizeof(T->st));
+  return T;
+}
+
+void ck_oracle_destroy(void* t) { delete (Table*)t; }
+
+void ck_oracle_hash(void* t, uint64_t key, uint64_t* out) { ((Table*)t)->hash(key, out); }
+
+// Insert n keys (assumed absent, Sec. 3).  Per-op outputs: status, bins
+// viewed by the plan that decided the op, kicks, and rounds lost to claims.
+void ck_oracle_insert(void* tp, const uint64_t* keys, const uint64_t* vals, uint64_t n,
+                      uint8_t* status, uint32_t* views, uint32_t* kicks, uint32_t* retries) {
+  Table& T = *(Table*)tp;
+  const uint64_t slots = T.p.n * (uint64_t)T.p.B;
+  for (uint64_t b0 = 0; b0 < n; b0 += T.p.batch_ops) {
+    uint64_t m = std::min<uint64_t>(T.p.batch_ops, n - b0);
+    uint64_t base = T.insert_count + b0;
+    std::vector<uint64_t> ids;
+    std::vector<OpResult> res(m);
+    for (uint64_t i = 0; i < m; ++i) {
+      if (keys[b0 + i] == kEmpty) res[i].status = ST_BAD_KEY;
+      else ids.push_back(i);
+    }
+    auto fn = [&](uint64_t i) { return plan_insert(T, base + i, keys[b0 + i], vals[b0 + i]); };
+    T.st.rounds += run_rounds(T, ids, fn, res);
+    // Per-op results and density bands: an op's density is that of the table
+    // had the sub-batch been applied one op at a time in op order.
+    uint64_t ok_before = 0;
+    for (uint64_t i = 0; i < m; ++i) {
+      const OpResult& r = res[i];
+      status[b0 + i] = (uint8_t)r.status;
+      views[b0 + i] = r.status == ST_ABORTED ? 0 : r.views;
+      kicks[b0 + i] = r.status == ST_OK ? r.kicks : 0;
+      retries[b0 + i] = r.retries;
+      if (r.status == ST_BAD_KEY) { ++T.st.inserts_bad_key; continue; }
+      T.st.retries += r.retries;
+      T.st.views_all += r.views_all;
+      if (r.status == ST_ABORTED) { ++T.st.inserts_aborted; continue; }
+      uint64_t band = (uint64_t)kBands * (T.st.stored + ok_before) / slots;
+      if (band >= (uint64_t)kBands) band = kBands - 1;
+      T.st.band_inserts[band] += 1;
+      T.st.band_views[band] += r.views;
+      T.st.views += r.views;
+      if (r.status == ST_OK) {
+        ++ok_before;
+        ++T.st.inserts_ok;
+        T.st.band_kicks[band] += r.kicks;
+        T.st.kicks += r.kicks;
+        T.st.max_kicks = std::max<uint64_t>(T.st.max_kicks, r.kicks);
+        T.st.twin_updates += r.twins;
+      } else {
+        ++T.st.inserts_failed;
+        T.st.band_fails[band] += 1;
+      }
+    }
+    T.st.stored += ok_before;
+  }
+  T.insert_count += n;
+}
+
+// Lookup (Sec. 1): the key is in one of its bins, probed in hash order.
+void ck_oracle_lookup(void* tp, const uint64_t* keys, uint64_t n, uint64_t* vals_out,
+                      uint8_t* found) {
+  Table& T = *(Table*)tp;
+  for (uint64_t q = 0; q < n; ++q) {
+    uint64_t h[4];
+    T.hash(keys[q], h);
+    found[q] = 0;
+    vals_out[q] = 0;
+    ++T.st.lookups;
+    if (keys[q] == kEmpty) continue;
+    for (int i = 0; i < T.p.H && !found[q]; ++i) {
+      ++T.st.lookup_probes;
+      const BinState& s = T.bins[h[i]];
+      for (int j = 0; j < T.p.B; ++j)
+        if (s.s[j].key == keys[q]) {
+          found[q] = 1;
+          vals_out[q] = s.s[j].val;
+          break;
+        }
+    }
+    T.st.lookup_hits += found[q];
+  }
+}
+
+void ck_oracle_delete(void* tp, const uint64_t* keys, uint64_t n, uint8_t* found,
+                      uint32_t* retries) {
+  Table& T = *(Table*)tp;
+  for (uint64_t b0 = 0; b0 < n; b0 += T.p.batch_ops) {
+    uint64_t m = std::min<uint64_t>(T.p.batch_ops, n - b0);
+    std::vector<uint64_t> ids;
+    std::vector<OpResult> res(m);
+    std::vector<uint32_t> probes(m, 0);
+    for (uint64_t i = 0; i < m; ++i) {
+      if (keys[b0 + i] == kEmpty) res[i].status = ST_BAD_KEY;
+      else ids.push_back(i);
+    }
+    auto fn = [&](uint64_t i) { return plan_delete(T, keys[b0 + i], &probes[i]); };
+    run_rounds(T, ids, fn, res);
+    for (uint64_t i = 0; i < m; ++i) {
+      found[b0 + i] = (uint8_t)res[i].status;
+      retries[b0 + i] = res[i].retries;
+      if (res[i].status == ST_BAD_KEY) continue;
+      ++T.st.deletes;
+      T.st.delete_retries += res[i].retries;
+      T.st.delete_probes += probes[i];
+      if (res[i].status == ST_OK) { ++T.st.deletes_found; --T.st.stored; }
+    }
+  }
+}
+
+// Canonical image of the table: keys and values per slot, rattle counters
+// per slot, and per bin the metadata word
+//   bits 0-7 duplicate marks, bits 8-11 spawn count, bits 24-31 hit counter.
+void ck_oracle_export(void* tp, uint64_t* keys, uint64_t* vals, uint16_t* rattle,
+                      uint32_t* meta) {
+  Table& T = *(Table*)tp;
+  for (uint64_t b = 0; b < T.p.n; ++b) {
+    const BinState& s = T.bins[b];
+    for (int j = 0; j < T.p.B; ++j) {
+      keys[b * T.p.B + j] = s.s[j].key;
+      vals[b * T.p.B + j] = s.s[j].val;
+      rattle[b * T.p.B + j] = s.s[j].rattle;
+    }
+    meta[b] = (uint32_t)s.dup | ((uint32_t)s.sc << 8) | ((uint32_t)s.hc << 24);
+  }
+}
+
+// Load a canonical image (inverse of export); `stored` is recomputed.
+void ck_oracle_import(void* tp, const uint64_t* keys, const uint64_t* vals,
+                      const uint16_t* rattle, const uint32_t* meta) {
+  Table& T = *(Table*)tp;
+  uint64_t distinct = 0;
+  for (uint64_t b = 0; b < T.p.n; ++b) {
+    BinState& s = T.bins[b];
+    for (int j = 0; j < T.p.B; ++j) {
+      s.s[j].key = keys[b * T.p.B + j];
+      s.s[j].val = vals[b * T.p.B + j];
+      s.s[j].rattle = rattle[b * T.p.B + j];
+      if (s.s[j].key != kEmpty && !((meta[b] >> j) & 1)) ++distinct;
+    }
+    s.dup = (uint8_t)(meta[b] & 0xFF);
+    s.sc = (uint8_t)((meta[b] >> 8) & 0xF);
+    s.hc = (uint8_t)(meta[b] >> 24);
+  }
+  // Every ghost pair contributes two duplicate-marked copies of one key.
+  uint64_t dups = 0;
+  for (uint64_t b = 0; b < T.p.n; ++b)
+    for (int j = 0; j < T.p.B; ++j)
+      if (T.bins[b].s[j].key != kEmpty && ((T.bins[b].dup >> j) & 1)) ++dups;
+  T.st.stored = distinct + dups / 2;
+}
+
+void ck_oracle_stats(void* tp, ck_oracle_stats_t* out) {
+  std::memcpy(out, &((Table*)tp)->st, sizeof(ck_oracle_stats_t));
+}
+
+uint64_t ck_oracle_insert_count(void* tp) { return ((Table*)tp)->insert_count; }
+
+}  // extern "C"

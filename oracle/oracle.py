@@ -1,0 +1,152 @@
+"""ctypes front end of the CPU oracle (``ck_oracle.cpp``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by the
+CPU-baseline leg of the benchmark, never by the GPU library.  It shares no code
+with the library; it only marshals numpy arrays into the oracle's C calls.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "ck_oracle.cpp")
+LIB = os.path.join(HERE, "libck_oracle.so")
+
+RANDOM_WALK, BFS, SORTED, QUEUE, RATTLE = range(5)
+SCHEMES = {"random_walk": RANDOM_WALK, "bfs": BFS, "sorted": SORTED, "queue": QUEUE,
+           "rattle": RATTLE}
+ST_NOT_FOUND, ST_OK, ST_FAIL, ST_ABORTED, ST_BAD_KEY = range(5)
+EMPTY = np.uint64(0xFFFFFFFFFFFFFFFF)
+BANDS = 200
+
+_STAT_SCALARS = ["inserts_ok", "inserts_failed", "inserts_aborted", "inserts_bad_key",
+                 "views", "views_all", "kicks", "max_kicks", "retries", "rounds",
+                 "twin_updates", "lookups", "lookup_hits", "lookup_probes", "deletes",
+                 "deletes_found", "delete_probes", "delete_retries", "stored"]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in _STAT_SCALARS] + [
+        ("band_inserts", ctypes.c_uint64 * BANDS), ("band_views", ctypes.c_uint64 * BANDS),
+        ("band_kicks", ctypes.c_uint64 * BANDS), ("band_fails", ctypes.c_uint64 * BANDS)]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with g++ (plain C++17, -O2)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-Wall", "-shared", "-fPIC",
+                               "-o", tmp, SRC])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = ctypes.CDLL(build())
+        u64, u32, i32, vp = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p
+        L.ck_oracle_create.restype = vp
+        L.ck_oracle_create.argtypes = [u64, i32, i32, i32, i32, i32, u32, u32, u32, u32, u64, u64]
+        L.ck_oracle_destroy.argtypes = [vp]
+        L.ck_oracle_hash.argtypes = [vp, u64, vp]
+        L.ck_oracle_insert.argtypes = [vp, vp, vp, u64, vp, vp, vp, vp]
+        L.ck_oracle_lookup.argtypes = [vp, vp, u64, vp, vp]
+        L.ck_oracle_delete.argtypes = [vp, vp, u64, vp, vp]
+        L.ck_oracle_export.argtypes = [vp, vp, vp, vp, vp]
+        L.ck_oracle_import.argtypes = [vp, vp, vp, vp, vp]
+        L.ck_oracle_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
+        L.ck_oracle_insert_count.restype = u64
+        L.ck_oracle_insert_count.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class OracleTable:
+    """One cuckoo table of the oracle.  ``batch_ops`` is the sub-batch size of
+    the phased-round protocol; ``batch_ops=1`` is the plain serial algorithm."""
+
+    def __init__(self, bins, slots_per_bin=4, d=2, scheme="random_walk", ghost=False,
+                 load_balance=False, max_chain=500, max_search=500, max_rounds=0,
+                 batch_ops=1, hash_seed=0, rng_seed=0):
+        self.n, self.B, self.H = int(bins), int(slots_per_bin), int(d)
+        self.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
+        self._t = lib().ck_oracle_create(self.n, self.B, self.H, self.scheme, int(ghost),
+                                         int(load_balance), max_chain, max_search,
+                                         max_rounds, batch_ops, hash_seed, rng_seed)
+        if not self._t:
+            raise ValueError("oracle rejected the table parameters")
+
+    def __del__(self):
+        if getattr(self, "_t", None):
+            lib().ck_oracle_destroy(self._t)
+            self._t = None
+
+    def hash(self, key) -> list[int]:
+        out = np.zeros(4, dtype=np.uint64)
+        lib().ck_oracle_hash(self._t, int(key), _p(out))
+        return [int(v) for v in out[: self.H]]
+
+    def insert(self, keys, vals):
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        vals = np.ascontiguousarray(vals, dtype=np.uint64)
+        n = keys.size
+        status = np.zeros(n, np.uint8)
+        views = np.zeros(n, np.uint32)
+        kicks = np.zeros(n, np.uint32)
+        retries = np.zeros(n, np.uint32)
+        lib().ck_oracle_insert(self._t, _p(keys), _p(vals), n, _p(status), _p(views),
+                               _p(kicks), _p(retries))
+        return {"status": status, "views": views, "kicks": kicks, "retries": retries}
+
+    def lookup(self, keys):
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        vals = np.zeros(keys.size, np.uint64)
+        found = np.zeros(keys.size, np.uint8)
+        lib().ck_oracle_lookup(self._t, _p(keys), keys.size, _p(vals), _p(found))
+        return vals, found
+
+    def delete(self, keys):
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        found = np.zeros(keys.size, np.uint8)
+        retries = np.zeros(keys.size, np.uint32)
+        lib().ck_oracle_delete(self._t, _p(keys), keys.size, _p(found), _p(retries))
+        return found, retries
+
+    def export(self):
+        S = self.n * self.B
+        keys = np.zeros(S, np.uint64)
+        vals = np.zeros(S, np.uint64)
+        rattle = np.zeros(S, np.uint16)
+        meta = np.zeros(self.n, np.uint32)
+        lib().ck_oracle_export(self._t, _p(keys), _p(vals), _p(rattle), _p(meta))
+        return {"keys": keys, "vals": vals, "rattle": rattle, "meta": meta}
+
+    def load(self, img):
+        lib().ck_oracle_import(self._t, _p(np.ascontiguousarray(img["keys"], np.uint64)),
+                               _p(np.ascontiguousarray(img["vals"], np.uint64)),
+                               _p(np.ascontiguousarray(img["rattle"], np.uint16)),
+                               _p(np.ascontiguousarray(img["meta"], np.uint32)))
+
+    def stats(self) -> dict:
+        s = _Stats()
+        lib().ck_oracle_stats(self._t, ctypes.byref(s))
+        out = {n: int(getattr(s, n)) for n in _STAT_SCALARS}
+        for f in ("band_inserts", "band_views", "band_kicks", "band_fails"):
+            out[f] = np.array(list(getattr(s, f)), dtype=np.uint64)
+        return out
+
+    @property
+    def insert_count(self) -> int:
+        return int(lib().ck_oracle_insert_count(self._t))
