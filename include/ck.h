@@ -1,0 +1,186 @@
+/*
+ * ck.h -- C ABI of libck, batched cuckoo hash tables on AMD Instinct MI355X
+ * (gfx950) with the kick-out eviction schemes of Kuszmaul, "Fast Concurrent
+ * Cuckoo Kick-out Eviction Schemes for High-Density Tables" (arXiv 1605.05236).
+ *
+ * A table has `bins` bins of `slots_per_bin` slots and `d` hash functions
+ * (Sec. 1: two bins per key, bins of 4 or 8 slots; Sec. 7: d-ary tables with
+ * single-slot bins).  Keys are 64-bit; the all-ones key is reserved to mark an
+ * empty slot.  Values are 64-bit for slots_per_bin >= 2 and 32-bit for
+ * single-slot bins (whose slot also carries the 16-bit rattle counter of
+ * Sec. 7).
+ *
+ * Concurrency model.  A batch of inserts (or deletes) is applied in phased
+ * rounds: every pending op plans its kick-out chain against the same snapshot
+ * of the table, claims every bin its plan writes (lowest op index wins a bin;
+ * the per-bin claim word is the paper's claim flag, Sec. 8.2), and the ops that
+ * own all their bins commit their chains in reverse order (the "system
+ * transaction" order of Sec. 8.2).  The rest re-plan next round.  The result is
+ * a pure function of the table, the batch and the seeds, independent of thread
+ * timing; a batch of one op is the paper's serial algorithm.
+ *
+ * Conventions for every call:
+ *   - returns ck_status (0 = CK_OK, negative = error); nothing else signals
+ *     errors and no exception crosses the ABI;
+ *   - `d_` pointers are device pointers (HIP global memory) owned by the
+ *     caller; `h_` pointers are host pointers owned by the caller;
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
+ *     it; ck_insert and ck_delete synchronise it once per round to read the
+ *     number of ops still pending, so they return with all their rounds
+ *     enqueued and the last round complete;
+ *   - calls on one table must not overlap; tables are independent.
+ */
+#ifndef CK_H
+#define CK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CK_EMPTY_KEY 0xFFFFFFFFFFFFFFFFull
+#define CK_BANDS 200 /* density bands of 0.5 % */
+
+typedef struct ck_table ck_table; /* opaque host-side handle */
+
+typedef enum {
+  CK_OK = 0,
+  CK_EINVAL = -1,       /* bad argument (geometry, sizes, null pointers) */
+  CK_ENOMEM = -2,       /* storage too small or scratch allocation failed */
+  CK_EDEVICE = -3,      /* a HIP runtime call failed (sticky device error) */
+  CK_EUNSUPPORTED = -5  /* valid request this library does not implement */
+} ck_status;
+
+/* Kick-out eviction schemes.
+ *   CK_RANDOM_WALK  random kicking: a random victim in a random bin, the
+ *                   victim moves to one of its other bins (Sec. 1, Sec. 6).
+ *   CK_BFS          breadth-first search for the shortest chain (Sec. 1, 5).
+ *   CK_SORTED       sorted search by per-bin spawn count (Sec. 5).
+ *   CK_QUEUE        queue-kicking with hit counters, load and hit balancing
+ *                   (Sec. 6); two hash functions only.
+ *   CK_RATTLE       rattle-kicking, d-ary tables with single-slot bins (Sec. 7). */
+typedef enum {
+  CK_RANDOM_WALK = 0,
+  CK_BFS = 1,
+  CK_SORTED = 2,
+  CK_QUEUE = 3,
+  CK_RATTLE = 4
+} ck_scheme;
+
+/* Per-op result bytes written to device arrays. */
+enum {
+  CK_OP_NOT_FOUND = 0, /* lookup/delete: key absent */
+  CK_OP_OK = 1,        /* inserted / found / deleted */
+  CK_OP_FAIL_CHAIN = 2,/* insert: chain or search cap exceeded; table unchanged */
+  CK_OP_ABORTED = 3,   /* lost its claims in max_rounds rounds; table unchanged */
+  CK_OP_BAD_KEY = 4    /* the key is CK_EMPTY_KEY */
+};
+
+typedef struct {
+  uint32_t ghost;        /* ghost insertions (Sec. 4); d == 2 only */
+  uint32_t load_balance; /* fresh insert into the less full bin (Sec. 2);
+                            CK_QUEUE always balances */
+  uint32_t max_chain;    /* kicks (walk schemes) or tries (rattle) before an
+                            insert fails; <= 2048 */
+  uint32_t max_search;   /* bins viewed before a BFS/sorted insert fails; <= 1024 */
+  uint32_t max_rounds;   /* lost rounds before CK_OP_ABORTED; 0 = never */
+  uint32_t batch_ops;    /* sub-batch size of the round protocol; results
+                            depend on it (1 = serial) */
+  uint64_t hash_seed;    /* seeds the hash multipliers */
+  uint64_t rng_seed;     /* seeds the random walk's choices */
+} ck_options;
+
+/* Counters of one table since creation (or the last ck_stats_reset). */
+typedef struct {
+  uint64_t inserts_ok, inserts_failed, inserts_aborted, inserts_bad_key;
+  uint64_t views;       /* bins viewed by the plans that decided each insert */
+  uint64_t views_all;   /* bins viewed by every plan, including lost rounds */
+  uint64_t kicks, max_kicks, retries, rounds, twin_updates;
+  uint64_t lookups, lookup_hits, lookup_probes;
+  uint64_t deletes, deletes_found, delete_probes, delete_retries;
+  uint64_t stored;      /* distinct keys currently stored */
+  /* per 0.5 % density band: inserts, their bins viewed, kicks, failures;
+     an op's density is the table's had its sub-batch been applied in op order */
+  uint64_t band_inserts[CK_BANDS], band_views[CK_BANDS];
+  uint64_t band_kicks[CK_BANDS], band_fails[CK_BANDS];
+} ck_stats;
+
+/* Defaults: no ghosts, first fit, max_chain 500, max_search 500, max_rounds 0,
+   batch_ops 2^20, hash_seed 0, rng_seed 0. */
+void ck_default_options(ck_options* opt);
+
+/* Device bytes a table of this geometry needs (slots, per-bin metadata word,
+   per-bin claim word).  Errors: CK_EINVAL for an unsupported geometry. */
+ck_status ck_storage_bytes(uint64_t bins, uint32_t slots_per_bin, uint32_t d, size_t* out);
+
+/* Create a table in caller-owned device memory `d_storage` (>= storage bytes,
+   256-byte aligned; must outlive the table) and initialise it to empty on
+   `stream`.  Geometry: 1 <= bins < 2^32 and bins >= d; slots_per_bin in
+   {1, 2, 4, 8}; d in {2, 3, 4}; d > 2 needs slots_per_bin == 1; CK_RATTLE needs
+   slots_per_bin == 1; CK_QUEUE and ghosts need d == 2.  The library allocates
+   its own round scratch with hipMalloc (released by ck_destroy). */
+ck_status ck_create(uint64_t bins, uint32_t slots_per_bin, uint32_t d, ck_scheme scheme,
+                    const ck_options* opt, void* d_storage, size_t storage_bytes,
+                    void* stream, ck_table** out);
+
+/* Insert n keys with their values (8-byte values, 4-byte for single-slot
+   bins).  Keys must be absent from the table and distinct within the call
+   (Sec. 3: inserts do not check for presence); violating this is undefined.
+   d_status[i] receives a CK_OP_* byte.  Sub-batches of batch_ops ops run the
+   round protocol in order. */
+ck_status ck_insert(ck_table* t, const uint64_t* d_keys, const void* d_vals, uint64_t n,
+                    uint8_t* d_status, void* stream);
+
+/* ck_insert plus per-op diagnostics (each may be NULL): bins viewed by the
+   deciding plan, kicks of the committed chain, rounds lost to claims. */
+ck_status ck_insert_ex(ck_table* t, const uint64_t* d_keys, const void* d_vals, uint64_t n,
+                       uint8_t* d_status, uint32_t* d_views, uint32_t* d_kicks,
+                       uint32_t* d_retries, void* stream);
+
+/* Lookup (Sec. 1): probe the key's bins in hash order.  d_vals_out gets the
+   value (0 when absent), d_found 1/0.  Fully asynchronous on `stream`. */
+ck_status ck_lookup(ck_table* t, const uint64_t* d_keys, uint64_t n, void* d_vals_out,
+                    uint8_t* d_found, void* stream);
+
+/* Lookup with an explicit lanes-per-probe (1 or slots_per_bin); 0 = auto. */
+ck_status ck_lookup_lpp(ck_table* t, const uint64_t* d_keys, uint64_t n, void* d_vals_out,
+                        uint8_t* d_found, uint32_t lanes_per_probe, void* stream);
+
+/* Delete (Sec. 1): empty every slot holding the key (both copies of a ghost
+   pair).  d_found gets CK_OP_OK / CK_OP_NOT_FOUND / CK_OP_ABORTED /
+   CK_OP_BAD_KEY.  Deleting one key twice in a call: the first op finds it. */
+ck_status ck_delete(ck_table* t, const uint64_t* d_keys, uint64_t n, uint8_t* d_found,
+                    void* stream);
+
+/* Copy the counters to host memory (synchronises `stream`). */
+ck_status ck_stats_get(ck_table* t, ck_stats* h_out, void* stream);
+ck_status ck_stats_reset(ck_table* t, void* stream);
+
+/* Canonical image of the table in host memory: per slot key, value (zero
+   extended for 32-bit values) and rattle counter; per bin the metadata word
+     bits 0-7 duplicate marks, bits 8-11 spawn count, bits 24-31 hit counter.
+   Arrays hold bins*slots_per_bin (keys, vals, rattle) and bins (meta)
+   entries.  Export synchronises `stream`; import recomputes `stored`. */
+ck_status ck_export(ck_table* t, uint64_t* h_keys, uint64_t* h_vals, uint16_t* h_rattle,
+                    uint32_t* h_meta, void* stream);
+ck_status ck_import(ck_table* t, const uint64_t* h_keys, const uint64_t* h_vals,
+                    const uint16_t* h_rattle, const uint32_t* h_meta, void* stream);
+
+/* Hash a key as the table does (the d bin indices, in order). */
+ck_status ck_hash(const ck_table* t, uint64_t key, uint64_t* h_bins_out);
+
+/* Number of insert ops submitted so far (the id of the next insert op). */
+uint64_t ck_insert_count(const ck_table* t);
+
+/* Release the handle and the library's scratch; the caller's storage is not
+   freed.  Synchronises the device. */
+ck_status ck_destroy(ck_table* t);
+
+const char* ck_strerror(ck_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CK_H */

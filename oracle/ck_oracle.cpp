@@ -566,6 +566,7 @@ void* ck_oracle_create(uint64_t n, int B, int H, int scheme, int ghost, int load
   if (ghost && H != 2) return nullptr;                 // ghosts need exactly two bins
   if (scheme == RATTLE && (B != 1 || ghost)) return nullptr;
   if (scheme == QUEUE && H != 2) return nullptr;
+  if (load_balance && H != 2) return nullptr;           // balancing compares two bins
   Table* T = new Table();
   T->p = Params{n, B, H, scheme, ghost, load_balance, max_chain, max_search, max_rounds,
                 batch_ops, hash_seed, rng_seed};

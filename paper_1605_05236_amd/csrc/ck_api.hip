@@ -1,0 +1,490 @@
+// ck_api.hip -- host runtime of libck: table objects, the round driver and the
+// C ABI declared in include/ck.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ck_internal.h"
+
+using namespace ck;
+
+struct ck_table {
+  Geo g;
+  ck_options opt;
+  uint64_t bins;
+  uint32_t B, H;
+  ck_scheme scheme;
+  uint64_t insert_count = 0;
+  uint32_t epoch = 0;
+  // round scratch
+  uint32_t batch_cap = 0;
+  uint32_t* pend[2] = {nullptr, nullptr};
+  PlanHdr* hdr = nullptr;
+  uint32_t* evict = nullptr;
+  Move* arena = nullptr;
+  uint32_t arena_cap = 0;
+  uint32_t* spawns = nullptr;
+  uint32_t spawn_cap = 0;
+  uint32_t* op[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // views, views_all, kicks, retries, twins
+  Ctr* ctr = nullptr;
+  Ctr* h_ctr = nullptr;
+  void* wg_scratch = nullptr;
+  uint32_t wg_bytes = 0;
+  uint32_t evict_grid = 0;
+  DevStats* dstats = nullptr;
+  uint32_t* block_tmp = nullptr;
+  // host-side counters
+  uint64_t rounds = 0, lookups = 0;
+};
+
+namespace {
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// splitmix64 (Steele, Lea, Flood): derives the hash multipliers from the seed.
+uint64_t sm_next(uint64_t& s) {
+  s += 0x9E3779B97F4A7C15ull;
+  uint64_t z = s;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+struct Layout {
+  size_t slots, meta, owner, total;
+};
+Layout layout(uint64_t bins, uint32_t B) {
+  Layout L;
+  L.slots = 0;
+  L.meta = align256(bins * B * 16);
+  L.owner = L.meta + align256(bins * 4);
+  L.total = L.owner + align256(bins * 8);
+  return L;
+}
+
+bool geometry_ok(uint64_t bins, uint32_t B, uint32_t d) {
+  if (bins == 0 || bins >= (1ull << 32) || bins < d) return false;
+  if (!(B == 1 || B == 2 || B == 4 || B == 8)) return false;
+  if (d < 2 || d > 4) return false;
+  if (d > 2 && B != 1) return false;
+  return true;
+}
+
+#define HIP_TRY(x)                         \
+  do {                                     \
+    if ((x) != hipSuccess) return CK_EDEVICE; \
+  } while (0)
+
+template <class T>
+hipError_t dalloc(T** p, size_t count) {
+  return hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
+}
+
+void free_scratch(ck_table* t) {
+  (void)hipFree(t->pend[0]);
+  (void)hipFree(t->pend[1]);
+  (void)hipFree(t->hdr);
+  (void)hipFree(t->evict);
+  (void)hipFree(t->arena);
+  (void)hipFree(t->spawns);
+  for (auto& p : t->op) (void)hipFree(p);
+  (void)hipFree(t->ctr);
+  if (t->h_ctr) (void)hipHostFree(t->h_ctr);
+  (void)hipFree(t->wg_scratch);
+  (void)hipFree(t->dstats);
+  (void)hipFree(t->block_tmp);
+}
+
+ck_status alloc_scratch(ck_table* t) {
+  const uint32_t m = t->opt.batch_ops;
+  t->batch_cap = m;
+  HIP_TRY(dalloc(&t->pend[0], m));
+  HIP_TRY(dalloc(&t->pend[1], m));
+  HIP_TRY(dalloc(&t->hdr, m));
+  HIP_TRY(dalloc(&t->evict, m));
+  for (auto& p : t->op) HIP_TRY(dalloc(&p, m));
+  t->arena_cap = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(4096, (uint64_t)m * 4), 1u << 30);
+  HIP_TRY(dalloc(&t->arena, t->arena_cap));
+  t->spawn_cap = t->scheme == CK_SORTED ? (uint32_t)std::max<uint64_t>(4096, (uint64_t)m * 2) : 16;
+  HIP_TRY(dalloc(&t->spawns, t->spawn_cap));
+  HIP_TRY(dalloc(&t->ctr, 1));
+  HIP_TRY(hipHostMalloc((void**)&t->h_ctr, sizeof(Ctr), hipHostMallocDefault));
+  HIP_TRY(dalloc(&t->dstats, 1));
+  HIP_TRY(hipMemset(t->dstats, 0, sizeof(DevStats)));
+  const uint32_t nb = (m + 1023) / 1024;
+  HIP_TRY(dalloc(&t->block_tmp, ((nb + 63) & ~63u) + 16));
+  // persistent eviction planners: workgroups that fit the LDS budget
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const size_t lds = evict_lds_bytes(t->g);
+  size_t per_cu = std::max<size_t>(1, std::min<size_t>(16, (160 * 1024) / std::max<size_t>(lds, 1)));
+  t->evict_grid = (uint32_t)(cus * per_cu);
+  t->wg_bytes = (uint32_t)evict_wg_scratch_bytes(t->g);
+  HIP_TRY(hipMalloc(&t->wg_scratch, (size_t)t->evict_grid * t->wg_bytes));
+  return CK_OK;
+}
+
+ck_status grow_arena(ck_table* t) {
+  HIP_TRY(hipDeviceSynchronize());
+  (void)hipFree(t->arena);
+  t->arena = nullptr;
+  uint64_t nc = std::min<uint64_t>((uint64_t)t->arena_cap * 2, 1u << 30);
+  t->arena_cap = (uint32_t)nc;
+  HIP_TRY(dalloc(&t->arena, t->arena_cap));
+  if (t->scheme == CK_SORTED) {
+    (void)hipFree(t->spawns);
+    t->spawns = nullptr;
+    t->spawn_cap = (uint32_t)std::min<uint64_t>((uint64_t)t->spawn_cap * 2, 1u << 30);
+    HIP_TRY(dalloc(&t->spawns, t->spawn_cap));
+  }
+  return CK_OK;
+}
+
+Round make_round(ck_table* t, const uint64_t* keys, const void* vals, uint8_t* status,
+                 uint32_t** ops, uint64_t op_base, bool is_delete) {
+  Round r{};
+  r.keys = keys;
+  r.vals = vals;
+  r.hdr = t->hdr;
+  r.evict = t->evict;
+  r.arena = t->arena;
+  r.arena_cap = t->arena_cap;
+  r.spawns = t->spawns;
+  r.spawn_cap = t->spawn_cap;
+  r.ctr = t->ctr;
+  r.op_base = op_base;
+  r.status = status;
+  r.op_views = ops[0];
+  r.op_views_all = ops[1];
+  r.op_kicks = ops[2];
+  r.op_retries = ops[3];
+  r.op_twins = ops[4];
+  r.max_rounds = t->opt.max_rounds;
+  r.is_delete = is_delete ? 1 : 0;
+  r.wg_scratch = t->wg_scratch;
+  r.wg_scratch_bytes = t->wg_bytes;
+  r.stats = t->dstats;
+  return r;
+}
+
+// Run the phased rounds of one sub-batch until no op is pending.
+ck_status run_rounds(ck_table* t, Round& r, uint64_t m, hipStream_t s) {
+  uint32_t npend = (uint32_t)m;
+  int cur = 0;
+  // The lowest pending op always commits, so m rounds suffice; arena growth
+  // adds a few void rounds.  Anything beyond that is a fault, not progress.
+  uint64_t guard = 2 * m + 64;
+  while (npend > 0) {
+    if (guard-- == 0) return CK_EDEVICE;
+    ++t->epoch;
+    if (t->epoch == 0) {  // claim tags wrapped: reset every claim word
+      HIP_TRY(hipMemsetAsync(t->g.owner, 0xFF, (size_t)t->bins * 8, s));
+      t->epoch = 1;
+    }
+    r.tag = (unsigned long long)(~t->epoch) << 32;
+    r.pend = t->pend[cur];
+    r.npend = npend;
+    r.next = t->pend[cur ^ 1];
+    r.arena = t->arena;
+    r.arena_cap = t->arena_cap;
+    r.spawns = t->spawns;
+    r.spawn_cap = t->spawn_cap;
+    HIP_TRY(launch_round_begin(t->ctr, s));
+    if (r.is_delete) {
+      HIP_TRY(launch_plan_delete(t->g, r, s));
+    } else {
+      HIP_TRY(launch_plan_fresh(t->g, r, s));
+      HIP_TRY(launch_plan_evict(t->g, r, t->evict_grid, s));
+    }
+    HIP_TRY(launch_commit(t->g, r, s));
+    HIP_TRY(hipMemcpyAsync(t->h_ctr, t->ctr, sizeof(Ctr), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const Ctr c = *t->h_ctr;
+    if (c.overflow) {
+      ck_status st = grow_arena(t);
+      if (st != CK_OK) return st;
+    } else if (!r.is_delete) {
+      ++t->rounds;
+    }
+    npend = c.next_pending;
+    cur ^= 1;
+  }
+  return CK_OK;
+}
+
+ck_status run_batches(ck_table* t, const uint64_t* keys, const void* vals, uint64_t n,
+                      uint8_t* status, uint32_t* views, uint32_t* kicks, uint32_t* retries,
+                      bool is_delete, hipStream_t s) {
+  const uint32_t vb = t->B == 1 ? 4 : 8;
+  const uint64_t slots = t->bins * t->B;
+  for (uint64_t b0 = 0; b0 < n; b0 += t->opt.batch_ops) {
+    const uint64_t m = std::min<uint64_t>(t->opt.batch_ops, n - b0);
+    uint32_t* ops[5] = {views ? views + b0 : t->op[0], t->op[1],
+                        kicks ? kicks + b0 : t->op[2], retries ? retries + b0 : t->op[3],
+                        t->op[4]};
+    Round r = make_round(t, keys + b0, vals ? (const char*)vals + b0 * vb : nullptr,
+                         status + b0, ops, t->insert_count + b0, is_delete);
+    HIP_TRY(launch_batch_begin(keys + b0, m, t->pend[0], status + b0, ops[0], ops[1], ops[2],
+                               ops[3], ops[4], CK_OP_BAD_KEY, t->ctr, s));
+    ck_status st = run_rounds(t, r, m, s);
+    if (st != CK_OK) return st;
+    HIP_TRY(launch_batch_stats(r, m, slots, t->block_tmp, is_delete ? 1 : 0, s));
+  }
+  if (!is_delete) t->insert_count += n;
+  return CK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ck_default_options(ck_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->max_chain = 500;
+  o->max_search = 500;
+  o->batch_ops = 1u << 20;
+}
+
+ck_status ck_storage_bytes(uint64_t bins, uint32_t B, uint32_t d, size_t* out) {
+  if (!out || !geometry_ok(bins, B, d)) return CK_EINVAL;
+  *out = layout(bins, B).total;
+  return CK_OK;
+}
+
+ck_status ck_create(uint64_t bins, uint32_t B, uint32_t d, ck_scheme scheme,
+                    const ck_options* opt, void* storage, size_t bytes, void* stream,
+                    ck_table** out) {
+  if (!out || !storage || !geometry_ok(bins, B, d)) return CK_EINVAL;
+  *out = nullptr;
+  ck_options o;
+  ck_default_options(&o);
+  if (opt) o = *opt;
+  if ((int)scheme < CK_RANDOM_WALK || (int)scheme > CK_RATTLE) return CK_EINVAL;
+  if (scheme == CK_RATTLE && (B != 1 || o.ghost)) return CK_EINVAL;
+  if (scheme == CK_QUEUE && d != 2) return CK_EINVAL;
+  if (o.ghost && d != 2) return CK_EINVAL;
+  if (o.load_balance && d != 2) return CK_EINVAL;
+  if (o.batch_ops == 0 || o.batch_ops > (1u << 26)) return CK_EINVAL;
+  if (o.max_chain > 2048 || o.max_search > 1024 || o.max_search < d) return CK_EINVAL;
+  if (((uintptr_t)storage & 255) != 0) return CK_EINVAL;
+  const Layout L = layout(bins, B);
+  if (bytes < L.total) return CK_ENOMEM;
+  ck_table* t = new (std::nothrow) ck_table();
+  if (!t) return CK_ENOMEM;
+  t->opt = o;
+  t->bins = bins;
+  t->B = B;
+  t->H = d;
+  t->scheme = scheme;
+  uint64_t s = o.hash_seed;
+  for (int i = 0; i < 4; ++i) {
+    t->g.a[i] = sm_next(s) | 1ull;
+    t->g.c[i] = sm_next(s);
+  }
+  char* base = (char*)storage;
+  t->g.slots = (ulonglong2*)(base + L.slots);
+  t->g.meta = (uint32_t*)(base + L.meta);
+  t->g.owner = (unsigned long long*)(base + L.owner);
+  t->g.n = (uint32_t)bins;
+  t->g.B = B;
+  t->g.H = d;
+  t->g.scheme = scheme;
+  t->g.ghost = o.ghost;
+  t->g.balance = o.load_balance;
+  t->g.max_chain = o.max_chain;
+  t->g.max_search = o.max_search;
+  t->g.rng_seed = o.rng_seed;
+  ck_status st = alloc_scratch(t);
+  if (st != CK_OK) {
+    free_scratch(t);
+    delete t;
+    return st;
+  }
+  if (launch_init(t->g, (hipStream_t)stream) != hipSuccess) {
+    free_scratch(t);
+    delete t;
+    return CK_EDEVICE;
+  }
+  *out = t;
+  return CK_OK;
+}
+
+ck_status ck_insert_ex(ck_table* t, const uint64_t* keys, const void* vals, uint64_t n,
+                       uint8_t* status, uint32_t* views, uint32_t* kicks, uint32_t* retries,
+                       void* stream) {
+  if (!t) return CK_EINVAL;
+  if (n == 0) return CK_OK;
+  if (!keys || !vals || !status) return CK_EINVAL;
+  return run_batches(t, keys, vals, n, status, views, kicks, retries, false, (hipStream_t)stream);
+}
+
+ck_status ck_insert(ck_table* t, const uint64_t* keys, const void* vals, uint64_t n,
+                    uint8_t* status, void* stream) {
+  return ck_insert_ex(t, keys, vals, n, status, nullptr, nullptr, nullptr, stream);
+}
+
+ck_status ck_lookup_lpp(ck_table* t, const uint64_t* keys, uint64_t n, void* vals_out,
+                        uint8_t* found, uint32_t lpp, void* stream) {
+  if (!t) return CK_EINVAL;
+  if (n == 0) return CK_OK;
+  if (!keys || !vals_out || !found) return CK_EINVAL;
+  if (lpp == 0) lpp = t->B;
+  if (lpp != 1 && lpp != t->B) return CK_EINVAL;
+  HIP_TRY(launch_lookup(t->g, keys, n, vals_out, found, lpp, t->dstats, (hipStream_t)stream));
+  t->lookups += n;
+  return CK_OK;
+}
+
+ck_status ck_lookup(ck_table* t, const uint64_t* keys, uint64_t n, void* vals_out,
+                    uint8_t* found, void* stream) {
+  return ck_lookup_lpp(t, keys, n, vals_out, found, 0, stream);
+}
+
+ck_status ck_delete(ck_table* t, const uint64_t* keys, uint64_t n, uint8_t* found,
+                    void* stream) {
+  if (!t) return CK_EINVAL;
+  if (n == 0) return CK_OK;
+  if (!keys || !found) return CK_EINVAL;
+  return run_batches(t, keys, nullptr, n, found, nullptr, nullptr, nullptr, true,
+                     (hipStream_t)stream);
+}
+
+ck_status ck_stats_get(ck_table* t, ck_stats* out, void* stream) {
+  if (!t || !out) return CK_EINVAL;
+  DevStats d;
+  HIP_TRY(hipMemcpyAsync(&d, t->dstats, sizeof(d), hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  std::memset(out, 0, sizeof(*out));
+  out->inserts_ok = d.v[S_INS_OK];
+  out->inserts_failed = d.v[S_INS_FAIL];
+  out->inserts_aborted = d.v[S_INS_ABORT];
+  out->inserts_bad_key = d.v[S_INS_BAD];
+  out->views = d.v[S_VIEWS];
+  out->views_all = d.v[S_VIEWS_ALL];
+  out->kicks = d.v[S_KICKS];
+  out->max_kicks = d.v[S_MAX_KICKS];
+  out->retries = d.v[S_RETRIES];
+  out->rounds = t->rounds;
+  out->twin_updates = d.v[S_TWINS];
+  out->lookups = t->lookups;
+  out->lookup_hits = d.v[S_LOOKUP_HITS];
+  out->lookup_probes = d.v[S_LOOKUP_PROBES];
+  out->deletes = d.v[S_DELETES];
+  out->deletes_found = d.v[S_DEL_FOUND];
+  out->delete_probes = d.v[S_DEL_PROBES];
+  out->delete_retries = d.v[S_DEL_RETRIES];
+  out->stored = d.v[S_STORED];
+  for (int b = 0; b < CK_BANDS; ++b) {
+    out->band_inserts[b] = d.band[0][b];
+    out->band_views[b] = d.band[1][b];
+    out->band_kicks[b] = d.band[2][b];
+    out->band_fails[b] = d.band[3][b];
+  }
+  return CK_OK;
+}
+
+ck_status ck_stats_reset(ck_table* t, void* stream) {
+  if (!t) return CK_EINVAL;
+  DevStats d;
+  HIP_TRY(hipMemcpyAsync(&d, t->dstats, sizeof(d), hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  const unsigned long long stored = d.v[S_STORED];
+  std::memset(&d, 0, sizeof(d));
+  d.v[S_STORED] = stored;
+  HIP_TRY(hipMemcpyAsync(t->dstats, &d, sizeof(d), hipMemcpyHostToDevice, (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  t->rounds = 0;
+  t->lookups = 0;
+  return CK_OK;
+}
+
+ck_status ck_export(ck_table* t, uint64_t* keys, uint64_t* vals, uint16_t* rattle,
+                    uint32_t* meta, void* stream) {
+  if (!t || !keys || !vals || !rattle || !meta) return CK_EINVAL;
+  const uint64_t S = t->bins * t->B;
+  std::vector<ulonglong2> buf(S);
+  HIP_TRY(hipMemcpyAsync(buf.data(), t->g.slots, S * 16, hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIP_TRY(hipMemcpyAsync(meta, t->g.meta, t->bins * 4, hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  for (uint64_t i = 0; i < S; ++i) {
+    keys[i] = buf[i].x;
+    if (t->B == 1) {
+      vals[i] = buf[i].y & 0xFFFFFFFFull;
+      rattle[i] = (uint16_t)((buf[i].y >> 32) & 0xFFFF);
+    } else {
+      vals[i] = buf[i].y;
+      rattle[i] = 0;
+    }
+  }
+  return CK_OK;
+}
+
+ck_status ck_import(ck_table* t, const uint64_t* keys, const uint64_t* vals,
+                    const uint16_t* rattle, const uint32_t* meta, void* stream) {
+  if (!t || !keys || !vals || !rattle || !meta) return CK_EINVAL;
+  const uint64_t S = t->bins * t->B;
+  std::vector<ulonglong2> buf(S);
+  uint64_t single = 0, dups = 0;
+  for (uint64_t i = 0; i < S; ++i) {
+    buf[i].x = keys[i];
+    if (t->B == 1) buf[i].y = (vals[i] & 0xFFFFFFFFull) | ((uint64_t)rattle[i] << 32);
+    else buf[i].y = vals[i];
+    if (keys[i] != kEmpty) {
+      if ((meta[i / t->B] >> (i % t->B)) & 1u) ++dups;
+      else ++single;
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(t->g.slots, buf.data(), S * 16, hipMemcpyHostToDevice, (hipStream_t)stream));
+  HIP_TRY(hipMemcpyAsync(t->g.meta, meta, t->bins * 4, hipMemcpyHostToDevice, (hipStream_t)stream));
+  HIP_TRY(hipMemsetAsync(t->g.owner, 0xFF, t->bins * 8, (hipStream_t)stream));
+  unsigned long long stored = single + dups / 2;
+  HIP_TRY(hipMemcpyAsync(&t->dstats->v[S_STORED], &stored, 8, hipMemcpyHostToDevice,
+                         (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  return CK_OK;
+}
+
+ck_status ck_hash(const ck_table* t, uint64_t key, uint64_t* out) {
+  if (!t || !out) return CK_EINVAL;
+  for (uint32_t i = 0; i < t->H; ++i) {
+    uint64_t z = t->g.a[i] * key + t->g.c[i];
+    uint64_t b = (uint64_t)(((unsigned __int128)z * t->bins) >> 64);
+    for (;;) {
+      bool clash = false;
+      for (uint32_t j = 0; j < i; ++j) clash |= out[j] == b;
+      if (!clash) break;
+      b = (b + 1 == t->bins) ? 0 : b + 1;
+    }
+    out[i] = b;
+  }
+  return CK_OK;
+}
+
+uint64_t ck_insert_count(const ck_table* t) { return t ? t->insert_count : 0; }
+
+ck_status ck_destroy(ck_table* t) {
+  if (!t) return CK_EINVAL;
+  (void)hipDeviceSynchronize();
+  free_scratch(t);
+  delete t;
+  return CK_OK;
+}
+
+const char* ck_strerror(ck_status s) {
+  switch (s) {
+    case CK_OK: return "ok";
+    case CK_EINVAL: return "invalid argument";
+    case CK_ENOMEM: return "out of memory or storage too small";
+    case CK_EDEVICE: return "HIP runtime error";
+    case CK_EUNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

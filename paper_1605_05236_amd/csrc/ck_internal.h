@@ -1,0 +1,136 @@
+// ck_internal.h -- device-side data layout and kernel launchers of libck.
+//
+// HBM layout of one table (caller storage, each array 256-byte aligned):
+//   slots  bins*B x 16 B   {u64 key, u64 aux}; B >= 2: aux = value;
+//                          B == 1: aux = value(32) | rattle(16) << 32
+//   meta   bins x 4 B      bits 0-7 duplicate marks, 8-11 spawn count,
+//                          24-31 hit counter
+//   owner  bins x 8 B      claim word of the round protocol:
+//                          (~epoch) << 32 | op index; the smallest word wins,
+//                          so a newer round always overrides an older one.
+// A bin of B >= 4 slots is one 64- or 128-byte line: one probe is one
+// coalesced HBM transaction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ck.h"
+
+namespace ck {
+
+constexpr uint64_t kEmpty = CK_EMPTY_KEY;
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+// Move flags: one entry of a plan (a write to one slot, or a mark update).
+enum : uint8_t {
+  MV_SUPERSEDED = 1,  // a later move of the same plan rewrites this slot
+  MV_DUP = 2,         // the written record is a ghost duplicate
+  MV_HC = 4,          // the write is an insertion counted by the hit counter
+  MV_DUPCLR = 8,      // no slot write: clear the duplicate mark only (ghost twin)
+  MV_CLEAR = 16,      // delete: the slot becomes empty
+};
+
+struct Move {            // 24 bytes
+  uint64_t key;
+  uint64_t aux;
+  uint32_t bin;
+  uint8_t slot;
+  uint8_t flags;
+  uint16_t pad;
+};
+
+enum : uint32_t { PL_FAIL = 0, PL_OK = 1, PL_EVICT = 2, PL_NOTFOUND = 3 };
+
+struct PlanHdr {         // per op of the sub-batch
+  uint32_t status;
+  uint32_t views;
+  uint32_t kicks;
+  uint32_t twins;
+  uint32_t n_moves;
+  uint32_t off;          // arena offset of the moves
+  uint32_t n_spawn;
+  uint32_t spawn_off;    // spawn arena offset (sorted search)
+};
+
+struct Ctr {             // device counters of one round
+  uint32_t next_pending;
+  uint32_t evict_count;
+  uint32_t evict_taken;
+  uint32_t arena_used;
+  uint32_t spawn_used;
+  uint32_t overflow;
+  uint32_t pad[2];
+};
+
+struct DevStats {        // device accumulators (mirrors ck_stats)
+  unsigned long long v[19];
+  unsigned long long band[4][CK_BANDS];
+};
+enum {
+  S_INS_OK, S_INS_FAIL, S_INS_ABORT, S_INS_BAD, S_VIEWS, S_VIEWS_ALL, S_KICKS, S_MAX_KICKS,
+  S_RETRIES, S_ROUNDS, S_TWINS, S_LOOKUPS, S_LOOKUP_HITS, S_LOOKUP_PROBES, S_DELETES,
+  S_DEL_FOUND, S_DEL_PROBES, S_DEL_RETRIES, S_STORED
+};
+
+// Everything a kernel needs about a table, passed by value.
+struct Geo {
+  uint64_t a[4], c[4];
+  ulonglong2* slots;
+  uint32_t* meta;
+  unsigned long long* owner;
+  uint32_t n;            // bins (< 2^32)
+  uint32_t B, H, scheme;
+  uint32_t ghost, balance, max_chain, max_search;
+  uint64_t rng_seed;
+};
+
+// Round-scratch pointers of one sub-batch.
+struct Round {
+  const uint64_t* keys;      // sub-batch keys
+  const void* vals;          // sub-batch values (8 or 4 bytes each)
+  const uint32_t* pend;      // pending op indices this round
+  uint32_t npend;
+  uint32_t* next;            // losers for the next round
+  uint32_t* evict;           // ops that need an eviction plan
+  PlanHdr* hdr;
+  Move* arena;
+  uint32_t arena_cap;
+  uint32_t* spawns;
+  uint32_t spawn_cap;
+  Ctr* ctr;
+  uint64_t op_base;          // global insert index of op 0 of the sub-batch
+  unsigned long long tag;    // (~epoch) << 32
+  uint8_t* status;           // caller's per-op status (sub-batch view)
+  uint32_t* op_views;
+  uint32_t* op_views_all;
+  uint32_t* op_kicks;
+  uint32_t* op_retries;
+  uint32_t* op_twins;
+  uint32_t max_rounds;
+  uint32_t is_delete;
+  void* wg_scratch;          // per-workgroup scratch of the eviction planners
+  uint32_t wg_scratch_bytes;
+  DevStats* stats;
+};
+
+// ---- launchers (ck_kernels.hip) ----
+hipError_t launch_init(const Geo& g, hipStream_t s);
+hipError_t launch_lookup(const Geo& g, const uint64_t* keys, uint64_t n, void* vals_out,
+                         uint8_t* found, uint32_t lpp, DevStats* st, hipStream_t s);
+hipError_t launch_round_begin(Ctr* c, hipStream_t s);
+hipError_t launch_batch_begin(const uint64_t* keys, uint64_t m, uint32_t* pend, uint8_t* status,
+                              uint32_t* views, uint32_t* views_all, uint32_t* kicks,
+                              uint32_t* retries, uint32_t* twins, uint32_t bad_status,
+                              Ctr* ctr, hipStream_t s);
+hipError_t launch_plan_fresh(const Geo& g, const Round& r, hipStream_t s);
+hipError_t launch_plan_evict(const Geo& g, const Round& r, uint32_t grid, hipStream_t s);
+hipError_t launch_plan_delete(const Geo& g, const Round& r, hipStream_t s);
+hipError_t launch_commit(const Geo& g, const Round& r, hipStream_t s);
+hipError_t launch_batch_stats(const Round& r, uint64_t m, uint64_t slots, uint32_t* block_tmp,
+                              uint32_t is_delete, hipStream_t s);
+size_t evict_lds_bytes(const Geo& g);
+size_t evict_wg_scratch_bytes(const Geo& g);
+hipError_t launch_export_meta(const Geo& g, hipStream_t s);
+
+}  // namespace ck

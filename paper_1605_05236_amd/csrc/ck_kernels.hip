@@ -1,0 +1,1367 @@
+// ck_kernels.hip -- gfx950 kernels of libck.
+//
+// Kernel map (one sub-batch of inserts runs plan -> commit rounds):
+//   k_init          empty table (keys all-ones, metadata zero, claims reset)
+//   k_lookup        lane group of LPP lanes per query; each probe loads one
+//                   bin as one coalesced 64/128-byte access and ballots for the
+//                   key (Sec. 1: the key is in one of its bins)
+//   k_plan_fresh    lane group of B lanes per pending insert: views the key's
+//                   bins and plans the placement when no kick-out is needed
+//                   (first fit, load balancing, ghost insertion, duplicate
+//                   reuse); every other op is handed to an eviction planner
+//   k_plan_walk     one wavefront per op: random kicking, queue-kicking,
+//                   rattle-kicking; the chain is logged in LDS and later bin
+//                   reads see the chain's own earlier writes
+//   k_plan_search   one wavefront per op: BFS and sorted search; visited-bin
+//                   set and spawn list in LDS, record list in per-workgroup
+//                   global scratch
+//   k_plan_delete   lane group per pending delete
+//   k_commit        8 lanes per plan: claim check, reverse-order chain write,
+//                   metadata atomics, spawn-count updates, losers re-queued
+//   k_stats_*       per-op counters -> totals and density bands
+//
+// Every planner reads the round-start snapshot only and claims each bin it
+// will write with a 64-bit atomicMin on the bin's claim word.
+#include <hip/hip_runtime.h>
+
+#include "ck_internal.h"
+
+namespace ck {
+
+// ---------------------------------------------------------------------------
+// hashing and randomness
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// h_i(x) = floor(((a_i x + c_i) mod 2^64) * n / 2^64), stepped past clashes.
+template <int H>
+__device__ __forceinline__ void hash_key(const Geo& g, uint64_t x, uint32_t* h) {
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    uint32_t b = (uint32_t)__umul64hi(g.a[i] * x + g.c[i], (uint64_t)g.n);
+    for (;;) {
+      bool clash = false;
+#pragma unroll
+      for (int j = 0; j < i; ++j) clash |= (h[j] == b);
+      if (!clash) break;
+      b = (b + 1 == g.n) ? 0u : b + 1;
+    }
+    h[i] = b;
+  }
+}
+
+// Uniform choice in [0, m): draw t of op `op`; m == 1 consumes no draw.
+__device__ __forceinline__ uint32_t uniform_choice(const Geo& g, uint64_t op, uint32_t& draws,
+                                                   uint32_t m) {
+  if (m <= 1) return 0;
+  uint64_t r = mix64(g.rng_seed ^ (op * 0x9E3779B97F4A7C15ull) ^ (uint64_t)(draws + 1));
+  ++draws;
+  return (uint32_t)__umul64hi(r, (uint64_t)m);
+}
+
+__device__ __forceinline__ uint64_t load_aux(const void* vals, uint32_t i, int B) {
+  if (B == 1) return (uint64_t)((const uint32_t*)vals)[i];
+  return ((const uint64_t*)vals)[i];
+}
+
+__device__ __forceinline__ uint32_t ffs32(uint32_t m) { return (uint32_t)(__ffs(m) - 1); }
+
+__device__ __forceinline__ uint32_t rattle_of(uint64_t aux) { return (uint32_t)((aux >> 32) & 0xFFFF); }
+__device__ __forceinline__ uint64_t with_rattle(uint64_t aux, uint32_t r) {
+  return (aux & 0xFFFFFFFFull) | ((uint64_t)(r & 0xFFFF) << 32);
+}
+
+// ---------------------------------------------------------------------------
+// init
+// ---------------------------------------------------------------------------
+__global__ void k_init(Geo g) {
+  const uint64_t nslots = (uint64_t)g.n * g.B;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nslots; i += stride)
+    g.slots[i] = make_ulonglong2(kEmpty, 0ull);
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.n; i += stride) {
+    g.meta[i] = 0u;
+    g.owner[i] = ~0ull;
+  }
+}
+
+hipError_t launch_init(const Geo& g, hipStream_t s) {
+  hipLaunchKernelGGL(k_init, dim3(2048), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// block reduction helper (u64 sum over a block of up to 1024 threads)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ unsigned long long wave_max(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    unsigned long long w = __shfl_xor(v, o, 64);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// lookup: LPP lanes per query, B/LPP slots per lane
+// ---------------------------------------------------------------------------
+template <int B, int LPP, int H>
+__global__ __launch_bounds__(256) void k_lookup(Geo g, const uint64_t* __restrict__ keys,
+                                                uint64_t n, void* __restrict__ out,
+                                                uint8_t* __restrict__ found, DevStats* st) {
+  constexpr int SPL = B / LPP;
+  const int lane = threadIdx.x & 63;
+  const int gl = lane % LPP;
+  const int gshift = lane - gl;
+  const uint64_t gmask = (LPP == 64) ? ~0ull : ((1ull << LPP) - 1);
+  const uint64_t q = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPP;
+  const bool active = q < n;
+  const uint64_t x = active ? keys[q] : kEmpty;
+  uint32_t probes = 0;
+  bool hit = false;
+  uint64_t val = 0;
+  int winner = 0;
+  if (x != kEmpty) {
+    uint32_t h[H];
+    hash_key<H>(g, x, h);
+#pragma unroll
+    for (int hi = 0; hi < H; ++hi) {
+      const ulonglong2* p = g.slots + (uint64_t)h[hi] * B + gl * SPL;
+      ulonglong2 s[SPL];
+#pragma unroll
+      for (int k = 0; k < SPL; ++k) s[k] = p[k];
+      ++probes;
+      int mk = -1;
+#pragma unroll
+      for (int k = SPL - 1; k >= 0; --k)
+        if (s[k].x == x) mk = k;
+      const uint64_t m = (__ballot(mk >= 0) >> gshift) & gmask;
+      if (m) {
+        winner = __ffsll((unsigned long long)m) - 1;
+        if (gl == winner) {
+          uint64_t v = 0;
+#pragma unroll
+          for (int k = 0; k < SPL; ++k)
+            if (k == mk) v = s[k].y;
+          val = v;
+        }
+        hit = true;
+        break;
+      }
+    }
+  }
+  if (active && gl == winner) {
+    if (B == 1) ((uint32_t*)out)[q] = (uint32_t)val;
+    else ((uint64_t*)out)[q] = val;
+    found[q] = hit ? 1 : 0;
+  }
+  // counters: one contribution per query (lane gl == 0)
+  unsigned long long pr = (active && gl == 0) ? probes : 0;
+  unsigned long long ht = (active && gl == 0 && hit) ? 1 : 0;
+  pr = wave_sum(pr);
+  ht = wave_sum(ht);
+  if (lane == 0) {
+    if (pr) atomicAdd(&st->v[S_LOOKUP_PROBES], pr);
+    if (ht) atomicAdd(&st->v[S_LOOKUP_HITS], ht);
+  }
+}
+
+template <int B, int LPP, int H>
+static void lookup_go(const Geo& g, const uint64_t* keys, uint64_t n, void* out, uint8_t* found,
+                      DevStats* st, hipStream_t s) {
+  const uint64_t threads = n * LPP;
+  const uint32_t grid = (uint32_t)((threads + 255) / 256);
+  hipLaunchKernelGGL((k_lookup<B, LPP, H>), dim3(grid), dim3(256), 0, s, g, keys, n, out, found,
+                     st);
+}
+
+hipError_t launch_lookup(const Geo& g, const uint64_t* keys, uint64_t n, void* out,
+                         uint8_t* found, uint32_t lpp, DevStats* st, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const bool wide = (lpp == g.B);
+  switch (g.B) {
+    case 1:
+      if (g.H == 2) lookup_go<1, 1, 2>(g, keys, n, out, found, st, s);
+      else if (g.H == 3) lookup_go<1, 1, 3>(g, keys, n, out, found, st, s);
+      else lookup_go<1, 1, 4>(g, keys, n, out, found, st, s);
+      break;
+    case 2:
+      if (wide) lookup_go<2, 2, 2>(g, keys, n, out, found, st, s);
+      else lookup_go<2, 1, 2>(g, keys, n, out, found, st, s);
+      break;
+    case 4:
+      if (wide) lookup_go<4, 4, 2>(g, keys, n, out, found, st, s);
+      else lookup_go<4, 1, 2>(g, keys, n, out, found, st, s);
+      break;
+    case 8:
+      if (wide) lookup_go<8, 8, 2>(g, keys, n, out, found, st, s);
+      else lookup_go<8, 1, 2>(g, keys, n, out, found, st, s);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// round bookkeeping
+// ---------------------------------------------------------------------------
+__global__ void k_round_begin(Ctr* c) {
+  if (threadIdx.x == 0) {
+    c->next_pending = 0;
+    c->evict_count = 0;
+    c->evict_taken = 0;
+    c->arena_used = 0;
+    c->spawn_used = 0;
+    c->overflow = 0;
+  }
+}
+hipError_t launch_round_begin(Ctr* c, hipStream_t s) {
+  hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(64), 0, s, c);
+  return hipGetLastError();
+}
+
+__global__ void k_batch_begin(uint64_t m, uint32_t* pend, uint32_t* views, uint32_t* views_all,
+                              uint32_t* kicks, uint32_t* retries, uint32_t* twins) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+    pend[i] = (uint32_t)i;
+    views[i] = 0;
+    views_all[i] = 0;
+    kicks[i] = 0;
+    retries[i] = 0;
+    twins[i] = 0;
+  }
+}
+hipError_t launch_batch_begin(const uint64_t* keys, uint64_t m, uint32_t* pend, uint8_t* status,
+                              uint32_t* views, uint32_t* views_all, uint32_t* kicks,
+                              uint32_t* retries, uint32_t* twins, uint32_t bad_status, Ctr* ctr,
+                              hipStream_t s) {
+  (void)keys; (void)status; (void)bad_status; (void)ctr;
+  uint32_t grid = (uint32_t)std::min<uint64_t>((m + 255) / 256, 4096);
+  if (grid == 0) grid = 1;
+  hipLaunchKernelGGL(k_batch_begin, dim3(grid), dim3(256), 0, s, m, pend, views, views_all, kicks,
+                     retries, twins);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// plan emission helpers (called by one lane)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t arena_alloc(const Round& r, uint32_t n) {
+  if (n == 0) return 0;
+  uint32_t off = atomicAdd(&r.ctr->arena_used, n);
+  if (off + n > r.arena_cap) {
+    atomicOr(&r.ctr->overflow, 1u);
+    return kNone;
+  }
+  return off;
+}
+
+__device__ __forceinline__ void claim(const Geo& g, const Round& r, uint32_t bin, uint32_t i) {
+  atomicMin(&g.owner[bin], r.tag | (unsigned long long)i);
+}
+
+// ---------------------------------------------------------------------------
+// k_plan_fresh: B lanes per op, placement without eviction
+// ---------------------------------------------------------------------------
+template <int B>
+struct GroupCtx {
+  int lane, sl, gshift;
+  __device__ __forceinline__ uint32_t ballot(bool p) const {
+    return (uint32_t)((__ballot(p) >> gshift) & ((B == 64) ? ~0ull : ((1ull << B) - 1)));
+  }
+};
+
+template <int B, int H>
+__global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
+  GroupCtx<B> G;
+  G.lane = threadIdx.x & 63;
+  G.sl = G.lane % B;
+  G.gshift = G.lane - G.sl;
+  const uint64_t gidx = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / B;
+  if (gidx >= r.npend) return;
+  const uint32_t i = r.pend[gidx];
+  const uint64_t x = r.keys[i];
+  const bool leader = G.sl == 0;
+  if (x == kEmpty) {  // reserved key: rejected, no plan
+    if (leader) {
+      PlanHdr h{};
+      h.status = PL_FAIL;
+      h.n_moves = 0;
+      r.hdr[i] = h;
+    }
+    return;
+  }
+  const uint64_t xa = load_aux(r.vals, i, B);
+  const uint32_t hc_flag = (g.scheme == CK_QUEUE) ? MV_HC : 0;
+  if (g.scheme == CK_RATTLE) {  // rattle-kicking has no separate fresh phase
+    if (leader) {
+      uint32_t k = atomicAdd(&r.ctr->evict_count, 1u);
+      r.evict[k] = i;
+    }
+    return;
+  }
+  uint32_t h[H];
+  hash_key<H>(g, x, h);
+  // Up to three moves, group-uniform.
+  uint32_t mb[3], ms[3], mf[3];
+  uint64_t mk[3], ma[3];
+  uint32_t nm = 0, views = 0, twins = 0;
+  bool placed = false;
+  auto add = [&](uint32_t b, uint32_t s, uint64_t k, uint64_t a, uint32_t f) {
+    mb[nm] = b; ms[nm] = s; mk[nm] = k; ma[nm] = a; mf[nm] = f; ++nm;
+  };
+  if (g.ghost) {
+    ulonglong2 s0 = g.slots[(uint64_t)h[0] * B + G.sl];
+    ulonglong2 s1 = g.slots[(uint64_t)h[1] * B + G.sl];
+    views = 2;
+    uint32_t e0 = G.ballot(s0.x == kEmpty), e1 = G.ballot(s1.x == kEmpty);
+    if (e0 && e1) {
+      add(h[0], ffs32(e0), x, xa, MV_DUP | hc_flag);
+      add(h[1], ffs32(e1), x, xa, MV_DUP | hc_flag);
+      placed = true;
+    } else if (e0) {
+      add(h[0], ffs32(e0), x, xa, hc_flag);
+      placed = true;
+    } else if (e1) {
+      add(h[1], ffs32(e1), x, xa, hc_flag);
+      placed = true;
+    } else {
+      const uint32_t full = (B == 32) ? ~0u : ((1u << B) - 1);
+      uint32_t d0 = g.meta[h[0]] & full, d1 = g.meta[h[1]] & full;
+      if (d0 || d1) {
+        const int w = d0 ? 0 : 1;
+        const uint32_t b = h[w];
+        const uint32_t ds = ffs32(d0 ? d0 : d1);
+        const uint64_t dk = __shfl(w == 0 ? s0.x : s1.x, G.gshift + (int)ds, 64);
+        uint32_t hd[2];
+        hash_key<2>(g, dk, hd);
+        const uint32_t tb = hd[0] == b ? hd[1] : hd[0];
+        ulonglong2 ts = g.slots[(uint64_t)tb * B + G.sl];
+        uint32_t tm = G.ballot(ts.x == dk);
+        add(tb, ffs32(tm), 0, 0, MV_DUPCLR);
+        add(b, ds, x, xa, hc_flag);
+        twins = 1;
+        placed = true;
+      }
+    }
+  } else if (g.balance || g.scheme == CK_QUEUE) {
+    ulonglong2 s0 = g.slots[(uint64_t)h[0] * B + G.sl];
+    ulonglong2 s1 = g.slots[(uint64_t)h[1] * B + G.sl];
+    views = 2;
+    uint32_t e0 = G.ballot(s0.x == kEmpty), e1 = G.ballot(s1.x == kEmpty);
+    int o0 = B - __popc(e0), o1 = B - __popc(e1);
+    if (o0 < B || o1 < B) {
+      if (o0 <= o1) add(h[0], ffs32(e0), x, xa, hc_flag);
+      else add(h[1], ffs32(e1), x, xa, hc_flag);
+      placed = true;
+    }
+  } else {
+#pragma unroll
+    for (int hi = 0; hi < H; ++hi) {
+      ulonglong2 s = g.slots[(uint64_t)h[hi] * B + G.sl];
+      ++views;
+      uint32_t e = G.ballot(s.x == kEmpty);
+      if (e) {
+        add(h[hi], ffs32(e), x, xa, hc_flag);
+        placed = true;
+        break;
+      }
+    }
+  }
+  if (!leader) return;
+  if (!placed) {
+    uint32_t k = atomicAdd(&r.ctr->evict_count, 1u);
+    r.evict[k] = i;
+    return;
+  }
+  uint32_t off = arena_alloc(r, nm);
+  PlanHdr hd{};
+  hd.status = PL_OK;
+  hd.views = views;
+  hd.twins = twins;
+  hd.n_moves = nm;
+  hd.off = off;
+  r.hdr[i] = hd;
+  if (off == kNone) return;
+  for (uint32_t j = 0; j < nm; ++j) {
+    Move mv;
+    mv.key = mk[j];
+    mv.aux = ma[j];
+    mv.bin = mb[j];
+    mv.slot = (uint8_t)ms[j];
+    mv.flags = (uint8_t)mf[j];
+    mv.pad = 0;
+    r.arena[off + j] = mv;
+    claim(g, r, mb[j], i);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// wavefront planners (k_plan_walk, k_plan_search) share this context.
+// One workgroup = one wavefront = one op at a time.  Lanes 0..B-1 hold the
+// slots of the bin being viewed; all 64 lanes scan the LDS move log.
+// ---------------------------------------------------------------------------
+struct WaveLog {
+  uint64_t* key;
+  uint64_t* aux;
+  uint32_t* bin;
+  uint32_t* sf;   // slot | flags << 8
+  int* last;      // [8]
+  uint32_t* misc; // [8]: 0 hc adds, 1.. broadcast words
+};
+
+template <int B, int H>
+struct WavePlanner {
+  const Geo& g;
+  const Round& r;
+  WaveLog L;
+  int lane;
+  uint32_t cap;        // log capacity
+  uint32_t nm = 0;     // moves logged
+  uint32_t views = 0, kicks = 0, twins = 0, draws = 0;
+  uint64_t op = 0;     // global insert index
+  bool overflow = false;
+
+  // bin view state (lanes < B)
+  uint64_t vkey = kEmpty, vaux = 0;
+  bool vdup = false;
+  int vprev = -1;      // log index of the last write to this lane's slot
+  uint32_t vhc = 0;    // hit counter of the viewed bin (uniform)
+  uint32_t vbin = kNone;
+
+  __device__ WavePlanner(const Geo& g_, const Round& r_, WaveLog l, uint32_t cap_)
+      : g(g_), r(r_), L(l), lane(threadIdx.x), cap(cap_) {}
+
+  __device__ __forceinline__ uint32_t ballotB(bool p) const {
+    return (uint32_t)(__ballot(lane < B && p) & ((1ull << B) - 1));
+  }
+
+  // Load bin b into lanes < B, applying this plan's earlier writes.
+  // `count` = true makes it a bin view (Sec. 3 cost unit).
+  __device__ void load(uint32_t b, bool count) {
+    if (count) ++views;
+    ulonglong2 s = make_ulonglong2(kEmpty, 0ull);
+    if (lane < B) s = g.slots[(uint64_t)b * B + lane];
+    uint32_t m = (g.ghost || g.scheme == CK_QUEUE) ? g.meta[b] : 0u;
+    bool dup = lane < B && ((m >> lane) & 1u);
+    int prev = -1;
+    uint32_t hcadd = 0;
+    if (nm > 0) {
+      if (lane < 8) L.last[lane] = -1;
+      if (lane == 0) L.misc[0] = 0;
+      __syncthreads();
+      for (uint32_t j = lane; j < nm; j += 64) {
+        if (L.bin[j] == b) {
+          uint32_t sf = L.sf[j];
+          uint32_t f = sf >> 8;
+          if (!(f & MV_DUPCLR)) atomicMax(&L.last[sf & 0xFF], (int)j);
+          if (f & MV_HC) atomicAdd(&L.misc[0], 1u);
+        }
+      }
+      __syncthreads();
+      if (lane < B) {
+        prev = L.last[lane];
+        if (prev >= 0) {
+          s.x = L.key[prev];
+          s.y = L.aux[prev];
+          dup = (L.sf[prev] >> 8) & MV_DUP;
+        }
+      }
+      hcadd = L.misc[0];
+      __syncthreads();
+    }
+    vkey = s.x;
+    vaux = s.y;
+    vdup = dup && s.x != kEmpty;
+    vprev = prev;
+    vhc = ((m >> 24) + hcadd) & 0xFFu;
+    vbin = b;
+  }
+
+  __device__ __forceinline__ uint32_t empty_mask() const { return ballotB(vkey == kEmpty); }
+  __device__ __forceinline__ uint32_t dup_mask() const { return ballotB(vdup); }
+  __device__ __forceinline__ bool terminal() const {
+    return empty_mask() != 0 || (g.ghost && dup_mask() != 0);
+  }
+  __device__ __forceinline__ uint64_t slot_key(uint32_t s) const { return __shfl(vkey, (int)s, 64); }
+  __device__ __forceinline__ uint64_t slot_aux(uint32_t s) const { return __shfl(vaux, (int)s, 64); }
+
+  // Log a write of (key, aux) to slot s of the currently viewed bin.
+  __device__ void emit_here(uint32_t s, uint64_t k, uint64_t a, uint32_t flags) {
+    const int prev = __shfl(vprev, (int)s, 64);
+    if (nm >= cap) { overflow = true; return; }
+    if (lane == 0) {
+      if (prev >= 0) L.sf[prev] |= ((uint32_t)MV_SUPERSEDED << 8);
+      L.key[nm] = k;
+      L.aux[nm] = a;
+      L.bin[nm] = vbin;
+      L.sf[nm] = s | (flags << 8);
+    }
+    ++nm;
+    // keep the view coherent with the write (the walk may read this bin again)
+    if (lane == (int)s) {
+      vkey = k;
+      vaux = a;
+      vdup = (flags & MV_DUP) != 0;
+      vprev = (int)nm - 1;
+    }
+    if (flags & MV_HC) vhc = (vhc + 1) & 0xFFu;
+    __syncthreads();
+  }
+  __device__ void emit_other(uint32_t b, uint32_t s, uint64_t k, uint64_t a, uint32_t flags) {
+    if (nm >= cap) { overflow = true; return; }
+    if (lane == 0) {
+      L.key[nm] = k;
+      L.aux[nm] = a;
+      L.bin[nm] = b;
+      L.sf[nm] = s | (flags << 8);
+    }
+    ++nm;
+    __syncthreads();
+  }
+
+  // Drop the duplicate in slot s of the viewed bin and put (k, a) there; the
+  // twin copy in the duplicate key's other bin loses its mark (Sec. 4).
+  __device__ void replace_dup(uint32_t s, uint64_t k, uint64_t a, uint32_t flags) {
+    const uint64_t dk = slot_key(s);
+    uint32_t hd[2];
+    hash_key<2>(g, dk, hd);
+    const uint32_t here = vbin;
+    const uint32_t tb = hd[0] == here ? hd[1] : hd[0];
+    ulonglong2 ts = make_ulonglong2(kEmpty, 0ull);
+    if (lane < B) ts = g.slots[(uint64_t)tb * B + lane];
+    const uint32_t tm = ballotB(ts.x == dk);
+    emit_other(tb, ffs32(tm), 0, 0, MV_DUPCLR);
+    ++twins;
+    emit_here(s, k, a, flags);
+  }
+
+  // Put (k, a) into the viewed terminal bin: a free slot first, else a duplicate.
+  __device__ void place_terminal(uint64_t k, uint64_t a, uint32_t flags) {
+    const uint32_t e = empty_mask();
+    if (e) emit_here(ffs32(e), k, a, flags);
+    else replace_dup(ffs32(dup_mask()), k, a, flags);
+  }
+
+  // The fresh insert (no kick-out); same rules as k_plan_fresh.
+  __device__ bool place_fresh(uint64_t x, uint64_t xa, const uint32_t* h) {
+    const uint32_t hc_flag = (g.scheme == CK_QUEUE) ? MV_HC : 0;
+    if (g.ghost) {
+      load(h[0], true);
+      const uint32_t e0 = empty_mask(), d0 = dup_mask();
+      load(h[1], true);
+      const uint32_t e1 = empty_mask(), d1 = dup_mask();
+      if (e0 && e1) {
+        emit_other(h[0], ffs32(e0), x, xa, MV_DUP | hc_flag);
+        emit_here(ffs32(e1), x, xa, MV_DUP | hc_flag);
+        return true;
+      }
+      if (e0) { emit_other(h[0], ffs32(e0), x, xa, hc_flag); return true; }
+      if (e1) { emit_here(ffs32(e1), x, xa, hc_flag); return true; }
+      if (d0) {
+        load(h[0], false);  // back to the view of h[0] to reuse its duplicate
+        replace_dup(ffs32(d0), x, xa, hc_flag);
+        return true;
+      }
+      if (d1) { replace_dup(ffs32(d1), x, xa, hc_flag); return true; }
+      return false;
+    }
+    if (g.balance || g.scheme == CK_QUEUE) {
+      load(h[0], true);
+      const uint32_t e0 = empty_mask();
+      load(h[1], true);
+      const uint32_t e1 = empty_mask();
+      const int o0 = B - __popc(e0), o1 = B - __popc(e1);
+      if (o0 < B || o1 < B) {
+        if (o0 <= o1) emit_other(h[0], ffs32(e0), x, xa, hc_flag);
+        else emit_here(ffs32(e1), x, xa, hc_flag);
+        return true;
+      }
+      return false;
+    }
+    for (int hi = 0; hi < H; ++hi) {
+      load(h[hi], true);
+      const uint32_t e = empty_mask();
+      if (e) { emit_here(ffs32(e), x, xa, hc_flag); return true; }
+    }
+    return false;
+  }
+
+  // ---- random kicking (Sec. 1; d-ary: victim moves to one of its other bins)
+  __device__ uint32_t random_walk(uint64_t x, uint64_t xa, const uint32_t* h) {
+    if (place_fresh(x, xa, h)) return PL_OK;
+    uint32_t cur = h[uniform_choice(g, op, draws, H)];
+    load(cur, false);
+    uint64_t ck = x, ca = xa;
+    for (;;) {
+      if (kicks == g.max_chain) return PL_FAIL;
+      const uint32_t s = uniform_choice(g, op, draws, B);
+      const uint64_t vk = slot_key(s), va = slot_aux(s);
+      emit_here(s, ck, ca, 0);
+      if (overflow) return PL_FAIL;
+      ++kicks;
+      ck = vk;
+      ca = va;
+      uint32_t hv[H];
+      hash_key<H>(g, ck, hv);
+      uint32_t oth[H];
+      uint32_t no = 0;
+      for (int q = 0; q < H; ++q)
+        if (hv[q] != cur) oth[no++] = hv[q];
+      cur = oth[uniform_choice(g, op, draws, no)];
+      load(cur, true);
+      if (terminal()) {
+        place_terminal(ck, ca, 0);
+        return overflow ? PL_FAIL : PL_OK;
+      }
+    }
+  }
+
+  // ---- queue-kicking with hit counters and hit balancing (Sec. 6)
+  __device__ uint32_t queue_kick(uint64_t x, uint64_t xa, const uint32_t* h) {
+    if (place_fresh(x, xa, h)) return PL_OK;
+    const uint32_t hc0 = g.meta[h[0]] >> 24, hc1 = g.meta[h[1]] >> 24;
+    uint32_t t = hc0 <= hc1 ? h[0] : h[1];
+    load(t, false);
+    uint64_t ck = x, ca = xa;
+    for (;;) {
+      if (kicks == g.max_chain) return PL_FAIL;
+      const uint32_t s = vhc % B;
+      const uint64_t vk = slot_key(s), va = slot_aux(s);
+      emit_here(s, ck, ca, MV_HC);
+      if (overflow) return PL_FAIL;
+      ++kicks;
+      ck = vk;
+      ca = va;
+      uint32_t hv[2];
+      hash_key<2>(g, ck, hv);
+      t = hv[0] == t ? hv[1] : hv[0];
+      load(t, true);
+      if (terminal()) {
+        place_terminal(ck, ca, MV_HC);
+        return overflow ? PL_FAIL : PL_OK;
+      }
+    }
+  }
+
+  // ---- rattle-kicking (Sec. 7), single-slot bins
+  __device__ uint32_t rattle(uint64_t x, uint64_t xa) {
+    uint64_t ck = x, ca = with_rattle(xa, 0);
+    uint32_t tries = 0;
+    for (;;) {
+      if (tries == g.max_chain) return PL_FAIL;
+      uint32_t hv[H];
+      hash_key<H>(g, ck, hv);
+      uint32_t rr = rattle_of(ca);
+      const uint32_t b = hv[rr % H];
+      rr = (rr + 1) & 0xFFFF;
+      ca = with_rattle(ca, rr);
+      ++tries;
+      load(b, true);
+      const uint64_t yk = slot_key(0), ya = slot_aux(0);
+      if (yk == kEmpty) {
+        emit_here(0, ck, ca, 0);
+        return overflow ? PL_FAIL : PL_OK;
+      }
+      if (rr > rattle_of(ya)) {
+        emit_here(0, ck, ca, 0);
+        if (overflow) return PL_FAIL;
+        ++kicks;
+        ck = yk;
+        ca = ya;
+      }
+    }
+  }
+
+  // Copy the logged moves to the arena, write the header and claim bins.
+  __device__ void finish(uint32_t i, uint32_t status, uint32_t n_spawn, uint32_t spawn_off) {
+    __shared__ uint32_t s_off;
+    if (status != PL_OK) nm = 0;
+    if (lane == 0) s_off = arena_alloc(r, nm);
+    __syncthreads();
+    const uint32_t off = s_off;
+    __syncthreads();
+    if (off != kNone) {
+      for (uint32_t j = lane; j < nm; j += 64) {
+        Move mv;
+        mv.key = L.key[j];
+        mv.aux = L.aux[j];
+        mv.bin = L.bin[j];
+        mv.slot = (uint8_t)(L.sf[j] & 0xFF);
+        mv.flags = (uint8_t)(L.sf[j] >> 8);
+        mv.pad = 0;
+        r.arena[off + j] = mv;
+        claim(g, r, mv.bin, i);
+      }
+    }
+    if (lane == 0) {
+      PlanHdr hd{};
+      hd.status = status;
+      hd.views = views;
+      hd.kicks = status == PL_OK ? kicks : 0;
+      hd.twins = status == PL_OK ? twins : 0;
+      hd.n_moves = nm;
+      hd.off = off;
+      hd.n_spawn = n_spawn;
+      hd.spawn_off = spawn_off;
+      r.hdr[i] = hd;
+    }
+    __syncthreads();
+  }
+};
+
+__device__ __forceinline__ uint32_t wave_take(const Round& r) {
+  __shared__ uint32_t s_k;
+  if (threadIdx.x == 0) s_k = atomicAdd(&r.ctr->evict_taken, 1u);
+  __syncthreads();
+  uint32_t k = s_k;
+  __syncthreads();
+  return k;
+}
+
+template <int B, int H>
+__global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
+  extern __shared__ uint64_t lds64[];
+  const uint32_t cap = g.max_chain + 8;
+  WaveLog L;
+  L.key = lds64;
+  L.aux = lds64 + cap;
+  L.bin = (uint32_t*)(lds64 + 2 * cap);
+  L.sf = L.bin + cap;
+  L.last = (int*)(L.sf + cap);
+  L.misc = (uint32_t*)(L.last + 8);
+  const uint32_t total = __hip_atomic_load(&r.ctr->evict_count, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+  for (;;) {
+    const uint32_t k = wave_take(r);
+    if (k >= total) break;
+    const uint32_t i = r.evict[k];
+    const uint64_t x = r.keys[i];
+    const uint64_t xa = load_aux(r.vals, i, B);
+    WavePlanner<B, H> P(g, r, L, cap);
+    P.op = r.op_base + i;
+    uint32_t h[H];
+    hash_key<H>(g, x, h);
+    uint32_t st;
+    if (g.scheme == CK_RATTLE) st = P.rattle(x, xa);
+    else if (g.scheme == CK_QUEUE) st = P.queue_kick(x, xa, h);
+    else st = P.random_walk(x, xa, h);
+    P.finish(i, st, 0, 0);
+  }
+}
+
+// ---- breadth-first and sorted search (Sec. 5) ------------------------------
+struct Ent {
+  uint64_t key;
+  uint32_t bin;
+  uint32_t ps;  // parent entry << 3 | slot ; parent kNone>>3 for root records
+};
+constexpr uint32_t kRootParent = 0x1FFFFFFFu;
+
+template <int B, int H>
+__global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
+  extern __shared__ uint64_t lds64[];
+  const uint32_t cap = g.max_search + 8;   // move log: path, terminal, twin
+  WaveLog L;
+  L.key = lds64;
+  L.aux = lds64 + cap;
+  L.bin = (uint32_t*)(lds64 + 2 * cap);
+  L.sf = L.bin + cap;
+  L.last = (int*)(L.sf + cap);
+  L.misc = (uint32_t*)(L.last + 8);
+  // visited set: open addressing on bin+1, capacity VC (power of two)
+  uint32_t VC = 1;
+  while (VC < 2 * (g.max_search + 8)) VC <<= 1;
+  uint32_t* vis = L.misc + 8;
+  uint32_t* spl = vis + VC;                    // spawn list (sorted search)
+  uint32_t* bhead = spl + g.max_search + 8;    // 16 bucket heads
+  uint32_t* btail = bhead + 16;
+  uint32_t* path = btail + 16;                 // path entries, up to max_search + 8
+  const int lane = threadIdx.x;
+  const bool sorted = g.scheme == CK_SORTED;
+  Ent* ent = (Ent*)((char*)r.wg_scratch + (size_t)blockIdx.x * r.wg_scratch_bytes);
+  const uint32_t ecap = (g.max_search + 8) * B;
+  uint32_t* nxt = (uint32_t*)(ent + ecap);
+  const uint32_t total = __hip_atomic_load(&r.ctr->evict_count, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+  const uint32_t vshift = 32 - (31 - __clz(VC));
+
+  auto vis_find_or_insert = [&](uint32_t b, bool insert) -> bool {
+    // all lanes walk the same probe sequence; lane 0 writes
+    uint32_t pos = (b * 0x9E3779B1u) >> vshift;
+    for (;;) {
+      const uint32_t v = vis[pos];
+      if (v == b + 1) return true;
+      if (v == 0) {
+        if (insert) {
+          if (lane == 0) vis[pos] = b + 1;
+          __syncthreads();
+        }
+        return false;
+      }
+      pos = (pos + 1) & (VC - 1);
+    }
+  };
+
+  for (;;) {
+    const uint32_t k = wave_take(r);
+    if (k >= total) break;
+    const uint32_t i = r.evict[k];
+    const uint64_t x = r.keys[i];
+    const uint64_t xa = load_aux(r.vals, i, B);
+    WavePlanner<B, H> P(g, r, L, cap);
+    P.op = r.op_base + i;
+    uint32_t h[H];
+    hash_key<H>(g, x, h);
+    if (P.place_fresh(x, xa, h)) {
+      P.finish(i, PL_OK, 0, 0);
+      continue;
+    }
+    for (uint32_t j = lane; j < VC; j += 64) vis[j] = 0;
+    if (lane < 16) { bhead[lane] = kNone; btail[lane] = kNone; }
+    __syncthreads();
+    uint32_t head = 0, tail = 0, nsp = 0;
+    // enqueue the records of bin b (already loaded into lanes < B), parent p
+    auto enqueue = [&](uint32_t b, uint32_t parent, uint32_t bucket) {
+      if (lane < B) {
+        Ent e;
+        e.key = P.vkey;
+        e.bin = b;
+        e.ps = (parent << 3) | (uint32_t)lane;
+        ent[tail + lane] = e;
+        if (sorted) nxt[tail + lane] = (lane + 1 < B) ? tail + lane + 1 : kNone;
+      }
+      if (sorted && lane == 0) {
+        if (btail[bucket] == kNone) bhead[bucket] = tail;
+        else nxt[btail[bucket]] = tail;
+        btail[bucket] = tail + B - 1;
+      }
+      tail += B;
+      __syncthreads();
+    };
+    for (int q = 0; q < H; ++q) {
+      vis_find_or_insert(h[q], true);
+      P.load(h[q], false);
+      const uint32_t bk = sorted ? min(15u, (g.meta[h[q]] >> 8) & 0xFu) : 0u;
+      enqueue(h[q], kRootParent, bk);
+    }
+    uint32_t st = PL_FAIL;
+    bool done = false;
+    while (!done) {
+      uint32_t e;
+      if (!sorted) {
+        if (head == tail) break;
+        e = head++;
+      } else {
+        int kb = -1;
+        for (int q = 0; q < 16; ++q)
+          if (bhead[q] != kNone) { kb = q; break; }
+        if (kb < 0) break;
+        e = bhead[kb];
+        __syncthreads();
+        if (lane == 0) {
+          const uint32_t nx = nxt[e];
+          bhead[kb] = nx;
+          if (nx == kNone) btail[kb] = kNone;
+        }
+        __syncthreads();
+      }
+      const Ent E = ent[e];
+      uint32_t hv[H];
+      hash_key<H>(g, E.key, hv);
+      bool spawned = false;
+      for (int q = 0; q < H && !done; ++q) {
+        const uint32_t c = hv[q];
+        if (c == E.bin) continue;
+        if (vis_find_or_insert(c, false)) continue;
+        if (P.views == g.max_search) { done = true; break; }
+        if (!spawned && sorted) {
+          if (lane == 0) spl[nsp] = E.bin;
+          ++nsp;
+        }
+        spawned = true;
+        vis_find_or_insert(c, true);
+        P.load(c, true);
+        if (P.terminal()) {
+          // path: e, parent(e), ..., root record
+          uint32_t depth = 0;
+          uint32_t cur = e;
+          for (;;) {
+            if (lane == 0) path[depth] = cur;
+            ++depth;
+            const uint32_t par = ent[cur].ps >> 3;
+            if (par == kRootParent) break;
+            cur = par;
+          }
+          __syncthreads();
+          // contents of the path records, from the snapshot
+          // moves in chain order: x -> root position, ..., e's record -> c
+          // (the terminal write goes through place_terminal on the view of c)
+          for (uint32_t d = depth; d-- > 0;) {
+            const Ent pe = ent[path[d]];
+            uint64_t content_k, content_a;
+            if (d + 1 == depth) {
+              content_k = x;
+              content_a = xa;
+            } else {
+              const Ent ce = ent[path[d + 1]];
+              const ulonglong2 sv = g.slots[(uint64_t)ce.bin * B + (ce.ps & 7)];
+              content_k = sv.x;
+              content_a = sv.y;
+            }
+            P.emit_other(pe.bin, pe.ps & 7, content_k, content_a, 0);
+            ++P.kicks;
+          }
+          const Ent le = ent[path[0]];
+          const ulonglong2 lv = g.slots[(uint64_t)le.bin * B + (le.ps & 7)];
+          P.place_terminal(lv.x, lv.y, 0);
+          st = P.overflow ? PL_FAIL : PL_OK;
+          done = true;
+          break;
+        }
+        const uint32_t bk = sorted ? min(15u, (g.meta[c] >> 8) & 0xFu) : 0u;
+        enqueue(c, e, bk);
+      }
+    }
+    // spawn counts go to the spawn arena for every plan, winning or not
+    uint32_t soff = 0;
+    if (sorted && nsp > 0) {
+      __shared__ uint32_t s_soff;
+      if (lane == 0) {
+        uint32_t o = atomicAdd(&r.ctr->spawn_used, nsp);
+        if (o + nsp > r.spawn_cap) {
+          atomicOr(&r.ctr->overflow, 1u);
+          o = kNone;
+        }
+        s_soff = o;
+      }
+      __syncthreads();
+      soff = s_soff;
+      __syncthreads();
+      if (soff != kNone)
+        for (uint32_t j = lane; j < nsp; j += 64) r.spawns[soff + j] = spl[j];
+      else
+        nsp = 0;
+    }
+    P.finish(i, st, nsp, soff);
+  }
+}
+
+size_t evict_lds_bytes(const Geo& g) {
+  if (g.scheme == CK_BFS || g.scheme == CK_SORTED) {
+    const size_t cap = g.max_search + 8;
+    size_t VC = 1;
+    while (VC < 2 * (g.max_search + 8)) VC <<= 1;
+    return cap * 24 + 8 * 4 + 8 * 4 + VC * 4 + (g.max_search + 8) * 4 + 32 * 4 +
+           (g.max_search + 8) * 4 + 64;
+  }
+  const size_t cap = g.max_chain + 8;
+  return cap * 24 + 8 * 4 + 8 * 4 + 64;
+}
+
+size_t evict_wg_scratch_bytes(const Geo& g) {
+  if (g.scheme == CK_BFS || g.scheme == CK_SORTED) {
+    size_t b = (size_t)(g.max_search + 8) * g.B * (sizeof(Ent) + 4);
+    return (b + 255) & ~(size_t)255;
+  }
+  return 256;
+}
+
+template <int B, int H>
+static void evict_go(const Geo& g, const Round& r, uint32_t grid, hipStream_t s) {
+  const size_t lds = evict_lds_bytes(g);
+  if (g.scheme == CK_BFS || g.scheme == CK_SORTED)
+    hipLaunchKernelGGL((k_plan_search<B, H>), dim3(grid), dim3(64), lds, s, g, r);
+  else
+    hipLaunchKernelGGL((k_plan_walk<B, H>), dim3(grid), dim3(64), lds, s, g, r);
+}
+
+template <int B, int H>
+static void fresh_go(const Geo& g, const Round& r, hipStream_t s) {
+  const uint64_t threads = (uint64_t)r.npend * B;
+  const uint32_t grid = (uint32_t)((threads + 255) / 256);
+  hipLaunchKernelGGL((k_plan_fresh<B, H>), dim3(grid), dim3(256), 0, s, g, r);
+}
+
+#define CK_DISPATCH(FN, ...)                                  \
+  switch (g.B) {                                              \
+    case 1:                                                   \
+      if (g.H == 2) FN<1, 2>(__VA_ARGS__);                    \
+      else if (g.H == 3) FN<1, 3>(__VA_ARGS__);               \
+      else FN<1, 4>(__VA_ARGS__);                             \
+      break;                                                  \
+    case 2: FN<2, 2>(__VA_ARGS__); break;                     \
+    case 4: FN<4, 2>(__VA_ARGS__); break;                     \
+    case 8: FN<8, 2>(__VA_ARGS__); break;                     \
+    default: return hipErrorInvalidValue;                     \
+  }
+
+hipError_t launch_plan_fresh(const Geo& g, const Round& r, hipStream_t s) {
+  if (r.npend == 0) return hipSuccess;
+  CK_DISPATCH(fresh_go, g, r, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_evict(const Geo& g, const Round& r, uint32_t grid, hipStream_t s) {
+  if (r.npend == 0) return hipSuccess;
+  CK_DISPATCH(evict_go, g, r, grid, s);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// delete planning: B lanes per op
+// ---------------------------------------------------------------------------
+template <int B, int H>
+__global__ __launch_bounds__(256) void k_plan_delete(Geo g, Round r) {
+  GroupCtx<B> G;
+  G.lane = threadIdx.x & 63;
+  G.sl = G.lane % B;
+  G.gshift = G.lane - G.sl;
+  const uint64_t gidx = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / B;
+  if (gidx >= r.npend) return;
+  const uint32_t i = r.pend[gidx];
+  const uint64_t x = r.keys[i];
+  const bool leader = G.sl == 0;
+  uint32_t mb[2], ms[2];
+  uint32_t nm = 0, probes = 0;
+  uint32_t status = PL_NOTFOUND;
+  if (x != kEmpty) {
+    uint32_t h[H];
+    hash_key<H>(g, x, h);
+#pragma unroll
+    for (int hi = 0; hi < H; ++hi) {
+      ulonglong2 s = g.slots[(uint64_t)h[hi] * B + G.sl];
+      ++probes;
+      const uint32_t m = G.ballot(s.x == x);
+      if (m) {
+        const uint32_t slot = ffs32(m);
+        mb[nm] = h[hi];
+        ms[nm] = slot;
+        ++nm;
+        if (g.ghost && ((g.meta[h[hi]] >> slot) & 1u)) {
+          const uint32_t tb = h[1 - hi];
+          ulonglong2 t = g.slots[(uint64_t)tb * B + G.sl];
+          ++probes;
+          const uint32_t tm = G.ballot(t.x == x);
+          mb[nm] = tb;
+          ms[nm] = ffs32(tm);
+          ++nm;
+        }
+        status = PL_OK;
+        break;
+      }
+    }
+  }
+  if (!leader) return;
+  uint32_t off = arena_alloc(r, nm);
+  PlanHdr hd{};
+  hd.status = x == kEmpty ? PL_FAIL : status;
+  hd.views = probes;
+  hd.n_moves = nm;
+  hd.off = off;
+  r.hdr[i] = hd;
+  if (off == kNone) return;
+  for (uint32_t j = 0; j < nm; ++j) {
+    Move mv;
+    mv.key = kEmpty;
+    mv.aux = 0;
+    mv.bin = mb[j];
+    mv.slot = (uint8_t)ms[j];
+    mv.flags = MV_CLEAR;
+    mv.pad = 0;
+    r.arena[off + j] = mv;
+    claim(g, r, mb[j], i);
+  }
+}
+
+template <int B, int H>
+static void delete_go(const Geo& g, const Round& r, hipStream_t s) {
+  const uint64_t threads = (uint64_t)r.npend * B;
+  const uint32_t grid = (uint32_t)((threads + 255) / 256);
+  hipLaunchKernelGGL((k_plan_delete<B, H>), dim3(grid), dim3(256), 0, s, g, r);
+}
+
+hipError_t launch_plan_delete(const Geo& g, const Round& r, hipStream_t s) {
+  if (r.npend == 0) return hipSuccess;
+  CK_DISPATCH(delete_go, g, r, s);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// commit: 8 lanes per plan
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void sc_increment(uint32_t* meta) {
+  uint32_t old = __hip_atomic_load(meta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (;;) {
+    const uint32_t sc = (old >> 8) & 0xFu;
+    if (sc >= 15) return;
+    const uint32_t nw = (old & ~0xF00u) | ((sc + 1) << 8);
+    const uint32_t seen = atomicCAS(meta, old, nw);
+    if (seen == old) return;
+    old = seen;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
+  const int lane = threadIdx.x & 63;
+  const int gl = lane & 7;
+  const int gshift = lane & ~7;
+  const uint64_t gidx = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  if (gidx >= r.npend) return;
+  const uint32_t i = r.pend[gidx];
+  const bool leader = gl == 0;
+  const bool void_round = __hip_atomic_load(&r.ctr->overflow, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT) != 0;
+  if (void_round) {  // a planner ran out of arena: nothing of this round applies
+    if (leader) r.next[atomicAdd(&r.ctr->next_pending, 1u)] = i;
+    return;
+  }
+  const PlanHdr h = r.hdr[i];
+  const uint64_t me = r.tag | (unsigned long long)i;
+  bool mine = true;
+  for (uint32_t j = gl; j < h.n_moves; j += 8) {
+    const Move mv = r.arena[h.off + j];
+    if (g.owner[mv.bin] != me) mine = false;
+  }
+  const bool win = ((__ballot(!mine) >> gshift) & 0xFFull) == 0;
+  if (win) {
+    // chain written from its end backwards (Sec. 8.2 system-transaction order)
+    for (int base = (int)h.n_moves - 1; base >= 0; base -= 8) {
+      const int j = base - gl;
+      if (j < 0) continue;
+      const Move mv = r.arena[h.off + j];
+      uint32_t* mw = g.meta + mv.bin;
+      if (mv.flags & MV_DUPCLR) {
+        atomicAnd(mw, ~(1u << mv.slot));
+        continue;
+      }
+      if (!(mv.flags & MV_SUPERSEDED)) {
+        g.slots[(uint64_t)mv.bin * g.B + mv.slot] = (mv.flags & MV_CLEAR)
+                                                        ? make_ulonglong2(kEmpty, 0ull)
+                                                        : make_ulonglong2(mv.key, mv.aux);
+        if (g.ghost) {
+          if (mv.flags & MV_DUP) atomicOr(mw, 1u << mv.slot);
+          else atomicAnd(mw, ~(1u << mv.slot));
+        }
+      }
+      if (mv.flags & MV_HC) atomicAdd(mw, 1u << 24);
+    }
+    if (leader) {
+      uint8_t st;
+      if (r.keys[i] == kEmpty) st = CK_OP_BAD_KEY;
+      else if (r.is_delete) st = h.status == PL_OK ? CK_OP_OK : CK_OP_NOT_FOUND;
+      else st = h.status == PL_OK ? CK_OP_OK : CK_OP_FAIL_CHAIN;
+      r.status[i] = st;
+      r.op_views[i] = h.views;
+      r.op_kicks[i] = h.kicks;
+      r.op_twins[i] = h.twins;
+      r.op_views_all[i] += h.views;
+    }
+  } else if (leader) {
+    r.op_views_all[i] += h.views;
+    const uint32_t rt = r.op_retries[i] + 1;
+    r.op_retries[i] = rt;
+    if (r.max_rounds && rt >= r.max_rounds) {
+      r.status[i] = CK_OP_ABORTED;
+      r.op_views[i] = 0;
+    } else {
+      r.next[atomicAdd(&r.ctr->next_pending, 1u)] = i;
+    }
+  }
+  // spawn counts (Sec. 5) of every plan, committed or not, saturating at 15
+  for (uint32_t j = gl; j < h.n_spawn; j += 8) sc_increment(g.meta + r.spawns[h.spawn_off + j]);
+}
+
+hipError_t launch_commit(const Geo& g, const Round& r, hipStream_t s) {
+  if (r.npend == 0) return hipSuccess;
+  const uint64_t threads = (uint64_t)r.npend * 8;
+  const uint32_t grid = (uint32_t)((threads + 255) / 256);
+  hipLaunchKernelGGL(k_commit, dim3(grid), dim3(256), 0, s, g, r);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// per-sub-batch statistics
+// ---------------------------------------------------------------------------
+constexpr int kStatBlock = 1024;
+
+// pass 1: successful inserts per block of 1024 ops
+__global__ __launch_bounds__(kStatBlock) void k_stats_count(const uint8_t* status, uint64_t m,
+                                                            uint32_t* block_ok) {
+  __shared__ uint32_t s_sum;
+  if (threadIdx.x == 0) s_sum = 0;
+  __syncthreads();
+  const uint64_t i = (uint64_t)blockIdx.x * kStatBlock + threadIdx.x;
+  const bool ok = i < m && status[i] == CK_OP_OK;
+  const uint64_t b = __ballot(ok);
+  if ((threadIdx.x & 63) == 0 && b) atomicAdd(&s_sum, (uint32_t)__popcll(b));
+  __syncthreads();
+  if (threadIdx.x == 0) block_ok[blockIdx.x] = s_sum;
+}
+
+// pass 2 (one block): exclusive scan of the block counts; snapshot `stored`
+__global__ __launch_bounds__(kStatBlock) void k_stats_scan(uint32_t* block_ok, uint32_t nblocks,
+                                                           DevStats* st, uint64_t* stored_before) {
+  __shared__ uint32_t carry;
+  __shared__ uint32_t wsum[kStatBlock / 64];
+  if (threadIdx.x == 0) {
+    carry = 0;
+    *stored_before = st->v[S_STORED];
+  }
+  __syncthreads();
+  for (uint32_t base = 0; base < nblocks; base += kStatBlock) {
+    const uint32_t idx = base + threadIdx.x;
+    const uint32_t v = idx < nblocks ? block_ok[idx] : 0;
+    // inclusive scan within the wave
+    uint32_t x = v;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[threadIdx.x >> 6] = x;
+    __syncthreads();
+    uint32_t wpre = 0;
+    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wpre += wsum[w];
+    const uint32_t excl = carry + wpre + x - v;
+    __syncthreads();
+    if (idx < nblocks) block_ok[idx] = excl;
+    if (threadIdx.x == kStatBlock - 1) carry = excl + v;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) st->v[S_STORED] += carry;
+}
+
+// pass 3: density band of every op, totals
+__global__ __launch_bounds__(kStatBlock) void k_stats_apply(
+    const uint8_t* status, const uint32_t* views, const uint32_t* views_all, const uint32_t* kicks,
+    const uint32_t* retries, const uint32_t* twins, uint64_t m, const uint32_t* block_ok,
+    const uint64_t* stored_before, uint64_t slots, DevStats* st) {
+  __shared__ unsigned long long hb[4][CK_BANDS];
+  __shared__ unsigned long long tot[11];
+  __shared__ uint32_t wsum[kStatBlock / 64];
+  for (int j = threadIdx.x; j < 4 * CK_BANDS; j += kStatBlock) hb[j / CK_BANDS][j % CK_BANDS] = 0;
+  if (threadIdx.x < 11) tot[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t i = (uint64_t)blockIdx.x * kStatBlock + threadIdx.x;
+  const uint8_t s = i < m ? status[i] : 0xFF;
+  const bool ok = s == CK_OP_OK;
+  const int lane = threadIdx.x & 63;
+  const uint64_t bal = __ballot(ok);
+  const uint32_t before_in_wave = __popcll(bal & ((1ull << lane) - 1));
+  if (lane == 0) wsum[threadIdx.x >> 6] = __popcll(bal);
+  __syncthreads();
+  uint32_t wpre = 0;
+  for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wpre += wsum[w];
+  const uint64_t rank = (uint64_t)block_ok[blockIdx.x] + wpre + before_in_wave;
+  unsigned long long a_ok = 0, a_fail = 0, a_abort = 0, a_bad = 0, a_views = 0, a_vall = 0,
+                     a_kicks = 0, a_maxk = 0, a_ret = 0, a_tw = 0;
+  if (i < m) {
+    if (s == CK_OP_BAD_KEY) {
+      a_bad = 1;
+    } else {
+      a_ret = retries[i];
+      a_vall = views_all[i];
+      if (s == CK_OP_ABORTED) {
+        a_abort = 1;
+      } else {
+        uint64_t band = (uint64_t)CK_BANDS * (*stored_before + rank) / slots;
+        if (band >= CK_BANDS) band = CK_BANDS - 1;
+        atomicAdd(&hb[0][band], 1ull);
+        atomicAdd(&hb[1][band], (unsigned long long)views[i]);
+        a_views = views[i];
+        if (ok) {
+          a_ok = 1;
+          a_kicks = kicks[i];
+          a_maxk = kicks[i];
+          a_tw = twins[i];
+          atomicAdd(&hb[2][band], (unsigned long long)kicks[i]);
+        } else {
+          a_fail = 1;
+          atomicAdd(&hb[3][band], 1ull);
+        }
+      }
+    }
+  }
+  a_ok = wave_sum(a_ok); a_fail = wave_sum(a_fail); a_abort = wave_sum(a_abort);
+  a_bad = wave_sum(a_bad); a_views = wave_sum(a_views); a_vall = wave_sum(a_vall);
+  a_kicks = wave_sum(a_kicks); a_maxk = wave_max(a_maxk); a_ret = wave_sum(a_ret);
+  a_tw = wave_sum(a_tw);
+  if (lane == 0) {
+    atomicAdd(&tot[0], a_ok); atomicAdd(&tot[1], a_fail); atomicAdd(&tot[2], a_abort);
+    atomicAdd(&tot[3], a_bad); atomicAdd(&tot[4], a_views); atomicAdd(&tot[5], a_vall);
+    atomicAdd(&tot[6], a_kicks); atomicMax(&tot[7], a_maxk); atomicAdd(&tot[8], a_ret);
+    atomicAdd(&tot[9], a_tw);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int map[10] = {S_INS_OK, S_INS_FAIL, S_INS_ABORT, S_INS_BAD, S_VIEWS,
+                         S_VIEWS_ALL, S_KICKS, S_MAX_KICKS, S_RETRIES, S_TWINS};
+    for (int j = 0; j < 10; ++j) {
+      if (!tot[j]) continue;
+      if (j == 7) atomicMax(&st->v[S_MAX_KICKS], tot[j]);
+      else atomicAdd(&st->v[map[j]], tot[j]);
+    }
+  }
+  for (int j = threadIdx.x; j < 4 * CK_BANDS; j += kStatBlock) {
+    const unsigned long long v = hb[j / CK_BANDS][j % CK_BANDS];
+    if (v) atomicAdd(&st->band[j / CK_BANDS][j % CK_BANDS], v);
+  }
+}
+
+// deletes: found/probes/retries totals; `stored` decreases by the found count
+__global__ __launch_bounds__(256) void k_stats_delete(const uint8_t* status, const uint32_t* probes,
+                                                      const uint32_t* retries, uint64_t m,
+                                                      DevStats* st) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long d = 0, f = 0, p = 0, rt = 0;
+  if (i < m && status[i] != CK_OP_BAD_KEY) {
+    d = 1;
+    f = status[i] == CK_OP_OK;
+    p = probes[i];
+    rt = retries[i];
+  }
+  d = wave_sum(d); f = wave_sum(f); p = wave_sum(p); rt = wave_sum(rt);
+  if ((threadIdx.x & 63) == 0) {
+    if (d) atomicAdd(&st->v[S_DELETES], d);
+    if (f) {
+      atomicAdd(&st->v[S_DEL_FOUND], f);
+      atomicAdd(&st->v[S_STORED], (unsigned long long)(0ull - f));
+    }
+    if (p) atomicAdd(&st->v[S_DEL_PROBES], p);
+    if (rt) atomicAdd(&st->v[S_DEL_RETRIES], rt);
+  }
+}
+
+hipError_t launch_batch_stats(const Round& r, uint64_t m, uint64_t slots, uint32_t* block_tmp,
+                              uint32_t is_delete, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  if (is_delete) {
+    hipLaunchKernelGGL(k_stats_delete, dim3((uint32_t)((m + 255) / 256)), dim3(256), 0, s,
+                       r.status, r.op_views, r.op_retries, m, r.stats);
+    return hipGetLastError();
+  }
+  const uint32_t nb = (uint32_t)((m + kStatBlock - 1) / kStatBlock);
+  uint64_t* stored_before = (uint64_t*)(block_tmp + ((nb + 63) & ~63u));
+  hipLaunchKernelGGL(k_stats_count, dim3(nb), dim3(kStatBlock), 0, s, r.status, m, block_tmp);
+  hipLaunchKernelGGL(k_stats_scan, dim3(1), dim3(kStatBlock), 0, s, block_tmp, nb, r.stats,
+                     stored_before);
+  hipLaunchKernelGGL(k_stats_apply, dim3(nb), dim3(kStatBlock), 0, s, r.status, r.op_views,
+                     r.op_views_all, r.op_kicks, r.op_retries, r.op_twins, m, block_tmp,
+                     stored_before, slots, r.stats);
+  return hipGetLastError();
+}
+
+}  // namespace ck

@@ -1,0 +1,172 @@
+"""GPU parity: the HIP library (called through its C ABI) against the oracle,
+element by element on the same seeded inputs.  Integer work, so the bar is
+bit-exact: per-op status, bins viewed, kicks and lost rounds; the whole table
+image (keys, values, rattle counters, metadata words); and every counter."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import checks
+from gpu_util import (assert_same_image, assert_same_ops, assert_same_stats, gpu_delete,
+                      gpu_insert, gpu_lookup, gpu_table, keys_for, oracle_table)
+from paper_1605_05236_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+# (scheme, B, d, ghost, load_balance) -- every scheme, with and without ghosts
+GEOMS = [
+    ("random_walk", 4, 2, False, False),
+    ("random_walk", 4, 2, True, False),
+    ("random_walk", 8, 2, False, True),
+    ("random_walk", 2, 2, False, False),
+    ("random_walk", 1, 3, False, False),
+    ("random_walk", 1, 4, False, False),
+    ("bfs", 4, 2, False, False),
+    ("bfs", 8, 2, True, False),
+    ("bfs", 1, 4, False, False),
+    ("sorted", 4, 2, False, False),
+    ("sorted", 8, 2, False, False),
+    ("sorted", 4, 2, True, False),
+    ("sorted", 1, 3, False, False),
+    ("queue", 4, 2, False, False),
+    ("queue", 8, 2, True, False),
+    ("queue", 2, 2, False, False),
+    ("rattle", 1, 2, False, False),
+    ("rattle", 1, 3, False, False),
+    ("rattle", 1, 4, False, False),
+]
+
+
+def ident(p):
+    return "-".join(str(x) for x in p)
+
+
+@pytest.mark.parametrize("geom", GEOMS, ids=ident)
+@pytest.mark.parametrize("batch", [1 << 8, 777])
+def test_fill_parity(geom, batch):
+    scheme, B, d, ghost, lb = geom
+    n = 1 << 12 if B > 1 else 1 << 13
+    load = {1: 0.95 if d == 4 else (0.9 if d == 3 else 0.48)}.get(B, 0.97)
+    keys, vals = keys_for(n, B, load, seed=3)
+    kw = dict(ghost=ghost, load_balance=lb, max_chain=1000 if B == 1 else 500, max_search=500,
+              batch_ops=batch)
+    print(f"fill parity {geom} batch={batch} n={n} keys={keys.size}", flush=True)
+    g = gpu_table(n, B, d, scheme, seed=3, **kw)
+    o = oracle_table(n, B, d, scheme, seed=3, **kw)
+    rg = gpu_insert(g, keys, vals)
+    ro = o.insert(keys, vals)
+    assert_same_ops(rg, ro, f"{geom}")
+    assert_same_image(g.export(), o.export(), f"{geom}")
+    assert_same_stats(g.stats(), o.stats(), f"{geom}")
+    # the table answers for every key it accepted
+    ok = ro["status"] == 1
+    v, f = gpu_lookup(g, keys[ok])
+    assert f.all() and np.array_equal(v, vals[ok])
+
+
+MIXED = [GEOMS[i] for i in (0, 1, 4, 6, 9, 11, 13, 14, 17)]
+
+
+@pytest.mark.parametrize("geom", MIXED, ids=ident)
+def test_mixed_stream_parity(geom):
+    # lookups, deletes (present, absent, repeated) and inserts interleaved
+    scheme, B, d, ghost, lb = geom
+    n = 1 << 11 if B > 1 else 1 << 12
+    kw = dict(ghost=ghost, load_balance=lb, max_chain=1000, batch_ops=300)
+    g = gpu_table(n, B, d, scheme, seed=5, **kw)
+    o = oracle_table(n, B, d, scheme, seed=5, **kw)
+    keys, vals = keys_for(n, B, 0.99, seed=9)
+    rng = np.random.default_rng(5)
+    live = []
+    pos = 0
+    for step in range(12):
+        m = int(0.08 * keys.size)
+        ks, vs = keys[pos:pos + m], vals[pos:pos + m]
+        pos += m
+        rg, ro = gpu_insert(g, ks, vs), o.insert(ks, vs)
+        assert_same_ops(rg, ro, f"{geom} step {step} insert")
+        live.extend(ks[ro["status"] == 1].tolist())
+        if live:
+            pick = np.array(live, np.uint64)[rng.integers(0, len(live), 50)]
+            pick = np.concatenate([pick, keys[-20:], pick[:5]])
+            fg, fo = gpu_delete(g, pick), o.delete(pick)[0]
+            assert np.array_equal(fg, fo), f"{geom} step {step} delete"
+            gone = set(pick[fo == 1].tolist())
+            live = [k for k in live if k not in gone]
+        q = np.concatenate([np.array(live[:200], np.uint64), keys[-40:]])
+        vg, fg = gpu_lookup(g, q)
+        vo, fo = o.lookup(q)
+        assert np.array_equal(fg, fo) and np.array_equal(vg, vo)
+        assert_same_image(g.export(), o.export(), f"{geom} step {step}")
+    assert_same_stats(g.stats(), o.stats(), f"{geom}")
+    checks.check_invariants(g.export(), n, B, d, 105, ghost=ghost, rattle=scheme == "rattle")
+
+
+@pytest.mark.parametrize("B,d", [(1, 2), (1, 3), (1, 4), (2, 2), (4, 2), (8, 2)])
+@pytest.mark.parametrize("lpp", [0, 1])
+def test_lookup_parity_on_imported_table(B, d, lpp):
+    # a table built by the oracle alone, uploaded, then queried on the GPU
+    n = 1 << 12
+    o = oracle_table(n, B, d, "random_walk" if B > 1 else "rattle", seed=7, max_chain=1000)
+    keys, vals = keys_for(n, B, 0.9 if B > 1 else (0.45 if d == 2 else 0.85), seed=11)
+    o.insert(keys, vals)
+    g = gpu_table(n, B, d, "random_walk" if B > 1 else "rattle", seed=7)
+    g.load(o.export())
+    q, _ = inputs.lookup_mix(13, keys, keys.size, 5000, 0.5, key_seed=11)
+    q = np.concatenate([q, np.array([0xFFFFFFFFFFFFFFFF], np.uint64)])
+    vg, fg = gpu_lookup(g, q, lpp)
+    vo, fo = o.lookup(q)
+    assert np.array_equal(fg, fo)
+    assert np.array_equal(vg, vo)
+    assert g.stats()["lookup_probes"] == o.stats()["lookup_probes"]
+
+
+def test_edge_cases():
+    g = gpu_table(64, 2, 2, "random_walk", seed=1, max_chain=0, batch_ops=16)
+    o = oracle_table(64, 2, 2, "random_walk", seed=1, max_chain=0, batch_ops=16)
+    # empty batch
+    empty = np.zeros(0, np.uint64)
+    assert gpu_insert(g, np.array([5], np.uint64), np.array([6], np.uint64))["status"][0] == 1
+    o.insert(np.array([5], np.uint64), np.array([6], np.uint64))
+    # reserved key, cap of zero kicks (every eviction fails), ragged batch
+    keys, vals = inputs.keys_values(17, 150)
+    keys[3] = np.uint64(0xFFFFFFFFFFFFFFFF)
+    rg, ro = gpu_insert(g, keys, vals), o.insert(keys, vals)
+    assert_same_ops(rg, ro, "edge")
+    assert rg["status"][3] == 4 and (rg["status"] == 2).any()
+    assert_same_image(g.export(), o.export(), "edge")
+    assert_same_stats(g.stats(), o.stats(), "edge")
+    from paper_1605_05236_amd.table import CuckooTable
+    import torch
+    t = g
+    z = torch.zeros(0, dtype=torch.int64, device="cuda")
+    assert t.insert(z, z)["status"].numel() == 0
+    assert t.lookup(z)[1].numel() == 0
+    assert t.delete(z).numel() == 0
+    del empty, CuckooTable
+
+
+def test_max_rounds_abort():
+    # max_rounds = 1: every op that loses its first claim is aborted, and
+    # both sides abort the same ops
+    kw = dict(batch_ops=4096, max_rounds=1)
+    g = gpu_table(1 << 9, 4, 2, "queue", seed=2, **kw)
+    o = oracle_table(1 << 9, 4, 2, "queue", seed=2, **kw)
+    keys, vals = keys_for(1 << 9, 4, 0.9, seed=2)
+    rg, ro = gpu_insert(g, keys, vals), o.insert(keys, vals)
+    assert (ro["status"] == 3).any()
+    assert_same_ops(rg, ro, "abort")
+    assert_same_image(g.export(), o.export(), "abort")
+    assert_same_stats(g.stats(), o.stats(), "abort")
+
+
+def test_round_mode_repeatable():
+    # same inputs, same bytes, whatever the thread timing
+    imgs = []
+    for _ in range(2):
+        g = gpu_table(1 << 12, 8, 2, "sorted", seed=4, ghost=True, batch_ops=1 << 12)
+        keys, vals = keys_for(1 << 12, 8, 0.97, seed=4)
+        gpu_insert(g, keys, vals)
+        imgs.append(g.export())
+    assert_same_image(imgs[0], imgs[1], "repeat")
