@@ -125,6 +125,10 @@ ck_status ck_create(uint64_t bins, uint32_t slots_per_bin, uint32_t d, ck_scheme
                     const ck_options* opt, void* d_storage, size_t storage_bytes,
                     void* stream, ck_table** out);
 
+/* Empty the table (every slot, metadata and claim word), zero its counters and
+   restart its insert-op count, on `stream`; storage and scratch are kept. */
+ck_status ck_clear(ck_table* t, void* stream);
+
 /* Insert n keys with their values (8-byte values, 4-byte for single-slot
    bins).  Keys must be absent from the table and distinct within the call
    (Sec. 3: inserts do not check for presence); violating this is undefined.

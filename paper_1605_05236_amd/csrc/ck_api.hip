@@ -24,6 +24,7 @@ struct ck_table {
   uint32_t batch_cap = 0;
   uint32_t* pend[2] = {nullptr, nullptr};
   PlanHdr* hdr = nullptr;
+  IMove* imv = nullptr;
   uint32_t* evict = nullptr;
   Move* arena = nullptr;
   uint32_t arena_cap = 0;
@@ -88,6 +89,7 @@ void free_scratch(ck_table* t) {
   (void)hipFree(t->pend[0]);
   (void)hipFree(t->pend[1]);
   (void)hipFree(t->hdr);
+  (void)hipFree(t->imv);
   (void)hipFree(t->evict);
   (void)hipFree(t->arena);
   (void)hipFree(t->spawns);
@@ -102,22 +104,8 @@ void free_scratch(ck_table* t) {
 ck_status alloc_scratch(ck_table* t) {
   const uint32_t m = t->opt.batch_ops;
   t->batch_cap = m;
-  HIP_TRY(dalloc(&t->pend[0], m));
-  HIP_TRY(dalloc(&t->pend[1], m));
-  HIP_TRY(dalloc(&t->hdr, m));
-  HIP_TRY(dalloc(&t->evict, m));
-  for (auto& p : t->op) HIP_TRY(dalloc(&p, m));
-  t->arena_cap = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(4096, (uint64_t)m * 4), 1u << 30);
-  HIP_TRY(dalloc(&t->arena, t->arena_cap));
-  t->spawn_cap = t->scheme == CK_SORTED ? (uint32_t)std::max<uint64_t>(4096, (uint64_t)m * 2) : 16;
-  HIP_TRY(dalloc(&t->spawns, t->spawn_cap));
-  HIP_TRY(dalloc(&t->ctr, 1));
-  HIP_TRY(hipHostMalloc((void**)&t->h_ctr, sizeof(Ctr), hipHostMallocDefault));
-  HIP_TRY(dalloc(&t->dstats, 1));
-  HIP_TRY(hipMemset(t->dstats, 0, sizeof(DevStats)));
-  const uint32_t nb = (m + 1023) / 1024;
-  HIP_TRY(dalloc(&t->block_tmp, ((nb + 63) & ~63u) + 16));
-  // persistent eviction planners: workgroups that fit the LDS budget
+  // persistent eviction planners: as many one-wavefront workgroups as fit the
+  // LDS budget of a CU (160 KiB on gfx950), at most 16 per CU
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -126,6 +114,26 @@ ck_status alloc_scratch(ck_table* t) {
   t->evict_grid = (uint32_t)(cus * per_cu);
   t->wg_bytes = (uint32_t)evict_wg_scratch_bytes(t->g);
   HIP_TRY(hipMalloc(&t->wg_scratch, (size_t)t->evict_grid * t->wg_bytes));
+  HIP_TRY(dalloc(&t->pend[0], m));
+  HIP_TRY(dalloc(&t->pend[1], m));
+  HIP_TRY(dalloc(&t->hdr, m));
+  HIP_TRY(dalloc(&t->imv, (size_t)m * kInlineMoves));
+  HIP_TRY(dalloc(&t->evict, m));
+  for (auto& p : t->op) HIP_TRY(dalloc(&p, m));
+  // eviction plans sub-allocate from per-workgroup windows of 256 entries
+  const uint64_t slack = (uint64_t)t->evict_grid * 512;
+  t->arena_cap = (uint32_t)std::min<uint64_t>((uint64_t)m * 4 + slack, 1u << 30);
+  HIP_TRY(dalloc(&t->arena, t->arena_cap));
+  t->spawn_cap = t->scheme == CK_SORTED
+                     ? (uint32_t)std::min<uint64_t>((uint64_t)m * 2 + slack, 1u << 30)
+                     : 16;
+  HIP_TRY(dalloc(&t->spawns, t->spawn_cap));
+  HIP_TRY(dalloc(&t->ctr, 1));
+  HIP_TRY(hipHostMalloc((void**)&t->h_ctr, sizeof(Ctr), hipHostMallocDefault));
+  HIP_TRY(dalloc(&t->dstats, 1));
+  HIP_TRY(hipMemset(t->dstats, 0, sizeof(DevStats)));
+  const uint32_t nb = (m + 1023) / 1024;
+  HIP_TRY(dalloc(&t->block_tmp, ((nb + 63) & ~63u) + 16));
   return CK_OK;
 }
 
@@ -151,6 +159,7 @@ Round make_round(ck_table* t, const uint64_t* keys, const void* vals, uint8_t* s
   r.keys = keys;
   r.vals = vals;
   r.hdr = t->hdr;
+  r.imv = t->imv;
   r.evict = t->evict;
   r.arena = t->arena;
   r.arena_cap = t->arena_cap;
@@ -312,6 +321,16 @@ ck_status ck_create(uint64_t bins, uint32_t B, uint32_t d, ck_scheme scheme,
     return CK_EDEVICE;
   }
   *out = t;
+  return CK_OK;
+}
+
+ck_status ck_clear(ck_table* t, void* stream) {
+  if (!t) return CK_EINVAL;
+  HIP_TRY(launch_init(t->g, (hipStream_t)stream));
+  HIP_TRY(hipMemsetAsync(t->dstats, 0, sizeof(DevStats), (hipStream_t)stream));
+  t->insert_count = 0;
+  t->rounds = 0;
+  t->lookups = 0;
   return CK_OK;
 }
 

@@ -40,6 +40,15 @@ struct Move {            // 24 bytes
   uint16_t pad;
 };
 
+// A move stored inline with its op: the written record is the op's own key
+// and value (or nothing, for clears and duplicate-mark updates).
+struct IMove {           // 8 bytes
+  uint32_t bin;
+  uint32_t sf;           // slot | flags << 8
+};
+constexpr uint32_t kInlineMoves = 3;
+constexpr uint32_t kInline = 0xFFFFFFFEu;  // PlanHdr::off of a plan with inline moves
+
 enum : uint32_t { PL_FAIL = 0, PL_OK = 1, PL_EVICT = 2, PL_NOTFOUND = 3 };
 
 struct PlanHdr {         // per op of the sub-batch
@@ -94,6 +103,7 @@ struct Round {
   uint32_t* next;            // losers for the next round
   uint32_t* evict;           // ops that need an eviction plan
   PlanHdr* hdr;
+  IMove* imv;                // kInlineMoves per op
   Move* arena;
   uint32_t arena_cap;
   uint32_t* spawns;

@@ -111,6 +111,38 @@ __device__ __forceinline__ unsigned long long wave_max(unsigned long long v) {
   return v;
 }
 
+// Append to a device list with one atomic per wavefront: every active lane
+// calls it; lanes with `pred` get consecutive positions.
+__device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool pred) {
+  const uint64_t b = __ballot(pred);
+  if (b == 0) return 0;
+  const int first = __ffsll((unsigned long long)b) - 1;
+  const int lane = threadIdx.x & 63;
+  uint32_t base = 0;
+  if (lane == first) base = atomicAdd(counter, (uint32_t)__popcll(b));
+  base = __shfl(base, first, 64);
+  return base + (uint32_t)__popcll(b & ((1ull << lane) - 1));
+}
+
+// Block-wide sum of two counters, one atomic per block and counter.
+__device__ __forceinline__ void block_add2(unsigned long long a, unsigned long long b,
+                                           unsigned long long* da, unsigned long long* db) {
+  __shared__ unsigned long long s_acc[2];
+  if (threadIdx.x == 0) { s_acc[0] = 0; s_acc[1] = 0; }
+  __syncthreads();
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if ((threadIdx.x & 63) == 0) {
+    if (a) atomicAdd(&s_acc[0], a);
+    if (b) atomicAdd(&s_acc[1], b);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_acc[0]) atomicAdd(da, s_acc[0]);
+    if (s_acc[1]) atomicAdd(db, s_acc[1]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // lookup: LPP lanes per query, B/LPP slots per lane
 // ---------------------------------------------------------------------------
@@ -119,67 +151,68 @@ __global__ __launch_bounds__(256) void k_lookup(Geo g, const uint64_t* __restric
                                                 uint64_t n, void* __restrict__ out,
                                                 uint8_t* __restrict__ found, DevStats* st) {
   constexpr int SPL = B / LPP;
+  constexpr int QPB = 256 / LPP;  // queries per block and iteration
   const int lane = threadIdx.x & 63;
   const int gl = lane % LPP;
   const int gshift = lane - gl;
   const uint64_t gmask = (LPP == 64) ? ~0ull : ((1ull << LPP) - 1);
-  const uint64_t q = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / LPP;
-  const bool active = q < n;
-  const uint64_t x = active ? keys[q] : kEmpty;
-  uint32_t probes = 0;
-  bool hit = false;
-  uint64_t val = 0;
-  int winner = 0;
-  if (x != kEmpty) {
-    uint32_t h[H];
-    hash_key<H>(g, x, h);
+  unsigned long long probes_acc = 0, hits_acc = 0;
+  for (uint64_t base = (uint64_t)blockIdx.x * QPB; base < n;
+       base += (uint64_t)gridDim.x * QPB) {
+    const uint64_t q = base + threadIdx.x / LPP;
+    const bool active = q < n;
+    const uint64_t x = active ? keys[q] : kEmpty;
+    uint32_t probes = 0;
+    bool hit = false;
+    uint64_t val = 0;
+    int winner = 0;
+    if (x != kEmpty) {
+      uint32_t h[H];
+      hash_key<H>(g, x, h);
 #pragma unroll
-    for (int hi = 0; hi < H; ++hi) {
-      const ulonglong2* p = g.slots + (uint64_t)h[hi] * B + gl * SPL;
-      ulonglong2 s[SPL];
+      for (int hi = 0; hi < H; ++hi) {
+        const ulonglong2* p = g.slots + (uint64_t)h[hi] * B + gl * SPL;
+        ulonglong2 sl[SPL];
 #pragma unroll
-      for (int k = 0; k < SPL; ++k) s[k] = p[k];
-      ++probes;
-      int mk = -1;
+        for (int k = 0; k < SPL; ++k) sl[k] = p[k];
+        ++probes;
+        int mk = -1;
 #pragma unroll
-      for (int k = SPL - 1; k >= 0; --k)
-        if (s[k].x == x) mk = k;
-      const uint64_t m = (__ballot(mk >= 0) >> gshift) & gmask;
-      if (m) {
-        winner = __ffsll((unsigned long long)m) - 1;
-        if (gl == winner) {
-          uint64_t v = 0;
+        for (int k = SPL - 1; k >= 0; --k)
+          if (sl[k].x == x) mk = k;
+        const uint64_t m = (__ballot(mk >= 0) >> gshift) & gmask;
+        if (m) {
+          winner = __ffsll((unsigned long long)m) - 1;
+          if (gl == winner) {
+            uint64_t v = 0;
 #pragma unroll
-          for (int k = 0; k < SPL; ++k)
-            if (k == mk) v = s[k].y;
-          val = v;
+            for (int k = 0; k < SPL; ++k)
+              if (k == mk) v = sl[k].y;
+            val = v;
+          }
+          hit = true;
+          break;
         }
-        hit = true;
-        break;
       }
     }
+    if (active && gl == winner) {
+      if (B == 1) ((uint32_t*)out)[q] = (uint32_t)val;
+      else ((uint64_t*)out)[q] = val;
+      found[q] = hit ? 1 : 0;
+    }
+    if (active && gl == 0) {
+      probes_acc += probes;
+      hits_acc += hit ? 1 : 0;
+    }
   }
-  if (active && gl == winner) {
-    if (B == 1) ((uint32_t*)out)[q] = (uint32_t)val;
-    else ((uint64_t*)out)[q] = val;
-    found[q] = hit ? 1 : 0;
-  }
-  // counters: one contribution per query (lane gl == 0)
-  unsigned long long pr = (active && gl == 0) ? probes : 0;
-  unsigned long long ht = (active && gl == 0 && hit) ? 1 : 0;
-  pr = wave_sum(pr);
-  ht = wave_sum(ht);
-  if (lane == 0) {
-    if (pr) atomicAdd(&st->v[S_LOOKUP_PROBES], pr);
-    if (ht) atomicAdd(&st->v[S_LOOKUP_HITS], ht);
-  }
+  block_add2(probes_acc, hits_acc, &st->v[S_LOOKUP_PROBES], &st->v[S_LOOKUP_HITS]);
 }
 
 template <int B, int LPP, int H>
 static void lookup_go(const Geo& g, const uint64_t* keys, uint64_t n, void* out, uint8_t* found,
                       DevStats* st, hipStream_t s) {
-  const uint64_t threads = n * LPP;
-  const uint32_t grid = (uint32_t)((threads + 255) / 256);
+  const uint64_t blocks = (n * LPP + 255) / 256;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(blocks, 8192);
   hipLaunchKernelGGL((k_lookup<B, LPP, H>), dim3(grid), dim3(256), 0, s, g, keys, n, out, found,
                      st);
 }
@@ -257,15 +290,28 @@ hipError_t launch_batch_begin(const uint64_t* keys, uint64_t m, uint32_t* pend, 
 // ---------------------------------------------------------------------------
 // plan emission helpers (called by one lane)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t arena_alloc(const Round& r, uint32_t n) {
+// Sub-allocate n entries from a per-workgroup window of a global arena; the
+// window is refilled with one atomic.  win[0] = next, win[1] = end.  Returns
+// kNone (and flags the round void) when the arena is exhausted.  One lane.
+__device__ __forceinline__ uint32_t window_alloc(uint32_t* win, uint32_t* used, uint32_t cap,
+                                                 uint32_t n, uint32_t chunk, Ctr* ctr) {
   if (n == 0) return 0;
-  uint32_t off = atomicAdd(&r.ctr->arena_used, n);
-  if (off + n > r.arena_cap) {
-    atomicOr(&r.ctr->overflow, 1u);
-    return kNone;
+  if (win[0] + n > win[1] || win[1] == 0) {
+    const uint32_t want = n > chunk ? n : chunk;
+    const uint32_t b = atomicAdd(used, want);
+    if (b + want > cap) {
+      atomicOr(&ctr->overflow, 1u);
+      win[0] = win[1] = 0;
+      return kNone;
+    }
+    win[0] = b;
+    win[1] = b + want;
   }
+  const uint32_t off = win[0];
+  win[0] += n;
   return off;
 }
+constexpr uint32_t kWindow = 256;
 
 __device__ __forceinline__ void claim(const Geo& g, const Round& r, uint32_t bin, uint32_t i) {
   atomicMin(&g.owner[bin], r.tag | (unsigned long long)i);
@@ -293,118 +339,96 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
   const uint32_t i = r.pend[gidx];
   const uint64_t x = r.keys[i];
   const bool leader = G.sl == 0;
-  if (x == kEmpty) {  // reserved key: rejected, no plan
-    if (leader) {
-      PlanHdr h{};
-      h.status = PL_FAIL;
-      h.n_moves = 0;
-      r.hdr[i] = h;
-    }
-    return;
-  }
-  const uint64_t xa = load_aux(r.vals, i, B);
+  const bool bad = x == kEmpty;  // reserved key: rejected, no plan
   const uint32_t hc_flag = (g.scheme == CK_QUEUE) ? MV_HC : 0;
-  if (g.scheme == CK_RATTLE) {  // rattle-kicking has no separate fresh phase
-    if (leader) {
-      uint32_t k = atomicAdd(&r.ctr->evict_count, 1u);
-      r.evict[k] = i;
-    }
-    return;
-  }
-  uint32_t h[H];
-  hash_key<H>(g, x, h);
-  // Up to three moves, group-uniform.
-  uint32_t mb[3], ms[3], mf[3];
-  uint64_t mk[3], ma[3];
+  // up to two moves (slot | flags << 8), group-uniform, kept in registers;
+  // the written record is always this op's own key and value
+  uint32_t b0 = 0, f0 = 0, b1 = 0, f1 = 0;
   uint32_t nm = 0, views = 0, twins = 0;
   bool placed = false;
-  auto add = [&](uint32_t b, uint32_t s, uint64_t k, uint64_t a, uint32_t f) {
-    mb[nm] = b; ms[nm] = s; mk[nm] = k; ma[nm] = a; mf[nm] = f; ++nm;
-  };
-  if (g.ghost) {
-    ulonglong2 s0 = g.slots[(uint64_t)h[0] * B + G.sl];
-    ulonglong2 s1 = g.slots[(uint64_t)h[1] * B + G.sl];
-    views = 2;
-    uint32_t e0 = G.ballot(s0.x == kEmpty), e1 = G.ballot(s1.x == kEmpty);
-    if (e0 && e1) {
-      add(h[0], ffs32(e0), x, xa, MV_DUP | hc_flag);
-      add(h[1], ffs32(e1), x, xa, MV_DUP | hc_flag);
-      placed = true;
-    } else if (e0) {
-      add(h[0], ffs32(e0), x, xa, hc_flag);
-      placed = true;
-    } else if (e1) {
-      add(h[1], ffs32(e1), x, xa, hc_flag);
-      placed = true;
-    } else {
-      const uint32_t full = (B == 32) ? ~0u : ((1u << B) - 1);
-      uint32_t d0 = g.meta[h[0]] & full, d1 = g.meta[h[1]] & full;
-      if (d0 || d1) {
-        const int w = d0 ? 0 : 1;
-        const uint32_t b = h[w];
-        const uint32_t ds = ffs32(d0 ? d0 : d1);
-        const uint64_t dk = __shfl(w == 0 ? s0.x : s1.x, G.gshift + (int)ds, 64);
-        uint32_t hd[2];
-        hash_key<2>(g, dk, hd);
-        const uint32_t tb = hd[0] == b ? hd[1] : hd[0];
-        ulonglong2 ts = g.slots[(uint64_t)tb * B + G.sl];
-        uint32_t tm = G.ballot(ts.x == dk);
-        add(tb, ffs32(tm), 0, 0, MV_DUPCLR);
-        add(b, ds, x, xa, hc_flag);
-        twins = 1;
+  // rattle-kicking has no separate fresh phase: every op goes to the walk
+  if (!bad && g.scheme != CK_RATTLE) {
+    uint32_t h[H];
+    hash_key<H>(g, x, h);
+    if (g.ghost) {
+      const ulonglong2 s0 = g.slots[(uint64_t)h[0] * B + G.sl];
+      const ulonglong2 s1 = g.slots[(uint64_t)h[1] * B + G.sl];
+      views = 2;
+      const uint32_t e0 = G.ballot(s0.x == kEmpty), e1 = G.ballot(s1.x == kEmpty);
+      if (e0 && e1) {
+        b0 = h[0]; f0 = ffs32(e0) | ((MV_DUP | hc_flag) << 8);
+        b1 = h[1]; f1 = ffs32(e1) | ((MV_DUP | hc_flag) << 8);
+        nm = 2;
+        placed = true;
+      } else if (e0) {
+        b0 = h[0]; f0 = ffs32(e0) | (hc_flag << 8); nm = 1;
+        placed = true;
+      } else if (e1) {
+        b0 = h[1]; f0 = ffs32(e1) | (hc_flag << 8); nm = 1;
+        placed = true;
+      } else {
+        const uint32_t full = (1u << B) - 1;
+        const uint32_t d0 = g.meta[h[0]] & full, d1 = g.meta[h[1]] & full;
+        if (d0 || d1) {
+          const int w = d0 ? 0 : 1;
+          const uint32_t b = w == 0 ? h[0] : h[1];
+          const uint32_t ds = ffs32(d0 ? d0 : d1);
+          const uint64_t dk = __shfl(w == 0 ? s0.x : s1.x, G.gshift + (int)ds, 64);
+          uint32_t hd[2];
+          hash_key<2>(g, dk, hd);
+          const uint32_t tb = hd[0] == b ? hd[1] : hd[0];
+          const ulonglong2 ts = g.slots[(uint64_t)tb * B + G.sl];
+          const uint32_t tm = G.ballot(ts.x == dk);
+          b0 = tb; f0 = ffs32(tm) | (MV_DUPCLR << 8);
+          b1 = b; f1 = ds | (hc_flag << 8);
+          nm = 2;
+          twins = 1;
+          placed = true;
+        }
+      }
+    } else if (g.balance || g.scheme == CK_QUEUE) {
+      const ulonglong2 s0 = g.slots[(uint64_t)h[0] * B + G.sl];
+      const ulonglong2 s1 = g.slots[(uint64_t)h[1] * B + G.sl];
+      views = 2;
+      const uint32_t e0 = G.ballot(s0.x == kEmpty), e1 = G.ballot(s1.x == kEmpty);
+      const int o0 = B - __popc(e0), o1 = B - __popc(e1);
+      if (o0 < B || o1 < B) {
+        if (o0 <= o1) { b0 = h[0]; f0 = ffs32(e0) | (hc_flag << 8); }
+        else { b0 = h[1]; f0 = ffs32(e1) | (hc_flag << 8); }
+        nm = 1;
         placed = true;
       }
-    }
-  } else if (g.balance || g.scheme == CK_QUEUE) {
-    ulonglong2 s0 = g.slots[(uint64_t)h[0] * B + G.sl];
-    ulonglong2 s1 = g.slots[(uint64_t)h[1] * B + G.sl];
-    views = 2;
-    uint32_t e0 = G.ballot(s0.x == kEmpty), e1 = G.ballot(s1.x == kEmpty);
-    int o0 = B - __popc(e0), o1 = B - __popc(e1);
-    if (o0 < B || o1 < B) {
-      if (o0 <= o1) add(h[0], ffs32(e0), x, xa, hc_flag);
-      else add(h[1], ffs32(e1), x, xa, hc_flag);
-      placed = true;
-    }
-  } else {
+    } else {
 #pragma unroll
-    for (int hi = 0; hi < H; ++hi) {
-      ulonglong2 s = g.slots[(uint64_t)h[hi] * B + G.sl];
-      ++views;
-      uint32_t e = G.ballot(s.x == kEmpty);
-      if (e) {
-        add(h[hi], ffs32(e), x, xa, hc_flag);
-        placed = true;
-        break;
+      for (int hi = 0; hi < H; ++hi) {
+        const ulonglong2 sv = g.slots[(uint64_t)h[hi] * B + G.sl];
+        ++views;
+        const uint32_t e = G.ballot(sv.x == kEmpty);
+        if (e) {
+          b0 = h[hi]; f0 = ffs32(e) | (hc_flag << 8); nm = 1;
+          placed = true;
+          break;
+        }
       }
     }
   }
+  const bool to_evict = !bad && !placed;
+  const uint32_t pos = wave_append(&r.ctr->evict_count, leader && to_evict);
   if (!leader) return;
-  if (!placed) {
-    uint32_t k = atomicAdd(&r.ctr->evict_count, 1u);
-    r.evict[k] = i;
+  if (to_evict) {
+    r.evict[pos] = i;
     return;
   }
-  uint32_t off = arena_alloc(r, nm);
   PlanHdr hd{};
-  hd.status = PL_OK;
+  hd.status = bad ? PL_FAIL : PL_OK;
   hd.views = views;
   hd.twins = twins;
   hd.n_moves = nm;
-  hd.off = off;
+  hd.off = kInline;
   r.hdr[i] = hd;
-  if (off == kNone) return;
-  for (uint32_t j = 0; j < nm; ++j) {
-    Move mv;
-    mv.key = mk[j];
-    mv.aux = ma[j];
-    mv.bin = mb[j];
-    mv.slot = (uint8_t)ms[j];
-    mv.flags = (uint8_t)mf[j];
-    mv.pad = 0;
-    r.arena[off + j] = mv;
-    claim(g, r, mb[j], i);
-  }
+  IMove* im = r.imv + (size_t)i * kInlineMoves;
+  if (nm > 0) { im[0] = IMove{b0, f0}; claim(g, r, b0, i); }
+  if (nm > 1) { im[1] = IMove{b1, f1}; claim(g, r, b1, i); }
 }
 
 // ---------------------------------------------------------------------------
@@ -685,10 +709,12 @@ struct WavePlanner {
   }
 
   // Copy the logged moves to the arena, write the header and claim bins.
-  __device__ void finish(uint32_t i, uint32_t status, uint32_t n_spawn, uint32_t spawn_off) {
+  // `win` is the workgroup's arena window (LDS).
+  __device__ void finish(uint32_t i, uint32_t status, uint32_t n_spawn, uint32_t spawn_off,
+                         uint32_t* win) {
     __shared__ uint32_t s_off;
     if (status != PL_OK) nm = 0;
-    if (lane == 0) s_off = arena_alloc(r, nm);
+    if (lane == 0) s_off = window_alloc(win, &r.ctr->arena_used, r.arena_cap, nm, kWindow, r.ctr);
     __syncthreads();
     const uint32_t off = s_off;
     __syncthreads();
@@ -721,9 +747,11 @@ struct WavePlanner {
   }
 };
 
+// Next chunk of eviction ops for this workgroup (one atomic per chunk).
+constexpr uint32_t kTake = 4;
 __device__ __forceinline__ uint32_t wave_take(const Round& r) {
   __shared__ uint32_t s_k;
-  if (threadIdx.x == 0) s_k = atomicAdd(&r.ctr->evict_taken, 1u);
+  if (threadIdx.x == 0) s_k = atomicAdd(&r.ctr->evict_taken, kTake);
   __syncthreads();
   uint32_t k = s_k;
   __syncthreads();
@@ -733,6 +761,7 @@ __device__ __forceinline__ uint32_t wave_take(const Round& r) {
 template <int B, int H>
 __global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
   extern __shared__ uint64_t lds64[];
+  __shared__ uint32_t win[2];
   const uint32_t cap = g.max_chain + 8;
   WaveLog L;
   L.key = lds64;
@@ -741,23 +770,27 @@ __global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
   L.sf = L.bin + cap;
   L.last = (int*)(L.sf + cap);
   L.misc = (uint32_t*)(L.last + 8);
+  if (threadIdx.x == 0) { win[0] = 0; win[1] = 0; }
   const uint32_t total = __hip_atomic_load(&r.ctr->evict_count, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
   for (;;) {
-    const uint32_t k = wave_take(r);
-    if (k >= total) break;
-    const uint32_t i = r.evict[k];
-    const uint64_t x = r.keys[i];
-    const uint64_t xa = load_aux(r.vals, i, B);
-    WavePlanner<B, H> P(g, r, L, cap);
-    P.op = r.op_base + i;
-    uint32_t h[H];
-    hash_key<H>(g, x, h);
-    uint32_t st;
-    if (g.scheme == CK_RATTLE) st = P.rattle(x, xa);
-    else if (g.scheme == CK_QUEUE) st = P.queue_kick(x, xa, h);
-    else st = P.random_walk(x, xa, h);
-    P.finish(i, st, 0, 0);
+    const uint32_t k0 = wave_take(r);
+    if (k0 >= total) break;
+    const uint32_t k1 = min(k0 + kTake, total);
+    for (uint32_t k = k0; k < k1; ++k) {
+      const uint32_t i = r.evict[k];
+      const uint64_t x = r.keys[i];
+      const uint64_t xa = load_aux(r.vals, i, B);
+      WavePlanner<B, H> P(g, r, L, cap);
+      P.op = r.op_base + i;
+      uint32_t h[H];
+      hash_key<H>(g, x, h);
+      uint32_t st;
+      if (g.scheme == CK_RATTLE) st = P.rattle(x, xa);
+      else if (g.scheme == CK_QUEUE) st = P.queue_kick(x, xa, h);
+      else st = P.random_walk(x, xa, h);
+      P.finish(i, st, 0, 0, win);
+    }
   }
 }
 
@@ -771,28 +804,34 @@ constexpr uint32_t kRootParent = 0x1FFFFFFFu;
 
 template <int B, int H>
 __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
-  extern __shared__ uint64_t lds64[];
-  const uint32_t cap = g.max_search + 8;   // move log: path, terminal, twin
+  // LDS: visited-bin set, spawn list, 16 bucket heads/tails, path; the move
+  // log and the record list live in this workgroup's global scratch (the
+  // search never re-reads its own writes, so the log needs no fast overlay).
+  extern __shared__ uint32_t lds32[];
+  __shared__ uint32_t win[4];  // arena window, spawn window
+  const uint32_t ms8 = g.max_search + 8;
+  uint32_t VC = 1;  // visited set: open addressing on bin+1, power-of-two size
+  while (VC < 2 * ms8) VC <<= 1;
   WaveLog L;
-  L.key = lds64;
-  L.aux = lds64 + cap;
-  L.bin = (uint32_t*)(lds64 + 2 * cap);
-  L.sf = L.bin + cap;
-  L.last = (int*)(L.sf + cap);
-  L.misc = (uint32_t*)(L.last + 8);
-  // visited set: open addressing on bin+1, capacity VC (power of two)
-  uint32_t VC = 1;
-  while (VC < 2 * (g.max_search + 8)) VC <<= 1;
-  uint32_t* vis = L.misc + 8;
-  uint32_t* spl = vis + VC;                    // spawn list (sorted search)
-  uint32_t* bhead = spl + g.max_search + 8;    // 16 bucket heads
+  L.last = (int*)lds32;
+  L.misc = lds32 + 8;
+  uint32_t* vis = lds32 + 16;
+  uint32_t* spl = vis + VC;        // spawn list (sorted search)
+  uint32_t* bhead = spl + ms8;     // 16 bucket heads
   uint32_t* btail = bhead + 16;
-  uint32_t* path = btail + 16;                 // path entries, up to max_search + 8
+  uint32_t* path = btail + 16;     // path entries
+  const uint32_t cap = ms8;        // move log: path, terminal, twin
+  const uint32_t ecap = ms8 * B;
+  char* scratch = (char*)r.wg_scratch + (size_t)blockIdx.x * r.wg_scratch_bytes;
+  Ent* ent = (Ent*)scratch;
+  uint32_t* nxt = (uint32_t*)(ent + ecap);
+  L.key = (uint64_t*)(nxt + ecap + (ecap & 1));
+  L.aux = L.key + cap;
+  L.bin = (uint32_t*)(L.aux + cap);
+  L.sf = L.bin + cap;
   const int lane = threadIdx.x;
   const bool sorted = g.scheme == CK_SORTED;
-  Ent* ent = (Ent*)((char*)r.wg_scratch + (size_t)blockIdx.x * r.wg_scratch_bytes);
-  const uint32_t ecap = (g.max_search + 8) * B;
-  uint32_t* nxt = (uint32_t*)(ent + ecap);
+  if (lane < 4) win[lane] = 0;
   const uint32_t total = __hip_atomic_load(&r.ctr->evict_count, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
   const uint32_t vshift = 32 - (31 - __clz(VC));
@@ -814,10 +853,14 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
     }
   };
 
+  uint32_t k = 0, k1 = 0;
   for (;;) {
-    const uint32_t k = wave_take(r);
-    if (k >= total) break;
-    const uint32_t i = r.evict[k];
+    if (k == k1) {
+      k = wave_take(r);
+      if (k >= total) break;
+      k1 = min(k + kTake, total);
+    }
+    const uint32_t i = r.evict[k++];
     const uint64_t x = r.keys[i];
     const uint64_t xa = load_aux(r.vals, i, B);
     WavePlanner<B, H> P(g, r, L, cap);
@@ -825,7 +868,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
     uint32_t h[H];
     hash_key<H>(g, x, h);
     if (P.place_fresh(x, xa, h)) {
-      P.finish(i, PL_OK, 0, 0);
+      P.finish(i, PL_OK, 0, 0, win);
       continue;
     }
     for (uint32_t j = lane; j < VC; j += 64) vis[j] = 0;
@@ -938,14 +981,8 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
     uint32_t soff = 0;
     if (sorted && nsp > 0) {
       __shared__ uint32_t s_soff;
-      if (lane == 0) {
-        uint32_t o = atomicAdd(&r.ctr->spawn_used, nsp);
-        if (o + nsp > r.spawn_cap) {
-          atomicOr(&r.ctr->overflow, 1u);
-          o = kNone;
-        }
-        s_soff = o;
-      }
+      if (lane == 0)
+        s_soff = window_alloc(win + 2, &r.ctr->spawn_used, r.spawn_cap, nsp, kWindow, r.ctr);
       __syncthreads();
       soff = s_soff;
       __syncthreads();
@@ -954,17 +991,16 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
       else
         nsp = 0;
     }
-    P.finish(i, st, nsp, soff);
+    P.finish(i, st, nsp, soff, win);
   }
 }
 
 size_t evict_lds_bytes(const Geo& g) {
   if (g.scheme == CK_BFS || g.scheme == CK_SORTED) {
-    const size_t cap = g.max_search + 8;
+    const size_t ms8 = g.max_search + 8;
     size_t VC = 1;
-    while (VC < 2 * (g.max_search + 8)) VC <<= 1;
-    return cap * 24 + 8 * 4 + 8 * 4 + VC * 4 + (g.max_search + 8) * 4 + 32 * 4 +
-           (g.max_search + 8) * 4 + 64;
+    while (VC < 2 * ms8) VC <<= 1;
+    return (16 + VC + 2 * ms8 + 32) * 4 + 64;
   }
   const size_t cap = g.max_chain + 8;
   return cap * 24 + 8 * 4 + 8 * 4 + 64;
@@ -972,7 +1008,9 @@ size_t evict_lds_bytes(const Geo& g) {
 
 size_t evict_wg_scratch_bytes(const Geo& g) {
   if (g.scheme == CK_BFS || g.scheme == CK_SORTED) {
-    size_t b = (size_t)(g.max_search + 8) * g.B * (sizeof(Ent) + 4);
+    const size_t ms8 = g.max_search + 8;
+    const size_t ecap = ms8 * g.B;
+    size_t b = ecap * (sizeof(Ent) + 4) + (ecap & 1) * 4 + ms8 * 24;
     return (b + 255) & ~(size_t)255;
   }
   return 256;
@@ -1064,23 +1102,15 @@ __global__ __launch_bounds__(256) void k_plan_delete(Geo g, Round r) {
     }
   }
   if (!leader) return;
-  uint32_t off = arena_alloc(r, nm);
   PlanHdr hd{};
   hd.status = x == kEmpty ? PL_FAIL : status;
   hd.views = probes;
   hd.n_moves = nm;
-  hd.off = off;
+  hd.off = kInline;
   r.hdr[i] = hd;
-  if (off == kNone) return;
+  IMove* im = r.imv + (size_t)i * kInlineMoves;
   for (uint32_t j = 0; j < nm; ++j) {
-    Move mv;
-    mv.key = kEmpty;
-    mv.aux = 0;
-    mv.bin = mb[j];
-    mv.slot = (uint8_t)ms[j];
-    mv.flags = MV_CLEAR;
-    mv.pad = 0;
-    r.arena[off + j] = mv;
+    im[j] = IMove{mb[j], ms[j] | ((uint32_t)MV_CLEAR << 8)};
     claim(g, r, mb[j], i);
   }
 }
@@ -1123,64 +1153,95 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
   const bool leader = gl == 0;
   const bool void_round = __hip_atomic_load(&r.ctr->overflow, __ATOMIC_RELAXED,
                                             __HIP_MEMORY_SCOPE_AGENT) != 0;
+  bool requeue = false;
+  uint32_t n_spawn = 0, spawn_off = 0;
   if (void_round) {  // a planner ran out of arena: nothing of this round applies
-    if (leader) r.next[atomicAdd(&r.ctr->next_pending, 1u)] = i;
-    return;
-  }
-  const PlanHdr h = r.hdr[i];
-  const uint64_t me = r.tag | (unsigned long long)i;
-  bool mine = true;
-  for (uint32_t j = gl; j < h.n_moves; j += 8) {
-    const Move mv = r.arena[h.off + j];
-    if (g.owner[mv.bin] != me) mine = false;
-  }
-  const bool win = ((__ballot(!mine) >> gshift) & 0xFFull) == 0;
-  if (win) {
-    // chain written from its end backwards (Sec. 8.2 system-transaction order)
-    for (int base = (int)h.n_moves - 1; base >= 0; base -= 8) {
-      const int j = base - gl;
-      if (j < 0) continue;
-      const Move mv = r.arena[h.off + j];
-      uint32_t* mw = g.meta + mv.bin;
-      if (mv.flags & MV_DUPCLR) {
-        atomicAnd(mw, ~(1u << mv.slot));
-        continue;
+    requeue = true;
+  } else {
+    const PlanHdr h = r.hdr[i];
+    const bool inl = h.off == kInline;
+    const uint64_t x = r.keys[i];
+    const uint64_t xa = (inl && r.vals) ? load_aux(r.vals, i, g.B) : 0;
+    // move j of the plan: bin, slot, flags and the record it writes
+    auto get = [&](uint32_t j, uint32_t& bin, uint32_t& slot, uint32_t& fl, uint64_t& k,
+                   uint64_t& a) {
+      if (inl) {
+        const IMove m = r.imv[(size_t)i * kInlineMoves + j];
+        bin = m.bin;
+        slot = m.sf & 0xFF;
+        fl = m.sf >> 8;
+        k = x;
+        a = xa;
+      } else {
+        const Move m = r.arena[h.off + j];
+        bin = m.bin;
+        slot = m.slot;
+        fl = m.flags;
+        k = m.key;
+        a = m.aux;
       }
-      if (!(mv.flags & MV_SUPERSEDED)) {
-        g.slots[(uint64_t)mv.bin * g.B + mv.slot] = (mv.flags & MV_CLEAR)
-                                                        ? make_ulonglong2(kEmpty, 0ull)
-                                                        : make_ulonglong2(mv.key, mv.aux);
-        if (g.ghost) {
-          if (mv.flags & MV_DUP) atomicOr(mw, 1u << mv.slot);
-          else atomicAnd(mw, ~(1u << mv.slot));
+    };
+    const unsigned long long me = r.tag | (unsigned long long)i;
+    bool mine = true;
+    for (uint32_t j = gl; j < h.n_moves; j += 8) {
+      uint32_t bin, slot, fl;
+      uint64_t k, a;
+      get(j, bin, slot, fl, k, a);
+      if (g.owner[bin] != me) mine = false;
+    }
+    const bool win = ((__ballot(!mine) >> gshift) & 0xFFull) == 0;
+    if (win) {
+      // chain written from its end backwards (Sec. 8.2 system-transaction order)
+      for (int base = (int)h.n_moves - 1; base >= 0; base -= 8) {
+        const int j = base - gl;
+        if (j < 0) continue;
+        uint32_t bin, slot, fl;
+        uint64_t k, a;
+        get((uint32_t)j, bin, slot, fl, k, a);
+        uint32_t* mw = g.meta + bin;
+        if (fl & MV_DUPCLR) {
+          atomicAnd(mw, ~(1u << slot));
+          continue;
         }
+        if (!(fl & MV_SUPERSEDED)) {
+          g.slots[(uint64_t)bin * g.B + slot] =
+              (fl & MV_CLEAR) ? make_ulonglong2(kEmpty, 0ull) : make_ulonglong2(k, a);
+          if (g.ghost) {
+            if (fl & MV_DUP) atomicOr(mw, 1u << slot);
+            else atomicAnd(mw, ~(1u << slot));
+          }
+        }
+        if (fl & MV_HC) atomicAdd(mw, 1u << 24);
       }
-      if (mv.flags & MV_HC) atomicAdd(mw, 1u << 24);
-    }
-    if (leader) {
-      uint8_t st;
-      if (r.keys[i] == kEmpty) st = CK_OP_BAD_KEY;
-      else if (r.is_delete) st = h.status == PL_OK ? CK_OP_OK : CK_OP_NOT_FOUND;
-      else st = h.status == PL_OK ? CK_OP_OK : CK_OP_FAIL_CHAIN;
-      r.status[i] = st;
-      r.op_views[i] = h.views;
-      r.op_kicks[i] = h.kicks;
-      r.op_twins[i] = h.twins;
+      if (leader) {
+        uint8_t st;
+        if (x == kEmpty) st = CK_OP_BAD_KEY;
+        else if (r.is_delete) st = h.status == PL_OK ? CK_OP_OK : CK_OP_NOT_FOUND;
+        else st = h.status == PL_OK ? CK_OP_OK : CK_OP_FAIL_CHAIN;
+        r.status[i] = st;
+        r.op_views[i] = h.views;
+        r.op_kicks[i] = h.kicks;
+        r.op_twins[i] = h.twins;
+        r.op_views_all[i] += h.views;
+      }
+    } else if (leader) {
       r.op_views_all[i] += h.views;
+      const uint32_t rt = r.op_retries[i] + 1;
+      r.op_retries[i] = rt;
+      if (r.max_rounds && rt >= r.max_rounds) {
+        r.status[i] = CK_OP_ABORTED;
+        r.op_views[i] = 0;
+      } else {
+        requeue = true;
+      }
     }
-  } else if (leader) {
-    r.op_views_all[i] += h.views;
-    const uint32_t rt = r.op_retries[i] + 1;
-    r.op_retries[i] = rt;
-    if (r.max_rounds && rt >= r.max_rounds) {
-      r.status[i] = CK_OP_ABORTED;
-      r.op_views[i] = 0;
-    } else {
-      r.next[atomicAdd(&r.ctr->next_pending, 1u)] = i;
-    }
+    n_spawn = h.n_spawn;
+    spawn_off = h.spawn_off;
   }
+  const uint32_t pos = wave_append(&r.ctr->next_pending, leader && requeue);
+  if (leader && requeue) r.next[pos] = i;
   // spawn counts (Sec. 5) of every plan, committed or not, saturating at 15
-  for (uint32_t j = gl; j < h.n_spawn; j += 8) sc_increment(g.meta + r.spawns[h.spawn_off + j]);
+  for (uint32_t j = gl; j < n_spawn; j += 8) sc_increment(g.meta + r.spawns[spawn_off + j]);
 }
 
 hipError_t launch_commit(const Geo& g, const Round& r, hipStream_t s) {

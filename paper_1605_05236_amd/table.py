@@ -45,7 +45,7 @@ class CkError(RuntimeError):
 
 _lib = None
 
-EXPORTED = ["ck_default_options", "ck_storage_bytes", "ck_create", "ck_insert", "ck_insert_ex",
+EXPORTED = ["ck_default_options", "ck_storage_bytes", "ck_create", "ck_clear", "ck_insert", "ck_insert_ex",
             "ck_lookup", "ck_lookup_lpp", "ck_delete", "ck_stats_get", "ck_stats_reset",
             "ck_export", "ck_import", "ck_hash", "ck_insert_count", "ck_destroy", "ck_strerror"]
 
@@ -65,6 +65,7 @@ def load_library(path: str = LIB_PATH):
     L.ck_storage_bytes.argtypes = [u64, u32, u32, ctypes.POINTER(ctypes.c_size_t)]
     L.ck_create.argtypes = [u64, u32, u32, i32, ctypes.POINTER(CkOptions), vp, ctypes.c_size_t,
                             vp, ctypes.POINTER(vp)]
+    L.ck_clear.argtypes = [vp, vp]
     L.ck_insert.argtypes = [vp, vp, vp, u64, vp, vp]
     L.ck_insert_ex.argtypes = [vp, vp, vp, u64, vp, vp, vp, vp, vp]
     L.ck_lookup.argtypes = [vp, vp, u64, vp, vp, vp]
@@ -80,7 +81,7 @@ def load_library(path: str = LIB_PATH):
     L.ck_destroy.argtypes = [vp]
     L.ck_strerror.argtypes = [i32]
     L.ck_strerror.restype = ctypes.c_char_p
-    for f in ("ck_storage_bytes", "ck_create", "ck_insert", "ck_insert_ex", "ck_lookup",
+    for f in ("ck_storage_bytes", "ck_create", "ck_clear", "ck_insert", "ck_insert_ex", "ck_lookup",
               "ck_lookup_lpp", "ck_delete", "ck_stats_get", "ck_stats_reset", "ck_export",
               "ck_import", "ck_hash", "ck_destroy"):
         getattr(L, f).restype = i32
@@ -155,6 +156,10 @@ class CuckooTable:
             self.close()
         except Exception:
             pass
+
+    def clear(self, stream=None):
+        """Empty the table and zero its counters (storage is kept)."""
+        _check(self._L.ck_clear(self._h, _stream(stream)))
 
     # ---- batched operations (device tensors in, device tensors out)
     def insert(self, keys, vals, stream=None, diagnostics=True):
