@@ -771,8 +771,7 @@ __global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
   L.last = (int*)(L.sf + cap);
   L.misc = (uint32_t*)(L.last + 8);
   if (threadIdx.x == 0) { win[0] = 0; win[1] = 0; }
-  const uint32_t total = __hip_atomic_load(&r.ctr->evict_count, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
+  const uint32_t total = r.ctr->evict_count;  // final: written by the fresh planner
   for (;;) {
     const uint32_t k0 = wave_take(r);
     if (k0 >= total) break;
@@ -832,8 +831,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
   const int lane = threadIdx.x;
   const bool sorted = g.scheme == CK_SORTED;
   if (lane < 4) win[lane] = 0;
-  const uint32_t total = __hip_atomic_load(&r.ctr->evict_count, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
+  const uint32_t total = r.ctr->evict_count;  // final: written by the fresh planner
   const uint32_t vshift = 32 - (31 - __clz(VC));
 
   auto vis_find_or_insert = [&](uint32_t b, bool insert) -> bool {
@@ -1151,8 +1149,10 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
   if (gidx >= r.npend) return;
   const uint32_t i = r.pend[gidx];
   const bool leader = gl == 0;
-  const bool void_round = __hip_atomic_load(&r.ctr->overflow, __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT) != 0;
+  // set by an earlier kernel: a plain load, once per wavefront, broadcast
+  uint32_t ov = 0;
+  if (lane == __ffsll((unsigned long long)__ballot(true)) - 1) ov = r.ctr->overflow;
+  const bool void_round = __shfl(ov, __ffsll((unsigned long long)__ballot(true)) - 1, 64) != 0;
   bool requeue = false;
   uint32_t n_spawn = 0, spawn_off = 0;
   if (void_round) {  // a planner ran out of arena: nothing of this round applies
