@@ -38,6 +38,8 @@ struct ck_table {
   uint32_t evict_grid = 0;
   DevStats* dstats = nullptr;
   uint32_t* block_tmp = nullptr;
+  uint32_t* comp_tmp = nullptr;
+  uint8_t* req = nullptr;
   // host-side counters
   uint64_t rounds = 0, lookups = 0;
 };
@@ -99,6 +101,8 @@ void free_scratch(ck_table* t) {
   (void)hipFree(t->wg_scratch);
   (void)hipFree(t->dstats);
   (void)hipFree(t->block_tmp);
+  (void)hipFree(t->comp_tmp);
+  (void)hipFree(t->req);
 }
 
 ck_status alloc_scratch(ck_table* t) {
@@ -134,6 +138,8 @@ ck_status alloc_scratch(ck_table* t) {
   HIP_TRY(hipMemset(t->dstats, 0, sizeof(DevStats)));
   const uint32_t nb = (m + 1023) / 1024;
   HIP_TRY(dalloc(&t->block_tmp, ((nb + 63) & ~63u) + 16));
+  HIP_TRY(dalloc(&t->comp_tmp, nb + 64));
+  HIP_TRY(dalloc(&t->req, m));
   return CK_OK;
 }
 
@@ -203,14 +209,17 @@ ck_status run_rounds(ck_table* t, Round& r, uint64_t m, hipStream_t s) {
     r.arena_cap = t->arena_cap;
     r.spawns = t->spawns;
     r.spawn_cap = t->spawn_cap;
+    r.req = t->req;
     HIP_TRY(launch_round_begin(t->ctr, s));
     if (r.is_delete) {
       HIP_TRY(launch_plan_delete(t->g, r, s));
     } else {
       HIP_TRY(launch_plan_fresh(t->g, r, s));
+      HIP_TRY(launch_compact(r, 0, t->evict, &t->ctr->evict_count, t->comp_tmp, s));
       HIP_TRY(launch_plan_evict(t->g, r, t->evict_grid, s));
     }
     HIP_TRY(launch_commit(t->g, r, s));
+    HIP_TRY(launch_compact(r, 1, r.next, &t->ctr->next_pending, t->comp_tmp, s));
     HIP_TRY(hipMemcpyAsync(t->h_ctr, t->ctr, sizeof(Ctr), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const Ctr c = *t->h_ctr;

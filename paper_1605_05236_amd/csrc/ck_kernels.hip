@@ -111,19 +111,6 @@ __device__ __forceinline__ unsigned long long wave_max(unsigned long long v) {
   return v;
 }
 
-// Append to a device list with one atomic per wavefront: every active lane
-// calls it; lanes with `pred` get consecutive positions.
-__device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool pred) {
-  const uint64_t b = __ballot(pred);
-  if (b == 0) return 0;
-  const int first = __ffsll((unsigned long long)b) - 1;
-  const int lane = threadIdx.x & 63;
-  uint32_t base = 0;
-  if (lane == first) base = atomicAdd(counter, (uint32_t)__popcll(b));
-  base = __shfl(base, first, 64);
-  return base + (uint32_t)__popcll(b & ((1ull << lane) - 1));
-}
-
 // Block-wide sum of two counters, one atomic per block and counter.
 __device__ __forceinline__ void block_add2(unsigned long long a, unsigned long long b,
                                            unsigned long long* da, unsigned long long* db) {
@@ -290,28 +277,26 @@ hipError_t launch_batch_begin(const uint64_t* keys, uint64_t m, uint32_t* pend, 
 // ---------------------------------------------------------------------------
 // plan emission helpers (called by one lane)
 // ---------------------------------------------------------------------------
-// Sub-allocate n entries from a per-workgroup window of a global arena; the
-// window is refilled with one atomic.  win[0] = next, win[1] = end.  Returns
-// kNone (and flags the round void) when the arena is exhausted.  One lane.
-__device__ __forceinline__ uint32_t window_alloc(uint32_t* win, uint32_t* used, uint32_t cap,
-                                                 uint32_t n, uint32_t chunk, Ctr* ctr) {
+// Every eviction-planner workgroup owns a fixed region of the plan arena
+// (cap / gridDim.x entries) and fills it in order: no shared counter.  A plan
+// that does not fit marks the round void; the host then grows the arena and
+// the round is planned again.  win[0] = next free entry, win[1] = region end.
+// One lane.
+__device__ __forceinline__ uint32_t region_alloc(uint32_t* win, uint32_t n, Ctr* ctr) {
   if (n == 0) return 0;
-  if (win[0] + n > win[1] || win[1] == 0) {
-    const uint32_t want = n > chunk ? n : chunk;
-    const uint32_t b = atomicAdd(used, want);
-    if (b + want > cap) {
-      atomicOr(&ctr->overflow, 1u);
-      win[0] = win[1] = 0;
-      return kNone;
-    }
-    win[0] = b;
-    win[1] = b + want;
+  if (win[0] + n > win[1]) {
+    atomicOr(&ctr->overflow, 1u);
+    return kNone;
   }
   const uint32_t off = win[0];
   win[0] += n;
   return off;
 }
-constexpr uint32_t kWindow = 256;
+__device__ __forceinline__ void region_init(uint32_t* win, uint32_t cap) {
+  const uint32_t per = cap / gridDim.x;
+  win[0] = blockIdx.x * per;
+  win[1] = win[0] + per;
+}
 
 __device__ __forceinline__ void claim(const Geo& g, const Round& r, uint32_t bin, uint32_t i) {
   atomicMin(&g.owner[bin], r.tag | (unsigned long long)i);
@@ -412,20 +397,17 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
       }
     }
   }
-  const bool to_evict = !bad && !placed;
-  const uint32_t pos = wave_append(&r.ctr->evict_count, leader && to_evict);
   if (!leader) return;
-  if (to_evict) {
-    r.evict[pos] = i;
-    return;
-  }
   PlanHdr hd{};
-  hd.status = bad ? PL_FAIL : PL_OK;
+  // ops that need a kick-out are marked; the evict list is compacted from
+  // the marks in op order (no shared counter)
+  hd.status = bad ? PL_FAIL : (placed ? PL_OK : PL_EVICT);
   hd.views = views;
   hd.twins = twins;
   hd.n_moves = nm;
   hd.off = kInline;
   r.hdr[i] = hd;
+  if (!placed) return;
   IMove* im = r.imv + (size_t)i * kInlineMoves;
   if (nm > 0) { im[0] = IMove{b0, f0}; claim(g, r, b0, i); }
   if (nm > 1) { im[1] = IMove{b1, f1}; claim(g, r, b1, i); }
@@ -714,7 +696,7 @@ struct WavePlanner {
                          uint32_t* win) {
     __shared__ uint32_t s_off;
     if (status != PL_OK) nm = 0;
-    if (lane == 0) s_off = window_alloc(win, &r.ctr->arena_used, r.arena_cap, nm, kWindow, r.ctr);
+    if (lane == 0) s_off = region_alloc(win, nm, r.ctr);
     __syncthreads();
     const uint32_t off = s_off;
     __syncthreads();
@@ -747,17 +729,6 @@ struct WavePlanner {
   }
 };
 
-// Next chunk of eviction ops for this workgroup (one atomic per chunk).
-constexpr uint32_t kTake = 4;
-__device__ __forceinline__ uint32_t wave_take(const Round& r) {
-  __shared__ uint32_t s_k;
-  if (threadIdx.x == 0) s_k = atomicAdd(&r.ctr->evict_taken, kTake);
-  __syncthreads();
-  uint32_t k = s_k;
-  __syncthreads();
-  return k;
-}
-
 template <int B, int H>
 __global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
   extern __shared__ uint64_t lds64[];
@@ -770,13 +741,11 @@ __global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
   L.sf = L.bin + cap;
   L.last = (int*)(L.sf + cap);
   L.misc = (uint32_t*)(L.last + 8);
-  if (threadIdx.x == 0) { win[0] = 0; win[1] = 0; }
-  const uint32_t total = r.ctr->evict_count;  // final: written by the fresh planner
-  for (;;) {
-    const uint32_t k0 = wave_take(r);
-    if (k0 >= total) break;
-    const uint32_t k1 = min(k0 + kTake, total);
-    for (uint32_t k = k0; k < k1; ++k) {
+  if (threadIdx.x == 0) region_init(win, r.arena_cap);
+  __syncthreads();
+  const uint32_t total = r.ctr->evict_count;  // final: written by the compaction
+  {
+    for (uint32_t k = blockIdx.x; k < total; k += gridDim.x) {
       const uint32_t i = r.evict[k];
       const uint64_t x = r.keys[i];
       const uint64_t xa = load_aux(r.vals, i, B);
@@ -830,8 +799,12 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
   L.sf = L.bin + cap;
   const int lane = threadIdx.x;
   const bool sorted = g.scheme == CK_SORTED;
-  if (lane < 4) win[lane] = 0;
-  const uint32_t total = r.ctr->evict_count;  // final: written by the fresh planner
+  if (lane == 0) {
+    region_init(win, r.arena_cap);
+    region_init(win + 2, r.spawn_cap);
+  }
+  __syncthreads();
+  const uint32_t total = r.ctr->evict_count;  // final: written by the compaction
   const uint32_t vshift = 32 - (31 - __clz(VC));
 
   auto vis_find_or_insert = [&](uint32_t b, bool insert) -> bool {
@@ -851,14 +824,8 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
     }
   };
 
-  uint32_t k = 0, k1 = 0;
-  for (;;) {
-    if (k == k1) {
-      k = wave_take(r);
-      if (k >= total) break;
-      k1 = min(k + kTake, total);
-    }
-    const uint32_t i = r.evict[k++];
+  for (uint32_t k = blockIdx.x; k < total; k += gridDim.x) {
+    const uint32_t i = r.evict[k];
     const uint64_t x = r.keys[i];
     const uint64_t xa = load_aux(r.vals, i, B);
     WavePlanner<B, H> P(g, r, L, cap);
@@ -980,7 +947,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
     if (sorted && nsp > 0) {
       __shared__ uint32_t s_soff;
       if (lane == 0)
-        s_soff = window_alloc(win + 2, &r.ctr->spawn_used, r.spawn_cap, nsp, kWindow, r.ctr);
+        s_soff = region_alloc(win + 2, nsp, r.ctr);
       __syncthreads();
       soff = s_soff;
       __syncthreads();
@@ -1238,8 +1205,7 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
     n_spawn = h.n_spawn;
     spawn_off = h.spawn_off;
   }
-  const uint32_t pos = wave_append(&r.ctr->next_pending, leader && requeue);
-  if (leader && requeue) r.next[pos] = i;
+  if (leader) r.req[gidx] = requeue ? 1 : 0;
   // spawn counts (Sec. 5) of every plan, committed or not, saturating at 15
   for (uint32_t j = gl; j < n_spawn; j += 8) sc_increment(g.meta + r.spawns[spawn_off + j]);
 }
@@ -1249,6 +1215,104 @@ hipError_t launch_commit(const Geo& g, const Round& r, hipStream_t s) {
   const uint64_t threads = (uint64_t)r.npend * 8;
   const uint32_t grid = (uint32_t)((threads + 255) / 256);
   hipLaunchKernelGGL(k_commit, dim3(grid), dim3(256), 0, s, g, r);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// ordered stream compaction of the pending list (count, scan, scatter): the
+// evict list and the next round's pending list, in op order, without any
+// shared counter
+// ---------------------------------------------------------------------------
+constexpr int kCompPer = 4;                // positions per thread
+constexpr int kCompTile = 256 * kCompPer;  // positions per block
+
+__device__ __forceinline__ bool keep_pos(const Round& r, int mode, uint32_t p) {
+  return mode == 0 ? r.hdr[r.pend[p]].status == PL_EVICT : r.req[p] != 0;
+}
+
+__device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_compact_count(Round r, int mode, uint32_t* cnt) {
+  __shared__ uint32_t ws[4];
+  const uint32_t base = blockIdx.x * kCompTile + threadIdx.x * kCompPer;
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < kCompPer; ++k)
+    if (base + k < r.npend && keep_pos(r, mode, base + k)) ++c;
+  c = wave_sum32(c);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+// one block: exclusive scan of a[0..n) in place, total to *total
+__global__ __launch_bounds__(1024) void k_scan_excl(uint32_t* a, uint32_t n, uint32_t* total) {
+  __shared__ uint32_t carry;
+  __shared__ uint32_t wsum[16];
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  for (uint32_t base = 0; base < n; base += 1024) {
+    const uint32_t idx = base + threadIdx.x;
+    const uint32_t v = idx < n ? a[idx] : 0;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[threadIdx.x >> 6] = x;
+    __syncthreads();
+    uint32_t wpre = 0;
+    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wpre += wsum[w];
+    const uint32_t excl = carry + wpre + x - v;
+    __syncthreads();
+    if (idx < n) a[idx] = excl;
+    if (threadIdx.x == 1023) carry = excl + v;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(256) void k_compact_scatter(Round r, int mode, const uint32_t* pre,
+                                                         uint32_t* out) {
+  __shared__ uint32_t ws[4];
+  const uint32_t base = blockIdx.x * kCompTile + threadIdx.x * kCompPer;
+  bool kk[kCompPer];
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < kCompPer; ++k) {
+    kk[k] = base + k < r.npend && keep_pos(r, mode, base + k);
+    c += kk[k] ? 1 : 0;
+  }
+  const int lane = threadIdx.x & 63;
+  uint32_t x = c;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) ws[threadIdx.x >> 6] = x;
+  __syncthreads();
+  uint32_t wpre = 0;
+  for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wpre += ws[w];
+  uint32_t pos = pre[blockIdx.x] + wpre + x - c;
+#pragma unroll
+  for (int k = 0; k < kCompPer; ++k)
+    if (kk[k]) out[pos++] = r.pend[base + k];
+}
+
+hipError_t launch_compact(const Round& r, int mode, uint32_t* out, uint32_t* count,
+                          uint32_t* tmp, hipStream_t s) {
+  const uint32_t nb = (r.npend + kCompTile - 1) / kCompTile;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(256), 0, s, r, mode, tmp);
+  hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, tmp, nb, count);
+  hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(256), 0, s, r, mode, tmp, out);
   return hipGetLastError();
 }
 
