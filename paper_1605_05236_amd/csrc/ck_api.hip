@@ -30,7 +30,8 @@ struct ck_table {
   uint32_t arena_cap = 0;
   uint32_t* spawns = nullptr;
   uint32_t spawn_cap = 0;
-  uint32_t* op[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // views, views_all, kicks, retries, twins
+  uint32_t* op[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // views, lost, kicks, retries, twins
+  unsigned long long* wg_views = nullptr;  // per eviction workgroup: bins viewed
   Ctr* ctr = nullptr;
   Ctr* h_ctr = nullptr;
   void* wg_scratch = nullptr;
@@ -99,6 +100,7 @@ void free_scratch(ck_table* t) {
   (void)hipFree(t->ctr);
   if (t->h_ctr) (void)hipHostFree(t->h_ctr);
   (void)hipFree(t->wg_scratch);
+  (void)hipFree(t->wg_views);
   (void)hipFree(t->dstats);
   (void)hipFree(t->block_tmp);
   (void)hipFree(t->comp_tmp);
@@ -109,19 +111,21 @@ ck_status alloc_scratch(ck_table* t) {
   const uint32_t m = t->opt.batch_ops;
   t->batch_cap = m;
   // persistent eviction planners: as many one-wavefront workgroups as fit the
-  // LDS budget of a CU (160 KiB on gfx950), at most 16 per CU
+  // LDS budget of a CU (160 KiB on gfx950), at most 32 per CU
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const size_t lds = evict_lds_bytes(t->g);
-  size_t per_cu = std::max<size_t>(1, std::min<size_t>(16, (160 * 1024) / std::max<size_t>(lds, 1)));
+  size_t per_cu = std::max<size_t>(1, std::min<size_t>(32, (160 * 1024) / std::max<size_t>(lds, 1)));
   t->evict_grid = (uint32_t)(cus * per_cu);
   t->wg_bytes = (uint32_t)evict_wg_scratch_bytes(t->g);
   HIP_TRY(hipMalloc(&t->wg_scratch, (size_t)t->evict_grid * t->wg_bytes));
+  HIP_TRY(dalloc(&t->wg_views, t->evict_grid));
+  HIP_TRY(hipMemset(t->wg_views, 0, (size_t)t->evict_grid * 8));
   HIP_TRY(dalloc(&t->pend[0], m));
   HIP_TRY(dalloc(&t->pend[1], m));
   HIP_TRY(dalloc(&t->hdr, m));
-  HIP_TRY(dalloc(&t->imv, (size_t)m * kInlineMoves));
+  HIP_TRY(dalloc(&t->imv, (size_t)m * kExtraInline));
   HIP_TRY(dalloc(&t->evict, m));
   for (auto& p : t->op) HIP_TRY(dalloc(&p, m));
   // eviction plans sub-allocate from per-workgroup windows of 256 entries
@@ -175,13 +179,14 @@ Round make_round(ck_table* t, const uint64_t* keys, const void* vals, uint8_t* s
   r.op_base = op_base;
   r.status = status;
   r.op_views = ops[0];
-  r.op_views_all = ops[1];
+  r.op_lost = ops[1];
   r.op_kicks = ops[2];
   r.op_retries = ops[3];
   r.op_twins = ops[4];
   r.max_rounds = t->opt.max_rounds;
   r.is_delete = is_delete ? 1 : 0;
   r.wg_scratch = t->wg_scratch;
+  r.wg_views = t->wg_views;
   r.wg_scratch_bytes = t->wg_bytes;
   r.stats = t->dstats;
   return r;
@@ -247,8 +252,7 @@ ck_status run_batches(ck_table* t, const uint64_t* keys, const void* vals, uint6
                         t->op[4]};
     Round r = make_round(t, keys + b0, vals ? (const char*)vals + b0 * vb : nullptr,
                          status + b0, ops, t->insert_count + b0, is_delete);
-    HIP_TRY(launch_batch_begin(keys + b0, m, t->pend[0], status + b0, ops[0], ops[1], ops[2],
-                               ops[3], ops[4], CK_OP_BAD_KEY, t->ctr, s));
+    HIP_TRY(launch_batch_begin(m, t->pend[0], ops[0], ops[1], ops[2], ops[3], ops[4], s));
     ck_status st = run_rounds(t, r, m, s);
     if (st != CK_OK) return st;
     HIP_TRY(launch_batch_stats(r, m, slots, t->block_tmp, is_delete ? 1 : 0, s));
@@ -337,6 +341,7 @@ ck_status ck_clear(ck_table* t, void* stream) {
   if (!t) return CK_EINVAL;
   HIP_TRY(launch_init(t->g, (hipStream_t)stream));
   HIP_TRY(hipMemsetAsync(t->dstats, 0, sizeof(DevStats), (hipStream_t)stream));
+  HIP_TRY(hipMemsetAsync(t->wg_views, 0, (size_t)t->evict_grid * 8, (hipStream_t)stream));
   t->insert_count = 0;
   t->rounds = 0;
   t->lookups = 0;

@@ -46,21 +46,26 @@ struct IMove {           // 8 bytes
   uint32_t bin;
   uint32_t sf;           // slot | flags << 8
 };
-constexpr uint32_t kInlineMoves = 3;
 constexpr uint32_t kInline = 0xFFFFFFFEu;  // PlanHdr::off of a plan with inline moves
 
 enum : uint32_t { PL_FAIL = 0, PL_OK = 1, PL_EVICT = 2, PL_NOTFOUND = 3 };
 
-struct PlanHdr {         // per op of the sub-batch
-  uint32_t status;
+// Plan of one op of the sub-batch (32 bytes, one load in the commit kernel).
+// Plans of at most three moves that write only the op's own record keep them
+// inline: the first here, the others in the per-op inline array.
+struct PlanHdr {
+  uint32_t st;           // status | twins << 4 | n_moves << 8
   uint32_t views;
   uint32_t kicks;
-  uint32_t twins;
-  uint32_t n_moves;
-  uint32_t off;          // arena offset of the moves
+  uint32_t off;          // arena offset of the moves, or kInline
   uint32_t n_spawn;
   uint32_t spawn_off;    // spawn arena offset (sorted search)
+  IMove mv0;             // first move when inline
 };
+constexpr uint32_t kExtraInline = 2;  // inline moves beyond mv0, per op
+__host__ __device__ inline uint32_t hdr_pack(uint32_t status, uint32_t twins, uint32_t nm) {
+  return status | (twins << 4) | (nm << 8);
+}
 
 struct Ctr {             // device counters of one round
   uint32_t next_pending;
@@ -104,7 +109,7 @@ struct Round {
   uint8_t* req;              // per pending position: 1 = pending again next round
   uint32_t* evict;           // ops that need an eviction plan
   PlanHdr* hdr;
-  IMove* imv;                // kInlineMoves per op
+  IMove* imv;                // kExtraInline per op
   Move* arena;
   uint32_t arena_cap;
   uint32_t* spawns;
@@ -113,13 +118,14 @@ struct Round {
   uint64_t op_base;          // global insert index of op 0 of the sub-batch
   unsigned long long tag;    // (~epoch) << 32
   uint8_t* status;           // caller's per-op status (sub-batch view)
-  uint32_t* op_views;
-  uint32_t* op_views_all;
+  uint32_t* op_views;         // bins viewed by the deciding plan
+  uint32_t* op_lost;          // bins viewed by plans that lost their claims
   uint32_t* op_kicks;
   uint32_t* op_retries;
   uint32_t* op_twins;
   uint32_t max_rounds;
   uint32_t is_delete;
+  unsigned long long* wg_views;  // per eviction workgroup: bins viewed (cumulative)
   void* wg_scratch;          // per-workgroup scratch of the eviction planners
   uint32_t wg_scratch_bytes;
   DevStats* stats;
@@ -130,10 +136,8 @@ hipError_t launch_init(const Geo& g, hipStream_t s);
 hipError_t launch_lookup(const Geo& g, const uint64_t* keys, uint64_t n, void* vals_out,
                          uint8_t* found, uint32_t lpp, DevStats* st, hipStream_t s);
 hipError_t launch_round_begin(Ctr* c, hipStream_t s);
-hipError_t launch_batch_begin(const uint64_t* keys, uint64_t m, uint32_t* pend, uint8_t* status,
-                              uint32_t* views, uint32_t* views_all, uint32_t* kicks,
-                              uint32_t* retries, uint32_t* twins, uint32_t bad_status,
-                              Ctr* ctr, hipStream_t s);
+hipError_t launch_batch_begin(uint64_t m, uint32_t* pend, uint32_t* views, uint32_t* lost,
+                              uint32_t* kicks, uint32_t* retries, uint32_t* twins, hipStream_t s);
 hipError_t launch_plan_fresh(const Geo& g, const Round& r, hipStream_t s);
 hipError_t launch_plan_evict(const Geo& g, const Round& r, uint32_t grid, hipStream_t s);
 hipError_t launch_plan_delete(const Geo& g, const Round& r, hipStream_t s);

@@ -250,26 +250,23 @@ hipError_t launch_round_begin(Ctr* c, hipStream_t s) {
   return hipGetLastError();
 }
 
-__global__ void k_batch_begin(uint64_t m, uint32_t* pend, uint32_t* views, uint32_t* views_all,
+__global__ void k_batch_begin(uint64_t m, uint32_t* pend, uint32_t* views, uint32_t* lost,
                               uint32_t* kicks, uint32_t* retries, uint32_t* twins) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
     pend[i] = (uint32_t)i;
     views[i] = 0;
-    views_all[i] = 0;
+    lost[i] = 0;
     kicks[i] = 0;
     retries[i] = 0;
     twins[i] = 0;
   }
 }
-hipError_t launch_batch_begin(const uint64_t* keys, uint64_t m, uint32_t* pend, uint8_t* status,
-                              uint32_t* views, uint32_t* views_all, uint32_t* kicks,
-                              uint32_t* retries, uint32_t* twins, uint32_t bad_status, Ctr* ctr,
-                              hipStream_t s) {
-  (void)keys; (void)status; (void)bad_status; (void)ctr;
+hipError_t launch_batch_begin(uint64_t m, uint32_t* pend, uint32_t* views, uint32_t* lost,
+                              uint32_t* kicks, uint32_t* retries, uint32_t* twins, hipStream_t s) {
   uint32_t grid = (uint32_t)std::min<uint64_t>((m + 255) / 256, 4096);
   if (grid == 0) grid = 1;
-  hipLaunchKernelGGL(k_batch_begin, dim3(grid), dim3(256), 0, s, m, pend, views, views_all, kicks,
+  hipLaunchKernelGGL(k_batch_begin, dim3(grid), dim3(256), 0, s, m, pend, views, lost, kicks,
                      retries, twins);
   return hipGetLastError();
 }
@@ -401,16 +398,17 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
   PlanHdr hd{};
   // ops that need a kick-out are marked; the evict list is compacted from
   // the marks in op order (no shared counter)
-  hd.status = bad ? PL_FAIL : (placed ? PL_OK : PL_EVICT);
+  hd.st = hdr_pack(bad ? PL_FAIL : (placed ? PL_OK : PL_EVICT), twins, nm);
   hd.views = views;
-  hd.twins = twins;
-  hd.n_moves = nm;
   hd.off = kInline;
+  hd.mv0 = IMove{b0, f0};
   r.hdr[i] = hd;
   if (!placed) return;
-  IMove* im = r.imv + (size_t)i * kInlineMoves;
-  if (nm > 0) { im[0] = IMove{b0, f0}; claim(g, r, b0, i); }
-  if (nm > 1) { im[1] = IMove{b1, f1}; claim(g, r, b1, i); }
+  if (nm > 0) claim(g, r, b0, i);
+  if (nm > 1) {
+    r.imv[(size_t)i * kExtraInline] = IMove{b1, f1};
+    claim(g, r, b1, i);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -444,6 +442,7 @@ struct WavePlanner {
   bool vdup = false;
   int vprev = -1;      // log index of the last write to this lane's slot
   uint32_t vhc = 0;    // hit counter of the viewed bin (uniform)
+  uint32_t vmeta = 0;  // metadata word of the viewed bin, as read (uniform)
   uint32_t vbin = kNone;
 
   __device__ WavePlanner(const Geo& g_, const Round& r_, WaveLog l, uint32_t cap_)
@@ -459,7 +458,7 @@ struct WavePlanner {
     if (count) ++views;
     ulonglong2 s = make_ulonglong2(kEmpty, 0ull);
     if (lane < B) s = g.slots[(uint64_t)b * B + lane];
-    uint32_t m = (g.ghost || g.scheme == CK_QUEUE) ? g.meta[b] : 0u;
+    uint32_t m = (g.ghost || g.scheme == CK_QUEUE || g.scheme == CK_SORTED) ? g.meta[b] : 0u;
     bool dup = lane < B && ((m >> lane) & 1u);
     int prev = -1;
     uint32_t hcadd = 0;
@@ -489,6 +488,7 @@ struct WavePlanner {
     }
     vkey = s.x;
     vaux = s.y;
+    vmeta = m;
     vdup = dup && s.x != kEmpty;
     vprev = prev;
     vhc = ((m >> 24) + hcadd) & 0xFFu;
@@ -560,53 +560,16 @@ struct WavePlanner {
     else replace_dup(ffs32(dup_mask()), k, a, flags);
   }
 
-  // The fresh insert (no kick-out); same rules as k_plan_fresh.
-  __device__ bool place_fresh(uint64_t x, uint64_t xa, const uint32_t* h) {
-    const uint32_t hc_flag = (g.scheme == CK_QUEUE) ? MV_HC : 0;
-    if (g.ghost) {
-      load(h[0], true);
-      const uint32_t e0 = empty_mask(), d0 = dup_mask();
-      load(h[1], true);
-      const uint32_t e1 = empty_mask(), d1 = dup_mask();
-      if (e0 && e1) {
-        emit_other(h[0], ffs32(e0), x, xa, MV_DUP | hc_flag);
-        emit_here(ffs32(e1), x, xa, MV_DUP | hc_flag);
-        return true;
-      }
-      if (e0) { emit_other(h[0], ffs32(e0), x, xa, hc_flag); return true; }
-      if (e1) { emit_here(ffs32(e1), x, xa, hc_flag); return true; }
-      if (d0) {
-        load(h[0], false);  // back to the view of h[0] to reuse its duplicate
-        replace_dup(ffs32(d0), x, xa, hc_flag);
-        return true;
-      }
-      if (d1) { replace_dup(ffs32(d1), x, xa, hc_flag); return true; }
-      return false;
-    }
-    if (g.balance || g.scheme == CK_QUEUE) {
-      load(h[0], true);
-      const uint32_t e0 = empty_mask();
-      load(h[1], true);
-      const uint32_t e1 = empty_mask();
-      const int o0 = B - __popc(e0), o1 = B - __popc(e1);
-      if (o0 < B || o1 < B) {
-        if (o0 <= o1) emit_other(h[0], ffs32(e0), x, xa, hc_flag);
-        else emit_here(ffs32(e1), x, xa, hc_flag);
-        return true;
-      }
-      return false;
-    }
-    for (int hi = 0; hi < H; ++hi) {
-      load(h[hi], true);
-      const uint32_t e = empty_mask();
-      if (e) { emit_here(ffs32(e), x, xa, hc_flag); return true; }
-    }
-    return false;
+  // Ops reach the eviction planners only after k_plan_fresh found no room
+  // for them in the same snapshot, so their fresh views need no re-reading:
+  // first fit viewed all H bins, ghost and load-balanced inserts both bins.
+  __device__ __forceinline__ uint32_t fresh_views_full() const {
+    return (g.ghost || g.balance || g.scheme == CK_QUEUE) ? 2u : (uint32_t)H;
   }
 
   // ---- random kicking (Sec. 1; d-ary: victim moves to one of its other bins)
   __device__ uint32_t random_walk(uint64_t x, uint64_t xa, const uint32_t* h) {
-    if (place_fresh(x, xa, h)) return PL_OK;
+    views = fresh_views_full();
     uint32_t cur = h[uniform_choice(g, op, draws, H)];
     load(cur, false);
     uint64_t ck = x, ca = xa;
@@ -636,7 +599,7 @@ struct WavePlanner {
 
   // ---- queue-kicking with hit counters and hit balancing (Sec. 6)
   __device__ uint32_t queue_kick(uint64_t x, uint64_t xa, const uint32_t* h) {
-    if (place_fresh(x, xa, h)) return PL_OK;
+    views = fresh_views_full();
     const uint32_t hc0 = g.meta[h[0]] >> 24, hc1 = g.meta[h[1]] >> 24;
     uint32_t t = hc0 <= hc1 ? h[0] : h[1];
     load(t, false);
@@ -693,7 +656,7 @@ struct WavePlanner {
   // Copy the logged moves to the arena, write the header and claim bins.
   // `win` is the workgroup's arena window (LDS).
   __device__ void finish(uint32_t i, uint32_t status, uint32_t n_spawn, uint32_t spawn_off,
-                         uint32_t* win) {
+                         uint32_t* win, unsigned long long* wg_views) {
     __shared__ uint32_t s_off;
     if (status != PL_OK) nm = 0;
     if (lane == 0) s_off = region_alloc(win, nm, r.ctr);
@@ -715,15 +678,14 @@ struct WavePlanner {
     }
     if (lane == 0) {
       PlanHdr hd{};
-      hd.status = status;
+      hd.st = hdr_pack(status, status == PL_OK ? twins : 0, nm);
       hd.views = views;
       hd.kicks = status == PL_OK ? kicks : 0;
-      hd.twins = status == PL_OK ? twins : 0;
-      hd.n_moves = nm;
       hd.off = off;
       hd.n_spawn = n_spawn;
       hd.spawn_off = spawn_off;
       r.hdr[i] = hd;
+      *wg_views += views;
     }
     __syncthreads();
   }
@@ -733,6 +695,7 @@ template <int B, int H>
 __global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
   extern __shared__ uint64_t lds64[];
   __shared__ uint32_t win[2];
+  __shared__ unsigned long long s_views;  // bins viewed by this workgroup's plans
   const uint32_t cap = g.max_chain + 8;
   WaveLog L;
   L.key = lds64;
@@ -741,7 +704,10 @@ __global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
   L.sf = L.bin + cap;
   L.last = (int*)(L.sf + cap);
   L.misc = (uint32_t*)(L.last + 8);
-  if (threadIdx.x == 0) region_init(win, r.arena_cap);
+  if (threadIdx.x == 0) {
+    region_init(win, r.arena_cap);
+    s_views = 0;
+  }
   __syncthreads();
   const uint32_t total = r.ctr->evict_count;  // final: written by the compaction
   {
@@ -757,9 +723,10 @@ __global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
       if (g.scheme == CK_RATTLE) st = P.rattle(x, xa);
       else if (g.scheme == CK_QUEUE) st = P.queue_kick(x, xa, h);
       else st = P.random_walk(x, xa, h);
-      P.finish(i, st, 0, 0, win);
+      P.finish(i, st, 0, 0, win, &s_views);
     }
   }
+  if (threadIdx.x == 0 && s_views) r.wg_views[blockIdx.x] += s_views;
 }
 
 // ---- breadth-first and sorted search (Sec. 5) ------------------------------
@@ -776,7 +743,8 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
   // log and the record list live in this workgroup's global scratch (the
   // search never re-reads its own writes, so the log needs no fast overlay).
   extern __shared__ uint32_t lds32[];
-  __shared__ uint32_t win[4];  // arena window, spawn window
+  __shared__ uint32_t win[4];  // arena region, spawn region
+  __shared__ unsigned long long s_views;  // bins viewed by this workgroup's plans
   const uint32_t ms8 = g.max_search + 8;
   uint32_t VC = 1;  // visited set: open addressing on bin+1, power-of-two size
   while (VC < 2 * ms8) VC <<= 1;
@@ -784,16 +752,16 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
   L.last = (int*)lds32;
   L.misc = lds32 + 8;
   uint32_t* vis = lds32 + 16;
-  uint32_t* spl = vis + VC;        // spawn list (sorted search)
-  uint32_t* bhead = spl + ms8;     // 16 bucket heads
+  uint32_t* bhead = vis + VC;      // 16 bucket heads
   uint32_t* btail = bhead + 16;
-  uint32_t* path = btail + 16;     // path entries
   const uint32_t cap = ms8;        // move log: path, terminal, twin
   const uint32_t ecap = ms8 * B;
   char* scratch = (char*)r.wg_scratch + (size_t)blockIdx.x * r.wg_scratch_bytes;
   Ent* ent = (Ent*)scratch;
   uint32_t* nxt = (uint32_t*)(ent + ecap);
-  L.key = (uint64_t*)(nxt + ecap + (ecap & 1));
+  uint32_t* spl = nxt + ecap;      // spawn list (sorted search)
+  uint32_t* path = spl + ms8;      // path entries
+  L.key = (uint64_t*)(path + ms8 + ((ecap + 2 * ms8) & 1));
   L.aux = L.key + cap;
   L.bin = (uint32_t*)(L.aux + cap);
   L.sf = L.bin + cap;
@@ -802,6 +770,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
   if (lane == 0) {
     region_init(win, r.arena_cap);
     region_init(win + 2, r.spawn_cap);
+    s_views = 0;
   }
   __syncthreads();
   const uint32_t total = r.ctr->evict_count;  // final: written by the compaction
@@ -832,10 +801,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
     P.op = r.op_base + i;
     uint32_t h[H];
     hash_key<H>(g, x, h);
-    if (P.place_fresh(x, xa, h)) {
-      P.finish(i, PL_OK, 0, 0, win);
-      continue;
-    }
+    P.views = P.fresh_views_full();
     for (uint32_t j = lane; j < VC; j += 64) vis[j] = 0;
     if (lane < 16) { bhead[lane] = kNone; btail[lane] = kNone; }
     __syncthreads();
@@ -858,11 +824,41 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
       tail += B;
       __syncthreads();
     };
-    for (int q = 0; q < H; ++q) {
-      vis_find_or_insert(h[q], true);
-      P.load(h[q], false);
-      const uint32_t bk = sorted ? min(15u, (g.meta[h[q]] >> 8) & 0xFu) : 0u;
-      enqueue(h[q], kRootParent, bk);
+    // the records of the key's own bins, all loaded at once (H*B lanes),
+    // listed bin by bin in hash order
+    for (int q = 0; q < H; ++q) vis_find_or_insert(h[q], true);
+    {
+      const int q = lane / B, sl = lane % B;
+      uint32_t bk = 0;
+      if (lane < H * B) {
+        uint32_t hb = h[0];
+#pragma unroll
+        for (int j = 1; j < H; ++j)
+          if (q == j) hb = h[j];
+        const ulonglong2 sv = g.slots[(uint64_t)hb * B + sl];
+        if (sorted) bk = min(15u, (g.meta[hb] >> 8) & 0xFu);
+        Ent e;
+        e.key = sv.x;
+        e.bin = hb;
+        e.ps = (kRootParent << 3) | (uint32_t)sl;
+        ent[lane] = e;
+        if (sorted) nxt[lane] = (sl + 1 < B) ? (uint32_t)lane + 1 : kNone;
+      }
+      uint32_t bks[H];
+#pragma unroll
+      for (int j = 0; j < H; ++j) bks[j] = __shfl(bk, j * B, 64);
+      __syncthreads();
+      if (sorted && lane == 0) {
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+          const uint32_t t0 = j * B;
+          if (btail[bks[j]] == kNone) bhead[bks[j]] = t0;
+          else nxt[btail[bks[j]]] = t0;
+          btail[bks[j]] = t0 + B - 1;
+        }
+      }
+      tail = H * B;
+      __syncthreads();
     }
     uint32_t st = PL_FAIL;
     bool done = false;
@@ -938,7 +934,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
           done = true;
           break;
         }
-        const uint32_t bk = sorted ? min(15u, (g.meta[c] >> 8) & 0xFu) : 0u;
+        const uint32_t bk = sorted ? min(15u, (P.vmeta >> 8) & 0xFu) : 0u;
         enqueue(c, e, bk);
       }
     }
@@ -956,8 +952,9 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
       else
         nsp = 0;
     }
-    P.finish(i, st, nsp, soff, win);
+    P.finish(i, st, nsp, soff, win, &s_views);
   }
+  if (threadIdx.x == 0 && s_views) r.wg_views[blockIdx.x] += s_views;
 }
 
 size_t evict_lds_bytes(const Geo& g) {
@@ -965,7 +962,7 @@ size_t evict_lds_bytes(const Geo& g) {
     const size_t ms8 = g.max_search + 8;
     size_t VC = 1;
     while (VC < 2 * ms8) VC <<= 1;
-    return (16 + VC + 2 * ms8 + 32) * 4 + 64;
+    return (16 + VC + 32) * 4 + 64;
   }
   const size_t cap = g.max_chain + 8;
   return cap * 24 + 8 * 4 + 8 * 4 + 64;
@@ -975,7 +972,7 @@ size_t evict_wg_scratch_bytes(const Geo& g) {
   if (g.scheme == CK_BFS || g.scheme == CK_SORTED) {
     const size_t ms8 = g.max_search + 8;
     const size_t ecap = ms8 * g.B;
-    size_t b = ecap * (sizeof(Ent) + 4) + (ecap & 1) * 4 + ms8 * 24;
+    size_t b = ecap * (sizeof(Ent) + 4) + 2 * ms8 * 4 + 8 + ms8 * 24;
     return (b + 255) & ~(size_t)255;
   }
   return 256;
@@ -1068,15 +1065,15 @@ __global__ __launch_bounds__(256) void k_plan_delete(Geo g, Round r) {
   }
   if (!leader) return;
   PlanHdr hd{};
-  hd.status = x == kEmpty ? PL_FAIL : status;
+  hd.st = hdr_pack(x == kEmpty ? PL_FAIL : status, 0, nm);
   hd.views = probes;
-  hd.n_moves = nm;
   hd.off = kInline;
+  if (nm > 0) hd.mv0 = IMove{mb[0], ms[0] | ((uint32_t)MV_CLEAR << 8)};
   r.hdr[i] = hd;
-  IMove* im = r.imv + (size_t)i * kInlineMoves;
-  for (uint32_t j = 0; j < nm; ++j) {
-    im[j] = IMove{mb[j], ms[j] | ((uint32_t)MV_CLEAR << 8)};
-    claim(g, r, mb[j], i);
+  if (nm > 0) claim(g, r, mb[0], i);
+  if (nm > 1) {
+    r.imv[(size_t)i * kExtraInline] = IMove{mb[1], ms[1] | ((uint32_t)MV_CLEAR << 8)};
+    claim(g, r, mb[1], i);
   }
 }
 
@@ -1108,39 +1105,50 @@ __device__ __forceinline__ void sc_increment(uint32_t* meta) {
   }
 }
 
+constexpr int kCommitLanes = 4;  // lanes per plan in the commit kernel
+
 __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
+  constexpr int CL = kCommitLanes;
   const int lane = threadIdx.x & 63;
-  const int gl = lane & 7;
-  const int gshift = lane & ~7;
-  const uint64_t gidx = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const int gl = lane & (CL - 1);
+  const int gshift = lane & ~(CL - 1);
+  const uint64_t gidx = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / CL;
   if (gidx >= r.npend) return;
   const uint32_t i = r.pend[gidx];
   const bool leader = gl == 0;
   // set by an earlier kernel: a plain load, once per wavefront, broadcast
+  const int first = __ffsll((unsigned long long)__ballot(true)) - 1;
   uint32_t ov = 0;
-  if (lane == __ffsll((unsigned long long)__ballot(true)) - 1) ov = r.ctr->overflow;
-  const bool void_round = __shfl(ov, __ffsll((unsigned long long)__ballot(true)) - 1, 64) != 0;
+  if (lane == first) ov = r.ctr->overflow;
+  const bool void_round = __shfl(ov, first, 64) != 0;
   bool requeue = false;
   uint32_t n_spawn = 0, spawn_off = 0;
   if (void_round) {  // a planner ran out of arena: nothing of this round applies
     requeue = true;
   } else {
     const PlanHdr h = r.hdr[i];
+    const uint32_t status = h.st & 0xF, twins = (h.st >> 4) & 0xF, nmv = h.st >> 8;
     const bool inl = h.off == kInline;
+    const uint32_t off = h.off, mv0_bin = h.mv0.bin, mv0_sf = h.mv0.sf;
     const uint64_t x = r.keys[i];
     const uint64_t xa = (inl && r.vals) ? load_aux(r.vals, i, g.B) : 0;
     // move j of the plan: bin, slot, flags and the record it writes
     auto get = [&](uint32_t j, uint32_t& bin, uint32_t& slot, uint32_t& fl, uint64_t& k,
                    uint64_t& a) {
       if (inl) {
-        const IMove m = r.imv[(size_t)i * kInlineMoves + j];
-        bin = m.bin;
-        slot = m.sf & 0xFF;
-        fl = m.sf >> 8;
+        uint32_t mb = mv0_bin, msf = mv0_sf;
+        if (j > 0) {
+          const IMove m = r.imv[(size_t)i * kExtraInline + (j - 1)];
+          mb = m.bin;
+          msf = m.sf;
+        }
+        bin = mb;
+        slot = msf & 0xFF;
+        fl = msf >> 8;
         k = x;
         a = xa;
       } else {
-        const Move m = r.arena[h.off + j];
+        const Move m = r.arena[off + j];
         bin = m.bin;
         slot = m.slot;
         fl = m.flags;
@@ -1150,16 +1158,16 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
     };
     const unsigned long long me = r.tag | (unsigned long long)i;
     bool mine = true;
-    for (uint32_t j = gl; j < h.n_moves; j += 8) {
+    for (uint32_t j = gl; j < nmv; j += CL) {
       uint32_t bin, slot, fl;
       uint64_t k, a;
       get(j, bin, slot, fl, k, a);
       if (g.owner[bin] != me) mine = false;
     }
-    const bool win = ((__ballot(!mine) >> gshift) & 0xFFull) == 0;
+    const bool win = ((__ballot(!mine) >> gshift) & ((1ull << CL) - 1)) == 0;
     if (win) {
       // chain written from its end backwards (Sec. 8.2 system-transaction order)
-      for (int base = (int)h.n_moves - 1; base >= 0; base -= 8) {
+      for (int base = (int)nmv - 1; base >= 0; base -= CL) {
         const int j = base - gl;
         if (j < 0) continue;
         uint32_t bin, slot, fl;
@@ -1183,16 +1191,15 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
       if (leader) {
         uint8_t st;
         if (x == kEmpty) st = CK_OP_BAD_KEY;
-        else if (r.is_delete) st = h.status == PL_OK ? CK_OP_OK : CK_OP_NOT_FOUND;
-        else st = h.status == PL_OK ? CK_OP_OK : CK_OP_FAIL_CHAIN;
+        else if (r.is_delete) st = status == PL_OK ? CK_OP_OK : CK_OP_NOT_FOUND;
+        else st = status == PL_OK ? CK_OP_OK : CK_OP_FAIL_CHAIN;
         r.status[i] = st;
         r.op_views[i] = h.views;
-        r.op_kicks[i] = h.kicks;
-        r.op_twins[i] = h.twins;
-        r.op_views_all[i] += h.views;
+        if (h.kicks) r.op_kicks[i] = h.kicks;
+        if (twins) r.op_twins[i] = twins;
       }
     } else if (leader) {
-      r.op_views_all[i] += h.views;
+      r.op_lost[i] += h.views;
       const uint32_t rt = r.op_retries[i] + 1;
       r.op_retries[i] = rt;
       if (r.max_rounds && rt >= r.max_rounds) {
@@ -1207,12 +1214,12 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
   }
   if (leader) r.req[gidx] = requeue ? 1 : 0;
   // spawn counts (Sec. 5) of every plan, committed or not, saturating at 15
-  for (uint32_t j = gl; j < n_spawn; j += 8) sc_increment(g.meta + r.spawns[spawn_off + j]);
+  for (uint32_t j = gl; j < n_spawn; j += CL) sc_increment(g.meta + r.spawns[spawn_off + j]);
 }
 
 hipError_t launch_commit(const Geo& g, const Round& r, hipStream_t s) {
   if (r.npend == 0) return hipSuccess;
-  const uint64_t threads = (uint64_t)r.npend * 8;
+  const uint64_t threads = (uint64_t)r.npend * kCommitLanes;
   const uint32_t grid = (uint32_t)((threads + 255) / 256);
   hipLaunchKernelGGL(k_commit, dim3(grid), dim3(256), 0, s, g, r);
   return hipGetLastError();
@@ -1227,7 +1234,7 @@ constexpr int kCompPer = 4;                // positions per thread
 constexpr int kCompTile = 256 * kCompPer;  // positions per block
 
 __device__ __forceinline__ bool keep_pos(const Round& r, int mode, uint32_t p) {
-  return mode == 0 ? r.hdr[r.pend[p]].status == PL_EVICT : r.req[p] != 0;
+  return mode == 0 ? (r.hdr[r.pend[p]].st & 0xF) == PL_EVICT : r.req[p] != 0;
 }
 
 __device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
@@ -1369,9 +1376,26 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_scan(uint32_t* block_ok, u
   if (threadIdx.x == 0) st->v[S_STORED] += carry;
 }
 
-// pass 3: density band of every op, totals
+// pass 3: density band of every op, totals.  Ops of one wavefront almost
+// always share a band: their contributions are summed across the wavefront
+// first, so the LDS histogram sees one atomic per wavefront and band.
+__device__ __forceinline__ void band_add(unsigned long long* hist, uint32_t band, bool valid,
+                                         unsigned long long v) {
+  const int lane = threadIdx.x & 63;
+  uint64_t todo = __ballot(valid);
+  while (todo) {
+    const int leader = __ffsll((unsigned long long)todo) - 1;
+    const uint32_t b = __shfl(band, leader, 64);
+    const bool mine = valid && band == b;
+    const uint64_t same = __ballot(mine);
+    const unsigned long long sum = wave_sum(mine ? v : 0ull);
+    if (lane == leader && sum) atomicAdd(&hist[b], sum);
+    todo &= ~same;
+  }
+}
+
 __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
-    const uint8_t* status, const uint32_t* views, const uint32_t* views_all, const uint32_t* kicks,
+    const uint8_t* status, const uint32_t* views, const uint32_t* lost, const uint32_t* kicks,
     const uint32_t* retries, const uint32_t* twins, uint64_t m, const uint32_t* block_ok,
     const uint64_t* stored_before, uint64_t slots, DevStats* st) {
   __shared__ unsigned long long hb[4][CK_BANDS];
@@ -1393,33 +1417,36 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
   const uint64_t rank = (uint64_t)block_ok[blockIdx.x] + wpre + before_in_wave;
   unsigned long long a_ok = 0, a_fail = 0, a_abort = 0, a_bad = 0, a_views = 0, a_vall = 0,
                      a_kicks = 0, a_maxk = 0, a_ret = 0, a_tw = 0;
+  bool banded = false;
+  uint32_t band = 0;
   if (i < m) {
     if (s == CK_OP_BAD_KEY) {
       a_bad = 1;
     } else {
       a_ret = retries[i];
-      a_vall = views_all[i];
+      a_vall = (unsigned long long)views[i] + lost[i];
       if (s == CK_OP_ABORTED) {
         a_abort = 1;
       } else {
-        uint64_t band = (uint64_t)CK_BANDS * (*stored_before + rank) / slots;
-        if (band >= CK_BANDS) band = CK_BANDS - 1;
-        atomicAdd(&hb[0][band], 1ull);
-        atomicAdd(&hb[1][band], (unsigned long long)views[i]);
+        uint64_t b = (uint64_t)CK_BANDS * (*stored_before + rank) / slots;
+        band = (uint32_t)(b >= CK_BANDS ? CK_BANDS - 1 : b);
+        banded = true;
         a_views = views[i];
         if (ok) {
           a_ok = 1;
           a_kicks = kicks[i];
           a_maxk = kicks[i];
           a_tw = twins[i];
-          atomicAdd(&hb[2][band], (unsigned long long)kicks[i]);
         } else {
           a_fail = 1;
-          atomicAdd(&hb[3][band], 1ull);
         }
       }
     }
   }
+  band_add(hb[0], band, banded, 1ull);
+  band_add(hb[1], band, banded, a_views);
+  band_add(hb[2], band, banded && ok, a_kicks);
+  band_add(hb[3], band, banded && !ok, 1ull);
   a_ok = wave_sum(a_ok); a_fail = wave_sum(a_fail); a_abort = wave_sum(a_abort);
   a_bad = wave_sum(a_bad); a_views = wave_sum(a_views); a_vall = wave_sum(a_vall);
   a_kicks = wave_sum(a_kicks); a_maxk = wave_max(a_maxk); a_ret = wave_sum(a_ret);
@@ -1484,7 +1511,7 @@ hipError_t launch_batch_stats(const Round& r, uint64_t m, uint64_t slots, uint32
   hipLaunchKernelGGL(k_stats_scan, dim3(1), dim3(kStatBlock), 0, s, block_tmp, nb, r.stats,
                      stored_before);
   hipLaunchKernelGGL(k_stats_apply, dim3(nb), dim3(kStatBlock), 0, s, r.status, r.op_views,
-                     r.op_views_all, r.op_kicks, r.op_retries, r.op_twins, m, block_tmp,
+                     r.op_lost, r.op_kicks, r.op_retries, r.op_twins, m, block_tmp,
                      stored_before, slots, r.stats);
   return hipGetLastError();
 }
