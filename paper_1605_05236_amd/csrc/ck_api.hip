@@ -220,11 +220,11 @@ ck_status run_rounds(ck_table* t, Round& r, uint64_t m, hipStream_t s) {
       HIP_TRY(launch_plan_delete(t->g, r, s));
     } else {
       HIP_TRY(launch_plan_fresh(t->g, r, s));
-      HIP_TRY(launch_compact(r, 0, t->evict, &t->ctr->evict_count, t->comp_tmp, s));
+      HIP_TRY(launch_compact(r, t->evict, &t->ctr->evict_count, t->comp_tmp, s));
       HIP_TRY(launch_plan_evict(t->g, r, t->evict_grid, s));
     }
     HIP_TRY(launch_commit(t->g, r, s));
-    HIP_TRY(launch_compact(r, 1, r.next, &t->ctr->next_pending, t->comp_tmp, s));
+    HIP_TRY(launch_compact(r, r.next, &t->ctr->next_pending, t->comp_tmp, s));
     HIP_TRY(hipMemcpyAsync(t->h_ctr, t->ctr, sizeof(Ctr), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const Ctr c = *t->h_ctr;

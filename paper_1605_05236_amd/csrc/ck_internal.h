@@ -142,10 +142,10 @@ hipError_t launch_plan_fresh(const Geo& g, const Round& r, hipStream_t s);
 hipError_t launch_plan_evict(const Geo& g, const Round& r, uint32_t grid, hipStream_t s);
 hipError_t launch_plan_delete(const Geo& g, const Round& r, hipStream_t s);
 hipError_t launch_commit(const Geo& g, const Round& r, hipStream_t s);
-// Ordered compaction of the pending list into `out`; the length goes to *count.
-// mode 0 keeps ops whose plan header says PL_EVICT, mode 1 ops with req[p] set.
-hipError_t launch_compact(const Round& r, int mode, uint32_t* out, uint32_t* count,
-                          uint32_t* tmp, hipStream_t s);
+// Ordered compaction of the pending list into `out` (keeps positions p with
+// req[p] set); the length goes to *count.
+hipError_t launch_compact(const Round& r, uint32_t* out, uint32_t* count, uint32_t* tmp,
+                          hipStream_t s);
 hipError_t launch_batch_stats(const Round& r, uint64_t m, uint64_t slots, uint32_t* block_tmp,
                               uint32_t is_delete, hipStream_t s);
 size_t evict_lds_bytes(const Geo& g);

@@ -395,9 +395,10 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
     }
   }
   if (!leader) return;
+  // ops that need a kick-out are flagged by pending position; the evict list
+  // is compacted from the flags in op order (no shared counter)
+  r.req[gidx] = (!bad && !placed) ? 1 : 0;
   PlanHdr hd{};
-  // ops that need a kick-out are marked; the evict list is compacted from
-  // the marks in op order (no shared counter)
   hd.st = hdr_pack(bad ? PL_FAIL : (placed ? PL_OK : PL_EVICT), twins, nm);
   hd.views = views;
   hd.off = kInline;
@@ -1233,9 +1234,7 @@ hipError_t launch_commit(const Geo& g, const Round& r, hipStream_t s) {
 constexpr int kCompPer = 4;                // positions per thread
 constexpr int kCompTile = 256 * kCompPer;  // positions per block
 
-__device__ __forceinline__ bool keep_pos(const Round& r, int mode, uint32_t p) {
-  return mode == 0 ? (r.hdr[r.pend[p]].st & 0xF) == PL_EVICT : r.req[p] != 0;
-}
+__device__ __forceinline__ bool keep_pos(const Round& r, uint32_t p) { return r.req[p] != 0; }
 
 __device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
 #pragma unroll
@@ -1243,13 +1242,13 @@ __device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
   return v;
 }
 
-__global__ __launch_bounds__(256) void k_compact_count(Round r, int mode, uint32_t* cnt) {
+__global__ __launch_bounds__(256) void k_compact_count(Round r, uint32_t* cnt) {
   __shared__ uint32_t ws[4];
   const uint32_t base = blockIdx.x * kCompTile + threadIdx.x * kCompPer;
   uint32_t c = 0;
 #pragma unroll
   for (int k = 0; k < kCompPer; ++k)
-    if (base + k < r.npend && keep_pos(r, mode, base + k)) ++c;
+    if (base + k < r.npend && keep_pos(r, base + k)) ++c;
   c = wave_sum32(c);
   if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = c;
   __syncthreads();
@@ -1285,7 +1284,7 @@ __global__ __launch_bounds__(1024) void k_scan_excl(uint32_t* a, uint32_t n, uin
   if (threadIdx.x == 0) *total = carry;
 }
 
-__global__ __launch_bounds__(256) void k_compact_scatter(Round r, int mode, const uint32_t* pre,
+__global__ __launch_bounds__(256) void k_compact_scatter(Round r, const uint32_t* pre,
                                                          uint32_t* out) {
   __shared__ uint32_t ws[4];
   const uint32_t base = blockIdx.x * kCompTile + threadIdx.x * kCompPer;
@@ -1293,7 +1292,7 @@ __global__ __launch_bounds__(256) void k_compact_scatter(Round r, int mode, cons
   uint32_t c = 0;
 #pragma unroll
   for (int k = 0; k < kCompPer; ++k) {
-    kk[k] = base + k < r.npend && keep_pos(r, mode, base + k);
+    kk[k] = base + k < r.npend && keep_pos(r, base + k);
     c += kk[k] ? 1 : 0;
   }
   const int lane = threadIdx.x & 63;
@@ -1313,13 +1312,41 @@ __global__ __launch_bounds__(256) void k_compact_scatter(Round r, int mode, cons
     if (kk[k]) out[pos++] = r.pend[base + k];
 }
 
-hipError_t launch_compact(const Round& r, int mode, uint32_t* out, uint32_t* count,
-                          uint32_t* tmp, hipStream_t s) {
+// Small lists (the later rounds of a sub-batch): one workgroup does it all.
+__global__ __launch_bounds__(1024) void k_compact_small(Round r, uint32_t* out, uint32_t* count) {
+  __shared__ uint32_t wsum[16];
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  for (uint32_t base = 0; base < r.npend; base += 1024) {
+    const uint32_t p = base + threadIdx.x;
+    const bool keep = p < r.npend && keep_pos(r, p);
+    const uint64_t b = __ballot(keep);
+    if (lane == 0) wsum[threadIdx.x >> 6] = (uint32_t)__popcll(b);
+    __syncthreads();
+    uint32_t pre = carry;
+    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) pre += wsum[w];
+    if (keep) out[pre + __popcll(b & ((1ull << lane) - 1))] = r.pend[p];
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int w = 0; w < 16; ++w) carry += wsum[w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *count = carry;
+}
+
+hipError_t launch_compact(const Round& r, uint32_t* out, uint32_t* count, uint32_t* tmp,
+                          hipStream_t s) {
   const uint32_t nb = (r.npend + kCompTile - 1) / kCompTile;
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(256), 0, s, r, mode, tmp);
+  if (r.npend <= 16 * 1024) {
+    hipLaunchKernelGGL(k_compact_small, dim3(1), dim3(1024), 0, s, r, out, count);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(256), 0, s, r, tmp);
   hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, tmp, nb, count);
-  hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(256), 0, s, r, mode, tmp, out);
+  hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(256), 0, s, r, tmp, out);
   return hipGetLastError();
 }
 
@@ -1404,49 +1431,56 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
   for (int j = threadIdx.x; j < 4 * CK_BANDS; j += kStatBlock) hb[j / CK_BANDS][j % CK_BANDS] = 0;
   if (threadIdx.x < 11) tot[threadIdx.x] = 0;
   __syncthreads();
-  const uint64_t i = (uint64_t)blockIdx.x * kStatBlock + threadIdx.x;
-  const uint8_t s = i < m ? status[i] : 0xFF;
-  const bool ok = s == CK_OP_OK;
   const int lane = threadIdx.x & 63;
-  const uint64_t bal = __ballot(ok);
-  const uint32_t before_in_wave = __popcll(bal & ((1ull << lane) - 1));
-  if (lane == 0) wsum[threadIdx.x >> 6] = __popcll(bal);
-  __syncthreads();
-  uint32_t wpre = 0;
-  for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wpre += wsum[w];
-  const uint64_t rank = (uint64_t)block_ok[blockIdx.x] + wpre + before_in_wave;
+  const uint32_t ntiles = (uint32_t)((m + kStatBlock - 1) / kStatBlock);
   unsigned long long a_ok = 0, a_fail = 0, a_abort = 0, a_bad = 0, a_views = 0, a_vall = 0,
                      a_kicks = 0, a_maxk = 0, a_ret = 0, a_tw = 0;
-  bool banded = false;
-  uint32_t band = 0;
-  if (i < m) {
-    if (s == CK_OP_BAD_KEY) {
-      a_bad = 1;
-    } else {
-      a_ret = retries[i];
-      a_vall = (unsigned long long)views[i] + lost[i];
-      if (s == CK_OP_ABORTED) {
-        a_abort = 1;
+  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const uint64_t i = (uint64_t)tile * kStatBlock + threadIdx.x;
+    const uint8_t s = i < m ? status[i] : 0xFF;
+    const bool ok = s == CK_OP_OK;
+    const uint64_t bal = __ballot(ok);
+    const uint32_t before_in_wave = __popcll(bal & ((1ull << lane) - 1));
+    if (lane == 0) wsum[threadIdx.x >> 6] = __popcll(bal);
+    __syncthreads();
+    uint32_t wpre = 0;
+    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wpre += wsum[w];
+    __syncthreads();
+    const uint64_t rank = (uint64_t)block_ok[tile] + wpre + before_in_wave;
+    bool banded = false;
+    uint32_t band = 0;
+    unsigned long long v_views = 0, v_kicks = 0;
+    if (i < m) {
+      if (s == CK_OP_BAD_KEY) {
+        a_bad += 1;
       } else {
-        uint64_t b = (uint64_t)CK_BANDS * (*stored_before + rank) / slots;
-        band = (uint32_t)(b >= CK_BANDS ? CK_BANDS - 1 : b);
-        banded = true;
-        a_views = views[i];
-        if (ok) {
-          a_ok = 1;
-          a_kicks = kicks[i];
-          a_maxk = kicks[i];
-          a_tw = twins[i];
+        a_ret += retries[i];
+        a_vall += (unsigned long long)views[i] + lost[i];
+        if (s == CK_OP_ABORTED) {
+          a_abort += 1;
         } else {
-          a_fail = 1;
+          const uint64_t b = (uint64_t)CK_BANDS * (*stored_before + rank) / slots;
+          band = (uint32_t)(b >= CK_BANDS ? CK_BANDS - 1 : b);
+          banded = true;
+          v_views = views[i];
+          a_views += v_views;
+          if (ok) {
+            v_kicks = kicks[i];
+            a_ok += 1;
+            a_kicks += v_kicks;
+            a_maxk = v_kicks > a_maxk ? v_kicks : a_maxk;
+            a_tw += twins[i];
+          } else {
+            a_fail += 1;
+          }
         }
       }
     }
+    band_add(hb[0], band, banded, 1ull);
+    band_add(hb[1], band, banded, v_views);
+    band_add(hb[2], band, banded && ok, v_kicks);
+    band_add(hb[3], band, banded && !ok, 1ull);
   }
-  band_add(hb[0], band, banded, 1ull);
-  band_add(hb[1], band, banded, a_views);
-  band_add(hb[2], band, banded && ok, a_kicks);
-  band_add(hb[3], band, banded && !ok, 1ull);
   a_ok = wave_sum(a_ok); a_fail = wave_sum(a_fail); a_abort = wave_sum(a_abort);
   a_bad = wave_sum(a_bad); a_views = wave_sum(a_views); a_vall = wave_sum(a_vall);
   a_kicks = wave_sum(a_kicks); a_maxk = wave_max(a_maxk); a_ret = wave_sum(a_ret);
@@ -1510,7 +1544,8 @@ hipError_t launch_batch_stats(const Round& r, uint64_t m, uint64_t slots, uint32
   hipLaunchKernelGGL(k_stats_count, dim3(nb), dim3(kStatBlock), 0, s, r.status, m, block_tmp);
   hipLaunchKernelGGL(k_stats_scan, dim3(1), dim3(kStatBlock), 0, s, block_tmp, nb, r.stats,
                      stored_before);
-  hipLaunchKernelGGL(k_stats_apply, dim3(nb), dim3(kStatBlock), 0, s, r.status, r.op_views,
+  hipLaunchKernelGGL(k_stats_apply, dim3(std::min<uint32_t>(nb, 256)), dim3(kStatBlock), 0, s,
+                     r.status, r.op_views,
                      r.op_lost, r.op_kicks, r.op_retries, r.op_twins, m, block_tmp,
                      stored_before, slots, r.stats);
   return hipGetLastError();
