@@ -107,7 +107,9 @@ def main():
     fout = torch.empty(nq, dtype=torch.uint8, device="cuda")
 
     def step(record):
-        res = {"fill_s": {}, "stats": {}}
+        res = {"fill_s": {}, "stats": {}, "timing": {}}
+        for s in schemes:
+            tables[s].timing(enable=record)
         for s in schemes:
             t = tables[s]
             t.clear()
@@ -119,6 +121,7 @@ def main():
             res["fill_s"][s] = e0.elapsed_time(e1) / 1e3
             if record:
                 res["stats"][s] = t.stats()
+                res["timing"][s] = t.timing()
         t = tables[schemes[-1]]
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         e0.record(stream)
@@ -129,6 +132,8 @@ def main():
         e2.synchronize()
         res["lookup_s"] = e0.elapsed_time(e1) / 1e3
         res["delete_s"] = e1.elapsed_time(e2) / 1e3
+        if record:
+            res["timing"]["_lookup"] = t.timing()
         return res
 
     for w in range(args.warmup):
@@ -138,6 +143,8 @@ def main():
     t_start = time.perf_counter()
     results = []
     for k in range(args.steps):
+        # the last timed step also records per-kernel HIP-event timing (two
+        # events per launch; their host cost is kept out of the other steps)
         results.append(step(k == args.steps - 1))
         print(f"# step {k}: fills {results[-1]['fill_s']} lookup {results[-1]['lookup_s']:.4f}s "
               f"delete {results[-1]['delete_s']:.4f}s", file=sys.stderr, flush=True)
@@ -168,6 +175,41 @@ def main():
     probes_per_q = lt["lookup_probes"] / max(1, lt["lookups"])
     bytes_per_q = 17 + probes_per_q * B * 16
     achieved = nq * bytes_per_q / lookup_s / 1e9
+    lookup_roof = {"bound": "hbm", "kernel": f"k_lookup<{B},{B},2>", "achieved": achieved,
+                   "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                   "bytes_per_query": bytes_per_q}
+    # per-kernel-class time over the timed steps (HIP events around each launch)
+    classes = ["plan_fresh", "plan_evict", "commit", "compact", "stats"]
+    kt = {c: {"ms": 0.0, "launches": 0} for c in classes}
+    evict_views = 0
+    evict_ms = {}
+    timed = [r for r in results if r["timing"]]
+    for r in timed:
+        for s in schemes:
+            tm = r["timing"][s]
+            for c in classes:
+                kt[c]["ms"] += tm[c]["ms"]
+                kt[c]["launches"] += tm[c]["launches"]
+            evict_views += tm["evict_views"]
+            evict_ms[s] = evict_ms.get(s, 0.0) + tm["plan_evict"]["ms"]
+    lk = sum(r["timing"]["_lookup"]["lookup"]["ms"] for r in timed)
+    kt["lookup"] = {"ms": lk, "launches": sum(r["timing"]["_lookup"]["lookup"]["launches"]
+                                             for r in timed)}
+    dominant = max(kt, key=lambda c: kt[c]["ms"])
+    # eviction planners: each bin viewed is one bin line (B x 16 bytes) plus
+    # its 4-byte metadata word; per launch = views of the launch's plans
+    per_view = B * 16 + 4
+    ev_ms = kt["plan_evict"]["ms"]
+    ev_achieved = evict_views * per_view / (ev_ms / 1e3) / 1e9 if ev_ms else 0.0
+    evict_roof = {"bound": "hbm", "kernel": "k_plan_search<8,2> (bfs, sorted) / "
+                                            "k_plan_walk<8,2> (queue)",
+                  "achieved": ev_achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                  "frac": ev_achieved / PEAK_HBM_GBS, "traffic": None,
+                  "bytes_per_view": per_view, "views": evict_views,
+                  "launches": kt["plan_evict"]["launches"],
+                  "avg_launch_us": ev_ms * 1e3 / max(1, kt["plan_evict"]["launches"])}
+    roofline = evict_roof if dominant in ("plan_evict",) else (
+        lookup_roof if dominant == "lookup" else evict_roof)
     out = {
         "metric": "inserts/s & bins viewed/insert at 95% load; lookups/s vs HBM roofline",
         "value": ins_rate,
@@ -197,10 +239,10 @@ def main():
         "lookups_per_s": nq / lookup_s,
         "deletes_per_s": dels.size / delete_s,
         "lookup_probes_per_query": probes_per_q,
-        "roofline": {"bound": "hbm", "kernel": "k_lookup<8,8,2>", "achieved": achieved,
-                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": None,
-                     "bytes_per_query": bytes_per_q},
+        "roofline": roofline,
+        "lookup_roofline": lookup_roof,
+        "kernel_ms_per_step": {c: kt[c]["ms"] / max(1, len(timed)) for c in kt},
+        "dominant_kernel_class": dominant,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, schemes)

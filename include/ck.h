@@ -162,6 +162,28 @@ ck_status ck_delete(ck_table* t, const uint64_t* d_keys, uint64_t n, uint8_t* d_
 ck_status ck_stats_get(ck_table* t, ck_stats* h_out, void* stream);
 ck_status ck_stats_reset(ck_table* t, void* stream);
 
+/* Per-kernel timing, measured with HIP events on the caller's stream around
+   every launch of each kernel class while enabled (enabling resets it). */
+typedef struct {
+  uint64_t launches;
+  double ms;            /* summed launch durations */
+} ck_kernel_time;
+
+typedef struct {
+  ck_kernel_time plan_fresh;  /* placement without eviction, every pending op */
+  ck_kernel_time plan_evict;  /* kick-out planners: walk (random/queue/rattle) or search */
+  ck_kernel_time plan_delete;
+  ck_kernel_time commit;      /* claim check, reverse-order writes, metadata */
+  ck_kernel_time compact;     /* evict / pending list compaction */
+  ck_kernel_time stats;       /* density bands and totals */
+  ck_kernel_time lookup;
+  uint64_t evict_views;       /* bins viewed by the kick-out planners while enabled */
+} ck_timing;
+
+ck_status ck_timing_enable(ck_table* t, int on);
+/* Synchronises `stream`, then copies the timing gathered since enabling. */
+ck_status ck_timing_get(ck_table* t, ck_timing* h_out, void* stream);
+
 /* Canonical image of the table in host memory: per slot key, value (zero
    extended for 32-bit values) and rattle counter; per bin the metadata word
      bits 0-7 duplicate marks, bits 8-11 spawn count, bits 24-31 hit counter.

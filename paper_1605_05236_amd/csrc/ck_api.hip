@@ -12,6 +12,61 @@
 
 using namespace ck;
 
+// Event timing of kernel classes (opt-in).  Pairs of events are recorded
+// around launches and resolved after the stream has been synchronised.
+enum TimedKind { TK_FRESH, TK_EVICT, TK_DELETE, TK_COMMIT, TK_COMPACT, TK_STATS, TK_LOOKUP, TK_N };
+struct Timer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  double ms[TK_N] = {0};
+  uint64_t launches[TK_N] = {0};
+  uint64_t views_base = 0, views_acc = 0;
+  hipEvent_t take() {
+    if (pool.empty()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      return e;
+    }
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t begin(hipStream_t s) {
+    if (!on) return nullptr;
+    hipEvent_t e = take();
+    if (e) (void)hipEventRecord(e, s);
+    return e;
+  }
+  void end(int kind, hipEvent_t b, hipStream_t s) {
+    if (!on || !b) return;
+    hipEvent_t e = take();
+    if (!e) return;
+    (void)hipEventRecord(e, s);
+    pending.push_back({kind, {b, e}});
+  }
+  void collect() {  // the stream has been synchronised
+    for (auto& p : pending) {
+      float t = 0;
+      if (hipEventElapsedTime(&t, p.second.first, p.second.second) == hipSuccess) {
+        ms[p.first] += t;
+        launches[p.first] += 1;
+      }
+      pool.push_back(p.second.first);
+      pool.push_back(p.second.second);
+    }
+    pending.clear();
+  }
+  void reset() {
+    collect();
+    for (int k = 0; k < TK_N; ++k) { ms[k] = 0; launches[k] = 0; }
+  }
+  ~Timer() {
+    for (auto& p : pending) { (void)hipEventDestroy(p.second.first); (void)hipEventDestroy(p.second.second); }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 struct ck_table {
   Geo g;
   ck_options opt;
@@ -43,6 +98,7 @@ struct ck_table {
   uint8_t* req = nullptr;
   // host-side counters
   uint64_t rounds = 0, lookups = 0;
+  Timer timer;
 };
 
 namespace {
@@ -215,18 +271,33 @@ ck_status run_rounds(ck_table* t, Round& r, uint64_t m, hipStream_t s) {
     r.spawns = t->spawns;
     r.spawn_cap = t->spawn_cap;
     r.req = t->req;
+    Timer& T = t->timer;
+    hipEvent_t ev;
     HIP_TRY(launch_round_begin(t->ctr, s));
     if (r.is_delete) {
+      ev = T.begin(s);
       HIP_TRY(launch_plan_delete(t->g, r, s));
+      T.end(TK_DELETE, ev, s);
     } else {
+      ev = T.begin(s);
       HIP_TRY(launch_plan_fresh(t->g, r, s));
+      T.end(TK_FRESH, ev, s);
+      ev = T.begin(s);
       HIP_TRY(launch_compact(r, t->evict, &t->ctr->evict_count, t->comp_tmp, s));
+      T.end(TK_COMPACT, ev, s);
+      ev = T.begin(s);
       HIP_TRY(launch_plan_evict(t->g, r, t->evict_grid, s));
+      T.end(TK_EVICT, ev, s);
     }
+    ev = T.begin(s);
     HIP_TRY(launch_commit(t->g, r, s));
+    T.end(TK_COMMIT, ev, s);
+    ev = T.begin(s);
     HIP_TRY(launch_compact(r, r.next, &t->ctr->next_pending, t->comp_tmp, s));
+    T.end(TK_COMPACT, ev, s);
     HIP_TRY(hipMemcpyAsync(t->h_ctr, t->ctr, sizeof(Ctr), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    T.collect();
     const Ctr c = *t->h_ctr;
     if (c.overflow) {
       ck_status st = grow_arena(t);
@@ -255,7 +326,9 @@ ck_status run_batches(ck_table* t, const uint64_t* keys, const void* vals, uint6
     HIP_TRY(launch_batch_begin(m, t->pend[0], ops[0], ops[1], ops[2], ops[3], ops[4], s));
     ck_status st = run_rounds(t, r, m, s);
     if (st != CK_OK) return st;
+    hipEvent_t ev = t->timer.begin(s);
     HIP_TRY(launch_batch_stats(r, m, slots, t->block_tmp, is_delete ? 1 : 0, s));
+    t->timer.end(TK_STATS, ev, s);
   }
   if (!is_delete) t->insert_count += n;
   return CK_OK;
@@ -337,8 +410,17 @@ ck_status ck_create(uint64_t bins, uint32_t B, uint32_t d, ck_scheme scheme,
   return CK_OK;
 }
 
+static uint64_t sum_wg_views(ck_table* t, hipStream_t s, ck_status* st);
+
 ck_status ck_clear(ck_table* t, void* stream) {
   if (!t) return CK_EINVAL;
+  if (t->timer.on) {  // keep the timing's view count continuous across a clear
+    ck_status st;
+    const uint64_t cur = sum_wg_views(t, (hipStream_t)stream, &st);
+    if (st != CK_OK) return st;
+    t->timer.views_acc += cur - t->timer.views_base;
+    t->timer.views_base = 0;
+  }
   HIP_TRY(launch_init(t->g, (hipStream_t)stream));
   HIP_TRY(hipMemsetAsync(t->dstats, 0, sizeof(DevStats), (hipStream_t)stream));
   HIP_TRY(hipMemsetAsync(t->wg_views, 0, (size_t)t->evict_grid * 8, (hipStream_t)stream));
@@ -369,7 +451,9 @@ ck_status ck_lookup_lpp(ck_table* t, const uint64_t* keys, uint64_t n, void* val
   if (!keys || !vals_out || !found) return CK_EINVAL;
   if (lpp == 0) lpp = t->B;
   if (lpp != 1 && lpp != t->B) return CK_EINVAL;
+  hipEvent_t ev = t->timer.begin((hipStream_t)stream);
   HIP_TRY(launch_lookup(t->g, keys, n, vals_out, found, lpp, t->dstats, (hipStream_t)stream));
+  t->timer.end(TK_LOOKUP, ev, (hipStream_t)stream);
   t->lookups += n;
   return CK_OK;
 }
@@ -435,6 +519,47 @@ ck_status ck_stats_reset(ck_table* t, void* stream) {
   t->rounds = 0;
   t->lookups = 0;
   return CK_OK;
+}
+
+static uint64_t sum_wg_views(ck_table* t, hipStream_t s, ck_status* st) {
+  std::vector<unsigned long long> v(t->evict_grid);
+  *st = CK_OK;
+  if (hipMemcpyAsync(v.data(), t->wg_views, v.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    *st = CK_EDEVICE;
+    return 0;
+  }
+  uint64_t sum = 0;
+  for (auto x : v) sum += x;
+  return sum;
+}
+
+ck_status ck_timing_enable(ck_table* t, int on) {
+  if (!t) return CK_EINVAL;
+  HIP_TRY(hipDeviceSynchronize());
+  t->timer.reset();
+  t->timer.on = on != 0;
+  ck_status st;
+  t->timer.views_acc = 0;
+  t->timer.views_base = sum_wg_views(t, nullptr, &st);
+  return st;
+}
+
+ck_status ck_timing_get(ck_table* t, ck_timing* out, void* stream) {
+  if (!t || !out) return CK_EINVAL;
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  t->timer.collect();
+  ck_kernel_time* dst[TK_N] = {&out->plan_fresh, &out->plan_evict, &out->plan_delete,
+                               &out->commit,     &out->compact,    &out->stats,
+                               &out->lookup};
+  for (int k = 0; k < TK_N; ++k) {
+    dst[k]->launches = t->timer.launches[k];
+    dst[k]->ms = t->timer.ms[k];
+  }
+  ck_status st;
+  const uint64_t v = sum_wg_views(t, (hipStream_t)stream, &st);
+  out->evict_views = t->timer.views_acc + v - t->timer.views_base;
+  return st;
 }
 
 ck_status ck_export(ck_table* t, uint64_t* keys, uint64_t* vals, uint16_t* rattle,

@@ -39,6 +39,17 @@ class CkStats(ctypes.Structure):
         ("band_kicks", ctypes.c_uint64 * BANDS), ("band_fails", ctypes.c_uint64 * BANDS)]
 
 
+class CkKernelTime(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_uint64), ("ms", ctypes.c_double)]
+
+
+_TIMED = ["plan_fresh", "plan_evict", "plan_delete", "commit", "compact", "stats", "lookup"]
+
+
+class CkTiming(ctypes.Structure):
+    _fields_ = [(n, CkKernelTime) for n in _TIMED] + [("evict_views", ctypes.c_uint64)]
+
+
 class CkError(RuntimeError):
     pass
 
@@ -47,7 +58,8 @@ _lib = None
 
 EXPORTED = ["ck_default_options", "ck_storage_bytes", "ck_create", "ck_clear", "ck_insert", "ck_insert_ex",
             "ck_lookup", "ck_lookup_lpp", "ck_delete", "ck_stats_get", "ck_stats_reset",
-            "ck_export", "ck_import", "ck_hash", "ck_insert_count", "ck_destroy", "ck_strerror"]
+            "ck_export", "ck_import", "ck_hash", "ck_insert_count", "ck_destroy", "ck_strerror",
+            "ck_timing_enable", "ck_timing_get"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -79,11 +91,13 @@ def load_library(path: str = LIB_PATH):
     L.ck_insert_count.argtypes = [vp]
     L.ck_insert_count.restype = u64
     L.ck_destroy.argtypes = [vp]
+    L.ck_timing_enable.argtypes = [vp, i32]
+    L.ck_timing_get.argtypes = [vp, ctypes.POINTER(CkTiming), vp]
     L.ck_strerror.argtypes = [i32]
     L.ck_strerror.restype = ctypes.c_char_p
     for f in ("ck_storage_bytes", "ck_create", "ck_clear", "ck_insert", "ck_insert_ex", "ck_lookup",
               "ck_lookup_lpp", "ck_delete", "ck_stats_get", "ck_stats_reset", "ck_export",
-              "ck_import", "ck_hash", "ck_destroy"):
+              "ck_import", "ck_hash", "ck_destroy", "ck_timing_enable", "ck_timing_get"):
         getattr(L, f).restype = i32
     if path == LIB_PATH:
         _lib = L
@@ -224,6 +238,18 @@ class CuckooTable:
                 np.ascontiguousarray(img["rattle"], np.uint16),
                 np.ascontiguousarray(img["meta"], np.uint32)]
         _check(self._L.ck_import(self._h, *[c(a) for a in arrs], _stream(stream)))
+
+    def timing(self, enable=None, stream=None):
+        """Enable/disable per-kernel event timing (resets it), or read it."""
+        if enable is not None:
+            _check(self._L.ck_timing_enable(self._h, int(bool(enable))))
+            return None
+        t = CkTiming()
+        _check(self._L.ck_timing_get(self._h, ctypes.byref(t), _stream(stream)))
+        out = {n: {"launches": int(getattr(t, n).launches), "ms": float(getattr(t, n).ms)}
+               for n in _TIMED}
+        out["evict_views"] = int(t.evict_views)
+        return out
 
     def hash(self, key) -> list[int]:
         out = np.zeros(4, np.uint64)
