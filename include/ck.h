@@ -204,6 +204,42 @@ uint64_t ck_insert_count(const ck_table* t);
    freed.  Synchronises the device. */
 ck_status ck_destroy(ck_table* t);
 
+/* ---- groups: many independent tables of uneven sizes served together ----
+   A group holds n_tables tables (bins[i] bins each; same slots_per_bin, d,
+   scheme and options) in one caller allocation.  Every op names its table
+   (d_table[i] < n_tables); one call serves ops of any mix of tables with the
+   same launches, and its results equal those of per-table calls: a table's
+   ops in one sub-batch of the call (batch_ops ops of the whole call) form that
+   table's sub-batch, in call order.  The random walk's choices are keyed by
+   the op's index in the group's stream of inserts.  Tables never interact:
+   each table's bins are a disjoint range of the group's bin array.  Counters
+   are kept for the group as a whole (no density bands). */
+typedef struct ck_group ck_group;
+
+ck_status ck_group_storage_bytes(uint32_t n_tables, const uint64_t* h_bins,
+                                 uint32_t slots_per_bin, uint32_t d, size_t* out);
+ck_status ck_group_create(uint32_t n_tables, const uint64_t* h_bins, uint32_t slots_per_bin,
+                          uint32_t d, ck_scheme scheme, const ck_options* opt, void* d_storage,
+                          size_t storage_bytes, void* stream, ck_group** out);
+/* Insert; d_views, d_kicks, d_retries may be NULL. */
+ck_status ck_group_insert(ck_group* g, const uint32_t* d_table, const uint64_t* d_keys,
+                          const void* d_vals, uint64_t n, uint8_t* d_status, uint32_t* d_views,
+                          uint32_t* d_kicks, uint32_t* d_retries, void* stream);
+ck_status ck_group_lookup(ck_group* g, const uint32_t* d_table, const uint64_t* d_keys,
+                          uint64_t n, void* d_vals_out, uint8_t* d_found,
+                          uint32_t lanes_per_probe, void* stream);
+ck_status ck_group_delete(ck_group* g, const uint32_t* d_table, const uint64_t* d_keys,
+                          uint64_t n, uint8_t* d_found, void* stream);
+/* Canonical image of one table of the group (as ck_export). */
+ck_status ck_group_export_table(ck_group* g, uint32_t table, uint64_t* h_keys, uint64_t* h_vals,
+                                uint16_t* h_rattle, uint32_t* h_meta, void* stream);
+ck_status ck_group_stats_get(ck_group* g, ck_stats* h_out, void* stream);
+ck_status ck_group_timing_enable(ck_group* g, int on);
+ck_status ck_group_timing_get(ck_group* g, ck_timing* h_out, void* stream);
+ck_status ck_group_clear(ck_group* g, void* stream);
+uint64_t ck_group_insert_count(const ck_group* g);
+ck_status ck_group_destroy(ck_group* g);
+
 const char* ck_strerror(ck_status s);
 
 #ifdef __cplusplus

@@ -586,8 +586,11 @@ void ck_oracle_hash(void* t, uint64_t key, uint64_t* out) { ((Table*)t)->hash(ke
 
 // Insert n keys (assumed absent, Sec. 3).  Per-op outputs: status, bins
 // viewed by the plan that decided the op, kicks, and rounds lost to claims.
-void ck_oracle_insert(void* tp, const uint64_t* keys, const uint64_t* vals, uint64_t n,
-                      uint8_t* status, uint32_t* views, uint32_t* kicks, uint32_t* retries) {
+// `op_ids` (may be null) gives each op's index for the walk's random choices;
+// by default it is the table's running insert count.
+void ck_oracle_insert_ids(void* tp, const uint64_t* keys, const uint64_t* vals,
+                          const uint64_t* op_ids, uint64_t n, uint8_t* status, uint32_t* views,
+                          uint32_t* kicks, uint32_t* retries) {
   Table& T = *(Table*)tp;
   const uint64_t slots = T.p.n * (uint64_t)T.p.B;
   for (uint64_t b0 = 0; b0 < n; b0 += T.p.batch_ops) {
@@ -599,7 +602,10 @@ void ck_oracle_insert(void* tp, const uint64_t* keys, const uint64_t* vals, uint
       if (keys[b0 + i] == kEmpty) res[i].status = ST_BAD_KEY;
       else ids.push_back(i);
     }
-    auto fn = [&](uint64_t i) { return plan_insert(T, base + i, keys[b0 + i], vals[b0 + i]); };
+    auto fn = [&](uint64_t i) {
+      const uint64_t op = op_ids ? op_ids[b0 + i] : base + i;
+      return plan_insert(T, op, keys[b0 + i], vals[b0 + i]);
+    };
     T.st.rounds += run_rounds(T, ids, fn, res);
     // Per-op results and density bands: an op's density is that of the table
     // had the sub-batch been applied one op at a time in op order.
@@ -634,6 +640,11 @@ void ck_oracle_insert(void* tp, const uint64_t* keys, const uint64_t* vals, uint
     T.st.stored += ok_before;
   }
   T.insert_count += n;
+}
+
+void ck_oracle_insert(void* tp, const uint64_t* keys, const uint64_t* vals, uint64_t n,
+                      uint8_t* status, uint32_t* views, uint32_t* kicks, uint32_t* retries) {
+  ck_oracle_insert_ids(tp, keys, vals, nullptr, n, status, views, kicks, retries);
 }
 
 // Lookup (Sec. 1): the key is in one of its bins, probed in hash order.

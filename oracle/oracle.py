@@ -58,6 +58,7 @@ def lib():
         L.ck_oracle_destroy.argtypes = [vp]
         L.ck_oracle_hash.argtypes = [vp, u64, vp]
         L.ck_oracle_insert.argtypes = [vp, vp, vp, u64, vp, vp, vp, vp]
+        L.ck_oracle_insert_ids.argtypes = [vp, vp, vp, vp, u64, vp, vp, vp, vp]
         L.ck_oracle_lookup.argtypes = [vp, vp, u64, vp, vp]
         L.ck_oracle_delete.argtypes = [vp, vp, u64, vp, vp]
         L.ck_oracle_export.argtypes = [vp, vp, vp, vp, vp]
@@ -98,7 +99,9 @@ class OracleTable:
         lib().ck_oracle_hash(self._t, int(key), _p(out))
         return [int(v) for v in out[: self.H]]
 
-    def insert(self, keys, vals):
+    def insert(self, keys, vals, op_ids=None):
+        """Insert; ``op_ids`` optionally fixes each op's index for the walk's
+        random choices (default: the table's running insert count)."""
         keys = np.ascontiguousarray(keys, dtype=np.uint64)
         vals = np.ascontiguousarray(vals, dtype=np.uint64)
         n = keys.size
@@ -106,8 +109,13 @@ class OracleTable:
         views = np.zeros(n, np.uint32)
         kicks = np.zeros(n, np.uint32)
         retries = np.zeros(n, np.uint32)
-        lib().ck_oracle_insert(self._t, _p(keys), _p(vals), n, _p(status), _p(views),
-                               _p(kicks), _p(retries))
+        if op_ids is None:
+            lib().ck_oracle_insert(self._t, _p(keys), _p(vals), n, _p(status), _p(views),
+                                   _p(kicks), _p(retries))
+        else:
+            ids = np.ascontiguousarray(op_ids, dtype=np.uint64)
+            lib().ck_oracle_insert_ids(self._t, _p(keys), _p(vals), _p(ids), n, _p(status),
+                                       _p(views), _p(kicks), _p(retries))
         return {"status": status, "views": views, "kicks": kicks, "retries": retries}
 
     def lookup(self, keys):

@@ -220,8 +220,11 @@ ck_status grow_arena(ck_table* t) {
 }
 
 Round make_round(ck_table* t, const uint64_t* keys, const void* vals, uint8_t* status,
-                 uint32_t** ops, uint64_t op_base, bool is_delete) {
+                 uint32_t** ops, uint64_t op_base, bool is_delete, const uint32_t* op_table,
+                 const uint2* tdesc) {
   Round r{};
+  r.op_table = op_table;
+  r.tdesc = tdesc;
   r.keys = keys;
   r.vals = vals;
   r.hdr = t->hdr;
@@ -313,7 +316,8 @@ ck_status run_rounds(ck_table* t, Round& r, uint64_t m, hipStream_t s) {
 
 ck_status run_batches(ck_table* t, const uint64_t* keys, const void* vals, uint64_t n,
                       uint8_t* status, uint32_t* views, uint32_t* kicks, uint32_t* retries,
-                      bool is_delete, hipStream_t s) {
+                      bool is_delete, hipStream_t s, const uint32_t* op_table = nullptr,
+                      const uint2* tdesc = nullptr) {
   const uint32_t vb = t->B == 1 ? 4 : 8;
   const uint64_t slots = t->bins * t->B;
   for (uint64_t b0 = 0; b0 < n; b0 += t->opt.batch_ops) {
@@ -322,12 +326,14 @@ ck_status run_batches(ck_table* t, const uint64_t* keys, const void* vals, uint6
                         kicks ? kicks + b0 : t->op[2], retries ? retries + b0 : t->op[3],
                         t->op[4]};
     Round r = make_round(t, keys + b0, vals ? (const char*)vals + b0 * vb : nullptr,
-                         status + b0, ops, t->insert_count + b0, is_delete);
+                         status + b0, ops, t->insert_count + b0, is_delete,
+                         op_table ? op_table + b0 : nullptr, tdesc);
     HIP_TRY(launch_batch_begin(m, t->pend[0], ops[0], ops[1], ops[2], ops[3], ops[4], s));
     ck_status st = run_rounds(t, r, m, s);
     if (st != CK_OK) return st;
     hipEvent_t ev = t->timer.begin(s);
-    HIP_TRY(launch_batch_stats(r, m, slots, t->block_tmp, is_delete ? 1 : 0, s));
+    // density bands are per table: a group keeps totals only
+    HIP_TRY(launch_batch_stats(r, m, op_table ? 0 : slots, t->block_tmp, is_delete ? 1 : 0, s));
     t->timer.end(TK_STATS, ev, s);
   }
   if (!is_delete) t->insert_count += n;
@@ -352,10 +358,20 @@ ck_status ck_storage_bytes(uint64_t bins, uint32_t B, uint32_t d, size_t* out) {
   return CK_OK;
 }
 
+static ck_status create_table(uint64_t bins, uint32_t B, uint32_t d, ck_scheme scheme,
+                              const ck_options* opt, void* storage, size_t bytes, void* stream,
+                              ck_table** out);
+
 ck_status ck_create(uint64_t bins, uint32_t B, uint32_t d, ck_scheme scheme,
                     const ck_options* opt, void* storage, size_t bytes, void* stream,
                     ck_table** out) {
   if (!out || !storage || !geometry_ok(bins, B, d)) return CK_EINVAL;
+  return create_table(bins, B, d, scheme, opt, storage, bytes, stream, out);
+}
+
+static ck_status create_table(uint64_t bins, uint32_t B, uint32_t d, ck_scheme scheme,
+                              const ck_options* opt, void* storage, size_t bytes, void* stream,
+                              ck_table** out) {
   *out = nullptr;
   ck_options o;
   ck_default_options(&o);
@@ -452,7 +468,8 @@ ck_status ck_lookup_lpp(ck_table* t, const uint64_t* keys, uint64_t n, void* val
   if (lpp == 0) lpp = t->B;
   if (lpp != 1 && lpp != t->B) return CK_EINVAL;
   hipEvent_t ev = t->timer.begin((hipStream_t)stream);
-  HIP_TRY(launch_lookup(t->g, keys, n, vals_out, found, lpp, t->dstats, (hipStream_t)stream));
+  HIP_TRY(launch_lookup(t->g, keys, n, vals_out, found, lpp, t->dstats, nullptr, nullptr,
+                        (hipStream_t)stream));
   t->timer.end(TK_LOOKUP, ev, (hipStream_t)stream);
   t->lookups += n;
   return CK_OK;
@@ -632,6 +649,154 @@ ck_status ck_destroy(ck_table* t) {
   free_scratch(t);
   delete t;
   return CK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// groups: many tables of uneven sizes in one bin array, served by the same
+// launches (every op carries its table index)
+// ---------------------------------------------------------------------------
+struct ck_group {
+  ck_table* t = nullptr;
+  std::vector<uint64_t> base, bins;
+  uint2* d_tdesc = nullptr;
+};
+
+static bool group_geometry(uint32_t n_tables, const uint64_t* bins, uint32_t B, uint32_t d,
+                           uint64_t* total) {
+  if (n_tables == 0 || !bins) return false;
+  uint64_t sum = 0;
+  for (uint32_t i = 0; i < n_tables; ++i) {
+    if (!geometry_ok(bins[i], B, d)) return false;
+    sum += bins[i];
+  }
+  if (sum >= (1ull << 32)) return false;
+  *total = sum;
+  return true;
+}
+
+ck_status ck_group_storage_bytes(uint32_t n_tables, const uint64_t* bins, uint32_t B,
+                                 uint32_t d, size_t* out) {
+  uint64_t total = 0;
+  if (!out || !group_geometry(n_tables, bins, B, d, &total)) return CK_EINVAL;
+  *out = layout(total, B).total;
+  return CK_OK;
+}
+
+ck_status ck_group_create(uint32_t n_tables, const uint64_t* bins, uint32_t B, uint32_t d,
+                          ck_scheme scheme, const ck_options* opt, void* storage, size_t bytes,
+                          void* stream, ck_group** out) {
+  uint64_t total = 0;
+  if (!out || !storage || !group_geometry(n_tables, bins, B, d, &total)) return CK_EINVAL;
+  *out = nullptr;
+  ck_group* G = new (std::nothrow) ck_group();
+  if (!G) return CK_ENOMEM;
+  ck_status st = create_table(total, B, d, scheme, opt, storage, bytes, stream, &G->t);
+  if (st != CK_OK) {
+    delete G;
+    return st;
+  }
+  std::vector<uint2> desc(n_tables);
+  uint64_t b = 0;
+  for (uint32_t i = 0; i < n_tables; ++i) {
+    G->base.push_back(b);
+    G->bins.push_back(bins[i]);
+    desc[i] = make_uint2((uint32_t)b, (uint32_t)bins[i]);
+    b += bins[i];
+  }
+  if (hipMalloc((void**)&G->d_tdesc, desc.size() * sizeof(uint2)) != hipSuccess ||
+      hipMemcpy(G->d_tdesc, desc.data(), desc.size() * sizeof(uint2), hipMemcpyHostToDevice) !=
+          hipSuccess) {
+    ck_destroy(G->t);
+    (void)hipFree(G->d_tdesc);
+    delete G;
+    return CK_EDEVICE;
+  }
+  *out = G;
+  return CK_OK;
+}
+
+ck_status ck_group_insert(ck_group* G, const uint32_t* d_table, const uint64_t* keys,
+                          const void* vals, uint64_t n, uint8_t* status, uint32_t* views,
+                          uint32_t* kicks, uint32_t* retries, void* stream) {
+  if (!G) return CK_EINVAL;
+  if (n == 0) return CK_OK;
+  if (!d_table || !keys || !vals || !status) return CK_EINVAL;
+  return run_batches(G->t, keys, vals, n, status, views, kicks, retries, false,
+                     (hipStream_t)stream, d_table, G->d_tdesc);
+}
+
+ck_status ck_group_lookup(ck_group* G, const uint32_t* d_table, const uint64_t* keys, uint64_t n,
+                          void* vals_out, uint8_t* found, uint32_t lpp, void* stream) {
+  if (!G) return CK_EINVAL;
+  if (n == 0) return CK_OK;
+  if (!d_table || !keys || !vals_out || !found) return CK_EINVAL;
+  ck_table* t = G->t;
+  if (lpp == 0) lpp = t->B;
+  if (lpp != 1 && lpp != t->B) return CK_EINVAL;
+  hipEvent_t ev = t->timer.begin((hipStream_t)stream);
+  HIP_TRY(launch_lookup(t->g, keys, n, vals_out, found, lpp, t->dstats, d_table, G->d_tdesc,
+                        (hipStream_t)stream));
+  t->timer.end(TK_LOOKUP, ev, (hipStream_t)stream);
+  t->lookups += n;
+  return CK_OK;
+}
+
+ck_status ck_group_delete(ck_group* G, const uint32_t* d_table, const uint64_t* keys, uint64_t n,
+                          uint8_t* found, void* stream) {
+  if (!G) return CK_EINVAL;
+  if (n == 0) return CK_OK;
+  if (!d_table || !keys || !found) return CK_EINVAL;
+  return run_batches(G->t, keys, nullptr, n, found, nullptr, nullptr, nullptr, true,
+                     (hipStream_t)stream, d_table, G->d_tdesc);
+}
+
+ck_status ck_group_export_table(ck_group* G, uint32_t table, uint64_t* keys, uint64_t* vals,
+                                uint16_t* rattle, uint32_t* meta, void* stream) {
+  if (!G || table >= G->bins.size() || !keys || !vals || !rattle || !meta) return CK_EINVAL;
+  ck_table* t = G->t;
+  const uint64_t b0 = G->base[table], nb = G->bins[table];
+  const uint64_t S = nb * t->B;
+  std::vector<ulonglong2> buf(S);
+  HIP_TRY(hipMemcpyAsync(buf.data(), t->g.slots + b0 * t->B, S * 16, hipMemcpyDeviceToHost,
+                         (hipStream_t)stream));
+  HIP_TRY(hipMemcpyAsync(meta, t->g.meta + b0, nb * 4, hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  for (uint64_t i = 0; i < S; ++i) {
+    keys[i] = buf[i].x;
+    vals[i] = t->B == 1 ? (buf[i].y & 0xFFFFFFFFull) : buf[i].y;
+    rattle[i] = t->B == 1 ? (uint16_t)((buf[i].y >> 32) & 0xFFFF) : 0;
+  }
+  return CK_OK;
+}
+
+ck_status ck_group_stats_get(ck_group* G, ck_stats* out, void* stream) {
+  if (!G) return CK_EINVAL;
+  return ck_stats_get(G->t, out, stream);
+}
+
+ck_status ck_group_timing_enable(ck_group* G, int on) {
+  if (!G) return CK_EINVAL;
+  return ck_timing_enable(G->t, on);
+}
+
+ck_status ck_group_timing_get(ck_group* G, ck_timing* out, void* stream) {
+  if (!G) return CK_EINVAL;
+  return ck_timing_get(G->t, out, stream);
+}
+
+ck_status ck_group_clear(ck_group* G, void* stream) {
+  if (!G) return CK_EINVAL;
+  return ck_clear(G->t, stream);
+}
+
+uint64_t ck_group_insert_count(const ck_group* G) { return G ? G->t->insert_count : 0; }
+
+ck_status ck_group_destroy(ck_group* G) {
+  if (!G) return CK_EINVAL;
+  ck_status st = ck_destroy(G->t);
+  (void)hipFree(G->d_tdesc);
+  delete G;
+  return st;
 }
 
 const char* ck_strerror(ck_status s) {

@@ -87,6 +87,11 @@ enum {
   S_DEL_FOUND, S_DEL_PROBES, S_DEL_RETRIES, S_STORED
 };
 
+// A table's bin range inside the bin array (a group of tables shares one).
+struct Tab {
+  uint32_t base, n;
+};
+
 // Everything a kernel needs about a table, passed by value.
 struct Geo {
   uint64_t a[4], c[4];
@@ -103,6 +108,8 @@ struct Geo {
 struct Round {
   const uint64_t* keys;      // sub-batch keys
   const void* vals;          // sub-batch values (8 or 4 bytes each)
+  const uint32_t* op_table;  // group mode: table index of each op (else null)
+  const uint2* tdesc;        // group mode: {bin base, bins} of each table
   const uint32_t* pend;      // pending op indices this round
   uint32_t npend;
   uint32_t* next;            // losers for the next round
@@ -134,7 +141,8 @@ struct Round {
 // ---- launchers (ck_kernels.hip) ----
 hipError_t launch_init(const Geo& g, hipStream_t s);
 hipError_t launch_lookup(const Geo& g, const uint64_t* keys, uint64_t n, void* vals_out,
-                         uint8_t* found, uint32_t lpp, DevStats* st, hipStream_t s);
+                         uint8_t* found, uint32_t lpp, DevStats* st, const uint32_t* op_table,
+                         const uint2* tdesc, hipStream_t s);
 hipError_t launch_round_begin(Ctr* c, hipStream_t s);
 hipError_t launch_batch_begin(uint64_t m, uint32_t* pend, uint32_t* views, uint32_t* lost,
                               uint32_t* kicks, uint32_t* retries, uint32_t* twins, hipStream_t s);

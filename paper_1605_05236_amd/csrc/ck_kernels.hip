@@ -37,21 +37,34 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-// h_i(x) = floor(((a_i x + c_i) mod 2^64) * n / 2^64), stepped past clashes.
+// h_i(x) = floor(((a_i x + c_i) mod 2^64) * n / 2^64), stepped past clashes,
+// in the bin range [t.base, t.base + t.n) of the key's table (a group of
+// tables shares one bin array; a single table has base 0).
 template <int H>
-__device__ __forceinline__ void hash_key(const Geo& g, uint64_t x, uint32_t* h) {
+__device__ __forceinline__ void hash_key(const Geo& g, Tab t, uint64_t x, uint32_t* h) {
+  const uint32_t end = t.base + t.n;
 #pragma unroll
   for (int i = 0; i < H; ++i) {
-    uint32_t b = (uint32_t)__umul64hi(g.a[i] * x + g.c[i], (uint64_t)g.n);
+    uint32_t b = t.base + (uint32_t)__umul64hi(g.a[i] * x + g.c[i], (uint64_t)t.n);
     for (;;) {
       bool clash = false;
 #pragma unroll
       for (int j = 0; j < i; ++j) clash |= (h[j] == b);
       if (!clash) break;
-      b = (b + 1 == g.n) ? 0u : b + 1;
+      b = (b + 1 == end) ? t.base : b + 1;
     }
     h[i] = b;
   }
+}
+
+// The table of op i: from the group's descriptors, else the single table.
+__device__ __forceinline__ Tab tab_of(const Geo& g, const uint32_t* op_table, const uint2* tdesc,
+                                      uint64_t i) {
+  if (op_table) {
+    const uint2 d = tdesc[op_table[i]];
+    return Tab{d.x, d.y};
+  }
+  return Tab{0u, g.n};
 }
 
 // Uniform choice in [0, m): draw t of op `op`; m == 1 consumes no draw.
@@ -136,7 +149,8 @@ __device__ __forceinline__ void block_add2(unsigned long long a, unsigned long l
 template <int B, int LPP, int H>
 __global__ __launch_bounds__(256) void k_lookup(Geo g, const uint64_t* __restrict__ keys,
                                                 uint64_t n, void* __restrict__ out,
-                                                uint8_t* __restrict__ found, DevStats* st) {
+                                                uint8_t* __restrict__ found, DevStats* st,
+                                                const uint32_t* op_table, const uint2* tdesc) {
   constexpr int SPL = B / LPP;
   constexpr int QPB = 256 / LPP;  // queries per block and iteration
   const int lane = threadIdx.x & 63;
@@ -155,7 +169,7 @@ __global__ __launch_bounds__(256) void k_lookup(Geo g, const uint64_t* __restric
     int winner = 0;
     if (x != kEmpty) {
       uint32_t h[H];
-      hash_key<H>(g, x, h);
+      hash_key<H>(g, tab_of(g, op_table, tdesc, q), x, h);
 #pragma unroll
       for (int hi = 0; hi < H; ++hi) {
         const ulonglong2* p = g.slots + (uint64_t)h[hi] * B + gl * SPL;
@@ -197,34 +211,35 @@ __global__ __launch_bounds__(256) void k_lookup(Geo g, const uint64_t* __restric
 
 template <int B, int LPP, int H>
 static void lookup_go(const Geo& g, const uint64_t* keys, uint64_t n, void* out, uint8_t* found,
-                      DevStats* st, hipStream_t s) {
+                      DevStats* st, const uint32_t* op_table, const uint2* tdesc, hipStream_t s) {
   const uint64_t blocks = (n * LPP + 255) / 256;
   const uint32_t grid = (uint32_t)std::min<uint64_t>(blocks, 8192);
   hipLaunchKernelGGL((k_lookup<B, LPP, H>), dim3(grid), dim3(256), 0, s, g, keys, n, out, found,
-                     st);
+                     st, op_table, tdesc);
 }
 
 hipError_t launch_lookup(const Geo& g, const uint64_t* keys, uint64_t n, void* out,
-                         uint8_t* found, uint32_t lpp, DevStats* st, hipStream_t s) {
+                         uint8_t* found, uint32_t lpp, DevStats* st, const uint32_t* op_table,
+                         const uint2* tdesc, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const bool wide = (lpp == g.B);
   switch (g.B) {
     case 1:
-      if (g.H == 2) lookup_go<1, 1, 2>(g, keys, n, out, found, st, s);
-      else if (g.H == 3) lookup_go<1, 1, 3>(g, keys, n, out, found, st, s);
-      else lookup_go<1, 1, 4>(g, keys, n, out, found, st, s);
+      if (g.H == 2) lookup_go<1, 1, 2>(g, keys, n, out, found, st, op_table, tdesc, s);
+      else if (g.H == 3) lookup_go<1, 1, 3>(g, keys, n, out, found, st, op_table, tdesc, s);
+      else lookup_go<1, 1, 4>(g, keys, n, out, found, st, op_table, tdesc, s);
       break;
     case 2:
-      if (wide) lookup_go<2, 2, 2>(g, keys, n, out, found, st, s);
-      else lookup_go<2, 1, 2>(g, keys, n, out, found, st, s);
+      if (wide) lookup_go<2, 2, 2>(g, keys, n, out, found, st, op_table, tdesc, s);
+      else lookup_go<2, 1, 2>(g, keys, n, out, found, st, op_table, tdesc, s);
       break;
     case 4:
-      if (wide) lookup_go<4, 4, 2>(g, keys, n, out, found, st, s);
-      else lookup_go<4, 1, 2>(g, keys, n, out, found, st, s);
+      if (wide) lookup_go<4, 4, 2>(g, keys, n, out, found, st, op_table, tdesc, s);
+      else lookup_go<4, 1, 2>(g, keys, n, out, found, st, op_table, tdesc, s);
       break;
     case 8:
-      if (wide) lookup_go<8, 8, 2>(g, keys, n, out, found, st, s);
-      else lookup_go<8, 1, 2>(g, keys, n, out, found, st, s);
+      if (wide) lookup_go<8, 8, 2>(g, keys, n, out, found, st, op_table, tdesc, s);
+      else lookup_go<8, 1, 2>(g, keys, n, out, found, st, op_table, tdesc, s);
       break;
     default:
       return hipErrorInvalidValue;
@@ -329,9 +344,10 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
   uint32_t nm = 0, views = 0, twins = 0;
   bool placed = false;
   // rattle-kicking has no separate fresh phase: every op goes to the walk
+  const Tab T = tab_of(g, r.op_table, r.tdesc, i);
   if (!bad && g.scheme != CK_RATTLE) {
     uint32_t h[H];
-    hash_key<H>(g, x, h);
+    hash_key<H>(g, T, x, h);
     if (g.ghost) {
       const ulonglong2 s0 = g.slots[(uint64_t)h[0] * B + G.sl];
       const ulonglong2 s1 = g.slots[(uint64_t)h[1] * B + G.sl];
@@ -357,7 +373,7 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
           const uint32_t ds = ffs32(d0 ? d0 : d1);
           const uint64_t dk = __shfl(w == 0 ? s0.x : s1.x, G.gshift + (int)ds, 64);
           uint32_t hd[2];
-          hash_key<2>(g, dk, hd);
+          hash_key<2>(g, T, dk, hd);
           const uint32_t tb = hd[0] == b ? hd[1] : hd[0];
           const ulonglong2 ts = g.slots[(uint64_t)tb * B + G.sl];
           const uint32_t tm = G.ballot(ts.x == dk);
@@ -436,6 +452,7 @@ struct WavePlanner {
   uint32_t nm = 0;     // moves logged
   uint32_t views = 0, kicks = 0, twins = 0, draws = 0;
   uint64_t op = 0;     // global insert index
+  Tab T{0u, 0u};       // the op's table
   bool overflow = false;
 
   // bin view state (lanes < B)
@@ -543,7 +560,7 @@ struct WavePlanner {
   __device__ void replace_dup(uint32_t s, uint64_t k, uint64_t a, uint32_t flags) {
     const uint64_t dk = slot_key(s);
     uint32_t hd[2];
-    hash_key<2>(g, dk, hd);
+    hash_key<2>(g, T, dk, hd);
     const uint32_t here = vbin;
     const uint32_t tb = hd[0] == here ? hd[1] : hd[0];
     ulonglong2 ts = make_ulonglong2(kEmpty, 0ull);
@@ -584,7 +601,7 @@ struct WavePlanner {
       ck = vk;
       ca = va;
       uint32_t hv[H];
-      hash_key<H>(g, ck, hv);
+      hash_key<H>(g, T, ck, hv);
       uint32_t oth[H];
       uint32_t no = 0;
       for (int q = 0; q < H; ++q)
@@ -615,7 +632,7 @@ struct WavePlanner {
       ck = vk;
       ca = va;
       uint32_t hv[2];
-      hash_key<2>(g, ck, hv);
+      hash_key<2>(g, T, ck, hv);
       t = hv[0] == t ? hv[1] : hv[0];
       load(t, true);
       if (terminal()) {
@@ -632,7 +649,7 @@ struct WavePlanner {
     for (;;) {
       if (tries == g.max_chain) return PL_FAIL;
       uint32_t hv[H];
-      hash_key<H>(g, ck, hv);
+      hash_key<H>(g, T, ck, hv);
       uint32_t rr = rattle_of(ca);
       const uint32_t b = hv[rr % H];
       rr = (rr + 1) & 0xFFFF;
@@ -718,8 +735,9 @@ __global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
       const uint64_t xa = load_aux(r.vals, i, B);
       WavePlanner<B, H> P(g, r, L, cap);
       P.op = r.op_base + i;
+      P.T = tab_of(g, r.op_table, r.tdesc, i);
       uint32_t h[H];
-      hash_key<H>(g, x, h);
+      hash_key<H>(g, P.T, x, h);
       uint32_t st;
       if (g.scheme == CK_RATTLE) st = P.rattle(x, xa);
       else if (g.scheme == CK_QUEUE) st = P.queue_kick(x, xa, h);
@@ -800,8 +818,9 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
     const uint64_t xa = load_aux(r.vals, i, B);
     WavePlanner<B, H> P(g, r, L, cap);
     P.op = r.op_base + i;
+    P.T = tab_of(g, r.op_table, r.tdesc, i);
     uint32_t h[H];
-    hash_key<H>(g, x, h);
+    hash_key<H>(g, P.T, x, h);
     P.views = P.fresh_views_full();
     for (uint32_t j = lane; j < VC; j += 64) vis[j] = 0;
     if (lane < 16) { bhead[lane] = kNone; btail[lane] = kNone; }
@@ -884,7 +903,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
       }
       const Ent E = ent[e];
       uint32_t hv[H];
-      hash_key<H>(g, E.key, hv);
+      hash_key<H>(g, P.T, E.key, hv);
       bool spawned = false;
       for (int q = 0; q < H && !done; ++q) {
         const uint32_t c = hv[q];
@@ -1039,7 +1058,7 @@ __global__ __launch_bounds__(256) void k_plan_delete(Geo g, Round r) {
   uint32_t status = PL_NOTFOUND;
   if (x != kEmpty) {
     uint32_t h[H];
-    hash_key<H>(g, x, h);
+    hash_key<H>(g, tab_of(g, r.op_table, r.tdesc, i), x, h);
 #pragma unroll
     for (int hi = 0; hi < H; ++hi) {
       ulonglong2 s = g.slots[(uint64_t)h[hi] * B + G.sl];
@@ -1459,9 +1478,11 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
         if (s == CK_OP_ABORTED) {
           a_abort += 1;
         } else {
-          const uint64_t b = (uint64_t)CK_BANDS * (*stored_before + rank) / slots;
-          band = (uint32_t)(b >= CK_BANDS ? CK_BANDS - 1 : b);
-          banded = true;
+          if (slots) {  // a group of tables has no single density: totals only
+            const uint64_t b = (uint64_t)CK_BANDS * (*stored_before + rank) / slots;
+            band = (uint32_t)(b >= CK_BANDS ? CK_BANDS - 1 : b);
+            banded = true;
+          }
           v_views = views[i];
           a_views += v_views;
           if (ok) {

@@ -59,7 +59,10 @@ _lib = None
 EXPORTED = ["ck_default_options", "ck_storage_bytes", "ck_create", "ck_clear", "ck_insert", "ck_insert_ex",
             "ck_lookup", "ck_lookup_lpp", "ck_delete", "ck_stats_get", "ck_stats_reset",
             "ck_export", "ck_import", "ck_hash", "ck_insert_count", "ck_destroy", "ck_strerror",
-            "ck_timing_enable", "ck_timing_get"]
+            "ck_timing_enable", "ck_timing_get", "ck_group_storage_bytes", "ck_group_create",
+            "ck_group_insert", "ck_group_lookup", "ck_group_delete", "ck_group_export_table",
+            "ck_group_stats_get", "ck_group_timing_enable", "ck_group_timing_get",
+            "ck_group_clear", "ck_group_insert_count", "ck_group_destroy"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -93,11 +96,29 @@ def load_library(path: str = LIB_PATH):
     L.ck_destroy.argtypes = [vp]
     L.ck_timing_enable.argtypes = [vp, i32]
     L.ck_timing_get.argtypes = [vp, ctypes.POINTER(CkTiming), vp]
+    L.ck_group_storage_bytes.argtypes = [u32, vp, u32, u32, ctypes.POINTER(ctypes.c_size_t)]
+    L.ck_group_create.argtypes = [u32, vp, u32, u32, i32, ctypes.POINTER(CkOptions), vp,
+                                  ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.ck_group_insert.argtypes = [vp, vp, vp, vp, u64, vp, vp, vp, vp, vp]
+    L.ck_group_lookup.argtypes = [vp, vp, vp, u64, vp, vp, u32, vp]
+    L.ck_group_delete.argtypes = [vp, vp, vp, u64, vp, vp]
+    L.ck_group_export_table.argtypes = [vp, u32, vp, vp, vp, vp, vp]
+    L.ck_group_stats_get.argtypes = [vp, ctypes.POINTER(CkStats), vp]
+    L.ck_group_timing_enable.argtypes = [vp, i32]
+    L.ck_group_timing_get.argtypes = [vp, ctypes.POINTER(CkTiming), vp]
+    L.ck_group_clear.argtypes = [vp, vp]
+    L.ck_group_insert_count.argtypes = [vp]
+    L.ck_group_insert_count.restype = u64
+    L.ck_group_destroy.argtypes = [vp]
     L.ck_strerror.argtypes = [i32]
     L.ck_strerror.restype = ctypes.c_char_p
     for f in ("ck_storage_bytes", "ck_create", "ck_clear", "ck_insert", "ck_insert_ex", "ck_lookup",
               "ck_lookup_lpp", "ck_delete", "ck_stats_get", "ck_stats_reset", "ck_export",
-              "ck_import", "ck_hash", "ck_destroy", "ck_timing_enable", "ck_timing_get"):
+              "ck_import", "ck_hash", "ck_destroy", "ck_timing_enable", "ck_timing_get",
+              "ck_group_storage_bytes", "ck_group_create", "ck_group_insert", "ck_group_lookup",
+              "ck_group_delete", "ck_group_export_table", "ck_group_stats_get",
+              "ck_group_timing_enable", "ck_group_timing_get", "ck_group_clear",
+              "ck_group_destroy"):
         getattr(L, f).restype = i32
     if path == LIB_PATH:
         _lib = L
@@ -259,3 +280,125 @@ class CuckooTable:
     @property
     def insert_count(self) -> int:
         return int(self._L.ck_insert_count(self._h))
+
+
+def _options(ghost, load_balance, max_chain, max_search, max_rounds, batch_ops, hash_seed,
+             rng_seed):
+    opt = CkOptions()
+    load_library().ck_default_options(ctypes.byref(opt))
+    opt.ghost, opt.load_balance = int(ghost), int(load_balance)
+    opt.max_chain, opt.max_search, opt.max_rounds = max_chain, max_search, max_rounds
+    opt.batch_ops, opt.hash_seed, opt.rng_seed = batch_ops, hash_seed, rng_seed
+    return opt
+
+
+def _timing_dict(t: CkTiming) -> dict:
+    out = {n: {"launches": int(getattr(t, n).launches), "ms": float(getattr(t, n).ms)}
+           for n in _TIMED}
+    out["evict_views"] = int(t.evict_views)
+    return out
+
+
+class CuckooGroup:
+    """Many independent tables of uneven sizes in one device allocation, served
+    by the same launches: every op carries its table index (int32 tensor)."""
+
+    def __init__(self, bins, slots_per_bin=4, d=2, scheme="queue", ghost=False,
+                 load_balance=False, max_chain=500, max_search=500, max_rounds=0,
+                 batch_ops=1 << 20, hash_seed=0, rng_seed=0, device="cuda", stream=None):
+        import torch
+        L = load_library()
+        self.bins = np.ascontiguousarray(bins, dtype=np.uint64)
+        self.n_tables, self.B, self.H = int(self.bins.size), int(slots_per_bin), int(d)
+        self.device = torch.device(device)
+        self.value_dtype = torch.int32 if self.B == 1 else torch.int64
+        size = ctypes.c_size_t()
+        _check(L.ck_group_storage_bytes(self.n_tables, self.bins.ctypes.data_as(ctypes.c_void_p),
+                                        self.B, self.H, ctypes.byref(size)))
+        self.storage = torch.empty(int(size.value), dtype=torch.uint8, device=self.device)
+        opt = _options(ghost, load_balance, max_chain, max_search, max_rounds, batch_ops,
+                       hash_seed, rng_seed)
+        h = ctypes.c_void_p()
+        sch = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
+        _check(L.ck_group_create(self.n_tables, self.bins.ctypes.data_as(ctypes.c_void_p),
+                                 self.B, self.H, sch, ctypes.byref(opt), _ptr(self.storage),
+                                 self.storage.numel(), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self._L = L
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.ck_group_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def clear(self, stream=None):
+        _check(self._L.ck_group_clear(self._h, _stream(stream)))
+
+    def insert(self, tables, keys, vals, stream=None, diagnostics=True):
+        import torch
+        n = keys.numel()
+        status = torch.empty(n, dtype=torch.uint8, device=self.device)
+        if diagnostics:
+            views = torch.empty(n, dtype=torch.int32, device=self.device)
+            kicks, retries = torch.empty_like(views), torch.empty_like(views)
+            ptrs = (_ptr(views), _ptr(kicks), _ptr(retries))
+        else:
+            ptrs = (None, None, None)
+        _check(self._L.ck_group_insert(self._h, _ptr(tables), _ptr(keys), _ptr(vals), n,
+                                       _ptr(status), *ptrs, _stream(stream)))
+        if not diagnostics:
+            return {"status": status}
+        return {"status": status, "views": views, "kicks": kicks, "retries": retries}
+
+    def lookup(self, tables, keys, lanes_per_probe=0, stream=None, out=None, found=None):
+        import torch
+        n = keys.numel()
+        if out is None:
+            out = torch.empty(n, dtype=self.value_dtype, device=self.device)
+        if found is None:
+            found = torch.empty(n, dtype=torch.uint8, device=self.device)
+        _check(self._L.ck_group_lookup(self._h, _ptr(tables), _ptr(keys), n, _ptr(out),
+                                       _ptr(found), lanes_per_probe, _stream(stream)))
+        return out, found
+
+    def delete(self, tables, keys, stream=None):
+        import torch
+        found = torch.empty(keys.numel(), dtype=torch.uint8, device=self.device)
+        _check(self._L.ck_group_delete(self._h, _ptr(tables), _ptr(keys), keys.numel(),
+                                       _ptr(found), _stream(stream)))
+        return found
+
+    def export_table(self, table, stream=None) -> dict:
+        nb = int(self.bins[table])
+        S = nb * self.B
+        keys = np.zeros(S, np.uint64)
+        vals = np.zeros(S, np.uint64)
+        rattle = np.zeros(S, np.uint16)
+        meta = np.zeros(nb, np.uint32)
+        c = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        _check(self._L.ck_group_export_table(self._h, int(table), c(keys), c(vals), c(rattle),
+                                             c(meta), _stream(stream)))
+        return {"keys": keys, "vals": vals, "rattle": rattle, "meta": meta}
+
+    def stats(self, stream=None) -> dict:
+        st = CkStats()
+        _check(self._L.ck_group_stats_get(self._h, ctypes.byref(st), _stream(stream)))
+        return {n: int(getattr(st, n)) for n in _SCALARS}
+
+    def timing(self, enable=None, stream=None):
+        if enable is not None:
+            _check(self._L.ck_group_timing_enable(self._h, int(bool(enable))))
+            return None
+        t = CkTiming()
+        _check(self._L.ck_group_timing_get(self._h, ctypes.byref(t), _stream(stream)))
+        return _timing_dict(t)
+
+    @property
+    def insert_count(self) -> int:
+        return int(self._L.ck_group_insert_count(self._h))
