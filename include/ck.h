@@ -163,7 +163,8 @@ ck_status ck_stats_get(ck_table* t, ck_stats* h_out, void* stream);
 ck_status ck_stats_reset(ck_table* t, void* stream);
 
 /* Per-kernel timing, measured with HIP events on the caller's stream around
-   every launch of each kernel class while enabled (enabling resets it). */
+   every launch of each enabled kernel class (enabling resets it).  Two events
+   per timed launch: time only the classes of interest in timed runs. */
 typedef struct {
   uint64_t launches;
   double ms;            /* summed launch durations */
@@ -180,7 +181,12 @@ typedef struct {
   uint64_t evict_views;       /* bins viewed by the kick-out planners while enabled */
 } ck_timing;
 
-ck_status ck_timing_enable(ck_table* t, int on);
+/* Classes to time (bit mask for ck_timing_enable); 0 turns timing off. */
+enum {
+  CK_TIME_PLAN_FRESH = 1, CK_TIME_PLAN_EVICT = 2, CK_TIME_PLAN_DELETE = 4, CK_TIME_COMMIT = 8,
+  CK_TIME_COMPACT = 16, CK_TIME_STATS = 32, CK_TIME_LOOKUP = 64, CK_TIME_ALL = 127
+};
+ck_status ck_timing_enable(ck_table* t, uint32_t class_mask);
 /* Synchronises `stream`, then copies the timing gathered since enabling. */
 ck_status ck_timing_get(ck_table* t, ck_timing* h_out, void* stream);
 
@@ -234,7 +240,7 @@ ck_status ck_group_delete(ck_group* g, const uint32_t* d_table, const uint64_t* 
 ck_status ck_group_export_table(ck_group* g, uint32_t table, uint64_t* h_keys, uint64_t* h_vals,
                                 uint16_t* h_rattle, uint32_t* h_meta, void* stream);
 ck_status ck_group_stats_get(ck_group* g, ck_stats* h_out, void* stream);
-ck_status ck_group_timing_enable(ck_group* g, int on);
+ck_status ck_group_timing_enable(ck_group* g, uint32_t class_mask);
 ck_status ck_group_timing_get(ck_group* g, ck_timing* h_out, void* stream);
 ck_status ck_group_clear(ck_group* g, void* stream);
 uint64_t ck_group_insert_count(const ck_group* g);

@@ -17,6 +17,7 @@ using namespace ck;
 enum TimedKind { TK_FRESH, TK_EVICT, TK_DELETE, TK_COMMIT, TK_COMPACT, TK_STATS, TK_LOOKUP, TK_N };
 struct Timer {
   bool on = false;
+  uint32_t mask = 0;
   std::vector<hipEvent_t> pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
   double ms[TK_N] = {0};
@@ -32,8 +33,8 @@ struct Timer {
     pool.pop_back();
     return e;
   }
-  hipEvent_t begin(hipStream_t s) {
-    if (!on) return nullptr;
+  hipEvent_t begin(hipStream_t s, int kind) {
+    if (!on || !(mask & (1u << kind))) return nullptr;
     hipEvent_t e = take();
     if (e) (void)hipEventRecord(e, s);
     return e;
@@ -251,65 +252,81 @@ Round make_round(ck_table* t, const uint64_t* keys, const void* vals, uint8_t* s
   return r;
 }
 
-// Run the phased rounds of one sub-batch until no op is pending.
+// Run the phased rounds of one sub-batch until no op is pending.  Large
+// rounds are sized from the pending count the host read back; once at most
+// kTailOps ops remain, kTailRounds rounds are enqueued back to back with the
+// count held in device memory (grids sized for the last count read, which
+// only shrinks), and the host synchronises once per group of rounds.
+constexpr uint32_t kTailOps = 4096;
+constexpr int kTailRounds = 4;
+
 ck_status run_rounds(ck_table* t, Round& r, uint64_t m, hipStream_t s) {
   uint32_t npend = (uint32_t)m;
   int cur = 0;
   // The lowest pending op always commits, so m rounds suffice; arena growth
   // adds a few void rounds.  Anything beyond that is a fault, not progress.
   uint64_t guard = 2 * m + 64;
+  Timer& T = t->timer;
+  HIP_TRY(hipMemsetAsync(&t->ctr->rounds, 0, 4, s));
+  HIP_TRY(hipMemsetAsync(&t->ctr->overflow_seen, 0, 4, s));
   while (npend > 0) {
-    if (guard-- == 0) return CK_EDEVICE;
-    ++t->epoch;
-    if (t->epoch == 0) {  // claim tags wrapped: reset every claim word
-      HIP_TRY(hipMemsetAsync(t->g.owner, 0xFF, (size_t)t->bins * 8, s));
-      t->epoch = 1;
-    }
-    r.tag = (unsigned long long)(~t->epoch) << 32;
-    r.pend = t->pend[cur];
-    r.npend = npend;
-    r.next = t->pend[cur ^ 1];
-    r.arena = t->arena;
-    r.arena_cap = t->arena_cap;
-    r.spawns = t->spawns;
-    r.spawn_cap = t->spawn_cap;
-    r.req = t->req;
-    Timer& T = t->timer;
-    hipEvent_t ev;
-    HIP_TRY(launch_round_begin(t->ctr, s));
-    if (r.is_delete) {
-      ev = T.begin(s);
-      HIP_TRY(launch_plan_delete(t->g, r, s));
-      T.end(TK_DELETE, ev, s);
-    } else {
-      ev = T.begin(s);
-      HIP_TRY(launch_plan_fresh(t->g, r, s));
-      T.end(TK_FRESH, ev, s);
-      ev = T.begin(s);
-      HIP_TRY(launch_compact(r, t->evict, &t->ctr->evict_count, t->comp_tmp, s));
+    if (guard == 0) return CK_EDEVICE;
+    const int K = npend <= kTailOps ? kTailRounds : 1;
+    for (int k = 0; k < K; ++k) {
+      --guard;
+      ++t->epoch;
+      if (t->epoch == 0) {  // claim tags wrapped: reset every claim word
+        HIP_TRY(hipMemsetAsync(t->g.owner, 0xFF, (size_t)t->bins * 8, s));
+        t->epoch = 1;
+      }
+      r.tag = (unsigned long long)(~t->epoch) << 32;
+      r.pend = t->pend[cur];
+      r.npend = npend;
+      r.npend_dev = k == 0 ? nullptr : &t->ctr->pending[cur];
+      r.next = t->pend[cur ^ 1];
+      r.next_count = &t->ctr->pending[cur ^ 1];
+      r.arena = t->arena;
+      r.arena_cap = t->arena_cap;
+      r.spawns = t->spawns;
+      r.spawn_cap = t->spawn_cap;
+      r.req = t->req;
+      hipEvent_t ev;
+      HIP_TRY(launch_round_begin(t->ctr, s));
+      if (r.is_delete) {
+        ev = T.begin(s, TK_DELETE);
+        HIP_TRY(launch_plan_delete(t->g, r, s));
+        T.end(TK_DELETE, ev, s);
+      } else {
+        ev = T.begin(s, TK_FRESH);
+        HIP_TRY(launch_plan_fresh(t->g, r, s));
+        T.end(TK_FRESH, ev, s);
+        ev = T.begin(s, TK_COMPACT);
+        HIP_TRY(launch_compact(r, t->evict, &t->ctr->evict_count, t->comp_tmp, s));
+        T.end(TK_COMPACT, ev, s);
+        ev = T.begin(s, TK_EVICT);
+        HIP_TRY(launch_plan_evict(t->g, r, t->evict_grid, s));
+        T.end(TK_EVICT, ev, s);
+      }
+      ev = T.begin(s, TK_COMMIT);
+      HIP_TRY(launch_commit(t->g, r, s));
+      T.end(TK_COMMIT, ev, s);
+      ev = T.begin(s, TK_COMPACT);
+      HIP_TRY(launch_compact(r, r.next, r.next_count, t->comp_tmp, s));
       T.end(TK_COMPACT, ev, s);
-      ev = T.begin(s);
-      HIP_TRY(launch_plan_evict(t->g, r, t->evict_grid, s));
-      T.end(TK_EVICT, ev, s);
+      cur ^= 1;
     }
-    ev = T.begin(s);
-    HIP_TRY(launch_commit(t->g, r, s));
-    T.end(TK_COMMIT, ev, s);
-    ev = T.begin(s);
-    HIP_TRY(launch_compact(r, r.next, &t->ctr->next_pending, t->comp_tmp, s));
-    T.end(TK_COMPACT, ev, s);
     HIP_TRY(hipMemcpyAsync(t->h_ctr, t->ctr, sizeof(Ctr), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     T.collect();
     const Ctr c = *t->h_ctr;
-    if (c.overflow) {
+    if (c.overflow || c.overflow_seen) {
       ck_status st = grow_arena(t);
       if (st != CK_OK) return st;
-    } else if (!r.is_delete) {
-      ++t->rounds;
+      HIP_TRY(hipMemsetAsync(&t->ctr->overflow_seen, 0, 4, s));
+      HIP_TRY(hipMemsetAsync(&t->ctr->overflow, 0, 4, s));
     }
-    npend = c.next_pending;
-    cur ^= 1;
+    npend = c.pending[cur];
+    if (npend == 0 && !r.is_delete) t->rounds += c.rounds;
   }
   return CK_OK;
 }
@@ -331,7 +348,7 @@ ck_status run_batches(ck_table* t, const uint64_t* keys, const void* vals, uint6
     HIP_TRY(launch_batch_begin(m, t->pend[0], ops[0], ops[1], ops[2], ops[3], ops[4], s));
     ck_status st = run_rounds(t, r, m, s);
     if (st != CK_OK) return st;
-    hipEvent_t ev = t->timer.begin(s);
+    hipEvent_t ev = t->timer.begin(s, TK_STATS);
     // density bands are per table: a group keeps totals only
     HIP_TRY(launch_batch_stats(r, m, op_table ? 0 : slots, t->block_tmp, is_delete ? 1 : 0, s));
     t->timer.end(TK_STATS, ev, s);
@@ -467,7 +484,7 @@ ck_status ck_lookup_lpp(ck_table* t, const uint64_t* keys, uint64_t n, void* val
   if (!keys || !vals_out || !found) return CK_EINVAL;
   if (lpp == 0) lpp = t->B;
   if (lpp != 1 && lpp != t->B) return CK_EINVAL;
-  hipEvent_t ev = t->timer.begin((hipStream_t)stream);
+  hipEvent_t ev = t->timer.begin((hipStream_t)stream, TK_LOOKUP);
   HIP_TRY(launch_lookup(t->g, keys, n, vals_out, found, lpp, t->dstats, nullptr, nullptr,
                         (hipStream_t)stream));
   t->timer.end(TK_LOOKUP, ev, (hipStream_t)stream);
@@ -551,11 +568,12 @@ static uint64_t sum_wg_views(ck_table* t, hipStream_t s, ck_status* st) {
   return sum;
 }
 
-ck_status ck_timing_enable(ck_table* t, int on) {
+ck_status ck_timing_enable(ck_table* t, uint32_t mask) {
   if (!t) return CK_EINVAL;
   HIP_TRY(hipDeviceSynchronize());
   t->timer.reset();
-  t->timer.on = on != 0;
+  t->timer.on = mask != 0;
+  t->timer.mask = mask;
   ck_status st;
   t->timer.views_acc = 0;
   t->timer.views_base = sum_wg_views(t, nullptr, &st);
@@ -733,7 +751,7 @@ ck_status ck_group_lookup(ck_group* G, const uint32_t* d_table, const uint64_t* 
   ck_table* t = G->t;
   if (lpp == 0) lpp = t->B;
   if (lpp != 1 && lpp != t->B) return CK_EINVAL;
-  hipEvent_t ev = t->timer.begin((hipStream_t)stream);
+  hipEvent_t ev = t->timer.begin((hipStream_t)stream, TK_LOOKUP);
   HIP_TRY(launch_lookup(t->g, keys, n, vals_out, found, lpp, t->dstats, d_table, G->d_tdesc,
                         (hipStream_t)stream));
   t->timer.end(TK_LOOKUP, ev, (hipStream_t)stream);
@@ -774,9 +792,9 @@ ck_status ck_group_stats_get(ck_group* G, ck_stats* out, void* stream) {
   return ck_stats_get(G->t, out, stream);
 }
 
-ck_status ck_group_timing_enable(ck_group* G, int on) {
+ck_status ck_group_timing_enable(ck_group* G, uint32_t mask) {
   if (!G) return CK_EINVAL;
-  return ck_timing_enable(G->t, on);
+  return ck_timing_enable(G->t, mask);
 }
 
 ck_status ck_group_timing_get(ck_group* G, ck_timing* out, void* stream) {

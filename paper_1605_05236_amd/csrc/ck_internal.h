@@ -67,13 +67,12 @@ __host__ __device__ inline uint32_t hdr_pack(uint32_t status, uint32_t twins, ui
   return status | (twins << 4) | (nm << 8);
 }
 
-struct Ctr {             // device counters of one round
-  uint32_t next_pending;
-  uint32_t evict_count;
-  uint32_t evict_taken;
-  uint32_t arena_used;
-  uint32_t spawn_used;
-  uint32_t overflow;
+struct Ctr {             // device counters of the round loop
+  uint32_t pending[2];   // pending ops of the round of parity p (written by compaction)
+  uint32_t evict_count;  // ops of this round that need an eviction plan
+  uint32_t overflow;     // a planner ran out of arena this round (round is void)
+  uint32_t overflow_seen;  // sticky: some round since the host last looked was void
+  uint32_t rounds;       // rounds that committed (not void, ops pending)
   uint32_t pad[2];
 };
 
@@ -111,7 +110,9 @@ struct Round {
   const uint32_t* op_table;  // group mode: table index of each op (else null)
   const uint2* tdesc;        // group mode: {bin base, bins} of each table
   const uint32_t* pend;      // pending op indices this round
-  uint32_t npend;
+  uint32_t npend;            // pending ops, or an upper bound when npend_dev is set
+  const uint32_t* npend_dev; // device-held pending count (rounds enqueued without a sync)
+  uint32_t* next_count;      // where this round's compaction writes next round's count
   uint32_t* next;            // losers for the next round
   uint8_t* req;              // per pending position: 1 = pending again next round
   uint32_t* evict;           // ops that need an eviction plan

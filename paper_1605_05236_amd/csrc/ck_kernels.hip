@@ -57,6 +57,13 @@ __device__ __forceinline__ void hash_key(const Geo& g, Tab t, uint64_t x, uint32
   }
 }
 
+// Pending ops of this round: a kernel argument, or (for rounds enqueued
+// back to back without a host sync) the count the previous round's
+// compaction left in device memory; the argument is then an upper bound.
+__device__ __forceinline__ uint32_t npend_of(const Round& r) {
+  return r.npend_dev ? *r.npend_dev : r.npend;
+}
+
 // The table of op i: from the group's descriptors, else the single table.
 __device__ __forceinline__ Tab tab_of(const Geo& g, const uint32_t* op_table, const uint2* tdesc,
                                       uint64_t i) {
@@ -252,11 +259,8 @@ hipError_t launch_lookup(const Geo& g, const uint64_t* keys, uint64_t n, void* o
 // ---------------------------------------------------------------------------
 __global__ void k_round_begin(Ctr* c) {
   if (threadIdx.x == 0) {
-    c->next_pending = 0;
+    if (c->overflow) c->overflow_seen = 1;
     c->evict_count = 0;
-    c->evict_taken = 0;
-    c->arena_used = 0;
-    c->spawn_used = 0;
     c->overflow = 0;
   }
 }
@@ -332,7 +336,7 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
   G.sl = G.lane % B;
   G.gshift = G.lane - G.sl;
   const uint64_t gidx = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / B;
-  if (gidx >= r.npend) return;
+  if (gidx >= npend_of(r)) return;
   const uint32_t i = r.pend[gidx];
   const uint64_t x = r.keys[i];
   const bool leader = G.sl == 0;
@@ -1049,7 +1053,7 @@ __global__ __launch_bounds__(256) void k_plan_delete(Geo g, Round r) {
   G.sl = G.lane % B;
   G.gshift = G.lane - G.sl;
   const uint64_t gidx = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / B;
-  if (gidx >= r.npend) return;
+  if (gidx >= npend_of(r)) return;
   const uint32_t i = r.pend[gidx];
   const uint64_t x = r.keys[i];
   const bool leader = G.sl == 0;
@@ -1133,7 +1137,7 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
   const int gl = lane & (CL - 1);
   const int gshift = lane & ~(CL - 1);
   const uint64_t gidx = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / CL;
-  if (gidx >= r.npend) return;
+  if (gidx >= npend_of(r)) return;
   const uint32_t i = r.pend[gidx];
   const bool leader = gl == 0;
   // set by an earlier kernel: a plain load, once per wavefront, broadcast
@@ -1141,6 +1145,7 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
   uint32_t ov = 0;
   if (lane == first) ov = r.ctr->overflow;
   const bool void_round = __shfl(ov, first, 64) != 0;
+  if (gidx == 0 && leader && !void_round) atomicAdd(&r.ctr->rounds, 1u);
   bool requeue = false;
   uint32_t n_spawn = 0, spawn_off = 0;
   if (void_round) {  // a planner ran out of arena: nothing of this round applies
@@ -1263,11 +1268,12 @@ __device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
 
 __global__ __launch_bounds__(256) void k_compact_count(Round r, uint32_t* cnt) {
   __shared__ uint32_t ws[4];
+  const uint32_t n = npend_of(r);
   const uint32_t base = blockIdx.x * kCompTile + threadIdx.x * kCompPer;
   uint32_t c = 0;
 #pragma unroll
   for (int k = 0; k < kCompPer; ++k)
-    if (base + k < r.npend && keep_pos(r, base + k)) ++c;
+    if (base + k < n && keep_pos(r, base + k)) ++c;
   c = wave_sum32(c);
   if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = c;
   __syncthreads();
@@ -1306,12 +1312,13 @@ __global__ __launch_bounds__(1024) void k_scan_excl(uint32_t* a, uint32_t n, uin
 __global__ __launch_bounds__(256) void k_compact_scatter(Round r, const uint32_t* pre,
                                                          uint32_t* out) {
   __shared__ uint32_t ws[4];
+  const uint32_t n = npend_of(r);
   const uint32_t base = blockIdx.x * kCompTile + threadIdx.x * kCompPer;
   bool kk[kCompPer];
   uint32_t c = 0;
 #pragma unroll
   for (int k = 0; k < kCompPer; ++k) {
-    kk[k] = base + k < r.npend && keep_pos(r, base + k);
+    kk[k] = base + k < n && keep_pos(r, base + k);
     c += kk[k] ? 1 : 0;
   }
   const int lane = threadIdx.x & 63;
@@ -1338,9 +1345,10 @@ __global__ __launch_bounds__(1024) void k_compact_small(Round r, uint32_t* out, 
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  for (uint32_t base = 0; base < r.npend; base += 1024) {
+  const uint32_t n = npend_of(r);
+  for (uint32_t base = 0; base < n; base += 1024) {
     const uint32_t p = base + threadIdx.x;
-    const bool keep = p < r.npend && keep_pos(r, p);
+    const bool keep = p < n && keep_pos(r, p);
     const uint64_t b = __ballot(keep);
     if (lane == 0) wsum[threadIdx.x >> 6] = (uint32_t)__popcll(b);
     __syncthreads();

@@ -44,6 +44,16 @@ class CkKernelTime(ctypes.Structure):
 
 
 _TIMED = ["plan_fresh", "plan_evict", "plan_delete", "commit", "compact", "stats", "lookup"]
+TIME_ALL = 127
+
+
+def time_mask(classes) -> int:
+    """Bit mask of kernel classes for timing(enable=...)."""
+    if classes is True:
+        return TIME_ALL
+    if not classes:
+        return 0
+    return sum(1 << _TIMED.index(c) for c in classes)
 
 
 class CkTiming(ctypes.Structure):
@@ -94,7 +104,7 @@ def load_library(path: str = LIB_PATH):
     L.ck_insert_count.argtypes = [vp]
     L.ck_insert_count.restype = u64
     L.ck_destroy.argtypes = [vp]
-    L.ck_timing_enable.argtypes = [vp, i32]
+    L.ck_timing_enable.argtypes = [vp, u32]
     L.ck_timing_get.argtypes = [vp, ctypes.POINTER(CkTiming), vp]
     L.ck_group_storage_bytes.argtypes = [u32, vp, u32, u32, ctypes.POINTER(ctypes.c_size_t)]
     L.ck_group_create.argtypes = [u32, vp, u32, u32, i32, ctypes.POINTER(CkOptions), vp,
@@ -104,7 +114,7 @@ def load_library(path: str = LIB_PATH):
     L.ck_group_delete.argtypes = [vp, vp, vp, u64, vp, vp]
     L.ck_group_export_table.argtypes = [vp, u32, vp, vp, vp, vp, vp]
     L.ck_group_stats_get.argtypes = [vp, ctypes.POINTER(CkStats), vp]
-    L.ck_group_timing_enable.argtypes = [vp, i32]
+    L.ck_group_timing_enable.argtypes = [vp, u32]
     L.ck_group_timing_get.argtypes = [vp, ctypes.POINTER(CkTiming), vp]
     L.ck_group_clear.argtypes = [vp, vp]
     L.ck_group_insert_count.argtypes = [vp]
@@ -261,9 +271,10 @@ class CuckooTable:
         _check(self._L.ck_import(self._h, *[c(a) for a in arrs], _stream(stream)))
 
     def timing(self, enable=None, stream=None):
-        """Enable/disable per-kernel event timing (resets it), or read it."""
+        """Enable per-kernel event timing (True = every class, or a list of
+        class names; False or [] disables; enabling resets it), or read it."""
         if enable is not None:
-            _check(self._L.ck_timing_enable(self._h, int(bool(enable))))
+            _check(self._L.ck_timing_enable(self._h, time_mask(enable)))
             return None
         t = CkTiming()
         _check(self._L.ck_timing_get(self._h, ctypes.byref(t), _stream(stream)))
@@ -393,7 +404,7 @@ class CuckooGroup:
 
     def timing(self, enable=None, stream=None):
         if enable is not None:
-            _check(self._L.ck_group_timing_enable(self._h, int(bool(enable))))
+            _check(self._L.ck_group_timing_enable(self._h, time_mask(enable)))
             return None
         t = CkTiming()
         _check(self._L.ck_group_timing_get(self._h, ctypes.byref(t), _stream(stream)))
