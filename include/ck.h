@@ -90,6 +90,10 @@ typedef struct {
                             depend on it (1 = serial) */
   uint64_t hash_seed;    /* seeds the hash multipliers */
   uint64_t rng_seed;     /* seeds the random walk's choices */
+  uint32_t evict_wgs_per_cu; /* kick-out planner workgroups per compute unit;
+                                0 = as many as the LDS budget allows (<= 32).
+                                Performance only: results do not depend on it */
+  uint32_t reserved;
 } ck_options;
 
 /* Counters of one table since creation (or the last ck_stats_reset). */

@@ -174,6 +174,7 @@ ck_status alloc_scratch(ck_table* t) {
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const size_t lds = evict_lds_bytes(t->g);
   size_t per_cu = std::max<size_t>(1, std::min<size_t>(32, (160 * 1024) / std::max<size_t>(lds, 1)));
+  if (t->opt.evict_wgs_per_cu) per_cu = std::min<size_t>(per_cu, t->opt.evict_wgs_per_cu);
   t->evict_grid = (uint32_t)(cus * per_cu);
   t->wg_bytes = (uint32_t)evict_wg_scratch_bytes(t->g);
   HIP_TRY(hipMalloc(&t->wg_scratch, (size_t)t->evict_grid * t->wg_bytes));

@@ -87,3 +87,124 @@ def log_uniform_int(seed: int, count: int, lo_exp: float, hi_exp: float) -> np.n
     rng = np.random.default_rng(seed)
     return np.round(np.power(2.0, lo_exp + (hi_exp - lo_exp) * rng.random(count))).astype(
         np.int64)
+
+
+# ---------------------------------------------------------------------------
+# device-side generation for large workloads (bit-identical to splitmix64())
+# ---------------------------------------------------------------------------
+def _i64(c: int) -> int:
+    return c - (1 << 64) if c >= (1 << 63) else c
+
+
+def splitmix64_torch(seed: int, start: int, count: int, device="cuda"):
+    """Same outputs as splitmix64(seed, start, count), as an int64 tensor holding
+    the uint64 bit patterns, computed on `device` (two's-complement wrap)."""
+    import torch
+    idx = torch.arange(start + 1, start + count + 1, dtype=torch.int64, device=device)
+    z = _i64(seed & ((1 << 64) - 1)) + idx * _i64(int(GOLDEN))
+    lo34 = (1 << 34) - 1
+    lo37 = (1 << 37) - 1
+    lo33 = (1 << 33) - 1
+    z = (z ^ ((z >> 30) & lo34)) * _i64(int(_M1))
+    z = (z ^ ((z >> 27) & lo37)) * _i64(int(_M2))
+    return z ^ ((z >> 31) & lo33)
+
+
+def keys_values_torch(seed: int, count: int, start: int = 0, device="cuda", value_bits=64):
+    """keys_values() on the device: (keys, values) int64 tensors."""
+    s = splitmix64_torch(seed, 2 * start, 2 * count, device)
+    keys = s[0::2].contiguous()
+    vals = s[1::2].contiguous()
+    if value_bits == 32:
+        vals = vals & 0xFFFFFFFF
+    if bool((keys == -1).any()):
+        raise ValueError("key stream hit the reserved empty key")
+    return keys, vals
+
+
+# ---------------------------------------------------------------------------
+# many tables: bin counts and request streams
+# ---------------------------------------------------------------------------
+def group_tables(seed: int, count: int, lo_exp: float, hi_exp: float, min_bins: int = 4):
+    """Bin counts round(2^(lo + (hi-lo) u)), u uniform."""
+    return np.maximum(log_uniform_int(seed, count, lo_exp, hi_exp), min_bins).astype(np.uint64)
+
+
+class RequestStream:
+    """Seeded requests to many tables prefilled from one key stream.
+
+    Table t is prefilled with records [pre_start[t], pre_start[t] + pre[t]) of
+    the key stream `key_seed`: the first half is the lookup target (never
+    deleted), the second half is consumed in order by deletes.  Inserts take
+    fresh records from a per-table range beyond every prefill; lookup misses are
+    fresh records nobody inserts.  Requests: a table (uniform), a type (lookup,
+    insert, delete with the given shares), a size log-uniform on [1, max_ops].
+    """
+
+    def __init__(self, seed, bins, slots_per_bin, prefill_load, key_seed, shares=(0.7, 0.2, 0.1),
+                 max_ops=65536, hit_rate=0.9):
+        self.rng = np.random.default_rng(seed)
+        self.bins = np.asarray(bins, dtype=np.int64)
+        self.nt = self.bins.size
+        self.pre = np.floor(prefill_load * self.bins * slots_per_bin).astype(np.int64)
+        self.pre_start = np.concatenate([[0], np.cumsum(self.pre)[:-1]])
+        total_pre = int(self.pre.sum())
+        cap = (self.bins * slots_per_bin - self.pre).astype(np.int64)
+        self.fresh_start = total_pre + np.concatenate([[0], np.cumsum(cap)[:-1]])
+        self.fresh_cap = cap
+        self.miss_start = total_pre + int(cap.sum())
+        self.key_seed = key_seed
+        self.shares = np.asarray(shares, dtype=np.float64) / np.sum(shares)
+        self.max_ops = max_ops
+        self.hit_rate = hit_rate
+        self.fresh_used = np.zeros(self.nt, np.int64)
+        self.del_used = np.zeros(self.nt, np.int64)
+        self.miss_used = 0
+
+    def prefill_records(self):
+        """(start, count) of the prefill records of every table, in table order."""
+        return self.pre_start, self.pre
+
+    def next(self):
+        """One request: (kind, table, record indices into the key stream)."""
+        rng = self.rng
+        t = int(rng.integers(0, self.nt))
+        kind = int(rng.choice(3, p=self.shares))
+        n = int(np.round(np.exp(rng.uniform(0.0, np.log(self.max_ops)))))
+        n = max(1, min(n, self.max_ops))
+        if kind == 1:  # insert fresh records (bounded by the table's free slots)
+            n = int(min(n, max(0, self.fresh_cap[t] // 2 - self.fresh_used[t])))
+            rec = self.fresh_start[t] + self.fresh_used[t] + np.arange(n, dtype=np.int64)
+            self.fresh_used[t] += n
+        elif kind == 2:  # delete the next unused records of the second half
+            half = self.pre[t] // 2
+            n = int(min(n, max(0, self.pre[t] - half - self.del_used[t])))
+            rec = self.pre_start[t] + half + self.del_used[t] + np.arange(n, dtype=np.int64)
+            self.del_used[t] += n
+        else:  # lookups: hits in the first half, misses from the miss range
+            half = max(1, self.pre[t] // 2)
+            hits = rng.random(n) < self.hit_rate
+            rec = np.where(hits, self.pre_start[t] + rng.integers(0, half, n), -1)
+            nm = int((~hits).sum())
+            rec[~hits] = self.miss_start + self.miss_used + np.arange(nm)
+            self.miss_used += nm
+        return kind, t, rec.astype(np.int64)
+
+
+def _mix_torch(z):
+    lo34, lo37, lo33 = (1 << 34) - 1, (1 << 37) - 1, (1 << 33) - 1
+    z = (z ^ ((z >> 30) & lo34)) * _i64(int(_M1))
+    z = (z ^ ((z >> 27) & lo37)) * _i64(int(_M2))
+    return z ^ ((z >> 31) & lo33)
+
+
+def keys_at_torch(seed: int, records, value_bits=64):
+    """Key and value of arbitrary record indices (int64 tensor) of the stream
+    keys_values(seed, ...): record r is splitmix64 outputs 2r and 2r+1."""
+    s0 = _i64(seed & ((1 << 64) - 1))
+    g = _i64(int(GOLDEN))
+    keys = _mix_torch(s0 + (2 * records + 1) * g)
+    vals = _mix_torch(s0 + (2 * records + 2) * g)
+    if value_bits == 32:
+        vals = vals & 0xFFFFFFFF
+    return keys, vals
