@@ -45,6 +45,8 @@ def parse():
     p.add_argument("--hit-rate", type=float, default=0.9)
     p.add_argument("--deletes-log2", type=int, default=20)
     p.add_argument("--max-search", type=int, default=500)
+    p.add_argument("--lpp", type=int, default=0,
+                   help="lookup lanes per probe (1 or slots per bin; 0 = slots per bin)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-bins-log2", type=int, default=19)
     p.add_argument("--workload", default="fill", choices=["fill", "group"],
@@ -258,7 +260,7 @@ def main():
         t = tables[schemes[-1]]
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         e0.record(stream)
-        t.lookup(dq, out=vout, found=fout)
+        t.lookup(dq, out=vout, found=fout, lanes_per_probe=args.lpp)
         e1.record(stream)
         t.delete(ddel)
         e2.record(stream)
@@ -318,7 +320,8 @@ def main():
     probes_per_q = lt["lookup_probes"] / max(1, lt["lookups"])
     bytes_per_q = 17 + probes_per_q * B * 16
     achieved = nq * bytes_per_q / lookup_s / 1e9
-    lookup_roof = {"bound": "hbm", "kernel": f"k_lookup<{B},{B},2>", "achieved": achieved,
+    lpp = args.lpp or B
+    lookup_roof = {"bound": "hbm", "kernel": f"k_lookup<{B},{lpp},2>", "achieved": achieved,
                    "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                    "bytes_per_query": bytes_per_q}
     # the dominant kernel class, timed with HIP events over every timed step
