@@ -139,18 +139,26 @@ class RequestStream:
     fresh records from a per-table range beyond every prefill; lookup misses are
     fresh records nobody inserts.  Requests: a table (uniform), a type (lookup,
     insert, delete with the given shares), a size log-uniform on [1, max_ops].
+
+    `take(count)` draws requests as arrays; `records_torch` expands them into
+    the record index of every op, on any torch device.  A lookup op with
+    global lookup index g draws u = splitmix64 output g of `lookup_seed`: it
+    hits (record pre_start[t] + floor(lo32(u) * half / 2^32)) when
+    hi53(u) / 2^53 < hit_rate, else it misses (record miss_start + g).
     """
 
     def __init__(self, seed, bins, slots_per_bin, prefill_load, key_seed, shares=(0.7, 0.2, 0.1),
                  max_ops=65536, hit_rate=0.9):
         self.rng = np.random.default_rng(seed)
+        self.lookup_seed = int(self.rng.integers(0, 1 << 62))
         self.bins = np.asarray(bins, dtype=np.int64)
         self.nt = self.bins.size
         self.pre = np.floor(prefill_load * self.bins * slots_per_bin).astype(np.int64)
-        self.pre_start = np.concatenate([[0], np.cumsum(self.pre)[:-1]])
+        self.pre_start = np.concatenate([[0], np.cumsum(self.pre)[:-1]]).astype(np.int64)
+        self.half = np.maximum(1, self.pre // 2)
         total_pre = int(self.pre.sum())
         cap = (self.bins * slots_per_bin - self.pre).astype(np.int64)
-        self.fresh_start = total_pre + np.concatenate([[0], np.cumsum(cap)[:-1]])
+        self.fresh_start = total_pre + np.concatenate([[0], np.cumsum(cap)[:-1]]).astype(np.int64)
         self.fresh_cap = cap
         self.miss_start = total_pre + int(cap.sum())
         self.key_seed = key_seed
@@ -159,36 +167,113 @@ class RequestStream:
         self.hit_rate = hit_rate
         self.fresh_used = np.zeros(self.nt, np.int64)
         self.del_used = np.zeros(self.nt, np.int64)
-        self.miss_used = 0
+        self.lookup_used = 0
 
     def prefill_records(self):
         """(start, count) of the prefill records of every table, in table order."""
         return self.pre_start, self.pre
 
+    def take(self, count):
+        """`count` requests: dict of int64 arrays kind (0 lookup, 1 insert,
+        2 delete), table, n (ops; inserts and deletes are clipped to what the
+        table has left) and base (the first op's index within its kind's
+        per-table range, or the first global lookup index)."""
+        rng = self.rng
+        table = rng.integers(0, self.nt, count).astype(np.int64)
+        kind = rng.choice(3, size=count, p=self.shares).astype(np.int64)
+        n = np.round(np.exp(rng.uniform(0.0, np.log(self.max_ops), count))).astype(np.int64)
+        n = np.clip(n, 1, self.max_ops)
+        base = np.zeros(count, np.int64)
+        fresh_left = self.fresh_cap // 2 - self.fresh_used
+        del_left = self.pre - self.pre // 2 - self.del_used
+        for i in range(count):  # per-table budgets make clipping sequential
+            t, k = table[i], kind[i]
+            if k == 1:
+                m = min(n[i], max(0, fresh_left[t]))
+                base[i] = self.fresh_used[t]
+                self.fresh_used[t] += m
+                fresh_left[t] -= m
+                n[i] = m
+            elif k == 2:
+                m = min(n[i], max(0, del_left[t]))
+                base[i] = self.del_used[t]
+                self.del_used[t] += m
+                del_left[t] -= m
+                n[i] = m
+            else:
+                base[i] = self.lookup_used
+                self.lookup_used += n[i]
+        return {"kind": kind, "table": table, "n": n, "base": base}
+
+    def records_torch(self, req, r0=0, r1=None, device="cuda"):
+        """Record index of every op of requests [r0, r1) of `req` (from take),
+        concatenated in request order, as an int64 tensor on `device`."""
+        import torch
+        r1 = req["n"].size if r1 is None else r1
+        n = torch.from_numpy(req["n"][r0:r1]).to(device)
+        total = int(req["n"][r0:r1].sum())
+        seg = torch.repeat_interleave(torch.arange(r1 - r0, device=device), n, output_size=total)
+        first = torch.cumsum(n, 0) - n
+        j = torch.arange(total, device=device) - first[seg]
+        t = torch.from_numpy(req["table"][r0:r1]).to(device)[seg]
+        k = torch.from_numpy(req["kind"][r0:r1]).to(device)[seg]
+        b = torch.from_numpy(req["base"][r0:r1]).to(device)[seg] + j
+        pre_start = torch.from_numpy(self.pre_start).to(device)
+        half = torch.from_numpy(self.half).to(device)
+        fresh_start = torch.from_numpy(self.fresh_start).to(device)
+        ins = fresh_start[t] + b
+        dele = pre_start[t] + (torch.from_numpy(self.pre).to(device) // 2)[t] + b
+        u = _mix_torch(_i64(self.lookup_seed) + (b + 1) * _i64(int(GOLDEN)))
+        hit = ((u >> 11) & ((1 << 53) - 1)).to(torch.float64) < self.hit_rate * float(1 << 53)
+        pos = ((u & 0xFFFFFFFF) * half[t]) >> 32
+        look = torch.where(hit, pre_start[t] + pos, self.miss_start + b)
+        return torch.where(k == 1, ins, torch.where(k == 2, dele, look))
+
+    def payload(self, req, device="cuda", chunk_ops=1 << 25, pin=True):
+        """Keys and values of every op of `req` in request order, as int64
+        tensors in host memory (pinned when `pin`), generated on `device` chunk
+        by chunk, and per op the expected answer (uint8): 1 for inserts,
+        deletes and lookups that hit, 0 for lookup misses."""
+        import torch
+        off = np.concatenate([[0], np.cumsum(req["n"])]).astype(np.int64)
+        total = int(off[-1])
+        keys = torch.empty(max(total, 1), dtype=torch.int64, pin_memory=pin)
+        vals = torch.empty(max(total, 1), dtype=torch.int64, pin_memory=pin)
+        expect = torch.empty(max(total, 1), dtype=torch.uint8, pin_memory=pin)
+        r0, R = 0, off.size - 1
+        while r0 < R:
+            r1 = int(np.searchsorted(off, off[r0] + chunk_ops, side="right")) - 1
+            r1 = min(max(r1, r0 + 1), R)
+            o0, o1 = int(off[r0]), int(off[r1])
+            if o1 > o0:
+                rec = self.records_torch(req, r0, r1, device)
+                k, v = keys_at_torch(self.key_seed, rec)
+                keys[o0:o1].copy_(k)
+                vals[o0:o1].copy_(v)
+                expect[o0:o1].copy_((rec < self.miss_start).to(torch.uint8))
+            r0 = r1
+        return keys, vals, expect
+
+    def prefill_payload(self, device="cuda", chunk_ops=1 << 25, pin=True):
+        """Keys and values of every prefill record, table after table (the
+        records are 0 .. sum(pre) - 1), as int64 tensors in host memory."""
+        import torch
+        total = int(self.pre.sum())
+        keys = torch.empty(max(total, 1), dtype=torch.int64, pin_memory=pin)
+        vals = torch.empty(max(total, 1), dtype=torch.int64, pin_memory=pin)
+        for c0 in range(0, total, chunk_ops):
+            c1 = min(total, c0 + chunk_ops)
+            k, v = keys_at_torch(self.key_seed,
+                                 torch.arange(c0, c1, dtype=torch.int64, device=device))
+            keys[c0:c1].copy_(k)
+            vals[c0:c1].copy_(v)
+        return keys, vals
+
     def next(self):
         """One request: (kind, table, record indices into the key stream)."""
-        rng = self.rng
-        t = int(rng.integers(0, self.nt))
-        kind = int(rng.choice(3, p=self.shares))
-        n = int(np.round(np.exp(rng.uniform(0.0, np.log(self.max_ops)))))
-        n = max(1, min(n, self.max_ops))
-        if kind == 1:  # insert fresh records (bounded by the table's free slots)
-            n = int(min(n, max(0, self.fresh_cap[t] // 2 - self.fresh_used[t])))
-            rec = self.fresh_start[t] + self.fresh_used[t] + np.arange(n, dtype=np.int64)
-            self.fresh_used[t] += n
-        elif kind == 2:  # delete the next unused records of the second half
-            half = self.pre[t] // 2
-            n = int(min(n, max(0, self.pre[t] - half - self.del_used[t])))
-            rec = self.pre_start[t] + half + self.del_used[t] + np.arange(n, dtype=np.int64)
-            self.del_used[t] += n
-        else:  # lookups: hits in the first half, misses from the miss range
-            half = max(1, self.pre[t] // 2)
-            hits = rng.random(n) < self.hit_rate
-            rec = np.where(hits, self.pre_start[t] + rng.integers(0, half, n), -1)
-            nm = int((~hits).sum())
-            rec[~hits] = self.miss_start + self.miss_used + np.arange(nm)
-            self.miss_used += nm
-        return kind, t, rec.astype(np.int64)
+        r = self.take(1)
+        rec = self.records_torch(r, device="cpu").numpy()
+        return int(r["kind"][0]), int(r["table"][0]), rec
 
 
 def _mix_torch(z):
