@@ -76,6 +76,24 @@ def zipf_ranks(seed: int, n_items: int, count: int, s: float = 0.99) -> np.ndarr
     return np.minimum(np.searchsorted(cdf, rng.random(count)), n_items - 1)
 
 
+class ZipfTorch:
+    """Ranks in [0, n_items) with P(rank k) proportional to 1/(k+1)^s, drawn on
+    a torch device from a seeded generator (inverse CDF by binary search)."""
+
+    def __init__(self, n_items: int, s: float = 0.99, device="cuda"):
+        import torch
+        self.n = int(n_items)
+        w = torch.arange(1, self.n + 1, dtype=torch.float64, device=device).pow_(-s)
+        self.cdf = torch.cumsum(w, 0)
+        self.cdf /= self.cdf[-1].clone()
+        self.device = device
+
+    def sample(self, gen, count: int):
+        import torch
+        u = torch.rand(count, generator=gen, dtype=torch.float64, device=self.device)
+        return torch.searchsorted(self.cdf, u).clamp_(max=self.n - 1)
+
+
 def poisson_arrivals(seed: int, count: int, rate_per_s: float) -> np.ndarray:
     """Open-loop arrival times in seconds (exponential gaps of mean 1/rate)."""
     rng = np.random.default_rng(seed)

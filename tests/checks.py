@@ -98,3 +98,73 @@ def check_invariants(img, n, B, H, hash_seed, ghost=False, rattle=False):
         where = hb[np.arange(k.size), (r - 1) % H]
         assert np.all(where == b), "rattle counter does not name the key's bin"
     return set(uk.tolist())
+
+
+# ---------------------------------------------------------------------------
+# the same checks in torch (wrapping int64 arithmetic), for full-size images
+# on the GPU; held equal to the numpy checks above by a CPU test
+# ---------------------------------------------------------------------------
+def _i64(c: int) -> int:
+    return c - (1 << 64) if c >= (1 << 63) else c
+
+
+def bins_of_torch(keys, n: int, H: int, hash_seed: int):
+    """bins_of() for an int64 tensor of uint64 bit patterns: (len, H) int64."""
+    import torch
+    assert n < (1 << 32)
+    a, c = hash_params(hash_seed, H)
+    m32 = 0xFFFFFFFF
+    out = []
+    for i in range(H):
+        z = keys * _i64(a[i]) + _i64(c[i])
+        hi = (z >> 32) & m32
+        lo = z & m32
+        h = ((hi * n + (((lo * n) >> 32) & m32)) >> 32) & m32
+        while True:
+            clash = torch.zeros_like(h, dtype=torch.bool)
+            for j in range(i):
+                clash |= out[j] == h
+            if not bool(clash.any()):
+                break
+            h = torch.where(clash, (h + 1) % n, h)
+        out.append(h)
+    return torch.stack(out, dim=1)
+
+
+def check_image_torch(img, n, B, H, hash_seed, ghost=False, rattle=False, device="cuda"):
+    """check_invariants() on `device`.  Returns the number of distinct stored keys."""
+    import torch
+    keys = torch.from_numpy(np.ascontiguousarray(img["keys"]).view(np.int64)).to(device)
+    vals = torch.from_numpy(np.ascontiguousarray(img["vals"]).view(np.int64)).to(device)
+    meta = torch.from_numpy(np.ascontiguousarray(img["meta"]).astype(np.int64)).to(device)
+    S = n * B
+    assert keys.numel() == S and meta.numel() == n
+    occ = keys != -1
+    slot = torch.arange(S, device=device)
+    sbin = slot // B
+    dup = ((meta[sbin] >> (slot % B)) & 1).bool()
+    assert not bool((dup & ~occ).any()), "duplicate mark on an empty slot"
+    k, b, d, v = keys[occ], sbin[occ], dup[occ], vals[occ]
+    del slot, sbin, dup
+    hb = bins_of_torch(k, n, H, hash_seed)
+    assert bool((hb == b[:, None]).any(dim=1).all()), "a key sits outside its bins"
+    if not ghost:
+        assert not bool(d.any()), "duplicate marks without ghost insertions"
+    if rattle:
+        r = torch.from_numpy(np.ascontiguousarray(img["rattle"]).astype(np.int64)).to(device)[occ]
+        assert bool((r >= 1).all()), "stored key with no try recorded"
+        where = hb[torch.arange(k.numel(), device=device), (r - 1) % H]
+        assert bool((where == b).all()), "rattle counter does not name the key's bin"
+    del hb
+    ks, order = torch.sort(k, stable=True)
+    uk, counts = torch.unique_consecutive(ks, return_counts=True)
+    cnt = torch.repeat_interleave(counts, counts)
+    ds = d[order]
+    assert bool((cnt[~ds] == 1).all()), "unmarked key stored twice"
+    if bool(ds.any()):
+        assert bool((cnt[ds] == 2).all()), "a duplicate without its twin"
+        bs, vs = b[order][ds], v[order][ds]
+        assert bool((ks[ds][0::2] == ks[ds][1::2]).all()), "a duplicate without its twin"
+        assert bool((bs[0::2] != bs[1::2]).all()), "ghost twins in the same bin"
+        assert bool((vs[0::2] == vs[1::2]).all()), "ghost twins with different values"
+    return int(uk.numel())

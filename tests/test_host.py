@@ -95,3 +95,73 @@ def test_payload_matches_key_stream():
     npre = int(rs.pre.sum())
     assert np.array_equal(pk.numpy()[:npre].view(np.uint64), kk[:npre] if kk.size >= npre
                           else inputs.keys_values(41, npre)[0])
+
+
+# ---------------------------------------------------------------------------
+# the torch image checker (used at full size on the GPU) agrees with the numpy
+# checker on oracle images and catches the same planted faults
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("scheme,B,d,ghost", [("queue", 4, 2, True), ("bfs", 8, 2, False),
+                                              ("rattle", 1, 3, False),
+                                              ("random_walk", 1, 4, False)])
+def test_torch_checker_matches_numpy_checker(scheme, B, d, ghost):
+    import checks
+    import oracle
+    n = 1 << 10
+    load = 0.95 if B > 1 else 0.85
+    keys, vals = inputs.keys_values(12, inputs.target_count(n, B, load),
+                                    value_bits=32 if B == 1 else 64)
+    o = oracle.OracleTable(n, B, d, scheme, ghost=ghost, hash_seed=77, rng_seed=78,
+                           max_chain=1000, batch_ops=100)
+    st = o.insert(keys, vals)["status"]
+    img = o.export()
+    rat = scheme == "rattle"
+    stored = checks.check_invariants(img, n, B, d, 77, ghost=ghost, rattle=rat)
+    assert checks.check_image_torch(img, n, B, d, 77, ghost=ghost, rattle=rat,
+                                    device="cpu") == len(stored) == int((st == 1).sum())
+    hb = checks.bins_of(keys[:500], n, d, 77)
+    import torch
+    ht = checks.bins_of_torch(torch.from_numpy(keys[:500].view(np.int64)), n, d, 77).numpy()
+    assert np.array_equal(hb.astype(np.int64), ht)
+
+    def planted(mutate):
+        bad = {f: a.copy() for f, a in img.items()}
+        mutate(bad)
+        for fn in (lambda: checks.check_invariants(bad, n, B, d, 77, ghost=ghost, rattle=rat),
+                   lambda: checks.check_image_torch(bad, n, B, d, 77, ghost=ghost, rattle=rat,
+                                                    device="cpu")):
+            with pytest.raises(AssertionError):
+                fn()
+
+    occ = np.nonzero(img["keys"] != checks.EMPTY)[0]
+    empty = np.nonzero(img["keys"] == checks.EMPTY)[0]
+    s0 = occ[0]
+    others = [s for s in empty if s // B not in set(checks.bins_of(img["keys"][s0:s0 + 1], n, d,
+                                                                   77)[0].tolist())]
+
+    def move_out(bad):  # a key copied into a slot outside its bins
+        bad["keys"][others[0]] = bad["keys"][s0]
+        bad["keys"][s0] = checks.EMPTY
+
+    def twice(bad):  # an unmarked second copy (in one of its own bins)
+        hb0 = checks.bins_of(img["keys"][s0:s0 + 1], n, d, 77)[0]
+        for bb in hb0.tolist():
+            free = [s for s in range(bb * B, bb * B + B) if img["keys"][s] == checks.EMPTY]
+            if free:
+                bad["keys"][free[0]] = bad["keys"][s0]
+                if rat:
+                    bad["rattle"][free[0]] = 1 + hb0.tolist().index(bb)
+                return
+        bad["keys"][others[0]] = bad["keys"][s0]  # no room: falls back to a misplacement
+
+    planted(move_out)
+    planted(twice)
+    if rat:
+        def wrong_counter(bad):
+            bad["rattle"][s0] = bad["rattle"][s0] % d + 1
+        planted(wrong_counter)
+    if ghost:
+        def mark_single(bad):  # a duplicate mark with no twin
+            s = next(x for x in occ if not (img["meta"][x // B] >> np.uint32(x % B)) & 1)
+            bad["meta"][s // B] |= np.uint32(1 << (s % B))
+        planted(mark_single)
