@@ -753,43 +753,55 @@ __global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
 }
 
 // ---- breadth-first and sorted search (Sec. 5) ------------------------------
-struct Ent {
-  uint64_t key;
-  uint32_t bin;
-  uint32_t ps;  // parent entry << 3 | slot ; parent kNone>>3 for root records
-};
-constexpr uint32_t kRootParent = 0x1FFFFFFFu;
+// Records are kept in runs: run r holds the B slots of the r-th bin put on
+// the search frontier (runs 0..H-1 are the key's own bins, in hash order), so
+// record e is slot e % B of run e / B.  A bin is visited iff it is the bin of
+// a run (a viewed bin that is not terminal becomes a run; a terminal one ends
+// the search).  When a run is created its B keys are hashed in parallel and
+// each record's candidate bins (its key's other bins) are stored; the root
+// records keep theirs in registers.  BFS expands records in index order;
+// sorted search keeps 16 FIFO buckets of runs by spawn count and expands the
+// head record of the lowest non-empty bucket.
+//
+// The frontier is expanded 64 / B bins at a time: the next records in search
+// order are taken as a group, their candidate bins are fetched by one
+// wave-wide load (B lanes per bin), and the records are then processed one by
+// one in order, exactly as the serial search does.  Searches read the
+// round-start snapshot only, so fetching ahead changes no result; a group is
+// abandoned at a record boundary when a new run has gone to a lower bucket,
+// since the next record in order is then another one.
+//
+// The plan (chain moves root first, then the terminal write, preceded by the
+// twin's mark clear when a ghost duplicate is replaced) goes straight to the
+// workgroup's arena region, one move per lane.
+constexpr uint32_t kRootParent = 0xFFFFFFFFu;
+
+size_t search_runs(const Geo& g) { return (size_t)g.max_search + 8 + g.H; }
 
 template <int B, int H>
 __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
-  // LDS: visited-bin set, spawn list, 16 bucket heads/tails, path; the move
-  // log and the record list live in this workgroup's global scratch (the
-  // search never re-reads its own writes, so the log needs no fast overlay).
+  // LDS: run bins, run parents, bucket lists.  Workgroup scratch (global):
+  // candidate bins of non-root records, spawn list, deep paths.
   extern __shared__ uint32_t lds32[];
   __shared__ uint32_t win[4];  // arena region, spawn region
+  __shared__ uint32_t s_off;
   __shared__ unsigned long long s_views;  // bins viewed by this workgroup's plans
-  const uint32_t ms8 = g.max_search + 8;
-  uint32_t VC = 1;  // visited set: open addressing on bin+1, power-of-two size
-  while (VC < 2 * ms8) VC <<= 1;
-  WaveLog L;
-  L.last = (int*)lds32;
-  L.misc = lds32 + 8;
-  uint32_t* vis = lds32 + 16;
-  uint32_t* bhead = vis + VC;      // 16 bucket heads
-  uint32_t* btail = bhead + 16;
-  const uint32_t cap = ms8;        // move log: path, terminal, twin
-  const uint32_t ecap = ms8 * B;
+  constexpr uint32_t C = H - 1;   // candidates per record
+  constexpr uint32_t G = 64 / B;  // bins per wave-wide load
+  constexpr uint32_t RB = H * B;  // root records
+  const uint32_t RC = g.max_search + 8 + H;
+  uint32_t* rbin = lds32;         // run -> bin
+  uint32_t* rpar = rbin + RC;     // run -> parent record (kRootParent for roots)
+  uint32_t* rnext = rpar + RC;    // run -> next run of its bucket (sorted)
+  uint32_t* bhead = rnext + RC;   // record at the head of each bucket
+  uint32_t* btail = bhead + 16;   // last run of each bucket
   char* scratch = (char*)r.wg_scratch + (size_t)blockIdx.x * r.wg_scratch_bytes;
-  Ent* ent = (Ent*)scratch;
-  uint32_t* nxt = (uint32_t*)(ent + ecap);
-  uint32_t* spl = nxt + ecap;      // spawn list (sorted search)
-  uint32_t* path = spl + ms8;      // path entries
-  L.key = (uint64_t*)(path + ms8 + ((ecap + 2 * ms8) & 1));
-  L.aux = L.key + cap;
-  L.bin = (uint32_t*)(L.aux + cap);
-  L.sf = L.bin + cap;
+  uint32_t* cand = (uint32_t*)scratch;         // RC * B * C
+  uint32_t* spl = cand + (size_t)RC * B * C;   // RC: runs that spawned (sorted)
+  uint32_t* path = spl + RC;                   // RC: records, deepest first
   const int lane = threadIdx.x;
   const bool sorted = g.scheme == CK_SORTED;
+  const bool need_meta = sorted || g.ghost;
   if (lane == 0) {
     region_init(win, r.arena_cap);
     region_init(win + 2, r.spawn_cap);
@@ -797,196 +809,325 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
   }
   __syncthreads();
   const uint32_t total = r.ctr->evict_count;  // final: written by the compaction
-  const uint32_t vshift = 32 - (31 - __clz(VC));
-
-  auto vis_find_or_insert = [&](uint32_t b, bool insert) -> bool {
-    // all lanes walk the same probe sequence; lane 0 writes
-    uint32_t pos = (b * 0x9E3779B1u) >> vshift;
-    for (;;) {
-      const uint32_t v = vis[pos];
-      if (v == b + 1) return true;
-      if (v == 0) {
-        if (insert) {
-          if (lane == 0) vis[pos] = b + 1;
-          __syncthreads();
-        }
-        return false;
-      }
-      pos = (pos + 1) & (VC - 1);
-    }
-  };
 
   for (uint32_t k = blockIdx.x; k < total; k += gridDim.x) {
     const uint32_t i = r.evict[k];
     const uint64_t x = r.keys[i];
     const uint64_t xa = load_aux(r.vals, i, B);
-    WavePlanner<B, H> P(g, r, L, cap);
-    P.op = r.op_base + i;
-    P.T = tab_of(g, r.op_table, r.tdesc, i);
+    const Tab T = tab_of(g, r.op_table, r.tdesc, i);
     uint32_t h[H];
-    hash_key<H>(g, P.T, x, h);
-    P.views = P.fresh_views_full();
-    for (uint32_t j = lane; j < VC; j += 64) vis[j] = 0;
-    if (lane < 16) { bhead[lane] = kNone; btail[lane] = kNone; }
-    __syncthreads();
-    uint32_t head = 0, tail = 0, nsp = 0;
-    // enqueue the records of bin b (already loaded into lanes < B), parent p
-    auto enqueue = [&](uint32_t b, uint32_t parent, uint32_t bucket) {
-      if (lane < B) {
-        Ent e;
-        e.key = P.vkey;
-        e.bin = b;
-        e.ps = (parent << 3) | (uint32_t)lane;
-        ent[tail + lane] = e;
-        if (sorted) nxt[tail + lane] = (lane + 1 < B) ? tail + lane + 1 : kNone;
-      }
-      if (sorted && lane == 0) {
-        if (btail[bucket] == kNone) bhead[bucket] = tail;
-        else nxt[btail[bucket]] = tail;
-        btail[bucket] = tail + B - 1;
-      }
-      tail += B;
-      __syncthreads();
-    };
-    // the records of the key's own bins, all loaded at once (H*B lanes),
-    // listed bin by bin in hash order
-    for (int q = 0; q < H; ++q) vis_find_or_insert(h[q], true);
-    {
+    hash_key<H>(g, T, x, h);
+    // ops reach this planner after the fresh planner found no room in the
+    // same snapshot: first fit viewed all H bins, ghost inserts both bins
+    uint32_t views = g.ghost ? 2u : (uint32_t)H;
+    // ---- root runs: the key's own bins, loaded at once by H*B lanes
+    uint32_t rc[C];
+#pragma unroll
+    for (int j = 0; j < (int)C; ++j) rc[j] = 0;
+    uint32_t bk = 0;
+    if (lane < (int)RB) {
       const int q = lane / B, sl = lane % B;
-      uint32_t bk = 0;
-      if (lane < H * B) {
-        uint32_t hb = h[0];
+      uint32_t hb = h[0];
 #pragma unroll
-        for (int j = 1; j < H; ++j)
-          if (q == j) hb = h[j];
-        const ulonglong2 sv = g.slots[(uint64_t)hb * B + sl];
-        if (sorted) bk = min(15u, (g.meta[hb] >> 8) & 0xFu);
-        Ent e;
-        e.key = sv.x;
-        e.bin = hb;
-        e.ps = (kRootParent << 3) | (uint32_t)sl;
-        ent[lane] = e;
-        if (sorted) nxt[lane] = (sl + 1 < B) ? (uint32_t)lane + 1 : kNone;
+      for (int j = 1; j < H; ++j)
+        if (q == j) hb = h[j];
+      const uint64_t key = g.slots[(uint64_t)hb * B + sl].x;
+      if (sorted) bk = min(15u, (g.meta[hb] >> 8) & 0xFu);
+      uint32_t hv[H];
+      hash_key<H>(g, T, key, hv);
+      uint32_t o = 0;
+#pragma unroll
+      for (int j = 0; j < H; ++j) {
+        if (hv[j] == hb) continue;
+#pragma unroll
+        for (int t = 0; t < (int)C; ++t)
+          if (t == (int)o) rc[t] = hv[j];
+        ++o;
       }
-      uint32_t bks[H];
-#pragma unroll
-      for (int j = 0; j < H; ++j) bks[j] = __shfl(bk, j * B, 64);
-      __syncthreads();
-      if (sorted && lane == 0) {
-#pragma unroll
-        for (int j = 0; j < H; ++j) {
-          const uint32_t t0 = j * B;
-          if (btail[bks[j]] == kNone) bhead[bks[j]] = t0;
-          else nxt[btail[bks[j]]] = t0;
-          btail[bks[j]] = t0 + B - 1;
-        }
-      }
-      tail = H * B;
-      __syncthreads();
     }
-    uint32_t st = PL_FAIL;
+    if (lane < H) {
+      uint32_t hb = h[0];
+#pragma unroll
+      for (int j = 1; j < H; ++j)
+        if (lane == j) hb = h[j];
+      rbin[lane] = hb;
+      rpar[lane] = kRootParent;
+    }
+    if (lane < 16) { bhead[lane] = kNone; btail[lane] = kNone; }
+    uint32_t bks[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) bks[j] = __shfl(bk, j * B, 64);
+    __syncthreads();
+    if (sorted && lane == 0) {
+#pragma unroll
+      for (int j = 0; j < H; ++j) {
+        rnext[j] = kNone;
+        if (btail[bks[j]] == kNone) bhead[bks[j]] = j * B;
+        else rnext[btail[bks[j]]] = j;
+        btail[bks[j]] = j;
+      }
+    }
+    __syncthreads();
+    uint32_t nruns = H;
+    uint32_t head = 0;  // BFS: next record
+    uint32_t nsp = 0;
+    bool found = false;
+    uint32_t term_e = 0, term_c = 0;
+    uint64_t tkey = kEmpty;  // the terminal bin's view (lanes < B)
+    uint32_t tmeta = 0;
     bool done = false;
     while (!done) {
-      uint32_t e;
+      // ---- the next records in search order, as one group
+      uint32_t my_e = 0, my_j = 0, nu = 0;
       if (!sorted) {
+        const uint32_t tail = nruns * B;
         if (head == tail) break;
-        e = head++;
+        const uint32_t nrec = min(G / C, tail - head);
+        nu = nrec * C;
+        my_e = head + (uint32_t)lane / C;
+        my_j = (uint32_t)lane % C;
       } else {
         int kb = -1;
         for (int q = 0; q < 16; ++q)
           if (bhead[q] != kNone) { kb = q; break; }
         if (kb < 0) break;
-        e = bhead[kb];
-        __syncthreads();
-        if (lane == 0) {
-          const uint32_t nx = nxt[e];
-          bhead[kb] = nx;
-          if (nx == kNone) btail[kb] = kNone;
+        uint32_t e = bhead[kb];
+        while (e != kNone && nu + C <= G) {
+#pragma unroll
+          for (uint32_t j = 0; j < C; ++j)
+            if ((uint32_t)lane == nu + j) { my_e = e; my_j = j; }
+          nu += C;
+          if (((e + 1) & (B - 1)) != 0) {
+            e = e + 1;
+          } else {
+            const uint32_t nr = rnext[e / B];
+            e = nr == kNone ? kNone : nr * B;
+          }
         }
-        __syncthreads();
       }
-      const Ent E = ent[e];
-      uint32_t hv[H];
-      hash_key<H>(g, P.T, E.key, hv);
-      bool spawned = false;
-      for (int q = 0; q < H && !done; ++q) {
-        const uint32_t c = hv[q];
-        if (c == E.bin) continue;
-        if (vis_find_or_insert(c, false)) continue;
-        if (P.views == g.max_search) { done = true; break; }
-        if (!spawned && sorted) {
-          if (lane == 0) spl[nsp] = E.bin;
-          ++nsp;
-        }
-        spawned = true;
-        vis_find_or_insert(c, true);
-        P.load(c, true);
-        if (P.terminal()) {
-          // path: e, parent(e), ..., root record
-          uint32_t depth = 0;
-          uint32_t cur = e;
-          for (;;) {
-            if (lane == 0) path[depth] = cur;
-            ++depth;
-            const uint32_t par = ent[cur].ps >> 3;
-            if (par == kRootParent) break;
-            cur = par;
+      // ---- candidate bins (root records from registers), then contents
+      uint32_t rv = 0;
+#pragma unroll
+      for (int t = 0; t < (int)C; ++t) {
+        const uint32_t v = __shfl(rc[t], (int)min(my_e, 63u), 64);
+        if ((uint32_t)t == my_j) rv = v;
+      }
+      uint32_t cu = 0;
+      if ((uint32_t)lane < nu) cu = my_e < RB ? rv : cand[(size_t)my_e * C + my_j];
+      const uint32_t ul = (uint32_t)lane / B, sl = (uint32_t)lane % B;
+      const uint32_t cb = __shfl(cu, (int)ul, 64);
+      ulonglong2 sv = make_ulonglong2(kEmpty, 0ull);
+      uint32_t mv = 0;
+      if (ul < nu) {
+        sv = g.slots[(uint64_t)cb * B + sl];
+        if (need_meta) mv = g.meta[cb];
+      }
+      // ---- records one by one, in order
+      for (uint32_t u = 0; u < nu && !done; u += C) {
+        const uint32_t e = __shfl(my_e, (int)u, 64);
+        if (sorted) {
+          int kb = -1;
+          for (int q = 0; q < 16; ++q)
+            if (bhead[q] != kNone) { kb = q; break; }
+          if (kb < 0 || bhead[kb] != e) break;  // order changed: regroup
+          __syncthreads();
+          if (lane == 0) {
+            if (((e + 1) & (B - 1)) != 0) {
+              bhead[kb] = e + 1;
+            } else {
+              const uint32_t nr = rnext[e / B];
+              bhead[kb] = nr == kNone ? kNone : nr * B;
+              if (nr == kNone) btail[kb] = kNone;
+            }
           }
           __syncthreads();
-          // contents of the path records, from the snapshot
-          // moves in chain order: x -> root position, ..., e's record -> c
-          // (the terminal write goes through place_terminal on the view of c)
-          for (uint32_t d = depth; d-- > 0;) {
-            const Ent pe = ent[path[d]];
-            uint64_t content_k, content_a;
-            if (d + 1 == depth) {
-              content_k = x;
-              content_a = xa;
-            } else {
-              const Ent ce = ent[path[d + 1]];
-              const ulonglong2 sv = g.slots[(uint64_t)ce.bin * B + (ce.ps & 7)];
-              content_k = sv.x;
-              content_a = sv.y;
-            }
-            P.emit_other(pe.bin, pe.ps & 7, content_k, content_a, 0);
-            ++P.kicks;
-          }
-          const Ent le = ent[path[0]];
-          const ulonglong2 lv = g.slots[(uint64_t)le.bin * B + (le.ps & 7)];
-          P.place_terminal(lv.x, lv.y, 0);
-          st = P.overflow ? PL_FAIL : PL_OK;
-          done = true;
-          break;
+        } else {
+          ++head;
         }
-        const uint32_t bk = sorted ? min(15u, (P.vmeta >> 8) & 0xFu) : 0u;
-        enqueue(c, e, bk);
+        bool spawned = false;
+        for (uint32_t j = 0; j < C; ++j) {
+          const uint32_t uu = u + j;
+          const uint32_t c = __shfl(cu, (int)uu, 64);
+          bool seen = false;
+          for (uint32_t base = 0; base < nruns; base += 64) {
+            const uint32_t q = base + (uint32_t)lane;
+            seen |= __ballot(q < nruns && rbin[q] == c) != 0;
+          }
+          if (seen) continue;
+          if (views == g.max_search) { done = true; break; }
+          if (sorted && !spawned) {
+            if (lane == 0) spl[nsp] = e / B;
+            ++nsp;
+          }
+          spawned = true;
+          ++views;
+          const int src = (int)(uu * B + ((uint32_t)lane & (B - 1)));
+          const uint64_t vk = __shfl(sv.x, src, 64);
+          const uint32_t vm = __shfl(mv, (int)(uu * B), 64);
+          const bool empty = lane < B && vk == kEmpty;
+          const bool dup = g.ghost && lane < B && vk != kEmpty && ((vm >> lane) & 1u);
+          if (__ballot(empty || dup) != 0) {
+            found = true;
+            term_e = e;
+            term_c = c;
+            tkey = vk;
+            tmeta = vm;
+            done = true;
+            break;
+          }
+          // a new run: its records' candidate bins, its bin and parent
+          const uint32_t run = nruns++;
+          if (lane < B) {
+            uint32_t hv[H];
+            hash_key<H>(g, T, vk, hv);
+            uint32_t o = 0;
+#pragma unroll
+            for (int q = 0; q < H; ++q)
+              if (hv[q] != c) cand[((size_t)run * B + lane) * C + o++] = hv[q];
+          }
+          if (lane == 0) {
+            rbin[run] = c;
+            rpar[run] = e;
+          }
+          __syncthreads();
+          if (sorted) {
+            const uint32_t b2 = min(15u, (vm >> 8) & 0xFu);
+            if (lane == 0) {
+              rnext[run] = kNone;
+              if (btail[b2] == kNone) bhead[b2] = run * B;
+              else rnext[btail[b2]] = run;
+              btail[b2] = run;
+            }
+            __syncthreads();
+          }
+        }
       }
     }
-    // spawn counts go to the spawn arena for every plan, winning or not
+    // ---- spawn counts go to the spawn arena for every plan, winning or not
     uint32_t soff = 0;
     if (sorted && nsp > 0) {
-      __shared__ uint32_t s_soff;
-      if (lane == 0)
-        s_soff = region_alloc(win + 2, nsp, r.ctr);
+      if (lane == 0) s_off = region_alloc(win + 2, nsp, r.ctr);
       __syncthreads();
-      soff = s_soff;
+      soff = s_off;
       __syncthreads();
       if (soff != kNone)
-        for (uint32_t j = lane; j < nsp; j += 64) r.spawns[soff + j] = spl[j];
+        for (uint32_t j = lane; j < nsp; j += 64) r.spawns[soff + j] = rbin[spl[j]];
       else
         nsp = 0;
     }
-    P.finish(i, st, nsp, soff, win, &s_views);
+    // ---- the plan
+    uint32_t nm = 0, depth = 0, twin = 0, off = 0;
+    if (found) {
+      // path: term_e, its parent record, ..., a root record
+      uint32_t preg = 0;
+      for (uint32_t cur = term_e;;) {
+        if (lane == (int)depth) preg = cur;
+        if (lane == 0) path[depth] = cur;
+        ++depth;
+        const uint32_t par = rpar[cur / B];
+        if (par == kRootParent) break;
+        cur = par;
+      }
+      const uint32_t emask = (uint32_t)(__ballot(lane < B && tkey == kEmpty) & ((1ull << B) - 1));
+      uint32_t tslot;
+      uint64_t dk = 0;
+      if (emask) {
+        tslot = ffs32(emask);
+      } else {
+        const uint32_t dmask = (uint32_t)(__ballot(lane < B && tkey != kEmpty &&
+                                                   ((tmeta >> lane) & 1u)) & ((1ull << B) - 1));
+        tslot = ffs32(dmask);
+        dk = __shfl(tkey, (int)tslot, 64);
+        twin = 1;
+      }
+      nm = depth + 1 + twin;
+      if (lane == 0) s_off = region_alloc(win, nm, r.ctr);
+      __syncthreads();
+      off = s_off;
+      __syncthreads();
+      // the terminal write's content is the deepest record's snapshot content
+      const ulonglong2 tv = g.slots[(uint64_t)rbin[term_e / B] * B + term_e % B];
+      const uint64_t tk = tv.x, ta = tv.y;
+      uint32_t tb = 0, tws = 0;
+      if (twin) {  // the duplicate's twin, in the duplicate key's other bin
+        uint32_t hd[2];
+        hash_key<2>(g, T, dk, hd);
+        tb = hd[0] == term_c ? hd[1] : hd[0];
+        uint64_t tk2 = kEmpty;
+        if (lane < B) tk2 = g.slots[(uint64_t)tb * B + lane].x;
+        tws = ffs32((uint32_t)(__ballot(lane < B && tk2 == dk) & ((1ull << B) - 1)));
+      }
+      // chain moves: move m puts the content of path[depth - m] (x for m = 0)
+      // into the slot of path[depth - 1 - m]
+      for (uint32_t mb = 0; mb < depth; mb += 64) {
+        const uint32_t m = mb + (uint32_t)lane;
+        const uint32_t d = m < depth ? depth - 1 - m : 0;
+        const uint32_t p_reg = __shfl(preg, (int)min(d, 63u), 64);
+        const uint32_t s_reg = __shfl(preg, (int)min(d + 1, 63u), 64);
+        if (m < depth) {
+          const uint32_t prec = depth <= 64 ? p_reg : path[d];
+          Move mvv;
+          if (m == 0) {
+            mvv.key = x;
+            mvv.aux = xa;
+          } else {
+            const uint32_t srec = depth <= 64 ? s_reg : path[d + 1];
+            const ulonglong2 v = g.slots[(uint64_t)rbin[srec / B] * B + srec % B];
+            mvv.key = v.x;
+            mvv.aux = v.y;
+          }
+          mvv.bin = rbin[prec / B];
+          mvv.slot = (uint8_t)(prec % B);
+          mvv.flags = 0;
+          mvv.pad = 0;
+          if (off != kNone) {
+            r.arena[off + m] = mvv;
+            claim(g, r, mvv.bin, i);
+          }
+        }
+      }
+      if (lane == 0 && off != kNone) {
+        if (twin) {
+          Move t2;
+          t2.key = 0;
+          t2.aux = 0;
+          t2.bin = tb;
+          t2.slot = (uint8_t)tws;
+          t2.flags = MV_DUPCLR;
+          t2.pad = 0;
+          r.arena[off + depth] = t2;
+          claim(g, r, tb, i);
+        }
+        Move t1;
+        t1.key = tk;
+        t1.aux = ta;
+        t1.bin = term_c;
+        t1.slot = (uint8_t)tslot;
+        t1.flags = 0;
+        t1.pad = 0;
+        r.arena[off + depth + twin] = t1;
+        claim(g, r, term_c, i);
+      }
+    }
+    if (lane == 0) {
+      PlanHdr hd{};
+      hd.st = hdr_pack(found ? PL_OK : PL_FAIL, twin, nm);
+      hd.views = views;
+      hd.kicks = found ? depth : 0;
+      hd.off = off;
+      hd.n_spawn = nsp;
+      hd.spawn_off = soff;
+      r.hdr[i] = hd;
+      s_views += views;
+    }
+    __syncthreads();
   }
   if (threadIdx.x == 0 && s_views) r.wg_views[blockIdx.x] += s_views;
 }
 
 size_t evict_lds_bytes(const Geo& g) {
   if (g.scheme == CK_BFS || g.scheme == CK_SORTED) {
-    const size_t ms8 = g.max_search + 8;
-    size_t VC = 1;
-    while (VC < 2 * ms8) VC <<= 1;
-    return (16 + VC + 32) * 4 + 64;
+    return (3 * search_runs(g) + 32) * 4 + 64;
   }
   const size_t cap = g.max_chain + 8;
   return cap * 24 + 8 * 4 + 8 * 4 + 64;
@@ -994,9 +1135,8 @@ size_t evict_lds_bytes(const Geo& g) {
 
 size_t evict_wg_scratch_bytes(const Geo& g) {
   if (g.scheme == CK_BFS || g.scheme == CK_SORTED) {
-    const size_t ms8 = g.max_search + 8;
-    const size_t ecap = ms8 * g.B;
-    size_t b = ecap * (sizeof(Ent) + 4) + 2 * ms8 * 4 + 8 + ms8 * 24;
+    const size_t RC = search_runs(g);
+    size_t b = RC * g.B * (g.H - 1) * 4 + 2 * RC * 4;
     return (b + 255) & ~(size_t)255;
   }
   return 256;
