@@ -810,29 +810,70 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
   __syncthreads();
   const uint32_t total = r.ctr->evict_count;  // final: written by the compaction
 
-  for (uint32_t k = blockIdx.x; k < total; k += gridDim.x) {
-    const uint32_t i = r.evict[k];
-    const uint64_t x = r.keys[i];
-    const uint64_t xa = load_aux(r.vals, i, B);
-    const Tab T = tab_of(g, r.op_table, r.tdesc, i);
+  // Ops are software-pipelined: while op k is planned, the key of the next
+  // op and the index of the one after are in flight, and the next op's root
+  // bins are fetched as soon as op k's search ends.
+  const uint32_t step = gridDim.x;
+  uint32_t k = blockIdx.x;
+  uint32_t i_nx = 0, i_nx2 = 0;  // next op, op after next
+  uint64_t x_nx = 0, xa_nx = 0;
+  Tab T_nx{0u, 0u};
+  uint32_t h_nx[H];
+  uint64_t rk_nx = kEmpty;  // next op's root slot (lanes < H*B)
+  uint32_t rm_nx = 0;       // its bin's metadata word (sorted)
+  auto fetch_roots = [&]() {
+    T_nx = tab_of(g, r.op_table, r.tdesc, i_nx);
+    hash_key<H>(g, T_nx, x_nx, h_nx);
+    if (lane < (int)RB) {
+      const int q = lane / B, sl = lane % B;
+      uint32_t hb = h_nx[0];
+#pragma unroll
+      for (int j = 1; j < H; ++j)
+        if (q == j) hb = h_nx[j];
+      rk_nx = g.slots[(uint64_t)hb * B + sl].x;
+      if (sorted) rm_nx = g.meta[hb];
+    }
+  };
+  if (k < total) {
+    i_nx = r.evict[k];
+    if (k + step < total) i_nx2 = r.evict[k + step];
+    x_nx = r.keys[i_nx];
+    xa_nx = load_aux(r.vals, i_nx, B);
+    fetch_roots();
+  }
+  for (; k < total; k += step) {
+    const uint32_t i = i_nx;
+    const uint64_t x = x_nx;
+    const uint64_t xa = xa_nx;
+    const Tab T = T_nx;
     uint32_t h[H];
-    hash_key<H>(g, T, x, h);
+#pragma unroll
+    for (int j = 0; j < H; ++j) h[j] = h_nx[j];
+    const uint64_t rkey = rk_nx;
+    const uint32_t rmeta = rm_nx;
+    const bool more = k + step < total;
+    if (more) {
+      i_nx = i_nx2;
+      x_nx = r.keys[i_nx];
+      xa_nx = load_aux(r.vals, i_nx, B);
+      if (k + 2 * step < total) i_nx2 = r.evict[k + 2 * step];
+    }
     // ops reach this planner after the fresh planner found no room in the
     // same snapshot: first fit viewed all H bins, ghost inserts both bins
     uint32_t views = g.ghost ? 2u : (uint32_t)H;
-    // ---- root runs: the key's own bins, loaded at once by H*B lanes
+    // ---- root runs: the key's own bins (slots already fetched, H*B lanes)
     uint32_t rc[C];
 #pragma unroll
     for (int j = 0; j < (int)C; ++j) rc[j] = 0;
     uint32_t bk = 0;
     if (lane < (int)RB) {
-      const int q = lane / B, sl = lane % B;
+      const int q = lane / B;
       uint32_t hb = h[0];
 #pragma unroll
       for (int j = 1; j < H; ++j)
         if (q == j) hb = h[j];
-      const uint64_t key = g.slots[(uint64_t)hb * B + sl].x;
-      if (sorted) bk = min(15u, (g.meta[hb] >> 8) & 0xFu);
+      const uint64_t key = rkey;
+      if (sorted) bk = min(15u, (rmeta >> 8) & 0xFu);
       uint32_t hv[H];
       hash_key<H>(g, T, key, hv);
       uint32_t o = 0;
@@ -1003,6 +1044,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
         }
       }
     }
+    if (more) fetch_roots();
     // ---- spawn counts go to the spawn arena for every plan, winning or not
     uint32_t soff = 0;
     if (sorted && nsp > 0) {
