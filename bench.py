@@ -49,11 +49,15 @@ def parse():
                    help="lookup lanes per probe (1 or slots per bin; 0 = slots per bin)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-bins-log2", type=int, default=19)
-    p.add_argument("--workload", default="fill", choices=["fill", "group", "serve"],
+    p.add_argument("--workload", default="fill", choices=["fill", "group", "serve", "mixed", "dary"],
                    help="fill: one 2^24 x 8 table (default); group: 4096 tables of "
                         "2^10..2^20 bins x 4 slots, batched vs per-request launches; "
                         "serve: the same tables behind the continuous-batching server, "
-                        "Poisson arrivals")
+                        "Poisson arrivals; mixed: steady-state lookups/inserts/deletes "
+                        "with ghosts on a 2^25 x 4 table at 97%; dary: single-slot bins, "
+                        "d = 3 and 4, rattle vs random walk")
+    p.add_argument("--mixed-steps", type=int, default=1024, help="mixed: steps of 2^18 ops")
+    p.add_argument("--dary-schemes", default="rattle,random_walk", help="dary: schemes")
     p.add_argument("--rate", type=float, default=200_000.0, help="serve: requests per second")
     p.add_argument("--max-batch-ops", type=int, default=1 << 22, help="serve: ops per batch cap")
     p.add_argument("--tables", type=int, default=4096)
@@ -278,6 +282,167 @@ def run_serve(args):
         sys.exit("served answers differ from the request stream's expectations")
 
 
+def run_mixed(args):
+    """Steady state with ghost insertions and claims: a 2^25 x 4 table prefilled
+    to 97% with queue-kicking, then steps of 2^18 ops (90% lookups drawn
+    Zipf(0.99) over the stored keys, 5% inserts of fresh keys, 5% deletes of
+    random stored keys; per step: lookups, deletes, inserts).  The op stream is
+    generated before timing, assuming every insert succeeds (a failed insert
+    only turns later lookups or deletes of its key into misses)."""
+    import torch
+    from paper_1605_05236_amd import inputs
+    from paper_1605_05236_amd.table import CuckooTable
+    torch.cuda.set_device(0)
+    n, B, seed = 1 << 25, 4, 4
+    step_ops = 1 << 18
+    steps = args.mixed_steps
+    n_look, n_ins = int(step_ops * 0.9), int(step_ops * 0.05)
+    n_del = step_ops - n_look - n_ins
+    t = CuckooTable(n, B, 2, "queue", ghost=True, batch_ops=step_ops, hash_seed=104,
+                    rng_seed=204)
+    m = inputs.target_count(n, B, 0.97)
+    t0 = time.time()
+    rec = torch.arange(m, dtype=torch.int64, device="cuda")
+    k, v = inputs.keys_at_torch(seed, rec)
+    st = t.insert(k, v, diagnostics=False)["status"]
+    stored = torch.empty(m + steps * n_ins, dtype=torch.int64, device="cuda")
+    ok = rec[st == 1]
+    size = ok.numel()
+    stored[:size] = ok
+    del k, v, st, rec, ok
+    # the op stream: record ids per step
+    zipf = inputs.ZipfTorch(size, 0.99)
+    gen = torch.Generator(device="cuda").manual_seed(504)
+    look = torch.empty(steps, n_look, dtype=torch.int64, device="cuda")
+    dels = torch.empty(steps, n_del, dtype=torch.int64, device="cuda")
+    ins = torch.empty(steps, n_ins, dtype=torch.int64, device="cuda")
+    fresh = m
+    for s in range(steps):
+        look[s] = stored[zipf.sample(gen, n_look).clamp_(max=size - 1)]
+        # n_del distinct uniform positions (unique() sorts, so shuffle before cutting)
+        pos = torch.unique(torch.randint(0, size, (n_del + n_del // 4,), generator=gen,
+                                         device="cuda"))
+        pos = pos[torch.randperm(pos.numel(), generator=gen, device="cuda")][:n_del]
+        d = pos.numel()
+        if d < n_del:
+            raise RuntimeError("too few distinct delete positions")
+        dels[s] = stored[pos]
+        # swap-remove: holes below the new size take the tail's survivors
+        new_size = size - d
+        tail = torch.arange(new_size, size, device="cuda")
+        is_del = torch.zeros(size - new_size, dtype=torch.bool, device="cuda")
+        in_tail = pos >= new_size
+        is_del[pos[in_tail] - new_size] = True
+        movers = tail[~is_del]
+        holes = pos[~in_tail]
+        stored[holes] = stored[movers]
+        size = new_size
+        ins[s] = torch.arange(fresh, fresh + n_ins, device="cuda")
+        stored[size:size + n_ins] = ins[s]
+        size += n_ins
+        fresh += n_ins
+    lk, _ = inputs.keys_at_torch(seed, look)
+    dk, _ = inputs.keys_at_torch(seed, dels)
+    ik, iv = inputs.keys_at_torch(seed, ins)
+    del look, dels, ins, stored
+    torch.cuda.synchronize()
+    print(f"# prefilled {m} keys; {steps} steps of {step_ops} ops ready in "
+          f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    before = t.stats()
+    vout = torch.empty(n_look, dtype=torch.int64, device="cuda")
+    fout = torch.empty(n_look, dtype=torch.uint8, device="cuda")
+    hits = torch.zeros((), dtype=torch.int64, device="cuda")
+    dfound = torch.zeros((), dtype=torch.int64, device="cuda")
+    iok = torch.zeros((), dtype=torch.int64, device="cuda")
+
+    def run():
+        for s in range(steps):
+            t.lookup(lk[s], out=vout, found=fout)
+            hits.add_(fout.sum())
+            dfound.add_((t.delete(dk[s]) == 1).sum())
+            iok.add_((t.insert(ik[s], iv[s], diagnostics=False)["status"] == 1).sum())
+
+    sec = _timed(run)
+    after = t.stats()
+    ops = steps * step_ops
+    diff = {f: after[f] - before[f] for f in ("inserts_ok", "inserts_failed", "inserts_aborted",
+                                              "retries", "delete_retries", "twin_updates",
+                                              "kicks", "rounds")}
+    out = {
+        "metric": "steady-state ops/s (lookup/insert/delete mix) with abort and retry counts",
+        "value": ops / sec, "unit": "ops/s", "n_gpus": 1, "steps": steps, "warmup": 0,
+        "ms_per_step": sec * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic (splitmix64 keys, seeded)",
+        "config": {"workload": f"2^25 bins x 4 slots prefilled to 0.97 ({m} keys), queue-kicking "
+                               f"with ghost insertions; {steps} steps of 2^18 ops (90% Zipf(0.99) "
+                               "lookups of stored keys, 5% fresh inserts, 5% deletes of stored "
+                               "keys)", "ops": ops},
+        "lookup_hit_rate": float(hits) / (steps * n_look),
+        "deletes_found": int(dfound), "deletes": steps * n_del,
+        "inserts_ok": int(iok), "inserts": steps * n_ins,
+        "counts": diff,
+        "aborts_per_insert": diff["inserts_aborted"] / (steps * n_ins),
+        "lost_rounds_per_insert": diff["retries"] / (steps * n_ins),
+        "delete_retries_per_delete": diff["delete_retries"] / (steps * n_del),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_dary(args):
+    """Single-slot bins with d = 3 and d = 4 hash functions, 2^26 slots of
+    uint64 key + uint32 value, chains capped at 1000, sub-batches of 2^20:
+    rattle-kicking against random-walk kicking, filled to 0.90 then 0.95
+    (d = 3) and to 0.97 (d = 4)."""
+    import torch
+    from paper_1605_05236_amd import inputs
+    from paper_1605_05236_amd.table import CuckooTable
+    torch.cuda.set_device(0)
+    n = 1 << 26
+    cases = [(3, (0.90, 0.95)), (4, (0.97,))]
+    schemes = [s for s in args.dary_schemes.split(",") if s]
+    res = {}
+    total_ins, total_s = 0, 0.0
+    for d, loads in cases:
+        mt = inputs.target_count(n, 1, loads[-1])
+        keys, vals = inputs.keys_values_torch(3, mt, value_bits=32)
+        vals = vals.to(torch.int32)
+        for scheme in schemes:
+            t = CuckooTable(n, 1, d, scheme, max_chain=1000, batch_ops=1 << 20, hash_seed=103,
+                            rng_seed=203)
+            done, out = 0, {}
+            for load in loads:
+                m = inputs.target_count(n, 1, load)
+                sec = _timed(lambda: t.insert(keys[done:m], vals[done:m], diagnostics=False))
+                st = t.stats()
+                bands = st["band_inserts"].astype(np.float64)
+                bv = st["band_views"].astype(np.float64)
+                top = int(np.floor(load * 200 - 1e-9))  # the band just below `load`
+                out[f"{load:.2f}"] = {
+                    "inserts_per_s": (m - done) / sec, "seconds": sec,
+                    "bins_viewed_per_insert_in_last_band": float(bv[top] / max(bands[top], 1)),
+                    "bins_viewed_per_insert_cumulative": float(st["views"] / max(st["inserts_ok"]
+                                                                              + st["inserts_failed"], 1)),
+                    "failed_inserts": st["inserts_failed"], "stored": st["stored"],
+                    "rounds": st["rounds"], "lost_rounds": st["retries"]}
+                total_ins += m - done
+                total_s += sec
+                done = m
+                print(f"# d={d} {scheme} to {load}: {out[f'{load:.2f}']}", file=sys.stderr,
+                      flush=True)
+            res[f"d{d}_{scheme}"] = out
+            t.close()
+        del keys, vals
+    print(json.dumps({
+        "metric": "d-ary inserts/s and bins viewed per insert: rattle vs random walk",
+        "value": total_ins / total_s, "unit": "inserts/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": total_s * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic (splitmix64 keys, seeded)",
+        "config": {"workload": "2^26 single-slot bins (uint64 key + uint32 value), d = 3 to "
+                               "0.90/0.95 and d = 4 to 0.97, max chain 1000, sub-batches of 2^20",
+                   "schemes": schemes},
+        "by_case": res}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -289,6 +454,12 @@ def main():
         return
     if args.workload == "serve":
         run_serve(args)
+        return
+    if args.workload == "mixed":
+        run_mixed(args)
+        return
+    if args.workload == "dary":
+        run_dary(args)
         return
     import torch
     from paper_1605_05236_amd import inputs

@@ -82,6 +82,7 @@ struct ck_table {
   PlanHdr* hdr = nullptr;
   IMove* imv = nullptr;
   uint32_t* evict = nullptr;
+  uint32_t* evict_cnt = nullptr;
   Move* arena = nullptr;
   uint32_t arena_cap = 0;
   uint32_t* spawns = nullptr;
@@ -151,6 +152,7 @@ void free_scratch(ck_table* t) {
   (void)hipFree(t->hdr);
   (void)hipFree(t->imv);
   (void)hipFree(t->evict);
+  (void)hipFree(t->evict_cnt);
   (void)hipFree(t->arena);
   (void)hipFree(t->spawns);
   for (auto& p : t->op) (void)hipFree(p);
@@ -184,7 +186,8 @@ ck_status alloc_scratch(ck_table* t) {
   HIP_TRY(dalloc(&t->pend[1], m));
   HIP_TRY(dalloc(&t->hdr, m));
   HIP_TRY(dalloc(&t->imv, (size_t)m * kExtraInline));
-  HIP_TRY(dalloc(&t->evict, m));
+  HIP_TRY(dalloc(&t->evict, (size_t)m + 256));
+  HIP_TRY(dalloc(&t->evict_cnt, ((size_t)m * t->B + 255) / 256 + 1));
   for (auto& p : t->op) HIP_TRY(dalloc(&p, m));
   // eviction plans sub-allocate from per-workgroup windows of 256 entries
   const uint64_t slack = (uint64_t)t->evict_grid * 512;
@@ -232,6 +235,7 @@ Round make_round(ck_table* t, const uint64_t* keys, const void* vals, uint8_t* s
   r.hdr = t->hdr;
   r.imv = t->imv;
   r.evict = t->evict;
+  r.evict_cnt = t->evict_cnt;
   r.arena = t->arena;
   r.arena_cap = t->arena_cap;
   r.spawns = t->spawns;
@@ -298,12 +302,12 @@ ck_status run_rounds(ck_table* t, Round& r, uint64_t m, hipStream_t s) {
         HIP_TRY(launch_plan_delete(t->g, r, s));
         T.end(TK_DELETE, ev, s);
       } else {
+        // the fresh planner's blocks leave the evict list in per-block regions
+        r.fresh_blocks = (uint32_t)(((uint64_t)npend * t->B + 255) / 256);
+        r.fresh_opb = 256 / t->B;
         ev = T.begin(s, TK_FRESH);
         HIP_TRY(launch_plan_fresh(t->g, r, s));
         T.end(TK_FRESH, ev, s);
-        ev = T.begin(s, TK_COMPACT);
-        HIP_TRY(launch_compact(r, t->evict, &t->ctr->evict_count, t->comp_tmp, s));
-        T.end(TK_COMPACT, ev, s);
         ev = T.begin(s, TK_EVICT);
         HIP_TRY(launch_plan_evict(t->g, r, t->evict_grid, s));
         T.end(TK_EVICT, ev, s);

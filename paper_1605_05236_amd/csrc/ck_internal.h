@@ -115,7 +115,11 @@ struct Round {
   uint32_t* next_count;      // where this round's compaction writes next round's count
   uint32_t* next;            // losers for the next round
   uint8_t* req;              // per pending position: 1 = pending again next round
-  uint32_t* evict;           // ops that need an eviction plan
+  uint32_t* evict;           // ops that need an eviction plan: fresh-planner block b
+                             // puts its evict_cnt[b] ops at evict[b * fresh_opb ...)
+  uint32_t* evict_cnt;       // per fresh-planner block
+  uint32_t fresh_blocks;     // fresh-planner blocks of this round (its grid)
+  uint32_t fresh_opb;        // ops per fresh-planner block (256 / B)
   PlanHdr* hdr;
   IMove* imv;                // kExtraInline per op
   Move* arena;

@@ -336,9 +336,9 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
   G.sl = G.lane % B;
   G.gshift = G.lane - G.sl;
   const uint64_t gidx = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / B;
-  if (gidx >= npend_of(r)) return;
-  const uint32_t i = r.pend[gidx];
-  const uint64_t x = r.keys[i];
+  const bool active = gidx < npend_of(r);
+  const uint32_t i = active ? r.pend[gidx] : 0u;
+  const uint64_t x = active ? r.keys[i] : kEmpty;
   const bool leader = G.sl == 0;
   const bool bad = x == kEmpty;  // reserved key: rejected, no plan
   const uint32_t hc_flag = (g.scheme == CK_QUEUE) ? MV_HC : 0;
@@ -348,8 +348,8 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
   uint32_t nm = 0, views = 0, twins = 0;
   bool placed = false;
   // rattle-kicking has no separate fresh phase: every op goes to the walk
-  const Tab T = tab_of(g, r.op_table, r.tdesc, i);
-  if (!bad && g.scheme != CK_RATTLE) {
+  const Tab T = active ? tab_of(g, r.op_table, r.tdesc, i) : Tab{0u, g.n};
+  if (active && !bad && g.scheme != CK_RATTLE) {
     uint32_t h[H];
     hash_key<H>(g, T, x, h);
     if (g.ghost) {
@@ -414,10 +414,22 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
       }
     }
   }
-  if (!leader) return;
-  // ops that need a kick-out are flagged by pending position; the evict list
-  // is compacted from the flags in op order (no shared counter)
-  r.req[gidx] = (!bad && !placed) ? 1 : 0;
+  // ops that need a kick-out go to this block's region of the evict list, in
+  // op order, with the block's count beside it (no shared counter)
+  {
+    __shared__ uint32_t s_wcnt[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const bool ev = active && leader && !bad && !placed;
+    const uint64_t bal = __ballot(ev);
+    if (lane == 0) s_wcnt[wv] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int w = 0; w < wv; ++w) pre += s_wcnt[w];
+    if (ev)
+      r.evict[(size_t)blockIdx.x * r.fresh_opb + pre + __popcll(bal & ((1ull << lane) - 1))] = i;
+    if (threadIdx.x == 0) r.evict_cnt[blockIdx.x] = s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
+  }
+  if (!active || !leader) return;
   PlanHdr hd{};
   hd.st = hdr_pack(bad ? PL_FAIL : (placed ? PL_OK : PL_EVICT), twins, nm);
   hd.views = views;
@@ -431,6 +443,61 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
     claim(g, r, b1, i);
   }
 }
+
+// ---------------------------------------------------------------------------
+// The ops of one round that need an eviction plan: fresh-planner block b put
+// its evict_cnt[b] ops at evict[b * fresh_opb + j], j < evict_cnt[b].
+// Positions are numbered slot-major, q = j * nb + b (nb blocks), so each
+// stretch of q holds one slot index of every block.  Eviction-planner
+// workgroup w takes q = w, w + gridDim.x, w + 2 gridDim.x, ...: an even
+// sample of every slot layer, hence an equal share of the occupied
+// positions; its item k is its k-th occupied position.  The wavefront checks
+// 64 positions per step (one per lane) and ballots the occupied ones.
+// ---------------------------------------------------------------------------
+struct EvictWork {
+  const uint32_t* list = nullptr;
+  const uint32_t* cnt = nullptr;
+  uint64_t npos = 0;   // fresh_blocks * fresh_opb
+  uint32_t opb = 1, nb = 1;
+  uint32_t c0 = 0;     // window: positions w + (64 c0 + lane) gridDim.x
+  uint64_t vmask = 0;  // occupied positions of the window
+  uint32_t base = 0;   // items before the window
+  uint32_t wtot = 0;   // items in the window
+
+  __device__ void window(uint32_t c) {
+    c0 = c;
+    const int lane = threadIdx.x & 63;
+    const uint64_t q = (uint64_t)blockIdx.x + ((uint64_t)c0 * 64 + lane) * gridDim.x;
+    bool v = false;
+    if (q < npos) v = (uint32_t)(q / nb) < cnt[q % nb];
+    vmask = (uint64_t)__ballot(v);
+    wtot = (uint32_t)__popcll(vmask);
+  }
+  __device__ void init(const Round& r) {
+    list = r.evict;
+    cnt = r.evict_cnt;
+    opb = r.fresh_opb;
+    nb = r.fresh_blocks;
+    npos = (uint64_t)nb * opb;
+    base = 0;
+    window(0);
+  }
+  // op index of item k, or kNone past the end; k must not decrease
+  __device__ uint32_t item(uint32_t k) {
+    while (k >= base + wtot) {
+      if ((uint64_t)blockIdx.x + (uint64_t)(c0 + 1) * 64 * gridDim.x >= npos) return kNone;
+      base += wtot;
+      window(c0 + 1);
+    }
+    const int lane = threadIdx.x & 63;
+    const uint32_t rel = k - base;
+    const uint32_t below = (uint32_t)__popcll(vmask & ((1ull << lane) - 1));
+    const bool hit = ((vmask >> lane) & 1ull) && below == rel;
+    const uint32_t t = (uint32_t)(__ffsll((unsigned long long)__ballot(hit)) - 1);
+    const uint64_t q = (uint64_t)blockIdx.x + ((uint64_t)c0 * 64 + t) * gridDim.x;
+    return list[(q % nb) * opb + q / nb];
+  }
+};
 
 // ---------------------------------------------------------------------------
 // wavefront planners (k_plan_walk, k_plan_search) share this context.
@@ -731,10 +798,12 @@ __global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
     s_views = 0;
   }
   __syncthreads();
-  const uint32_t total = r.ctr->evict_count;  // final: written by the compaction
+  EvictWork W;
+  W.init(r);
   {
-    for (uint32_t k = blockIdx.x; k < total; k += gridDim.x) {
-      const uint32_t i = r.evict[k];
+    for (uint32_t k = 0;; ++k) {
+      const uint32_t i = W.item(k);
+      if (i == kNone) break;
       const uint64_t x = r.keys[i];
       const uint64_t xa = load_aux(r.vals, i, B);
       WavePlanner<B, H> P(g, r, L, cap);
@@ -808,14 +877,14 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
     s_views = 0;
   }
   __syncthreads();
-  const uint32_t total = r.ctr->evict_count;  // final: written by the compaction
+  EvictWork W;
+  W.init(r);
 
   // Ops are software-pipelined: while op k is planned, the key of the next
   // op and the index of the one after are in flight, and the next op's root
   // bins are fetched as soon as op k's search ends.
-  const uint32_t step = gridDim.x;
-  uint32_t k = blockIdx.x;
-  uint32_t i_nx = 0, i_nx2 = 0;  // next op, op after next
+  uint32_t i_nx = W.item(0);                            // next op
+  uint32_t i_nx2 = i_nx != kNone ? W.item(1) : kNone;   // op after next
   uint64_t x_nx = 0, xa_nx = 0;
   Tab T_nx{0u, 0u};
   uint32_t h_nx[H];
@@ -834,14 +903,12 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
       if (sorted) rm_nx = g.meta[hb];
     }
   };
-  if (k < total) {
-    i_nx = r.evict[k];
-    if (k + step < total) i_nx2 = r.evict[k + step];
+  if (i_nx != kNone) {
     x_nx = r.keys[i_nx];
     xa_nx = load_aux(r.vals, i_nx, B);
     fetch_roots();
   }
-  for (; k < total; k += step) {
+  for (uint32_t k = 0; i_nx != kNone; ++k) {
     const uint32_t i = i_nx;
     const uint64_t x = x_nx;
     const uint64_t xa = xa_nx;
@@ -851,12 +918,12 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
     for (int j = 0; j < H; ++j) h[j] = h_nx[j];
     const uint64_t rkey = rk_nx;
     const uint32_t rmeta = rm_nx;
-    const bool more = k + step < total;
+    const bool more = i_nx2 != kNone;
+    i_nx = i_nx2;
     if (more) {
-      i_nx = i_nx2;
       x_nx = r.keys[i_nx];
       xa_nx = load_aux(r.vals, i_nx, B);
-      if (k + 2 * step < total) i_nx2 = r.evict[k + 2 * step];
+      i_nx2 = W.item(k + 2);
     }
     // ops reach this planner after the fresh planner found no room in the
     // same snapshot: first fit viewed all H bins, ghost inserts both bins
