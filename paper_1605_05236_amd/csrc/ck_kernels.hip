@@ -832,43 +832,94 @@ __global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
 // sorted search keeps 16 FIFO buckets of runs by spawn count and expands the
 // head record of the lowest non-empty bucket.
 //
-// The frontier is expanded 64 / B bins at a time: the next records in search
-// order are taken as a group, their candidate bins are fetched by one
-// wave-wide load (B lanes per bin), and the records are then processed one by
-// one in order, exactly as the serial search does.  Searches read the
-// round-start snapshot only, so fetching ahead changes no result; a group is
-// abandoned at a record boundary when a new run has gone to a lower bucket,
-// since the next record in order is then another one.
+// A wavefront runs 64 / W searches side by side, W lanes each (a group).  A
+// search expands its frontier W / B bins at a time: the next records in
+// search order are taken together, their candidate bins are fetched by one
+// group-wide load (B lanes per bin), and the records are then processed one
+// by one in order, exactly as the serial search does.  Searches read the
+// round-start snapshot only, so fetching ahead changes no result; a group of
+// records is abandoned at a record boundary when a new run has gone to a
+// lower bucket, since the next record in order is then another one.  The
+// first kSearchLdsRuns runs of a search live in LDS, the rest (long
+// searches only) in workgroup scratch.
 //
 // The plan (chain moves root first, then the terminal write, preceded by the
 // twin's mark clear when a ghost duplicate is replaced) goes straight to the
 // workgroup's arena region, one move per lane.
 constexpr uint32_t kRootParent = 0xFFFFFFFFu;
+constexpr uint32_t kSearchLdsRuns = 128;
+constexpr int kSearchW = 16;  // lanes per search
 
 size_t search_runs(const Geo& g) { return (size_t)g.max_search + 8 + g.H; }
+static size_t search_group_lds_words() { return 3 * kSearchLdsRuns + 32; }
+static size_t search_group_scratch_bytes(const Geo& g) {
+  const size_t RC = search_runs(g);
+  return ((RC * g.B * (g.H - 1) + 5 * RC) * 4 + 255) & ~(size_t)255;
+}
+
+// Orders LDS and memory accesses of the lanes of one wavefront (the search
+// workgroups are single wavefronts, so this is a full workgroup barrier);
+// valid in divergent code.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Arena regions shared by the workgroup's searches.
+__device__ __forceinline__ uint32_t region_take(uint32_t* win, uint32_t n, Ctr* ctr) {
+  if (n == 0) return 0;
+  const uint32_t off = atomicAdd(&win[0], n);
+  if (off + n > win[1]) {
+    atomicOr(&ctr->overflow, 1u);
+    return kNone;
+  }
+  return off;
+}
 
 template <int B, int H>
 __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
-  // LDS: run bins, run parents, bucket lists.  Workgroup scratch (global):
-  // candidate bins of non-root records, spawn list, deep paths.
+  constexpr int W = kSearchW;
+  constexpr int P = 64 / W;       // searches per wavefront
+  constexpr uint32_t C = H - 1;   // candidates per record
+  constexpr uint32_t G = W / B;   // bins per group-wide load
+  constexpr uint32_t RB = H * B;  // root records
+  constexpr uint32_t RL = kSearchLdsRuns;
+  static_assert(RB <= (uint32_t)W && G >= C, "search group too narrow");
   extern __shared__ uint32_t lds32[];
   __shared__ uint32_t win[4];  // arena region, spawn region
-  __shared__ uint32_t s_off;
   __shared__ unsigned long long s_views;  // bins viewed by this workgroup's plans
-  constexpr uint32_t C = H - 1;   // candidates per record
-  constexpr uint32_t G = 64 / B;  // bins per wave-wide load
-  constexpr uint32_t RB = H * B;  // root records
+  const int lane = threadIdx.x;
+  const int gl = lane % W;            // lane within the group
+  const int gb = lane - gl;           // the group's first lane
+  const int gi = lane / W;            // group index
+  const uint64_t gmask = W == 64 ? ~0ull : ((1ull << W) - 1);
+  auto gballot = [&](bool p) -> uint64_t { return (__ballot(p) >> gb) & gmask; };
   const uint32_t RC = g.max_search + 8 + H;
-  uint32_t* rbin = lds32;         // run -> bin
-  uint32_t* rpar = rbin + RC;     // run -> parent record (kRootParent for roots)
-  uint32_t* rnext = rpar + RC;    // run -> next run of its bucket (sorted)
-  uint32_t* bhead = rnext + RC;   // record at the head of each bucket
+  uint32_t* rbinL = lds32 + (size_t)gi * (3 * RL + 32);
+  uint32_t* rparL = rbinL + RL;
+  uint32_t* rnextL = rparL + RL;
+  uint32_t* bhead = rnextL + RL;  // record at the head of each bucket
   uint32_t* btail = bhead + 16;   // last run of each bucket
-  char* scratch = (char*)r.wg_scratch + (size_t)blockIdx.x * r.wg_scratch_bytes;
+  char* scratch = (char*)r.wg_scratch + (size_t)blockIdx.x * r.wg_scratch_bytes +
+                  (size_t)gi * (r.wg_scratch_bytes / P);
   uint32_t* cand = (uint32_t*)scratch;         // RC * B * C
   uint32_t* spl = cand + (size_t)RC * B * C;   // RC: runs that spawned (sorted)
   uint32_t* path = spl + RC;                   // RC: records, deepest first
-  const int lane = threadIdx.x;
+  uint32_t* rbinG = path + RC;                 // runs >= RL
+  uint32_t* rparG = rbinG + RC;
+  uint32_t* rnextG = rparG + RC;
+  auto rbin_at = [&](uint32_t j) -> uint32_t { return j < RL ? rbinL[j] : rbinG[j]; };
+  auto rpar_at = [&](uint32_t j) -> uint32_t { return j < RL ? rparL[j] : rparG[j]; };
+  auto rnext_at = [&](uint32_t j) -> uint32_t { return j < RL ? rnextL[j] : rnextG[j]; };
+  auto set_run = [&](uint32_t j, uint32_t bin, uint32_t par) {  // group leader
+    if (j < RL) { rbinL[j] = bin; rparL[j] = par; }
+    else { rbinG[j] = bin; rparG[j] = par; }
+  };
+  auto set_next = [&](uint32_t j, uint32_t nx) {  // group leader
+    if (j < RL) rnextL[j] = nx;
+    else rnextG[j] = nx;
+  };
   const bool sorted = g.scheme == CK_SORTED;
   const bool need_meta = sorted || g.ghost;
   if (lane == 0) {
@@ -876,25 +927,37 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
     region_init(win + 2, r.spawn_cap);
     s_views = 0;
   }
-  __syncthreads();
-  EvictWork W;
-  W.init(r);
+  wave_sync();
+  EvictWork Wk;
+  Wk.init(r);
+  // the group's op of batch kb is item kb + gi; item() is wave-uniform
+  auto batch_item = [&](uint32_t kb) -> uint32_t {
+    uint32_t mine = kNone;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const uint32_t v = Wk.item(kb + (uint32_t)p);
+      if (gi == p) mine = v;
+    }
+    return mine;
+  };
 
-  // Ops are software-pipelined: while op k is planned, the key of the next
-  // op and the index of the one after are in flight, and the next op's root
-  // bins are fetched as soon as op k's search ends.
-  uint32_t i_nx = W.item(0);                            // next op
-  uint32_t i_nx2 = i_nx != kNone ? W.item(1) : kNone;   // op after next
+  // Ops are software-pipelined: while batch kb is planned, the next batch's
+  // ops and keys are in flight, and their root bins are fetched as soon as
+  // the current searches end.
+  uint32_t i_nx = batch_item(0);
   uint64_t x_nx = 0, xa_nx = 0;
   Tab T_nx{0u, 0u};
   uint32_t h_nx[H];
-  uint64_t rk_nx = kEmpty;  // next op's root slot (lanes < H*B)
+#pragma unroll
+  for (int j = 0; j < H; ++j) h_nx[j] = 0;
+  uint64_t rk_nx = kEmpty;  // next op's root slot (group lanes < H*B)
   uint32_t rm_nx = 0;       // its bin's metadata word (sorted)
   auto fetch_roots = [&]() {
+    if (i_nx == kNone) return;
     T_nx = tab_of(g, r.op_table, r.tdesc, i_nx);
     hash_key<H>(g, T_nx, x_nx, h_nx);
-    if (lane < (int)RB) {
-      const int q = lane / B, sl = lane % B;
+    if (gl < (int)RB) {
+      const int q = gl / B, sl = gl % B;
       uint32_t hb = h_nx[0];
 #pragma unroll
       for (int j = 1; j < H; ++j)
@@ -906,10 +969,12 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
   if (i_nx != kNone) {
     x_nx = r.keys[i_nx];
     xa_nx = load_aux(r.vals, i_nx, B);
-    fetch_roots();
   }
-  for (uint32_t k = 0; i_nx != kNone; ++k) {
+  fetch_roots();
+  for (uint32_t kb = 0;; kb += P) {
+    if (__ballot(i_nx != kNone) == 0) break;  // wave-uniform
     const uint32_t i = i_nx;
+    const bool have = i != kNone;
     const uint64_t x = x_nx;
     const uint64_t xa = xa_nx;
     const Tab T = T_nx;
@@ -918,12 +983,10 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
     for (int j = 0; j < H; ++j) h[j] = h_nx[j];
     const uint64_t rkey = rk_nx;
     const uint32_t rmeta = rm_nx;
-    const bool more = i_nx2 != kNone;
-    i_nx = i_nx2;
-    if (more) {
+    i_nx = batch_item(kb + P);
+    if (i_nx != kNone) {
       x_nx = r.keys[i_nx];
       xa_nx = load_aux(r.vals, i_nx, B);
-      i_nx2 = W.item(k + 2);
     }
     // ops reach this planner after the fresh planner found no room in the
     // same snapshot: first fit viewed all H bins, ghost inserts both bins
@@ -933,16 +996,15 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
 #pragma unroll
     for (int j = 0; j < (int)C; ++j) rc[j] = 0;
     uint32_t bk = 0;
-    if (lane < (int)RB) {
-      const int q = lane / B;
+    if (have && gl < (int)RB) {
+      const int q = gl / B;
       uint32_t hb = h[0];
 #pragma unroll
       for (int j = 1; j < H; ++j)
         if (q == j) hb = h[j];
-      const uint64_t key = rkey;
       if (sorted) bk = min(15u, (rmeta >> 8) & 0xFu);
       uint32_t hv[H];
-      hash_key<H>(g, T, key, hv);
+      hash_key<H>(g, T, rkey, hv);
       uint32_t o = 0;
 #pragma unroll
       for (int j = 0; j < H; ++j) {
@@ -953,37 +1015,40 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
         ++o;
       }
     }
-    if (lane < H) {
+    if (have && gl < H) {
       uint32_t hb = h[0];
 #pragma unroll
       for (int j = 1; j < H; ++j)
-        if (lane == j) hb = h[j];
-      rbin[lane] = hb;
-      rpar[lane] = kRootParent;
+        if (gl == j) hb = h[j];
+      rbinL[gl] = hb;
+      rparL[gl] = kRootParent;
     }
-    if (lane < 16) { bhead[lane] = kNone; btail[lane] = kNone; }
+    for (int j = gl; j < 16; j += W) {
+      bhead[j] = kNone;
+      btail[j] = kNone;
+    }
     uint32_t bks[H];
 #pragma unroll
-    for (int j = 0; j < H; ++j) bks[j] = __shfl(bk, j * B, 64);
-    __syncthreads();
-    if (sorted && lane == 0) {
+    for (int j = 0; j < H; ++j) bks[j] = __shfl(bk, gb + j * B, 64);
+    wave_sync();
+    if (have && sorted && gl == 0) {
 #pragma unroll
       for (int j = 0; j < H; ++j) {
-        rnext[j] = kNone;
+        rnextL[j] = kNone;
         if (btail[bks[j]] == kNone) bhead[bks[j]] = j * B;
-        else rnext[btail[bks[j]]] = j;
+        else set_next(btail[bks[j]], j);
         btail[bks[j]] = j;
       }
     }
-    __syncthreads();
+    wave_sync();
     uint32_t nruns = H;
     uint32_t head = 0;  // BFS: next record
     uint32_t nsp = 0;
     bool found = false;
     uint32_t term_e = 0, term_c = 0;
-    uint64_t tkey = kEmpty;  // the terminal bin's view (lanes < B)
+    uint64_t tkey = kEmpty;  // the terminal bin's view (group lanes < B)
     uint32_t tmeta = 0;
-    bool done = false;
+    bool done = !have;
     while (!done) {
       // ---- the next records in search order, as one group
       uint32_t my_e = 0, my_j = 0, nu = 0;
@@ -992,23 +1057,23 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
         if (head == tail) break;
         const uint32_t nrec = min(G / C, tail - head);
         nu = nrec * C;
-        my_e = head + (uint32_t)lane / C;
-        my_j = (uint32_t)lane % C;
+        my_e = head + (uint32_t)gl / C;
+        my_j = (uint32_t)gl % C;
       } else {
-        int kb = -1;
+        int kb2 = -1;
         for (int q = 0; q < 16; ++q)
-          if (bhead[q] != kNone) { kb = q; break; }
-        if (kb < 0) break;
-        uint32_t e = bhead[kb];
+          if (bhead[q] != kNone) { kb2 = q; break; }
+        if (kb2 < 0) break;
+        uint32_t e = bhead[kb2];
         while (e != kNone && nu + C <= G) {
 #pragma unroll
           for (uint32_t j = 0; j < C; ++j)
-            if ((uint32_t)lane == nu + j) { my_e = e; my_j = j; }
+            if ((uint32_t)gl == nu + j) { my_e = e; my_j = j; }
           nu += C;
           if (((e + 1) & (B - 1)) != 0) {
             e = e + 1;
           } else {
-            const uint32_t nr = rnext[e / B];
+            const uint32_t nr = rnext_at(e / B);
             e = nr == kNone ? kNone : nr * B;
           }
         }
@@ -1017,13 +1082,13 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
       uint32_t rv = 0;
 #pragma unroll
       for (int t = 0; t < (int)C; ++t) {
-        const uint32_t v = __shfl(rc[t], (int)min(my_e, 63u), 64);
+        const uint32_t v = __shfl(rc[t], gb + (int)min(my_e, (uint32_t)W - 1), 64);
         if ((uint32_t)t == my_j) rv = v;
       }
       uint32_t cu = 0;
-      if ((uint32_t)lane < nu) cu = my_e < RB ? rv : cand[(size_t)my_e * C + my_j];
-      const uint32_t ul = (uint32_t)lane / B, sl = (uint32_t)lane % B;
-      const uint32_t cb = __shfl(cu, (int)ul, 64);
+      if ((uint32_t)gl < nu) cu = my_e < RB ? rv : cand[(size_t)my_e * C + my_j];
+      const uint32_t ul = (uint32_t)gl / B, sl = (uint32_t)gl % B;
+      const uint32_t cb = __shfl(cu, gb + (int)ul, 64);
       ulonglong2 sv = make_ulonglong2(kEmpty, 0ull);
       uint32_t mv = 0;
       if (ul < nu) {
@@ -1032,49 +1097,49 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
       }
       // ---- records one by one, in order
       for (uint32_t u = 0; u < nu && !done; u += C) {
-        const uint32_t e = __shfl(my_e, (int)u, 64);
+        const uint32_t e = __shfl(my_e, gb + (int)u, 64);
         if (sorted) {
-          int kb = -1;
+          int kb2 = -1;
           for (int q = 0; q < 16; ++q)
-            if (bhead[q] != kNone) { kb = q; break; }
-          if (kb < 0 || bhead[kb] != e) break;  // order changed: regroup
-          __syncthreads();
-          if (lane == 0) {
+            if (bhead[q] != kNone) { kb2 = q; break; }
+          if (kb2 < 0 || bhead[kb2] != e) break;  // order changed: regroup
+          wave_sync();
+          if (gl == 0) {
             if (((e + 1) & (B - 1)) != 0) {
-              bhead[kb] = e + 1;
+              bhead[kb2] = e + 1;
             } else {
-              const uint32_t nr = rnext[e / B];
-              bhead[kb] = nr == kNone ? kNone : nr * B;
-              if (nr == kNone) btail[kb] = kNone;
+              const uint32_t nr = rnext_at(e / B);
+              bhead[kb2] = nr == kNone ? kNone : nr * B;
+              if (nr == kNone) btail[kb2] = kNone;
             }
           }
-          __syncthreads();
+          wave_sync();
         } else {
           ++head;
         }
         bool spawned = false;
         for (uint32_t j = 0; j < C; ++j) {
           const uint32_t uu = u + j;
-          const uint32_t c = __shfl(cu, (int)uu, 64);
+          const uint32_t c = __shfl(cu, gb + (int)uu, 64);
           bool seen = false;
-          for (uint32_t base = 0; base < nruns; base += 64) {
-            const uint32_t q = base + (uint32_t)lane;
-            seen |= __ballot(q < nruns && rbin[q] == c) != 0;
+          for (uint32_t base = 0; base < nruns; base += W) {
+            const uint32_t q = base + (uint32_t)gl;
+            seen |= gballot(q < nruns && rbin_at(q) == c) != 0;
           }
           if (seen) continue;
           if (views == g.max_search) { done = true; break; }
           if (sorted && !spawned) {
-            if (lane == 0) spl[nsp] = e / B;
+            if (gl == 0) spl[nsp] = e / B;
             ++nsp;
           }
           spawned = true;
           ++views;
-          const int src = (int)(uu * B + ((uint32_t)lane & (B - 1)));
+          const int src = gb + (int)(uu * B + ((uint32_t)gl & (B - 1)));
           const uint64_t vk = __shfl(sv.x, src, 64);
-          const uint32_t vm = __shfl(mv, (int)(uu * B), 64);
-          const bool empty = lane < B && vk == kEmpty;
-          const bool dup = g.ghost && lane < B && vk != kEmpty && ((vm >> lane) & 1u);
-          if (__ballot(empty || dup) != 0) {
+          const uint32_t vm = __shfl(mv, gb + (int)(uu * B), 64);
+          const bool empty = gl < B && vk == kEmpty;
+          const bool dup = g.ghost && gl < B && vk != kEmpty && ((vm >> gl) & 1u);
+          if (gballot(empty || dup) != 0) {
             found = true;
             term_e = e;
             term_c = c;
@@ -1085,42 +1150,38 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
           }
           // a new run: its records' candidate bins, its bin and parent
           const uint32_t run = nruns++;
-          if (lane < B) {
+          if (gl < B) {
             uint32_t hv[H];
             hash_key<H>(g, T, vk, hv);
             uint32_t o = 0;
 #pragma unroll
             for (int q = 0; q < H; ++q)
-              if (hv[q] != c) cand[((size_t)run * B + lane) * C + o++] = hv[q];
+              if (hv[q] != c) cand[((size_t)run * B + gl) * C + o++] = hv[q];
           }
-          if (lane == 0) {
-            rbin[run] = c;
-            rpar[run] = e;
-          }
-          __syncthreads();
+          if (gl == 0) set_run(run, c, e);
+          wave_sync();
           if (sorted) {
             const uint32_t b2 = min(15u, (vm >> 8) & 0xFu);
-            if (lane == 0) {
-              rnext[run] = kNone;
+            if (gl == 0) {
+              set_next(run, kNone);
               if (btail[b2] == kNone) bhead[b2] = run * B;
-              else rnext[btail[b2]] = run;
+              else set_next(btail[b2], run);
               btail[b2] = run;
             }
-            __syncthreads();
+            wave_sync();
           }
         }
       }
     }
-    if (more) fetch_roots();
+    fetch_roots();
     // ---- spawn counts go to the spawn arena for every plan, winning or not
     uint32_t soff = 0;
     if (sorted && nsp > 0) {
-      if (lane == 0) s_off = region_alloc(win + 2, nsp, r.ctr);
-      __syncthreads();
-      soff = s_off;
-      __syncthreads();
+      uint32_t o = 0;
+      if (gl == 0) o = region_take(win + 2, nsp, r.ctr);
+      soff = __shfl(o, gb, 64);
       if (soff != kNone)
-        for (uint32_t j = lane; j < nsp; j += 64) r.spawns[soff + j] = rbin[spl[j]];
+        for (uint32_t j = gl; j < nsp; j += W) r.spawns[soff + j] = rbin_at(spl[j]);
       else
         nsp = 0;
     }
@@ -1130,62 +1191,61 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
       // path: term_e, its parent record, ..., a root record
       uint32_t preg = 0;
       for (uint32_t cur = term_e;;) {
-        if (lane == (int)depth) preg = cur;
-        if (lane == 0) path[depth] = cur;
+        if (gl == (int)depth) preg = cur;
+        if (gl == 0) path[depth] = cur;
         ++depth;
-        const uint32_t par = rpar[cur / B];
+        const uint32_t par = rpar_at(cur / B);
         if (par == kRootParent) break;
         cur = par;
       }
-      const uint32_t emask = (uint32_t)(__ballot(lane < B && tkey == kEmpty) & ((1ull << B) - 1));
+      const uint32_t emask = (uint32_t)(gballot(gl < B && tkey == kEmpty) & ((1ull << B) - 1));
       uint32_t tslot;
       uint64_t dk = 0;
       if (emask) {
         tslot = ffs32(emask);
       } else {
-        const uint32_t dmask = (uint32_t)(__ballot(lane < B && tkey != kEmpty &&
-                                                   ((tmeta >> lane) & 1u)) & ((1ull << B) - 1));
+        const uint32_t dmask = (uint32_t)(gballot(gl < B && tkey != kEmpty &&
+                                                  ((tmeta >> gl) & 1u)) & ((1ull << B) - 1));
         tslot = ffs32(dmask);
-        dk = __shfl(tkey, (int)tslot, 64);
+        dk = __shfl(tkey, gb + (int)tslot, 64);
         twin = 1;
       }
       nm = depth + 1 + twin;
-      if (lane == 0) s_off = region_alloc(win, nm, r.ctr);
-      __syncthreads();
-      off = s_off;
-      __syncthreads();
+      uint32_t o = 0;
+      if (gl == 0) o = region_take(win, nm, r.ctr);
+      off = __shfl(o, gb, 64);
+      wave_sync();  // the path array, written by the group leader
       // the terminal write's content is the deepest record's snapshot content
-      const ulonglong2 tv = g.slots[(uint64_t)rbin[term_e / B] * B + term_e % B];
-      const uint64_t tk = tv.x, ta = tv.y;
+      const ulonglong2 tv = g.slots[(uint64_t)rbin_at(term_e / B) * B + term_e % B];
       uint32_t tb = 0, tws = 0;
       if (twin) {  // the duplicate's twin, in the duplicate key's other bin
         uint32_t hd[2];
         hash_key<2>(g, T, dk, hd);
         tb = hd[0] == term_c ? hd[1] : hd[0];
         uint64_t tk2 = kEmpty;
-        if (lane < B) tk2 = g.slots[(uint64_t)tb * B + lane].x;
-        tws = ffs32((uint32_t)(__ballot(lane < B && tk2 == dk) & ((1ull << B) - 1)));
+        if (gl < B) tk2 = g.slots[(uint64_t)tb * B + gl].x;
+        tws = ffs32((uint32_t)(gballot(gl < B && tk2 == dk) & ((1ull << B) - 1)));
       }
       // chain moves: move m puts the content of path[depth - m] (x for m = 0)
       // into the slot of path[depth - 1 - m]
-      for (uint32_t mb = 0; mb < depth; mb += 64) {
-        const uint32_t m = mb + (uint32_t)lane;
+      for (uint32_t mb = 0; mb < depth; mb += W) {
+        const uint32_t m = mb + (uint32_t)gl;
         const uint32_t d = m < depth ? depth - 1 - m : 0;
-        const uint32_t p_reg = __shfl(preg, (int)min(d, 63u), 64);
-        const uint32_t s_reg = __shfl(preg, (int)min(d + 1, 63u), 64);
+        const uint32_t p_reg = __shfl(preg, gb + (int)min(d, (uint32_t)W - 1), 64);
+        const uint32_t s_reg = __shfl(preg, gb + (int)min(d + 1, (uint32_t)W - 1), 64);
         if (m < depth) {
-          const uint32_t prec = depth <= 64 ? p_reg : path[d];
+          const uint32_t prec = depth <= (uint32_t)W ? p_reg : path[d];
           Move mvv;
           if (m == 0) {
             mvv.key = x;
             mvv.aux = xa;
           } else {
-            const uint32_t srec = depth <= 64 ? s_reg : path[d + 1];
-            const ulonglong2 v = g.slots[(uint64_t)rbin[srec / B] * B + srec % B];
+            const uint32_t srec = depth <= (uint32_t)W ? s_reg : path[d + 1];
+            const ulonglong2 v = g.slots[(uint64_t)rbin_at(srec / B) * B + srec % B];
             mvv.key = v.x;
             mvv.aux = v.y;
           }
-          mvv.bin = rbin[prec / B];
+          mvv.bin = rbin_at(prec / B);
           mvv.slot = (uint8_t)(prec % B);
           mvv.flags = 0;
           mvv.pad = 0;
@@ -1195,7 +1255,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
           }
         }
       }
-      if (lane == 0 && off != kNone) {
+      if (gl == 0 && off != kNone) {
         if (twin) {
           Move t2;
           t2.key = 0;
@@ -1208,8 +1268,8 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
           claim(g, r, tb, i);
         }
         Move t1;
-        t1.key = tk;
-        t1.aux = ta;
+        t1.key = tv.x;
+        t1.aux = tv.y;
         t1.bin = term_c;
         t1.slot = (uint8_t)tslot;
         t1.flags = 0;
@@ -1218,7 +1278,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
         claim(g, r, term_c, i);
       }
     }
-    if (lane == 0) {
+    if (have && gl == 0) {
       PlanHdr hd{};
       hd.st = hdr_pack(found ? PL_OK : PL_FAIL, twin, nm);
       hd.views = views;
@@ -1227,27 +1287,23 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
       hd.n_spawn = nsp;
       hd.spawn_off = soff;
       r.hdr[i] = hd;
-      s_views += views;
+      atomicAdd(&s_views, (unsigned long long)views);
     }
-    __syncthreads();
+    wave_sync();
   }
   if (threadIdx.x == 0 && s_views) r.wg_views[blockIdx.x] += s_views;
 }
 
 size_t evict_lds_bytes(const Geo& g) {
-  if (g.scheme == CK_BFS || g.scheme == CK_SORTED) {
-    return (3 * search_runs(g) + 32) * 4 + 64;
-  }
+  if (g.scheme == CK_BFS || g.scheme == CK_SORTED)
+    return (64 / kSearchW) * search_group_lds_words() * 4 + 64;
   const size_t cap = g.max_chain + 8;
   return cap * 24 + 8 * 4 + 8 * 4 + 64;
 }
 
 size_t evict_wg_scratch_bytes(const Geo& g) {
-  if (g.scheme == CK_BFS || g.scheme == CK_SORTED) {
-    const size_t RC = search_runs(g);
-    size_t b = RC * g.B * (g.H - 1) * 4 + 2 * RC * 4;
-    return (b + 255) & ~(size_t)255;
-  }
+  if (g.scheme == CK_BFS || g.scheme == CK_SORTED)
+    return (64 / kSearchW) * search_group_scratch_bytes(g);
   return 256;
 }
 
