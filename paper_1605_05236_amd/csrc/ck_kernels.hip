@@ -901,24 +901,31 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
   uint32_t* rnextL = rparL + RL;
   uint32_t* bhead = rnextL + RL;  // record at the head of each bucket
   uint32_t* btail = bhead + 16;   // last run of each bucket
-  char* scratch = (char*)r.wg_scratch + (size_t)blockIdx.x * r.wg_scratch_bytes +
-                  (size_t)gi * (r.wg_scratch_bytes / P);
-  uint32_t* cand = (uint32_t*)scratch;         // RC * B * C
-  uint32_t* spl = cand + (size_t)RC * B * C;   // RC: runs that spawned (sorted)
-  uint32_t* path = spl + RC;                   // RC: records, deepest first
-  uint32_t* rbinG = path + RC;                 // runs >= RL
-  uint32_t* rparG = rbinG + RC;
-  uint32_t* rnextG = rparG + RC;
-  auto rbin_at = [&](uint32_t j) -> uint32_t { return j < RL ? rbinL[j] : rbinG[j]; };
-  auto rpar_at = [&](uint32_t j) -> uint32_t { return j < RL ? rparL[j] : rparG[j]; };
-  auto rnext_at = [&](uint32_t j) -> uint32_t { return j < RL ? rnextL[j] : rnextG[j]; };
+  // the group's scratch: one workgroup-uniform base plus a per-group word
+  // offset, so the arrays cost one register, not a pointer each
+  uint32_t* const wsb = (uint32_t*)((char*)r.wg_scratch + (size_t)blockIdx.x * r.wg_scratch_bytes);
+  const uint32_t go = (uint32_t)gi * (r.wg_scratch_bytes / P / 4);
+  const uint32_t o_spl = RC * B * C;  // cand: RC * B * C words first
+  const uint32_t o_path = o_spl + RC;
+  const uint32_t o_rbin = o_path + RC;  // runs >= RL
+  const uint32_t o_rpar = o_rbin + RC;
+  const uint32_t o_rnext = o_rpar + RC;
+  auto cand = [&](uint32_t j) -> uint32_t& { return wsb[go + j]; };
+  auto spl = [&](uint32_t j) -> uint32_t& { return wsb[go + o_spl + j]; };
+  auto path = [&](uint32_t j) -> uint32_t& { return wsb[go + o_path + j]; };
+  auto rbinG = [&](uint32_t j) -> uint32_t& { return wsb[go + o_rbin + j]; };
+  auto rparG = [&](uint32_t j) -> uint32_t& { return wsb[go + o_rpar + j]; };
+  auto rnextG = [&](uint32_t j) -> uint32_t& { return wsb[go + o_rnext + j]; };
+  auto rbin_at = [&](uint32_t j) -> uint32_t { return j < RL ? rbinL[j] : rbinG(j); };
+  auto rpar_at = [&](uint32_t j) -> uint32_t { return j < RL ? rparL[j] : rparG(j); };
+  auto rnext_at = [&](uint32_t j) -> uint32_t { return j < RL ? rnextL[j] : rnextG(j); };
   auto set_run = [&](uint32_t j, uint32_t bin, uint32_t par) {  // group leader
     if (j < RL) { rbinL[j] = bin; rparL[j] = par; }
-    else { rbinG[j] = bin; rparG[j] = par; }
+    else { rbinG(j) = bin; rparG(j) = par; }
   };
   auto set_next = [&](uint32_t j, uint32_t nx) {  // group leader
     if (j < RL) rnextL[j] = nx;
-    else rnextG[j] = nx;
+    else rnextG(j) = nx;
   };
   const bool sorted = g.scheme == CK_SORTED;
   const bool need_meta = sorted || g.ghost;
@@ -945,7 +952,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
   // ops and keys are in flight, and their root bins are fetched as soon as
   // the current searches end.
   uint32_t i_nx = batch_item(0);
-  uint64_t x_nx = 0, xa_nx = 0;
+  uint64_t x_nx = 0;
   Tab T_nx{0u, 0u};
   uint32_t h_nx[H];
 #pragma unroll
@@ -966,17 +973,12 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
       if (sorted) rm_nx = g.meta[hb];
     }
   };
-  if (i_nx != kNone) {
-    x_nx = r.keys[i_nx];
-    xa_nx = load_aux(r.vals, i_nx, B);
-  }
+  if (i_nx != kNone) x_nx = r.keys[i_nx];
   fetch_roots();
   for (uint32_t kb = 0;; kb += P) {
     if (__ballot(i_nx != kNone) == 0) break;  // wave-uniform
     const uint32_t i = i_nx;
     const bool have = i != kNone;
-    const uint64_t x = x_nx;
-    const uint64_t xa = xa_nx;
     const Tab T = T_nx;
     uint32_t h[H];
 #pragma unroll
@@ -984,10 +986,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
     const uint64_t rkey = rk_nx;
     const uint32_t rmeta = rm_nx;
     i_nx = batch_item(kb + P);
-    if (i_nx != kNone) {
-      x_nx = r.keys[i_nx];
-      xa_nx = load_aux(r.vals, i_nx, B);
-    }
+    if (i_nx != kNone) x_nx = r.keys[i_nx];
     // ops reach this planner after the fresh planner found no room in the
     // same snapshot: first fit viewed all H bins, ghost inserts both bins
     uint32_t views = g.ghost ? 2u : (uint32_t)H;
@@ -1086,7 +1085,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
         if ((uint32_t)t == my_j) rv = v;
       }
       uint32_t cu = 0;
-      if ((uint32_t)gl < nu) cu = my_e < RB ? rv : cand[(size_t)my_e * C + my_j];
+      if ((uint32_t)gl < nu) cu = my_e < RB ? rv : cand(my_e * C + my_j);
       const uint32_t ul = (uint32_t)gl / B, sl = (uint32_t)gl % B;
       const uint32_t cb = __shfl(cu, gb + (int)ul, 64);
       ulonglong2 sv = make_ulonglong2(kEmpty, 0ull);
@@ -1129,7 +1128,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
           if (seen) continue;
           if (views == g.max_search) { done = true; break; }
           if (sorted && !spawned) {
-            if (gl == 0) spl[nsp] = e / B;
+            if (gl == 0) spl(nsp) = e / B;
             ++nsp;
           }
           spawned = true;
@@ -1156,7 +1155,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
             uint32_t o = 0;
 #pragma unroll
             for (int q = 0; q < H; ++q)
-              if (hv[q] != c) cand[((size_t)run * B + gl) * C + o++] = hv[q];
+              if (hv[q] != c) cand((run * B + gl) * C + o++) = hv[q];
           }
           if (gl == 0) set_run(run, c, e);
           wave_sync();
@@ -1181,7 +1180,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
       if (gl == 0) o = region_take(win + 2, nsp, r.ctr);
       soff = __shfl(o, gb, 64);
       if (soff != kNone)
-        for (uint32_t j = gl; j < nsp; j += W) r.spawns[soff + j] = rbin_at(spl[j]);
+        for (uint32_t j = gl; j < nsp; j += W) r.spawns[soff + j] = rbin_at(spl(j));
       else
         nsp = 0;
     }
@@ -1192,7 +1191,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
       uint32_t preg = 0;
       for (uint32_t cur = term_e;;) {
         if (gl == (int)depth) preg = cur;
-        if (gl == 0) path[depth] = cur;
+        if (gl == 0) path(depth) = cur;
         ++depth;
         const uint32_t par = rpar_at(cur / B);
         if (par == kRootParent) break;
@@ -1234,13 +1233,13 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
         const uint32_t p_reg = __shfl(preg, gb + (int)min(d, (uint32_t)W - 1), 64);
         const uint32_t s_reg = __shfl(preg, gb + (int)min(d + 1, (uint32_t)W - 1), 64);
         if (m < depth) {
-          const uint32_t prec = depth <= (uint32_t)W ? p_reg : path[d];
+          const uint32_t prec = depth <= (uint32_t)W ? p_reg : path(d);
           Move mvv;
-          if (m == 0) {
-            mvv.key = x;
-            mvv.aux = xa;
+          if (m == 0) {  // the op's own key and value (re-read: not kept live)
+            mvv.key = r.keys[i];
+            mvv.aux = load_aux(r.vals, i, B);
           } else {
-            const uint32_t srec = depth <= (uint32_t)W ? s_reg : path[d + 1];
+            const uint32_t srec = depth <= (uint32_t)W ? s_reg : path(d + 1);
             const ulonglong2 v = g.slots[(uint64_t)rbin_at(srec / B) * B + srec % B];
             mvv.key = v.x;
             mvv.aux = v.y;
