@@ -262,7 +262,7 @@ Round make_round(ck_table* t, const uint64_t* keys, const void* vals, uint8_t* s
 // kTailOps ops remain, kTailRounds rounds are enqueued back to back with the
 // count held in device memory (grids sized for the last count read, which
 // only shrinks), and the host synchronises once per group of rounds.
-constexpr uint32_t kTailOps = 4096;
+constexpr uint32_t kTailOps = 65536;
 constexpr int kTailRounds = 4;
 
 ck_status run_rounds(ck_table* t, Round& r, uint64_t m, hipStream_t s) {
@@ -272,8 +272,7 @@ ck_status run_rounds(ck_table* t, Round& r, uint64_t m, hipStream_t s) {
   // adds a few void rounds.  Anything beyond that is a fault, not progress.
   uint64_t guard = 2 * m + 64;
   Timer& T = t->timer;
-  HIP_TRY(hipMemsetAsync(&t->ctr->rounds, 0, 4, s));
-  HIP_TRY(hipMemsetAsync(&t->ctr->overflow_seen, 0, 4, s));
+  // ctr->rounds and ctr->overflow_seen were cleared by k_batch_begin
   while (npend > 0) {
     if (guard == 0) return CK_EDEVICE;
     const int K = npend <= kTailOps ? kTailRounds : 1;
@@ -350,7 +349,7 @@ ck_status run_batches(ck_table* t, const uint64_t* keys, const void* vals, uint6
     Round r = make_round(t, keys + b0, vals ? (const char*)vals + b0 * vb : nullptr,
                          status + b0, ops, t->insert_count + b0, is_delete,
                          op_table ? op_table + b0 : nullptr, tdesc);
-    HIP_TRY(launch_batch_begin(m, t->pend[0], ops[0], ops[1], ops[2], ops[3], ops[4], s));
+    HIP_TRY(launch_batch_begin(m, t->pend[0], ops[0], ops[1], ops[2], ops[3], ops[4], t->ctr, s));
     ck_status st = run_rounds(t, r, m, s);
     if (st != CK_OK) return st;
     hipEvent_t ev = t->timer.begin(s, TK_STATS);

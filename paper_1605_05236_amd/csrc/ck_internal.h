@@ -150,7 +150,7 @@ hipError_t launch_lookup(const Geo& g, const uint64_t* keys, uint64_t n, void* v
                          const uint2* tdesc, hipStream_t s);
 hipError_t launch_round_begin(Ctr* c, hipStream_t s);
 hipError_t launch_batch_begin(uint64_t m, uint32_t* pend, uint32_t* views, uint32_t* lost,
-                              uint32_t* kicks, uint32_t* retries, uint32_t* twins, hipStream_t s);
+                              uint32_t* kicks, uint32_t* retries, uint32_t* twins, Ctr* c, hipStream_t s);
 hipError_t launch_plan_fresh(const Geo& g, const Round& r, hipStream_t s);
 hipError_t launch_plan_evict(const Geo& g, const Round& r, uint32_t grid, hipStream_t s);
 hipError_t launch_plan_delete(const Geo& g, const Round& r, hipStream_t s);

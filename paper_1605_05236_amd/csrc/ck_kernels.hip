@@ -270,7 +270,11 @@ hipError_t launch_round_begin(Ctr* c, hipStream_t s) {
 }
 
 __global__ void k_batch_begin(uint64_t m, uint32_t* pend, uint32_t* views, uint32_t* lost,
-                              uint32_t* kicks, uint32_t* retries, uint32_t* twins) {
+                              uint32_t* kicks, uint32_t* retries, uint32_t* twins, Ctr* c) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {  // the sub-batch's round counters
+    c->rounds = 0;
+    c->overflow_seen = 0;
+  }
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
     pend[i] = (uint32_t)i;
@@ -282,11 +286,12 @@ __global__ void k_batch_begin(uint64_t m, uint32_t* pend, uint32_t* views, uint3
   }
 }
 hipError_t launch_batch_begin(uint64_t m, uint32_t* pend, uint32_t* views, uint32_t* lost,
-                              uint32_t* kicks, uint32_t* retries, uint32_t* twins, hipStream_t s) {
+                              uint32_t* kicks, uint32_t* retries, uint32_t* twins, Ctr* c,
+                              hipStream_t s) {
   uint32_t grid = (uint32_t)std::min<uint64_t>((m + 255) / 256, 4096);
   if (grid == 0) grid = 1;
   hipLaunchKernelGGL(k_batch_begin, dim3(grid), dim3(256), 0, s, m, pend, views, lost, kicks,
-                     retries, twins);
+                     retries, twins, c);
   return hipGetLastError();
 }
 
@@ -1734,24 +1739,7 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_scan(uint32_t* block_ok, u
   if (threadIdx.x == 0) st->v[S_STORED] += carry;
 }
 
-// pass 3: density band of every op, totals.  Ops of one wavefront almost
-// always share a band: their contributions are summed across the wavefront
-// first, so the LDS histogram sees one atomic per wavefront and band.
-__device__ __forceinline__ void band_add(unsigned long long* hist, uint32_t band, bool valid,
-                                         unsigned long long v) {
-  const int lane = threadIdx.x & 63;
-  uint64_t todo = __ballot(valid);
-  while (todo) {
-    const int leader = __ffsll((unsigned long long)todo) - 1;
-    const uint32_t b = __shfl(band, leader, 64);
-    const bool mine = valid && band == b;
-    const uint64_t same = __ballot(mine);
-    const unsigned long long sum = wave_sum(mine ? v : 0ull);
-    if (lane == leader && sum) atomicAdd(&hist[b], sum);
-    todo &= ~same;
-  }
-}
-
+// pass 3: density band of every op, totals.
 __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
     const uint8_t* status, const uint32_t* views, const uint32_t* lost, const uint32_t* kicks,
     const uint32_t* retries, const uint32_t* twins, uint64_t m, const uint32_t* block_ok,
@@ -1766,7 +1754,24 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
   const uint32_t ntiles = (uint32_t)((m + kStatBlock - 1) / kStatBlock);
   unsigned long long a_ok = 0, a_fail = 0, a_abort = 0, a_bad = 0, a_views = 0, a_vall = 0,
                      a_kicks = 0, a_maxk = 0, a_ret = 0, a_tw = 0;
-  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  // Each block takes a contiguous run of tiles, so an op's density band
+  // changes rarely from one tile to the next: every lane sums its ops' band
+  // contributions in registers and adds them to the block histogram only
+  // when its band changes, and at the end.
+  uint32_t cb = kNone;
+  unsigned long long c_n = 0, c_views = 0, c_kicks = 0, c_fail = 0;
+  auto flush = [&]() {
+    if (cb != kNone) {
+      if (c_n) atomicAdd(&hb[0][cb], c_n);
+      if (c_views) atomicAdd(&hb[1][cb], c_views);
+      if (c_kicks) atomicAdd(&hb[2][cb], c_kicks);
+      if (c_fail) atomicAdd(&hb[3][cb], c_fail);
+    }
+    c_n = c_views = c_kicks = c_fail = 0;
+  };
+  const uint32_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+  const uint32_t t_end = min(ntiles, (blockIdx.x + 1) * per);
+  for (uint32_t tile = blockIdx.x * per; tile < t_end; ++tile) {
     const uint64_t i = (uint64_t)tile * kStatBlock + threadIdx.x;
     const uint8_t s = i < m ? status[i] : 0xFF;
     const bool ok = s == CK_OP_OK;
@@ -1809,11 +1814,18 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
         }
       }
     }
-    band_add(hb[0], band, banded, 1ull);
-    band_add(hb[1], band, banded, v_views);
-    band_add(hb[2], band, banded && ok, v_kicks);
-    band_add(hb[3], band, banded && !ok, 1ull);
+    if (banded) {
+      if (band != cb) {
+        flush();
+        cb = band;
+      }
+      c_n += 1;
+      c_views += v_views;
+      if (ok) c_kicks += v_kicks;
+      else c_fail += 1;
+    }
   }
+  flush();
   a_ok = wave_sum(a_ok); a_fail = wave_sum(a_fail); a_abort = wave_sum(a_abort);
   a_bad = wave_sum(a_bad); a_views = wave_sum(a_views); a_vall = wave_sum(a_vall);
   a_kicks = wave_sum(a_kicks); a_maxk = wave_max(a_maxk); a_ret = wave_sum(a_ret);
