@@ -299,20 +299,10 @@ hipError_t launch_batch_begin(uint64_t m, uint32_t* pend, uint32_t* views, uint3
 // plan emission helpers (called by one lane)
 // ---------------------------------------------------------------------------
 // Every eviction-planner workgroup owns a fixed region of the plan arena
-// (cap / gridDim.x entries) and fills it in order: no shared counter.  A plan
-// that does not fit marks the round void; the host then grows the arena and
-// the round is planned again.  win[0] = next free entry, win[1] = region end.
-// One lane.
-__device__ __forceinline__ uint32_t region_alloc(uint32_t* win, uint32_t n, Ctr* ctr) {
-  if (n == 0) return 0;
-  if (win[0] + n > win[1]) {
-    atomicOr(&ctr->overflow, 1u);
-    return kNone;
-  }
-  const uint32_t off = win[0];
-  win[0] += n;
-  return off;
-}
+// (cap / gridDim.x entries) and fills it in order: no device-wide counter.  A
+// plan that does not fit marks the round void; the host then grows the arena
+// and the round is planned again.  win[0] = next free entry, win[1] = region
+// end.
 __device__ __forceinline__ void region_init(uint32_t* win, uint32_t cap) {
   const uint32_t per = cap / gridDim.x;
   win[0] = blockIdx.x * per;
@@ -505,25 +495,74 @@ struct EvictWork {
 };
 
 // ---------------------------------------------------------------------------
-// wavefront planners (k_plan_walk, k_plan_search) share this context.
-// One workgroup = one wavefront = one op at a time.  Lanes 0..B-1 hold the
-// slots of the bin being viewed; all 64 lanes scan the LDS move log.
+// Walk planners (random kicking, queue-kicking, rattle-kicking): a
+// wavefront runs 64 / kWalkW walks side by side, kWalkW lanes each (a group);
+// lanes < B of a group hold the slots of the bin the walk is viewing.  A
+// walk logs its moves; a later view of a bin it already wrote shows its own
+// writes (the overlay).  The first kWalkLdsLog moves of a walk are logged in
+// LDS, longer chains continue in workgroup scratch.
 // ---------------------------------------------------------------------------
-struct WaveLog {
-  uint64_t* key;
+constexpr int kWalkW = 8;
+constexpr uint32_t kWalkLdsLog = 32;
+
+// Orders LDS and memory accesses of the lanes of one wavefront (the planner
+// workgroups are single wavefronts, so this is a full workgroup barrier);
+// valid in divergent code.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Arena regions shared by the workgroup's planners.
+__device__ __forceinline__ uint32_t region_take(uint32_t* win, uint32_t n, Ctr* ctr) {
+  if (n == 0) return 0;
+  const uint32_t off = atomicAdd(&win[0], n);
+  if (off + n > win[1]) {
+    atomicOr(&ctr->overflow, 1u);
+    return kNone;
+  }
+  return off;
+}
+
+// A walk's move log: entries < kWalkLdsLog in LDS, the rest in scratch, and
+// a filter of the bins it wrote (one bit per bin hash; a view of a bin whose
+// bit is clear has nothing to overlay).
+constexpr uint32_t kWalkMapWords = 64;  // 2048 bits
+struct WalkLog {
+  uint64_t* key;    // LDS, kWalkLdsLog each
   uint64_t* aux;
   uint32_t* bin;
-  uint32_t* sf;   // slot | flags << 8
-  int* last;      // [8]
-  uint32_t* misc; // [8]: 0 hc adds, 1.. broadcast words
+  uint32_t* sf;     // slot | flags << 8
+  int* last;        // LDS [8]
+  uint32_t* misc;   // LDS [8]: 0 hc adds
+  uint32_t* wmap;   // LDS [kWalkMapWords]
+  uint64_t* gkey;   // scratch, indexed from 0 (entries < kWalkLdsLog unused)
+  uint64_t* gaux;
+  uint32_t* gbin;
+  uint32_t* gsf;
+  __device__ __forceinline__ uint64_t& k(uint32_t j) const { return j < kWalkLdsLog ? key[j] : gkey[j]; }
+  __device__ __forceinline__ uint64_t& a(uint32_t j) const { return j < kWalkLdsLog ? aux[j] : gaux[j]; }
+  __device__ __forceinline__ uint32_t& b(uint32_t j) const { return j < kWalkLdsLog ? bin[j] : gbin[j]; }
+  __device__ __forceinline__ uint32_t& f(uint32_t j) const { return j < kWalkLdsLog ? sf[j] : gsf[j]; }
+  __device__ static __forceinline__ uint32_t mbit(uint32_t b) { return (b * 0x9E3779B1u) >> 21; }
+  __device__ __forceinline__ bool maybe_written(uint32_t b) const {
+    const uint32_t h = mbit(b);
+    return (wmap[h >> 5] >> (h & 31)) & 1u;
+  }
+  __device__ __forceinline__ void mark(uint32_t b) const {  // one lane
+    const uint32_t h = mbit(b);
+    wmap[h >> 5] |= 1u << (h & 31);
+  }
 };
 
 template <int B, int H>
-struct WavePlanner {
+struct WalkPlanner {
+  static constexpr int W = kWalkW;
   const Geo& g;
   const Round& r;
-  WaveLog L;
-  int lane;
+  WalkLog L;
+  int gl, gb;          // lane within the group, the group's first lane
   uint32_t cap;        // log capacity
   uint32_t nm = 0;     // moves logged
   uint32_t views = 0, kicks = 0, twins = 0, draws = 0;
@@ -531,54 +570,58 @@ struct WavePlanner {
   Tab T{0u, 0u};       // the op's table
   bool overflow = false;
 
-  // bin view state (lanes < B)
+  // bin view state (group lanes < B)
   uint64_t vkey = kEmpty, vaux = 0;
   bool vdup = false;
   int vprev = -1;      // log index of the last write to this lane's slot
-  uint32_t vhc = 0;    // hit counter of the viewed bin (uniform)
-  uint32_t vmeta = 0;  // metadata word of the viewed bin, as read (uniform)
+  uint32_t vhc = 0;    // hit counter of the viewed bin (group-uniform)
+  uint32_t vmeta = 0;  // metadata word of the viewed bin, as read (group-uniform)
   uint32_t vbin = kNone;
 
-  __device__ WavePlanner(const Geo& g_, const Round& r_, WaveLog l, uint32_t cap_)
-      : g(g_), r(r_), L(l), lane(threadIdx.x), cap(cap_) {}
+  __device__ WalkPlanner(const Geo& g_, const Round& r_, WalkLog l, uint32_t cap_)
+      : g(g_), r(r_), L(l), gl(threadIdx.x % W), gb(threadIdx.x - threadIdx.x % W), cap(cap_) {}
 
   __device__ __forceinline__ uint32_t ballotB(bool p) const {
-    return (uint32_t)(__ballot(lane < B && p) & ((1ull << B) - 1));
+    return (uint32_t)((__ballot(gl < B && p) >> gb) & ((1ull << B) - 1));
+  }
+  template <class V>
+  __device__ __forceinline__ V gshfl(V v, uint32_t src) const {
+    return __shfl(v, gb + (int)src, 64);
   }
 
-  // Load bin b into lanes < B, applying this plan's earlier writes.
+  // Load bin b into group lanes < B, applying this plan's earlier writes.
   // `count` = true makes it a bin view (Sec. 3 cost unit).
   __device__ void load(uint32_t b, bool count) {
     if (count) ++views;
     ulonglong2 s = make_ulonglong2(kEmpty, 0ull);
-    if (lane < B) s = g.slots[(uint64_t)b * B + lane];
-    uint32_t m = (g.ghost || g.scheme == CK_QUEUE || g.scheme == CK_SORTED) ? g.meta[b] : 0u;
-    bool dup = lane < B && ((m >> lane) & 1u);
+    if (gl < B) s = g.slots[(uint64_t)b * B + gl];
+    uint32_t m = (g.ghost || g.scheme == CK_QUEUE) ? g.meta[b] : 0u;
+    bool dup = gl < B && ((m >> gl) & 1u);
     int prev = -1;
     uint32_t hcadd = 0;
-    if (nm > 0) {
-      if (lane < 8) L.last[lane] = -1;
-      if (lane == 0) L.misc[0] = 0;
-      __syncthreads();
-      for (uint32_t j = lane; j < nm; j += 64) {
-        if (L.bin[j] == b) {
-          uint32_t sf = L.sf[j];
-          uint32_t f = sf >> 8;
+    if (nm > 0 && L.maybe_written(b)) {
+      if (gl < 8) L.last[gl] = -1;
+      if (gl == 0) L.misc[0] = 0;
+      wave_sync();
+      for (uint32_t j = gl; j < nm; j += W) {
+        if (L.b(j) == b) {
+          const uint32_t sf = L.f(j);
+          const uint32_t f = sf >> 8;
           if (!(f & MV_DUPCLR)) atomicMax(&L.last[sf & 0xFF], (int)j);
           if (f & MV_HC) atomicAdd(&L.misc[0], 1u);
         }
       }
-      __syncthreads();
-      if (lane < B) {
-        prev = L.last[lane];
+      wave_sync();
+      if (gl < B) {
+        prev = L.last[gl];
         if (prev >= 0) {
-          s.x = L.key[prev];
-          s.y = L.aux[prev];
-          dup = (L.sf[prev] >> 8) & MV_DUP;
+          s.x = L.k(prev);
+          s.y = L.a(prev);
+          dup = (L.f(prev) >> 8) & MV_DUP;
         }
       }
       hcadd = L.misc[0];
-      __syncthreads();
+      wave_sync();
     }
     vkey = s.x;
     vaux = s.y;
@@ -594,41 +637,43 @@ struct WavePlanner {
   __device__ __forceinline__ bool terminal() const {
     return empty_mask() != 0 || (g.ghost && dup_mask() != 0);
   }
-  __device__ __forceinline__ uint64_t slot_key(uint32_t s) const { return __shfl(vkey, (int)s, 64); }
-  __device__ __forceinline__ uint64_t slot_aux(uint32_t s) const { return __shfl(vaux, (int)s, 64); }
+  __device__ __forceinline__ uint64_t slot_key(uint32_t s) const { return gshfl(vkey, s); }
+  __device__ __forceinline__ uint64_t slot_aux(uint32_t s) const { return gshfl(vaux, s); }
 
   // Log a write of (key, aux) to slot s of the currently viewed bin.
   __device__ void emit_here(uint32_t s, uint64_t k, uint64_t a, uint32_t flags) {
-    const int prev = __shfl(vprev, (int)s, 64);
+    const int prev = gshfl(vprev, s);
     if (nm >= cap) { overflow = true; return; }
-    if (lane == 0) {
-      if (prev >= 0) L.sf[prev] |= ((uint32_t)MV_SUPERSEDED << 8);
-      L.key[nm] = k;
-      L.aux[nm] = a;
-      L.bin[nm] = vbin;
-      L.sf[nm] = s | (flags << 8);
+    if (gl == 0) {
+      if (prev >= 0) L.f(prev) |= ((uint32_t)MV_SUPERSEDED << 8);
+      L.k(nm) = k;
+      L.a(nm) = a;
+      L.b(nm) = vbin;
+      L.f(nm) = s | (flags << 8);
+      L.mark(vbin);
     }
     ++nm;
     // keep the view coherent with the write (the walk may read this bin again)
-    if (lane == (int)s) {
+    if (gl == (int)s) {
       vkey = k;
       vaux = a;
       vdup = (flags & MV_DUP) != 0;
       vprev = (int)nm - 1;
     }
     if (flags & MV_HC) vhc = (vhc + 1) & 0xFFu;
-    __syncthreads();
+    wave_sync();
   }
   __device__ void emit_other(uint32_t b, uint32_t s, uint64_t k, uint64_t a, uint32_t flags) {
     if (nm >= cap) { overflow = true; return; }
-    if (lane == 0) {
-      L.key[nm] = k;
-      L.aux[nm] = a;
-      L.bin[nm] = b;
-      L.sf[nm] = s | (flags << 8);
+    if (gl == 0) {
+      L.k(nm) = k;
+      L.a(nm) = a;
+      L.b(nm) = b;
+      L.f(nm) = s | (flags << 8);
+      L.mark(b);
     }
     ++nm;
-    __syncthreads();
+    wave_sync();
   }
 
   // Drop the duplicate in slot s of the viewed bin and put (k, a) there; the
@@ -640,7 +685,7 @@ struct WavePlanner {
     const uint32_t here = vbin;
     const uint32_t tb = hd[0] == here ? hd[1] : hd[0];
     ulonglong2 ts = make_ulonglong2(kEmpty, 0ull);
-    if (lane < B) ts = g.slots[(uint64_t)tb * B + lane];
+    if (gl < B) ts = g.slots[(uint64_t)tb * B + gl];
     const uint32_t tm = ballotB(ts.x == dk);
     emit_other(tb, ffs32(tm), 0, 0, MV_DUPCLR);
     ++twins;
@@ -748,80 +793,117 @@ struct WavePlanner {
   }
 
   // Copy the logged moves to the arena, write the header and claim bins.
-  // `win` is the workgroup's arena window (LDS).
-  __device__ void finish(uint32_t i, uint32_t status, uint32_t n_spawn, uint32_t spawn_off,
-                         uint32_t* win, unsigned long long* wg_views) {
-    __shared__ uint32_t s_off;
+  __device__ void finish(uint32_t i, uint32_t status, uint32_t* win,
+                         unsigned long long* wg_views) {
     if (status != PL_OK) nm = 0;
-    if (lane == 0) s_off = region_alloc(win, nm, r.ctr);
-    __syncthreads();
-    const uint32_t off = s_off;
-    __syncthreads();
+    uint32_t o = 0;
+    if (gl == 0) o = region_take(win, nm, r.ctr);
+    const uint32_t off = gshfl(o, 0);
     if (off != kNone) {
-      for (uint32_t j = lane; j < nm; j += 64) {
+      for (uint32_t j = gl; j < nm; j += W) {
         Move mv;
-        mv.key = L.key[j];
-        mv.aux = L.aux[j];
-        mv.bin = L.bin[j];
-        mv.slot = (uint8_t)(L.sf[j] & 0xFF);
-        mv.flags = (uint8_t)(L.sf[j] >> 8);
+        mv.key = L.k(j);
+        mv.aux = L.a(j);
+        mv.bin = L.b(j);
+        mv.slot = (uint8_t)(L.f(j) & 0xFF);
+        mv.flags = (uint8_t)(L.f(j) >> 8);
         mv.pad = 0;
         r.arena[off + j] = mv;
         claim(g, r, mv.bin, i);
       }
     }
-    if (lane == 0) {
+    if (gl == 0) {
       PlanHdr hd{};
       hd.st = hdr_pack(status, status == PL_OK ? twins : 0, nm);
       hd.views = views;
       hd.kicks = status == PL_OK ? kicks : 0;
       hd.off = off;
-      hd.n_spawn = n_spawn;
-      hd.spawn_off = spawn_off;
+      hd.n_spawn = 0;
+      hd.spawn_off = 0;
       r.hdr[i] = hd;
-      *wg_views += views;
+      atomicAdd(wg_views, (unsigned long long)views);
     }
-    __syncthreads();
+    wave_sync();
   }
 };
 
+__host__ __device__ constexpr size_t walk_group_lds_bytes() {
+  return kWalkLdsLog * 24 + 16 * 4 + kWalkMapWords * 4;
+}
+static size_t walk_group_scratch_bytes(const Geo& g) {
+  return ((size_t)(g.max_chain + 8) * 24 + 255) & ~(size_t)255;
+}
+
 template <int B, int H>
 __global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
+  constexpr int W = kWalkW;
+  constexpr int P = 64 / W;
   extern __shared__ uint64_t lds64[];
   __shared__ uint32_t win[2];
   __shared__ unsigned long long s_views;  // bins viewed by this workgroup's plans
+  const int lane = threadIdx.x;
+  const int gi = lane / W;
   const uint32_t cap = g.max_chain + 8;
-  WaveLog L;
-  L.key = lds64;
-  L.aux = lds64 + cap;
-  L.bin = (uint32_t*)(lds64 + 2 * cap);
-  L.sf = L.bin + cap;
-  L.last = (int*)(L.sf + cap);
-  L.misc = (uint32_t*)(L.last + 8);
-  if (threadIdx.x == 0) {
+  WalkLog L;
+  {
+    char* base = (char*)lds64 + (size_t)gi * walk_group_lds_bytes();
+    L.key = (uint64_t*)base;
+    L.aux = L.key + kWalkLdsLog;
+    L.bin = (uint32_t*)(L.aux + kWalkLdsLog);
+    L.sf = L.bin + kWalkLdsLog;
+    L.last = (int*)(L.sf + kWalkLdsLog);
+    L.misc = (uint32_t*)(L.last + 8);
+    L.wmap = L.misc + 8;
+    char* sc = (char*)r.wg_scratch + (size_t)blockIdx.x * r.wg_scratch_bytes +
+               (size_t)gi * (r.wg_scratch_bytes / P);
+    L.gkey = (uint64_t*)sc;
+    L.gaux = L.gkey + cap;
+    L.gbin = (uint32_t*)(L.gaux + cap);
+    L.gsf = L.gbin + cap;
+  }
+  if (lane == 0) {
     region_init(win, r.arena_cap);
     s_views = 0;
   }
-  __syncthreads();
-  EvictWork W;
-  W.init(r);
-  {
-    for (uint32_t k = 0;; ++k) {
-      const uint32_t i = W.item(k);
-      if (i == kNone) break;
-      const uint64_t x = r.keys[i];
-      const uint64_t xa = load_aux(r.vals, i, B);
-      WavePlanner<B, H> P(g, r, L, cap);
-      P.op = r.op_base + i;
-      P.T = tab_of(g, r.op_table, r.tdesc, i);
-      uint32_t h[H];
-      hash_key<H>(g, P.T, x, h);
-      uint32_t st;
-      if (g.scheme == CK_RATTLE) st = P.rattle(x, xa);
-      else if (g.scheme == CK_QUEUE) st = P.queue_kick(x, xa, h);
-      else st = P.random_walk(x, xa, h);
-      P.finish(i, st, 0, 0, win, &s_views);
+  wave_sync();
+  EvictWork Wk;
+  Wk.init(r);
+  // the group's op of batch kb is item kb + gi; item() is wave-uniform
+  auto batch_item = [&](uint32_t kb) -> uint32_t {
+    uint32_t mine = kNone;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const uint32_t v = Wk.item(kb + (uint32_t)p);
+      if (gi == p) mine = v;
     }
+    return mine;
+  };
+  // software-pipelined: the next batch's ops and keys are fetched while the
+  // current walks run
+  uint32_t i_nx = batch_item(0);
+  uint64_t x_nx = i_nx != kNone ? r.keys[i_nx] : 0ull;
+  for (uint32_t kb = 0;; kb += P) {
+    if (__ballot(i_nx != kNone) == 0) break;  // wave-uniform
+    const uint32_t i = i_nx;
+    const uint64_t x = x_nx;
+    i_nx = batch_item(kb + P);
+    if (i_nx != kNone) x_nx = r.keys[i_nx];
+    for (uint32_t j = lane % W; j < kWalkMapWords; j += W) L.wmap[j] = 0;
+    wave_sync();
+    if (i != kNone) {
+      const uint64_t xa = load_aux(r.vals, i, B);
+      WalkPlanner<B, H> Pl(g, r, L, cap);
+      Pl.op = r.op_base + i;
+      Pl.T = tab_of(g, r.op_table, r.tdesc, i);
+      uint32_t h[H];
+      hash_key<H>(g, Pl.T, x, h);
+      uint32_t st;
+      if (g.scheme == CK_RATTLE) st = Pl.rattle(x, xa);
+      else if (g.scheme == CK_QUEUE) st = Pl.queue_kick(x, xa, h);
+      else st = Pl.random_walk(x, xa, h);
+      Pl.finish(i, st, win, &s_views);
+    }
+    wave_sync();
   }
   if (threadIdx.x == 0 && s_views) r.wg_views[blockIdx.x] += s_views;
 }
@@ -860,26 +942,6 @@ static size_t search_group_lds_words() { return 3 * kSearchLdsRuns + 32; }
 static size_t search_group_scratch_bytes(const Geo& g) {
   const size_t RC = search_runs(g);
   return ((RC * g.B * (g.H - 1) + 5 * RC) * 4 + 255) & ~(size_t)255;
-}
-
-// Orders LDS and memory accesses of the lanes of one wavefront (the search
-// workgroups are single wavefronts, so this is a full workgroup barrier);
-// valid in divergent code.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-// Arena regions shared by the workgroup's searches.
-__device__ __forceinline__ uint32_t region_take(uint32_t* win, uint32_t n, Ctr* ctr) {
-  if (n == 0) return 0;
-  const uint32_t off = atomicAdd(&win[0], n);
-  if (off + n > win[1]) {
-    atomicOr(&ctr->overflow, 1u);
-    return kNone;
-  }
-  return off;
 }
 
 template <int B, int H>
@@ -1301,14 +1363,13 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
 size_t evict_lds_bytes(const Geo& g) {
   if (g.scheme == CK_BFS || g.scheme == CK_SORTED)
     return (64 / kSearchW) * search_group_lds_words() * 4 + 64;
-  const size_t cap = g.max_chain + 8;
-  return cap * 24 + 8 * 4 + 8 * 4 + 64;
+  return (64 / kWalkW) * walk_group_lds_bytes() + 64;
 }
 
 size_t evict_wg_scratch_bytes(const Geo& g) {
   if (g.scheme == CK_BFS || g.scheme == CK_SORTED)
     return (64 / kSearchW) * search_group_scratch_bytes(g);
-  return 256;
+  return (64 / kWalkW) * walk_group_scratch_bytes(g);
 }
 
 template <int B, int H>
