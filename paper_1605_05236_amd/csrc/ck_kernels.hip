@@ -1097,13 +1097,17 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
 #pragma unroll
     for (int j = 0; j < H; ++j) bks[j] = __shfl(bk, gb + j * B, 64);
     wave_sync();
-    if (have && sorted && gl == 0) {
+    uint32_t bmask = 0;  // sorted: non-empty buckets (group-uniform)
+    if (have && sorted) {
 #pragma unroll
       for (int j = 0; j < H; ++j) {
-        rnextL[j] = kNone;
-        if (btail[bks[j]] == kNone) bhead[bks[j]] = j * B;
-        else set_next(btail[bks[j]], j);
-        btail[bks[j]] = j;
+        if (gl == 0) {
+          rnextL[j] = kNone;
+          if (btail[bks[j]] == kNone) bhead[bks[j]] = j * B;
+          else set_next(btail[bks[j]], j);
+          btail[bks[j]] = j;
+        }
+        bmask |= 1u << bks[j];
       }
     }
     wave_sync();
@@ -1126,10 +1130,8 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
         my_e = head + (uint32_t)gl / C;
         my_j = (uint32_t)gl % C;
       } else {
-        int kb2 = -1;
-        for (int q = 0; q < 16; ++q)
-          if (bhead[q] != kNone) { kb2 = q; break; }
-        if (kb2 < 0) break;
+        if (bmask == 0) break;
+        const int kb2 = __ffs(bmask) - 1;
         uint32_t e = bhead[kb2];
         while (e != kNone && nu + C <= G) {
 #pragma unroll
@@ -1165,11 +1167,11 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
       for (uint32_t u = 0; u < nu && !done; u += C) {
         const uint32_t e = __shfl(my_e, gb + (int)u, 64);
         if (sorted) {
-          int kb2 = -1;
-          for (int q = 0; q < 16; ++q)
-            if (bhead[q] != kNone) { kb2 = q; break; }
+          const int kb2 = bmask ? __ffs(bmask) - 1 : -1;
           if (kb2 < 0 || bhead[kb2] != e) break;  // order changed: regroup
           wave_sync();
+          bool emptied = false;
+          if (((e + 1) & (B - 1)) == 0) emptied = rnext_at(e / B) == kNone;
           if (gl == 0) {
             if (((e + 1) & (B - 1)) != 0) {
               bhead[kb2] = e + 1;
@@ -1179,6 +1181,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
               if (nr == kNone) btail[kb2] = kNone;
             }
           }
+          if (emptied) bmask &= ~(1u << kb2);
           wave_sync();
         } else {
           ++head;
@@ -1234,6 +1237,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
               else set_next(btail[b2], run);
               btail[b2] = run;
             }
+            bmask |= 1u << b2;
             wave_sync();
           }
         }
