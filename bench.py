@@ -30,6 +30,36 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 
+# Measured HBM traffic of the eviction planners (k_plan_search, k_plan_walk)
+# per launch in the default fill workload: FETCH_SIZE + WRITE_SIZE from two
+# rocprofv3 --pmc runs of this benchmark (--steps 1 --warmup 1
+# --pmc-calibration), each scaled by its reading for a plain 256 MiB device
+# copy.  It describes the kernel source it was taken on; once that source
+# changes the benchmark reports null until the counters are taken again.
+MEASURED_EVICT_TRAFFIC = {
+    "kernels_sha256": "cfb5c2ff6e47ffea9a02147ec1f6fccd2b98f7cedcf58a011a9116b298161b3c",
+    "bytes_per_launch": 24756708,
+    "profile": "profiles/evict_planners__fill95_2e24x8.md",
+}
+
+
+def _kernels_sha256() -> str:
+    import hashlib
+    path = os.path.join(ROOT, "paper_1605_05236_amd", "csrc", "ck_kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def pmc_calibration_copies():
+    """Three plain device copies of 256 MiB (the yardstick of the HBM counters)."""
+    import torch
+    a = torch.ones(1 << 25, dtype=torch.int64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
 
 def parse():
     p = argparse.ArgumentParser()
@@ -48,6 +78,9 @@ def parse():
     p.add_argument("--lpp", type=int, default=0,
                    help="lookup lanes per probe (1 or slots per bin; 0 = slots per bin)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--pmc-calibration", action="store_true",
+                   help="first run three plain 256 MiB device copies (the yardstick "
+                        "for rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     p.add_argument("--cpu-bins-log2", type=int, default=19)
     p.add_argument("--workload", default="fill", choices=["fill", "group", "serve", "mixed", "dary"],
                    help="fill: one 2^24 x 8 table (default); group: 4096 tables of "
@@ -466,6 +499,8 @@ def main():
     from paper_1605_05236_amd.table import CuckooTable, as_device_keys
 
     torch.cuda.set_device(0)
+    if args.pmc_calibration:
+        pmc_calibration_copies()
     schemes = [s for s in args.schemes.split(",") if s]
     n, B = 1 << args.bins_log2, args.slots
     m = inputs.target_count(n, B, args.load)
@@ -593,10 +628,15 @@ def main():
         # its 4-byte metadata word; a launch's bytes are those of its plans' views
         per_view = B * 16 + 4
         ach = evict_views * per_view / (kt_ms / 1e3) / 1e9 if kt_ms else 0.0
+        traffic = None
+        if MEASURED_EVICT_TRAFFIC["kernels_sha256"] == _kernels_sha256():
+            traffic = MEASURED_EVICT_TRAFFIC["bytes_per_launch"]
         roofline = {"bound": "hbm", "kernel": "k_plan_search<8,2> (bfs, sorted) / "
                                               "k_plan_walk<8,2> (queue)",
                     "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": ach / PEAK_HBM_GBS, "traffic": None,
+                    "frac": ach / PEAK_HBM_GBS, "traffic": traffic,
+                    "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+                    "algorithmic_bytes_per_launch": evict_views * per_view / max(1, kt_launch),
                     "bytes_per_view": per_view, "views_per_step": evict_views / args.steps,
                     "launches_per_step": kt_launch / args.steps,
                     "avg_launch_us": kt_ms * 1e3 / max(1, kt_launch)}
