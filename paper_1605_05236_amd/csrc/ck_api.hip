@@ -96,7 +96,6 @@ struct ck_table {
   uint32_t evict_grid = 0;
   DevStats* dstats = nullptr;
   uint32_t* block_tmp = nullptr;
-  uint32_t* comp_tmp = nullptr;
   uint8_t* req = nullptr;
   // host-side counters
   uint64_t rounds = 0, lookups = 0;
@@ -162,7 +161,6 @@ void free_scratch(ck_table* t) {
   (void)hipFree(t->wg_views);
   (void)hipFree(t->dstats);
   (void)hipFree(t->block_tmp);
-  (void)hipFree(t->comp_tmp);
   (void)hipFree(t->req);
 }
 
@@ -203,7 +201,6 @@ ck_status alloc_scratch(ck_table* t) {
   HIP_TRY(hipMemset(t->dstats, 0, sizeof(DevStats)));
   const uint32_t nb = (m + 1023) / 1024;
   HIP_TRY(dalloc(&t->block_tmp, ((nb + 63) & ~63u) + 16));
-  HIP_TRY(dalloc(&t->comp_tmp, nb + 64));
   HIP_TRY(dalloc(&t->req, m));
   return CK_OK;
 }
@@ -295,7 +292,6 @@ ck_status run_rounds(ck_table* t, Round& r, uint64_t m, hipStream_t s) {
       r.spawn_cap = t->spawn_cap;
       r.req = t->req;
       hipEvent_t ev;
-      HIP_TRY(launch_round_begin(t->ctr, s));
       if (r.is_delete) {
         ev = T.begin(s, TK_DELETE);
         HIP_TRY(launch_plan_delete(t->g, r, s));
@@ -315,7 +311,7 @@ ck_status run_rounds(ck_table* t, Round& r, uint64_t m, hipStream_t s) {
       HIP_TRY(launch_commit(t->g, r, s));
       T.end(TK_COMMIT, ev, s);
       ev = T.begin(s, TK_COMPACT);
-      HIP_TRY(launch_compact(r, r.next, r.next_count, t->comp_tmp, s));
+      HIP_TRY(launch_compact(r, r.next, r.next_count, s));
       T.end(TK_COMPACT, ev, s);
       cur ^= 1;
     }

@@ -69,7 +69,7 @@ __host__ __device__ inline uint32_t hdr_pack(uint32_t status, uint32_t twins, ui
 
 struct Ctr {             // device counters of the round loop
   uint32_t pending[2];   // pending ops of the round of parity p (written by compaction)
-  uint32_t evict_count;  // ops of this round that need an eviction plan
+  uint32_t unused;
   uint32_t overflow;     // a planner ran out of arena this round (round is void)
   uint32_t overflow_seen;  // sticky: some round since the host last looked was void
   uint32_t rounds;       // rounds that committed (not void, ops pending)
@@ -148,7 +148,6 @@ hipError_t launch_init(const Geo& g, hipStream_t s);
 hipError_t launch_lookup(const Geo& g, const uint64_t* keys, uint64_t n, void* vals_out,
                          uint8_t* found, uint32_t lpp, DevStats* st, const uint32_t* op_table,
                          const uint2* tdesc, hipStream_t s);
-hipError_t launch_round_begin(Ctr* c, hipStream_t s);
 hipError_t launch_batch_begin(uint64_t m, uint32_t* pend, uint32_t* views, uint32_t* lost,
                               uint32_t* kicks, uint32_t* retries, uint32_t* twins, Ctr* c, hipStream_t s);
 hipError_t launch_plan_fresh(const Geo& g, const Round& r, hipStream_t s);
@@ -157,8 +156,7 @@ hipError_t launch_plan_delete(const Geo& g, const Round& r, hipStream_t s);
 hipError_t launch_commit(const Geo& g, const Round& r, hipStream_t s);
 // Ordered compaction of the pending list into `out` (keeps positions p with
 // req[p] set); the length goes to *count.
-hipError_t launch_compact(const Round& r, uint32_t* out, uint32_t* count, uint32_t* tmp,
-                          hipStream_t s);
+hipError_t launch_compact(const Round& r, uint32_t* out, uint32_t* count, hipStream_t s);
 hipError_t launch_batch_stats(const Round& r, uint64_t m, uint64_t slots, uint32_t* block_tmp,
                               uint32_t is_delete, hipStream_t s);
 size_t evict_lds_bytes(const Geo& g);

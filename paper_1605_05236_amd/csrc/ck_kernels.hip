@@ -257,16 +257,15 @@ hipError_t launch_lookup(const Geo& g, const uint64_t* keys, uint64_t n, void* o
 // ---------------------------------------------------------------------------
 // round bookkeeping
 // ---------------------------------------------------------------------------
-__global__ void k_round_begin(Ctr* c) {
-  if (threadIdx.x == 0) {
-    if (c->overflow) c->overflow_seen = 1;
-    c->evict_count = 0;
-    c->overflow = 0;
-  }
-}
-hipError_t launch_round_begin(Ctr* c, hipStream_t s) {
-  hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(64), 0, s, c);
-  return hipGetLastError();
+// Round start, done by one thread of the round's first kernel (the fresh or
+// delete planner): an arena overflow of the previous round is remembered for
+// the host and cleared, and the count this round's compaction accumulates
+// into is zeroed (no kernel of this round reads it before the compaction).
+__device__ __forceinline__ void round_start(const Round& r) {
+  Ctr* c = r.ctr;
+  if (c->overflow) c->overflow_seen = 1;
+  c->overflow = 0;
+  *r.next_count = 0;
 }
 
 __global__ void k_batch_begin(uint64_t m, uint32_t* pend, uint32_t* views, uint32_t* lost,
@@ -330,6 +329,7 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
   G.lane = threadIdx.x & 63;
   G.sl = G.lane % B;
   G.gshift = G.lane - G.sl;
+  if (blockIdx.x == 0 && threadIdx.x == 0) round_start(r);
   const uint64_t gidx = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / B;
   const bool active = gidx < npend_of(r);
   const uint32_t i = active ? r.pend[gidx] : 0u;
@@ -1426,6 +1426,7 @@ __global__ __launch_bounds__(256) void k_plan_delete(Geo g, Round r) {
   G.lane = threadIdx.x & 63;
   G.sl = G.lane % B;
   G.gshift = G.lane - G.sl;
+  if (blockIdx.x == 0 && threadIdx.x == 0) round_start(r);
   const uint64_t gidx = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / B;
   if (gidx >= npend_of(r)) return;
   const uint32_t i = r.pend[gidx];
@@ -1629,10 +1630,14 @@ hipError_t launch_commit(const Geo& g, const Round& r, hipStream_t s) {
 // evict list and the next round's pending list, in op order, without any
 // shared counter
 // ---------------------------------------------------------------------------
-constexpr int kCompPer = 4;                // positions per thread
-constexpr int kCompTile = 256 * kCompPer;  // positions per block
-
-__device__ __forceinline__ bool keep_pos(const Round& r, uint32_t p) { return r.req[p] != 0; }
+// The next round's pending list: the ops whose commit flagged them to go
+// again.  The order of the list is immaterial (every kernel's result for an
+// op depends on the op, never on its position), so one launch does it: each
+// block takes 4096 flags (16 per thread), scans them, reserves its output
+// range with one atomic add on the count (a few hundred per launch at most)
+// and writes its ops.  The count was zeroed at the start of the round.
+constexpr int kCompPer = 16;                // flags per thread
+constexpr int kCompTile = 256 * kCompPer;   // flags per block
 
 __device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
 #pragma unroll
@@ -1640,114 +1645,51 @@ __device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
   return v;
 }
 
-__global__ __launch_bounds__(256) void k_compact_count(Round r, uint32_t* cnt) {
+__global__ __launch_bounds__(256) void k_compact(Round r, uint32_t* out, uint32_t* count) {
   __shared__ uint32_t ws[4];
+  __shared__ uint32_t s_base;
   const uint32_t n = npend_of(r);
   const uint32_t base = blockIdx.x * kCompTile + threadIdx.x * kCompPer;
-  uint32_t c = 0;
+  uint32_t bits = 0;
+  if (base + kCompPer <= n) {
+    const uint4 f = *(const uint4*)(r.req + base);  // 16 flag bytes, 16-byte aligned
+    const uint32_t w[4] = {f.x, f.y, f.z, f.w};
 #pragma unroll
-  for (int k = 0; k < kCompPer; ++k)
-    if (base + k < n && keep_pos(r, base + k)) ++c;
-  c = wave_sum32(c);
-  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = c;
-  __syncthreads();
-  if (threadIdx.x == 0) cnt[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
-}
-
-// one block: exclusive scan of a[0..n) in place, total to *total
-__global__ __launch_bounds__(1024) void k_scan_excl(uint32_t* a, uint32_t n, uint32_t* total) {
-  __shared__ uint32_t carry;
-  __shared__ uint32_t wsum[16];
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
-  for (uint32_t base = 0; base < n; base += 1024) {
-    const uint32_t idx = base + threadIdx.x;
-    const uint32_t v = idx < n ? a[idx] : 0;
-    uint32_t x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t y = __shfl_up(x, o, 64);
-      if (lane >= o) x += y;
-    }
-    if (lane == 63) wsum[threadIdx.x >> 6] = x;
-    __syncthreads();
-    uint32_t wpre = 0;
-    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wpre += wsum[w];
-    const uint32_t excl = carry + wpre + x - v;
-    __syncthreads();
-    if (idx < n) a[idx] = excl;
-    if (threadIdx.x == 1023) carry = excl + v;
-    __syncthreads();
+    for (int k = 0; k < kCompPer; ++k)
+      if ((w[k >> 2] >> ((k & 3) * 8)) & 0xFFu) bits |= 1u << k;
+  } else {
+    for (int k = 0; k < kCompPer; ++k)
+      if (base + k < n && r.req[base + k]) bits |= 1u << k;
   }
-  if (threadIdx.x == 0) *total = carry;
-}
-
-__global__ __launch_bounds__(256) void k_compact_scatter(Round r, const uint32_t* pre,
-                                                         uint32_t* out) {
-  __shared__ uint32_t ws[4];
-  const uint32_t n = npend_of(r);
-  const uint32_t base = blockIdx.x * kCompTile + threadIdx.x * kCompPer;
-  bool kk[kCompPer];
-  uint32_t c = 0;
-#pragma unroll
-  for (int k = 0; k < kCompPer; ++k) {
-    kk[k] = base + k < n && keep_pos(r, base + k);
-    c += kk[k] ? 1 : 0;
-  }
-  const int lane = threadIdx.x & 63;
+  const uint32_t c = __popc(bits);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   uint32_t x = c;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
     const uint32_t y = __shfl_up(x, o, 64);
     if (lane >= o) x += y;
   }
-  if (lane == 63) ws[threadIdx.x >> 6] = x;
+  if (lane == 63) ws[wv] = x;
   __syncthreads();
   uint32_t wpre = 0;
-  for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wpre += ws[w];
-  uint32_t pos = pre[blockIdx.x] + wpre + x - c;
-#pragma unroll
-  for (int k = 0; k < kCompPer; ++k)
-    if (kk[k]) out[pos++] = r.pend[base + k];
-}
-
-// Small lists (the later rounds of a sub-batch): one workgroup does it all.
-__global__ __launch_bounds__(1024) void k_compact_small(Round r, uint32_t* out, uint32_t* count) {
-  __shared__ uint32_t wsum[16];
-  __shared__ uint32_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const uint32_t n = npend_of(r);
-  for (uint32_t base = 0; base < n; base += 1024) {
-    const uint32_t p = base + threadIdx.x;
-    const bool keep = p < n && keep_pos(r, p);
-    const uint64_t b = __ballot(keep);
-    if (lane == 0) wsum[threadIdx.x >> 6] = (uint32_t)__popcll(b);
-    __syncthreads();
-    uint32_t pre = carry;
-    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) pre += wsum[w];
-    if (keep) out[pre + __popcll(b & ((1ull << lane) - 1))] = r.pend[p];
-    __syncthreads();
-    if (threadIdx.x == 0)
-      for (int w = 0; w < 16; ++w) carry += wsum[w];
-    __syncthreads();
+  for (int w = 0; w < wv; ++w) wpre += ws[w];
+  if (threadIdx.x == 0) {
+    const uint32_t tot = ws[0] + ws[1] + ws[2] + ws[3];
+    s_base = tot ? atomicAdd(count, tot) : 0u;
   }
-  if (threadIdx.x == 0) *count = carry;
+  __syncthreads();
+  uint32_t pos = s_base + wpre + x - c;
+  while (bits) {
+    const int k = __ffs(bits) - 1;
+    bits &= bits - 1;
+    out[pos++] = r.pend[base + k];
+  }
 }
 
-hipError_t launch_compact(const Round& r, uint32_t* out, uint32_t* count, uint32_t* tmp,
-                          hipStream_t s) {
+hipError_t launch_compact(const Round& r, uint32_t* out, uint32_t* count, hipStream_t s) {
   const uint32_t nb = (r.npend + kCompTile - 1) / kCompTile;
   if (nb == 0) return hipSuccess;
-  if (r.npend <= 16 * 1024) {
-    hipLaunchKernelGGL(k_compact_small, dim3(1), dim3(1024), 0, s, r, out, count);
-    return hipGetLastError();
-  }
-  hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(256), 0, s, r, tmp);
-  hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, tmp, nb, count);
-  hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(256), 0, s, r, tmp, out);
+  hipLaunchKernelGGL(k_compact, dim3(nb), dim3(256), 0, s, r, out, count);
   return hipGetLastError();
 }
 
