@@ -269,7 +269,9 @@ ck_status run_rounds(ck_table* t, Round& r, uint64_t m, hipStream_t s) {
   // adds a few void rounds.  Anything beyond that is a fault, not progress.
   uint64_t guard = 2 * m + 64;
   Timer& T = t->timer;
-  // ctr->rounds and ctr->overflow_seen were cleared by k_batch_begin
+  // the first round's planner clears ctr->rounds and ctr->overflow_seen and
+  // the ops' counters; its pending list is the identity (no list is read)
+  bool first = true;
   while (npend > 0) {
     if (guard == 0) return CK_EDEVICE;
     const int K = npend <= kTailOps ? kTailRounds : 1;
@@ -291,6 +293,8 @@ ck_status run_rounds(ck_table* t, Round& r, uint64_t m, hipStream_t s) {
       r.spawns = t->spawns;
       r.spawn_cap = t->spawn_cap;
       r.req = t->req;
+      r.first = first ? 1u : 0u;
+      first = false;
       hipEvent_t ev;
       if (r.is_delete) {
         ev = T.begin(s, TK_DELETE);
@@ -345,7 +349,6 @@ ck_status run_batches(ck_table* t, const uint64_t* keys, const void* vals, uint6
     Round r = make_round(t, keys + b0, vals ? (const char*)vals + b0 * vb : nullptr,
                          status + b0, ops, t->insert_count + b0, is_delete,
                          op_table ? op_table + b0 : nullptr, tdesc);
-    HIP_TRY(launch_batch_begin(m, t->pend[0], ops[0], ops[1], ops[2], ops[3], ops[4], t->ctr, s));
     ck_status st = run_rounds(t, r, m, s);
     if (st != CK_OK) return st;
     hipEvent_t ev = t->timer.begin(s, TK_STATS);

@@ -137,6 +137,7 @@ struct Round {
   uint32_t* op_twins;
   uint32_t max_rounds;
   uint32_t is_delete;
+  uint32_t first;            // first round of the sub-batch: pend[p] = p, counters unset
   unsigned long long* wg_views;  // per eviction workgroup: bins viewed (cumulative)
   void* wg_scratch;          // per-workgroup scratch of the eviction planners
   uint32_t wg_scratch_bytes;
@@ -148,8 +149,6 @@ hipError_t launch_init(const Geo& g, hipStream_t s);
 hipError_t launch_lookup(const Geo& g, const uint64_t* keys, uint64_t n, void* vals_out,
                          uint8_t* found, uint32_t lpp, DevStats* st, const uint32_t* op_table,
                          const uint2* tdesc, hipStream_t s);
-hipError_t launch_batch_begin(uint64_t m, uint32_t* pend, uint32_t* views, uint32_t* lost,
-                              uint32_t* kicks, uint32_t* retries, uint32_t* twins, Ctr* c, hipStream_t s);
 hipError_t launch_plan_fresh(const Geo& g, const Round& r, hipStream_t s);
 hipError_t launch_plan_evict(const Geo& g, const Round& r, uint32_t grid, hipStream_t s);
 hipError_t launch_plan_delete(const Geo& g, const Round& r, hipStream_t s);

@@ -261,38 +261,26 @@ hipError_t launch_lookup(const Geo& g, const uint64_t* keys, uint64_t n, void* o
 // delete planner): an arena overflow of the previous round is remembered for
 // the host and cleared, and the count this round's compaction accumulates
 // into is zeroed (no kernel of this round reads it before the compaction).
+// The first round of a sub-batch also resets the sub-batch's counters; its
+// pending list is every op in order, so position and op index coincide.
 __device__ __forceinline__ void round_start(const Round& r) {
   Ctr* c = r.ctr;
+  if (r.first) {  // a new sub-batch
+    c->rounds = 0;
+    c->overflow_seen = 0;
+  }
   if (c->overflow) c->overflow_seen = 1;
   c->overflow = 0;
   *r.next_count = 0;
 }
+__device__ __forceinline__ void zero_op_counters(const Round& r, uint32_t i) {
+  r.op_views[i] = 0;
+  r.op_lost[i] = 0;
+  r.op_kicks[i] = 0;
+  r.op_retries[i] = 0;
+  r.op_twins[i] = 0;
+}
 
-__global__ void k_batch_begin(uint64_t m, uint32_t* pend, uint32_t* views, uint32_t* lost,
-                              uint32_t* kicks, uint32_t* retries, uint32_t* twins, Ctr* c) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {  // the sub-batch's round counters
-    c->rounds = 0;
-    c->overflow_seen = 0;
-  }
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
-    pend[i] = (uint32_t)i;
-    views[i] = 0;
-    lost[i] = 0;
-    kicks[i] = 0;
-    retries[i] = 0;
-    twins[i] = 0;
-  }
-}
-hipError_t launch_batch_begin(uint64_t m, uint32_t* pend, uint32_t* views, uint32_t* lost,
-                              uint32_t* kicks, uint32_t* retries, uint32_t* twins, Ctr* c,
-                              hipStream_t s) {
-  uint32_t grid = (uint32_t)std::min<uint64_t>((m + 255) / 256, 4096);
-  if (grid == 0) grid = 1;
-  hipLaunchKernelGGL(k_batch_begin, dim3(grid), dim3(256), 0, s, m, pend, views, lost, kicks,
-                     retries, twins, c);
-  return hipGetLastError();
-}
 
 // ---------------------------------------------------------------------------
 // plan emission helpers (called by one lane)
@@ -332,7 +320,8 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
   if (blockIdx.x == 0 && threadIdx.x == 0) round_start(r);
   const uint64_t gidx = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / B;
   const bool active = gidx < npend_of(r);
-  const uint32_t i = active ? r.pend[gidx] : 0u;
+  const uint32_t i = active ? (r.first ? (uint32_t)gidx : r.pend[gidx]) : 0u;
+  if (r.first && active && (threadIdx.x % B) == 0) zero_op_counters(r, i);
   const uint64_t x = active ? r.keys[i] : kEmpty;
   const bool leader = G.sl == 0;
   const bool bad = x == kEmpty;  // reserved key: rejected, no plan
@@ -1429,7 +1418,8 @@ __global__ __launch_bounds__(256) void k_plan_delete(Geo g, Round r) {
   if (blockIdx.x == 0 && threadIdx.x == 0) round_start(r);
   const uint64_t gidx = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / B;
   if (gidx >= npend_of(r)) return;
-  const uint32_t i = r.pend[gidx];
+  const uint32_t i = r.first ? (uint32_t)gidx : r.pend[gidx];
+  if (r.first && G.sl == 0) zero_op_counters(r, i);
   const uint64_t x = r.keys[i];
   const bool leader = G.sl == 0;
   uint32_t mb[2], ms[2];
@@ -1513,7 +1503,7 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
   const int gshift = lane & ~(CL - 1);
   const uint64_t gidx = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / CL;
   if (gidx >= npend_of(r)) return;
-  const uint32_t i = r.pend[gidx];
+  const uint32_t i = r.first ? (uint32_t)gidx : r.pend[gidx];
   const bool leader = gl == 0;
   // set by an earlier kernel: a plain load, once per wavefront, broadcast
   const int first = __ffsll((unsigned long long)__ballot(true)) - 1;
@@ -1682,7 +1672,7 @@ __global__ __launch_bounds__(256) void k_compact(Round r, uint32_t* out, uint32_
   while (bits) {
     const int k = __ffs(bits) - 1;
     bits &= bits - 1;
-    out[pos++] = r.pend[base + k];
+    out[pos++] = r.first ? base + k : r.pend[base + k];
   }
 }
 
