@@ -941,7 +941,8 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
   constexpr uint32_t G = W / B;   // bins per group-wide load
   constexpr uint32_t RB = H * B;  // root records
   constexpr uint32_t RL = kSearchLdsRuns;
-  static_assert(RB <= (uint32_t)W && G >= C, "search group too narrow");
+  constexpr int RBW = (int)((RB + W - 1) / W);  // root records per lane
+  static_assert(G >= C, "search group too narrow");
   extern __shared__ uint32_t lds32[];
   __shared__ uint32_t win[4];  // arena region, spawn region
   __shared__ unsigned long long s_views;  // bins viewed by this workgroup's plans
@@ -1013,20 +1014,27 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
   uint32_t h_nx[H];
 #pragma unroll
   for (int j = 0; j < H; ++j) h_nx[j] = 0;
-  uint64_t rk_nx = kEmpty;  // next op's root slot (group lanes < H*B)
-  uint32_t rm_nx = 0;       // its bin's metadata word (sorted)
+  // next op's root slots: root record e = gl + s W in lane gl, slot s
+  uint64_t rk_nx[RBW];
+  uint32_t rm_nx[RBW];  // their bins' metadata words (sorted)
+#pragma unroll
+  for (int t = 0; t < RBW; ++t) { rk_nx[t] = kEmpty; rm_nx[t] = 0; }
   auto fetch_roots = [&]() {
     if (i_nx == kNone) return;
     T_nx = tab_of(g, r.op_table, r.tdesc, i_nx);
     hash_key<H>(g, T_nx, x_nx, h_nx);
-    if (gl < (int)RB) {
-      const int q = gl / B, sl = gl % B;
-      uint32_t hb = h_nx[0];
 #pragma unroll
-      for (int j = 1; j < H; ++j)
-        if (q == j) hb = h_nx[j];
-      rk_nx = g.slots[(uint64_t)hb * B + sl].x;
-      if (sorted) rm_nx = g.meta[hb];
+    for (int t = 0; t < RBW; ++t) {
+      const int e = gl + t * W;
+      if (e < (int)RB) {
+        const int q = e / B, sl = e % B;
+        uint32_t hb = h_nx[0];
+#pragma unroll
+        for (int j = 1; j < H; ++j)
+          if (q == j) hb = h_nx[j];
+        rk_nx[t] = g.slots[(uint64_t)hb * B + sl].x;
+        if (sorted) rm_nx[t] = g.meta[hb];
+      }
     }
   };
   if (i_nx != kNone) x_nx = r.keys[i_nx];
@@ -1039,35 +1047,42 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
     uint32_t h[H];
 #pragma unroll
     for (int j = 0; j < H; ++j) h[j] = h_nx[j];
-    const uint64_t rkey = rk_nx;
-    const uint32_t rmeta = rm_nx;
+    uint64_t rkey[RBW];
+    uint32_t rmeta[RBW];
+#pragma unroll
+    for (int t = 0; t < RBW; ++t) { rkey[t] = rk_nx[t]; rmeta[t] = rm_nx[t]; }
     i_nx = batch_item(kb + P);
     if (i_nx != kNone) x_nx = r.keys[i_nx];
     // ops reach this planner after the fresh planner found no room in the
     // same snapshot: first fit viewed all H bins, ghost inserts both bins
     uint32_t views = g.ghost ? 2u : (uint32_t)H;
     // ---- root runs: the key's own bins (slots already fetched, H*B lanes)
-    uint32_t rc[C];
+    uint32_t rc[RBW][C];  // root record e's candidates: lane e % W, rc[e / W]
+    uint32_t bk[RBW];
 #pragma unroll
-    for (int j = 0; j < (int)C; ++j) rc[j] = 0;
-    uint32_t bk = 0;
-    if (have && gl < (int)RB) {
-      const int q = gl / B;
-      uint32_t hb = h[0];
+    for (int t2 = 0; t2 < RBW; ++t2) {
+      bk[t2] = 0;
 #pragma unroll
-      for (int j = 1; j < H; ++j)
-        if (q == j) hb = h[j];
-      if (sorted) bk = min(15u, (rmeta >> 8) & 0xFu);
-      uint32_t hv[H];
-      hash_key<H>(g, T, rkey, hv);
-      uint32_t o = 0;
+      for (int j = 0; j < (int)C; ++j) rc[t2][j] = 0;
+      const int e = gl + t2 * W;
+      if (have && e < (int)RB) {
+        const int q = e / B;
+        uint32_t hb = h[0];
 #pragma unroll
-      for (int j = 0; j < H; ++j) {
-        if (hv[j] == hb) continue;
+        for (int j = 1; j < H; ++j)
+          if (q == j) hb = h[j];
+        if (sorted) bk[t2] = min(15u, (rmeta[t2] >> 8) & 0xFu);
+        uint32_t hv[H];
+        hash_key<H>(g, T, rkey[t2], hv);
+        uint32_t o = 0;
 #pragma unroll
-        for (int t = 0; t < (int)C; ++t)
-          if (t == (int)o) rc[t] = hv[j];
-        ++o;
+        for (int j = 0; j < H; ++j) {
+          if (hv[j] == hb) continue;
+#pragma unroll
+          for (int t = 0; t < (int)C; ++t)
+            if (t == (int)o) rc[t2][t] = hv[j];
+          ++o;
+        }
       }
     }
     if (have && gl < H) {
@@ -1082,9 +1097,17 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
       bhead[j] = kNone;
       btail[j] = kNone;
     }
-    uint32_t bks[H];
+    uint32_t bks[H];  // root run j's bucket: from root record j B
 #pragma unroll
-    for (int j = 0; j < H; ++j) bks[j] = __shfl(bk, gb + j * B, 64);
+    for (int j = 0; j < H; ++j) {
+      uint32_t v = 0;
+#pragma unroll
+      for (int t2 = 0; t2 < RBW; ++t2) {
+        const uint32_t u = __shfl(bk[t2], gb + (j * B) % W, 64);
+        if (t2 == (j * B) / W) v = u;
+      }
+      bks[j] = v;
+    }
     wave_sync();
     uint32_t bmask = 0;  // sorted: non-empty buckets (group-uniform)
     if (have && sorted) {
@@ -1138,9 +1161,12 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
       // ---- candidate bins (root records from registers), then contents
       uint32_t rv = 0;
 #pragma unroll
-      for (int t = 0; t < (int)C; ++t) {
-        const uint32_t v = __shfl(rc[t], gb + (int)min(my_e, (uint32_t)W - 1), 64);
-        if ((uint32_t)t == my_j) rv = v;
+      for (int t2 = 0; t2 < RBW; ++t2) {
+#pragma unroll
+        for (int t = 0; t < (int)C; ++t) {
+          const uint32_t v = __shfl(rc[t2][t], gb + (int)(my_e % W), 64);
+          if ((uint32_t)t == my_j && my_e / W == (uint32_t)t2) rv = v;
+        }
       }
       uint32_t cu = 0;
       if ((uint32_t)gl < nu) cu = my_e < RB ? rv : cand(my_e * C + my_j);
