@@ -46,23 +46,28 @@ struct IMove {           // 8 bytes
   uint32_t bin;
   uint32_t sf;           // slot | flags << 8
 };
-constexpr uint32_t kInline = 0xFFFFFFFEu;  // PlanHdr::off of a plan with inline moves
 
 enum : uint32_t { PL_FAIL = 0, PL_OK = 1, PL_EVICT = 2, PL_NOTFOUND = 3 };
 
 // Plan of one op of the sub-batch (32 bytes, one load in the commit kernel).
 // Plans of at most three moves that write only the op's own record keep them
 // inline: the first here, the others in the per-op inline array.
+// A plan's header, 32 bytes in two halves.  Inline plans (fresh placements,
+// deletes) are written and read as the first half only:
+//   {st, views, first move's bin, first move's slot | flags << 8}.
+// Arena plans (kick-out chains) set kHdrArena in st and use both halves:
+//   {st, views, arena offset of the moves, kicks}, {n_spawn, spawn_off, -, -}.
 struct PlanHdr {
-  uint32_t st;           // status | twins << 4 | n_moves << 8
+  uint32_t st;           // status | twins << 4 | n_moves << 8 | kHdrArena
   uint32_t views;
-  uint32_t kicks;
-  uint32_t off;          // arena offset of the moves, or kInline
-  uint32_t n_spawn;
-  uint32_t spawn_off;    // spawn arena offset (sorted search)
-  IMove mv0;             // first move when inline
+  uint32_t a;            // inline: first move's bin; arena: arena offset
+  uint32_t b;            // inline: first move's slot | flags << 8; arena: kicks
+  uint32_t n_spawn;      // arena plans: spawn list length (sorted search)
+  uint32_t spawn_off;    //              and its spawn arena offset
+  uint32_t pad[2];
 };
-constexpr uint32_t kExtraInline = 2;  // inline moves beyond mv0, per op
+constexpr uint32_t kHdrArena = 1u << 28;
+constexpr uint32_t kExtraInline = 2;  // inline moves beyond the first, per op
 __host__ __device__ inline uint32_t hdr_pack(uint32_t status, uint32_t twins, uint32_t nm) {
   return status | (twins << 4) | (nm << 8);
 }

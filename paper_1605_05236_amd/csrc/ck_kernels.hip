@@ -414,12 +414,8 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
     if (threadIdx.x == 0) r.evict_cnt[blockIdx.x] = s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
   }
   if (!active || !leader) return;
-  PlanHdr hd{};
-  hd.st = hdr_pack(bad ? PL_FAIL : (placed ? PL_OK : PL_EVICT), twins, nm);
-  hd.views = views;
-  hd.off = kInline;
-  hd.mv0 = IMove{b0, f0};
-  r.hdr[i] = hd;
+  ((uint4*)r.hdr)[2 * (size_t)i] =
+      make_uint4(hdr_pack(bad ? PL_FAIL : (placed ? PL_OK : PL_EVICT), twins, nm), views, b0, f0);
   if (!placed) return;
   if (nm > 0) claim(g, r, b0, i);
   if (nm > 1) {
@@ -803,10 +799,10 @@ struct WalkPlanner {
     }
     if (gl == 0) {
       PlanHdr hd{};
-      hd.st = hdr_pack(status, status == PL_OK ? twins : 0, nm);
+      hd.st = hdr_pack(status, status == PL_OK ? twins : 0, nm) | kHdrArena;
       hd.views = views;
-      hd.kicks = status == PL_OK ? kicks : 0;
-      hd.off = off;
+      hd.a = off;
+      hd.b = status == PL_OK ? kicks : 0;
       hd.n_spawn = 0;
       hd.spawn_off = 0;
       r.hdr[i] = hd;
@@ -1365,10 +1361,10 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
     }
     if (have && gl == 0) {
       PlanHdr hd{};
-      hd.st = hdr_pack(found ? PL_OK : PL_FAIL, twin, nm);
+      hd.st = hdr_pack(found ? PL_OK : PL_FAIL, twin, nm) | kHdrArena;
       hd.views = views;
-      hd.kicks = found ? depth : 0;
-      hd.off = off;
+      hd.a = off;
+      hd.b = found ? depth : 0;
       hd.n_spawn = nsp;
       hd.spawn_off = soff;
       r.hdr[i] = hd;
@@ -1479,12 +1475,9 @@ __global__ __launch_bounds__(256) void k_plan_delete(Geo g, Round r) {
     }
   }
   if (!leader) return;
-  PlanHdr hd{};
-  hd.st = hdr_pack(x == kEmpty ? PL_FAIL : status, 0, nm);
-  hd.views = probes;
-  hd.off = kInline;
-  if (nm > 0) hd.mv0 = IMove{mb[0], ms[0] | ((uint32_t)MV_CLEAR << 8)};
-  r.hdr[i] = hd;
+  ((uint4*)r.hdr)[2 * (size_t)i] =
+      make_uint4(hdr_pack(x == kEmpty ? PL_FAIL : status, 0, nm), probes, nm > 0 ? mb[0] : 0u,
+                 nm > 0 ? (ms[0] | ((uint32_t)MV_CLEAR << 8)) : 0u);
   if (nm > 0) claim(g, r, mb[0], i);
   if (nm > 1) {
     r.imv[(size_t)i * kExtraInline] = IMove{mb[1], ms[1] | ((uint32_t)MV_CLEAR << 8)};
@@ -1542,10 +1535,19 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
   if (void_round) {  // a planner ran out of arena: nothing of this round applies
     requeue = true;
   } else {
-    const PlanHdr h = r.hdr[i];
-    const uint32_t status = h.st & 0xF, twins = (h.st >> 4) & 0xF, nmv = h.st >> 8;
-    const bool inl = h.off == kInline;
-    const uint32_t off = h.off, mv0_bin = h.mv0.bin, mv0_sf = h.mv0.sf;
+    // the header's first half; its second half only for arena plans
+    const uint4 h0 = ((const uint4*)r.hdr)[2 * (size_t)i];
+    const uint32_t status = h0.x & 0xF, twins = (h0.x >> 4) & 0xF, nmv = (h0.x >> 8) & 0xFFFFF;
+    const bool inl = (h0.x & kHdrArena) == 0;
+    const uint32_t h_views = h0.y;
+    const uint32_t off = h0.z, mv0_bin = h0.z, mv0_sf = h0.w;
+    const uint32_t h_kicks = inl ? 0u : h0.w;
+    uint32_t h_nsp = 0, h_soff = 0;
+    if (!inl) {
+      const uint4 h1 = ((const uint4*)r.hdr)[2 * (size_t)i + 1];
+      h_nsp = h1.x;
+      h_soff = h1.y;
+    }
     const uint64_t x = r.keys[i];
     const uint64_t xa = (inl && r.vals) ? load_aux(r.vals, i, g.B) : 0;
     // move j of the plan: bin, slot, flags and the record it writes
@@ -1610,12 +1612,12 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
         else if (r.is_delete) st = status == PL_OK ? CK_OP_OK : CK_OP_NOT_FOUND;
         else st = status == PL_OK ? CK_OP_OK : CK_OP_FAIL_CHAIN;
         r.status[i] = st;
-        r.op_views[i] = h.views;
-        if (h.kicks) r.op_kicks[i] = h.kicks;
+        r.op_views[i] = h_views;
+        if (h_kicks) r.op_kicks[i] = h_kicks;
         if (twins) r.op_twins[i] = twins;
       }
     } else if (leader) {
-      r.op_lost[i] += h.views;
+      r.op_lost[i] += h_views;
       const uint32_t rt = r.op_retries[i] + 1;
       r.op_retries[i] = rt;
       if (r.max_rounds && rt >= r.max_rounds) {
@@ -1625,8 +1627,8 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
         requeue = true;
       }
     }
-    n_spawn = h.n_spawn;
-    spawn_off = h.spawn_off;
+    n_spawn = h_nsp;
+    spawn_off = h_soff;
   }
   if (leader) r.req[gidx] = requeue ? 1 : 0;
   // spawn counts (Sec. 5) of every plan, committed or not, saturating at 15
@@ -1796,7 +1798,17 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
   const uint32_t t_end = min(ntiles, (blockIdx.x + 1) * per);
   for (uint32_t tile = blockIdx.x * per; tile < t_end; ++tile) {
     const uint64_t i = (uint64_t)tile * kStatBlock + threadIdx.x;
-    const uint8_t s = i < m ? status[i] : 0xFF;
+    // every per-op word this tile needs, fetched together up front
+    uint8_t s = 0xFF;
+    uint32_t o_ret = 0, o_views = 0, o_lost = 0, o_kicks = 0, o_twins = 0;
+    if (i < m) {
+      s = status[i];
+      o_ret = retries[i];
+      o_views = views[i];
+      o_lost = lost[i];
+      o_kicks = kicks[i];
+      o_twins = twins[i];
+    }
     const bool ok = s == CK_OP_OK;
     const uint64_t bal = __ballot(ok);
     const uint32_t before_in_wave = __popcll(bal & ((1ull << lane) - 1));
@@ -1813,8 +1825,8 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
       if (s == CK_OP_BAD_KEY) {
         a_bad += 1;
       } else {
-        a_ret += retries[i];
-        a_vall += (unsigned long long)views[i] + lost[i];
+        a_ret += o_ret;
+        a_vall += (unsigned long long)o_views + o_lost;
         if (s == CK_OP_ABORTED) {
           a_abort += 1;
         } else {
@@ -1823,14 +1835,14 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
             band = (uint32_t)(b >= CK_BANDS ? CK_BANDS - 1 : b);
             banded = true;
           }
-          v_views = views[i];
+          v_views = o_views;
           a_views += v_views;
           if (ok) {
-            v_kicks = kicks[i];
+            v_kicks = o_kicks;
             a_ok += 1;
             a_kicks += v_kicks;
             a_maxk = v_kicks > a_maxk ? v_kicks : a_maxk;
-            a_tw += twins[i];
+            a_tw += o_twins;
           } else {
             a_fail += 1;
           }
