@@ -8,16 +8,17 @@
 //   k_plan_fresh    lane group of B lanes per pending insert: views the key's
 //                   bins and plans the placement when no kick-out is needed
 //                   (first fit, load balancing, ghost insertion, duplicate
-//                   reuse); every other op is handed to an eviction planner
-//   k_plan_walk     one wavefront per op: random kicking, queue-kicking,
-//                   rattle-kicking; the chain is logged in LDS and later bin
-//                   reads see the chain's own earlier writes
-//   k_plan_search   one wavefront per op: BFS and sorted search; visited-bin
-//                   set and spawn list in LDS, record list in per-workgroup
-//                   global scratch
+//                   reuse); every other op goes to its block's region of the
+//                   evict list for an eviction planner
+//   k_plan_walk     eight walks per wavefront: random kicking, queue-kicking,
+//                   rattle-kicking; the chain is logged (LDS, then scratch)
+//                   and later bin reads see the chain's own earlier writes
+//   k_plan_search   four searches per wavefront: BFS and sorted search over
+//                   runs of B records, several frontier bins per load
 //   k_plan_delete   lane group per pending delete
-//   k_commit        8 lanes per plan: claim check, reverse-order chain write,
-//                   metadata atomics, spawn-count updates, losers re-queued
+//   k_commit        4 lanes per plan: claim check, reverse-order chain write,
+//                   metadata atomics, spawn-count updates, losers flagged
+//   k_compact       the next round's pending list from the losers' flags
 //   k_stats_*       per-op counters -> totals and density bands
 //
 // Every planner reads the round-start snapshot only and claims each bin it
