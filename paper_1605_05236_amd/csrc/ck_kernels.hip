@@ -922,6 +922,7 @@ __global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
 constexpr uint32_t kRootParent = 0xFFFFFFFFu;
 constexpr uint32_t kSearchLdsRuns = 128;
 constexpr int kSearchW = 16;  // lanes per search
+constexpr int kSearchLoads = 4;  // bin slots per lane in one group load
 
 size_t search_runs(const Geo& g) { return (size_t)g.max_search + 8 + g.H; }
 static size_t search_group_lds_words() { return 3 * kSearchLdsRuns + 32; }
@@ -935,7 +936,9 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
   constexpr int W = kSearchW;
   constexpr int P = 64 / W;       // searches per wavefront
   constexpr uint32_t C = H - 1;   // candidates per record
-  constexpr uint32_t G = W / B;   // bins per group-wide load
+  constexpr int KW = kSearchLoads;          // bin slots each lane loads per group load
+  constexpr uint32_t G = KW * W / B;        // bins per group load
+  constexpr int UW = (int)((G + W - 1) / W);  // group units per lane
   constexpr uint32_t RB = H * B;  // root records
   constexpr uint32_t RL = kSearchLdsRuns;
   constexpr int RBW = (int)((RB + W - 1) / W);  // root records per lane
@@ -1129,15 +1132,23 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
     uint32_t tmeta = 0;
     bool done = !have;
     while (!done) {
-      // ---- the next records in search order, as one group
-      uint32_t my_e = 0, my_j = 0, nu = 0;
+      // ---- the next records in search order, as one group; unit u (a
+      // record and one of its candidates) lives in lane u % W, register u / W
+      uint32_t my_e[UW], my_j[UW];
+#pragma unroll
+      for (int t = 0; t < UW; ++t) { my_e[t] = 0; my_j[t] = 0; }
+      uint32_t nu = 0;
       if (!sorted) {
         const uint32_t tail = nruns * B;
         if (head == tail) break;
         const uint32_t nrec = min(G / C, tail - head);
         nu = nrec * C;
-        my_e = head + (uint32_t)gl / C;
-        my_j = (uint32_t)gl % C;
+#pragma unroll
+        for (int t = 0; t < UW; ++t) {
+          const uint32_t u = (uint32_t)(gl + t * W);
+          my_e[t] = head + u / C;
+          my_j[t] = u % C;
+        }
       } else {
         if (bmask == 0) break;
         const int kb2 = __ffs(bmask) - 1;
@@ -1145,7 +1156,9 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
         while (e != kNone && nu + C <= G) {
 #pragma unroll
           for (uint32_t j = 0; j < C; ++j)
-            if ((uint32_t)gl == nu + j) { my_e = e; my_j = j; }
+#pragma unroll
+            for (int t = 0; t < UW; ++t)
+              if ((uint32_t)(gl + t * W) == nu + j) { my_e[t] = e; my_j[t] = j; }
           nu += C;
           if (((e + 1) & (B - 1)) != 0) {
             e = e + 1;
@@ -1156,28 +1169,181 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
         }
       }
       // ---- candidate bins (root records from registers), then contents
-      uint32_t rv = 0;
+      uint32_t cu[UW];
 #pragma unroll
-      for (int t2 = 0; t2 < RBW; ++t2) {
+      for (int t = 0; t < UW; ++t) {
+        uint32_t rv = 0;
 #pragma unroll
-        for (int t = 0; t < (int)C; ++t) {
-          const uint32_t v = __shfl(rc[t2][t], gb + (int)(my_e % W), 64);
-          if ((uint32_t)t == my_j && my_e / W == (uint32_t)t2) rv = v;
+        for (int t2 = 0; t2 < RBW; ++t2) {
+#pragma unroll
+          for (int tc = 0; tc < (int)C; ++tc) {
+            const uint32_t v = __shfl(rc[t2][tc], gb + (int)(my_e[t] % W), 64);
+            if ((uint32_t)tc == my_j[t] && my_e[t] / W == (uint32_t)t2) rv = v;
+          }
+        }
+        cu[t] = 0;
+        if ((uint32_t)(gl + t * W) < nu)
+          cu[t] = my_e[t] < RB ? rv : cand(my_e[t] * C + my_j[t]);
+      }
+      // load k: lane gl reads slot p % B of unit p / B, p = k W + gl
+      ulonglong2 sv[KW];
+      uint32_t mv[KW];
+#pragma unroll
+      for (int k = 0; k < KW; ++k) {
+        const uint32_t pidx = (uint32_t)(k * W + gl);
+        const uint32_t pu = pidx / B, ps = pidx % B;
+        const uint32_t cb = __shfl(cu[(k * W) / (B * W)], gb + (int)(pu % W), 64);
+        sv[k] = make_ulonglong2(kEmpty, 0ull);
+        mv[k] = 0;
+        if (pu < nu) {
+          sv[k] = g.slots[(uint64_t)cb * B + ps];
+          if (need_meta) mv[k] = g.meta[cb];
         }
       }
-      uint32_t cu = 0;
-      if ((uint32_t)gl < nu) cu = my_e < RB ? rv : cand(my_e * C + my_j);
-      const uint32_t ul = (uint32_t)gl / B, sl = (uint32_t)gl % B;
-      const uint32_t cb = __shfl(cu, gb + (int)ul, 64);
-      ulonglong2 sv = make_ulonglong2(kEmpty, 0ull);
-      uint32_t mv = 0;
-      if (ul < nu) {
-        sv = g.slots[(uint64_t)cb * B + sl];
-        if (need_meta) mv = g.meta[cb];
-      }
+      if constexpr (C == 1 && B >= 4) {
+        // ---- the whole group at once (one candidate per record, at most one
+        // record per lane): the serial rules become a cut in record order.
+        static_assert(G <= (uint32_t)W, "one record per lane");
+        const uint32_t u = (uint32_t)gl;  // this lane's record in the group
+        const bool valid = u < nu;
+        const uint32_t e_u = my_e[0], c_u = cu[0];
+        // visited: a run's bin, or the candidate of an earlier record
+        bool seen = false;
+        const uint32_t nl = min(nruns, RL);
+        for (uint32_t j = 0; j < nl; ++j) seen |= rbinL[j] == c_u;
+        for (uint32_t j = RL; j < nruns; ++j) seen |= rbinG(j) == c_u;
+#pragma unroll
+        for (uint32_t v = 0; v < G; ++v) {
+          const uint32_t cv = __shfl(c_u, gb + (int)v, 64);
+          seen |= v < u && v < nu && cv == c_u;
+        }
+        const bool nv = valid && !seen;
+        // terminal bins: a ballot per load; record u's slots are bits
+        // (u B) % W .. + B - 1 of load (u B) / W
+        uint64_t tb[KW];
+#pragma unroll
+        for (int k = 0; k < KW; ++k) {
+          const uint32_t pidx = (uint32_t)(k * W + gl);
+          const uint32_t pu = pidx / B, ps = pidx % B;
+          tb[k] = gballot(pu < nu && (sv[k].x == kEmpty || (g.ghost && ((mv[k] >> ps) & 1u))));
+        }
+        const uint32_t ku = (u * B) / W, su = (u * B) % W;
+        uint64_t tbu = 0;
+        uint32_t mu = 0;
+#pragma unroll
+        for (int k = 0; k < KW; ++k) {
+          const uint32_t m2 = __shfl(mv[k], gb + (int)su, 64);
+          if (ku == (uint32_t)k) { tbu = tb[k]; mu = m2; }
+        }
+        const bool term = ((tbu >> su) & ((1ull << B) - 1)) != 0;
+        const uint32_t b2 = min(15u, (mu >> 8) & 0xFu);
+        // the cut: first terminal (kept), first run into a lower bucket
+        // (kept, then regroup), or the view that would pass max_search (not kept)
+        const uint32_t kb_now = sorted ? (uint32_t)(__ffs(bmask) - 1) : 0u;
+        const uint64_t NV = gballot(nv);
+        const uint64_t below = (1ull << u) - 1;
+        const uint32_t rank = (uint32_t)__popcll(NV & below);
+        const uint32_t avail = g.max_search - views;
+        const uint64_t TERM = gballot(nv && term);
+        const uint64_t LOW = sorted ? gballot(nv && !term && b2 < kb_now) : 0ull;
+        const uint64_t CAP = gballot(nv && rank == avail);
+        const uint32_t t_term = TERM ? (uint32_t)__ffsll((unsigned long long)TERM) - 1 : 64u;
+        const uint32_t t_low = LOW ? (uint32_t)__ffsll((unsigned long long)LOW) - 1 : 64u;
+        const uint32_t t_cap = CAP ? (uint32_t)__ffsll((unsigned long long)CAP) - 1 : 64u;
+        uint32_t cut = nu;
+        bool capped = false;
+        if (t_cap <= t_term && t_cap <= t_low && t_cap < 64u) {
+          cut = t_cap;
+          capped = true;
+        } else if (t_term < t_low) {
+          cut = t_term + 1;
+          found = true;
+        } else if (t_low < 64u) {
+          cut = t_low + 1;
+        }
+        const uint64_t upto = cut >= 64 ? ~0ull : ((1ull << cut) - 1);
+        const uint64_t VIEW = NV & upto;
+        const uint64_t RUNS = VIEW & ~TERM;
+        views += (uint32_t)__popcll(VIEW);
+        // spawn list (sorted): every record that viewed its candidate
+        if (sorted && ((VIEW >> u) & 1ull)) spl(nsp + (uint32_t)__popcll(VIEW & below)) = e_u / B;
+        if (sorted) nsp += (uint32_t)__popcll(VIEW);
+        // new runs, in record order
+        const bool mkrun = (RUNS >> u) & 1ull;
+        const uint32_t run_u = nruns + (uint32_t)__popcll(RUNS & below);
+        if (mkrun) set_run(run_u, c_u, e_u);
+#pragma unroll
+        for (int k = 0; k < KW; ++k) {
+          const uint32_t pidx = (uint32_t)(k * W + gl);
+          const uint32_t pu = pidx / B, ps = pidx % B;
+          const uint32_t rp = __shfl(run_u, gb + (int)(pu % W), 64);
+          const uint32_t cp = __shfl(c_u, gb + (int)(pu % W), 64);
+          if (pu < G && ((RUNS >> pu) & 1ull)) {
+            uint32_t hv[H];
+            hash_key<H>(g, T, sv[k].x, hv);
+            cand(rp * B + ps) = hv[0] == cp ? hv[1] : hv[0];
+          }
+        }
+        const uint32_t nnew = (uint32_t)__popcll(RUNS);
+        if (found) {
+          term_e = __shfl(e_u, gb + (int)t_term, 64);
+          term_c = __shfl(c_u, gb + (int)t_term, 64);
+          const uint32_t kt = (t_term * B) / W, st2 = (t_term * B) % W;
+#pragma unroll
+          for (int k = 0; k < KW; ++k) {
+            const uint64_t a = __shfl(sv[k].x, gb + (int)(st2 + ((uint32_t)gl & (B - 1))), 64);
+            const uint32_t m2 = __shfl(mv[k], gb + (int)st2, 64);
+            if (kt == (uint32_t)k) { tkey = a; tmeta = m2; }
+          }
+        }
+        // pop the processed records, then link the new runs
+        if (!sorted) {
+          head += cut;
+        } else {
+          uint32_t eh = bhead[kb_now];
+          for (uint32_t q = 0; q < cut && eh != kNone; ++q) {
+            if (((eh + 1) & (B - 1)) != 0) {
+              eh = eh + 1;
+            } else {
+              const uint32_t nr = rnext_at(eh / B);
+              eh = nr == kNone ? kNone : nr * B;
+            }
+          }
+          wave_sync();
+          if (gl == 0) {
+            bhead[kb_now] = eh;
+            if (eh == kNone) btail[kb_now] = kNone;
+          }
+          if (eh == kNone) bmask &= ~(1u << kb_now);
+          wave_sync();
+          uint64_t rr = RUNS;
+          while (rr) {
+            const uint32_t v = (uint32_t)__ffsll((unsigned long long)rr) - 1;
+            rr &= rr - 1;
+            const uint32_t run = __shfl(run_u, gb + (int)v, 64);
+            const uint32_t bv = __shfl(b2, gb + (int)v, 64);
+            if (gl == 0) {
+              set_next(run, kNone);
+              if (btail[bv] == kNone) bhead[bv] = run * B;
+              else set_next(btail[bv], run);
+              btail[bv] = run;
+            }
+            bmask |= 1u << bv;
+            wave_sync();
+          }
+        }
+        nruns += nnew;
+        wave_sync();
+        if (found || capped) done = true;
+      } else {
       // ---- records one by one, in order
       for (uint32_t u = 0; u < nu && !done; u += C) {
-        const uint32_t e = __shfl(my_e, gb + (int)u, 64);
+        uint32_t e = 0;
+#pragma unroll
+        for (int t = 0; t < UW; ++t) {
+          const uint32_t v = __shfl(my_e[t], gb + (int)(u % W), 64);
+          if (u / W == (uint32_t)t) e = v;
+        }
         if (sorted) {
           const int kb2 = bmask ? __ffs(bmask) - 1 : -1;
           if (kb2 < 0 || bhead[kb2] != e) break;  // order changed: regroup
@@ -1201,7 +1367,12 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
         bool spawned = false;
         for (uint32_t j = 0; j < C; ++j) {
           const uint32_t uu = u + j;
-          const uint32_t c = __shfl(cu, gb + (int)uu, 64);
+          uint32_t c = 0;
+#pragma unroll
+          for (int t = 0; t < UW; ++t) {
+            const uint32_t v = __shfl(cu[t], gb + (int)(uu % W), 64);
+            if (uu / W == (uint32_t)t) c = v;
+          }
           bool seen = false;
           for (uint32_t base = 0; base < nruns; base += W) {
             const uint32_t q = base + (uint32_t)gl;
@@ -1215,9 +1386,17 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
           }
           spawned = true;
           ++views;
-          const int src = gb + (int)(uu * B + ((uint32_t)gl & (B - 1)));
-          const uint64_t vk = __shfl(sv.x, src, 64);
-          const uint32_t vm = __shfl(mv, gb + (int)(uu * B), 64);
+          // unit uu's bin: slot sl in lane (uu B) % W + sl, load (uu B) / W
+          const uint32_t kk = (uu * B) / W;
+          const int src = gb + (int)((uu * B) % W + ((uint32_t)gl & (B - 1)));
+          uint64_t vk = kEmpty;
+          uint32_t vm = 0;
+#pragma unroll
+          for (int k = 0; k < KW; ++k) {
+            const uint64_t a = __shfl(sv[k].x, src, 64);
+            const uint32_t m2 = __shfl(mv[k], gb + (int)((uu * B) % W), 64);
+            if (kk == (uint32_t)k) { vk = a; vm = m2; }
+          }
           const bool empty = gl < B && vk == kEmpty;
           const bool dup = g.ghost && gl < B && vk != kEmpty && ((vm >> gl) & 1u);
           if (gballot(empty || dup) != 0) {
@@ -1254,7 +1433,8 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
           }
         }
       }
-    }
+          }
+}
     fetch_roots();
     // ---- spawn counts go to the spawn arena for every plan, winning or not
     uint32_t soff = 0;
