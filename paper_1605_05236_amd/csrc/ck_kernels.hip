@@ -922,7 +922,7 @@ __global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
 constexpr uint32_t kRootParent = 0xFFFFFFFFu;
 constexpr uint32_t kSearchLdsRuns = 128;
 constexpr int kSearchW = 16;  // lanes per search
-constexpr int kSearchLoads = 4;  // bin slots per lane in one group load
+constexpr int kSearchLoads = 2;  // bin slots per lane in one group load
 
 size_t search_runs(const Geo& g) { return (size_t)g.max_search + 8 + g.H; }
 static size_t search_group_lds_words() { return 3 * kSearchLdsRuns + 32; }
