@@ -178,8 +178,7 @@ typedef struct {
   ck_kernel_time plan_fresh;  /* placement without eviction, every pending op */
   ck_kernel_time plan_evict;  /* kick-out planners: walk (random/queue/rattle) or search */
   ck_kernel_time plan_delete;
-  ck_kernel_time commit;      /* claim check, reverse-order writes, metadata */
-  ck_kernel_time compact;     /* evict / pending list compaction */
+  ck_kernel_time commit;      /* claim check, reverse-order writes, metadata, next list */
   ck_kernel_time stats;       /* density bands and totals */
   ck_kernel_time lookup;
   uint64_t evict_views;       /* bins viewed by the kick-out planners while enabled */
@@ -188,7 +187,7 @@ typedef struct {
 /* Classes to time (bit mask for ck_timing_enable); 0 turns timing off. */
 enum {
   CK_TIME_PLAN_FRESH = 1, CK_TIME_PLAN_EVICT = 2, CK_TIME_PLAN_DELETE = 4, CK_TIME_COMMIT = 8,
-  CK_TIME_COMPACT = 16, CK_TIME_STATS = 32, CK_TIME_LOOKUP = 64, CK_TIME_ALL = 127
+  CK_TIME_STATS = 16, CK_TIME_LOOKUP = 32, CK_TIME_ALL = 63
 };
 ck_status ck_timing_enable(ck_table* t, uint32_t class_mask);
 /* Synchronises `stream`, then copies the timing gathered since enabling. */

@@ -14,7 +14,7 @@ using namespace ck;
 
 // Event timing of kernel classes (opt-in).  Pairs of events are recorded
 // around launches and resolved after the stream has been synchronised.
-enum TimedKind { TK_FRESH, TK_EVICT, TK_DELETE, TK_COMMIT, TK_COMPACT, TK_STATS, TK_LOOKUP, TK_N };
+enum TimedKind { TK_FRESH, TK_EVICT, TK_DELETE, TK_COMMIT, TK_STATS, TK_LOOKUP, TK_N };
 struct Timer {
   bool on = false;
   uint32_t mask = 0;
@@ -25,8 +25,10 @@ struct Timer {
   uint64_t views_base = 0, views_acc = 0;
   hipEvent_t take() {
     if (pool.empty()) {
+      // timing only: no system-scope fence when the event is recorded, so an
+      // event costs less and disturbs the launches around it less
       hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
       return e;
     }
     hipEvent_t e = pool.back();
@@ -96,7 +98,9 @@ struct ck_table {
   uint32_t evict_grid = 0;
   DevStats* dstats = nullptr;
   uint32_t* block_tmp = nullptr;
-  uint8_t* req = nullptr;
+  uint32_t stripe_cap = 0;  // entries per pending-list segment
+  uint32_t tail_hint = 2;   // rounds the last insert sub-batch took (sizes the next enqueue)
+  uint32_t tail_hint_del = 1;  // the same for deletes
   // host-side counters
   uint64_t rounds = 0, lookups = 0;
   Timer timer;
@@ -161,7 +165,6 @@ void free_scratch(ck_table* t) {
   (void)hipFree(t->wg_views);
   (void)hipFree(t->dstats);
   (void)hipFree(t->block_tmp);
-  (void)hipFree(t->req);
 }
 
 ck_status alloc_scratch(ck_table* t) {
@@ -180,12 +183,16 @@ ck_status alloc_scratch(ck_table* t) {
   HIP_TRY(hipMalloc(&t->wg_scratch, (size_t)t->evict_grid * t->wg_bytes));
   HIP_TRY(dalloc(&t->wg_views, t->evict_grid));
   HIP_TRY(hipMemset(t->wg_views, 0, (size_t)t->evict_grid * 8));
-  HIP_TRY(dalloc(&t->pend[0], m));
-  HIP_TRY(dalloc(&t->pend[1], m));
+  t->stripe_cap = stripe_capacity(m);
+  HIP_TRY(dalloc(&t->pend[0], (size_t)kStripes * t->stripe_cap));
+  HIP_TRY(dalloc(&t->pend[1], (size_t)kStripes * t->stripe_cap));
   HIP_TRY(dalloc(&t->hdr, m));
   HIP_TRY(dalloc(&t->imv, (size_t)m * kExtraInline));
-  HIP_TRY(dalloc(&t->evict, (size_t)m + 256));
-  HIP_TRY(dalloc(&t->evict_cnt, ((size_t)m * t->B + 255) / 256 + 1));
+  // evict regions: one per fresh-planner wavefront (64 / B ops), every
+  // wavefront of the last pass included
+  const size_t evict_units = ((size_t)m * t->B + 255) / 256 * 4;
+  HIP_TRY(dalloc(&t->evict, evict_units * (64 / t->B)));
+  HIP_TRY(dalloc(&t->evict_cnt, evict_units));
   for (auto& p : t->op) HIP_TRY(dalloc(&p, m));
   // eviction plans sub-allocate from per-workgroup windows of 256 entries
   const uint64_t slack = (uint64_t)t->evict_grid * 512;
@@ -196,12 +203,12 @@ ck_status alloc_scratch(ck_table* t) {
                      : 16;
   HIP_TRY(dalloc(&t->spawns, t->spawn_cap));
   HIP_TRY(dalloc(&t->ctr, 1));
+  HIP_TRY(hipMemset(t->ctr, 0, sizeof(Ctr)));
   HIP_TRY(hipHostMalloc((void**)&t->h_ctr, sizeof(Ctr), hipHostMallocDefault));
   HIP_TRY(dalloc(&t->dstats, 1));
   HIP_TRY(hipMemset(t->dstats, 0, sizeof(DevStats)));
   const uint32_t nb = (m + 1023) / 1024;
   HIP_TRY(dalloc(&t->block_tmp, ((nb + 63) & ~63u) + 16));
-  HIP_TRY(dalloc(&t->req, m));
   return CK_OK;
 }
 
@@ -254,28 +261,35 @@ Round make_round(ck_table* t, const uint64_t* keys, const void* vals, uint8_t* s
   return r;
 }
 
-// Run the phased rounds of one sub-batch until no op is pending.  Large
-// rounds are sized from the pending count the host read back; once at most
-// kTailOps ops remain, kTailRounds rounds are enqueued back to back with the
-// count held in device memory (grids sized for the last count read, which
-// only shrinks), and the host synchronises once per group of rounds.
-constexpr uint32_t kTailOps = 65536;
-constexpr int kTailRounds = 4;
+// Run the phased rounds of one sub-batch until no op is pending, then its
+// statistics.  The first round's list is every op; each later round's list
+// (and count) exists only on the device, so those rounds run capped grids
+// that loop over whatever count they find.  The host enqueues the first
+// round, as many more as the last sub-batch took, and the statistics, and
+// synchronises once: the statistics apply only if the last list came out
+// empty, else more rounds and the statistics are enqueued again.
+constexpr uint32_t kMaxTailHint = 12;
 
-ck_status run_rounds(ck_table* t, Round& r, uint64_t m, hipStream_t s) {
-  uint32_t npend = (uint32_t)m;
+uint32_t list_count(const Ctr& c, int p) {
+  uint32_t n = 0;
+  for (uint32_t sg = 0; sg < kStripes; ++sg) n += c.cnt[p][sg * kStripeWords];
+  return n;
+}
+
+ck_status run_rounds(ck_table* t, Round& r, uint64_t m, uint64_t slots, hipStream_t s) {
   int cur = 0;
   // The lowest pending op always commits, so m rounds suffice; arena growth
   // adds a few void rounds.  Anything beyond that is a fault, not progress.
   uint64_t guard = 2 * m + 64;
   Timer& T = t->timer;
-  // the first round's planner clears ctr->rounds and ctr->overflow_seen and
-  // the ops' counters; its pending list is the identity (no list is read)
   bool first = true;
-  while (npend > 0) {
-    if (guard == 0) return CK_EDEVICE;
-    const int K = npend <= kTailOps ? kTailRounds : 1;
-    for (int k = 0; k < K; ++k) {
+  uint32_t used = 0;
+  for (;;) {
+    // as many rounds as the last sub-batch of this kind took, and one more
+    uint32_t& hint = r.is_delete ? t->tail_hint_del : t->tail_hint;
+    const uint32_t K = first ? hint + 1 : 2;
+    for (uint32_t k = 0; k < K; ++k) {
+      if (guard == 0) return CK_EDEVICE;
       --guard;
       ++t->epoch;
       if (t->epoch == 0) {  // claim tags wrapped: reset every claim word
@@ -283,17 +297,17 @@ ck_status run_rounds(ck_table* t, Round& r, uint64_t m, hipStream_t s) {
         t->epoch = 1;
       }
       r.tag = (unsigned long long)(~t->epoch) << 32;
+      r.first = first ? 1u : 0u;
+      r.npend = (uint32_t)m;  // grid size; later rounds cap it
       r.pend = t->pend[cur];
-      r.npend = npend;
-      r.npend_dev = k == 0 ? nullptr : &t->ctr->pending[cur];
+      r.pcnt = first ? nullptr : t->ctr->cnt[cur];
       r.next = t->pend[cur ^ 1];
-      r.next_count = &t->ctr->pending[cur ^ 1];
+      r.next_cnt = t->ctr->cnt[cur ^ 1];
+      r.stripe_cap = t->stripe_cap;
       r.arena = t->arena;
       r.arena_cap = t->arena_cap;
       r.spawns = t->spawns;
       r.spawn_cap = t->spawn_cap;
-      r.req = t->req;
-      r.first = first ? 1u : 0u;
       first = false;
       hipEvent_t ev;
       if (r.is_delete) {
@@ -301,9 +315,7 @@ ck_status run_rounds(ck_table* t, Round& r, uint64_t m, hipStream_t s) {
         HIP_TRY(launch_plan_delete(t->g, r, s));
         T.end(TK_DELETE, ev, s);
       } else {
-        // the fresh planner's blocks leave the evict list in per-block regions
-        r.fresh_blocks = (uint32_t)(((uint64_t)npend * t->B + 255) / 256);
-        r.fresh_opb = 256 / t->B;
+        // the fresh planner's wavefronts leave the evict list in regions
         ev = T.begin(s, TK_FRESH);
         HIP_TRY(launch_plan_fresh(t->g, r, s));
         T.end(TK_FRESH, ev, s);
@@ -314,24 +326,24 @@ ck_status run_rounds(ck_table* t, Round& r, uint64_t m, hipStream_t s) {
       ev = T.begin(s, TK_COMMIT);
       HIP_TRY(launch_commit(t->g, r, s));
       T.end(TK_COMMIT, ev, s);
-      ev = T.begin(s, TK_COMPACT);
-      HIP_TRY(launch_compact(r, r.next, r.next_count, s));
-      T.end(TK_COMPACT, ev, s);
       cur ^= 1;
     }
+    hipEvent_t ev = T.begin(s, TK_STATS);
+    HIP_TRY(launch_batch_stats(r, m, slots, t->block_tmp, r.is_delete, t->ctr->cnt[cur], s));
+    T.end(TK_STATS, ev, s);
     HIP_TRY(hipMemcpyAsync(t->h_ctr, t->ctr, sizeof(Ctr), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     T.collect();
-    const Ctr c = *t->h_ctr;
+    const Ctr& c = *t->h_ctr;
     if (c.overflow || c.overflow_seen) {
       ck_status st = grow_arena(t);
       if (st != CK_OK) return st;
-      HIP_TRY(hipMemsetAsync(&t->ctr->overflow_seen, 0, 4, s));
-      HIP_TRY(hipMemsetAsync(&t->ctr->overflow, 0, 4, s));
     }
-    npend = c.pending[cur];
-    if (npend == 0 && !r.is_delete) t->rounds += c.rounds;
+    used = c.rounds;
+    if (list_count(c, cur) == 0) break;
   }
+  if (!r.is_delete) t->rounds += used;
+  (r.is_delete ? t->tail_hint_del : t->tail_hint) = std::min(kMaxTailHint, std::max<uint32_t>(1, used));
   return CK_OK;
 }
 
@@ -349,12 +361,9 @@ ck_status run_batches(ck_table* t, const uint64_t* keys, const void* vals, uint6
     Round r = make_round(t, keys + b0, vals ? (const char*)vals + b0 * vb : nullptr,
                          status + b0, ops, t->insert_count + b0, is_delete,
                          op_table ? op_table + b0 : nullptr, tdesc);
-    ck_status st = run_rounds(t, r, m, s);
-    if (st != CK_OK) return st;
-    hipEvent_t ev = t->timer.begin(s, TK_STATS);
     // density bands are per table: a group keeps totals only
-    HIP_TRY(launch_batch_stats(r, m, op_table ? 0 : slots, t->block_tmp, is_delete ? 1 : 0, s));
-    t->timer.end(TK_STATS, ev, s);
+    ck_status st = run_rounds(t, r, m, op_table ? 0 : slots, s);
+    if (st != CK_OK) return st;
   }
   if (!is_delete) t->insert_count += n;
   return CK_OK;
@@ -588,8 +597,7 @@ ck_status ck_timing_get(ck_table* t, ck_timing* out, void* stream) {
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
   t->timer.collect();
   ck_kernel_time* dst[TK_N] = {&out->plan_fresh, &out->plan_evict, &out->plan_delete,
-                               &out->commit,     &out->compact,    &out->stats,
-                               &out->lookup};
+                               &out->commit,     &out->stats,      &out->lookup};
   for (int k = 0; k < TK_N; ++k) {
     dst[k]->launches = t->timer.launches[k];
     dst[k]->ms = t->timer.ms[k];

@@ -72,13 +72,29 @@ __host__ __device__ inline uint32_t hdr_pack(uint32_t status, uint32_t twins, ui
   return status | (twins << 4) | (nm << 8);
 }
 
+// Pending lists.  After the first round of a sub-batch (whose list is every
+// op in order), the ops that go again are listed by the commit kernel in
+// kStripes segments: commit wavefront u (kCommitWaveOps consecutive
+// positions) appends its ops to segment u % kStripes with one atomic add on
+// that segment's count, so the adds spread over kStripes counters (each on
+// its own 128-byte line).  A list of n ops has positions 0..n-1 through the
+// prefix sums of the counts.  The order within a list is immaterial: every
+// kernel's result for an op depends on the op, never on its position.
+constexpr uint32_t kStripes = 64;
+constexpr uint32_t kStripeWords = 32;
+constexpr uint32_t kCommitOps = 64;      // plans per commit workgroup pass (256 lanes / 4)
+constexpr uint32_t kCommitWaveOps = 16;  // plans per commit wavefront
+__host__ __device__ inline uint32_t stripe_capacity(uint32_t m) {
+  const uint32_t waves = (m + kCommitWaveOps - 1) / kCommitWaveOps;
+  return (waves + kStripes - 1) / kStripes * kCommitWaveOps;
+}
+
 struct Ctr {             // device counters of the round loop
-  uint32_t pending[2];   // pending ops of the round of parity p (written by compaction)
-  uint32_t unused;
   uint32_t overflow;     // a planner ran out of arena this round (round is void)
-  uint32_t overflow_seen;  // sticky: some round since the host last looked was void
+  uint32_t overflow_seen;  // sticky: some earlier round of the sub-batch was void
   uint32_t rounds;       // rounds that committed (not void, ops pending)
-  uint32_t pad[2];
+  uint32_t pad[29];
+  uint32_t cnt[2][kStripes * kStripeWords];  // segment counts of pending list p
 };
 
 struct DevStats {        // device accumulators (mirrors ck_stats)
@@ -114,17 +130,18 @@ struct Round {
   const void* vals;          // sub-batch values (8 or 4 bytes each)
   const uint32_t* op_table;  // group mode: table index of each op (else null)
   const uint2* tdesc;        // group mode: {bin base, bins} of each table
-  const uint32_t* pend;      // pending op indices this round
-  uint32_t npend;            // pending ops, or an upper bound when npend_dev is set
-  const uint32_t* npend_dev; // device-held pending count (rounds enqueued without a sync)
-  uint32_t* next_count;      // where this round's compaction writes next round's count
-  uint32_t* next;            // losers for the next round
-  uint8_t* req;              // per pending position: 1 = pending again next round
-  uint32_t* evict;           // ops that need an eviction plan: fresh-planner block b
-                             // puts its evict_cnt[b] ops at evict[b * fresh_opb ...)
-  uint32_t* evict_cnt;       // per fresh-planner block
-  uint32_t fresh_blocks;     // fresh-planner blocks of this round (its grid)
-  uint32_t fresh_opb;        // ops per fresh-planner block (256 / B)
+  const uint32_t* pend;      // this round's pending list (segments of stripe_cap)
+  const uint32_t* pcnt;      // its segment counts; null in the first round
+  uint32_t npend;            // first round: the op count; later rounds: the size
+                             // the grids are made for (kernels loop past it)
+  uint32_t stripe_cap;       // entries per list segment
+  uint32_t* next;            // the next round's list: ops that go again
+  uint32_t* next_cnt;        // its segment counts (zeroed by this round's planner)
+  uint32_t* evict;           // ops that need an eviction plan: fresh-planner
+                             // wavefront u (positions [u opw, (u + 1) opw),
+                             // opw = 64 / B) puts its evict_cnt[u] ops at
+                             // evict[u opw ...)
+  uint32_t* evict_cnt;       // per fresh-planner wavefront
   PlanHdr* hdr;
   IMove* imv;                // kExtraInline per op
   Move* arena;
@@ -158,11 +175,11 @@ hipError_t launch_plan_fresh(const Geo& g, const Round& r, hipStream_t s);
 hipError_t launch_plan_evict(const Geo& g, const Round& r, uint32_t grid, hipStream_t s);
 hipError_t launch_plan_delete(const Geo& g, const Round& r, hipStream_t s);
 hipError_t launch_commit(const Geo& g, const Round& r, hipStream_t s);
-// Ordered compaction of the pending list into `out` (keeps positions p with
-// req[p] set); the length goes to *count.
-hipError_t launch_compact(const Round& r, uint32_t* out, uint32_t* count, hipStream_t s);
+// Sub-batch statistics; they apply only if the pending list whose segment
+// counts `open` points to is empty (else the kernels return at once and the
+// host enqueues them again after more rounds).
 hipError_t launch_batch_stats(const Round& r, uint64_t m, uint64_t slots, uint32_t* block_tmp,
-                              uint32_t is_delete, hipStream_t s);
+                              uint32_t is_delete, const uint32_t* open, hipStream_t s);
 size_t evict_lds_bytes(const Geo& g);
 size_t evict_wg_scratch_bytes(const Geo& g);
 hipError_t launch_export_meta(const Geo& g, hipStream_t s);

@@ -8,7 +8,7 @@
 //   k_plan_fresh    lane group of B lanes per pending insert: views the key's
 //                   bins and plans the placement when no kick-out is needed
 //                   (first fit, load balancing, ghost insertion, duplicate
-//                   reuse); every other op goes to its block's region of the
+//                   reuse); every other op goes to its pass's region of the
 //                   evict list for an eviction planner
 //   k_plan_walk     eight walks per wavefront: random kicking, queue-kicking,
 //                   rattle-kicking; the chain is logged (LDS, then scratch)
@@ -17,8 +17,8 @@
 //                   runs of B records, several frontier bins per load
 //   k_plan_delete   lane group per pending delete
 //   k_commit        4 lanes per plan: claim check, reverse-order chain write,
-//                   metadata atomics, spawn-count updates, losers flagged
-//   k_compact       the next round's pending list from the losers' flags
+//                   metadata atomics, spawn-count updates; the losers form
+//                   the next round's pending list
 //   k_stats_*       per-op counters -> totals and density bands
 //
 // Every planner reads the round-start snapshot only and claims each bin it
@@ -58,11 +58,54 @@ __device__ __forceinline__ void hash_key(const Geo& g, Tab t, uint64_t x, uint32
   }
 }
 
-// Pending ops of this round: a kernel argument, or (for rounds enqueued
-// back to back without a host sync) the count the previous round's
-// compaction left in device memory; the argument is then an upper bound.
-__device__ __forceinline__ uint32_t npend_of(const Round& r) {
-  return r.npend_dev ? *r.npend_dev : r.npend;
+// The round's pending list as one wavefront sees it.  The first round of a
+// sub-batch lists every op in order (position = op index, count a kernel
+// argument); later rounds read the segment counts the previous commit left
+// (lane l loads segment l's count) and map a position to its segment through
+// their prefix sums.  init and at are called by all 64 lanes together.
+struct Pending {
+  const uint32_t* list = nullptr;
+  uint32_t cap = 0, n = 0, incl = 0, excl = 0;
+  bool ident = true;
+  __device__ void init(const Round& r) {
+    ident = r.first != 0;
+    if (ident) {
+      n = r.npend;
+      return;
+    }
+    list = r.pend;
+    cap = r.stripe_cap;
+    const int lane = threadIdx.x & 63;
+    const uint32_t c = r.pcnt[lane * kStripeWords];
+    uint32_t x = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    incl = x;
+    excl = x - c;
+    n = __shfl(x, 63, 64);
+  }
+  // op index at position p, kNone for p >= n
+  __device__ uint32_t at(uint32_t p) const {
+    if (ident) return p < n ? p : kNone;
+    // segment of p: the number of segments whose inclusive prefix is <= p
+    uint32_t sg = 0;
+#pragma unroll
+    for (uint32_t step = 32; step; step >>= 1)
+      if (__shfl(incl, (int)(sg + step - 1), 64) <= p) sg += step;
+    const uint32_t e = __shfl(excl, (int)(sg & 63), 64);
+    if (p >= n) return kNone;
+    return list[(size_t)sg * cap + (p - e)];
+  }
+};
+
+// True when the pending list with segment counts `cnt` is not empty (all 64
+// lanes call it together).
+__device__ __forceinline__ bool list_open(const uint32_t* cnt) {
+  const uint32_t c = cnt[(threadIdx.x & 63) * kStripeWords];
+  return __ballot(c != 0) != 0ull;
 }
 
 // The table of op i: from the group's descriptors, else the single table.
@@ -258,21 +301,23 @@ hipError_t launch_lookup(const Geo& g, const uint64_t* keys, uint64_t n, void* o
 // ---------------------------------------------------------------------------
 // round bookkeeping
 // ---------------------------------------------------------------------------
-// Round start, done by one thread of the round's first kernel (the fresh or
-// delete planner): an arena overflow of the previous round is remembered for
-// the host and cleared, and the count this round's compaction accumulates
-// into is zeroed (no kernel of this round reads it before the compaction).
-// The first round of a sub-batch also resets the sub-batch's counters; its
-// pending list is every op in order, so position and op index coincide.
+// Round start, done by block 0 of the round's first kernel (the fresh or
+// delete planner): the next list's segment counts are zeroed (the commit
+// kernel of this round is the first to touch them), and an arena overflow of
+// the previous round is remembered for the host and cleared.  The first round
+// of a sub-batch resets the sub-batch's counters instead; its pending list is
+// every op in order, so position and op index coincide.
 __device__ __forceinline__ void round_start(const Round& r) {
+  if (threadIdx.x < kStripes) r.next_cnt[threadIdx.x * kStripeWords] = 0;
+  if (threadIdx.x != 0) return;
   Ctr* c = r.ctr;
   if (r.first) {  // a new sub-batch
     c->rounds = 0;
     c->overflow_seen = 0;
+  } else if (c->overflow) {
+    c->overflow_seen = 1;
   }
-  if (c->overflow) c->overflow_seen = 1;
   c->overflow = 0;
-  *r.next_count = 0;
 }
 __device__ __forceinline__ void zero_op_counters(const Round& r, uint32_t i) {
   r.op_views[i] = 0;
@@ -318,118 +363,123 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
   G.lane = threadIdx.x & 63;
   G.sl = G.lane % B;
   G.gshift = G.lane - G.sl;
-  if (blockIdx.x == 0 && threadIdx.x == 0) round_start(r);
-  const uint64_t gidx = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / B;
-  const bool active = gidx < npend_of(r);
-  const uint32_t i = active ? (r.first ? (uint32_t)gidx : r.pend[gidx]) : 0u;
-  if (r.first && active && (threadIdx.x % B) == 0) zero_op_counters(r, i);
-  const uint64_t x = active ? r.keys[i] : kEmpty;
-  const bool leader = G.sl == 0;
-  const bool bad = x == kEmpty;  // reserved key: rejected, no plan
-  const uint32_t hc_flag = (g.scheme == CK_QUEUE) ? MV_HC : 0;
-  // up to two moves (slot | flags << 8), group-uniform, kept in registers;
-  // the written record is always this op's own key and value
-  uint32_t b0 = 0, f0 = 0, b1 = 0, f1 = 0;
-  uint32_t nm = 0, views = 0, twins = 0;
-  bool placed = false;
-  // rattle-kicking has no separate fresh phase: every op goes to the walk
-  const Tab T = active ? tab_of(g, r.op_table, r.tdesc, i) : Tab{0u, g.n};
-  if (active && !bad && g.scheme != CK_RATTLE) {
-    uint32_t h[H];
-    hash_key<H>(g, T, x, h);
-    if (g.ghost) {
-      const ulonglong2 s0 = g.slots[(uint64_t)h[0] * B + G.sl];
-      const ulonglong2 s1 = g.slots[(uint64_t)h[1] * B + G.sl];
-      views = 2;
-      const uint32_t e0 = G.ballot(s0.x == kEmpty), e1 = G.ballot(s1.x == kEmpty);
-      if (e0 && e1) {
-        b0 = h[0]; f0 = ffs32(e0) | ((MV_DUP | hc_flag) << 8);
-        b1 = h[1]; f1 = ffs32(e1) | ((MV_DUP | hc_flag) << 8);
-        nm = 2;
-        placed = true;
-      } else if (e0) {
-        b0 = h[0]; f0 = ffs32(e0) | (hc_flag << 8); nm = 1;
-        placed = true;
-      } else if (e1) {
-        b0 = h[1]; f0 = ffs32(e1) | (hc_flag << 8); nm = 1;
-        placed = true;
-      } else {
-        const uint32_t full = (1u << B) - 1;
-        const uint32_t d0 = g.meta[h[0]] & full, d1 = g.meta[h[1]] & full;
-        if (d0 || d1) {
-          const int w = d0 ? 0 : 1;
-          const uint32_t b = w == 0 ? h[0] : h[1];
-          const uint32_t ds = ffs32(d0 ? d0 : d1);
-          const uint64_t dk = __shfl(w == 0 ? s0.x : s1.x, G.gshift + (int)ds, 64);
-          uint32_t hd[2];
-          hash_key<2>(g, T, dk, hd);
-          const uint32_t tb = hd[0] == b ? hd[1] : hd[0];
-          const ulonglong2 ts = g.slots[(uint64_t)tb * B + G.sl];
-          const uint32_t tm = G.ballot(ts.x == dk);
-          b0 = tb; f0 = ffs32(tm) | (MV_DUPCLR << 8);
-          b1 = b; f1 = ds | (hc_flag << 8);
+  if (blockIdx.x == 0) round_start(r);
+  Pending P;
+  P.init(r);
+  constexpr uint32_t opb = 256 / B, opw = 64 / B;
+  const uint32_t passes = (P.n + opb - 1) / opb;
+  // pass c takes positions [c opb, (c + 1) opb); rounds after the first run a
+  // capped grid, so a workgroup may take several passes
+  for (uint32_t c = blockIdx.x; c < passes; c += gridDim.x) {
+    const uint32_t pi = P.at(c * opb + threadIdx.x / B);
+    const bool active = pi != kNone;
+    const uint32_t i = active ? pi : 0u;
+    if (r.first && active && (threadIdx.x % B) == 0) zero_op_counters(r, i);
+    const uint64_t x = active ? r.keys[i] : kEmpty;
+    const bool leader = G.sl == 0;
+    const bool bad = x == kEmpty;  // reserved key: rejected, no plan
+    const uint32_t hc_flag = (g.scheme == CK_QUEUE) ? MV_HC : 0;
+    // up to two moves (slot | flags << 8), group-uniform, kept in registers;
+    // the written record is always this op's own key and value
+    uint32_t b0 = 0, f0 = 0, b1 = 0, f1 = 0;
+    uint32_t nm = 0, views = 0, twins = 0;
+    bool placed = false;
+    // rattle-kicking has no separate fresh phase: every op goes to the walk
+    const Tab T = active ? tab_of(g, r.op_table, r.tdesc, i) : Tab{0u, g.n};
+    if (active && !bad && g.scheme != CK_RATTLE) {
+      uint32_t h[H];
+      hash_key<H>(g, T, x, h);
+      if (g.ghost) {
+        const ulonglong2 s0 = g.slots[(uint64_t)h[0] * B + G.sl];
+        const ulonglong2 s1 = g.slots[(uint64_t)h[1] * B + G.sl];
+        views = 2;
+        const uint32_t e0 = G.ballot(s0.x == kEmpty), e1 = G.ballot(s1.x == kEmpty);
+        if (e0 && e1) {
+          b0 = h[0]; f0 = ffs32(e0) | ((MV_DUP | hc_flag) << 8);
+          b1 = h[1]; f1 = ffs32(e1) | ((MV_DUP | hc_flag) << 8);
           nm = 2;
-          twins = 1;
+          placed = true;
+        } else if (e0) {
+          b0 = h[0]; f0 = ffs32(e0) | (hc_flag << 8); nm = 1;
+          placed = true;
+        } else if (e1) {
+          b0 = h[1]; f0 = ffs32(e1) | (hc_flag << 8); nm = 1;
+          placed = true;
+        } else {
+          const uint32_t full = (1u << B) - 1;
+          const uint32_t d0 = g.meta[h[0]] & full, d1 = g.meta[h[1]] & full;
+          if (d0 || d1) {
+            const int w = d0 ? 0 : 1;
+            const uint32_t b = w == 0 ? h[0] : h[1];
+            const uint32_t ds = ffs32(d0 ? d0 : d1);
+            const uint64_t dk = __shfl(w == 0 ? s0.x : s1.x, G.gshift + (int)ds, 64);
+            uint32_t hd[2];
+            hash_key<2>(g, T, dk, hd);
+            const uint32_t tb = hd[0] == b ? hd[1] : hd[0];
+            const ulonglong2 ts = g.slots[(uint64_t)tb * B + G.sl];
+            const uint32_t tm = G.ballot(ts.x == dk);
+            b0 = tb; f0 = ffs32(tm) | (MV_DUPCLR << 8);
+            b1 = b; f1 = ds | (hc_flag << 8);
+            nm = 2;
+            twins = 1;
+            placed = true;
+          }
+        }
+      } else if (g.balance || g.scheme == CK_QUEUE) {
+        const ulonglong2 s0 = g.slots[(uint64_t)h[0] * B + G.sl];
+        const ulonglong2 s1 = g.slots[(uint64_t)h[1] * B + G.sl];
+        views = 2;
+        const uint32_t e0 = G.ballot(s0.x == kEmpty), e1 = G.ballot(s1.x == kEmpty);
+        const int o0 = B - __popc(e0), o1 = B - __popc(e1);
+        if (o0 < B || o1 < B) {
+          if (o0 <= o1) { b0 = h[0]; f0 = ffs32(e0) | (hc_flag << 8); }
+          else { b0 = h[1]; f0 = ffs32(e1) | (hc_flag << 8); }
+          nm = 1;
           placed = true;
         }
-      }
-    } else if (g.balance || g.scheme == CK_QUEUE) {
-      const ulonglong2 s0 = g.slots[(uint64_t)h[0] * B + G.sl];
-      const ulonglong2 s1 = g.slots[(uint64_t)h[1] * B + G.sl];
-      views = 2;
-      const uint32_t e0 = G.ballot(s0.x == kEmpty), e1 = G.ballot(s1.x == kEmpty);
-      const int o0 = B - __popc(e0), o1 = B - __popc(e1);
-      if (o0 < B || o1 < B) {
-        if (o0 <= o1) { b0 = h[0]; f0 = ffs32(e0) | (hc_flag << 8); }
-        else { b0 = h[1]; f0 = ffs32(e1) | (hc_flag << 8); }
-        nm = 1;
-        placed = true;
-      }
-    } else {
+      } else {
 #pragma unroll
-      for (int hi = 0; hi < H; ++hi) {
-        const ulonglong2 sv = g.slots[(uint64_t)h[hi] * B + G.sl];
-        ++views;
-        const uint32_t e = G.ballot(sv.x == kEmpty);
-        if (e) {
-          b0 = h[hi]; f0 = ffs32(e) | (hc_flag << 8); nm = 1;
-          placed = true;
-          break;
+        for (int hi = 0; hi < H; ++hi) {
+          const ulonglong2 sv = g.slots[(uint64_t)h[hi] * B + G.sl];
+          ++views;
+          const uint32_t e = G.ballot(sv.x == kEmpty);
+          if (e) {
+            b0 = h[hi]; f0 = ffs32(e) | (hc_flag << 8); nm = 1;
+            placed = true;
+            break;
+          }
+        }
+      }
+    }
+    // ops that need a kick-out go to this wavefront's region of the evict
+    // list, in op order, with its count beside it (no shared counter)
+    {
+      const int lane = threadIdx.x & 63;
+      const uint32_t u = c * 4 + (threadIdx.x >> 6);
+      const bool ev = active && leader && !bad && !placed;
+      const uint64_t bal = __ballot(ev);
+      if (ev) r.evict[(size_t)u * opw + __popcll(bal & ((1ull << lane) - 1))] = i;
+      if (lane == 0) r.evict_cnt[u] = (uint32_t)__popcll(bal);
+    }
+    if (active && leader) {
+      ((uint4*)r.hdr)[2 * (size_t)i] = make_uint4(
+          hdr_pack(bad ? PL_FAIL : (placed ? PL_OK : PL_EVICT), twins, nm), views, b0, f0);
+      if (placed) {
+        if (nm > 0) claim(g, r, b0, i);
+        if (nm > 1) {
+          r.imv[(size_t)i * kExtraInline] = IMove{b1, f1};
+          claim(g, r, b1, i);
         }
       }
     }
   }
-  // ops that need a kick-out go to this block's region of the evict list, in
-  // op order, with the block's count beside it (no shared counter)
-  {
-    __shared__ uint32_t s_wcnt[4];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const bool ev = active && leader && !bad && !placed;
-    const uint64_t bal = __ballot(ev);
-    if (lane == 0) s_wcnt[wv] = (uint32_t)__popcll(bal);
-    __syncthreads();
-    uint32_t pre = 0;
-    for (int w = 0; w < wv; ++w) pre += s_wcnt[w];
-    if (ev)
-      r.evict[(size_t)blockIdx.x * r.fresh_opb + pre + __popcll(bal & ((1ull << lane) - 1))] = i;
-    if (threadIdx.x == 0) r.evict_cnt[blockIdx.x] = s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
-  }
-  if (!active || !leader) return;
-  ((uint4*)r.hdr)[2 * (size_t)i] =
-      make_uint4(hdr_pack(bad ? PL_FAIL : (placed ? PL_OK : PL_EVICT), twins, nm), views, b0, f0);
-  if (!placed) return;
-  if (nm > 0) claim(g, r, b0, i);
-  if (nm > 1) {
-    r.imv[(size_t)i * kExtraInline] = IMove{b1, f1};
-    claim(g, r, b1, i);
-  }
 }
 
 // ---------------------------------------------------------------------------
-// The ops of one round that need an eviction plan: fresh-planner block b put
-// its evict_cnt[b] ops at evict[b * fresh_opb + j], j < evict_cnt[b].
-// Positions are numbered slot-major, q = j * nb + b (nb blocks), so each
-// stretch of q holds one slot index of every block.  Eviction-planner
+// The ops of one round that need an eviction plan: fresh-planner wavefront b
+// put its evict_cnt[b] ops at evict[b * opw + j], j < evict_cnt[b] (opw = 64 /
+// B ops per wavefront).  Positions are numbered slot-major, q = j * nb + b (nb
+// wavefronts), so each stretch of q holds one slot index of every wavefront.  Eviction-planner
 // workgroup w takes q = w, w + gridDim.x, w + 2 gridDim.x, ...: an even
 // sample of every slot layer, hence an equal share of the occupied
 // positions; its item k is its k-th occupied position.  The wavefront checks
@@ -438,7 +488,7 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
 struct EvictWork {
   const uint32_t* list = nullptr;
   const uint32_t* cnt = nullptr;
-  uint64_t npos = 0;   // fresh_blocks * fresh_opb
+  uint64_t npos = 0;   // fresh-planner wavefronts * opw
   uint32_t opb = 1, nb = 1;
   uint32_t c0 = 0;     // window: positions w + (64 c0 + lane) gridDim.x
   uint64_t vmask = 0;  // occupied positions of the window
@@ -454,11 +504,13 @@ struct EvictWork {
     vmask = (uint64_t)__ballot(v);
     wtot = (uint32_t)__popcll(vmask);
   }
-  __device__ void init(const Round& r) {
+  __device__ void init(const Round& r, uint32_t opw) {  // all 64 lanes together
+    Pending P;
+    P.init(r);
     list = r.evict;
     cnt = r.evict_cnt;
-    opb = r.fresh_opb;
-    nb = r.fresh_blocks;
+    opb = opw;
+    nb = (P.n + opb - 1) / opb;
     npos = (uint64_t)nb * opb;
     base = 0;
     window(0);
@@ -853,7 +905,7 @@ __global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
   }
   wave_sync();
   EvictWork Wk;
-  Wk.init(r);
+  Wk.init(r, 64 / B);
   // the group's op of batch kb is item kb + gi; item() is wave-uniform
   auto batch_item = [&](uint32_t kb) -> uint32_t {
     uint32_t mine = kNone;
@@ -993,7 +1045,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
   }
   wave_sync();
   EvictWork Wk;
-  Wk.init(r);
+  Wk.init(r, 64 / B);
   // the group's op of batch kb is item kb + gi; item() is wave-uniform
   auto batch_item = [&](uint32_t kb) -> uint32_t {
     uint32_t mine = kNone;
@@ -1568,6 +1620,12 @@ size_t evict_wg_scratch_bytes(const Geo& g) {
   return (64 / kWalkW) * walk_group_scratch_bytes(g);
 }
 
+// Workgroups of a launch after a sub-batch's first round, whose pending count
+// is known only on the device: enough to fill the device, each taking as
+// many passes as the count needs.
+constexpr uint32_t kTailPlanBlocks = 2048;
+constexpr uint32_t kTailCommitBlocks = 1024;
+
 template <int B, int H>
 static void evict_go(const Geo& g, const Round& r, uint32_t grid, hipStream_t s) {
   const size_t lds = evict_lds_bytes(g);
@@ -1580,7 +1638,8 @@ static void evict_go(const Geo& g, const Round& r, uint32_t grid, hipStream_t s)
 template <int B, int H>
 static void fresh_go(const Geo& g, const Round& r, hipStream_t s) {
   const uint64_t threads = (uint64_t)r.npend * B;
-  const uint32_t grid = (uint32_t)((threads + 255) / 256);
+  uint32_t grid = (uint32_t)((threads + 255) / 256);
+  if (!r.first) grid = std::min(grid, kTailPlanBlocks);
   hipLaunchKernelGGL((k_plan_fresh<B, H>), dim3(grid), dim3(256), 0, s, g, r);
 }
 
@@ -1613,15 +1672,8 @@ hipError_t launch_plan_evict(const Geo& g, const Round& r, uint32_t grid, hipStr
 // delete planning: B lanes per op
 // ---------------------------------------------------------------------------
 template <int B, int H>
-__global__ __launch_bounds__(256) void k_plan_delete(Geo g, Round r) {
-  GroupCtx<B> G;
-  G.lane = threadIdx.x & 63;
-  G.sl = G.lane % B;
-  G.gshift = G.lane - G.sl;
-  if (blockIdx.x == 0 && threadIdx.x == 0) round_start(r);
-  const uint64_t gidx = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / B;
-  if (gidx >= npend_of(r)) return;
-  const uint32_t i = r.first ? (uint32_t)gidx : r.pend[gidx];
+__device__ __forceinline__ void delete_one(const Geo& g, const Round& r, const GroupCtx<B>& G,
+                                           uint32_t i) {
   if (r.first && G.sl == 0) zero_op_counters(r, i);
   const uint64_t x = r.keys[i];
   const bool leader = G.sl == 0;
@@ -1667,9 +1719,27 @@ __global__ __launch_bounds__(256) void k_plan_delete(Geo g, Round r) {
 }
 
 template <int B, int H>
+__global__ __launch_bounds__(256) void k_plan_delete(Geo g, Round r) {
+  GroupCtx<B> G;
+  G.lane = threadIdx.x & 63;
+  G.sl = G.lane % B;
+  G.gshift = G.lane - G.sl;
+  if (blockIdx.x == 0) round_start(r);
+  Pending P;
+  P.init(r);
+  constexpr uint32_t opb = 256 / B;
+  const uint32_t passes = (P.n + opb - 1) / opb;
+  for (uint32_t c = blockIdx.x; c < passes; c += gridDim.x) {
+    const uint32_t i = P.at(c * opb + threadIdx.x / B);
+    if (i != kNone) delete_one<B, H>(g, r, G, i);
+  }
+}
+
+template <int B, int H>
 static void delete_go(const Geo& g, const Round& r, hipStream_t s) {
   const uint64_t threads = (uint64_t)r.npend * B;
-  const uint32_t grid = (uint32_t)((threads + 255) / 256);
+  uint32_t grid = (uint32_t)((threads + 255) / 256);
+  if (!r.first) grid = std::min(grid, kTailPlanBlocks);
   hipLaunchKernelGGL((k_plan_delete<B, H>), dim3(grid), dim3(256), 0, s, g, r);
 }
 
@@ -1696,46 +1766,37 @@ __device__ __forceinline__ void sc_increment(uint32_t* meta) {
 
 constexpr int kCommitLanes = 4;  // lanes per plan in the commit kernel
 
+// The commit kernel, four lanes per plan, in two phases per plan: decide
+// (header, claim check; for a loser its retry count) and apply (the writes).
+// Between them each wavefront lists its losers for the next round: the
+// atomic that reserves their list entries is issued before the writes and
+// its result is used after them, so its latency hides behind them.
 __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
   constexpr int CL = kCommitLanes;
   const int lane = threadIdx.x & 63;
   const int gl = lane & (CL - 1);
   const int gshift = lane & ~(CL - 1);
-  const uint64_t gidx = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / CL;
-  if (gidx >= npend_of(r)) return;
-  const uint32_t i = r.first ? (uint32_t)gidx : r.pend[gidx];
   const bool leader = gl == 0;
+  Pending P;
+  P.init(r);
   // set by an earlier kernel: a plain load, once per wavefront, broadcast
-  const int first = __ffsll((unsigned long long)__ballot(true)) - 1;
   uint32_t ov = 0;
-  if (lane == first) ov = r.ctr->overflow;
-  const bool void_round = __shfl(ov, first, 64) != 0;
-  if (gidx == 0 && leader && !void_round) atomicAdd(&r.ctr->rounds, 1u);
-  bool requeue = false;
-  uint32_t n_spawn = 0, spawn_off = 0;
-  if (void_round) {  // a planner ran out of arena: nothing of this round applies
-    requeue = true;
-  } else {
-    // the header's first half; its second half only for arena plans
-    const uint4 h0 = ((const uint4*)r.hdr)[2 * (size_t)i];
-    const uint32_t status = h0.x & 0xF, twins = (h0.x >> 4) & 0xF, nmv = (h0.x >> 8) & 0xFFFFF;
-    const bool inl = (h0.x & kHdrArena) == 0;
-    const uint32_t h_views = h0.y;
-    const uint32_t off = h0.z, mv0_bin = h0.z, mv0_sf = h0.w;
-    const uint32_t h_kicks = inl ? 0u : h0.w;
-    uint32_t h_nsp = 0, h_soff = 0;
-    if (!inl) {
-      const uint4 h1 = ((const uint4*)r.hdr)[2 * (size_t)i + 1];
-      h_nsp = h1.x;
-      h_soff = h1.y;
-    }
-    const uint64_t x = r.keys[i];
-    const uint64_t xa = (inl && r.vals) ? load_aux(r.vals, i, g.B) : 0;
+  if (lane == 0) ov = r.ctr->overflow;
+  const bool void_round = __shfl(ov, 0, 64) != 0;
+  const uint32_t passes = (P.n + kCommitOps - 1) / kCommitOps;
+  for (uint32_t c = blockIdx.x; c < passes; c += gridDim.x) {
+    const uint32_t pos = c * kCommitOps + threadIdx.x / CL;
+    const uint32_t i = P.at(pos);
+    // ---- decide ----
+    uint32_t status = 0, twins = 0, nmv = 0, views = 0, off = 0, mv0_sf = 0, kicks = 0;
+    uint32_t n_spawn = 0, spawn_off = 0, lost = 0, retries = 0;
+    uint64_t x = 0, xa = 0;
+    bool live = false, inl = true, win = false, requeue = false, abort = false;
     // move j of the plan: bin, slot, flags and the record it writes
     auto get = [&](uint32_t j, uint32_t& bin, uint32_t& slot, uint32_t& fl, uint64_t& k,
                    uint64_t& a) {
       if (inl) {
-        uint32_t mb = mv0_bin, msf = mv0_sf;
+        uint32_t mb = off, msf = mv0_sf;
         if (j > 0) {
           const IMove m = r.imv[(size_t)i * kExtraInline + (j - 1)];
           mb = m.bin;
@@ -1755,140 +1816,112 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
         a = m.aux;
       }
     };
-    const unsigned long long me = r.tag | (unsigned long long)i;
-    bool mine = true;
-    for (uint32_t j = gl; j < nmv; j += CL) {
-      uint32_t bin, slot, fl;
-      uint64_t k, a;
-      get(j, bin, slot, fl, k, a);
-      if (g.owner[bin] != me) mine = false;
-    }
-    const bool win = ((__ballot(!mine) >> gshift) & ((1ull << CL) - 1)) == 0;
-    if (win) {
-      // chain written from its end backwards (Sec. 8.2 system-transaction order)
-      for (int base = (int)nmv - 1; base >= 0; base -= CL) {
-        const int j = base - gl;
-        if (j < 0) continue;
-        uint32_t bin, slot, fl;
-        uint64_t k, a;
-        get((uint32_t)j, bin, slot, fl, k, a);
-        uint32_t* mw = g.meta + bin;
-        if (fl & MV_DUPCLR) {
-          atomicAnd(mw, ~(1u << slot));
-          continue;
-        }
-        if (!(fl & MV_SUPERSEDED)) {
-          g.slots[(uint64_t)bin * g.B + slot] =
-              (fl & MV_CLEAR) ? make_ulonglong2(kEmpty, 0ull) : make_ulonglong2(k, a);
-          if (g.ghost) {
-            if (fl & MV_DUP) atomicOr(mw, 1u << slot);
-            else atomicAnd(mw, ~(1u << slot));
-          }
-        }
-        if (fl & MV_HC) atomicAdd(mw, 1u << 24);
-      }
-      if (leader) {
-        uint8_t st;
-        if (x == kEmpty) st = CK_OP_BAD_KEY;
-        else if (r.is_delete) st = status == PL_OK ? CK_OP_OK : CK_OP_NOT_FOUND;
-        else st = status == PL_OK ? CK_OP_OK : CK_OP_FAIL_CHAIN;
-        r.status[i] = st;
-        r.op_views[i] = h_views;
-        if (h_kicks) r.op_kicks[i] = h_kicks;
-        if (twins) r.op_twins[i] = twins;
-      }
-    } else if (leader) {
-      r.op_lost[i] += h_views;
-      const uint32_t rt = r.op_retries[i] + 1;
-      r.op_retries[i] = rt;
-      if (r.max_rounds && rt >= r.max_rounds) {
-        r.status[i] = CK_OP_ABORTED;
-        r.op_views[i] = 0;
-      } else {
+    if (i != kNone) {
+      if (pos == 0 && leader && !void_round) atomicAdd(&r.ctr->rounds, 1u);
+      if (void_round) {  // a planner ran out of arena: nothing of this round applies
         requeue = true;
+      } else {
+        live = true;
+        // the header's first half; its second half only for arena plans
+        const uint4 h0 = ((const uint4*)r.hdr)[2 * (size_t)i];
+        status = h0.x & 0xF;
+        twins = (h0.x >> 4) & 0xF;
+        nmv = (h0.x >> 8) & 0xFFFFF;
+        inl = (h0.x & kHdrArena) == 0;
+        views = h0.y;
+        off = h0.z;  // inline: the first move's bin; arena: the moves' offset
+        mv0_sf = h0.w;
+        kicks = inl ? 0u : h0.w;
+        if (!inl) {
+          const uint4 h1 = ((const uint4*)r.hdr)[2 * (size_t)i + 1];
+          n_spawn = h1.x;
+          spawn_off = h1.y;
+        }
+        x = r.keys[i];
+        xa = (inl && r.vals) ? load_aux(r.vals, i, g.B) : 0;
+        const unsigned long long me = r.tag | (unsigned long long)i;
+        bool mine = true;
+        for (uint32_t j = gl; j < nmv; j += CL) {
+          uint32_t bin, slot, fl;
+          uint64_t k, a;
+          get(j, bin, slot, fl, k, a);
+          if (g.owner[bin] != me) mine = false;
+        }
+        win = ((__ballot(!mine) >> gshift) & ((1ull << CL) - 1)) == 0;
+        if (!win && leader) {
+          lost = r.op_lost[i] + views;
+          retries = r.op_retries[i] + 1;
+          abort = r.max_rounds && retries >= r.max_rounds;
+          requeue = !abort;
+        }
       }
     }
-    n_spawn = h_nsp;
-    spawn_off = h_soff;
+    // ---- the ops that go again: segment u % kStripes of the next list
+    // (u = this wavefront's index), one atomic add per wavefront that has any
+    const bool rq = requeue && leader;
+    const uint64_t bal = __ballot(rq);
+    const uint32_t nrq = (uint32_t)__popcll(bal);
+    const uint32_t sg = (c * 4 + (threadIdx.x >> 6)) % kStripes;
+    uint32_t base = 0;
+    if (nrq && lane == 0) base = atomicAdd(&r.next_cnt[sg * kStripeWords], nrq);
+    // ---- apply ----
+    if (live) {
+      if (win) {
+        // chain written from its end backwards (Sec. 8.2 system-transaction order)
+        for (int top = (int)nmv - 1; top >= 0; top -= CL) {
+          const int j = top - gl;
+          if (j < 0) continue;
+          uint32_t bin, slot, fl;
+          uint64_t k, a;
+          get((uint32_t)j, bin, slot, fl, k, a);
+          uint32_t* mw = g.meta + bin;
+          if (fl & MV_DUPCLR) {
+            atomicAnd(mw, ~(1u << slot));
+            continue;
+          }
+          if (!(fl & MV_SUPERSEDED)) {
+            g.slots[(uint64_t)bin * g.B + slot] =
+                (fl & MV_CLEAR) ? make_ulonglong2(kEmpty, 0ull) : make_ulonglong2(k, a);
+            if (g.ghost) {
+              if (fl & MV_DUP) atomicOr(mw, 1u << slot);
+              else atomicAnd(mw, ~(1u << slot));
+            }
+          }
+          if (fl & MV_HC) atomicAdd(mw, 1u << 24);
+        }
+        if (leader) {
+          uint8_t st;
+          if (x == kEmpty) st = CK_OP_BAD_KEY;
+          else if (r.is_delete) st = status == PL_OK ? CK_OP_OK : CK_OP_NOT_FOUND;
+          else st = status == PL_OK ? CK_OP_OK : CK_OP_FAIL_CHAIN;
+          r.status[i] = st;
+          r.op_views[i] = views;
+          if (kicks) r.op_kicks[i] = kicks;
+          if (twins) r.op_twins[i] = twins;
+        }
+      } else if (leader) {
+        r.op_lost[i] = lost;
+        r.op_retries[i] = retries;
+        if (abort) {
+          r.status[i] = CK_OP_ABORTED;
+          r.op_views[i] = 0;
+        }
+      }
+      // spawn counts (Sec. 5) of every plan, committed or not, saturating at 15
+      for (uint32_t j = gl; j < n_spawn; j += CL) sc_increment(g.meta + r.spawns[spawn_off + j]);
+    }
+    if (nrq) {
+      base = __shfl(base, 0, 64);
+      if (rq) r.next[(size_t)sg * r.stripe_cap + base + __popcll(bal & ((1ull << lane) - 1))] = i;
+    }
   }
-  if (leader) r.req[gidx] = requeue ? 1 : 0;
-  // spawn counts (Sec. 5) of every plan, committed or not, saturating at 15
-  for (uint32_t j = gl; j < n_spawn; j += CL) sc_increment(g.meta + r.spawns[spawn_off + j]);
 }
 
 hipError_t launch_commit(const Geo& g, const Round& r, hipStream_t s) {
   if (r.npend == 0) return hipSuccess;
-  const uint64_t threads = (uint64_t)r.npend * kCommitLanes;
-  const uint32_t grid = (uint32_t)((threads + 255) / 256);
+  uint32_t grid = (uint32_t)(((uint64_t)r.npend + kCommitOps - 1) / kCommitOps);
+  if (!r.first) grid = std::min(grid, kTailCommitBlocks);
   hipLaunchKernelGGL(k_commit, dim3(grid), dim3(256), 0, s, g, r);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// ordered stream compaction of the pending list (count, scan, scatter): the
-// evict list and the next round's pending list, in op order, without any
-// shared counter
-// ---------------------------------------------------------------------------
-// The next round's pending list: the ops whose commit flagged them to go
-// again.  The order of the list is immaterial (every kernel's result for an
-// op depends on the op, never on its position), so one launch does it: each
-// block takes 4096 flags (16 per thread), scans them, reserves its output
-// range with one atomic add on the count (a few hundred per launch at most)
-// and writes its ops.  The count was zeroed at the start of the round.
-constexpr int kCompPer = 16;                // flags per thread
-constexpr int kCompTile = 256 * kCompPer;   // flags per block
-
-__device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-__global__ __launch_bounds__(256) void k_compact(Round r, uint32_t* out, uint32_t* count) {
-  __shared__ uint32_t ws[4];
-  __shared__ uint32_t s_base;
-  const uint32_t n = npend_of(r);
-  const uint32_t base = blockIdx.x * kCompTile + threadIdx.x * kCompPer;
-  uint32_t bits = 0;
-  if (base + kCompPer <= n) {
-    const uint4 f = *(const uint4*)(r.req + base);  // 16 flag bytes, 16-byte aligned
-    const uint32_t w[4] = {f.x, f.y, f.z, f.w};
-#pragma unroll
-    for (int k = 0; k < kCompPer; ++k)
-      if ((w[k >> 2] >> ((k & 3) * 8)) & 0xFFu) bits |= 1u << k;
-  } else {
-    for (int k = 0; k < kCompPer; ++k)
-      if (base + k < n && r.req[base + k]) bits |= 1u << k;
-  }
-  const uint32_t c = __popc(bits);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  uint32_t x = c;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) ws[wv] = x;
-  __syncthreads();
-  uint32_t wpre = 0;
-  for (int w = 0; w < wv; ++w) wpre += ws[w];
-  if (threadIdx.x == 0) {
-    const uint32_t tot = ws[0] + ws[1] + ws[2] + ws[3];
-    s_base = tot ? atomicAdd(count, tot) : 0u;
-  }
-  __syncthreads();
-  uint32_t pos = s_base + wpre + x - c;
-  while (bits) {
-    const int k = __ffs(bits) - 1;
-    bits &= bits - 1;
-    out[pos++] = r.first ? base + k : r.pend[base + k];
-  }
-}
-
-hipError_t launch_compact(const Round& r, uint32_t* out, uint32_t* count, hipStream_t s) {
-  const uint32_t nb = (r.npend + kCompTile - 1) / kCompTile;
-  if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_compact, dim3(nb), dim3(256), 0, s, r, out, count);
   return hipGetLastError();
 }
 
@@ -1897,9 +1930,25 @@ hipError_t launch_compact(const Round& r, uint32_t* out, uint32_t* count, hipStr
 // ---------------------------------------------------------------------------
 constexpr int kStatBlock = 1024;
 
+// The sub-batch still has pending ops (its last list is not empty): the
+// statistics kernels then leave everything untouched.  One wavefront per
+// workgroup reads the counts; every thread of the workgroup calls it.
+__device__ __forceinline__ bool stats_closed_out(const uint32_t* open) {
+  if (!open) return false;
+  __shared__ uint32_t s_open;
+  if (threadIdx.x < 64) {
+    const bool o = list_open(open);
+    if (threadIdx.x == 0) s_open = o ? 1u : 0u;
+  }
+  __syncthreads();
+  return s_open != 0;
+}
+
 // pass 1: successful inserts per block of 1024 ops
 __global__ __launch_bounds__(kStatBlock) void k_stats_count(const uint8_t* status, uint64_t m,
-                                                            uint32_t* block_ok) {
+                                                            uint32_t* block_ok,
+                                                            const uint32_t* open) {
+  if (stats_closed_out(open)) return;
   __shared__ uint32_t s_sum;
   if (threadIdx.x == 0) s_sum = 0;
   __syncthreads();
@@ -1913,7 +1962,9 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_count(const uint8_t* statu
 
 // pass 2 (one block): exclusive scan of the block counts; snapshot `stored`
 __global__ __launch_bounds__(kStatBlock) void k_stats_scan(uint32_t* block_ok, uint32_t nblocks,
-                                                           DevStats* st, uint64_t* stored_before) {
+                                                           DevStats* st, uint64_t* stored_before,
+                                                           const uint32_t* open) {
+  if (stats_closed_out(open)) return;
   __shared__ uint32_t carry;
   __shared__ uint32_t wsum[kStatBlock / 64];
   if (threadIdx.x == 0) {
@@ -1949,7 +2000,8 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_scan(uint32_t* block_ok, u
 __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
     const uint8_t* status, const uint32_t* views, const uint32_t* lost, const uint32_t* kicks,
     const uint32_t* retries, const uint32_t* twins, uint64_t m, const uint32_t* block_ok,
-    const uint64_t* stored_before, uint64_t slots, DevStats* st) {
+    const uint64_t* stored_before, uint64_t slots, DevStats* st, const uint32_t* open) {
+  if (stats_closed_out(open)) return;
   __shared__ unsigned long long hb[4][CK_BANDS];
   __shared__ unsigned long long tot[11];
   __shared__ uint32_t wsum[kStatBlock / 64];
@@ -2069,16 +2121,20 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
 }
 
 // deletes: found/probes/retries totals; `stored` decreases by the found count
-__global__ __launch_bounds__(256) void k_stats_delete(const uint8_t* status, const uint32_t* probes,
-                                                      const uint32_t* retries, uint64_t m,
-                                                      DevStats* st) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kStatBlock) void k_stats_delete(const uint8_t* status,
+                                                             const uint32_t* probes,
+                                                             const uint32_t* retries, uint64_t m,
+                                                             DevStats* st, const uint32_t* open) {
+  if (stats_closed_out(open)) return;
   unsigned long long d = 0, f = 0, p = 0, rt = 0;
-  if (i < m && status[i] != CK_OP_BAD_KEY) {
-    d = 1;
-    f = status[i] == CK_OP_OK;
-    p = probes[i];
-    rt = retries[i];
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    if (status[i] != CK_OP_BAD_KEY) {
+      d += 1;
+      f += status[i] == CK_OP_OK;
+      p += probes[i];
+      rt += retries[i];
+    }
   }
   d = wave_sum(d); f = wave_sum(f); p = wave_sum(p); rt = wave_sum(rt);
   if ((threadIdx.x & 63) == 0) {
@@ -2093,22 +2149,23 @@ __global__ __launch_bounds__(256) void k_stats_delete(const uint8_t* status, con
 }
 
 hipError_t launch_batch_stats(const Round& r, uint64_t m, uint64_t slots, uint32_t* block_tmp,
-                              uint32_t is_delete, hipStream_t s) {
+                              uint32_t is_delete, const uint32_t* open, hipStream_t s) {
   if (m == 0) return hipSuccess;
+  const uint32_t nb = (uint32_t)((m + kStatBlock - 1) / kStatBlock);
   if (is_delete) {
-    hipLaunchKernelGGL(k_stats_delete, dim3((uint32_t)((m + 255) / 256)), dim3(256), 0, s,
-                       r.status, r.op_views, r.op_retries, m, r.stats);
+    hipLaunchKernelGGL(k_stats_delete, dim3(std::min<uint32_t>(nb, 256)), dim3(kStatBlock), 0, s,
+                       r.status, r.op_views, r.op_retries, m, r.stats, open);
     return hipGetLastError();
   }
-  const uint32_t nb = (uint32_t)((m + kStatBlock - 1) / kStatBlock);
   uint64_t* stored_before = (uint64_t*)(block_tmp + ((nb + 63) & ~63u));
-  hipLaunchKernelGGL(k_stats_count, dim3(nb), dim3(kStatBlock), 0, s, r.status, m, block_tmp);
+  hipLaunchKernelGGL(k_stats_count, dim3(nb), dim3(kStatBlock), 0, s, r.status, m, block_tmp,
+                     open);
   hipLaunchKernelGGL(k_stats_scan, dim3(1), dim3(kStatBlock), 0, s, block_tmp, nb, r.stats,
-                     stored_before);
+                     stored_before, open);
   hipLaunchKernelGGL(k_stats_apply, dim3(std::min<uint32_t>(nb, 256)), dim3(kStatBlock), 0, s,
                      r.status, r.op_views,
                      r.op_lost, r.op_kicks, r.op_retries, r.op_twins, m, block_tmp,
-                     stored_before, slots, r.stats);
+                     stored_before, slots, r.stats, open);
   return hipGetLastError();
 }
 

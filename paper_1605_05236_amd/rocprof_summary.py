@@ -2,6 +2,7 @@
 
     python -m paper_1605_05236_amd.rocprof_summary --trace K.db \
         [--fetch F.db --write W.db] [--kernels REGEX] [--calibration-kib 262144]
+        [--group NAME=REGEX ...]
 
 * --trace: a `rocprofv3 --kernel-trace` database: calls, total and average
   duration per kernel.
@@ -11,6 +12,9 @@
   benchmark's --pmc-calibration option): the first copyBuffer dispatches whose
   WRITE_SIZE is at least half the copy size.  Output: HBM MiB per launch and
   the achieved HBM rate of every kernel.
+* --group NAME=REGEX: one more line per group of kernels taken together (for
+  example the planners that share one role): launches, average duration, and
+  HBM bytes per launch averaged over the group's launches.
 """
 from __future__ import annotations
 
@@ -70,6 +74,7 @@ def main():
     ap.add_argument("--kernels", default=".*")
     ap.add_argument("--calibration-kib", type=float, default=262144.0)
     ap.add_argument("--top", type=int, default=25)
+    ap.add_argument("--group", action="append", default=[])
     a = ap.parse_args()
     t = kernel_times(a.trace)
     f = w = None
@@ -97,6 +102,25 @@ def main():
             wr = wm[1] * cw / 1024 / max(wm[0], 1)
             gbs = (rd + wr) * n * 1048576 / (us * 1e-6) / 1e9 if us else 0.0
             line += f" {rd:.2f} | {wr:.2f} | {gbs:.0f} |"
+        print(line)
+    for spec in a.group:
+        name, rx = spec.split("=", 1)
+        g = re.compile(rx)
+        ks = [k for k in t if g.search(k)]
+        n = sum(t[k][0] for k in ks)
+        us = sum(t[k][1] for k in ks)
+        if not n:
+            print(f"group {name}: no launches")
+            continue
+        line = f"group {name} ({', '.join(sorted(ks))}): {n} launches, {us / n:.2f} us average"
+        if f is not None:
+            rd = sum(f.get(k, [0, 0.0])[1] for k in ks) * cf * 1024
+            wr = sum(w.get(k, [0, 0.0])[1] for k in ks) * cw * 1024
+            nf = sum(f.get(k, [0, 0.0])[0] for k in ks)
+            nw = sum(w.get(k, [0, 0.0])[0] for k in ks)
+            line += (f", HBM bytes per launch: read {rd / max(nf, 1):.0f}, "
+                     f"write {wr / max(nw, 1):.0f}, "
+                     f"total {rd / max(nf, 1) + wr / max(nw, 1):.0f}")
         print(line)
 
 

@@ -44,7 +44,7 @@ class CkKernelTime(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_uint64), ("ms", ctypes.c_double)]
 
 
-_TIMED = ["plan_fresh", "plan_evict", "plan_delete", "commit", "compact", "stats", "lookup"]
+_TIMED = ["plan_fresh", "plan_evict", "plan_delete", "commit", "stats", "lookup"]
 TIME_ALL = 127
 
 
