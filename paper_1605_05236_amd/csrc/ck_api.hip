@@ -518,11 +518,27 @@ ck_status ck_delete(ck_table* t, const uint64_t* keys, uint64_t n, uint8_t* foun
                      (hipStream_t)stream);
 }
 
+// The sum of the device accumulators' copies (the maximum for max_kicks).
+static DevStatLine stats_sum(const DevStats& ds) {
+  DevStatLine d;
+  std::memset(&d, 0, sizeof(d));
+  for (int k = 0; k < kStatStripes; ++k) {
+    const DevStatLine& x = ds.s[k];
+    for (int j = 0; j < 19; ++j)
+      d.v[j] = j == S_MAX_KICKS ? std::max(d.v[j], x.v[j]) : d.v[j] + x.v[j];
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < CK_BANDS; ++b) d.band[a][b] += x.band[a][b];
+  }
+  return d;
+}
+
 ck_status ck_stats_get(ck_table* t, ck_stats* out, void* stream) {
   if (!t || !out) return CK_EINVAL;
-  DevStats d;
-  HIP_TRY(hipMemcpyAsync(&d, t->dstats, sizeof(d), hipMemcpyDeviceToHost, (hipStream_t)stream));
+  std::vector<DevStats> dv(1);
+  HIP_TRY(hipMemcpyAsync(dv.data(), t->dstats, sizeof(DevStats), hipMemcpyDeviceToHost,
+                         (hipStream_t)stream));
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  const DevStatLine d = stats_sum(dv[0]);
   std::memset(out, 0, sizeof(*out));
   out->inserts_ok = d.v[S_INS_OK];
   out->inserts_failed = d.v[S_INS_FAIL];
@@ -554,13 +570,15 @@ ck_status ck_stats_get(ck_table* t, ck_stats* out, void* stream) {
 
 ck_status ck_stats_reset(ck_table* t, void* stream) {
   if (!t) return CK_EINVAL;
-  DevStats d;
-  HIP_TRY(hipMemcpyAsync(&d, t->dstats, sizeof(d), hipMemcpyDeviceToHost, (hipStream_t)stream));
+  std::vector<DevStats> dv(1);
+  HIP_TRY(hipMemcpyAsync(dv.data(), t->dstats, sizeof(DevStats), hipMemcpyDeviceToHost,
+                         (hipStream_t)stream));
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
-  const unsigned long long stored = d.v[S_STORED];
-  std::memset(&d, 0, sizeof(d));
-  d.v[S_STORED] = stored;
-  HIP_TRY(hipMemcpyAsync(t->dstats, &d, sizeof(d), hipMemcpyHostToDevice, (hipStream_t)stream));
+  const unsigned long long stored = stats_sum(dv[0]).v[S_STORED];
+  std::memset(dv.data(), 0, sizeof(DevStats));
+  dv[0].s[0].v[S_STORED] = stored;
+  HIP_TRY(hipMemcpyAsync(t->dstats, dv.data(), sizeof(DevStats), hipMemcpyHostToDevice,
+                         (hipStream_t)stream));
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
   t->rounds = 0;
   t->lookups = 0;
@@ -647,9 +665,11 @@ ck_status ck_import(ck_table* t, const uint64_t* keys, const uint64_t* vals,
   HIP_TRY(hipMemcpyAsync(t->g.slots, buf.data(), S * 16, hipMemcpyHostToDevice, (hipStream_t)stream));
   HIP_TRY(hipMemcpyAsync(t->g.meta, meta, t->bins * 4, hipMemcpyHostToDevice, (hipStream_t)stream));
   HIP_TRY(hipMemsetAsync(t->g.owner, 0xFF, t->bins * 8, (hipStream_t)stream));
-  unsigned long long stored = single + dups / 2;
-  HIP_TRY(hipMemcpyAsync(&t->dstats->v[S_STORED], &stored, 8, hipMemcpyHostToDevice,
-                         (hipStream_t)stream));
+  // the table's count goes to the first copy, the other copies' counts are zeroed
+  const unsigned long long stored[2] = {single + dups / 2, 0};
+  for (int k = 0; k < kStatStripes; ++k)
+    HIP_TRY(hipMemcpyAsync(&t->dstats->s[k].v[S_STORED], &stored[k == 0 ? 0 : 1], 8,
+                           hipMemcpyHostToDevice, (hipStream_t)stream));
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
   return CK_OK;
 }

@@ -97,9 +97,18 @@ struct Ctr {             // device counters of the round loop
   uint32_t cnt[2][kStripes * kStripeWords];  // segment counts of pending list p
 };
 
-struct DevStats {        // device accumulators (mirrors ck_stats)
+// Device accumulators (they mirror ck_stats), in kStatStripes copies:
+// workgroup w adds into copy w % kStatStripes, so the few adds per workgroup
+// of a statistics or lookup launch spread over separate lines instead of
+// serialising on one; readers sum the copies (`stored` included).
+constexpr int kStatStripes = 16;
+struct DevStatLine {
   unsigned long long v[19];
+  unsigned long long pad[13];  // 256 bytes
   unsigned long long band[4][CK_BANDS];
+};
+struct DevStats {
+  DevStatLine s[kStatStripes];
 };
 enum {
   S_INS_OK, S_INS_FAIL, S_INS_ABORT, S_INS_BAD, S_VIEWS, S_VIEWS_ALL, S_KICKS, S_MAX_KICKS,

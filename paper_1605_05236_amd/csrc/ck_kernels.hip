@@ -257,7 +257,8 @@ __global__ __launch_bounds__(256) void k_lookup(Geo g, const uint64_t* __restric
       hits_acc += hit ? 1 : 0;
     }
   }
-  block_add2(probes_acc, hits_acc, &st->v[S_LOOKUP_PROBES], &st->v[S_LOOKUP_HITS]);
+  DevStatLine& sl = st->s[blockIdx.x % kStatStripes];
+  block_add2(probes_acc, hits_acc, &sl.v[S_LOOKUP_PROBES], &sl.v[S_LOOKUP_HITS]);
 }
 
 template <int B, int LPP, int H>
@@ -1944,59 +1945,53 @@ __device__ __forceinline__ bool stats_closed_out(const uint32_t* open) {
   return s_open != 0;
 }
 
-// pass 1: successful inserts per block of 1024 ops
+// Two passes over the sub-batch, both over the same partition: workgroup k
+// takes tiles [k per, (k + 1) per) of kStatBlock ops (at most 256 workgroups,
+// so the few same-address adds per workgroup stay cheap).
+struct StatSplit {
+  uint32_t ntiles, per;
+  __host__ __device__ StatSplit(uint64_t m, uint32_t grid)
+      : ntiles((uint32_t)((m + kStatBlock - 1) / kStatBlock)),
+        per((ntiles + grid - 1) / grid) {}
+};
+constexpr uint32_t kStatMaxGrid = 256;
+
+// pass 1: successful inserts per workgroup; workgroup 0 snapshots `stored`
+// (no other kernel of the sub-batch changes it before pass 2 has read it)
 __global__ __launch_bounds__(kStatBlock) void k_stats_count(const uint8_t* status, uint64_t m,
                                                             uint32_t* block_ok,
+                                                            uint64_t* stored_before,
+                                                            const DevStats* st,
                                                             const uint32_t* open) {
   if (stats_closed_out(open)) return;
-  __shared__ uint32_t s_sum;
-  if (threadIdx.x == 0) s_sum = 0;
+  __shared__ uint32_t s_w[kStatBlock / 64];
+  const StatSplit sp(m, gridDim.x);
+  const uint32_t t0 = blockIdx.x * sp.per, t1 = min(sp.ntiles, t0 + sp.per);
+  uint32_t n = 0;
+  for (uint32_t tile = t0; tile < t1; ++tile) {
+    const uint64_t i = (uint64_t)tile * kStatBlock + threadIdx.x;
+    n += (i < m && status[i] == CK_OP_OK) ? 1u : 0u;
+  }
+  n = (uint32_t)wave_sum(n);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = n;
   __syncthreads();
-  const uint64_t i = (uint64_t)blockIdx.x * kStatBlock + threadIdx.x;
-  const bool ok = i < m && status[i] == CK_OP_OK;
-  const uint64_t b = __ballot(ok);
-  if ((threadIdx.x & 63) == 0 && b) atomicAdd(&s_sum, (uint32_t)__popcll(b));
-  __syncthreads();
-  if (threadIdx.x == 0) block_ok[blockIdx.x] = s_sum;
-}
-
-// pass 2 (one block): exclusive scan of the block counts; snapshot `stored`
-__global__ __launch_bounds__(kStatBlock) void k_stats_scan(uint32_t* block_ok, uint32_t nblocks,
-                                                           DevStats* st, uint64_t* stored_before,
-                                                           const uint32_t* open) {
-  if (stats_closed_out(open)) return;
-  __shared__ uint32_t carry;
-  __shared__ uint32_t wsum[kStatBlock / 64];
   if (threadIdx.x == 0) {
-    carry = 0;
-    *stored_before = st->v[S_STORED];
-  }
-  __syncthreads();
-  for (uint32_t base = 0; base < nblocks; base += kStatBlock) {
-    const uint32_t idx = base + threadIdx.x;
-    const uint32_t v = idx < nblocks ? block_ok[idx] : 0;
-    // inclusive scan within the wave
-    uint32_t x = v;
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      uint32_t y = __shfl_up(x, o, 64);
-      if (lane >= o) x += y;
+    uint32_t tot = 0;
+    for (int w = 0; w < kStatBlock / 64; ++w) tot += s_w[w];
+    block_ok[blockIdx.x] = tot;
+    if (blockIdx.x == 0) {
+      unsigned long long stored = 0;
+      for (int k = 0; k < kStatStripes; ++k) stored += st->s[k].v[S_STORED];
+      *stored_before = stored;
     }
-    if (lane == 63) wsum[threadIdx.x >> 6] = x;
-    __syncthreads();
-    uint32_t wpre = 0;
-    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wpre += wsum[w];
-    const uint32_t excl = carry + wpre + x - v;
-    __syncthreads();
-    if (idx < nblocks) block_ok[idx] = excl;
-    if (threadIdx.x == kStatBlock - 1) carry = excl + v;
-    __syncthreads();
   }
-  if (threadIdx.x == 0) st->v[S_STORED] += carry;
 }
 
-// pass 3: density band of every op, totals.
+// pass 2: the density band of every op and the totals.  An op's band comes
+// from the number of successful inserts before it (its rank) on top of
+// `stored` before the sub-batch; a tile whose first and last ranks fall in
+// one band (nearly all: a band holds slots / CK_BANDS inserts) needs no
+// per-op division.
 __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
     const uint8_t* status, const uint32_t* views, const uint32_t* lost, const uint32_t* kicks,
     const uint32_t* retries, const uint32_t* twins, uint64_t m, const uint32_t* block_ok,
@@ -2005,17 +2000,24 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
   __shared__ unsigned long long hb[4][CK_BANDS];
   __shared__ unsigned long long tot[11];
   __shared__ uint32_t wsum[kStatBlock / 64];
+  __shared__ uint64_t s_rank0;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int j = threadIdx.x; j < 4 * CK_BANDS; j += kStatBlock) hb[j / CK_BANDS][j % CK_BANDS] = 0;
   if (threadIdx.x < 11) tot[threadIdx.x] = 0;
+  // successful inserts of the earlier workgroups (one wavefront sums them)
+  if (wv == 0) {
+    unsigned long long pre = 0;
+    for (uint32_t k = lane; k < blockIdx.x; k += 64) pre += block_ok[k];
+    pre = wave_sum(pre);
+    if (lane == 0) s_rank0 = *stored_before + pre;
+  }
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const uint32_t ntiles = (uint32_t)((m + kStatBlock - 1) / kStatBlock);
+  const StatSplit sp(m, gridDim.x);
+  const uint32_t t0 = blockIdx.x * sp.per, t1 = min(sp.ntiles, t0 + sp.per);
   unsigned long long a_ok = 0, a_fail = 0, a_abort = 0, a_bad = 0, a_views = 0, a_vall = 0,
                      a_kicks = 0, a_maxk = 0, a_ret = 0, a_tw = 0;
-  // Each block takes a contiguous run of tiles, so an op's density band
-  // changes rarely from one tile to the next: every lane sums its ops' band
-  // contributions in registers and adds them to the block histogram only
-  // when its band changes, and at the end.
+  // per-lane sums of the current band, added to the workgroup histogram when
+  // the band changes and at the end
   uint32_t cb = kNone;
   unsigned long long c_n = 0, c_views = 0, c_kicks = 0, c_fail = 0;
   auto flush = [&]() {
@@ -2027,70 +2029,85 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
     }
     c_n = c_views = c_kicks = c_fail = 0;
   };
-  const uint32_t per = (ntiles + gridDim.x - 1) / gridDim.x;
-  const uint32_t t_end = min(ntiles, (blockIdx.x + 1) * per);
-  for (uint32_t tile = blockIdx.x * per; tile < t_end; ++tile) {
-    const uint64_t i = (uint64_t)tile * kStatBlock + threadIdx.x;
-    // every per-op word this tile needs, fetched together up front
-    uint8_t s = 0xFF;
-    uint32_t o_ret = 0, o_views = 0, o_lost = 0, o_kicks = 0, o_twins = 0;
-    if (i < m) {
-      s = status[i];
-      o_ret = retries[i];
-      o_views = views[i];
-      o_lost = lost[i];
-      o_kicks = kicks[i];
-      o_twins = twins[i];
+  auto band_of = [&](uint64_t stored) -> uint32_t {
+    const uint64_t b = (uint64_t)CK_BANDS * stored / slots;
+    return (uint32_t)(b >= CK_BANDS ? CK_BANDS - 1 : b);
+  };
+  uint64_t rank0 = s_rank0;
+  constexpr int kAhead = 4;  // tiles whose per-op words are fetched together
+  for (uint32_t tb = t0; tb < t1; tb += kAhead) {
+    uint8_t sv[kAhead];
+    uint32_t o_ret[kAhead], o_views[kAhead], o_lost[kAhead], o_kicks[kAhead], o_twins[kAhead];
+#pragma unroll
+    for (int q = 0; q < kAhead; ++q) {
+      const uint64_t i = (uint64_t)(tb + q) * kStatBlock + threadIdx.x;
+      sv[q] = 0xFF;
+      o_ret[q] = o_views[q] = o_lost[q] = o_kicks[q] = o_twins[q] = 0;
+      if (tb + q < t1 && i < m) {
+        sv[q] = status[i];
+        o_ret[q] = retries[i];
+        o_views[q] = views[i];
+        o_lost[q] = lost[i];
+        o_kicks[q] = kicks[i];
+        o_twins[q] = twins[i];
+      }
     }
-    const bool ok = s == CK_OP_OK;
-    const uint64_t bal = __ballot(ok);
-    const uint32_t before_in_wave = __popcll(bal & ((1ull << lane) - 1));
-    if (lane == 0) wsum[threadIdx.x >> 6] = __popcll(bal);
-    __syncthreads();
-    uint32_t wpre = 0;
-    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wpre += wsum[w];
-    __syncthreads();
-    const uint64_t rank = (uint64_t)block_ok[tile] + wpre + before_in_wave;
-    bool banded = false;
-    uint32_t band = 0;
-    unsigned long long v_views = 0, v_kicks = 0;
-    if (i < m) {
-      if (s == CK_OP_BAD_KEY) {
-        a_bad += 1;
-      } else {
-        a_ret += o_ret;
-        a_vall += (unsigned long long)o_views + o_lost;
-        if (s == CK_OP_ABORTED) {
-          a_abort += 1;
+#pragma unroll
+    for (int q = 0; q < kAhead; ++q) {
+      if (tb + q >= t1) break;  // uniform
+      const uint8_t s = sv[q];
+      const bool ok = s == CK_OP_OK;
+      const uint64_t bal = __ballot(ok);
+      const uint32_t before_in_wave = __popcll(bal & ((1ull << lane) - 1));
+      if (lane == 0) wsum[wv] = __popcll(bal);
+      __syncthreads();
+      uint32_t wpre = 0, ttot = 0;
+      for (int w = 0; w < kStatBlock / 64; ++w) {
+        const uint32_t c = wsum[w];
+        wpre += w < wv ? c : 0u;
+        ttot += c;
+      }
+      __syncthreads();  // wsum is rewritten by the next tile
+      const uint64_t rank = rank0 + wpre + before_in_wave;
+      uint32_t band = 0;
+      bool banded = false;
+      if (s != 0xFF) {
+        if (s == CK_OP_BAD_KEY) {
+          a_bad += 1;
         } else {
-          if (slots) {  // a group of tables has no single density: totals only
-            const uint64_t b = (uint64_t)CK_BANDS * (*stored_before + rank) / slots;
-            band = (uint32_t)(b >= CK_BANDS ? CK_BANDS - 1 : b);
-            banded = true;
-          }
-          v_views = o_views;
-          a_views += v_views;
-          if (ok) {
-            v_kicks = o_kicks;
-            a_ok += 1;
-            a_kicks += v_kicks;
-            a_maxk = v_kicks > a_maxk ? v_kicks : a_maxk;
-            a_tw += o_twins;
+          a_ret += o_ret[q];
+          a_vall += (unsigned long long)o_views[q] + o_lost[q];
+          if (s == CK_OP_ABORTED) {
+            a_abort += 1;
           } else {
-            a_fail += 1;
+            if (slots) {  // a group of tables has no single density: totals only
+              const uint32_t lo = band_of(rank0), hi = band_of(rank0 + ttot);
+              band = lo == hi ? lo : band_of(rank);
+              banded = true;
+            }
+            a_views += o_views[q];
+            if (ok) {
+              a_ok += 1;
+              a_kicks += o_kicks[q];
+              a_maxk = o_kicks[q] > a_maxk ? o_kicks[q] : a_maxk;
+              a_tw += o_twins[q];
+            } else {
+              a_fail += 1;
+            }
           }
         }
       }
-    }
-    if (banded) {
-      if (band != cb) {
-        flush();
-        cb = band;
+      if (banded) {
+        if (band != cb) {
+          flush();
+          cb = band;
+        }
+        c_n += 1;
+        c_views += o_views[q];
+        if (ok) c_kicks += o_kicks[q];
+        else c_fail += 1;
       }
-      c_n += 1;
-      c_views += v_views;
-      if (ok) c_kicks += v_kicks;
-      else c_fail += 1;
+      rank0 += ttot;
     }
   }
   flush();
@@ -2105,18 +2122,21 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
     atomicAdd(&tot[9], a_tw);
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  DevStatLine& sl = st->s[blockIdx.x % kStatStripes];
+  if (threadIdx.x < 10) {
     const int map[10] = {S_INS_OK, S_INS_FAIL, S_INS_ABORT, S_INS_BAD, S_VIEWS,
                          S_VIEWS_ALL, S_KICKS, S_MAX_KICKS, S_RETRIES, S_TWINS};
-    for (int j = 0; j < 10; ++j) {
-      if (!tot[j]) continue;
-      if (j == 7) atomicMax(&st->v[S_MAX_KICKS], tot[j]);
-      else atomicAdd(&st->v[map[j]], tot[j]);
+    const int j = threadIdx.x;
+    if (tot[j]) {
+      if (j == 7) atomicMax(&sl.v[S_MAX_KICKS], tot[j]);
+      else atomicAdd(&sl.v[map[j]], tot[j]);
     }
+    // `stored` grows by this workgroup's successful inserts
+    if (j == 0 && tot[0]) atomicAdd(&sl.v[S_STORED], tot[0]);
   }
   for (int j = threadIdx.x; j < 4 * CK_BANDS; j += kStatBlock) {
     const unsigned long long v = hb[j / CK_BANDS][j % CK_BANDS];
-    if (v) atomicAdd(&st->band[j / CK_BANDS][j % CK_BANDS], v);
+    if (v) atomicAdd(&sl.band[j / CK_BANDS][j % CK_BANDS], v);
   }
 }
 
@@ -2138,13 +2158,14 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_delete(const uint8_t* stat
   }
   d = wave_sum(d); f = wave_sum(f); p = wave_sum(p); rt = wave_sum(rt);
   if ((threadIdx.x & 63) == 0) {
-    if (d) atomicAdd(&st->v[S_DELETES], d);
+    DevStatLine& sl = st->s[(blockIdx.x * (kStatBlock / 64) + (threadIdx.x >> 6)) % kStatStripes];
+    if (d) atomicAdd(&sl.v[S_DELETES], d);
     if (f) {
-      atomicAdd(&st->v[S_DEL_FOUND], f);
-      atomicAdd(&st->v[S_STORED], (unsigned long long)(0ull - f));
+      atomicAdd(&sl.v[S_DEL_FOUND], f);
+      atomicAdd(&sl.v[S_STORED], (unsigned long long)(0ull - f));
     }
-    if (p) atomicAdd(&st->v[S_DEL_PROBES], p);
-    if (rt) atomicAdd(&st->v[S_DEL_RETRIES], rt);
+    if (p) atomicAdd(&sl.v[S_DEL_PROBES], p);
+    if (rt) atomicAdd(&sl.v[S_DEL_RETRIES], rt);
   }
 }
 
@@ -2158,12 +2179,10 @@ hipError_t launch_batch_stats(const Round& r, uint64_t m, uint64_t slots, uint32
     return hipGetLastError();
   }
   uint64_t* stored_before = (uint64_t*)(block_tmp + ((nb + 63) & ~63u));
-  hipLaunchKernelGGL(k_stats_count, dim3(nb), dim3(kStatBlock), 0, s, r.status, m, block_tmp,
-                     open);
-  hipLaunchKernelGGL(k_stats_scan, dim3(1), dim3(kStatBlock), 0, s, block_tmp, nb, r.stats,
-                     stored_before, open);
-  hipLaunchKernelGGL(k_stats_apply, dim3(std::min<uint32_t>(nb, 256)), dim3(kStatBlock), 0, s,
-                     r.status, r.op_views,
+  const uint32_t grid = std::min<uint32_t>(nb, kStatMaxGrid);
+  hipLaunchKernelGGL(k_stats_count, dim3(grid), dim3(kStatBlock), 0, s, r.status, m, block_tmp,
+                     stored_before, r.stats, open);
+  hipLaunchKernelGGL(k_stats_apply, dim3(grid), dim3(kStatBlock), 0, s, r.status, r.op_views,
                      r.op_lost, r.op_kicks, r.op_retries, r.op_twins, m, block_tmp,
                      stored_before, slots, r.stats, open);
   return hipGetLastError();
