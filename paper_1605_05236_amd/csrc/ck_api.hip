@@ -188,10 +188,11 @@ ck_status alloc_scratch(ck_table* t) {
   HIP_TRY(dalloc(&t->pend[1], (size_t)kStripes * t->stripe_cap));
   HIP_TRY(dalloc(&t->hdr, m));
   HIP_TRY(dalloc(&t->imv, (size_t)m * kExtraInline));
-  // evict regions: one per fresh-planner wavefront (64 / B ops), every
-  // wavefront of the last pass included
-  const size_t evict_units = ((size_t)m * t->B + 255) / 256 * 4;
-  HIP_TRY(dalloc(&t->evict, evict_units * (64 / t->B)));
+  // evict regions: one per fresh-planner wavefront (64 / lanes-per-op ops),
+  // every wavefront of the last pass included
+  const size_t fl = fresh_lanes((int)t->B);
+  const size_t evict_units = ((size_t)m * fl + 255) / 256 * 4;
+  HIP_TRY(dalloc(&t->evict, evict_units * (64 / fl)));
   HIP_TRY(dalloc(&t->evict_cnt, evict_units));
   for (auto& p : t->op) HIP_TRY(dalloc(&p, m));
   // eviction plans sub-allocate from per-workgroup windows of 256 entries

@@ -68,6 +68,11 @@ struct PlanHdr {
 };
 constexpr uint32_t kHdrArena = 1u << 28;
 constexpr uint32_t kExtraInline = 2;  // inline moves beyond the first, per op
+
+// Lanes per op in the fresh planner: each lane holds B / lanes consecutive
+// slots of a bin, so a wavefront keeps more ops (and their dependent bin
+// reads) in flight than with one lane per slot.
+__host__ __device__ constexpr int fresh_lanes(int B) { return B >= 4 ? B / 2 : B; }
 __host__ __device__ inline uint32_t hdr_pack(uint32_t status, uint32_t twins, uint32_t nm) {
   return status | (twins << 4) | (nm << 8);
 }
@@ -148,8 +153,8 @@ struct Round {
   uint32_t* next_cnt;        // its segment counts (zeroed by this round's planner)
   uint32_t* evict;           // ops that need an eviction plan: fresh-planner
                              // wavefront u (positions [u opw, (u + 1) opw),
-                             // opw = 64 / B) puts its evict_cnt[u] ops at
-                             // evict[u opw ...)
+                             // opw = 64 / fresh_lanes(B)) puts its
+                             // evict_cnt[u] ops at evict[u opw ...)
   uint32_t* evict_cnt;       // per fresh-planner wavefront
   PlanHdr* hdr;
   IMove* imv;                // kExtraInline per op

@@ -358,24 +358,62 @@ struct GroupCtx {
   }
 };
 
+// The keys of one bin as the L lanes of an op's group hold them: lane j has
+// slots [j S, (j + 1) S), S = B / L.
+template <int B, int L>
+struct BinKeys {
+  static constexpr int S = B / L;
+  uint64_t k[S];
+  __device__ __forceinline__ void load(const Geo& g, uint32_t bin, int sl) {
+    const ulonglong2* p = g.slots + (uint64_t)bin * B + (uint64_t)sl * S;
+#pragma unroll
+    for (int q = 0; q < S; ++q) k[q] = p[q].x;
+  }
+  // slots whose key is v, as a B-bit mask (bit = slot index)
+  __device__ __forceinline__ uint32_t match(const GroupCtx<L>& G, uint64_t v) const {
+    uint32_t m = 0;
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      const uint32_t bq = G.ballot(k[q] == v);
+      if (S == 1) {
+        m = bq;
+      } else {
+#pragma unroll
+        for (int j = 0; j < L; ++j) m |= ((bq >> j) & 1u) << (j * S + q);
+      }
+    }
+    return m;
+  }
+  // the key in slot `slot` (group-uniform)
+  __device__ __forceinline__ uint64_t at(const GroupCtx<L>& G, uint32_t slot) const {
+    uint64_t v = k[0];
+#pragma unroll
+    for (int q = 1; q < S; ++q)
+      if (slot % S == (uint32_t)q) v = k[q];
+    return __shfl(v, G.gshift + (int)(slot / S), 64);
+  }
+};
+
 template <int B, int H>
 __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
-  GroupCtx<B> G;
+  constexpr int L = fresh_lanes(B);
+  using Keys = BinKeys<B, L>;
+  GroupCtx<L> G;
   G.lane = threadIdx.x & 63;
-  G.sl = G.lane % B;
+  G.sl = G.lane % L;
   G.gshift = G.lane - G.sl;
   if (blockIdx.x == 0) round_start(r);
   Pending P;
   P.init(r);
-  constexpr uint32_t opb = 256 / B, opw = 64 / B;
+  constexpr uint32_t opb = 256 / L, opw = 64 / L;
   const uint32_t passes = (P.n + opb - 1) / opb;
   // pass c takes positions [c opb, (c + 1) opb); rounds after the first run a
   // capped grid, so a workgroup may take several passes
   for (uint32_t c = blockIdx.x; c < passes; c += gridDim.x) {
-    const uint32_t pi = P.at(c * opb + threadIdx.x / B);
+    const uint32_t pi = P.at(c * opb + threadIdx.x / L);
     const bool active = pi != kNone;
     const uint32_t i = active ? pi : 0u;
-    if (r.first && active && (threadIdx.x % B) == 0) zero_op_counters(r, i);
+    if (r.first && active && (threadIdx.x % L) == 0) zero_op_counters(r, i);
     const uint64_t x = active ? r.keys[i] : kEmpty;
     const bool leader = G.sl == 0;
     const bool bad = x == kEmpty;  // reserved key: rejected, no plan
@@ -391,10 +429,11 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
       uint32_t h[H];
       hash_key<H>(g, T, x, h);
       if (g.ghost) {
-        const ulonglong2 s0 = g.slots[(uint64_t)h[0] * B + G.sl];
-        const ulonglong2 s1 = g.slots[(uint64_t)h[1] * B + G.sl];
+        Keys s0, s1;
+        s0.load(g, h[0], G.sl);
+        s1.load(g, h[1], G.sl);
         views = 2;
-        const uint32_t e0 = G.ballot(s0.x == kEmpty), e1 = G.ballot(s1.x == kEmpty);
+        const uint32_t e0 = s0.match(G, kEmpty), e1 = s1.match(G, kEmpty);
         if (e0 && e1) {
           b0 = h[0]; f0 = ffs32(e0) | ((MV_DUP | hc_flag) << 8);
           b1 = h[1]; f1 = ffs32(e1) | ((MV_DUP | hc_flag) << 8);
@@ -413,12 +452,13 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
             const int w = d0 ? 0 : 1;
             const uint32_t b = w == 0 ? h[0] : h[1];
             const uint32_t ds = ffs32(d0 ? d0 : d1);
-            const uint64_t dk = __shfl(w == 0 ? s0.x : s1.x, G.gshift + (int)ds, 64);
+            const uint64_t dk = w == 0 ? s0.at(G, ds) : s1.at(G, ds);
             uint32_t hd[2];
             hash_key<2>(g, T, dk, hd);
             const uint32_t tb = hd[0] == b ? hd[1] : hd[0];
-            const ulonglong2 ts = g.slots[(uint64_t)tb * B + G.sl];
-            const uint32_t tm = G.ballot(ts.x == dk);
+            Keys ts;
+            ts.load(g, tb, G.sl);
+            const uint32_t tm = ts.match(G, dk);
             b0 = tb; f0 = ffs32(tm) | (MV_DUPCLR << 8);
             b1 = b; f1 = ds | (hc_flag << 8);
             nm = 2;
@@ -427,10 +467,11 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
           }
         }
       } else if (g.balance || g.scheme == CK_QUEUE) {
-        const ulonglong2 s0 = g.slots[(uint64_t)h[0] * B + G.sl];
-        const ulonglong2 s1 = g.slots[(uint64_t)h[1] * B + G.sl];
+        Keys s0, s1;
+        s0.load(g, h[0], G.sl);
+        s1.load(g, h[1], G.sl);
         views = 2;
-        const uint32_t e0 = G.ballot(s0.x == kEmpty), e1 = G.ballot(s1.x == kEmpty);
+        const uint32_t e0 = s0.match(G, kEmpty), e1 = s1.match(G, kEmpty);
         const int o0 = B - __popc(e0), o1 = B - __popc(e1);
         if (o0 < B || o1 < B) {
           if (o0 <= o1) { b0 = h[0]; f0 = ffs32(e0) | (hc_flag << 8); }
@@ -441,9 +482,10 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
       } else {
 #pragma unroll
         for (int hi = 0; hi < H; ++hi) {
-          const ulonglong2 sv = g.slots[(uint64_t)h[hi] * B + G.sl];
+          Keys sv;
+          sv.load(g, h[hi], G.sl);
           ++views;
-          const uint32_t e = G.ballot(sv.x == kEmpty);
+          const uint32_t e = sv.match(G, kEmpty);
           if (e) {
             b0 = h[hi]; f0 = ffs32(e) | (hc_flag << 8); nm = 1;
             placed = true;
@@ -479,7 +521,7 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
 // ---------------------------------------------------------------------------
 // The ops of one round that need an eviction plan: fresh-planner wavefront b
 // put its evict_cnt[b] ops at evict[b * opw + j], j < evict_cnt[b] (opw = 64 /
-// B ops per wavefront).  Positions are numbered slot-major, q = j * nb + b (nb
+// fresh_lanes(B) ops per wavefront).  Positions are numbered slot-major, q = j * nb + b (nb
 // wavefronts), so each stretch of q holds one slot index of every wavefront.  Eviction-planner
 // workgroup w takes q = w, w + gridDim.x, w + 2 gridDim.x, ...: an even
 // sample of every slot layer, hence an equal share of the occupied
@@ -906,7 +948,7 @@ __global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
   }
   wave_sync();
   EvictWork Wk;
-  Wk.init(r, 64 / B);
+  Wk.init(r, 64 / fresh_lanes(B));
   // the group's op of batch kb is item kb + gi; item() is wave-uniform
   auto batch_item = [&](uint32_t kb) -> uint32_t {
     uint32_t mine = kNone;
@@ -1046,7 +1088,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
   }
   wave_sync();
   EvictWork Wk;
-  Wk.init(r, 64 / B);
+  Wk.init(r, 64 / fresh_lanes(B));
   // the group's op of batch kb is item kb + gi; item() is wave-uniform
   auto batch_item = [&](uint32_t kb) -> uint32_t {
     uint32_t mine = kNone;
@@ -1638,7 +1680,7 @@ static void evict_go(const Geo& g, const Round& r, uint32_t grid, hipStream_t s)
 
 template <int B, int H>
 static void fresh_go(const Geo& g, const Round& r, hipStream_t s) {
-  const uint64_t threads = (uint64_t)r.npend * B;
+  const uint64_t threads = (uint64_t)r.npend * fresh_lanes(B);
   uint32_t grid = (uint32_t)((threads + 255) / 256);
   if (!r.first) grid = std::min(grid, kTailPlanBlocks);
   hipLaunchKernelGGL((k_plan_fresh<B, H>), dim3(grid), dim3(256), 0, s, g, r);
