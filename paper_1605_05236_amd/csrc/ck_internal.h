@@ -87,8 +87,9 @@ __host__ __device__ inline uint32_t hdr_pack(uint32_t status, uint32_t twins, ui
 // kernel's result for an op depends on the op, never on its position.
 constexpr uint32_t kStripes = 64;
 constexpr uint32_t kStripeWords = 32;
-constexpr uint32_t kCommitOps = 64;      // plans per commit workgroup pass (256 lanes / 4)
-constexpr uint32_t kCommitWaveOps = 16;  // plans per commit wavefront
+constexpr uint32_t kCommitLanes = 2;                    // lanes per plan in the commit kernel
+constexpr uint32_t kCommitOps = 256 / kCommitLanes;     // plans per commit workgroup pass
+constexpr uint32_t kCommitWaveOps = 64 / kCommitLanes;  // plans per commit wavefront
 __host__ __device__ inline uint32_t stripe_capacity(uint32_t m) {
   const uint32_t waves = (m + kCommitWaveOps - 1) / kCommitWaveOps;
   return (waves + kStripes - 1) / kStripes * kCommitWaveOps;

@@ -16,7 +16,7 @@
 //   k_plan_search   four searches per wavefront: BFS and sorted search over
 //                   runs of B records, several frontier bins per load
 //   k_plan_delete   lane group per pending delete
-//   k_commit        4 lanes per plan: claim check, reverse-order chain write,
+//   k_commit        2 lanes per plan: claim check, reverse-order chain write,
 //                   metadata atomics, spawn-count updates; the losers form
 //                   the next round's pending list
 //   k_stats_*       per-op counters -> totals and density bands
@@ -1793,7 +1793,7 @@ hipError_t launch_plan_delete(const Geo& g, const Round& r, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// commit: 8 lanes per plan
+// commit: kCommitLanes lanes per plan
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void sc_increment(uint32_t* meta) {
   uint32_t old = __hip_atomic_load(meta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1807,9 +1807,8 @@ __device__ __forceinline__ void sc_increment(uint32_t* meta) {
   }
 }
 
-constexpr int kCommitLanes = 4;  // lanes per plan in the commit kernel
 
-// The commit kernel, four lanes per plan, in two phases per plan: decide
+// The commit kernel, kCommitLanes lanes per plan, in two phases per plan: decide
 // (header, claim check; for a loser its retry count) and apply (the writes).
 // Between them each wavefront lists its losers for the next round: the
 // atomic that reserves their list entries is issued before the writes and
