@@ -48,8 +48,13 @@ struct Timer {
     (void)hipEventRecord(e, s);
     pending.push_back({kind, {b, e}});
   }
-  void collect() {  // the stream has been synchronised
-    for (auto& p : pending) {
+  // Resolves the pairs whose end event has completed (pairs complete in the
+  // order they were recorded); later pairs stay pending.
+  void collect() {
+    size_t k = 0;
+    for (; k < pending.size(); ++k) {
+      auto& p = pending[k];
+      if (hipEventQuery(p.second.second) == hipErrorNotReady) break;
       float t = 0;
       if (hipEventElapsedTime(&t, p.second.first, p.second.second) == hipSuccess) {
         ms[p.first] += t;
@@ -58,7 +63,7 @@ struct Timer {
       pool.push_back(p.second.first);
       pool.push_back(p.second.second);
     }
-    pending.clear();
+    pending.erase(pending.begin(), pending.begin() + k);
   }
   void reset() {
     collect();
@@ -91,8 +96,9 @@ struct ck_table {
   uint32_t spawn_cap = 0;
   uint32_t* op[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // views, lost, kicks, retries, twins
   unsigned long long* wg_views = nullptr;  // per eviction workgroup: bins viewed
-  Ctr* ctr = nullptr;
-  Ctr* h_ctr = nullptr;
+  Ctr* ctr = nullptr;    // two sets: sub-batches alternate between them
+  Ctr* h_ctr = nullptr;  // pinned copies of the two sets
+  hipEvent_t ctr_ready[2] = {nullptr, nullptr};  // a set's copy has landed
   void* wg_scratch = nullptr;
   uint32_t wg_bytes = 0;
   uint32_t evict_grid = 0;
@@ -161,6 +167,8 @@ void free_scratch(ck_table* t) {
   for (auto& p : t->op) (void)hipFree(p);
   (void)hipFree(t->ctr);
   if (t->h_ctr) (void)hipHostFree(t->h_ctr);
+  for (auto& e : t->ctr_ready)
+    if (e) (void)hipEventDestroy(e);
   (void)hipFree(t->wg_scratch);
   (void)hipFree(t->wg_views);
   (void)hipFree(t->dstats);
@@ -203,9 +211,10 @@ ck_status alloc_scratch(ck_table* t) {
                      ? (uint32_t)std::min<uint64_t>((uint64_t)m * 2 + slack, 1u << 30)
                      : 16;
   HIP_TRY(dalloc(&t->spawns, t->spawn_cap));
-  HIP_TRY(dalloc(&t->ctr, 1));
-  HIP_TRY(hipMemset(t->ctr, 0, sizeof(Ctr)));
-  HIP_TRY(hipHostMalloc((void**)&t->h_ctr, sizeof(Ctr), hipHostMallocDefault));
+  HIP_TRY(dalloc(&t->ctr, 2));
+  HIP_TRY(hipMemset(t->ctr, 0, 2 * sizeof(Ctr)));
+  HIP_TRY(hipHostMalloc((void**)&t->h_ctr, 2 * sizeof(Ctr), hipHostMallocDefault));
+  for (auto& e : t->ctr_ready) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   HIP_TRY(dalloc(&t->dstats, 1));
   HIP_TRY(hipMemset(t->dstats, 0, sizeof(DevStats)));
   const uint32_t nb = (m + 1023) / 1024;
@@ -262,13 +271,19 @@ Round make_round(ck_table* t, const uint64_t* keys, const void* vals, uint8_t* s
   return r;
 }
 
-// Run the phased rounds of one sub-batch until no op is pending, then its
-// statistics.  The first round's list is every op; each later round's list
-// (and count) exists only on the device, so those rounds run capped grids
-// that loop over whatever count they find.  The host enqueues the first
-// round, as many more as the last sub-batch took, and the statistics, and
-// synchronises once: the statistics apply only if the last list came out
-// empty, else more rounds and the statistics are enqueued again.
+// The phased rounds of a sub-batch, then its statistics.  The first round's
+// list is every op; each later round's list (and count) exists only on the
+// device, so those rounds run capped grids that loop over whatever count
+// they find.  The host enqueues a sub-batch as its first round, as many more
+// rounds as the last sub-batch of its kind took, the statistics and a copy
+// of its counters, and does so one sub-batch ahead: sub-batch b + 1 is
+// enqueued before the host waits for b's counters.  Every kernel of b + 1
+// checks that b's last list came out empty (its gate) and otherwise does
+// nothing; the host then runs more rounds of b and enqueues b + 1 again.
+// The statistics of a sub-batch apply only when its own last list is empty
+// too; their first kernel records the outcome in the `unfinished` flag that
+// the next sub-batch's kernels read.  Sub-batches alternate between two sets
+// of round counters.
 constexpr uint32_t kMaxTailHint = 12;
 
 uint32_t list_count(const Ctr& c, int p) {
@@ -277,75 +292,104 @@ uint32_t list_count(const Ctr& c, int p) {
   return n;
 }
 
-ck_status run_rounds(ck_table* t, Round& r, uint64_t m, uint64_t slots, hipStream_t s) {
-  int cur = 0;
-  // The lowest pending op always commits, so m rounds suffice; arena growth
-  // adds a few void rounds.  Anything beyond that is a fault, not progress.
-  uint64_t guard = 2 * m + 64;
+// One sub-batch in flight, as the host tracks it.
+struct Flight {
+  Round r;
+  uint64_t m = 0, slots = 0;
+  int set = 0;          // its round-counter set
+  int cur = 0;          // list parity its next round reads
+  uint64_t guard = 0;   // rounds left before the loop counts as stuck
+  bool live = false;
+};
+
+ck_status enqueue_rounds(ck_table* t, Flight& f, uint32_t K, bool first, const uint32_t* gate,
+                         hipStream_t s) {
   Timer& T = t->timer;
-  bool first = true;
-  uint32_t used = 0;
-  for (;;) {
-    // as many rounds as the last sub-batch of this kind took, and one more
-    uint32_t& hint = r.is_delete ? t->tail_hint_del : t->tail_hint;
-    const uint32_t K = first ? hint + 1 : 2;
-    for (uint32_t k = 0; k < K; ++k) {
-      if (guard == 0) return CK_EDEVICE;
-      --guard;
-      ++t->epoch;
-      if (t->epoch == 0) {  // claim tags wrapped: reset every claim word
-        HIP_TRY(hipMemsetAsync(t->g.owner, 0xFF, (size_t)t->bins * 8, s));
-        t->epoch = 1;
-      }
-      r.tag = (unsigned long long)(~t->epoch) << 32;
-      r.first = first ? 1u : 0u;
-      r.npend = (uint32_t)m;  // grid size; later rounds cap it
-      r.pend = t->pend[cur];
-      r.pcnt = first ? nullptr : t->ctr->cnt[cur];
-      r.next = t->pend[cur ^ 1];
-      r.next_cnt = t->ctr->cnt[cur ^ 1];
-      r.stripe_cap = t->stripe_cap;
-      r.arena = t->arena;
-      r.arena_cap = t->arena_cap;
-      r.spawns = t->spawns;
-      r.spawn_cap = t->spawn_cap;
-      first = false;
-      hipEvent_t ev;
-      if (r.is_delete) {
-        ev = T.begin(s, TK_DELETE);
-        HIP_TRY(launch_plan_delete(t->g, r, s));
-        T.end(TK_DELETE, ev, s);
-      } else {
-        // the fresh planner's wavefronts leave the evict list in regions
-        ev = T.begin(s, TK_FRESH);
-        HIP_TRY(launch_plan_fresh(t->g, r, s));
-        T.end(TK_FRESH, ev, s);
-        ev = T.begin(s, TK_EVICT);
-        HIP_TRY(launch_plan_evict(t->g, r, t->evict_grid, s));
-        T.end(TK_EVICT, ev, s);
-      }
-      ev = T.begin(s, TK_COMMIT);
-      HIP_TRY(launch_commit(t->g, r, s));
-      T.end(TK_COMMIT, ev, s);
-      cur ^= 1;
+  Round& r = f.r;
+  Ctr* c = t->ctr + f.set;
+  if (first) f.cur = 0;
+  for (uint32_t k = 0; k < K; ++k) {
+    // The lowest pending op always commits, so m rounds suffice; arena growth
+    // adds a few void rounds.  Anything beyond that is a fault, not progress.
+    if (f.guard == 0) return CK_EDEVICE;
+    --f.guard;
+    ++t->epoch;
+    if (t->epoch == 0) {  // claim tags wrapped: reset every claim word
+      HIP_TRY(hipMemsetAsync(t->g.owner, 0xFF, (size_t)t->bins * 8, s));
+      t->epoch = 1;
     }
-    hipEvent_t ev = T.begin(s, TK_STATS);
-    HIP_TRY(launch_batch_stats(r, m, slots, t->block_tmp, r.is_delete, t->ctr->cnt[cur], s));
-    T.end(TK_STATS, ev, s);
-    HIP_TRY(hipMemcpyAsync(t->h_ctr, t->ctr, sizeof(Ctr), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    T.collect();
-    const Ctr& c = *t->h_ctr;
-    if (c.overflow || c.overflow_seen) {
-      ck_status st = grow_arena(t);
-      if (st != CK_OK) return st;
+    r.tag = (unsigned long long)(~t->epoch) << 32;
+    r.first = first ? 1u : 0u;
+    r.npend = (uint32_t)f.m;  // grid size; later rounds cap it
+    r.ctr = c;
+    r.gate = gate;
+    r.pend = t->pend[f.cur];
+    r.pcnt = first ? nullptr : c->cnt[f.cur];
+    r.next = t->pend[f.cur ^ 1];
+    r.next_cnt = c->cnt[f.cur ^ 1];
+    r.stripe_cap = t->stripe_cap;
+    r.arena = t->arena;
+    r.arena_cap = t->arena_cap;
+    r.spawns = t->spawns;
+    r.spawn_cap = t->spawn_cap;
+    first = false;
+    hipEvent_t ev;
+    if (r.is_delete) {
+      ev = T.begin(s, TK_DELETE);
+      HIP_TRY(launch_plan_delete(t->g, r, s));
+      T.end(TK_DELETE, ev, s);
+    } else {
+      // the fresh planner's wavefronts leave the evict list in regions
+      ev = T.begin(s, TK_FRESH);
+      HIP_TRY(launch_plan_fresh(t->g, r, s));
+      T.end(TK_FRESH, ev, s);
+      ev = T.begin(s, TK_EVICT);
+      HIP_TRY(launch_plan_evict(t->g, r, t->evict_grid, s));
+      T.end(TK_EVICT, ev, s);
     }
-    used = c.rounds;
-    if (list_count(c, cur) == 0) break;
+    ev = T.begin(s, TK_COMMIT);
+    HIP_TRY(launch_commit(t->g, r, s));
+    T.end(TK_COMMIT, ev, s);
+    f.cur ^= 1;
   }
-  if (!r.is_delete) t->rounds += used;
-  (r.is_delete ? t->tail_hint_del : t->tail_hint) = std::min(kMaxTailHint, std::max<uint32_t>(1, used));
+  // the statistics (gated on this list and the gate), then the counters' copy
+  hipEvent_t ev = T.begin(s, TK_STATS);
+  HIP_TRY(launch_batch_stats(r, f.m, f.slots, t->block_tmp, r.is_delete, c->cnt[f.cur], s));
+  T.end(TK_STATS, ev, s);
+  HIP_TRY(hipMemcpyAsync(t->h_ctr + f.set, c, sizeof(Ctr), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipEventRecord(t->ctr_ready[f.set], s));
   return CK_OK;
+}
+
+// Waits for a sub-batch's counters; *done tells whether its last list came
+// out empty (its statistics have then applied).
+ck_status settle(ck_table* t, Flight& f, bool* done) {
+  HIP_TRY(hipEventSynchronize(t->ctr_ready[f.set]));
+  t->timer.collect();
+  const Ctr& c = t->h_ctr[f.set];
+  if (c.overflow || c.overflow_seen) {  // a void round: a larger arena for what follows
+    ck_status st = grow_arena(t);
+    if (st != CK_OK) return st;
+  }
+  *done = list_count(c, f.cur) == 0;
+  if (*done) {
+    if (!f.r.is_delete) t->rounds += c.rounds;
+    (f.r.is_delete ? t->tail_hint_del : t->tail_hint) =
+        std::min(kMaxTailHint, std::max<uint32_t>(1, c.rounds));
+  }
+  return CK_OK;
+}
+
+// Runs a sub-batch's remaining rounds until its last list is empty.
+ck_status finish(ck_table* t, Flight& f, hipStream_t s) {
+  for (;;) {
+    bool done = false;
+    ck_status st = settle(t, f, &done);
+    if (st != CK_OK) return st;
+    if (done) return CK_OK;
+    st = enqueue_rounds(t, f, 2, false, nullptr, s);
+    if (st != CK_OK) return st;
+  }
 }
 
 ck_status run_batches(ck_table* t, const uint64_t* keys, const void* vals, uint64_t n,
@@ -354,16 +398,43 @@ ck_status run_batches(ck_table* t, const uint64_t* keys, const void* vals, uint6
                       const uint2* tdesc = nullptr) {
   const uint32_t vb = t->B == 1 ? 4 : 8;
   const uint64_t slots = t->bins * t->B;
+  Flight prev;
+  int set = 0;
   for (uint64_t b0 = 0; b0 < n; b0 += t->opt.batch_ops) {
     const uint64_t m = std::min<uint64_t>(t->opt.batch_ops, n - b0);
     uint32_t* ops[5] = {views ? views + b0 : t->op[0], t->op[1],
                         kicks ? kicks + b0 : t->op[2], retries ? retries + b0 : t->op[3],
                         t->op[4]};
-    Round r = make_round(t, keys + b0, vals ? (const char*)vals + b0 * vb : nullptr,
-                         status + b0, ops, t->insert_count + b0, is_delete,
-                         op_table ? op_table + b0 : nullptr, tdesc);
-    // density bands are per table: a group keeps totals only
-    ck_status st = run_rounds(t, r, m, op_table ? 0 : slots, s);
+    Flight f;
+    f.r = make_round(t, keys + b0, vals ? (const char*)vals + b0 * vb : nullptr, status + b0, ops,
+                     t->insert_count + b0, is_delete, op_table ? op_table + b0 : nullptr, tdesc);
+    f.m = m;
+    f.slots = op_table ? 0 : slots;  // density bands are per table: a group keeps totals only
+    f.set = set;
+    f.guard = 2 * m + 64;
+    f.live = true;
+    set ^= 1;
+    const uint32_t K = (is_delete ? t->tail_hint_del : t->tail_hint) + 1;
+    const uint32_t* gate = prev.live ? &t->ctr[prev.set].unfinished : nullptr;
+    ck_status st = enqueue_rounds(t, f, K, true, gate, s);
+    if (st != CK_OK) return st;
+    if (prev.live) {
+      bool done = false;
+      st = settle(t, prev, &done);
+      if (st != CK_OK) return st;
+      if (!done) {
+        // this sub-batch saw a non-empty gate and did nothing: finish the
+        // previous one, then enqueue this one again
+        st = enqueue_rounds(t, prev, 2, false, nullptr, s);
+        if (st == CK_OK) st = finish(t, prev, s);
+        if (st == CK_OK) st = enqueue_rounds(t, f, K, true, nullptr, s);
+        if (st != CK_OK) return st;
+      }
+    }
+    prev = f;
+  }
+  if (prev.live) {
+    ck_status st = finish(t, prev, s);
     if (st != CK_OK) return st;
   }
   if (!is_delete) t->insert_count += n;

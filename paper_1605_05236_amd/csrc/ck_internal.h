@@ -99,7 +99,9 @@ struct Ctr {             // device counters of the round loop
   uint32_t overflow;     // a planner ran out of arena this round (round is void)
   uint32_t overflow_seen;  // sticky: some earlier round of the sub-batch was void
   uint32_t rounds;       // rounds that committed (not void, ops pending)
-  uint32_t pad[29];
+  uint32_t unfinished;   // set by the statistics: the sub-batch (or the one
+                         // before it) still had pending ops, nothing applied
+  uint32_t pad[28];
   uint32_t cnt[2][kStripes * kStripeWords];  // segment counts of pending list p
 };
 
@@ -152,6 +154,9 @@ struct Round {
   uint32_t stripe_cap;       // entries per list segment
   uint32_t* next;            // the next round's list: ops that go again
   uint32_t* next_cnt;        // its segment counts (zeroed by this round's planner)
+  const uint32_t* gate;      // the previous sub-batch's `unfinished` flag, or
+                             // null: while it is set, every kernel of this round
+                             // does nothing (the host enqueues one sub-batch ahead)
   uint32_t* evict;           // ops that need an eviction plan: fresh-planner
                              // wavefront u (positions [u opw, (u + 1) opw),
                              // opw = 64 / fresh_lanes(B)) puts its
@@ -191,8 +196,9 @@ hipError_t launch_plan_evict(const Geo& g, const Round& r, uint32_t grid, hipStr
 hipError_t launch_plan_delete(const Geo& g, const Round& r, hipStream_t s);
 hipError_t launch_commit(const Geo& g, const Round& r, hipStream_t s);
 // Sub-batch statistics; they apply only if the pending list whose segment
-// counts `open` points to is empty (else the kernels return at once and the
-// host enqueues them again after more rounds).
+// counts `open` points to is empty and the flag `r.gate` points to is clear
+// (else the kernels return at once and the host enqueues them again later).
+// The first statistics kernel records the outcome in r.ctr->unfinished.
 hipError_t launch_batch_stats(const Round& r, uint64_t m, uint64_t slots, uint32_t* block_tmp,
                               uint32_t is_delete, const uint32_t* open, hipStream_t s);
 size_t evict_lds_bytes(const Geo& g);

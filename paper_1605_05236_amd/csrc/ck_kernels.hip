@@ -58,17 +58,31 @@ __device__ __forceinline__ void hash_key(const Geo& g, Tab t, uint64_t x, uint32
   }
 }
 
+// True when the pending list with segment counts `cnt` is not empty (all 64
+// lanes call it together).
+__device__ __forceinline__ bool list_open(const uint32_t* cnt) {
+  const uint32_t c = cnt[(threadIdx.x & 63) * kStripeWords];
+  return __ballot(c != 0) != 0ull;
+}
+
 // The round's pending list as one wavefront sees it.  The first round of a
 // sub-batch lists every op in order (position = op index, count a kernel
 // argument); later rounds read the segment counts the previous commit left
 // (lane l loads segment l's count) and map a position to its segment through
-// their prefix sums.  init and at are called by all 64 lanes together.
+// their prefix sums.  A round whose gate (the previous sub-batch's last
+// list) is not empty sees no ops.  init and at are called by all 64 lanes
+// together.
 struct Pending {
   const uint32_t* list = nullptr;
   uint32_t cap = 0, n = 0, incl = 0, excl = 0;
   bool ident = true;
   __device__ void init(const Round& r) {
     ident = r.first != 0;
+    if (r.gate && *r.gate) {  // the previous sub-batch is not finished
+      ident = true;
+      n = 0;
+      return;
+    }
     if (ident) {
       n = r.npend;
       return;
@@ -100,13 +114,6 @@ struct Pending {
     return list[(size_t)sg * cap + (p - e)];
   }
 };
-
-// True when the pending list with segment counts `cnt` is not empty (all 64
-// lanes call it together).
-__device__ __forceinline__ bool list_open(const uint32_t* cnt) {
-  const uint32_t c = cnt[(threadIdx.x & 63) * kStripeWords];
-  return __ballot(c != 0) != 0ull;
-}
 
 // The table of op i: from the group's descriptors, else the single table.
 __device__ __forceinline__ Tab tab_of(const Geo& g, const uint32_t* op_table, const uint2* tdesc,
@@ -1972,15 +1979,21 @@ hipError_t launch_commit(const Geo& g, const Round& r, hipStream_t s) {
 // ---------------------------------------------------------------------------
 constexpr int kStatBlock = 1024;
 
-// The sub-batch still has pending ops (its last list is not empty): the
-// statistics kernels then leave everything untouched.  One wavefront per
-// workgroup reads the counts; every thread of the workgroup calls it.
-__device__ __forceinline__ bool stats_closed_out(const uint32_t* open) {
-  if (!open) return false;
+// The sub-batch still has pending ops (its last list is not empty), or the
+// one before it has (its gate flag is set): the statistics kernels then leave
+// everything untouched.  One wavefront per workgroup reads the counts; every
+// thread of the workgroup calls it.  With `record`, workgroup 0 stores the
+// outcome in `unfinished` (the next sub-batch's gate).
+__device__ __forceinline__ bool stats_closed_out(const uint32_t* open, const uint32_t* gate,
+                                                 uint32_t* unfinished, bool record) {
   __shared__ uint32_t s_open;
   if (threadIdx.x < 64) {
-    const bool o = list_open(open);
-    if (threadIdx.x == 0) s_open = o ? 1u : 0u;
+    bool o = gate && *gate;
+    o = o || (open && list_open(open));
+    if (threadIdx.x == 0) {
+      s_open = o ? 1u : 0u;
+      if (record && blockIdx.x == 0) *unfinished = o ? 1u : 0u;
+    }
   }
   __syncthreads();
   return s_open != 0;
@@ -2003,8 +2016,10 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_count(const uint8_t* statu
                                                             uint32_t* block_ok,
                                                             uint64_t* stored_before,
                                                             const DevStats* st,
-                                                            const uint32_t* open) {
-  if (stats_closed_out(open)) return;
+                                                            const uint32_t* open,
+                                                            const uint32_t* gate,
+                                                            uint32_t* unfinished) {
+  if (stats_closed_out(open, gate, unfinished, true)) return;
   __shared__ uint32_t s_w[kStatBlock / 64];
   const StatSplit sp(m, gridDim.x);
   const uint32_t t0 = blockIdx.x * sp.per, t1 = min(sp.ntiles, t0 + sp.per);
@@ -2036,8 +2051,9 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_count(const uint8_t* statu
 __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
     const uint8_t* status, const uint32_t* views, const uint32_t* lost, const uint32_t* kicks,
     const uint32_t* retries, const uint32_t* twins, uint64_t m, const uint32_t* block_ok,
-    const uint64_t* stored_before, uint64_t slots, DevStats* st, const uint32_t* open) {
-  if (stats_closed_out(open)) return;
+    const uint64_t* stored_before, uint64_t slots, DevStats* st, const uint32_t* open,
+    const uint32_t* gate) {
+  if (stats_closed_out(open, gate, nullptr, false)) return;
   __shared__ unsigned long long hb[4][CK_BANDS];
   __shared__ unsigned long long tot[11];
   __shared__ uint32_t wsum[kStatBlock / 64];
@@ -2185,8 +2201,10 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
 __global__ __launch_bounds__(kStatBlock) void k_stats_delete(const uint8_t* status,
                                                              const uint32_t* probes,
                                                              const uint32_t* retries, uint64_t m,
-                                                             DevStats* st, const uint32_t* open) {
-  if (stats_closed_out(open)) return;
+                                                             DevStats* st, const uint32_t* open,
+                                                             const uint32_t* gate,
+                                                             uint32_t* unfinished) {
+  if (stats_closed_out(open, gate, unfinished, true)) return;
   unsigned long long d = 0, f = 0, p = 0, rt = 0;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
        i += (uint64_t)gridDim.x * blockDim.x) {
@@ -2216,16 +2234,17 @@ hipError_t launch_batch_stats(const Round& r, uint64_t m, uint64_t slots, uint32
   const uint32_t nb = (uint32_t)((m + kStatBlock - 1) / kStatBlock);
   if (is_delete) {
     hipLaunchKernelGGL(k_stats_delete, dim3(std::min<uint32_t>(nb, 256)), dim3(kStatBlock), 0, s,
-                       r.status, r.op_views, r.op_retries, m, r.stats, open);
+                       r.status, r.op_views, r.op_retries, m, r.stats, open, r.gate,
+                       &r.ctr->unfinished);
     return hipGetLastError();
   }
   uint64_t* stored_before = (uint64_t*)(block_tmp + ((nb + 63) & ~63u));
   const uint32_t grid = std::min<uint32_t>(nb, kStatMaxGrid);
   hipLaunchKernelGGL(k_stats_count, dim3(grid), dim3(kStatBlock), 0, s, r.status, m, block_tmp,
-                     stored_before, r.stats, open);
+                     stored_before, r.stats, open, r.gate, &r.ctr->unfinished);
   hipLaunchKernelGGL(k_stats_apply, dim3(grid), dim3(kStatBlock), 0, s, r.status, r.op_views,
                      r.op_lost, r.op_kicks, r.op_retries, r.op_twins, m, block_tmp,
-                     stored_before, slots, r.stats, open);
+                     stored_before, slots, r.stats, open, r.gate);
   return hipGetLastError();
 }
 
