@@ -93,7 +93,11 @@ typedef struct {
   uint32_t evict_wgs_per_cu; /* kick-out planner workgroups per compute unit;
                                 0 = as many as the LDS budget allows (<= 32).
                                 Performance only: results do not depend on it */
-  uint32_t reserved;
+  uint32_t enqueue_rounds;   /* rounds enqueued per sub-batch before the host
+                                first looks at its counters (more follow in
+                                groups of this size while ops are pending);
+                                0 = as many as the previous sub-batch took, plus
+                                one, then groups of two.  Performance only */
 } ck_options;
 
 /* Counters of one table since creation (or the last ck_stats_reset). */

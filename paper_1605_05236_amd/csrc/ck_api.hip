@@ -387,7 +387,8 @@ ck_status finish(ck_table* t, Flight& f, hipStream_t s) {
     ck_status st = settle(t, f, &done);
     if (st != CK_OK) return st;
     if (done) return CK_OK;
-    st = enqueue_rounds(t, f, 2, false, nullptr, s);
+    st = enqueue_rounds(t, f, t->opt.enqueue_rounds ? t->opt.enqueue_rounds : 2, false, nullptr,
+                        s);
     if (st != CK_OK) return st;
   }
 }
@@ -414,7 +415,9 @@ ck_status run_batches(ck_table* t, const uint64_t* keys, const void* vals, uint6
     f.guard = 2 * m + 64;
     f.live = true;
     set ^= 1;
-    const uint32_t K = (is_delete ? t->tail_hint_del : t->tail_hint) + 1;
+    const uint32_t K = t->opt.enqueue_rounds
+                           ? t->opt.enqueue_rounds
+                           : (is_delete ? t->tail_hint_del : t->tail_hint) + 1;
     const uint32_t* gate = prev.live ? &t->ctr[prev.set].unfinished : nullptr;
     ck_status st = enqueue_rounds(t, f, K, true, gate, s);
     if (st != CK_OK) return st;
@@ -425,7 +428,8 @@ ck_status run_batches(ck_table* t, const uint64_t* keys, const void* vals, uint6
       if (!done) {
         // this sub-batch saw a non-empty gate and did nothing: finish the
         // previous one, then enqueue this one again
-        st = enqueue_rounds(t, prev, 2, false, nullptr, s);
+        st = enqueue_rounds(t, prev, t->opt.enqueue_rounds ? t->opt.enqueue_rounds : 2, false,
+                            nullptr, s);
         if (st == CK_OK) st = finish(t, prev, s);
         if (st == CK_OK) st = enqueue_rounds(t, f, K, true, nullptr, s);
         if (st != CK_OK) return st;

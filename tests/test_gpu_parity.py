@@ -147,6 +147,35 @@ def test_edge_cases():
     del empty, CuckooTable
 
 
+@pytest.mark.parametrize("geom", [GEOMS[i] for i in (1, 4, 6, 10, 14, 17)], ids=ident)
+@pytest.mark.parametrize("depth", [1, 3])
+def test_enqueue_depth_parity(geom, depth):
+    """How many rounds the host enqueues per sub-batch before it looks at the
+    counters is performance only.  With one, nearly every sub-batch still has
+    ops pending when it is checked, so the next sub-batch (already enqueued
+    behind it) finds its gate flag set, does nothing, and is enqueued again.
+    Inserts and deletes stay bit-exact against the oracle."""
+    scheme, B, d, ghost, lb = geom
+    n = 1 << 12 if B > 1 else 1 << 13
+    load = {1: 0.95 if d == 4 else (0.9 if d == 3 else 0.48)}.get(B, 0.97)
+    keys, vals = keys_for(n, B, load, seed=6)
+    kw = dict(ghost=ghost, load_balance=lb, max_chain=1000 if B == 1 else 500, max_search=500,
+              batch_ops=256)
+    print(f"enqueue depth {depth} {geom} keys={keys.size}", flush=True)
+    g = gpu_table(n, B, d, scheme, seed=6, enqueue_rounds=depth, **kw)
+    o = oracle_table(n, B, d, scheme, seed=6, **kw)
+    rg, ro = gpu_insert(g, keys, vals), o.insert(keys, vals)
+    assert_same_ops(rg, ro, f"{geom} depth {depth}")
+    assert_same_image(g.export(), o.export(), f"{geom} depth {depth}")
+    rng = np.random.default_rng(depth)
+    pick = np.concatenate([keys[rng.permutation(keys.size)[: keys.size // 2]], keys_for(n, B, 0.05,
+                                                                                         seed=99)[0]])
+    fg, fo = gpu_delete(g, pick), o.delete(pick)[0]
+    assert np.array_equal(fg, fo), f"{geom} depth {depth} delete"
+    assert_same_image(g.export(), o.export(), f"{geom} depth {depth} after deletes")
+    assert_same_stats(g.stats(), o.stats(), f"{geom} depth {depth}")
+
+
 def test_max_rounds_abort():
     # max_rounds = 1: every op that loses its first claim is aborted, and
     # both sides abort the same ops
