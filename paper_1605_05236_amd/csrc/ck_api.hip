@@ -178,13 +178,17 @@ void free_scratch(ck_table* t) {
 ck_status alloc_scratch(ck_table* t) {
   const uint32_t m = t->opt.batch_ops;
   t->batch_cap = m;
-  // persistent eviction planners: as many one-wavefront workgroups as fit the
-  // LDS budget of a CU (160 KiB on gfx950), at most 32 per CU
+  // persistent eviction planners: as many one-wavefront workgroups as can be
+  // resident at once (registers, LDS, wave slots), so no workgroup waits for
+  // another to finish; when the query fails, as many as the LDS of a CU holds
+  // (160 KiB on gfx950), at most 32
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const size_t lds = evict_lds_bytes(t->g);
   size_t per_cu = std::max<size_t>(1, std::min<size_t>(32, (160 * 1024) / std::max<size_t>(lds, 1)));
+  const int resident = evict_resident_per_cu(t->g);
+  if (resident > 0) per_cu = std::min<size_t>(per_cu, (size_t)resident);
   if (t->opt.evict_wgs_per_cu) per_cu = std::min<size_t>(per_cu, t->opt.evict_wgs_per_cu);
   t->evict_grid = (uint32_t)(cus * per_cu);
   t->wg_bytes = (uint32_t)evict_wg_scratch_bytes(t->g);

@@ -202,6 +202,7 @@ hipError_t launch_commit(const Geo& g, const Round& r, hipStream_t s);
 hipError_t launch_batch_stats(const Round& r, uint64_t m, uint64_t slots, uint32_t* block_tmp,
                               uint32_t is_delete, const uint32_t* open, hipStream_t s);
 size_t evict_lds_bytes(const Geo& g);
+int evict_resident_per_cu(const Geo& g);
 size_t evict_wg_scratch_bytes(const Geo& g);
 hipError_t launch_export_meta(const Geo& g, hipStream_t s);
 

@@ -366,29 +366,22 @@ struct GroupCtx {
 };
 
 // The keys of one bin as the L lanes of an op's group hold them: lane j has
-// slots [j S, (j + 1) S), S = B / L.
+// slots j, j + L, j + 2L, ... (S = B / L of them), so each of the S loads of
+// the group reads one contiguous stretch of the bin's line.
 template <int B, int L>
 struct BinKeys {
   static constexpr int S = B / L;
   uint64_t k[S];
   __device__ __forceinline__ void load(const Geo& g, uint32_t bin, int sl) {
-    const ulonglong2* p = g.slots + (uint64_t)bin * B + (uint64_t)sl * S;
+    const ulonglong2* p = g.slots + (uint64_t)bin * B + sl;
 #pragma unroll
-    for (int q = 0; q < S; ++q) k[q] = p[q].x;
+    for (int q = 0; q < S; ++q) k[q] = p[q * L].x;
   }
   // slots whose key is v, as a B-bit mask (bit = slot index)
   __device__ __forceinline__ uint32_t match(const GroupCtx<L>& G, uint64_t v) const {
     uint32_t m = 0;
 #pragma unroll
-    for (int q = 0; q < S; ++q) {
-      const uint32_t bq = G.ballot(k[q] == v);
-      if (S == 1) {
-        m = bq;
-      } else {
-#pragma unroll
-        for (int j = 0; j < L; ++j) m |= ((bq >> j) & 1u) << (j * S + q);
-      }
-    }
+    for (int q = 0; q < S; ++q) m |= G.ballot(k[q] == v) << (q * L);
     return m;
   }
   // the key in slot `slot` (group-uniform)
@@ -396,8 +389,8 @@ struct BinKeys {
     uint64_t v = k[0];
 #pragma unroll
     for (int q = 1; q < S; ++q)
-      if (slot % S == (uint32_t)q) v = k[q];
-    return __shfl(v, G.gshift + (int)(slot / S), 64);
+      if (slot / L == (uint32_t)q) v = k[q];
+    return __shfl(v, G.gshift + (int)(slot % L), 64);
   }
 };
 
@@ -1705,6 +1698,27 @@ static void fresh_go(const Geo& g, const Round& r, hipStream_t s) {
     case 8: FN<8, 2>(__VA_ARGS__); break;                     \
     default: return hipErrorInvalidValue;                     \
   }
+
+template <int B, int H>
+static void evict_occupancy(const Geo& g, int* per_cu) {
+  const size_t lds = evict_lds_bytes(g);
+  if (g.scheme == CK_BFS || g.scheme == CK_SORTED)
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_plan_search<B, H>, 64, lds);
+  else
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_plan_walk<B, H>, 64, lds);
+}
+
+// Eviction-planner workgroups that can be resident on one compute unit at
+// once (registers, LDS and wave slots all counted).
+int evict_resident_per_cu(const Geo& g) {
+  int per_cu = 0;
+  auto go = [&]() -> hipError_t {
+    CK_DISPATCH(evict_occupancy, g, &per_cu);
+    return hipSuccess;
+  };
+  if (go() != hipSuccess) return 0;
+  return per_cu;
+}
 
 hipError_t launch_plan_fresh(const Geo& g, const Round& r, hipStream_t s) {
   if (r.npend == 0) return hipSuccess;
