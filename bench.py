@@ -34,20 +34,25 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 # per launch in the default fill workload: FETCH_SIZE + WRITE_SIZE from two
 # rocprofv3 --pmc runs of this benchmark (--steps 1 --warmup 1
 # --pmc-calibration), each scaled by its reading for a plain 256 MiB device
-# copy.  It describes the kernel source it was taken on; once that source
-# changes the benchmark reports null until the counters are taken again.
+# copy.  It describes the library source it was taken on (kernels, launch
+# shapes, host loop); once that source changes the benchmark reports null
+# until the counters are taken again.
 MEASURED_EVICT_TRAFFIC = {
-    "kernels_sha256": "cfb5c2ff6e47ffea9a02147ec1f6fccd2b98f7cedcf58a011a9116b298161b3c",
-    "bytes_per_launch": 24756708,
+    "sources_sha256": "dec0c57552d92fd368e94c0167644f0a3b402bc0da747661f9b8d077143d18e8",
+    "bytes_per_launch": 34270096,
     "profile": "profiles/evict_planners__fill95_2e24x8.md",
 }
+_SOURCES = ("ck_kernels.hip", "ck_api.hip", "ck_internal.h")
 
 
-def _kernels_sha256() -> str:
+def _sources_sha256() -> str:
+    """sha256 over the library's sources, in the order of _SOURCES."""
     import hashlib
-    path = os.path.join(ROOT, "paper_1605_05236_amd", "csrc", "ck_kernels.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in _SOURCES:
+        with open(os.path.join(ROOT, "paper_1605_05236_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def pmc_calibration_copies():
@@ -629,7 +634,7 @@ def main():
         per_view = B * 16 + 4
         ach = evict_views * per_view / (kt_ms / 1e3) / 1e9 if kt_ms else 0.0
         traffic = None
-        if MEASURED_EVICT_TRAFFIC["kernels_sha256"] == _kernels_sha256():
+        if MEASURED_EVICT_TRAFFIC["sources_sha256"] == _sources_sha256():
             traffic = MEASURED_EVICT_TRAFFIC["bytes_per_launch"]
         roofline = {"bound": "hbm", "kernel": "k_plan_search<8,2> (bfs, sorted) / "
                                               "k_plan_walk<8,2> (queue)",
