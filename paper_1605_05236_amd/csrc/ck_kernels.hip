@@ -2033,15 +2033,16 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_count(const uint8_t* statu
                                                             const uint32_t* open,
                                                             const uint32_t* gate,
                                                             uint32_t* unfinished) {
-  if (stats_closed_out(open, gate, unfinished, true)) return;
   __shared__ uint32_t s_w[kStatBlock / 64];
   const StatSplit sp(m, gridDim.x);
   const uint32_t t0 = blockIdx.x * sp.per, t1 = min(sp.ntiles, t0 + sp.per);
+  // the status bytes are read before the gate check (unused if it is closed)
   uint32_t n = 0;
   for (uint32_t tile = t0; tile < t1; ++tile) {
     const uint64_t i = (uint64_t)tile * kStatBlock + threadIdx.x;
     n += (i < m && status[i] == CK_OP_OK) ? 1u : 0u;
   }
+  if (stats_closed_out(open, gate, unfinished, true)) return;
   n = (uint32_t)wave_sum(n);
   if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = n;
   __syncthreads();
@@ -2067,6 +2068,30 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
     const uint32_t* retries, const uint32_t* twins, uint64_t m, const uint32_t* block_ok,
     const uint64_t* stored_before, uint64_t slots, DevStats* st, const uint32_t* open,
     const uint32_t* gate) {
+  const StatSplit sp(m, gridDim.x);
+  const uint32_t t0 = blockIdx.x * sp.per, t1 = min(sp.ntiles, t0 + sp.per);
+  // the per-op words of up to kAhead tiles, fetched together; the first
+  // fetch is issued before the gate check and the prefix sum, whose
+  // latencies it then overlaps (if the gate is closed the words go unused)
+  constexpr int kAhead = 4;
+  uint8_t sv[kAhead];
+  uint32_t o_ret[kAhead], o_views[kAhead], o_lost[kAhead], o_kicks[kAhead], o_twins[kAhead];
+  auto fetch = [&](uint32_t tb) {
+#pragma unroll
+    for (int q = 0; q < kAhead; ++q) {
+      const uint64_t idx = (uint64_t)(tb + q) * kStatBlock + threadIdx.x;
+      const bool v = tb + q < t1 && idx < m;
+      const uint64_t i = v ? idx : 0;  // every load in bounds, none behind a branch
+      sv[q] = status[i];
+      o_ret[q] = retries[i];
+      o_views[q] = views[i];
+      o_lost[q] = lost[i];
+      o_kicks[q] = kicks[i];
+      o_twins[q] = twins[i];
+      if (!v) sv[q] = 0xFF;
+    }
+  };
+  if (t0 < t1) fetch(t0);
   if (stats_closed_out(open, gate, nullptr, false)) return;
   __shared__ unsigned long long hb[4][CK_BANDS];
   __shared__ unsigned long long tot[11];
@@ -2083,8 +2108,6 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
     if (lane == 0) s_rank0 = *stored_before + pre;
   }
   __syncthreads();
-  const StatSplit sp(m, gridDim.x);
-  const uint32_t t0 = blockIdx.x * sp.per, t1 = min(sp.ntiles, t0 + sp.per);
   unsigned long long a_ok = 0, a_fail = 0, a_abort = 0, a_bad = 0, a_views = 0, a_vall = 0,
                      a_kicks = 0, a_maxk = 0, a_ret = 0, a_tw = 0;
   // per-lane sums of the current band, added to the workgroup histogram when
@@ -2105,24 +2128,17 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
     return (uint32_t)(b >= CK_BANDS ? CK_BANDS - 1 : b);
   };
   uint64_t rank0 = s_rank0;
-  constexpr int kAhead = 4;  // tiles whose per-op words are fetched together
+  // the band at the workgroup's first rank and the first rank of the next
+  // band: below it an op's band needs no division (bands hold slots /
+  // CK_BANDS inserts, so a workgroup's ranks rarely cross one)
+  uint32_t cb0 = 0;
+  uint64_t next_edge = ~0ull;
+  if (slots) {
+    cb0 = band_of(rank0);
+    if (cb0 + 1 < CK_BANDS) next_edge = ((uint64_t)(cb0 + 1) * slots + CK_BANDS - 1) / CK_BANDS;
+  }
   for (uint32_t tb = t0; tb < t1; tb += kAhead) {
-    uint8_t sv[kAhead];
-    uint32_t o_ret[kAhead], o_views[kAhead], o_lost[kAhead], o_kicks[kAhead], o_twins[kAhead];
-#pragma unroll
-    for (int q = 0; q < kAhead; ++q) {
-      const uint64_t i = (uint64_t)(tb + q) * kStatBlock + threadIdx.x;
-      sv[q] = 0xFF;
-      o_ret[q] = o_views[q] = o_lost[q] = o_kicks[q] = o_twins[q] = 0;
-      if (tb + q < t1 && i < m) {
-        sv[q] = status[i];
-        o_ret[q] = retries[i];
-        o_views[q] = views[i];
-        o_lost[q] = lost[i];
-        o_kicks[q] = kicks[i];
-        o_twins[q] = twins[i];
-      }
-    }
+    if (tb != t0) fetch(tb);
 #pragma unroll
     for (int q = 0; q < kAhead; ++q) {
       if (tb + q >= t1) break;  // uniform
@@ -2152,8 +2168,7 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
             a_abort += 1;
           } else {
             if (slots) {  // a group of tables has no single density: totals only
-              const uint32_t lo = band_of(rank0), hi = band_of(rank0 + ttot);
-              band = lo == hi ? lo : band_of(rank);
+              band = rank < next_edge ? cb0 : band_of(rank);
               banded = true;
             }
             a_views += o_views[q];
