@@ -105,8 +105,11 @@ struct ck_table {
   DevStats* dstats = nullptr;
   uint32_t* block_tmp = nullptr;
   uint32_t stripe_cap = 0;  // entries per pending-list segment
-  uint32_t tail_hint = 2;   // rounds the last insert sub-batch took (sizes the next enqueue)
-  uint32_t tail_hint_del = 1;  // the same for deletes
+  // rounds the last two insert sub-batches took (the larger sizes the next
+  // enqueue) and the rounds the last delete sub-batch took
+  uint32_t tail_hint = 2;
+  uint32_t tail_prev = 2;
+  uint32_t tail_hint_del = 1;
   // host-side counters
   uint64_t rounds = 0, lookups = 0;
   Timer timer;
@@ -278,9 +281,10 @@ Round make_round(ck_table* t, const uint64_t* keys, const void* vals, uint8_t* s
 // The phased rounds of a sub-batch, then its statistics.  The first round's
 // list is every op; each later round's list (and count) exists only on the
 // device, so those rounds run capped grids that loop over whatever count
-// they find.  The host enqueues a sub-batch as its first round, as many more
-// rounds as the last sub-batch of its kind took, the statistics and a copy
-// of its counters, and does so one sub-batch ahead: sub-batch b + 1 is
+// they find.  The host enqueues a sub-batch as as many rounds as the larger
+// of the last two insert sub-batches took (deletes: one more than the last
+// delete sub-batch), the statistics and a copy of its counters, and does so
+// one sub-batch ahead: sub-batch b + 1 is
 // enqueued before the host waits for b's counters.  Every kernel of b + 1
 // checks that b's last list came out empty (its gate) and otherwise does
 // nothing; the host then runs more rounds of b and enqueues b + 1 again.
@@ -378,6 +382,7 @@ ck_status settle(ck_table* t, Flight& f, bool* done) {
   *done = list_count(c, f.cur) == 0;
   if (*done) {
     if (!f.r.is_delete) t->rounds += c.rounds;
+    if (!f.r.is_delete) t->tail_prev = t->tail_hint;
     (f.r.is_delete ? t->tail_hint_del : t->tail_hint) =
         std::min(kMaxTailHint, std::max<uint32_t>(1, c.rounds));
   }
@@ -421,7 +426,8 @@ ck_status run_batches(ck_table* t, const uint64_t* keys, const void* vals, uint6
     set ^= 1;
     const uint32_t K = t->opt.enqueue_rounds
                            ? t->opt.enqueue_rounds
-                           : (is_delete ? t->tail_hint_del : t->tail_hint) + 1;
+                           : (is_delete ? t->tail_hint_del + 1
+                                        : std::max(t->tail_hint, t->tail_prev));
     const uint32_t* gate = prev.live ? &t->ctr[prev.set].unfinished : nullptr;
     ck_status st = enqueue_rounds(t, f, K, true, gate, s);
     if (st != CK_OK) return st;
