@@ -38,8 +38,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 # shapes, host loop); once that source changes the benchmark reports null
 # until the counters are taken again.
 MEASURED_EVICT_TRAFFIC = {
-    "sources_sha256": "dec0c57552d92fd368e94c0167644f0a3b402bc0da747661f9b8d077143d18e8",
-    "bytes_per_launch": 34270096,
+    "sources_sha256": "4fba00321257fa5092efee1953f128a54524adaf406295277d79a741956a196e",
+    "bytes_per_launch": 36350179,
     "profile": "profiles/evict_planners__fill95_2e24x8.md",
 }
 _SOURCES = ("ck_kernels.hip", "ck_api.hip", "ck_internal.h")

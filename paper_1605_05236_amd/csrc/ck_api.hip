@@ -281,7 +281,7 @@ Round make_round(ck_table* t, const uint64_t* keys, const void* vals, uint8_t* s
 // The phased rounds of a sub-batch, then its statistics.  The first round's
 // list is every op; each later round's list (and count) exists only on the
 // device, so those rounds run capped grids that loop over whatever count
-// they find.  The host enqueues a sub-batch as as many rounds as the larger
+// they find.  For a sub-batch the host enqueues as many rounds as the larger
 // of the last two insert sub-batches took (deletes: one more than the last
 // delete sub-batch), the statistics and a copy of its counters, and does so
 // one sub-batch ahead: sub-batch b + 1 is
