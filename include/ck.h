@@ -96,8 +96,9 @@ typedef struct {
   uint32_t enqueue_rounds;   /* rounds enqueued per sub-batch before the host
                                 first looks at its counters (more follow in
                                 groups of this size while ops are pending);
-                                0 = as many as the previous sub-batch took, plus
-                                one, then groups of two.  Performance only */
+                                0 = as many as the larger of the last two
+                                insert sub-batches took (deletes: one more than
+                                the last), then groups of two.  Performance only */
 } ck_options;
 
 /* Counters of one table since creation (or the last ck_stats_reset). */
@@ -113,6 +114,8 @@ typedef struct {
      an op's density is the table's had its sub-batch been applied in op order */
   uint64_t band_inserts[CK_BANDS], band_views[CK_BANDS];
   uint64_t band_kicks[CK_BANDS], band_fails[CK_BANDS];
+  uint64_t arena_moves; /* capacity of the plan arena (moves of one round's
+                           kick-out plans); it doubles when a round runs out */
 } ck_stats;
 
 /* Defaults: no ghosts, first fit, max_chain 500, max_search 500, max_rounds 0,

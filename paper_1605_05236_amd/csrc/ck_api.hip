@@ -371,13 +371,17 @@ ck_status enqueue_rounds(ck_table* t, Flight& f, uint32_t K, bool first, const u
 
 // Waits for a sub-batch's counters; *done tells whether its last list came
 // out empty (its statistics have then applied).
-ck_status settle(ck_table* t, Flight& f, bool* done) {
+ck_status settle(ck_table* t, Flight& f, hipStream_t s, bool* done) {
   HIP_TRY(hipEventSynchronize(t->ctr_ready[f.set]));
   t->timer.collect();
   const Ctr& c = t->h_ctr[f.set];
   if (c.overflow || c.overflow_seen) {  // a void round: a larger arena for what follows
     ck_status st = grow_arena(t);
     if (st != CK_OK) return st;
+    // the flags are seen: clear them before any later round of this
+    // sub-batch (the only user of this counter set until it is done) runs,
+    // or each later look would grow the arena again
+    HIP_TRY(hipMemsetAsync(&t->ctr[f.set].overflow, 0, 2 * sizeof(uint32_t), s));
   }
   *done = list_count(c, f.cur) == 0;
   if (*done) {
@@ -393,7 +397,7 @@ ck_status settle(ck_table* t, Flight& f, bool* done) {
 ck_status finish(ck_table* t, Flight& f, hipStream_t s) {
   for (;;) {
     bool done = false;
-    ck_status st = settle(t, f, &done);
+    ck_status st = settle(t, f, s, &done);
     if (st != CK_OK) return st;
     if (done) return CK_OK;
     st = enqueue_rounds(t, f, t->opt.enqueue_rounds ? t->opt.enqueue_rounds : 2, false, nullptr,
@@ -433,7 +437,7 @@ ck_status run_batches(ck_table* t, const uint64_t* keys, const void* vals, uint6
     if (st != CK_OK) return st;
     if (prev.live) {
       bool done = false;
-      st = settle(t, prev, &done);
+      st = settle(t, prev, s, &done);
       if (st != CK_OK) return st;
       if (!done) {
         // this sub-batch saw a non-empty gate and did nothing: finish the
@@ -651,6 +655,7 @@ ck_status ck_stats_get(ck_table* t, ck_stats* out, void* stream) {
     out->band_kicks[b] = d.band[2][b];
     out->band_fails[b] = d.band[3][b];
   }
+  out->arena_moves = t->arena_cap;
   return CK_OK;
 }
 

@@ -37,7 +37,8 @@ class CkOptions(ctypes.Structure):
 class CkStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in _SCALARS] + [
         ("band_inserts", ctypes.c_uint64 * BANDS), ("band_views", ctypes.c_uint64 * BANDS),
-        ("band_kicks", ctypes.c_uint64 * BANDS), ("band_fails", ctypes.c_uint64 * BANDS)]
+        ("band_kicks", ctypes.c_uint64 * BANDS), ("band_fails", ctypes.c_uint64 * BANDS),
+        ("arena_moves", ctypes.c_uint64)]
 
 
 class CkKernelTime(ctypes.Structure):
@@ -45,7 +46,7 @@ class CkKernelTime(ctypes.Structure):
 
 
 _TIMED = ["plan_fresh", "plan_evict", "plan_delete", "commit", "stats", "lookup"]
-TIME_ALL = 127
+TIME_ALL = 63
 
 
 def time_mask(classes) -> int:
@@ -250,6 +251,7 @@ class CuckooTable:
         out = {n: int(getattr(s, n)) for n in _SCALARS}
         for f in ("band_inserts", "band_views", "band_kicks", "band_fails"):
             out[f] = np.array(list(getattr(s, f)), dtype=np.uint64)
+        out["arena_moves"] = int(s.arena_moves)
         return out
 
     def reset_stats(self, stream=None):

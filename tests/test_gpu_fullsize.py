@@ -194,3 +194,28 @@ def test_steady_state_mixed_ghost_queue():
     _lookup_all(t, k, v)
     assert checks.check_image_torch(t.export(), n, B, 2, 104, ghost=True) == stored.numel()
     assert t.stats()["stored"] == stored.numel()
+
+
+def test_arena_growth_stays_bounded():
+    """A d-ary random walk past its threshold overflows the first plan arena
+    (long walks, many rounds).  The arena doubles only when a round runs out:
+    it must end above its first size and below 2 m (max_chain + 1) moves, the
+    most one round of m ops can need, doubled.  Results keep their
+    properties: stored keys found with their values, failed keys absent."""
+    import torch
+    n, d, m, chain = 1 << 18, 3, 1 << 16, 1000
+    t = _table(n, 1, d, "random_walk", max_chain=chain, batch_ops=m, hash_seed=106,
+               rng_seed=206)
+    arena0 = t.stats()["arena_moves"]
+    total = inputs.target_count(n, 1, 0.93)
+    keys, vals = inputs.keys_values_torch(7, total, value_bits=32)
+    print(f"arena growth: {total} inserts, first arena {arena0} moves", flush=True)
+    st = t.insert(keys, _values_for(vals, 1), diagnostics=False)["status"]
+    s = t.stats()
+    print(f"arena growth: arena {s['arena_moves']} moves, rounds {s['rounds']}, "
+          f"failed {int((st != 1).sum())}", flush=True)
+    assert arena0 < s["arena_moves"] <= 2 * m * (chain + 1)
+    ok = st == 1
+    _lookup_all(t, keys[ok], vals[ok])
+    _absent(t, keys[~ok])
+    assert checks.check_image_torch(t.export(), n, 1, d, 106) == int(ok.sum())
