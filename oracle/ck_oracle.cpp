@@ -21,7 +21,8 @@
 //                                  assumed absent; cost = bins viewed per insert.
 //   Sec. 4  (Ghost insertions)     duplicates in both bins; Proposition 4.1.
 //   Sec. 5  (Sorted search)        BFS over records; spawn-count ordering with
-//                                  16 buckets; visited-bin set; Theorem 5.1.
+//                                  16 buckets; visited-bin set; Theorem 5.1;
+//                                  the sorted/BFS hybrid (depth, then count).
 //   Sec. 6  (Queue-kicking)        FIFO victims via per-bin hit counters; hit
 //                                  balancing; fetch-and-add slot scheduling.
 //   Sec. 7  (Rattle-kicking)       d-ary tables, per-key rattle counters.
@@ -33,6 +34,7 @@
 // quoted statistics); see the test files for which pin covers which function.
 
 #include <algorithm>
+#include <array>
 #include <cstdint>
 #include <cstring>
 #include <deque>
@@ -45,7 +47,7 @@ namespace {
 constexpr uint64_t kEmpty = ~0ull;  // reserved key marking an empty slot
 constexpr int kBands = 200;         // 0.5 % density bands
 
-enum Scheme { RANDOM_WALK = 0, BFS = 1, SORTED = 2, QUEUE = 3, RATTLE = 4 };
+enum Scheme { RANDOM_WALK = 0, BFS = 1, SORTED = 2, QUEUE = 3, RATTLE = 4, HYBRID = 5 };
 enum OpStatus { ST_NOT_FOUND = 0, ST_OK = 1, ST_FAIL = 2, ST_ABORTED = 3, ST_BAD_KEY = 4 };
 
 // ---------------------------------------------------------------------------
@@ -329,47 +331,58 @@ struct Plan {
     }
   }
 
-  // ---- Breadth-first search and sorted search (Sec. 5) --------------------------
+  // ---- Breadth-first search, sorted search and their hybrid (Sec. 5) -------------
   // The search state is a list of records viewed but not yet spawned.  BFS
   // spawns them in FIFO order; sorted search spawns the one whose bin has the
   // smallest spawn count, kept as 16 FIFO buckets (bucket sort) keyed by the
-  // capped spawn count read when the record enters the list.  Bins already
-  // visited by this search are never viewed again.
+  // capped spawn count read when the record enters the list.  The hybrid
+  // orders first by the depth at which a record entered the search (the
+  // records of the key's own bins have depth 0, those of a bin viewed while
+  // spawning a depth-d record depth d + 1), then by that spawn count, FIFO
+  // among equals.  Bins already visited by this search are never viewed
+  // again, in all three.
+  enum Order { BY_FIFO = 0, BY_COUNT = 1, BY_DEPTH_COUNT = 2 };
   struct Entry {
     uint64_t bin;
     int slot;
     int parent;  // index into `entries`, -1 for the records of the key's own bins
+    int depth;
   };
-  void search(const Slot& x, const uint64_t* h, bool sorted) {
+  void search(const Slot& x, const uint64_t* h, Order order) {
     if (place_fresh(x, h)) { status = ST_OK; return; }
     std::vector<Entry> entries;
-    std::deque<int> bucket[16];
+    // bucket[level][count]: level = depth for the hybrid, else 0
+    std::vector<std::array<std::deque<int>, 16>> bucket(1);
     std::set<uint64_t> visited;
-    auto enqueue_bin = [&](uint64_t b, int parent) {
+    auto enqueue_bin = [&](uint64_t b, int parent, int depth) {
       BinState s = read(b);
-      int key = sorted ? std::min<int>(15, s.sc) : 0;
+      int key = order != BY_FIFO ? std::min<int>(15, s.sc) : 0;
+      size_t level = order == BY_DEPTH_COUNT ? (size_t)depth : 0;
+      if (bucket.size() <= level) bucket.resize(level + 1);
       for (int i = 0; i < T.p.B; ++i) {
-        entries.push_back({b, i, parent});
-        bucket[key].push_back((int)entries.size() - 1);
+        entries.push_back({b, i, parent, depth});
+        bucket[level][key].push_back((int)entries.size() - 1);
       }
     };
     for (int i = 0; i < T.p.H; ++i) {
       visited.insert(h[i]);
-      enqueue_bin(h[i], -1);
+      enqueue_bin(h[i], -1, 0);
     }
     for (;;) {
-      int k = 0;
-      while (k < 16 && bucket[k].empty()) ++k;
-      if (k == 16) { status = ST_FAIL; return; }  // nothing left to spawn
-      int e = bucket[k].front();
-      bucket[k].pop_front();
+      std::deque<int>* q = nullptr;
+      for (size_t lv = 0; lv < bucket.size() && !q; ++lv)
+        for (int k = 0; k < 16 && !q; ++k)
+          if (!bucket[lv][k].empty()) q = &bucket[lv][k];
+      if (!q) { status = ST_FAIL; return; }  // nothing left to spawn
+      int e = q->front();
+      q->pop_front();
       Entry en = entries[e];
       Slot rec = read(en.bin).s[en.slot];
       bool spawned = false;
       for (uint64_t child : others(rec.key, en.bin)) {
         if (visited.count(child)) continue;
         if (views == T.p.max_search) { status = ST_FAIL; return; }
-        if (!spawned && sorted) spawns.push_back(en.bin);
+        if (!spawned && order != BY_FIFO) spawns.push_back(en.bin);
         spawned = true;
         visited.insert(child);
         if (terminal(view(child))) {
@@ -388,7 +401,7 @@ struct Plan {
           status = ST_OK;
           return;
         }
-        enqueue_bin(child, e);
+        enqueue_bin(child, e, en.depth + 1);
       }
     }
   }
@@ -434,8 +447,9 @@ Plan plan_insert(const Table& T, uint64_t op, uint64_t key, uint64_t val) {
   T.hash(key, h);
   switch (T.p.scheme) {
     case RANDOM_WALK: pl.random_walk(x, h); break;
-    case BFS: pl.search(x, h, false); break;
-    case SORTED: pl.search(x, h, true); break;
+    case BFS: pl.search(x, h, Plan::BY_FIFO); break;
+    case SORTED: pl.search(x, h, Plan::BY_COUNT); break;
+    case HYBRID: pl.search(x, h, Plan::BY_DEPTH_COUNT); break;
     case QUEUE: pl.queue_kick(x, h); break;
     case RATTLE: pl.rattle(x, h); break;
   }
@@ -561,7 +575,7 @@ void* ck_oracle_create(uint64_t n, int B, int H, int scheme, int ghost, int load
                        uint32_t max_chain, uint32_t max_search, uint32_t max_rounds,
                        uint32_t batch_ops, uint64_t hash_seed, uint64_t rng_seed) {
   if (n < (uint64_t)H || B < 1 || B > 8 || H < 2 || H > 4 || batch_ops == 0) return nullptr;
-  if (scheme < RANDOM_WALK || scheme > RATTLE) return nullptr;
+  if (scheme < RANDOM_WALK || scheme > HYBRID) return nullptr;
   if (H > 2 && B != 1) return nullptr;                 // d-ary tables use single-slot bins
   if (ghost && H != 2) return nullptr;                 // ghosts need exactly two bins
   if (scheme == RATTLE && (B != 1 || ghost)) return nullptr;

@@ -16,9 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "ck_oracle.cpp")
 LIB = os.path.join(HERE, "libck_oracle.so")
 
-RANDOM_WALK, BFS, SORTED, QUEUE, RATTLE = range(5)
+RANDOM_WALK, BFS, SORTED, QUEUE, RATTLE, HYBRID = range(6)
 SCHEMES = {"random_walk": RANDOM_WALK, "bfs": BFS, "sorted": SORTED, "queue": QUEUE,
-           "rattle": RATTLE}
+           "rattle": RATTLE, "hybrid": HYBRID}
 ST_NOT_FOUND, ST_OK, ST_FAIL, ST_ABORTED, ST_BAD_KEY = range(5)
 EMPTY = np.uint64(0xFFFFFFFFFFFFFFFF)
 BANDS = 200

@@ -80,7 +80,7 @@ def test_hash_uniform():
 
 
 # --------------------------------------------------------------------------- invariants
-CASES = [(s, g) for s in ("random_walk", "bfs", "sorted", "queue") for g in (False, True)]
+CASES = [(s, g) for s in ("random_walk", "bfs", "sorted", "hybrid", "queue") for g in (False, True)]
 
 
 @pytest.mark.parametrize("scheme,ghost", CASES)
@@ -101,7 +101,8 @@ def test_invariants_after_fill(scheme, ghost, batch):
 
 
 @pytest.mark.parametrize("scheme,d", [("random_walk", 3), ("random_walk", 4), ("rattle", 2),
-                                      ("rattle", 3), ("rattle", 4), ("bfs", 4), ("sorted", 3)])
+                                      ("rattle", 3), ("rattle", 4), ("bfs", 4), ("sorted", 3),
+                                      ("hybrid", 3)])
 def test_invariants_dary(scheme, d):
     t = make(1 << 11, 1, d, scheme, max_chain=1000, max_search=1000)
     k, v, r = fill(t, 0.9 if d > 2 else 0.45)
@@ -132,7 +133,8 @@ def test_failed_insert_leaves_table_unchanged():
 
 # --------------------------------------------------------------------------- dictionary semantics
 @pytest.mark.parametrize("scheme,ghost,d,B", [("random_walk", False, 2, 4), ("bfs", True, 2, 4),
-                                              ("sorted", False, 2, 8), ("queue", True, 2, 4),
+                                              ("sorted", False, 2, 8), ("hybrid", True, 2, 4),
+                                              ("queue", True, 2, 4),
                                               ("queue", False, 2, 2), ("rattle", False, 3, 1),
                                               ("random_walk", True, 2, 1)])
 @pytest.mark.parametrize("batch", [1, 16])
@@ -216,11 +218,16 @@ def brute_min_kicks(img, n, B, x, seed):
     return best[0]
 
 
+@pytest.mark.parametrize("scheme", ["bfs", "hybrid"])
 @pytest.mark.parametrize("n,B", [(6, 1), (8, 1), (6, 2), (8, 2)])
-def test_bfs_chain_is_shortest(n, B):
+def test_bfs_chain_is_shortest(n, B, scheme):
+    # Sec. 5: BFS returns the shortest kick-out chain.  The sorted/BFS hybrid
+    # spawns every record of one depth before any of the next, so the first
+    # free slot it meets is at the least depth too: its chains are shortest
+    # as well, whatever the spawn counts (sorted search's need not be).
     checked = 0
     for trial in range(60):
-        t = make(n, B, 2, "bfs", seed=trial, max_search=1000)
+        t = make(n, B, 2, scheme, seed=trial, max_search=1000)
         keys, vals = inputs.keys_values(1000 + trial, n * B + 4)
         for i in range(keys.size):
             h = t.hash(keys[i])
@@ -240,9 +247,11 @@ def test_bfs_chain_is_shortest(n, B):
     assert checked > 50
 
 
-def test_sorted_with_equal_counts_is_bfs():
+@pytest.mark.parametrize("scheme", ["sorted", "hybrid"])
+def test_sorted_with_equal_counts_is_bfs(scheme):
     # Sec. 5: sorted search differs from BFS only by its ordering statistic;
-    # with every spawn count equal (all buckets the same) it is BFS.
+    # with every spawn count equal (all buckets the same) it is BFS.  So is
+    # the hybrid, whose depth order within one count is BFS order.
     for seed in range(8):
         base = make(1 << 6, 4, 2, "bfs", seed=seed, max_search=1000)
         k, v, _ = fill(base, 0.9, seed)
@@ -250,8 +259,8 @@ def test_sorted_with_equal_counts_is_bfs():
         img["meta"] &= np.uint32(0xFF0000FF)  # spawn counts to zero
         nk, nv = inputs.keys_values(500 + seed, 20)
         res = []
-        for scheme in ("bfs", "sorted"):
-            t = make(1 << 6, 4, 2, scheme, seed=seed, max_search=1000)
+        for sch in ("bfs", scheme):
+            t = make(1 << 6, 4, 2, sch, seed=seed, max_search=1000)
             t.load(img)
             r = t.insert(nk[:1], nv[:1])
             out = t.export()
@@ -260,7 +269,7 @@ def test_sorted_with_equal_counts_is_bfs():
 
 
 # --------------------------------------------------------------------------- ghosts: Prop. 4.1
-@pytest.mark.parametrize("scheme", ["random_walk", "bfs", "sorted", "queue"])
+@pytest.mark.parametrize("scheme", ["random_walk", "bfs", "sorted", "hybrid", "queue"])
 def test_prop_4_1_chains_end_on_duplicates(scheme):
     # Proposition 4.1: in an insert-only table with ghost insertions, the last
     # bin of every kick-out chain held a duplicate.  Observable: a chain with
@@ -386,7 +395,7 @@ def test_rattle_near_ideal_below_85(d):
 def fig1():
     # Sec. 3 setup (2^13 bins x 4 slots filled to 97.5%), ten tables each.
     out = {}
-    for scheme in ("random_walk", "bfs", "sorted", "queue"):
+    for scheme in ("random_walk", "bfs", "sorted", "hybrid", "queue"):
         for ghost in (False, True):
             out[(scheme, ghost)] = run_fill(1 << 13, 4, 2, scheme, 0.975, range(1, 11),
                                             ghost=ghost)
@@ -415,6 +424,16 @@ def test_sorted_beats_bfs_and_random(fig1):
         o = band_mean(fig1[other], 194, 195)
         assert o / s > 4.0
         assert o / sg > 5.0
+
+
+def test_hybrid_between_sorted_and_bfs(fig1):
+    # Sec. 5: the sorted/BFS hybrid's cost falls between sorted search's and
+    # BFS's (Fig. 1 setup, the last band before 97.5%).
+    for ghost in (False, True):
+        s = band_mean(fig1[("sorted", ghost)], 194, 195)
+        h = band_mean(fig1[("hybrid", ghost)], 194, 195)
+        b = band_mean(fig1[("bfs", ghost)], 194, 195)
+        assert s < h < b, (ghost, s, h, b)
 
 
 def test_queue_kicking_beats_random(fig1):
