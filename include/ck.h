@@ -60,13 +60,16 @@ typedef enum {
  *   CK_SORTED       sorted search by per-bin spawn count (Sec. 5).
  *   CK_QUEUE        queue-kicking with hit counters, load and hit balancing
  *                   (Sec. 6); two hash functions only.
- *   CK_RATTLE       rattle-kicking, d-ary tables with single-slot bins (Sec. 7). */
+ *   CK_RATTLE       rattle-kicking, d-ary tables with single-slot bins (Sec. 7).
+ *   CK_HYBRID       the sorted-search / BFS hybrid: records spawned by depth,
+ *                   then by spawn count (Sec. 5). */
 typedef enum {
   CK_RANDOM_WALK = 0,
   CK_BFS = 1,
   CK_SORTED = 2,
   CK_QUEUE = 3,
-  CK_RATTLE = 4
+  CK_RATTLE = 4,
+  CK_HYBRID = 5
 } ck_scheme;
 
 /* Per-op result bytes written to device arrays. */

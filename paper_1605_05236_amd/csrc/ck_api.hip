@@ -214,7 +214,7 @@ ck_status alloc_scratch(ck_table* t) {
   const uint64_t slack = (uint64_t)t->evict_grid * 512;
   t->arena_cap = (uint32_t)std::min<uint64_t>((uint64_t)m * 4 + slack, 1u << 30);
   HIP_TRY(dalloc(&t->arena, t->arena_cap));
-  t->spawn_cap = t->scheme == CK_SORTED
+  t->spawn_cap = (t->scheme == CK_SORTED || t->scheme == CK_HYBRID)
                      ? (uint32_t)std::min<uint64_t>((uint64_t)m * 2 + slack, 1u << 30)
                      : 16;
   HIP_TRY(dalloc(&t->spawns, t->spawn_cap));
@@ -236,7 +236,7 @@ ck_status grow_arena(ck_table* t) {
   uint64_t nc = std::min<uint64_t>((uint64_t)t->arena_cap * 2, 1u << 30);
   t->arena_cap = (uint32_t)nc;
   HIP_TRY(dalloc(&t->arena, t->arena_cap));
-  if (t->scheme == CK_SORTED) {
+  if (t->scheme == CK_SORTED || t->scheme == CK_HYBRID) {
     (void)hipFree(t->spawns);
     t->spawns = nullptr;
     t->spawn_cap = (uint32_t)std::min<uint64_t>((uint64_t)t->spawn_cap * 2, 1u << 30);
@@ -495,7 +495,7 @@ static ck_status create_table(uint64_t bins, uint32_t B, uint32_t d, ck_scheme s
   ck_options o;
   ck_default_options(&o);
   if (opt) o = *opt;
-  if ((int)scheme < CK_RANDOM_WALK || (int)scheme > CK_RATTLE) return CK_EINVAL;
+  if ((int)scheme < CK_RANDOM_WALK || (int)scheme > CK_HYBRID) return CK_EINVAL;
   if (scheme == CK_RATTLE && (B != 1 || o.ghost)) return CK_EINVAL;
   if (scheme == CK_QUEUE && d != 2) return CK_EINVAL;
   if (o.ghost && d != 2) return CK_EINVAL;

@@ -1020,14 +1020,26 @@ constexpr int kSearchW = 16;  // lanes per search
 constexpr int kSearchLoads = 2;  // bin slots per lane in one group load
 
 size_t search_runs(const Geo& g) { return (size_t)g.max_search + 8 + g.H; }
-static size_t search_group_lds_words() { return 3 * kSearchLdsRuns + 32; }
+// search orders: BFS (FIFO), sorted search (spawn count), their hybrid
+// (depth, then spawn count)
+constexpr int kOrderFifo = 0, kOrderCount = 1, kOrderDepthCount = 2;
+// LDS words of one search group: run bins, parents and links (kSearchLdsRuns
+// each), then bucket heads and tails, and the hybrid's next-depth heads and
+// tails (16 each).  The kernel's group stride and the launch's size both
+// come from here.
+__host__ __device__ constexpr uint32_t search_group_lds_words() {
+  return 3 * kSearchLdsRuns + 4 * 16;
+}
 static size_t search_group_scratch_bytes(const Geo& g) {
   const size_t RC = search_runs(g);
   return ((RC * g.B * (g.H - 1) + 5 * RC) * 4 + 255) & ~(size_t)255;
 }
 
-template <int B, int H>
-__global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
+// At least four wavefronts per SIMD: the register budget that keeps 16
+// one-wavefront workgroups resident per CU.
+template <int B, int H, int O>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_plan_search(
+    Geo g, Round r) {
   constexpr int W = kSearchW;
   constexpr int P = 64 / W;       // searches per wavefront
   constexpr uint32_t C = H - 1;   // candidates per record
@@ -1048,11 +1060,14 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
   const uint64_t gmask = W == 64 ? ~0ull : ((1ull << W) - 1);
   auto gballot = [&](bool p) -> uint64_t { return (__ballot(p) >> gb) & gmask; };
   const uint32_t RC = g.max_search + 8 + H;
-  uint32_t* rbinL = lds32 + (size_t)gi * (3 * RL + 32);
+  uint32_t* rbinL = lds32 + (size_t)gi * search_group_lds_words();
   uint32_t* rparL = rbinL + RL;
   uint32_t* rnextL = rparL + RL;
   uint32_t* bhead = rnextL + RL;  // record at the head of each bucket
   uint32_t* btail = bhead + 16;   // last run of each bucket
+  uint32_t* nhead = btail + 16;   // the hybrid: the next depth's buckets
+  uint32_t* ntail = nhead + 16;
+  static_assert(3 * RL + 4 * 16 <= search_group_lds_words(), "search group LDS layout");
   // the group's scratch: one workgroup-uniform base plus a per-group word
   // offset, so the arrays cost one register, not a pointer each
   uint32_t* const wsb = (uint32_t*)((char*)r.wg_scratch + (size_t)blockIdx.x * r.wg_scratch_bytes);
@@ -1079,8 +1094,11 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
     if (j < RL) rnextL[j] = nx;
     else rnextG(j) = nx;
   };
-  const bool sorted = g.scheme == CK_SORTED;
-  const bool need_meta = sorted || g.ghost;
+  // spawn counts order the search (sorted search, the hybrid); the hybrid
+  // spawns a whole depth before the next
+  constexpr bool by_count = O != kOrderFifo;
+  constexpr bool hybrid = O == kOrderDepthCount;
+  const bool need_meta = by_count || g.ghost;
   if (lane == 0) {
     region_init(win, r.arena_cap);
     region_init(win + 2, r.spawn_cap);
@@ -1111,7 +1129,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
   for (int j = 0; j < H; ++j) h_nx[j] = 0;
   // next op's root slots: root record e = gl + s W in lane gl, slot s
   uint64_t rk_nx[RBW];
-  uint32_t rm_nx[RBW];  // their bins' metadata words (sorted)
+  uint32_t rm_nx[RBW];  // their bins' metadata words (spawn-count orders)
 #pragma unroll
   for (int t = 0; t < RBW; ++t) { rk_nx[t] = kEmpty; rm_nx[t] = 0; }
   auto fetch_roots = [&]() {
@@ -1128,7 +1146,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
         for (int j = 1; j < H; ++j)
           if (q == j) hb = h_nx[j];
         rk_nx[t] = g.slots[(uint64_t)hb * B + sl].x;
-        if (sorted) rm_nx[t] = g.meta[hb];
+        if (by_count) rm_nx[t] = g.meta[hb];
       }
     }
   };
@@ -1166,7 +1184,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
 #pragma unroll
         for (int j = 1; j < H; ++j)
           if (q == j) hb = h[j];
-        if (sorted) bk[t2] = min(15u, (rmeta[t2] >> 8) & 0xFu);
+        if (by_count) bk[t2] = min(15u, (rmeta[t2] >> 8) & 0xFu);
         uint32_t hv[H];
         hash_key<H>(g, T, rkey[t2], hv);
         uint32_t o = 0;
@@ -1191,6 +1209,8 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
     for (int j = gl; j < 16; j += W) {
       bhead[j] = kNone;
       btail[j] = kNone;
+      nhead[j] = kNone;
+      ntail[j] = kNone;
     }
     uint32_t bks[H];  // root run j's bucket: from root record j B
 #pragma unroll
@@ -1204,8 +1224,9 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
       bks[j] = v;
     }
     wave_sync();
-    uint32_t bmask = 0;  // sorted: non-empty buckets (group-uniform)
-    if (have && sorted) {
+    uint32_t bmask = 0;   // spawn-count orders: non-empty buckets (group-uniform)
+    uint32_t nbmask = 0;  // the hybrid: non-empty buckets of the next depth
+    if (have && by_count) {
 #pragma unroll
       for (int j = 0; j < H; ++j) {
         if (gl == 0) {
@@ -1233,7 +1254,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
 #pragma unroll
       for (int t = 0; t < UW; ++t) { my_e[t] = 0; my_j[t] = 0; }
       uint32_t nu = 0;
-      if (!sorted) {
+      if (!by_count) {
         const uint32_t tail = nruns * B;
         if (head == tail) break;
         const uint32_t nrec = min(G / C, tail - head);
@@ -1245,7 +1266,21 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
           my_j[t] = u % C;
         }
       } else {
-        if (bmask == 0) break;
+        if (bmask == 0) {
+          if (!hybrid || nbmask == 0) break;
+          // the hybrid: this depth is spawned out, the next one's buckets
+          // become current
+          wave_sync();
+          if (gl < 16) {
+            bhead[gl] = nhead[gl];
+            btail[gl] = ntail[gl];
+            nhead[gl] = kNone;
+            ntail[gl] = kNone;
+          }
+          wave_sync();
+          bmask = nbmask;
+          nbmask = 0;
+        }
         const int kb2 = __ffs(bmask) - 1;
         uint32_t e = bhead[kb2];
         while (e != kNone && nu + C <= G) {
@@ -1334,13 +1369,14 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
         const uint32_t b2 = min(15u, (mu >> 8) & 0xFu);
         // the cut: first terminal (kept), first run into a lower bucket
         // (kept, then regroup), or the view that would pass max_search (not kept)
-        const uint32_t kb_now = sorted ? (uint32_t)(__ffs(bmask) - 1) : 0u;
+        const uint32_t kb_now = by_count ? (uint32_t)(__ffs(bmask) - 1) : 0u;
         const uint64_t NV = gballot(nv);
         const uint64_t below = (1ull << u) - 1;
         const uint32_t rank = (uint32_t)__popcll(NV & below);
         const uint32_t avail = g.max_search - views;
         const uint64_t TERM = gballot(nv && term);
-        const uint64_t LOW = sorted ? gballot(nv && !term && b2 < kb_now) : 0ull;
+        // (the hybrid's new runs are one depth down: never ahead of this group)
+        const uint64_t LOW = (by_count && !hybrid) ? gballot(nv && !term && b2 < kb_now) : 0ull;
         const uint64_t CAP = gballot(nv && rank == avail);
         const uint32_t t_term = TERM ? (uint32_t)__ffsll((unsigned long long)TERM) - 1 : 64u;
         const uint32_t t_low = LOW ? (uint32_t)__ffsll((unsigned long long)LOW) - 1 : 64u;
@@ -1360,9 +1396,9 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
         const uint64_t VIEW = NV & upto;
         const uint64_t RUNS = VIEW & ~TERM;
         views += (uint32_t)__popcll(VIEW);
-        // spawn list (sorted): every record that viewed its candidate
-        if (sorted && ((VIEW >> u) & 1ull)) spl(nsp + (uint32_t)__popcll(VIEW & below)) = e_u / B;
-        if (sorted) nsp += (uint32_t)__popcll(VIEW);
+        // spawn list (spawn-count orders): every record that viewed its candidate
+        if (by_count && ((VIEW >> u) & 1ull)) spl(nsp + (uint32_t)__popcll(VIEW & below)) = e_u / B;
+        if (by_count) nsp += (uint32_t)__popcll(VIEW);
         // new runs, in record order
         const bool mkrun = (RUNS >> u) & 1ull;
         const uint32_t run_u = nruns + (uint32_t)__popcll(RUNS & below);
@@ -1392,7 +1428,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
           }
         }
         // pop the processed records, then link the new runs
-        if (!sorted) {
+        if (!by_count) {
           head += cut;
         } else {
           uint32_t eh = bhead[kb_now];
@@ -1417,13 +1453,16 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
             rr &= rr - 1;
             const uint32_t run = __shfl(run_u, gb + (int)v, 64);
             const uint32_t bv = __shfl(b2, gb + (int)v, 64);
+            uint32_t* const lh = hybrid ? nhead : bhead;
+            uint32_t* const lt = hybrid ? ntail : btail;
             if (gl == 0) {
               set_next(run, kNone);
-              if (btail[bv] == kNone) bhead[bv] = run * B;
-              else set_next(btail[bv], run);
-              btail[bv] = run;
+              if (lt[bv] == kNone) lh[bv] = run * B;
+              else set_next(lt[bv], run);
+              lt[bv] = run;
             }
-            bmask |= 1u << bv;
+            if (hybrid) nbmask |= 1u << bv;
+            else bmask |= 1u << bv;
             wave_sync();
           }
         }
@@ -1439,7 +1478,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
           const uint32_t v = __shfl(my_e[t], gb + (int)(u % W), 64);
           if (u / W == (uint32_t)t) e = v;
         }
-        if (sorted) {
+        if (by_count) {
           const int kb2 = bmask ? __ffs(bmask) - 1 : -1;
           if (kb2 < 0 || bhead[kb2] != e) break;  // order changed: regroup
           wave_sync();
@@ -1475,7 +1514,7 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
           }
           if (seen) continue;
           if (views == g.max_search) { done = true; break; }
-          if (sorted && !spawned) {
+          if (by_count && !spawned) {
             if (gl == 0) spl(nsp) = e / B;
             ++nsp;
           }
@@ -1515,25 +1554,28 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
           }
           if (gl == 0) set_run(run, c, e);
           wave_sync();
-          if (sorted) {
+          if (by_count) {
             const uint32_t b2 = min(15u, (vm >> 8) & 0xFu);
+            uint32_t* const lh = hybrid ? nhead : bhead;
+            uint32_t* const lt = hybrid ? ntail : btail;
             if (gl == 0) {
               set_next(run, kNone);
-              if (btail[b2] == kNone) bhead[b2] = run * B;
-              else set_next(btail[b2], run);
-              btail[b2] = run;
+              if (lt[b2] == kNone) lh[b2] = run * B;
+              else set_next(lt[b2], run);
+              lt[b2] = run;
             }
-            bmask |= 1u << b2;
+            if (hybrid) nbmask |= 1u << b2;
+            else bmask |= 1u << b2;
             wave_sync();
           }
         }
       }
-          }
-}
+      }
+    }
     fetch_roots();
     // ---- spawn counts go to the spawn arena for every plan, winning or not
     uint32_t soff = 0;
-    if (sorted && nsp > 0) {
+    if (by_count && nsp > 0) {
       uint32_t o = 0;
       if (gl == 0) o = region_take(win + 2, nsp, r.ctr);
       soff = __shfl(o, gb, 64);
@@ -1651,14 +1693,18 @@ __global__ __launch_bounds__(64) void k_plan_search(Geo g, Round r) {
   if (threadIdx.x == 0 && s_views) r.wg_views[blockIdx.x] += s_views;
 }
 
+static bool is_search(uint32_t scheme) {
+  return scheme == CK_BFS || scheme == CK_SORTED || scheme == CK_HYBRID;
+}
+
 size_t evict_lds_bytes(const Geo& g) {
-  if (g.scheme == CK_BFS || g.scheme == CK_SORTED)
+  if (is_search(g.scheme))
     return (64 / kSearchW) * search_group_lds_words() * 4 + 64;
   return (64 / kWalkW) * walk_group_lds_bytes() + 64;
 }
 
 size_t evict_wg_scratch_bytes(const Geo& g) {
-  if (g.scheme == CK_BFS || g.scheme == CK_SORTED)
+  if (is_search(g.scheme))
     return (64 / kSearchW) * search_group_scratch_bytes(g);
   return (64 / kWalkW) * walk_group_scratch_bytes(g);
 }
@@ -1672,8 +1718,13 @@ constexpr uint32_t kTailCommitBlocks = 1024;
 template <int B, int H>
 static void evict_go(const Geo& g, const Round& r, uint32_t grid, hipStream_t s) {
   const size_t lds = evict_lds_bytes(g);
-  if (g.scheme == CK_BFS || g.scheme == CK_SORTED)
-    hipLaunchKernelGGL((k_plan_search<B, H>), dim3(grid), dim3(64), lds, s, g, r);
+  if (g.scheme == CK_BFS)
+    hipLaunchKernelGGL((k_plan_search<B, H, kOrderFifo>), dim3(grid), dim3(64), lds, s, g, r);
+  else if (g.scheme == CK_SORTED)
+    hipLaunchKernelGGL((k_plan_search<B, H, kOrderCount>), dim3(grid), dim3(64), lds, s, g, r);
+  else if (g.scheme == CK_HYBRID)
+    hipLaunchKernelGGL((k_plan_search<B, H, kOrderDepthCount>), dim3(grid), dim3(64), lds, s, g,
+                       r);
   else
     hipLaunchKernelGGL((k_plan_walk<B, H>), dim3(grid), dim3(64), lds, s, g, r);
 }
@@ -1702,8 +1753,15 @@ static void fresh_go(const Geo& g, const Round& r, hipStream_t s) {
 template <int B, int H>
 static void evict_occupancy(const Geo& g, int* per_cu) {
   const size_t lds = evict_lds_bytes(g);
-  if (g.scheme == CK_BFS || g.scheme == CK_SORTED)
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_plan_search<B, H>, 64, lds);
+  if (g.scheme == CK_BFS)
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_plan_search<B, H, kOrderFifo>, 64,
+                                                       lds);
+  else if (g.scheme == CK_SORTED)
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_plan_search<B, H, kOrderCount>, 64,
+                                                       lds);
+  else if (g.scheme == CK_HYBRID)
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        per_cu, k_plan_search<B, H, kOrderDepthCount>, 64, lds);
   else
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_plan_walk<B, H>, 64, lds);
 }

@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libck.so")
 
-SCHEMES = {"random_walk": 0, "bfs": 1, "sorted": 2, "queue": 3, "rattle": 4}
+SCHEMES = {"random_walk": 0, "bfs": 1, "sorted": 2, "queue": 3, "rattle": 4, "hybrid": 5}
 OP_NOT_FOUND, OP_OK, OP_FAIL_CHAIN, OP_ABORTED, OP_BAD_KEY = range(5)
 BANDS = 200
 EMPTY_KEY = 0xFFFFFFFFFFFFFFFF

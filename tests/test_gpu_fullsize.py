@@ -77,7 +77,7 @@ def test_random_walk_2e16x4_full_parity():
     assert np.array_equal(fg.astype(bool), present)
 
 
-@pytest.mark.parametrize("scheme", ["bfs", "sorted", "queue"])
+@pytest.mark.parametrize("scheme", ["bfs", "sorted", "hybrid", "queue"])
 def test_2e24x8_fill_properties(scheme):
     """2^24 bins x 8 slots (2 GiB), sub-batches of 2^20, one call to 95% as the
     benchmark makes it, then on to 98%, then 2^20 deletes."""

@@ -31,7 +31,8 @@ def dev(a, dtype):
 
 @pytest.mark.parametrize("scheme,B,d,ghost", [("queue", 4, 2, True), ("sorted", 4, 2, False),
                                               ("random_walk", 8, 2, False),
-                                              ("bfs", 2, 2, True), ("rattle", 1, 3, False)])
+                                              ("bfs", 2, 2, True), ("rattle", 1, 3, False),
+                                              ("hybrid", 8, 2, False)])
 def test_group_matches_tables_alone(scheme, B, d, ghost):
     rng = np.random.default_rng(7)
     nt = 24

@@ -35,6 +35,9 @@ GEOMS = [
     ("rattle", 1, 2, False, False),
     ("rattle", 1, 3, False, False),
     ("rattle", 1, 4, False, False),
+    ("hybrid", 4, 2, False, False),
+    ("hybrid", 8, 2, True, False),
+    ("hybrid", 1, 3, False, False),
 ]
 
 
@@ -65,7 +68,7 @@ def test_fill_parity(geom, batch):
     assert f.all() and np.array_equal(v, vals[ok])
 
 
-MIXED = [GEOMS[i] for i in (0, 1, 4, 6, 9, 11, 13, 14, 17)]
+MIXED = [GEOMS[i] for i in (0, 1, 4, 6, 9, 11, 13, 14, 17, 20)]
 
 
 @pytest.mark.parametrize("geom", MIXED, ids=ident)
@@ -147,7 +150,7 @@ def test_edge_cases():
     del empty, CuckooTable
 
 
-@pytest.mark.parametrize("geom", [GEOMS[i] for i in (1, 4, 6, 10, 14, 17)], ids=ident)
+@pytest.mark.parametrize("geom", [GEOMS[i] for i in (1, 4, 6, 10, 14, 17, 19)], ids=ident)
 @pytest.mark.parametrize("depth", [1, 3])
 def test_enqueue_depth_parity(geom, depth):
     """How many rounds the host enqueues per sub-batch before it looks at the
