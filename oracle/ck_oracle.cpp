@@ -496,6 +496,38 @@ Plan plan_delete(const Table& T, uint64_t key, uint32_t* probes) {
   return pl;
 }
 
+// Overwrite (Sec. 1): a stored key gets a new value in place, in every slot
+// holding it (both copies of a ghost duplicate).  The key, its duplicate mark,
+// its rattle counter and the bin's counters stay as they are.  An absent key
+// is not found and changes nothing.
+Plan plan_overwrite(const Table& T, uint64_t key, uint64_t val, uint32_t* probes) {
+  Plan pl(T, 0);
+  uint64_t h[4];
+  T.hash(key, h);
+  pl.status = ST_NOT_FOUND;
+  *probes = 0;
+  const uint64_t v = T.p.B == 1 ? (val & 0xFFFFFFFFull) : val;  // single-slot bins: 32-bit values
+  for (int i = 0; i < T.p.H; ++i) {
+    BinState s = pl.read(h[i]);
+    ++*probes;
+    for (int j = 0; j < T.p.B; ++j) {
+      if (s.s[j].key != key) continue;
+      bool was_dup = (s.dup >> j) & 1;
+      pl.write(h[i]).s[j].val = v;
+      if (was_dup) {
+        uint64_t tb = h[1 - i];
+        BinState t = pl.read(tb);
+        ++*probes;
+        for (int k = 0; k < T.p.B; ++k)
+          if (t.s[k].key == key) pl.write(tb).s[k].val = v;
+      }
+      pl.status = ST_OK;
+      return pl;
+    }
+  }
+  return pl;
+}
+
 // ---- Deterministic phased rounds ------------------------------------------------
 // Every pending op plans against the same snapshot; each plan claims the bins
 // it writes, lowest op index winning a bin; a plan that owns all its bins is
@@ -708,6 +740,32 @@ void ck_oracle_delete(void* tp, const uint64_t* keys, uint64_t n, uint8_t* found
       T.st.delete_retries += res[i].retries;
       T.st.delete_probes += probes[i];
       if (res[i].status == ST_OK) { ++T.st.deletes_found; --T.st.stored; }
+    }
+  }
+}
+
+// Overwrite n keys' values (a key absent is reported, nothing changes).
+// Per-op outputs: status (found or not) and rounds lost to claims.  The
+// table's counters are not changed.
+void ck_oracle_overwrite(void* tp, const uint64_t* keys, const uint64_t* vals, uint64_t n,
+                         uint8_t* found, uint32_t* retries) {
+  Table& T = *(Table*)tp;
+  for (uint64_t b0 = 0; b0 < n; b0 += T.p.batch_ops) {
+    uint64_t m = std::min<uint64_t>(T.p.batch_ops, n - b0);
+    std::vector<uint64_t> ids;
+    std::vector<OpResult> res(m);
+    std::vector<uint32_t> probes(m, 0);
+    for (uint64_t i = 0; i < m; ++i) {
+      if (keys[b0 + i] == kEmpty) res[i].status = ST_BAD_KEY;
+      else ids.push_back(i);
+    }
+    auto fn = [&](uint64_t i) {
+      return plan_overwrite(T, keys[b0 + i], vals[b0 + i], &probes[i]);
+    };
+    run_rounds(T, ids, fn, res);
+    for (uint64_t i = 0; i < m; ++i) {
+      found[b0 + i] = (uint8_t)res[i].status;
+      retries[b0 + i] = res[i].retries;
     }
   }
 }

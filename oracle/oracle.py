@@ -61,6 +61,7 @@ def lib():
         L.ck_oracle_insert_ids.argtypes = [vp, vp, vp, vp, u64, vp, vp, vp, vp]
         L.ck_oracle_lookup.argtypes = [vp, vp, u64, vp, vp]
         L.ck_oracle_delete.argtypes = [vp, vp, u64, vp, vp]
+        L.ck_oracle_overwrite.argtypes = [vp, vp, vp, u64, vp, vp]
         L.ck_oracle_export.argtypes = [vp, vp, vp, vp, vp]
         L.ck_oracle_import.argtypes = [vp, vp, vp, vp, vp]
         L.ck_oracle_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
@@ -130,6 +131,15 @@ class OracleTable:
         found = np.zeros(keys.size, np.uint8)
         retries = np.zeros(keys.size, np.uint32)
         lib().ck_oracle_delete(self._t, _p(keys), keys.size, _p(found), _p(retries))
+        return found, retries
+
+    def overwrite(self, keys, vals):
+        """New values for stored keys; returns (status per op, rounds lost)."""
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        vals = np.ascontiguousarray(vals, dtype=np.uint64)
+        found = np.zeros(keys.size, np.uint8)
+        retries = np.zeros(keys.size, np.uint32)
+        lib().ck_oracle_overwrite(self._t, _p(keys), _p(vals), keys.size, _p(found), _p(retries))
         return found, retries
 
     def export(self):

@@ -139,16 +139,18 @@ def test_failed_insert_leaves_table_unchanged():
                                               ("random_walk", True, 2, 1)])
 @pytest.mark.parametrize("batch", [1, 16])
 def test_dictionary_semantics(scheme, ghost, d, B, batch):
-    # P3: lookups and deletes answer exactly like a textbook dictionary fed
-    # the same operation stream (Sec. 1: constant-time reads and deletes).
+    # P3: lookups, deletes and overwrites answer exactly like a textbook
+    # dictionary fed the same operation stream (Sec. 1: constant-time reads,
+    # overwrites and deletes).
     t = make(1 << 8, B, d, scheme, ghost=ghost, batch_ops=batch, max_chain=1000)
     rng = np.random.default_rng(11)
     keys, vals = inputs.keys_values(21, 4000, value_bits=32 if B == 1 else 64)
     model: dict[int, int] = {}
     nxt = 0
     cap = int(0.85 * t.n * B)
-    for step in range(60):
-        kind = rng.integers(0, 3)
+    mask = 0xFFFFFFFF if B == 1 else 0xFFFFFFFFFFFFFFFF
+    for step in range(80):
+        kind = rng.integers(0, 4)
         if kind == 0 and len(model) < cap:
             m = int(rng.integers(1, 40))
             ks, vs = keys[nxt:nxt + m], vals[nxt:nxt + m]
@@ -170,6 +172,19 @@ def test_dictionary_semantics(scheme, ghost, d, B, batch):
                 seen.add(x)
             for x in pick:
                 model.pop(x, None)
+        elif kind == 3 and model:
+            # new values for stored keys (repeats included: the later op in the
+            # batch wins) and for absent keys (not found, nothing changes)
+            present = list(model)
+            m = int(rng.integers(1, 20))
+            pick = [present[i] for i in rng.integers(0, len(present), m)]
+            pick += keys[3000 + step * 5: 3000 + step * 5 + 3].tolist()
+            nv = rng.integers(0, 1 << 63, len(pick), dtype=np.uint64)
+            f, _ = t.overwrite(np.array(pick, np.uint64), nv)
+            for x, y, s2 in zip(pick, nv.tolist(), f.tolist()):
+                assert s2 == (oracle.ST_OK if x in model else oracle.ST_NOT_FOUND)
+                if x in model:
+                    model[x] = y & mask
         else:
             q = np.concatenate([np.array(list(model)[:50], np.uint64), keys[3500:3520]])
             got, found = t.lookup(q)
