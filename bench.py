@@ -8,7 +8,8 @@ already resident in HBM:
      rounds: fresh placement, kick-out planning, claims, reverse-order commit,
      metadata and spawn counts, per-band statistics);
   2. 2^26 lookups at a 90% hit rate on the last table;
-  3. 2^20 deletes of stored keys on that table.
+  3. 2^20 overwrites of stored keys, then 2^20 deletes of the same keys, on
+     that table.
 `value` is inserts per second over the three fills.  Lookup and delete rates,
 bins viewed per insert around 95% load, the roofline of the dominant kernel
 and the CPU oracle's rate on a bounded sample are reported beside it.
@@ -518,6 +519,8 @@ def main():
     rng = np.random.default_rng(402)
     dels = keys[rng.choice(m, 1 << args.deletes_log2, replace=False)]
     ddel = as_device_keys(dels)
+    # the same stored keys get new values first (overwrites), then go
+    dnew = torch.from_numpy(rng.integers(0, 1 << 63, dels.size, dtype=np.int64)).cuda()
     del q
     print(f"# inputs ready in {time.time() - t0:.1f}s: {m} inserts, {nq} lookups, "
           f"{dels.size} deletes", file=sys.stderr, flush=True)
@@ -547,15 +550,19 @@ def main():
             if timed:
                 res["timing"][s] = t.timing()
         t = tables[schemes[-1]]
-        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0, e1, e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
         e0.record(stream)
         t.lookup(dq, out=vout, found=fout, lanes_per_probe=args.lpp)
         e1.record(stream)
-        t.delete(ddel)
+        fw = t.overwrite(ddel, dnew)
         e2.record(stream)
-        e2.synchronize()
+        t.delete(ddel)
+        e3.record(stream)
+        e3.synchronize()
         res["lookup_s"] = e0.elapsed_time(e1) / 1e3
-        res["delete_s"] = e1.elapsed_time(e2) / 1e3
+        res["overwrite_s"] = e1.elapsed_time(e2) / 1e3
+        res["delete_s"] = e2.elapsed_time(e3) / 1e3
+        res["overwrites_found"] = bool((fw == 1).all())
         if timed:
             res["lookup_timing"] = t.timing()["lookup"]
         return res
@@ -581,7 +588,8 @@ def main():
     for k in range(args.steps):
         results.append(step(k == args.steps - 1, [dominant]))
         print(f"# step {k}: fills {results[-1]['fill_s']} lookup {results[-1]['lookup_s']:.4f}s "
-              f"delete {results[-1]['delete_s']:.4f}s", file=sys.stderr, flush=True)
+              f"overwrite {results[-1]['overwrite_s']:.4f}s delete {results[-1]['delete_s']:.4f}s",
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
 
@@ -592,6 +600,8 @@ def main():
     fill = {s: float(np.mean([r["fill_s"][s] for r in results])) for s in schemes}
     lookup_s = float(np.mean([r["lookup_s"] for r in results]))
     delete_s = float(np.mean([r["delete_s"] for r in results]))
+    overwrite_s = float(np.mean([r["overwrite_s"] for r in results]))
+    assert all(r["overwrites_found"] for r in results), "an overwrite missed a stored key"
     ins_rate = len(schemes) * m / sum(fill.values())
     st = results[-1]["stats"]
     band = int(round(args.load * 200)) - 1  # the [load - 0.5%, load) band
@@ -662,7 +672,8 @@ def main():
                                f"{n * B * 16 / 2**30:.0f} GiB), 2 hash functions, "
                                f"fill to {args.load} in sub-batches of 2^{args.batch_log2} "
                                f"with {','.join(schemes)}; 2^{args.lookups_log2} lookups at "
-                               f"{args.hit_rate} hits; 2^{args.deletes_log2} deletes",
+                               f"{args.hit_rate} hits; 2^{args.deletes_log2} overwrites, "
+                               f"then deletes, of stored keys",
                    "bins": n, "slots_per_bin": B, "inserts_per_fill": m,
                    "lookups": nq, "deletes": int(dels.size), "max_search": args.max_search},
         "inserts_per_s_by_scheme": {s: m / fill[s] for s in schemes},
@@ -673,6 +684,7 @@ def main():
         "lost_rounds_per_insert": retries,
         "lookups_per_s": nq / lookup_s,
         "deletes_per_s": dels.size / delete_s,
+        "overwrites_per_s": dels.size / overwrite_s,
         "lookup_probes_per_query": probes_per_q,
         "roofline": roofline,
         "lookup_roofline": lookup_roof,

@@ -25,9 +25,9 @@
  *   - `d_` pointers are device pointers (HIP global memory) owned by the
  *     caller; `h_` pointers are host pointers owned by the caller;
  *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
- *     it; ck_insert and ck_delete synchronise it once per round to read the
- *     number of ops still pending, so they return with all their rounds
- *     enqueued and the last round complete;
+ *     it; ck_insert, ck_delete and ck_overwrite wait once per sub-batch for
+ *     its round counters (one sub-batch ahead), so they return with every
+ *     round complete;
  *   - calls on one table must not overlap; tables are independent.
  */
 #ifndef CK_H
@@ -172,6 +172,15 @@ ck_status ck_lookup_lpp(ck_table* t, const uint64_t* d_keys, uint64_t n, void* d
 ck_status ck_delete(ck_table* t, const uint64_t* d_keys, uint64_t n, uint8_t* d_found,
                     void* stream);
 
+/* Overwrite (Sec. 1: constant-time overwrites): a stored key gets the new
+   value (8 bytes, or 4 for single-slot bins) in every slot holding it; its
+   key, ghost mark and rattle counter stay.  An absent key is not inserted.
+   d_found gets CK_OP_OK / CK_OP_NOT_FOUND / CK_OP_ABORTED / CK_OP_BAD_KEY.  A
+   key given twice in a call keeps the later op's value.  No counter of
+   ck_stats changes. */
+ck_status ck_overwrite(ck_table* t, const uint64_t* d_keys, const void* d_vals, uint64_t n,
+                       uint8_t* d_found, void* stream);
+
 /* Copy the counters to host memory (synchronises `stream`). */
 ck_status ck_stats_get(ck_table* t, ck_stats* h_out, void* stream);
 ck_status ck_stats_reset(ck_table* t, void* stream);
@@ -249,6 +258,8 @@ ck_status ck_group_lookup(ck_group* g, const uint32_t* d_table, const uint64_t* 
                           uint32_t lanes_per_probe, void* stream);
 ck_status ck_group_delete(ck_group* g, const uint32_t* d_table, const uint64_t* d_keys,
                           uint64_t n, uint8_t* d_found, void* stream);
+ck_status ck_group_overwrite(ck_group* g, const uint32_t* d_table, const uint64_t* d_keys,
+                             const void* d_vals, uint64_t n, uint8_t* d_found, void* stream);
 /* Canonical image of one table of the group (as ck_export). */
 ck_status ck_group_export_table(ck_group* g, uint32_t table, uint64_t* h_keys, uint64_t* h_vals,
                                 uint16_t* h_rattle, uint32_t* h_meta, void* stream);

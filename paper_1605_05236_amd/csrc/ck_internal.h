@@ -29,6 +29,8 @@ enum : uint8_t {
   MV_HC = 4,          // the write is an insertion counted by the hit counter
   MV_DUPCLR = 8,      // no slot write: clear the duplicate mark only (ghost twin)
   MV_CLEAR = 16,      // delete: the slot becomes empty
+  MV_VALUE = 32,      // overwrite: only the value changes (key, mark and, in a
+                      // single-slot bin, the rattle counter stay)
 };
 
 struct Move {            // 24 bytes
@@ -178,7 +180,8 @@ struct Round {
   uint32_t* op_retries;
   uint32_t* op_twins;
   uint32_t max_rounds;
-  uint32_t is_delete;
+  uint32_t is_delete;         // the delete planner: deletes, and overwrites when
+  uint32_t overwrite;         // this is set (new values in place)
   uint32_t first;            // first round of the sub-batch: pend[p] = p, counters unset
   unsigned long long* wg_views;  // per eviction workgroup: bins viewed (cumulative)
   void* wg_scratch;          // per-workgroup scratch of the eviction planners

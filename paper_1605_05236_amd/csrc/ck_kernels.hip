@@ -1830,12 +1830,13 @@ __device__ __forceinline__ void delete_one(const Geo& g, const Round& r, const G
     }
   }
   if (!leader) return;
+  const uint32_t fl = r.overwrite ? MV_VALUE : MV_CLEAR;
   ((uint4*)r.hdr)[2 * (size_t)i] =
       make_uint4(hdr_pack(x == kEmpty ? PL_FAIL : status, 0, nm), probes, nm > 0 ? mb[0] : 0u,
-                 nm > 0 ? (ms[0] | ((uint32_t)MV_CLEAR << 8)) : 0u);
+                 nm > 0 ? (ms[0] | (fl << 8)) : 0u);
   if (nm > 0) claim(g, r, mb[0], i);
   if (nm > 1) {
-    r.imv[(size_t)i * kExtraInline] = IMove{mb[1], ms[1] | ((uint32_t)MV_CLEAR << 8)};
+    r.imv[(size_t)i * kExtraInline] = IMove{mb[1], ms[1] | (fl << 8)};
     claim(g, r, mb[1], i);
   }
 }
@@ -2000,7 +2001,11 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
             atomicAnd(mw, ~(1u << slot));
             continue;
           }
-          if (!(fl & MV_SUPERSEDED)) {
+          if (fl & MV_VALUE) {  // overwrite: the value word only
+            unsigned long long* vw = &g.slots[(uint64_t)bin * g.B + slot].y;
+            if (g.B == 1) *(uint32_t*)vw = (uint32_t)a;  // the rattle counter above stays
+            else *vw = a;
+          } else if (!(fl & MV_SUPERSEDED)) {
             g.slots[(uint64_t)bin * g.B + slot] =
                 (fl & MV_CLEAR) ? make_ulonglong2(kEmpty, 0ull) : make_ulonglong2(k, a);
             if (g.ghost) {
@@ -2290,8 +2295,10 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_delete(const uint8_t* stat
                                                              const uint32_t* retries, uint64_t m,
                                                              DevStats* st, const uint32_t* open,
                                                              const uint32_t* gate,
-                                                             uint32_t* unfinished) {
+                                                             uint32_t* unfinished,
+                                                             uint32_t count) {
   if (stats_closed_out(open, gate, unfinished, true)) return;
+  if (!count) return;  // overwrites: no counters, only the completion flag
   unsigned long long d = 0, f = 0, p = 0, rt = 0;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
        i += (uint64_t)gridDim.x * blockDim.x) {
@@ -2322,7 +2329,7 @@ hipError_t launch_batch_stats(const Round& r, uint64_t m, uint64_t slots, uint32
   if (is_delete) {
     hipLaunchKernelGGL(k_stats_delete, dim3(std::min<uint32_t>(nb, 256)), dim3(kStatBlock), 0, s,
                        r.status, r.op_views, r.op_retries, m, r.stats, open, r.gate,
-                       &r.ctr->unfinished);
+                       &r.ctr->unfinished, r.overwrite ? 0u : 1u);
     return hipGetLastError();
   }
   uint64_t* stored_before = (uint64_t*)(block_tmp + ((nb + 63) & ~63u));

@@ -69,10 +69,12 @@ class CkError(RuntimeError):
 _lib = None
 
 EXPORTED = ["ck_default_options", "ck_storage_bytes", "ck_create", "ck_clear", "ck_insert", "ck_insert_ex",
-            "ck_lookup", "ck_lookup_lpp", "ck_delete", "ck_stats_get", "ck_stats_reset",
+            "ck_lookup", "ck_lookup_lpp", "ck_delete", "ck_overwrite", "ck_stats_get",
+            "ck_stats_reset",
             "ck_export", "ck_import", "ck_hash", "ck_insert_count", "ck_destroy", "ck_strerror",
             "ck_timing_enable", "ck_timing_get", "ck_group_storage_bytes", "ck_group_create",
-            "ck_group_insert", "ck_group_lookup", "ck_group_delete", "ck_group_export_table",
+            "ck_group_insert", "ck_group_lookup", "ck_group_delete", "ck_group_overwrite",
+            "ck_group_export_table",
             "ck_group_stats_get", "ck_group_timing_enable", "ck_group_timing_get",
             "ck_group_clear", "ck_group_insert_count", "ck_group_destroy"]
 
@@ -98,6 +100,7 @@ def load_library(path: str = LIB_PATH):
     L.ck_lookup.argtypes = [vp, vp, u64, vp, vp, vp]
     L.ck_lookup_lpp.argtypes = [vp, vp, u64, vp, vp, u32, vp]
     L.ck_delete.argtypes = [vp, vp, u64, vp, vp]
+    L.ck_overwrite.argtypes = [vp, vp, vp, u64, vp, vp]
     L.ck_stats_get.argtypes = [vp, ctypes.POINTER(CkStats), vp]
     L.ck_stats_reset.argtypes = [vp, vp]
     L.ck_export.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -114,6 +117,7 @@ def load_library(path: str = LIB_PATH):
     L.ck_group_insert.argtypes = [vp, vp, vp, vp, u64, vp, vp, vp, vp, vp]
     L.ck_group_lookup.argtypes = [vp, vp, vp, u64, vp, vp, u32, vp]
     L.ck_group_delete.argtypes = [vp, vp, vp, u64, vp, vp]
+    L.ck_group_overwrite.argtypes = [vp, vp, vp, vp, u64, vp, vp]
     L.ck_group_export_table.argtypes = [vp, u32, vp, vp, vp, vp, vp]
     L.ck_group_stats_get.argtypes = [vp, ctypes.POINTER(CkStats), vp]
     L.ck_group_timing_enable.argtypes = [vp, u32]
@@ -125,10 +129,12 @@ def load_library(path: str = LIB_PATH):
     L.ck_strerror.argtypes = [i32]
     L.ck_strerror.restype = ctypes.c_char_p
     for f in ("ck_storage_bytes", "ck_create", "ck_clear", "ck_insert", "ck_insert_ex", "ck_lookup",
-              "ck_lookup_lpp", "ck_delete", "ck_stats_get", "ck_stats_reset", "ck_export",
+              "ck_lookup_lpp", "ck_delete", "ck_overwrite", "ck_stats_get", "ck_stats_reset",
+              "ck_export",
               "ck_import", "ck_hash", "ck_destroy", "ck_timing_enable", "ck_timing_get",
               "ck_group_storage_bytes", "ck_group_create", "ck_group_insert", "ck_group_lookup",
-              "ck_group_delete", "ck_group_export_table", "ck_group_stats_get",
+              "ck_group_delete", "ck_group_overwrite", "ck_group_export_table",
+              "ck_group_stats_get",
               "ck_group_timing_enable", "ck_group_timing_get", "ck_group_clear",
               "ck_group_destroy"):
         getattr(L, f).restype = i32
@@ -242,6 +248,14 @@ class CuckooTable:
         found = torch.empty(keys.numel(), dtype=torch.uint8, device=self.device)
         _check(self._L.ck_delete(self._h, _ptr(keys), keys.numel(), _ptr(found),
                                  _stream(stream)))
+        return found
+
+    def overwrite(self, keys, vals, stream=None):
+        """New values for stored keys (absent keys are reported, not inserted)."""
+        import torch
+        found = torch.empty(keys.numel(), dtype=torch.uint8, device=self.device)
+        _check(self._L.ck_overwrite(self._h, _ptr(keys), _ptr(vals), keys.numel(), _ptr(found),
+                                    _stream(stream)))
         return found
 
     # ---- host-side views
@@ -390,6 +404,13 @@ class CuckooGroup:
         found = torch.empty(keys.numel(), dtype=torch.uint8, device=self.device)
         _check(self._L.ck_group_delete(self._h, _ptr(tables), _ptr(keys), keys.numel(),
                                        _ptr(found), _stream(stream)))
+        return found
+
+    def overwrite(self, tables, keys, vals, stream=None):
+        import torch
+        found = torch.empty(keys.numel(), dtype=torch.uint8, device=self.device)
+        _check(self._L.ck_group_overwrite(self._h, _ptr(tables), _ptr(keys), _ptr(vals),
+                                          keys.numel(), _ptr(found), _stream(stream)))
         return found
 
     def export_table(self, table, stream=None) -> dict:

@@ -49,6 +49,10 @@ def gpu_delete(t, keys):
     return t.delete(to_dev(keys)).cpu().numpy()
 
 
+def gpu_overwrite(t, keys, vals):
+    return t.overwrite(to_dev(keys), dev_values(vals, t.B)).cpu().numpy()
+
+
 def assert_same_image(a, b, what=""):
     for f in ("keys", "vals", "rattle", "meta"):
         if not np.array_equal(a[f], b[f]):

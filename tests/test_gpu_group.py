@@ -76,7 +76,7 @@ def test_group_matches_tables_alone(scheme, B, d, ghost):
     for t in range(nt):
         img = g.export_table(t)
         assert_same_image(img, orc[t].export(), f"{scheme} table {t}")
-    # lookups and deletes through the group
+    # lookups, overwrites and deletes through the group
     q = np.concatenate([keys[::3], inputs.keys_values(32, 500)[0]])
     qt = np.concatenate([tids[::3], rng.integers(0, nt, 500).astype(np.uint32)])
     v, f = g.lookup(dev(qt, "u32"), dev(q, "u64"))
@@ -87,6 +87,19 @@ def test_group_matches_tables_alone(scheme, B, d, ghost):
         pos = np.nonzero(qt == t)[0]
         vo, fo = orc[t].lookup(q[pos])
         assert np.array_equal(f[pos], fo) and np.array_equal(v[pos], vo)
+    # new values through the group (stored keys and a few absent ones)
+    ok_, ot = np.concatenate([keys[1::4], q[-50:]]), np.concatenate([tids[1::4], qt[-50:]])
+    nv = rng.integers(0, 1 << 63, ok_.size, dtype=np.uint64)
+    if B == 1:
+        nv &= np.uint64(0xFFFFFFFF)
+    fw = g.overwrite(dev(ot, "u32"), dev(ok_, "u64"), dev(nv, "u32" if B == 1 else "u64"))
+    fw = fw.cpu().numpy()
+    for c0 in range(0, ok_.size, chunk):
+        c1 = min(ok_.size, c0 + chunk)
+        for t in range(nt):
+            pos = np.nonzero(ot[c0:c1] == t)[0] + c0
+            if pos.size:
+                assert np.array_equal(fw[pos], orc[t].overwrite(ok_[pos], nv[pos])[0])
     dk, dt = keys[::5], tids[::5]
     fd = g.delete(dev(dt, "u32"), dev(dk, "u64")).cpu().numpy()
     for c0 in range(0, dk.size, chunk):

@@ -9,7 +9,7 @@ import pytest
 
 import checks
 from gpu_util import (assert_same_image, assert_same_ops, assert_same_stats, gpu_delete,
-                      gpu_insert, gpu_lookup, gpu_table, keys_for, oracle_table)
+                      gpu_insert, gpu_lookup, gpu_overwrite, gpu_table, keys_for, oracle_table)
 from paper_1605_05236_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -73,7 +73,8 @@ MIXED = [GEOMS[i] for i in (0, 1, 4, 6, 9, 11, 13, 14, 17, 20)]
 
 @pytest.mark.parametrize("geom", MIXED, ids=ident)
 def test_mixed_stream_parity(geom):
-    # lookups, deletes (present, absent, repeated) and inserts interleaved
+    # lookups, deletes and overwrites (present, absent, repeated) and inserts
+    # interleaved
     scheme, B, d, ghost, lb = geom
     n = 1 << 11 if B > 1 else 1 << 12
     kw = dict(ghost=ghost, load_balance=lb, max_chain=1000, batch_ops=300)
@@ -97,6 +98,15 @@ def test_mixed_stream_parity(geom):
             assert np.array_equal(fg, fo), f"{geom} step {step} delete"
             gone = set(pick[fo == 1].tolist())
             live = [k for k in live if k not in gone]
+        if live:
+            # new values for stored keys (some twice) and for absent ones
+            pick = np.array(live, np.uint64)[rng.integers(0, len(live), 40)]
+            pick = np.concatenate([pick, pick[:4], keys[-10:]])
+            nv = rng.integers(0, 1 << 63, pick.size, dtype=np.uint64)
+            if B == 1:
+                nv &= np.uint64(0xFFFFFFFF)
+            fg, fo = gpu_overwrite(g, pick, nv), o.overwrite(pick, nv)[0]
+            assert np.array_equal(fg, fo), f"{geom} step {step} overwrite"
         q = np.concatenate([np.array(live[:200], np.uint64), keys[-40:]])
         vg, fg = gpu_lookup(g, q)
         vo, fo = o.lookup(q)
