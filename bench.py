@@ -39,8 +39,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 # shapes, host loop); once that source changes the benchmark reports null
 # until the counters are taken again.
 MEASURED_EVICT_TRAFFIC = {
-    "sources_sha256": "4fba00321257fa5092efee1953f128a54524adaf406295277d79a741956a196e",
-    "bytes_per_launch": 36350179,
+    "sources_sha256": "ec621a9f3b5027c1a26b4d3547bcca79ef6ee269aeafe706b721779eceb496fe",
+    "bytes_per_launch": 36324754,
     "profile": "profiles/evict_planners__fill95_2e24x8.md",
 }
 _SOURCES = ("ck_kernels.hip", "ck_api.hip", "ck_internal.h")
