@@ -48,7 +48,8 @@ constexpr uint64_t kEmpty = ~0ull;  // reserved key marking an empty slot
 constexpr int kBands = 200;         // 0.5 % density bands
 
 enum Scheme { RANDOM_WALK = 0, BFS = 1, SORTED = 2, QUEUE = 3, RATTLE = 4, HYBRID = 5 };
-enum OpStatus { ST_NOT_FOUND = 0, ST_OK = 1, ST_FAIL = 2, ST_ABORTED = 3, ST_BAD_KEY = 4 };
+enum OpStatus { ST_NOT_FOUND = 0, ST_OK = 1, ST_FAIL = 2, ST_ABORTED = 3, ST_BAD_KEY = 4,
+                ST_UPDATED = 5 };
 
 // ---------------------------------------------------------------------------
 // splitmix64 (Steele, Lea, Flood 2014): state advances by the golden-ratio
@@ -147,6 +148,7 @@ struct Plan {
   uint64_t op;  // global insert index, keys the random choices
   uint32_t draws = 0;
   std::map<uint64_t, BinState> draft;
+  std::set<uint64_t> claims;  // bins claimed without being written (upsert key claims)
   std::vector<uint64_t> spawns;
   uint32_t views = 0, kicks = 0, twins = 0;
   int status = ST_FAIL;
@@ -528,6 +530,33 @@ Plan plan_overwrite(const Table& T, uint64_t key, uint64_t val, uint32_t* probes
   return pl;
 }
 
+// Upsert: a stored key gets the new value in place, as an overwrite (status
+// UPDATED); an absent key is inserted with the table's scheme.  The presence
+// check views the key's bins in hash order until the key turns up (all d of
+// them when it is absent; reading a ghost twin is bookkeeping), and an
+// absent key's plan adds its own views.  An absent key's plan also claims
+// the key's first bin without writing it, so two upserts of one new key in a
+// round conflict: the later one, next round, finds the key and overwrites it.
+Plan plan_upsert(const Table& T, uint64_t op, uint64_t key, uint64_t val) {
+  uint64_t h[4];
+  T.hash(key, h);
+  for (int i = 0; i < T.p.H; ++i) {
+    const BinState& s = T.bins[h[i]];
+    for (int j = 0; j < T.p.B; ++j)
+      if (s.s[j].key == key) {
+        uint32_t probes = 0;
+        Plan pl = plan_overwrite(T, key, val, &probes);
+        pl.status = ST_UPDATED;
+        pl.views = (uint32_t)(i + 1);
+        return pl;
+      }
+  }
+  Plan pl = plan_insert(T, op, key, val);
+  pl.views += (uint32_t)T.p.H;
+  pl.claims.insert(h[0]);
+  return pl;
+}
+
 // ---- Deterministic phased rounds ------------------------------------------------
 // Every pending op plans against the same snapshot; each plan claims the bins
 // it writes, lowest op index winning a bin; a plan that owns all its bins is
@@ -549,19 +578,25 @@ uint32_t run_rounds(Table& T, const std::vector<uint64_t>& ids, PlanFn plan_fn,
     std::vector<Plan> plans;
     plans.reserve(pending.size());
     for (uint64_t i : pending) plans.push_back(plan_fn(i));
-    // Claims: the lowest op index that writes a bin owns it this round.
+    // Claims: the lowest op index that writes (or claims) a bin owns it this
+    // round.
     std::map<uint64_t, uint64_t> owner;
-    for (size_t k = 0; k < plans.size(); ++k)
-      for (auto& kv : plans[k].draft) {
-        auto it = owner.find(kv.first);
-        if (it == owner.end() || pending[k] < it->second) owner[kv.first] = pending[k];
-      }
+    auto take = [&](uint64_t b, uint64_t i) {
+      auto it = owner.find(b);
+      if (it == owner.end() || i < it->second) owner[b] = i;
+    };
+    for (size_t k = 0; k < plans.size(); ++k) {
+      for (auto& kv : plans[k].draft) take(kv.first, pending[k]);
+      for (uint64_t b : plans[k].claims) take(b, pending[k]);
+    }
     std::vector<uint64_t> next;
     for (size_t k = 0; k < plans.size(); ++k) {
       uint64_t i = pending[k];
       bool wins = true;
       for (auto& kv : plans[k].draft)
         if (owner[kv.first] != i) wins = false;
+      for (uint64_t b : plans[k].claims)
+        if (owner[b] != i) wins = false;
       res[i].views_all += plans[k].views;
       if (wins) {
         for (auto& kv : plans[k].draft) {
@@ -634,9 +669,9 @@ void ck_oracle_hash(void* t, uint64_t key, uint64_t* out) { ((Table*)t)->hash(ke
 // viewed by the plan that decided the op, kicks, and rounds lost to claims.
 // `op_ids` (may be null) gives each op's index for the walk's random choices;
 // by default it is the table's running insert count.
-void ck_oracle_insert_ids(void* tp, const uint64_t* keys, const uint64_t* vals,
-                          const uint64_t* op_ids, uint64_t n, uint8_t* status, uint32_t* views,
-                          uint32_t* kicks, uint32_t* retries) {
+static void insert_batch(void* tp, const uint64_t* keys, const uint64_t* vals,
+                         const uint64_t* op_ids, uint64_t n, uint8_t* status, uint32_t* views,
+                         uint32_t* kicks, uint32_t* retries, bool upsert) {
   Table& T = *(Table*)tp;
   const uint64_t slots = T.p.n * (uint64_t)T.p.B;
   for (uint64_t b0 = 0; b0 < n; b0 += T.p.batch_ops) {
@@ -650,7 +685,8 @@ void ck_oracle_insert_ids(void* tp, const uint64_t* keys, const uint64_t* vals,
     }
     auto fn = [&](uint64_t i) {
       const uint64_t op = op_ids ? op_ids[b0 + i] : base + i;
-      return plan_insert(T, op, keys[b0 + i], vals[b0 + i]);
+      return upsert ? plan_upsert(T, op, keys[b0 + i], vals[b0 + i])
+                    : plan_insert(T, op, keys[b0 + i], vals[b0 + i]);
     };
     T.st.rounds += run_rounds(T, ids, fn, res);
     // Per-op results and density bands: an op's density is that of the table
@@ -663,6 +699,7 @@ void ck_oracle_insert_ids(void* tp, const uint64_t* keys, const uint64_t* vals,
       kicks[b0 + i] = r.status == ST_OK ? r.kicks : 0;
       retries[b0 + i] = r.retries;
       if (r.status == ST_BAD_KEY) { ++T.st.inserts_bad_key; continue; }
+      if (r.status == ST_UPDATED) continue;  // an upsert that overwrote: not an insert
       T.st.retries += r.retries;
       T.st.views_all += r.views_all;
       if (r.status == ST_ABORTED) { ++T.st.inserts_aborted; continue; }
@@ -688,9 +725,22 @@ void ck_oracle_insert_ids(void* tp, const uint64_t* keys, const uint64_t* vals,
   T.insert_count += n;
 }
 
+void ck_oracle_insert_ids(void* tp, const uint64_t* keys, const uint64_t* vals,
+                          const uint64_t* op_ids, uint64_t n, uint8_t* status, uint32_t* views,
+                          uint32_t* kicks, uint32_t* retries) {
+  insert_batch(tp, keys, vals, op_ids, n, status, views, kicks, retries, false);
+}
+
 void ck_oracle_insert(void* tp, const uint64_t* keys, const uint64_t* vals, uint64_t n,
                       uint8_t* status, uint32_t* views, uint32_t* kicks, uint32_t* retries) {
-  ck_oracle_insert_ids(tp, keys, vals, nullptr, n, status, views, kicks, retries);
+  insert_batch(tp, keys, vals, nullptr, n, status, views, kicks, retries, false);
+}
+
+// Upsert n keys: stored keys get new values (status UPDATED), the others are
+// inserted; per-op outputs as for inserts.
+void ck_oracle_upsert(void* tp, const uint64_t* keys, const uint64_t* vals, uint64_t n,
+                      uint8_t* status, uint32_t* views, uint32_t* kicks, uint32_t* retries) {
+  insert_batch(tp, keys, vals, nullptr, n, status, views, kicks, retries, true);
 }
 
 // Lookup (Sec. 1): the key is in one of its bins, probed in hash order.

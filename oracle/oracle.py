@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libck_oracle.so")
 RANDOM_WALK, BFS, SORTED, QUEUE, RATTLE, HYBRID = range(6)
 SCHEMES = {"random_walk": RANDOM_WALK, "bfs": BFS, "sorted": SORTED, "queue": QUEUE,
            "rattle": RATTLE, "hybrid": HYBRID}
-ST_NOT_FOUND, ST_OK, ST_FAIL, ST_ABORTED, ST_BAD_KEY = range(5)
+ST_NOT_FOUND, ST_OK, ST_FAIL, ST_ABORTED, ST_BAD_KEY, ST_UPDATED = range(6)
 EMPTY = np.uint64(0xFFFFFFFFFFFFFFFF)
 BANDS = 200
 
@@ -62,6 +62,7 @@ def lib():
         L.ck_oracle_lookup.argtypes = [vp, vp, u64, vp, vp]
         L.ck_oracle_delete.argtypes = [vp, vp, u64, vp, vp]
         L.ck_oracle_overwrite.argtypes = [vp, vp, vp, u64, vp, vp]
+        L.ck_oracle_upsert.argtypes = [vp, vp, vp, u64, vp, vp, vp, vp]
         L.ck_oracle_export.argtypes = [vp, vp, vp, vp, vp]
         L.ck_oracle_import.argtypes = [vp, vp, vp, vp, vp]
         L.ck_oracle_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
@@ -132,6 +133,19 @@ class OracleTable:
         retries = np.zeros(keys.size, np.uint32)
         lib().ck_oracle_delete(self._t, _p(keys), keys.size, _p(found), _p(retries))
         return found, retries
+
+    def upsert(self, keys, vals):
+        """Insert, or give a stored key its new value (status ST_UPDATED)."""
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        vals = np.ascontiguousarray(vals, dtype=np.uint64)
+        n = keys.size
+        status = np.zeros(n, np.uint8)
+        views = np.zeros(n, np.uint32)
+        kicks = np.zeros(n, np.uint32)
+        retries = np.zeros(n, np.uint32)
+        lib().ck_oracle_upsert(self._t, _p(keys), _p(vals), n, _p(status), _p(views),
+                               _p(kicks), _p(retries))
+        return {"status": status, "views": views, "kicks": kicks, "retries": retries}
 
     def overwrite(self, keys, vals):
         """New values for stored keys; returns (status per op, rounds lost)."""

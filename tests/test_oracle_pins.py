@@ -139,9 +139,9 @@ def test_failed_insert_leaves_table_unchanged():
                                               ("random_walk", True, 2, 1)])
 @pytest.mark.parametrize("batch", [1, 16])
 def test_dictionary_semantics(scheme, ghost, d, B, batch):
-    # P3: lookups, deletes and overwrites answer exactly like a textbook
-    # dictionary fed the same operation stream (Sec. 1: constant-time reads,
-    # overwrites and deletes).
+    # P3: lookups, deletes, overwrites and upserts answer exactly like a
+    # textbook dictionary fed the same operation stream (Sec. 1: constant-time
+    # reads, overwrites and deletes).
     t = make(1 << 8, B, d, scheme, ghost=ghost, batch_ops=batch, max_chain=1000)
     rng = np.random.default_rng(11)
     keys, vals = inputs.keys_values(21, 4000, value_bits=32 if B == 1 else 64)
@@ -150,7 +150,7 @@ def test_dictionary_semantics(scheme, ghost, d, B, batch):
     cap = int(0.85 * t.n * B)
     mask = 0xFFFFFFFF if B == 1 else 0xFFFFFFFFFFFFFFFF
     for step in range(80):
-        kind = rng.integers(0, 4)
+        kind = rng.integers(0, 5)
         if kind == 0 and len(model) < cap:
             m = int(rng.integers(1, 40))
             ks, vs = keys[nxt:nxt + m], vals[nxt:nxt + m]
@@ -172,6 +172,29 @@ def test_dictionary_semantics(scheme, ghost, d, B, batch):
                 seen.add(x)
             for x in pick:
                 model.pop(x, None)
+        elif kind == 4 and len(model) < cap:
+            # upserts: stored keys, new keys, and new keys twice in the batch.
+            # Statuses follow one-at-a-time order: updated exactly when the key
+            # is stored at that point (a repeated new key: inserted, then
+            # updated), so no key is ever stored twice.
+            present = list(model)
+            m = int(rng.integers(1, 12))
+            fresh = keys[nxt:nxt + m].tolist()
+            nxt += m
+            pick = [present[i] for i in rng.integers(0, len(present), m)] if present else []
+            pick += fresh + fresh[:3]
+            order = rng.permutation(len(pick))
+            pick = [pick[i] for i in order]
+            nv = rng.integers(0, 1 << 63, len(pick), dtype=np.uint64)
+            r = t.upsert(np.array(pick, np.uint64), nv)
+            for x, y, s2 in zip(pick, nv.tolist(), r["status"].tolist()):
+                if x in model:
+                    assert s2 == oracle.ST_UPDATED
+                    model[x] = y & mask
+                else:
+                    assert s2 in (oracle.ST_OK, oracle.ST_FAIL)
+                    if s2 == oracle.ST_OK:
+                        model[x] = y & mask
         elif kind == 3 and model:
             # new values for stored keys (repeats included: the later op in the
             # batch wins) and for absent keys (not found, nothing changes)
@@ -281,6 +304,32 @@ def test_sorted_with_equal_counts_is_bfs(scheme):
             out = t.export()
             res.append((r["status"][0], r["views"][0], r["kicks"][0], out["keys"].tobytes()))
         assert res[0] == res[1]
+
+
+@pytest.mark.parametrize("scheme,B", [("random_walk", 4), ("random_walk", 1)])
+def test_upsert_repeated_new_key_is_inserted_once(scheme, B):
+    # A new key given twice in one upsert batch: the first op inserts it, the
+    # second finds it and overwrites.  On a full random-walk table the two ops
+    # walk different chains (their draws differ), so only the claim on the
+    # key's first bin keeps them from storing the key twice.
+    d = 2 if B > 1 else 3
+    t = make(1 << 9, B, d, scheme, max_chain=1000, batch_ops=1 << 12)  # one sub-batch
+    k, v, _ = fill(t, 0.97 if B > 1 else 0.88)
+    new, nv = inputs.keys_values(77, 300, value_bits=32 if B == 1 else 64)
+    batch = np.empty(600, np.uint64)
+    batch[0::2], batch[1::2] = new, new
+    vals = np.empty(600, np.uint64)
+    vals[0::2], vals[1::2] = nv, nv[::-1]
+    r = t.upsert(batch, vals)
+    st = r["status"].reshape(300, 2)
+    inserted = st[:, 0] == oracle.ST_OK
+    assert np.all(st[inserted, 1] == oracle.ST_UPDATED)
+    assert inserted.sum() > 20
+    stored = checks.check_invariants(t.export(), t.n, B, d, 101, rattle=scheme == "rattle")
+    assert stored.issuperset(set(new[inserted].tolist()))
+    got, found = t.lookup(new[inserted])
+    mask = np.uint64(0xFFFFFFFF) if B == 1 else np.uint64(0xFFFFFFFFFFFFFFFF)
+    assert found.all() and np.array_equal(got, nv[::-1][inserted] & mask)
 
 
 # --------------------------------------------------------------------------- ghosts: Prop. 4.1
