@@ -25,9 +25,9 @@
  *   - `d_` pointers are device pointers (HIP global memory) owned by the
  *     caller; `h_` pointers are host pointers owned by the caller;
  *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
- *     it; ck_insert, ck_delete and ck_overwrite wait once per sub-batch for
- *     its round counters (one sub-batch ahead), so they return with every
- *     round complete;
+ *     it; ck_insert, ck_upsert, ck_delete and ck_overwrite wait once per
+ *     sub-batch for its round counters (one sub-batch ahead), so they return
+ *     with every round complete;
  *   - calls on one table must not overlap; tables are independent.
  */
 #ifndef CK_H
@@ -78,7 +78,8 @@ enum {
   CK_OP_OK = 1,        /* inserted / found / deleted */
   CK_OP_FAIL_CHAIN = 2,/* insert: chain or search cap exceeded; table unchanged */
   CK_OP_ABORTED = 3,   /* lost its claims in max_rounds rounds; table unchanged */
-  CK_OP_BAD_KEY = 4    /* the key is CK_EMPTY_KEY */
+  CK_OP_BAD_KEY = 4,   /* the key is CK_EMPTY_KEY */
+  CK_OP_UPDATED = 5    /* upsert: the key was stored and got the new value */
 };
 
 typedef struct {
@@ -181,6 +182,21 @@ ck_status ck_delete(ck_table* t, const uint64_t* d_keys, uint64_t n, uint8_t* d_
 ck_status ck_overwrite(ck_table* t, const uint64_t* d_keys, const void* d_vals, uint64_t n,
                        uint8_t* d_found, void* stream);
 
+/* Upsert (Sec. 1, inserts next to constant-time overwrites): each op first
+   looks for its key in the key's bins, in hash order.  A stored key gets the
+   new value in place, as ck_overwrite, and d_status[i] = CK_OP_UPDATED; an
+   absent key is inserted with the table's scheme (CK_OP_OK / FAIL_CHAIN /
+   ABORTED), and its plan also claims the key's first bin, so that a key given
+   several times in one call is inserted by its first op and overwritten by the
+   later ones, in op order.  Keys need not be absent or distinct.  The
+   diagnostics (each may be NULL) are ck_insert_ex's; an absent key's views
+   include the H bins of the presence check, a found key's are the bins
+   searched up to it.  Updated ops count in no ck_stats counter; the others
+   count as inserts, and the call adds n to the insert-op count. */
+ck_status ck_upsert(ck_table* t, const uint64_t* d_keys, const void* d_vals, uint64_t n,
+                    uint8_t* d_status, uint32_t* d_views, uint32_t* d_kicks,
+                    uint32_t* d_retries, void* stream);
+
 /* Copy the counters to host memory (synchronises `stream`). */
 ck_status ck_stats_get(ck_table* t, ck_stats* h_out, void* stream);
 ck_status ck_stats_reset(ck_table* t, void* stream);
@@ -260,6 +276,10 @@ ck_status ck_group_delete(ck_group* g, const uint32_t* d_table, const uint64_t* 
                           uint64_t n, uint8_t* d_found, void* stream);
 ck_status ck_group_overwrite(ck_group* g, const uint32_t* d_table, const uint64_t* d_keys,
                              const void* d_vals, uint64_t n, uint8_t* d_found, void* stream);
+/* Upsert (as ck_upsert); d_views, d_kicks, d_retries may be NULL. */
+ck_status ck_group_upsert(ck_group* g, const uint32_t* d_table, const uint64_t* d_keys,
+                          const void* d_vals, uint64_t n, uint8_t* d_status, uint32_t* d_views,
+                          uint32_t* d_kicks, uint32_t* d_retries, void* stream);
 /* Canonical image of one table of the group (as ck_export). */
 ck_status ck_group_export_table(ck_group* g, uint32_t table, uint64_t* h_keys, uint64_t* h_vals,
                                 uint16_t* h_rattle, uint32_t* h_meta, void* stream);

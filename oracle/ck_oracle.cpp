@@ -743,6 +743,12 @@ void ck_oracle_upsert(void* tp, const uint64_t* keys, const uint64_t* vals, uint
   insert_batch(tp, keys, vals, nullptr, n, status, views, kicks, retries, true);
 }
 
+void ck_oracle_upsert_ids(void* tp, const uint64_t* keys, const uint64_t* vals,
+                          const uint64_t* op_ids, uint64_t n, uint8_t* status, uint32_t* views,
+                          uint32_t* kicks, uint32_t* retries) {
+  insert_batch(tp, keys, vals, op_ids, n, status, views, kicks, retries, true);
+}
+
 // Lookup (Sec. 1): the key is in one of its bins, probed in hash order.
 void ck_oracle_lookup(void* tp, const uint64_t* keys, uint64_t n, uint64_t* vals_out,
                       uint8_t* found) {

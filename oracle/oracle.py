@@ -63,6 +63,7 @@ def lib():
         L.ck_oracle_delete.argtypes = [vp, vp, u64, vp, vp]
         L.ck_oracle_overwrite.argtypes = [vp, vp, vp, u64, vp, vp]
         L.ck_oracle_upsert.argtypes = [vp, vp, vp, u64, vp, vp, vp, vp]
+        L.ck_oracle_upsert_ids.argtypes = [vp, vp, vp, vp, u64, vp, vp, vp, vp]
         L.ck_oracle_export.argtypes = [vp, vp, vp, vp, vp]
         L.ck_oracle_import.argtypes = [vp, vp, vp, vp, vp]
         L.ck_oracle_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
@@ -134,8 +135,9 @@ class OracleTable:
         lib().ck_oracle_delete(self._t, _p(keys), keys.size, _p(found), _p(retries))
         return found, retries
 
-    def upsert(self, keys, vals):
-        """Insert, or give a stored key its new value (status ST_UPDATED)."""
+    def upsert(self, keys, vals, op_ids=None):
+        """Insert, or give a stored key its new value (status ST_UPDATED);
+        ``op_ids`` as for insert."""
         keys = np.ascontiguousarray(keys, dtype=np.uint64)
         vals = np.ascontiguousarray(vals, dtype=np.uint64)
         n = keys.size
@@ -143,8 +145,13 @@ class OracleTable:
         views = np.zeros(n, np.uint32)
         kicks = np.zeros(n, np.uint32)
         retries = np.zeros(n, np.uint32)
-        lib().ck_oracle_upsert(self._t, _p(keys), _p(vals), n, _p(status), _p(views),
-                               _p(kicks), _p(retries))
+        if op_ids is None:
+            lib().ck_oracle_upsert(self._t, _p(keys), _p(vals), n, _p(status), _p(views),
+                                   _p(kicks), _p(retries))
+        else:
+            ids = np.ascontiguousarray(op_ids, dtype=np.uint64)
+            lib().ck_oracle_upsert_ids(self._t, _p(keys), _p(vals), _p(ids), n, _p(status),
+                                       _p(views), _p(kicks), _p(retries))
         return {"status": status, "views": views, "kicks": kicks, "retries": retries}
 
     def overwrite(self, keys, vals):

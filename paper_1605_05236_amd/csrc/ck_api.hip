@@ -409,7 +409,8 @@ ck_status finish(ck_table* t, Flight& f, hipStream_t s) {
 ck_status run_batches(ck_table* t, const uint64_t* keys, const void* vals, uint64_t n,
                       uint8_t* status, uint32_t* views, uint32_t* kicks, uint32_t* retries,
                       bool is_delete, hipStream_t s, const uint32_t* op_table = nullptr,
-                      const uint2* tdesc = nullptr, bool overwrite = false) {
+                      const uint2* tdesc = nullptr, bool overwrite = false,
+                      bool upsert = false) {
   const uint32_t vb = t->B == 1 ? 4 : 8;
   const uint64_t slots = t->bins * t->B;
   Flight prev;
@@ -423,6 +424,7 @@ ck_status run_batches(ck_table* t, const uint64_t* keys, const void* vals, uint6
     f.r = make_round(t, keys + b0, vals ? (const char*)vals + b0 * vb : nullptr, status + b0, ops,
                      t->insert_count + b0, is_delete, op_table ? op_table + b0 : nullptr, tdesc);
     f.r.overwrite = overwrite ? 1u : 0u;
+    f.r.upsert = upsert ? 1u : 0u;
     f.m = m;
     f.slots = op_table ? 0 : slots;  // density bands are per table: a group keeps totals only
     f.set = set;
@@ -616,6 +618,16 @@ ck_status ck_overwrite(ck_table* t, const uint64_t* keys, const void* vals, uint
   if (!keys || !vals || !found) return CK_EINVAL;
   return run_batches(t, keys, vals, n, found, nullptr, nullptr, nullptr, true,
                      (hipStream_t)stream, nullptr, nullptr, true);
+}
+
+ck_status ck_upsert(ck_table* t, const uint64_t* keys, const void* vals, uint64_t n,
+                    uint8_t* status, uint32_t* views, uint32_t* kicks, uint32_t* retries,
+                    void* stream) {
+  if (!t) return CK_EINVAL;
+  if (n == 0) return CK_OK;
+  if (!keys || !vals || !status) return CK_EINVAL;
+  return run_batches(t, keys, vals, n, status, views, kicks, retries, false,
+                     (hipStream_t)stream, nullptr, nullptr, false, true);
 }
 
 // The sum of the device accumulators' copies (the maximum for max_kicks).
@@ -907,6 +919,16 @@ ck_status ck_group_overwrite(ck_group* G, const uint32_t* d_table, const uint64_
   if (!d_table || !keys || !vals || !found) return CK_EINVAL;
   return run_batches(G->t, keys, vals, n, found, nullptr, nullptr, nullptr, true,
                      (hipStream_t)stream, d_table, G->d_tdesc, true);
+}
+
+ck_status ck_group_upsert(ck_group* G, const uint32_t* d_table, const uint64_t* keys,
+                          const void* vals, uint64_t n, uint8_t* status, uint32_t* views,
+                          uint32_t* kicks, uint32_t* retries, void* stream) {
+  if (!G) return CK_EINVAL;
+  if (n == 0) return CK_OK;
+  if (!d_table || !keys || !vals || !status) return CK_EINVAL;
+  return run_batches(G->t, keys, vals, n, status, views, kicks, retries, false,
+                     (hipStream_t)stream, d_table, G->d_tdesc, false, true);
 }
 
 ck_status ck_group_export_table(ck_group* G, uint32_t table, uint64_t* keys, uint64_t* vals,

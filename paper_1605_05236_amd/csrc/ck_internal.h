@@ -49,7 +49,7 @@ struct IMove {           // 8 bytes
   uint32_t sf;           // slot | flags << 8
 };
 
-enum : uint32_t { PL_FAIL = 0, PL_OK = 1, PL_EVICT = 2, PL_NOTFOUND = 3 };
+enum : uint32_t { PL_FAIL = 0, PL_OK = 1, PL_EVICT = 2, PL_NOTFOUND = 3, PL_UPDATED = 4 };
 
 // Plan of one op of the sub-batch (32 bytes, one load in the commit kernel).
 // Plans of at most three moves that write only the op's own record keep them
@@ -69,6 +69,9 @@ struct PlanHdr {
   uint32_t pad[2];
 };
 constexpr uint32_t kHdrArena = 1u << 28;
+// Upsert of an absent key: the plan also holds a claim on the key's first bin
+// (which it may not write), so that two upserts of one new key conflict.
+constexpr uint32_t kHdrKeyClaim = 1u << 29;
 constexpr uint32_t kExtraInline = 2;  // inline moves beyond the first, per op
 
 // Lanes per op in the fresh planner: each lane holds B / lanes consecutive
@@ -182,6 +185,7 @@ struct Round {
   uint32_t max_rounds;
   uint32_t is_delete;         // the delete planner: deletes, and overwrites when
   uint32_t overwrite;         // this is set (new values in place)
+  uint32_t upsert;            // inserts that first look for the key (found: new value)
   uint32_t first;            // first round of the sub-batch: pend[p] = p, counters unset
   unsigned long long* wg_views;  // per eviction workgroup: bins viewed (cumulative)
   void* wg_scratch;          // per-workgroup scratch of the eviction planners

@@ -423,9 +423,41 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
     uint32_t b0 = 0, f0 = 0, b1 = 0, f1 = 0;
     uint32_t nm = 0, views = 0, twins = 0;
     bool placed = false;
-    // rattle-kicking has no separate fresh phase: every op goes to the walk
     const Tab T = active ? tab_of(g, r.op_table, r.tdesc, i) : Tab{0u, g.n};
-    if (active && !bad && g.scheme != CK_RATTLE) {
+    // upsert: the key's bins are searched in hash order first.  A stored key
+    // gets its new value in place (both copies of a ghost pair); an absent
+    // one is inserted as below, having viewed all H bins, and its plan also
+    // claims the key's first bin (kHdrKeyClaim), so that of two upserts of
+    // one new key in a round the later one loses and then finds the key.
+    const bool ups = r.upsert && active && !bad;
+    bool updated = false;
+    uint32_t key_bin = 0;
+    if (ups) {
+      uint32_t h[H];
+      hash_key<H>(g, T, x, h);
+      key_bin = h[0];
+#pragma unroll
+      for (int hi = 0; hi < H; ++hi) {
+        Keys sv;
+        sv.load(g, h[hi], G.sl);
+        const uint32_t m = sv.match(G, x);
+        if (m) {
+          const uint32_t slot = ffs32(m);
+          b0 = h[hi]; f0 = slot | (MV_VALUE << 8); nm = 1;
+          if (g.ghost && ((g.meta[h[hi]] >> slot) & 1u)) {
+            const uint32_t tb = h[hi ^ 1];
+            Keys ts;
+            ts.load(g, tb, G.sl);
+            b1 = tb; f1 = ffs32(ts.match(G, x)) | (MV_VALUE << 8); nm = 2;
+          }
+          views = (uint32_t)hi + 1;
+          updated = true;
+          break;
+        }
+      }
+    }
+    // rattle-kicking has no separate fresh phase: every op goes to the walk
+    if (active && !bad && !updated && g.scheme != CK_RATTLE) {
       uint32_t h[H];
       hash_key<H>(g, T, x, h);
       if (g.ghost) {
@@ -499,21 +531,25 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
     {
       const int lane = threadIdx.x & 63;
       const uint32_t u = c * 4 + (threadIdx.x >> 6);
-      const bool ev = active && leader && !bad && !placed;
+      const bool ev = active && leader && !bad && !placed && !updated;
       const uint64_t bal = __ballot(ev);
       if (ev) r.evict[(size_t)u * opw + __popcll(bal & ((1ull << lane) - 1))] = i;
       if (lane == 0) r.evict_cnt[u] = (uint32_t)__popcll(bal);
     }
     if (active && leader) {
-      ((uint4*)r.hdr)[2 * (size_t)i] = make_uint4(
-          hdr_pack(bad ? PL_FAIL : (placed ? PL_OK : PL_EVICT), twins, nm), views, b0, f0);
-      if (placed) {
+      const bool key_claim = ups && !updated;
+      const uint32_t st = bad ? PL_FAIL : (updated ? PL_UPDATED : (placed ? PL_OK : PL_EVICT));
+      ((uint4*)r.hdr)[2 * (size_t)i] =
+          make_uint4(hdr_pack(st, twins, nm) | (key_claim ? kHdrKeyClaim : 0u),
+                     views + (key_claim ? (uint32_t)H : 0u), b0, f0);
+      if (placed || updated) {
         if (nm > 0) claim(g, r, b0, i);
         if (nm > 1) {
           r.imv[(size_t)i * kExtraInline] = IMove{b1, f1};
           claim(g, r, b1, i);
         }
       }
+      if (key_claim) claim(g, r, key_bin, i);
     }
   }
 }
@@ -895,8 +931,11 @@ struct WalkPlanner {
     }
     if (gl == 0) {
       PlanHdr hd{};
-      hd.st = hdr_pack(status, status == PL_OK ? twins : 0, nm) | kHdrArena;
-      hd.views = views;
+      // an upsert's plan adds the presence check's views and its key claim
+      // (made by the fresh planner)
+      hd.st = hdr_pack(status, status == PL_OK ? twins : 0, nm) | kHdrArena |
+              (r.upsert ? kHdrKeyClaim : 0u);
+      hd.views = views + (r.upsert ? (uint32_t)H : 0u);
       hd.a = off;
       hd.b = status == PL_OK ? kicks : 0;
       hd.n_spawn = 0;
@@ -1679,8 +1718,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     }
     if (have && gl == 0) {
       PlanHdr hd{};
-      hd.st = hdr_pack(found ? PL_OK : PL_FAIL, twin, nm) | kHdrArena;
-      hd.views = views;
+      hd.st = hdr_pack(found ? PL_OK : PL_FAIL, twin, nm) | kHdrArena |
+              (r.upsert ? kHdrKeyClaim : 0u);
+      hd.views = views + (r.upsert ? (uint32_t)H : 0u);
       hd.a = off;
       hd.b = found ? depth : 0;
       hd.n_spawn = nsp;
@@ -1969,6 +2009,11 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
           get(j, bin, slot, fl, k, a);
           if (g.owner[bin] != me) mine = false;
         }
+        if ((h0.x & kHdrKeyClaim) && leader) {  // an upsert's claim on its key's first bin
+          uint32_t kb[1];
+          hash_key<1>(g, tab_of(g, r.op_table, r.tdesc, i), x, kb);
+          if (g.owner[kb[0]] != me) mine = false;
+        }
         win = ((__ballot(!mine) >> gshift) & ((1ull << CL) - 1)) == 0;
         if (!win && leader) {
           lost = r.op_lost[i] + views;
@@ -2019,7 +2064,8 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
           uint8_t st;
           if (x == kEmpty) st = CK_OP_BAD_KEY;
           else if (r.is_delete) st = status == PL_OK ? CK_OP_OK : CK_OP_NOT_FOUND;
-          else st = status == PL_OK ? CK_OP_OK : CK_OP_FAIL_CHAIN;
+          else if (status == PL_OK) st = CK_OP_OK;
+          else st = status == PL_UPDATED ? CK_OP_UPDATED : CK_OP_FAIL_CHAIN;
           r.status[i] = st;
           r.op_views[i] = views;
           if (kicks) r.op_kicks[i] = kicks;
@@ -2151,7 +2197,8 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
       o_lost[q] = lost[i];
       o_kicks[q] = kicks[i];
       o_twins[q] = twins[i];
-      if (!v) sv[q] = 0xFF;
+      // an upsert that gave a stored key its new value is not an insert
+      if (!v || sv[q] == CK_OP_UPDATED) sv[q] = 0xFF;
     }
   };
   if (t0 < t1) fetch(t0);

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libck.so")
 
 SCHEMES = {"random_walk": 0, "bfs": 1, "sorted": 2, "queue": 3, "rattle": 4, "hybrid": 5}
-OP_NOT_FOUND, OP_OK, OP_FAIL_CHAIN, OP_ABORTED, OP_BAD_KEY = range(5)
+OP_NOT_FOUND, OP_OK, OP_FAIL_CHAIN, OP_ABORTED, OP_BAD_KEY, OP_UPDATED = range(6)
 BANDS = 200
 EMPTY_KEY = 0xFFFFFFFFFFFFFFFF
 
@@ -69,12 +69,12 @@ class CkError(RuntimeError):
 _lib = None
 
 EXPORTED = ["ck_default_options", "ck_storage_bytes", "ck_create", "ck_clear", "ck_insert", "ck_insert_ex",
-            "ck_lookup", "ck_lookup_lpp", "ck_delete", "ck_overwrite", "ck_stats_get",
-            "ck_stats_reset",
+            "ck_lookup", "ck_lookup_lpp", "ck_delete", "ck_overwrite", "ck_upsert",
+            "ck_stats_get", "ck_stats_reset",
             "ck_export", "ck_import", "ck_hash", "ck_insert_count", "ck_destroy", "ck_strerror",
             "ck_timing_enable", "ck_timing_get", "ck_group_storage_bytes", "ck_group_create",
             "ck_group_insert", "ck_group_lookup", "ck_group_delete", "ck_group_overwrite",
-            "ck_group_export_table",
+            "ck_group_upsert", "ck_group_export_table",
             "ck_group_stats_get", "ck_group_timing_enable", "ck_group_timing_get",
             "ck_group_clear", "ck_group_insert_count", "ck_group_destroy"]
 
@@ -101,6 +101,7 @@ def load_library(path: str = LIB_PATH):
     L.ck_lookup_lpp.argtypes = [vp, vp, u64, vp, vp, u32, vp]
     L.ck_delete.argtypes = [vp, vp, u64, vp, vp]
     L.ck_overwrite.argtypes = [vp, vp, vp, u64, vp, vp]
+    L.ck_upsert.argtypes = [vp, vp, vp, u64, vp, vp, vp, vp, vp]
     L.ck_stats_get.argtypes = [vp, ctypes.POINTER(CkStats), vp]
     L.ck_stats_reset.argtypes = [vp, vp]
     L.ck_export.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -118,6 +119,7 @@ def load_library(path: str = LIB_PATH):
     L.ck_group_lookup.argtypes = [vp, vp, vp, u64, vp, vp, u32, vp]
     L.ck_group_delete.argtypes = [vp, vp, vp, u64, vp, vp]
     L.ck_group_overwrite.argtypes = [vp, vp, vp, vp, u64, vp, vp]
+    L.ck_group_upsert.argtypes = [vp, vp, vp, vp, u64, vp, vp, vp, vp, vp]
     L.ck_group_export_table.argtypes = [vp, u32, vp, vp, vp, vp, vp]
     L.ck_group_stats_get.argtypes = [vp, ctypes.POINTER(CkStats), vp]
     L.ck_group_timing_enable.argtypes = [vp, u32]
@@ -129,12 +131,12 @@ def load_library(path: str = LIB_PATH):
     L.ck_strerror.argtypes = [i32]
     L.ck_strerror.restype = ctypes.c_char_p
     for f in ("ck_storage_bytes", "ck_create", "ck_clear", "ck_insert", "ck_insert_ex", "ck_lookup",
-              "ck_lookup_lpp", "ck_delete", "ck_overwrite", "ck_stats_get", "ck_stats_reset",
-              "ck_export",
+              "ck_lookup_lpp", "ck_delete", "ck_overwrite", "ck_upsert", "ck_stats_get",
+              "ck_stats_reset", "ck_export",
               "ck_import", "ck_hash", "ck_destroy", "ck_timing_enable", "ck_timing_get",
               "ck_group_storage_bytes", "ck_group_create", "ck_group_insert", "ck_group_lookup",
-              "ck_group_delete", "ck_group_overwrite", "ck_group_export_table",
-              "ck_group_stats_get",
+              "ck_group_delete", "ck_group_overwrite", "ck_group_upsert",
+              "ck_group_export_table", "ck_group_stats_get",
               "ck_group_timing_enable", "ck_group_timing_get", "ck_group_clear",
               "ck_group_destroy"):
         getattr(L, f).restype = i32
@@ -257,6 +259,23 @@ class CuckooTable:
         _check(self._L.ck_overwrite(self._h, _ptr(keys), _ptr(vals), keys.numel(), _ptr(found),
                                     _stream(stream)))
         return found
+
+    def upsert(self, keys, vals, stream=None, diagnostics=True):
+        """Insert absent keys; stored keys get the new value (status UPDATED)."""
+        import torch
+        n = keys.numel()
+        status = torch.empty(n, dtype=torch.uint8, device=self.device)
+        if diagnostics:
+            views = torch.empty(n, dtype=torch.int32, device=self.device)
+            kicks, retries = torch.empty_like(views), torch.empty_like(views)
+            ptrs = (_ptr(views), _ptr(kicks), _ptr(retries))
+        else:
+            ptrs = (None, None, None)
+        _check(self._L.ck_upsert(self._h, _ptr(keys), _ptr(vals), n, _ptr(status), *ptrs,
+                                 _stream(stream)))
+        if not diagnostics:
+            return {"status": status}
+        return {"status": status, "views": views, "kicks": kicks, "retries": retries}
 
     # ---- host-side views
     def stats(self, stream=None) -> dict:
@@ -412,6 +431,22 @@ class CuckooGroup:
         _check(self._L.ck_group_overwrite(self._h, _ptr(tables), _ptr(keys), _ptr(vals),
                                           keys.numel(), _ptr(found), _stream(stream)))
         return found
+
+    def upsert(self, tables, keys, vals, stream=None, diagnostics=True):
+        import torch
+        n = keys.numel()
+        status = torch.empty(n, dtype=torch.uint8, device=self.device)
+        if diagnostics:
+            views = torch.empty(n, dtype=torch.int32, device=self.device)
+            kicks, retries = torch.empty_like(views), torch.empty_like(views)
+            ptrs = (_ptr(views), _ptr(kicks), _ptr(retries))
+        else:
+            ptrs = (None, None, None)
+        _check(self._L.ck_group_upsert(self._h, _ptr(tables), _ptr(keys), _ptr(vals), n,
+                                       _ptr(status), *ptrs, _stream(stream)))
+        if not diagnostics:
+            return {"status": status}
+        return {"status": status, "views": views, "kicks": kicks, "retries": retries}
 
     def export_table(self, table, stream=None) -> dict:
         nb = int(self.bins[table])

@@ -81,3 +81,9 @@ def assert_same_ops(g, o, what=""):
 def keys_for(n, B, load, seed):
     m = inputs.target_count(n, B, load)
     return inputs.keys_values(seed, m, value_bits=32 if B == 1 else 64)
+
+
+def gpu_upsert(t, keys, vals):
+    r = t.upsert(to_dev(keys), dev_values(vals, t.B))
+    return {k: v.cpu().numpy().view(np.uint32 if k != "status" else np.uint8)
+            for k, v in r.items()}

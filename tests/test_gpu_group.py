@@ -100,6 +100,31 @@ def test_group_matches_tables_alone(scheme, B, d, ghost):
             pos = np.nonzero(ot[c0:c1] == t)[0] + c0
             if pos.size:
                 assert np.array_equal(fw[pos], orc[t].overwrite(ok_[pos], nv[pos])[0])
+    # upserts through the group: stored keys, new keys (some twice), per table
+    # and per chunk as the oracle's sub-batches
+    nk, _ = inputs.keys_values(33, 400, value_bits=32 if B == 1 else 64)
+    nt_ = rng.integers(0, nt, 400).astype(np.uint32)
+    uk = np.concatenate([keys[2::7], nk, nk[:60]])
+    ut = np.concatenate([tids[2::7], nt_, nt_[:60]])
+    perm = rng.permutation(uk.size)
+    uk, ut = uk[perm], ut[perm]
+    uv = rng.integers(0, 1 << 63, uk.size, dtype=np.uint64)
+    if B == 1:
+        uv &= np.uint64(0xFFFFFFFF)
+    base = g.insert_count
+    ru = g.upsert(dev(ut, "u32"), dev(uk, "u64"), dev(uv, "u32" if B == 1 else "u64"))
+    ru = {k: v.cpu().numpy().view(np.uint8 if k == "status" else np.uint32) for k, v in ru.items()}
+    for c0 in range(0, uk.size, chunk):
+        c1 = min(uk.size, c0 + chunk)
+        for t in range(nt):
+            pos = np.nonzero(ut[c0:c1] == t)[0] + c0
+            if pos.size == 0:
+                continue
+            ro = orc[t].upsert(uk[pos], uv[pos], op_ids=base + pos)
+            for f in ("status", "views", "kicks", "retries"):
+                assert np.array_equal(ru[f][pos].astype(np.int64), ro[f].astype(np.int64)), \
+                    (scheme, t, f, "upsert")
+    assert (ru["status"] == oracle.ST_UPDATED).sum() >= (got["status"][2::7] == 1).sum()
     dk, dt = keys[::5], tids[::5]
     fd = g.delete(dev(dt, "u32"), dev(dk, "u64")).cpu().numpy()
     for c0 in range(0, dk.size, chunk):

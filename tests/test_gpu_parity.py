@@ -9,7 +9,8 @@ import pytest
 
 import checks
 from gpu_util import (assert_same_image, assert_same_ops, assert_same_stats, gpu_delete,
-                      gpu_insert, gpu_lookup, gpu_overwrite, gpu_table, keys_for, oracle_table)
+                      gpu_insert, gpu_lookup, gpu_overwrite, gpu_table, gpu_upsert, keys_for,
+                      oracle_table)
 from paper_1605_05236_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -114,6 +115,65 @@ def test_mixed_stream_parity(geom):
         assert_same_image(g.export(), o.export(), f"{geom} step {step}")
     assert_same_stats(g.stats(), o.stats(), f"{geom}")
     checks.check_invariants(g.export(), n, B, d, 105, ghost=ghost, rattle=scheme == "rattle")
+
+
+@pytest.mark.parametrize("geom", GEOMS, ids=ident)
+def test_upsert_parity(geom):
+    # Upsert batches that mix stored keys, new keys, new and stored keys given
+    # several times, and the reserved key, up to a near-full table; every call
+    # is compared op by op, then the image and the counters.
+    scheme, B, d, ghost, lb = geom
+    n = 1 << 11 if B > 1 else 1 << 12
+    load = {1: 0.9 if d == 4 else (0.85 if d == 3 else 0.45)}.get(B, 0.96)
+    kw = dict(ghost=ghost, load_balance=lb, max_chain=1000, max_search=500, batch_ops=500)
+    print(f"upsert parity {geom} n={n}", flush=True)
+    g = gpu_table(n, B, d, scheme, seed=6, **kw)
+    o = oracle_table(n, B, d, scheme, seed=6, **kw)
+    keys, _ = keys_for(n, B, load, seed=12)
+    rng = np.random.default_rng(6)
+    mask = np.uint64(0xFFFFFFFF) if B == 1 else np.uint64(0xFFFFFFFFFFFFFFFF)
+    pos, seen = 0, []
+    for step in range(8):
+        m = keys.size // 8
+        new = keys[pos:pos + m]
+        pos += m
+        old = np.array(seen, np.uint64)[rng.integers(0, len(seen), m // 3)] if seen else \
+            np.zeros(0, np.uint64)
+        batch = np.concatenate([new, old, new[:m // 10], old[:20], new[:5],
+                                np.array([inputs.EMPTY], np.uint64)])
+        batch = batch[rng.permutation(batch.size)]
+        vals = rng.integers(0, 1 << 63, batch.size, dtype=np.uint64) & mask
+        rg, ro = gpu_upsert(g, batch, vals), o.upsert(batch, vals)
+        assert_same_ops(rg, ro, f"{geom} step {step} upsert")
+        assert_same_image(g.export(), o.export(), f"{geom} step {step}")
+        seen.extend(new[np.isin(new, batch[ro["status"] == 1])].tolist())
+        assert (ro["status"] == 5).any() or step == 0
+    assert_same_stats(g.stats(), o.stats(), f"{geom}")
+    assert g.insert_count == o.insert_count
+    checks.check_invariants(g.export(), n, B, d, 106, ghost=ghost, rattle=scheme == "rattle")
+
+
+@pytest.mark.parametrize("scheme,B", [("random_walk", 4), ("random_walk", 1), ("bfs", 8),
+                                      ("rattle", 1)])
+def test_upsert_repeated_new_key_parity(scheme, B):
+    # A full table, then each new key twice in one sub-batch: the claim on the
+    # key's first bin makes the second op lose, retry and overwrite.
+    d = 2 if B > 1 else 3
+    n = 1 << 9
+    kw = dict(max_chain=1000, batch_ops=1 << 12)
+    g = gpu_table(n, B, d, scheme, seed=8, **kw)
+    o = oracle_table(n, B, d, scheme, seed=8, **kw)
+    keys, vals = keys_for(n, B, 0.97 if B > 1 else 0.88, seed=14)
+    assert_same_ops(gpu_insert(g, keys, vals), o.insert(keys, vals), "fill")
+    new, nv = inputs.keys_values(77, 300, value_bits=32 if B == 1 else 64)
+    batch = np.repeat(new, 2)
+    vb = np.empty(600, np.uint64)
+    vb[0::2], vb[1::2] = nv, nv[::-1]
+    rg, ro = gpu_upsert(g, batch, vb), o.upsert(batch, vb)
+    assert_same_ops(rg, ro, f"{scheme} {B}")
+    assert (ro["status"][1::2] == 5).sum() > 20
+    assert_same_image(g.export(), o.export(), f"{scheme} {B}")
+    assert_same_stats(g.stats(), o.stats(), f"{scheme} {B}")
 
 
 @pytest.mark.parametrize("B,d", [(1, 2), (1, 3), (1, 4), (2, 2), (4, 2), (8, 2)])
