@@ -16,7 +16,8 @@
 // Paper map:
 //   Sec. 1  (Introduction)         two distinct bins per key, first-fit insert,
 //                                  kick-out chains, constant-time lookup/delete.
-//   Sec. 2  (Past work)            load balancing (insert into the less full bin).
+//   Sec. 2  (Past work)            load balancing (insert into the less full bin);
+//                                  stashing keys whose chains are abandoned.
 //   Sec. 3  (Experimental setup)   uniformly random hashes; inserted keys are
 //                                  assumed absent; cost = bins viewed per insert.
 //   Sec. 4  (Ghost insertions)     duplicates in both bins; Proposition 4.1.
@@ -49,7 +50,8 @@ constexpr int kBands = 200;         // 0.5 % density bands
 
 enum Scheme { RANDOM_WALK = 0, BFS = 1, SORTED = 2, QUEUE = 3, RATTLE = 4, HYBRID = 5 };
 enum OpStatus { ST_NOT_FOUND = 0, ST_OK = 1, ST_FAIL = 2, ST_ABORTED = 3, ST_BAD_KEY = 4,
-                ST_UPDATED = 5 };
+                ST_UPDATED = 5, ST_STASHED = 6 };
+constexpr uint32_t kMaxStash = 64;
 
 // ---------------------------------------------------------------------------
 // splitmix64 (Steele, Lea, Flood 2014): state advances by the golden-ratio
@@ -96,6 +98,7 @@ struct Params {
   int load_balance;  // fresh insert into the less full bin (Sec. 2)
   uint32_t max_chain, max_search, max_rounds, batch_ops;
   uint64_t hash_seed, rng_seed;
+  uint32_t stash = 0;  // stash entries (Sec. 2); 0: no stash
 };
 
 struct Stats {
@@ -103,7 +106,7 @@ struct Stats {
   uint64_t views, views_all, kicks, max_kicks, retries, rounds, twin_updates;
   uint64_t lookups, lookup_hits, lookup_probes;
   uint64_t deletes, deletes_found, delete_probes, delete_retries;
-  uint64_t stored;
+  uint64_t stored, inserts_stashed;
   uint64_t band_inserts[kBands], band_views[kBands], band_kicks[kBands], band_fails[kBands];
 };
 
@@ -111,10 +114,19 @@ struct Table {
   Params p;
   uint64_t a[4], c[4];          // hash multipliers and offsets
   std::vector<BinState> bins;
+  std::vector<Slot> stash;      // the stash (Sec. 2): key kEmpty marks a free entry
   uint64_t insert_count = 0;    // global index of the next insert op
   Stats st;
 
   BinState bin(uint64_t b) const { return bins[b]; }
+
+  // The stash entry holding key x, else -1; the first free entry, else -1.
+  int stash_find(uint64_t x) const {
+    for (size_t j = 0; j < stash.size(); ++j)
+      if (stash[j].key == x) return (int)j;
+    return -1;
+  }
+  int stash_free() const { return stash_find(kEmpty); }
 
   // Bin indices of key x (reading of Sec. 1 / Sec. 3): H distinct bins.
   // h_i(x) = floor(((a_i x + c_i) mod 2^64) * n / 2^64); a clash with an
@@ -149,6 +161,9 @@ struct Plan {
   uint32_t draws = 0;
   std::map<uint64_t, BinState> draft;
   std::set<uint64_t> claims;  // bins claimed without being written (upsert key claims)
+  // At most one stash entry written: its index (-1: none) and new contents.
+  int stash_at = -1;
+  Slot stash_rec;
   std::vector<uint64_t> spawns;
   uint32_t views = 0, kicks = 0, twins = 0;
   int status = ST_FAIL;
@@ -459,6 +474,16 @@ Plan plan_insert(const Table& T, uint64_t op, uint64_t key, uint64_t val) {
     pl.draft.clear();
     pl.kicks = 0;
     pl.twins = 0;
+    // Stashing (Sec. 2): the key whose kick-out chain was abandoned goes to
+    // the first free stash entry, if there is one.  Plans leave the table as
+    // it was, so the homeless key is the inserted one.
+    const int j = T.stash_free();
+    if (j >= 0) {
+      pl.status = ST_STASHED;
+      pl.stash_at = j;
+      pl.stash_rec.key = key;
+      pl.stash_rec.val = T.p.B == 1 ? (val & 0xFFFFFFFFull) : val;
+    }
   }
   return pl;
 }
@@ -495,6 +520,15 @@ Plan plan_delete(const Table& T, uint64_t key, uint32_t* probes) {
       return pl;
     }
   }
+  if (!T.stash.empty()) {  // then the stash, searched as one unit
+    ++*probes;
+    const int j = T.stash_find(key);
+    if (j >= 0) {
+      pl.stash_at = j;
+      pl.stash_rec = Slot();
+      pl.status = ST_OK;
+    }
+  }
   return pl;
 }
 
@@ -527,6 +561,16 @@ Plan plan_overwrite(const Table& T, uint64_t key, uint64_t val, uint32_t* probes
       return pl;
     }
   }
+  if (!T.stash.empty()) {
+    ++*probes;
+    const int j = T.stash_find(key);
+    if (j >= 0) {
+      pl.stash_at = j;
+      pl.stash_rec = T.stash[j];
+      pl.stash_rec.val = v;
+      pl.status = ST_OK;
+    }
+  }
   return pl;
 }
 
@@ -537,22 +581,31 @@ Plan plan_overwrite(const Table& T, uint64_t key, uint64_t val, uint32_t* probes
 // absent key's plan adds its own views.  An absent key's plan also claims
 // the key's first bin without writing it, so two upserts of one new key in a
 // round conflict: the later one, next round, finds the key and overwrites it.
+// With a stash, the stash is searched after the bins, as one more view.
 Plan plan_upsert(const Table& T, uint64_t op, uint64_t key, uint64_t val) {
   uint64_t h[4];
   T.hash(key, h);
-  for (int i = 0; i < T.p.H; ++i) {
+  uint32_t seen = 0;
+  bool found = false;
+  for (int i = 0; i < T.p.H && !found; ++i) {
     const BinState& s = T.bins[h[i]];
+    ++seen;
     for (int j = 0; j < T.p.B; ++j)
-      if (s.s[j].key == key) {
-        uint32_t probes = 0;
-        Plan pl = plan_overwrite(T, key, val, &probes);
-        pl.status = ST_UPDATED;
-        pl.views = (uint32_t)(i + 1);
-        return pl;
-      }
+      if (s.s[j].key == key) found = true;
+  }
+  if (!found && !T.stash.empty()) {
+    ++seen;
+    found = T.stash_find(key) >= 0;
+  }
+  if (found) {
+    uint32_t probes = 0;
+    Plan pl = plan_overwrite(T, key, val, &probes);
+    pl.status = ST_UPDATED;
+    pl.views = seen;
+    return pl;
   }
   Plan pl = plan_insert(T, op, key, val);
-  pl.views += (uint32_t)T.p.H;
+  pl.views += seen;
   pl.claims.insert(h[0]);
   return pl;
 }
@@ -588,6 +641,8 @@ uint32_t run_rounds(Table& T, const std::vector<uint64_t>& ids, PlanFn plan_fn,
     for (size_t k = 0; k < plans.size(); ++k) {
       for (auto& kv : plans[k].draft) take(kv.first, pending[k]);
       for (uint64_t b : plans[k].claims) take(b, pending[k]);
+      // stash entry j is claimed like one more bin, numbered n + j
+      if (plans[k].stash_at >= 0) take(T.p.n + (uint64_t)plans[k].stash_at, pending[k]);
     }
     std::vector<uint64_t> next;
     for (size_t k = 0; k < plans.size(); ++k) {
@@ -597,6 +652,8 @@ uint32_t run_rounds(Table& T, const std::vector<uint64_t>& ids, PlanFn plan_fn,
         if (owner[kv.first] != i) wins = false;
       for (uint64_t b : plans[k].claims)
         if (owner[b] != i) wins = false;
+      if (plans[k].stash_at >= 0 && owner[T.p.n + (uint64_t)plans[k].stash_at] != i)
+        wins = false;
       res[i].views_all += plans[k].views;
       if (wins) {
         for (auto& kv : plans[k].draft) {
@@ -604,6 +661,7 @@ uint32_t run_rounds(Table& T, const std::vector<uint64_t>& ids, PlanFn plan_fn,
           nb.sc = T.bins[kv.first].sc;  // spawn counts are merged below
           T.bins[kv.first] = nb;
         }
+        if (plans[k].stash_at >= 0) T.stash[(size_t)plans[k].stash_at] = plans[k].stash_rec;
         res[i].status = plans[k].status;
         res[i].views = plans[k].views;
         res[i].kicks = plans[k].kicks;
@@ -634,7 +692,7 @@ struct ck_oracle_stats_t {
   uint64_t views, views_all, kicks, max_kicks, retries, rounds, twin_updates;
   uint64_t lookups, lookup_hits, lookup_probes;
   uint64_t deletes, deletes_found, delete_probes, delete_retries;
-  uint64_t stored;
+  uint64_t stored, inserts_stashed;
   uint64_t band_inserts[kBands], band_views[kBands], band_kicks[kBands], band_fails[kBands];
 };
 
@@ -662,6 +720,35 @@ void* ck_oracle_create(uint64_t n, int B, int H, int scheme, int ghost, int load
 }
 
 void ck_oracle_destroy(void* t) { delete (Table*)t; }
+
+// Give an empty table a stash of `entries` entries (at most kMaxStash).
+int ck_oracle_set_stash(void* tp, uint32_t entries) {
+  Table& T = *(Table*)tp;
+  if (entries > kMaxStash) return -1;
+  T.p.stash = entries;
+  T.stash.assign(entries, Slot());
+  return 0;
+}
+
+// The stash's keys and values, entry by entry (key kEmpty: free).
+void ck_oracle_export_stash(void* tp, uint64_t* keys, uint64_t* vals) {
+  Table& T = *(Table*)tp;
+  for (size_t j = 0; j < T.stash.size(); ++j) {
+    keys[j] = T.stash[j].key;
+    vals[j] = T.stash[j].val;
+  }
+}
+
+// Load the stash (after ck_oracle_import, which counts the bins' keys).
+void ck_oracle_import_stash(void* tp, const uint64_t* keys, const uint64_t* vals) {
+  Table& T = *(Table*)tp;
+  for (size_t j = 0; j < T.stash.size(); ++j) {
+    T.stash[j].key = keys[j];
+    T.stash[j].val = vals[j];
+    T.stash[j].rattle = 0;
+    if (keys[j] != kEmpty) ++T.st.stored;
+  }
+}
 
 void ck_oracle_hash(void* t, uint64_t key, uint64_t* out) { ((Table*)t)->hash(key, out); }
 
@@ -716,7 +803,14 @@ static void insert_batch(void* tp, const uint64_t* keys, const uint64_t* vals,
         T.st.max_kicks = std::max<uint64_t>(T.st.max_kicks, r.kicks);
         T.st.twin_updates += r.twins;
       } else {
-        ++T.st.inserts_failed;
+        // the chain failed; a stashed key is still held by the table, and
+        // `stored` counts every key held, in bins or in the stash
+        if (r.status == ST_STASHED) {
+          ++ok_before;
+          ++T.st.inserts_stashed;
+        } else {
+          ++T.st.inserts_failed;
+        }
         T.st.band_fails[band] += 1;
       }
     }
@@ -769,6 +863,14 @@ void ck_oracle_lookup(void* tp, const uint64_t* keys, uint64_t n, uint64_t* vals
           vals_out[q] = s.s[j].val;
           break;
         }
+    }
+    if (!found[q] && !T.stash.empty()) {  // then the stash, one more probe
+      ++T.st.lookup_probes;
+      const int j = T.stash_find(keys[q]);
+      if (j >= 0) {
+        found[q] = 1;
+        vals_out[q] = T.stash[(size_t)j].val;
+      }
     }
     T.st.lookup_hits += found[q];
   }
@@ -867,6 +969,8 @@ void ck_oracle_import(void* tp, const uint64_t* keys, const uint64_t* vals,
       if (T.bins[b].s[j].key != kEmpty && ((T.bins[b].dup >> j) & 1)) ++dups;
   T.st.stored = distinct + dups / 2;
 }
+
+static_assert(sizeof(ck_oracle_stats_t) == sizeof(Stats), "the C view of the counters");
 
 void ck_oracle_stats(void* tp, ck_oracle_stats_t* out) {
   std::memcpy(out, &((Table*)tp)->st, sizeof(ck_oracle_stats_t));

@@ -19,14 +19,15 @@ LIB = os.path.join(HERE, "libck_oracle.so")
 RANDOM_WALK, BFS, SORTED, QUEUE, RATTLE, HYBRID = range(6)
 SCHEMES = {"random_walk": RANDOM_WALK, "bfs": BFS, "sorted": SORTED, "queue": QUEUE,
            "rattle": RATTLE, "hybrid": HYBRID}
-ST_NOT_FOUND, ST_OK, ST_FAIL, ST_ABORTED, ST_BAD_KEY, ST_UPDATED = range(6)
+ST_NOT_FOUND, ST_OK, ST_FAIL, ST_ABORTED, ST_BAD_KEY, ST_UPDATED, ST_STASHED = range(7)
 EMPTY = np.uint64(0xFFFFFFFFFFFFFFFF)
 BANDS = 200
 
 _STAT_SCALARS = ["inserts_ok", "inserts_failed", "inserts_aborted", "inserts_bad_key",
                  "views", "views_all", "kicks", "max_kicks", "retries", "rounds",
                  "twin_updates", "lookups", "lookup_hits", "lookup_probes", "deletes",
-                 "deletes_found", "delete_probes", "delete_retries", "stored"]
+                 "deletes_found", "delete_probes", "delete_retries", "stored",
+                 "inserts_stashed"]
 
 
 class _Stats(ctypes.Structure):
@@ -65,6 +66,10 @@ def lib():
         L.ck_oracle_upsert.argtypes = [vp, vp, vp, u64, vp, vp, vp, vp]
         L.ck_oracle_upsert_ids.argtypes = [vp, vp, vp, vp, u64, vp, vp, vp, vp]
         L.ck_oracle_export.argtypes = [vp, vp, vp, vp, vp]
+        L.ck_oracle_set_stash.argtypes = [vp, ctypes.c_uint32]
+        L.ck_oracle_set_stash.restype = ctypes.c_int
+        L.ck_oracle_export_stash.argtypes = [vp, vp, vp]
+        L.ck_oracle_import_stash.argtypes = [vp, vp, vp]
         L.ck_oracle_import.argtypes = [vp, vp, vp, vp, vp]
         L.ck_oracle_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
         L.ck_oracle_insert_count.restype = u64
@@ -83,7 +88,7 @@ class OracleTable:
 
     def __init__(self, bins, slots_per_bin=4, d=2, scheme="random_walk", ghost=False,
                  load_balance=False, max_chain=500, max_search=500, max_rounds=0,
-                 batch_ops=1, hash_seed=0, rng_seed=0):
+                 batch_ops=1, hash_seed=0, rng_seed=0, stash=0):
         self.n, self.B, self.H = int(bins), int(slots_per_bin), int(d)
         self.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
         self._t = lib().ck_oracle_create(self.n, self.B, self.H, self.scheme, int(ghost),
@@ -91,6 +96,9 @@ class OracleTable:
                                          max_rounds, batch_ops, hash_seed, rng_seed)
         if not self._t:
             raise ValueError("oracle rejected the table parameters")
+        self.stash = int(stash)
+        if self.stash and lib().ck_oracle_set_stash(self._t, self.stash) != 0:
+            raise ValueError("oracle rejected the stash size")
 
     def __del__(self):
         if getattr(self, "_t", None):
@@ -170,13 +178,23 @@ class OracleTable:
         rattle = np.zeros(S, np.uint16)
         meta = np.zeros(self.n, np.uint32)
         lib().ck_oracle_export(self._t, _p(keys), _p(vals), _p(rattle), _p(meta))
-        return {"keys": keys, "vals": vals, "rattle": rattle, "meta": meta}
+        img = {"keys": keys, "vals": vals, "rattle": rattle, "meta": meta}
+        if self.stash:
+            sk = np.zeros(self.stash, np.uint64)
+            sv = np.zeros(self.stash, np.uint64)
+            lib().ck_oracle_export_stash(self._t, _p(sk), _p(sv))
+            img["stash_keys"], img["stash_vals"] = sk, sv
+        return img
 
     def load(self, img):
         lib().ck_oracle_import(self._t, _p(np.ascontiguousarray(img["keys"], np.uint64)),
                                _p(np.ascontiguousarray(img["vals"], np.uint64)),
                                _p(np.ascontiguousarray(img["rattle"], np.uint16)),
                                _p(np.ascontiguousarray(img["meta"], np.uint32)))
+        if self.stash:
+            lib().ck_oracle_import_stash(
+                self._t, _p(np.ascontiguousarray(img["stash_keys"], np.uint64)),
+                _p(np.ascontiguousarray(img["stash_vals"], np.uint64)))
 
     def stats(self) -> dict:
         s = _Stats()

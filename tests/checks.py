@@ -97,7 +97,13 @@ def check_invariants(img, n, B, H, hash_seed, ghost=False, rattle=False):
         assert np.all(r >= 1), "stored key with no try recorded"
         where = hb[np.arange(k.size), (r - 1) % H]
         assert np.all(where == b), "rattle counter does not name the key's bin"
-    return set(uk.tolist())
+    held = set(uk.tolist())
+    if "stash_keys" in img:  # stashed keys: distinct, and in no bin
+        sk = img["stash_keys"][img["stash_keys"] != EMPTY]
+        assert np.unique(sk).size == sk.size, "a key stashed twice"
+        assert not held.intersection(sk.tolist()), "a stashed key also sits in a bin"
+        held.update(sk.tolist())
+    return held
 
 
 # ---------------------------------------------------------------------------

@@ -143,11 +143,65 @@ def test_dictionary_semantics(scheme, ghost, d, B, batch):
     # textbook dictionary fed the same operation stream (Sec. 1: constant-time
     # reads, overwrites and deletes).
     t = make(1 << 8, B, d, scheme, ghost=ghost, batch_ops=batch, max_chain=1000)
+    run_dictionary(t, scheme, ghost, d, B, int(0.85 * t.n * B))
+
+
+@pytest.mark.parametrize("scheme,ghost,d,B", [("random_walk", False, 2, 4), ("bfs", True, 2, 4),
+                                              ("sorted", False, 2, 8), ("queue", False, 2, 2),
+                                              ("rattle", False, 3, 1)])
+@pytest.mark.parametrize("batch", [1, 16])
+def test_dictionary_semantics_with_stash(scheme, ghost, d, B, batch):
+    # The same with a stash (Sec. 2) and short chain caps, driven past the
+    # load where chains fail: a stashed key is held like a placed one.
+    t = make(1 << 7, B, d, scheme, ghost=ghost, batch_ops=batch, max_chain=6, max_search=12,
+             stash=8)
+    st = run_dictionary(t, scheme, ghost, d, B, int(1.2 * t.n * B), prefill=int(0.95 * t.n * B))
+    assert st["inserts_stashed"] > 0 and st["inserts_failed"] > 0
+
+
+HELD = (oracle.ST_OK, oracle.ST_STASHED)
+
+
+@pytest.mark.parametrize("scheme,d,B", [("random_walk", 2, 4), ("bfs", 2, 4), ("rattle", 3, 1)])
+def test_stash_catches_exactly_the_first_failures(scheme, d, B):
+    # Stashing (Sec. 2) only changes where the key of an abandoned chain goes.
+    # Serially, a failed plan leaves the bins as they were, so the same insert
+    # stream gives the same per-op results and the same bins with or without
+    # a stash, except that the first S failures are stashed, in order.
+    kw = dict(max_chain=6, max_search=12)
+    a = make(1 << 7, B, d, scheme, **kw)
+    b = make(1 << 7, B, d, scheme, stash=5, **kw)
+    keys, vals = inputs.keys_values(5, int(0.99 * (1 << 7) * B), value_bits=32 if B == 1 else 64)
+    ra, rb = a.insert(keys, vals), b.insert(keys, vals)
+    fails = np.nonzero(ra["status"] == oracle.ST_FAIL)[0]
+    assert fails.size > 5
+    expect = ra["status"].copy()
+    expect[fails[:5]] = oracle.ST_STASHED
+    assert np.array_equal(rb["status"], expect)
+    for f in ("views", "kicks"):
+        assert np.array_equal(ra[f], rb[f])
+    ia, ib = a.export(), b.export()
+    for f in ("keys", "vals", "rattle", "meta"):
+        assert np.array_equal(ia[f], ib[f])
+    assert ib["stash_keys"].tolist() == keys[fails[:5]].tolist()
+    mask = np.uint64(0xFFFFFFFF) if B == 1 else np.uint64(0xFFFFFFFFFFFFFFFF)
+    assert np.array_equal(ib["stash_vals"], vals[fails[:5]] & mask)
+    got, found = b.lookup(keys[fails])
+    assert found.tolist() == [1] * 5 + [0] * (fails.size - 5)
+    sa, sb = a.stats(), b.stats()
+    assert sb["inserts_stashed"] == 5 and sb["inserts_failed"] == sa["inserts_failed"] - 5
+    assert sb["stored"] == sa["stored"] + 5
+
+
+def run_dictionary(t, scheme, ghost, d, B, cap, prefill=0):
     rng = np.random.default_rng(11)
     keys, vals = inputs.keys_values(21, 4000, value_bits=32 if B == 1 else 64)
     model: dict[int, int] = {}
-    nxt = 0
-    cap = int(0.85 * t.n * B)
+    r = t.insert(keys[:prefill], vals[:prefill])
+    for x, y, s in zip(keys[:prefill].tolist(), vals[:prefill].tolist(), r["status"].tolist()):
+        if s in HELD:
+            model[x] = y
+    nxt = prefill
     mask = 0xFFFFFFFF if B == 1 else 0xFFFFFFFFFFFFFFFF
     for step in range(80):
         kind = rng.integers(0, 5)
@@ -157,7 +211,7 @@ def test_dictionary_semantics(scheme, ghost, d, B, batch):
             nxt += m
             r = t.insert(ks, vs)
             for x, y, s in zip(ks.tolist(), vs.tolist(), r["status"].tolist()):
-                if s == oracle.ST_OK:
+                if s in HELD:
                     model[x] = y
         elif kind == 1 and model:
             present = list(model)
@@ -192,8 +246,8 @@ def test_dictionary_semantics(scheme, ghost, d, B, batch):
                     assert s2 == oracle.ST_UPDATED
                     model[x] = y & mask
                 else:
-                    assert s2 in (oracle.ST_OK, oracle.ST_FAIL)
-                    if s2 == oracle.ST_OK:
+                    assert s2 in HELD + (oracle.ST_FAIL,)
+                    if s2 in HELD:
                         model[x] = y & mask
         elif kind == 3 and model:
             # new values for stored keys (repeats included: the later op in the
@@ -215,8 +269,12 @@ def test_dictionary_semantics(scheme, ghost, d, B, batch):
                 assert f == (x in model)
                 if f:
                     assert g == model[x]
-    assert t.stats()["stored"] == len(model)
-    checks.check_invariants(t.export(), t.n, B, d, 101, ghost=ghost, rattle=scheme == "rattle")
+    st = t.stats()
+    assert st["stored"] == len(model)
+    held = checks.check_invariants(t.export(), t.n, B, d, 101, ghost=ghost,
+                                   rattle=scheme == "rattle")
+    assert held == set(model)
+    return st
 
 
 def test_empty_key_rejected():
