@@ -8,8 +8,9 @@ already resident in HBM:
      rounds: fresh placement, kick-out planning, claims, reverse-order commit,
      metadata and spawn counts, per-band statistics);
   2. 2^26 lookups at a 90% hit rate on the last table;
-  3. 2^20 overwrites of stored keys, then 2^20 deletes of the same keys, on
-     that table.
+  3. 2^20 overwrites of stored keys, 2^21 upserts (those keys again,
+     interleaved with as many absent ones), then 2^20 deletes of the stored
+     keys, on that table.
 `value` is inserts per second over the three fills.  Lookup and delete rates,
 bins viewed per insert around 95% load, the roofline of the dominant kernel
 and the CPU oracle's rate on a bounded sample are reported beside it.
@@ -39,8 +40,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 # shapes, host loop); once that source changes the benchmark reports null
 # until the counters are taken again.
 MEASURED_EVICT_TRAFFIC = {
-    "sources_sha256": "ec621a9f3b5027c1a26b4d3547bcca79ef6ee269aeafe706b721779eceb496fe",
-    "bytes_per_launch": 36324754,
+    "sources_sha256": "a473900933a71fe5caa23907ebabd29ac52cc8684b08fbb1db07085710685d00",
+    "bytes_per_launch": 36658443,
     "profile": "profiles/evict_planners__fill95_2e24x8.md",
 }
 _SOURCES = ("ck_kernels.hip", "ck_api.hip", "ck_internal.h")
@@ -521,6 +522,14 @@ def main():
     ddel = as_device_keys(dels)
     # the same stored keys get new values first (overwrites), then go
     dnew = torch.from_numpy(rng.integers(0, 1 << 63, dels.size, dtype=np.int64)).cuda()
+    # then upserts: the same stored keys (new values again) and as many absent
+    # keys, interleaved
+    fresh, fresh_v = inputs.keys_values(3, dels.size)
+    ups = np.empty(2 * dels.size, np.uint64)
+    ups[0::2], ups[1::2] = dels, fresh
+    ups_v = np.empty(2 * dels.size, np.uint64)
+    ups_v[0::2], ups_v[1::2] = rng.integers(0, 1 << 63, dels.size, dtype=np.uint64), fresh_v
+    dups, dups_v = as_device_keys(ups), as_device_keys(ups_v)
     del q
     print(f"# inputs ready in {time.time() - t0:.1f}s: {m} inserts, {nq} lookups, "
           f"{dels.size} deletes", file=sys.stderr, flush=True)
@@ -556,13 +565,19 @@ def main():
         e1.record(stream)
         fw = t.overwrite(ddel, dnew)
         e2.record(stream)
+        ru = t.upsert(dups, dups_v, diagnostics=False)["status"]
+        e4 = torch.cuda.Event(enable_timing=True)
+        e4.record(stream)
         t.delete(ddel)
         e3.record(stream)
         e3.synchronize()
         res["lookup_s"] = e0.elapsed_time(e1) / 1e3
         res["overwrite_s"] = e1.elapsed_time(e2) / 1e3
-        res["delete_s"] = e2.elapsed_time(e3) / 1e3
+        res["upsert_s"] = e2.elapsed_time(e4) / 1e3
+        res["delete_s"] = e4.elapsed_time(e3) / 1e3
         res["overwrites_found"] = bool((fw == 1).all())
+        # stored keys are updated (5), absent ones inserted (1)
+        res["upserts_as_expected"] = bool((ru[0::2] == 5).all() and (ru[1::2] == 1).all())
         if timed:
             res["lookup_timing"] = t.timing()["lookup"]
         return res
@@ -588,7 +603,8 @@ def main():
     for k in range(args.steps):
         results.append(step(k == args.steps - 1, [dominant]))
         print(f"# step {k}: fills {results[-1]['fill_s']} lookup {results[-1]['lookup_s']:.4f}s "
-              f"overwrite {results[-1]['overwrite_s']:.4f}s delete {results[-1]['delete_s']:.4f}s",
+              f"overwrite {results[-1]['overwrite_s']:.4f}s upsert {results[-1]['upsert_s']:.4f}s "
+              f"delete {results[-1]['delete_s']:.4f}s",
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
@@ -601,7 +617,9 @@ def main():
     lookup_s = float(np.mean([r["lookup_s"] for r in results]))
     delete_s = float(np.mean([r["delete_s"] for r in results]))
     overwrite_s = float(np.mean([r["overwrite_s"] for r in results]))
+    upsert_s = float(np.mean([r["upsert_s"] for r in results]))
     assert all(r["overwrites_found"] for r in results), "an overwrite missed a stored key"
+    assert all(r["upserts_as_expected"] for r in results), "an upsert gave an unexpected status"
     ins_rate = len(schemes) * m / sum(fill.values())
     st = results[-1]["stats"]
     band = int(round(args.load * 200)) - 1  # the [load - 0.5%, load) band
@@ -672,8 +690,9 @@ def main():
                                f"{n * B * 16 / 2**30:.0f} GiB), 2 hash functions, "
                                f"fill to {args.load} in sub-batches of 2^{args.batch_log2} "
                                f"with {','.join(schemes)}; 2^{args.lookups_log2} lookups at "
-                               f"{args.hit_rate} hits; 2^{args.deletes_log2} overwrites, "
-                               f"then deletes, of stored keys",
+                               f"{args.hit_rate} hits; 2^{args.deletes_log2} overwrites of "
+                               f"stored keys, 2^{args.deletes_log2 + 1} upserts (half stored, "
+                               f"half absent), then deletes of the stored keys",
                    "bins": n, "slots_per_bin": B, "inserts_per_fill": m,
                    "lookups": nq, "deletes": int(dels.size), "max_search": args.max_search},
         "inserts_per_s_by_scheme": {s: m / fill[s] for s in schemes},
@@ -685,6 +704,7 @@ def main():
         "lookups_per_s": nq / lookup_s,
         "deletes_per_s": dels.size / delete_s,
         "overwrites_per_s": dels.size / overwrite_s,
+        "upserts_per_s": ups.size / upsert_s,
         "lookup_probes_per_query": probes_per_q,
         "roofline": roofline,
         "lookup_roofline": lookup_roof,

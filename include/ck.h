@@ -79,7 +79,8 @@ enum {
   CK_OP_FAIL_CHAIN = 2,/* insert: chain or search cap exceeded; table unchanged */
   CK_OP_ABORTED = 3,   /* lost its claims in max_rounds rounds; table unchanged */
   CK_OP_BAD_KEY = 4,   /* the key is CK_EMPTY_KEY */
-  CK_OP_UPDATED = 5    /* upsert: the key was stored and got the new value */
+  CK_OP_UPDATED = 5,   /* upsert: the key was stored and got the new value */
+  CK_OP_STASHED = 6    /* insert: the chain failed and the key went to the stash */
 };
 
 typedef struct {
@@ -103,6 +104,11 @@ typedef struct {
                                 0 = as many as the larger of the last two
                                 insert sub-batches took (deletes: one more than
                                 the last), then groups of two.  Performance only */
+  uint32_t stash;            /* stash entries per table (Sec. 2), <= 64; 0 = no
+                                stash.  An insert whose chain fails puts its key
+                                in the first free entry (CK_OP_STASHED); lookups,
+                                deletes, overwrites and upserts search the stash
+                                after the key's bins, as one more probe */
 } ck_options;
 
 /* Counters of one table since creation (or the last ck_stats_reset). */
@@ -120,6 +126,9 @@ typedef struct {
   uint64_t band_kicks[CK_BANDS], band_fails[CK_BANDS];
   uint64_t arena_moves; /* capacity of the plan arena (moves of one round's
                            kick-out plans); it doubles when a round runs out */
+  uint64_t inserts_stashed; /* inserts whose chain failed and whose key went to
+                               the stash (counted in band_fails and `stored`,
+                               not in inserts_failed) */
 } ck_stats;
 
 /* Defaults: no ghosts, first fit, max_chain 500, max_search 500, max_rounds 0,
@@ -238,6 +247,14 @@ ck_status ck_export(ck_table* t, uint64_t* h_keys, uint64_t* h_vals, uint16_t* h
 ck_status ck_import(ck_table* t, const uint64_t* h_keys, const uint64_t* h_vals,
                     const uint16_t* h_rattle, const uint32_t* h_meta, void* stream);
 
+/* The stash (Sec. 2) in host memory: `stash` keys and values, entry by entry
+   (key CK_EMPTY_KEY: free; values zero extended).  Export synchronises
+   `stream`; import (after ck_import) adds the stashed keys to `stored`.
+   CK_EINVAL when the table has no stash. */
+ck_status ck_export_stash(ck_table* t, uint64_t* h_keys, uint64_t* h_vals, void* stream);
+ck_status ck_import_stash(ck_table* t, const uint64_t* h_keys, const uint64_t* h_vals,
+                          void* stream);
+
 /* Hash a key as the table does (the d bin indices, in order). */
 ck_status ck_hash(const ck_table* t, uint64_t key, uint64_t* h_bins_out);
 
@@ -280,6 +297,9 @@ ck_status ck_group_overwrite(ck_group* g, const uint32_t* d_table, const uint64_
 ck_status ck_group_upsert(ck_group* g, const uint32_t* d_table, const uint64_t* d_keys,
                           const void* d_vals, uint64_t n, uint8_t* d_status, uint32_t* d_views,
                           uint32_t* d_kicks, uint32_t* d_retries, void* stream);
+/* One table's stash (as ck_export_stash). */
+ck_status ck_group_export_stash(ck_group* g, uint32_t table, uint64_t* h_keys, uint64_t* h_vals,
+                                void* stream);
 /* Canonical image of one table of the group (as ck_export). */
 ck_status ck_group_export_table(ck_group* g, uint32_t table, uint64_t* h_keys, uint64_t* h_vals,
                                 uint16_t* h_rattle, uint32_t* h_meta, void* stream);

@@ -99,6 +99,7 @@ struct Params {
   uint32_t max_chain, max_search, max_rounds, batch_ops;
   uint64_t hash_seed, rng_seed;
   uint32_t stash = 0;  // stash entries (Sec. 2); 0: no stash
+  uint32_t hash_bias = 0;  // 0: uniform hashes; 1-4: biased (Sec. 9)
 };
 
 struct Stats {
@@ -131,10 +132,22 @@ struct Table {
   // Bin indices of key x (reading of Sec. 1 / Sec. 3): H distinct bins.
   // h_i(x) = floor(((a_i x + c_i) mod 2^64) * n / 2^64); a clash with an
   // earlier h_j is resolved by stepping to the next bin modulo n.
+  //
+  // Biased hashes (Sec. 9 asks how the schemes fare with them): with
+  // hash_bias = k in 1..4, a second word w = mix64(z) decides by its two low
+  // bits whether the choice is the lesser of floor(z n / 2^64) and
+  // floor(w n / 2^64) (when they are below k, so for a fraction k / 4 of the
+  // keys).  Bin b is then chosen with probability about
+  //   (1 - k/4) / n + (k/4) (2 (n - b) - 1) / n^2,
+  // from 1 + k/4 times the mean at bin 0 down to 1 - k/4 times it at the top.
   void hash(uint64_t x, uint64_t* out) const {
     for (int i = 0; i < p.H; ++i) {
       uint64_t z = a[i] * x + c[i];
       uint64_t h = scale(z, p.n);
+      if (p.hash_bias) {
+        const uint64_t w = mix64(z);
+        if ((w & 3) < p.hash_bias) h = std::min(h, scale(w, p.n));
+      }
       bool clash = true;
       while (clash) {
         clash = false;
@@ -720,6 +733,14 @@ void* ck_oracle_create(uint64_t n, int B, int H, int scheme, int ghost, int load
 }
 
 void ck_oracle_destroy(void* t) { delete (Table*)t; }
+
+// Biased hashing of level k (0: uniform, up to 4), set on an empty table.
+int ck_oracle_set_hash_bias(void* tp, uint32_t k) {
+  Table& T = *(Table*)tp;
+  if (k > 4) return -1;
+  T.p.hash_bias = k;
+  return 0;
+}
 
 // Give an empty table a stash of `entries` entries (at most kMaxStash).
 int ck_oracle_set_stash(void* tp, uint32_t entries) {

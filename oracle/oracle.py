@@ -67,6 +67,8 @@ def lib():
         L.ck_oracle_upsert_ids.argtypes = [vp, vp, vp, vp, u64, vp, vp, vp, vp]
         L.ck_oracle_export.argtypes = [vp, vp, vp, vp, vp]
         L.ck_oracle_set_stash.argtypes = [vp, ctypes.c_uint32]
+        L.ck_oracle_set_hash_bias.argtypes = [vp, ctypes.c_uint32]
+        L.ck_oracle_set_hash_bias.restype = ctypes.c_int
         L.ck_oracle_set_stash.restype = ctypes.c_int
         L.ck_oracle_export_stash.argtypes = [vp, vp, vp]
         L.ck_oracle_import_stash.argtypes = [vp, vp, vp]
@@ -88,7 +90,7 @@ class OracleTable:
 
     def __init__(self, bins, slots_per_bin=4, d=2, scheme="random_walk", ghost=False,
                  load_balance=False, max_chain=500, max_search=500, max_rounds=0,
-                 batch_ops=1, hash_seed=0, rng_seed=0, stash=0):
+                 batch_ops=1, hash_seed=0, rng_seed=0, stash=0, hash_bias=0):
         self.n, self.B, self.H = int(bins), int(slots_per_bin), int(d)
         self.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
         self._t = lib().ck_oracle_create(self.n, self.B, self.H, self.scheme, int(ghost),
@@ -99,6 +101,9 @@ class OracleTable:
         self.stash = int(stash)
         if self.stash and lib().ck_oracle_set_stash(self._t, self.stash) != 0:
             raise ValueError("oracle rejected the stash size")
+        self.hash_bias = int(hash_bias)
+        if self.hash_bias and lib().ck_oracle_set_hash_bias(self._t, self.hash_bias) != 0:
+            raise ValueError("oracle rejected the hash bias")
 
     def __del__(self):
         if getattr(self, "_t", None):

@@ -176,6 +176,9 @@ void free_scratch(ck_table* t) {
   (void)hipFree(t->wg_views);
   (void)hipFree(t->dstats);
   (void)hipFree(t->block_tmp);
+  (void)hipFree(t->g.stash);
+  (void)hipFree(t->g.stash_owner);
+  (void)hipFree(t->g.stash_cnt);
 }
 
 ck_status alloc_scratch(ck_table* t) {
@@ -226,6 +229,13 @@ ck_status alloc_scratch(ck_table* t) {
   HIP_TRY(hipMemset(t->dstats, 0, sizeof(DevStats)));
   const uint32_t nb = (m + 1023) / 1024;
   HIP_TRY(dalloc(&t->block_tmp, ((nb + 63) & ~63u) + 16));
+  // the stash: entries, their claim words, and a count per table
+  if (t->g.stash_n) {
+    const size_t ns = (size_t)t->g.stash_tables * t->g.stash_n;
+    HIP_TRY(dalloc(&t->g.stash, ns));
+    HIP_TRY(dalloc(&t->g.stash_owner, ns));
+    HIP_TRY(dalloc(&t->g.stash_cnt, t->g.stash_tables));
+  }
   return CK_OK;
 }
 
@@ -324,6 +334,9 @@ ck_status enqueue_rounds(ck_table* t, Flight& f, uint32_t K, bool first, const u
     ++t->epoch;
     if (t->epoch == 0) {  // claim tags wrapped: reset every claim word
       HIP_TRY(hipMemsetAsync(t->g.owner, 0xFF, (size_t)t->bins * 8, s));
+      if (t->g.stash_n)
+        HIP_TRY(hipMemsetAsync(t->g.stash_owner, 0xFF,
+                               (size_t)t->g.stash_tables * t->g.stash_n * 8, s));
       t->epoch = 1;
     }
     r.tag = (unsigned long long)(~t->epoch) << 32;
@@ -482,7 +495,7 @@ ck_status ck_storage_bytes(uint64_t bins, uint32_t B, uint32_t d, size_t* out) {
 
 static ck_status create_table(uint64_t bins, uint32_t B, uint32_t d, ck_scheme scheme,
                               const ck_options* opt, void* storage, size_t bytes, void* stream,
-                              ck_table** out);
+                              ck_table** out, uint32_t n_tables = 1);
 
 ck_status ck_create(uint64_t bins, uint32_t B, uint32_t d, ck_scheme scheme,
                     const ck_options* opt, void* storage, size_t bytes, void* stream,
@@ -493,7 +506,7 @@ ck_status ck_create(uint64_t bins, uint32_t B, uint32_t d, ck_scheme scheme,
 
 static ck_status create_table(uint64_t bins, uint32_t B, uint32_t d, ck_scheme scheme,
                               const ck_options* opt, void* storage, size_t bytes, void* stream,
-                              ck_table** out) {
+                              ck_table** out, uint32_t n_tables) {
   *out = nullptr;
   ck_options o;
   ck_default_options(&o);
@@ -505,6 +518,7 @@ static ck_status create_table(uint64_t bins, uint32_t B, uint32_t d, ck_scheme s
   if (o.load_balance && d != 2) return CK_EINVAL;
   if (o.batch_ops == 0 || o.batch_ops > (1u << 26)) return CK_EINVAL;
   if (o.max_chain > 2048 || o.max_search > 1024 || o.max_search < d) return CK_EINVAL;
+  if (o.stash > kMaxStash) return CK_EINVAL;
   if (((uintptr_t)storage & 255) != 0) return CK_EINVAL;
   const Layout L = layout(bins, B);
   if (bytes < L.total) return CK_ENOMEM;
@@ -533,6 +547,8 @@ static ck_status create_table(uint64_t bins, uint32_t B, uint32_t d, ck_scheme s
   t->g.max_chain = o.max_chain;
   t->g.max_search = o.max_search;
   t->g.rng_seed = o.rng_seed;
+  t->g.stash_n = o.stash;
+  t->g.stash_tables = n_tables;
   ck_status st = alloc_scratch(t);
   if (st != CK_OK) {
     free_scratch(t);
@@ -636,7 +652,7 @@ static DevStatLine stats_sum(const DevStats& ds) {
   std::memset(&d, 0, sizeof(d));
   for (int k = 0; k < kStatStripes; ++k) {
     const DevStatLine& x = ds.s[k];
-    for (int j = 0; j < 19; ++j)
+    for (int j = 0; j < S_NUM; ++j)
       d.v[j] = j == S_MAX_KICKS ? std::max(d.v[j], x.v[j]) : d.v[j] + x.v[j];
     for (int a = 0; a < 4; ++a)
       for (int b = 0; b < CK_BANDS; ++b) d.band[a][b] += x.band[a][b];
@@ -678,6 +694,7 @@ ck_status ck_stats_get(ck_table* t, ck_stats* out, void* stream) {
     out->band_fails[b] = d.band[3][b];
   }
   out->arena_moves = t->arena_cap;
+  out->inserts_stashed = d.v[S_INS_STASHED];
   return CK_OK;
 }
 
@@ -778,11 +795,68 @@ ck_status ck_import(ck_table* t, const uint64_t* keys, const uint64_t* vals,
   HIP_TRY(hipMemcpyAsync(t->g.slots, buf.data(), S * 16, hipMemcpyHostToDevice, (hipStream_t)stream));
   HIP_TRY(hipMemcpyAsync(t->g.meta, meta, t->bins * 4, hipMemcpyHostToDevice, (hipStream_t)stream));
   HIP_TRY(hipMemsetAsync(t->g.owner, 0xFF, t->bins * 8, (hipStream_t)stream));
+  std::vector<ulonglong2> empty_stash;
+  if (t->g.stash_n) {  // the image has no stash: emptied here, ck_import_stash fills it
+    const size_t ns = (size_t)t->g.stash_tables * t->g.stash_n;
+    empty_stash.assign(ns, make_ulonglong2(kEmpty, 0ull));
+    HIP_TRY(hipMemcpyAsync(t->g.stash, empty_stash.data(), ns * 16, hipMemcpyHostToDevice,
+                           (hipStream_t)stream));
+    HIP_TRY(hipMemsetAsync(t->g.stash_owner, 0xFF, ns * 8, (hipStream_t)stream));
+    HIP_TRY(hipMemsetAsync(t->g.stash_cnt, 0, (size_t)t->g.stash_tables * 4,
+                           (hipStream_t)stream));
+  }
   // the table's count goes to the first copy, the other copies' counts are zeroed
   const unsigned long long stored[2] = {single + dups / 2, 0};
   for (int k = 0; k < kStatStripes; ++k)
     HIP_TRY(hipMemcpyAsync(&t->dstats->s[k].v[S_STORED], &stored[k == 0 ? 0 : 1], 8,
                            hipMemcpyHostToDevice, (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  return CK_OK;
+}
+
+// Stash entries [first, first + stash_n) to or from host memory.
+static ck_status stash_export(ck_table* t, uint32_t table, uint64_t* keys, uint64_t* vals,
+                              void* stream) {
+  const uint32_t S = t->g.stash_n;
+  if (!S || !keys || !vals || table >= t->g.stash_tables) return CK_EINVAL;
+  std::vector<ulonglong2> buf(S);
+  HIP_TRY(hipMemcpyAsync(buf.data(), t->g.stash + (size_t)table * S, S * 16,
+                         hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  for (uint32_t j = 0; j < S; ++j) {
+    keys[j] = buf[j].x;
+    vals[j] = buf[j].y;
+  }
+  return CK_OK;
+}
+
+ck_status ck_export_stash(ck_table* t, uint64_t* keys, uint64_t* vals, void* stream) {
+  if (!t) return CK_EINVAL;
+  return stash_export(t, 0, keys, vals, stream);
+}
+
+ck_status ck_import_stash(ck_table* t, const uint64_t* keys, const uint64_t* vals,
+                          void* stream) {
+  if (!t || !keys || !vals || !t->g.stash_n) return CK_EINVAL;
+  const uint32_t S = t->g.stash_n;
+  std::vector<ulonglong2> buf(S);
+  uint32_t used = 0;
+  for (uint32_t j = 0; j < S; ++j) {
+    buf[j].x = keys[j];
+    buf[j].y = t->B == 1 ? (vals[j] & 0xFFFFFFFFull) : vals[j];
+    used += keys[j] != kEmpty;
+  }
+  std::vector<DevStats> dv(1);
+  HIP_TRY(hipMemcpyAsync(dv.data(), t->dstats, sizeof(DevStats), hipMemcpyDeviceToHost,
+                         (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  const unsigned long long stored = dv[0].s[0].v[S_STORED] + used;
+  HIP_TRY(hipMemcpyAsync(t->g.stash, buf.data(), S * 16, hipMemcpyHostToDevice,
+                         (hipStream_t)stream));
+  HIP_TRY(hipMemsetAsync(t->g.stash_owner, 0xFF, (size_t)S * 8, (hipStream_t)stream));
+  HIP_TRY(hipMemcpyAsync(t->g.stash_cnt, &used, 4, hipMemcpyHostToDevice, (hipStream_t)stream));
+  HIP_TRY(hipMemcpyAsync(&t->dstats->s[0].v[S_STORED], &stored, 8, hipMemcpyHostToDevice,
+                         (hipStream_t)stream));
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
   return CK_OK;
 }
@@ -852,7 +926,7 @@ ck_status ck_group_create(uint32_t n_tables, const uint64_t* bins, uint32_t B, u
   *out = nullptr;
   ck_group* G = new (std::nothrow) ck_group();
   if (!G) return CK_ENOMEM;
-  ck_status st = create_table(total, B, d, scheme, opt, storage, bytes, stream, &G->t);
+  ck_status st = create_table(total, B, d, scheme, opt, storage, bytes, stream, &G->t, n_tables);
   if (st != CK_OK) {
     delete G;
     return st;
@@ -929,6 +1003,12 @@ ck_status ck_group_upsert(ck_group* G, const uint32_t* d_table, const uint64_t* 
   if (!d_table || !keys || !vals || !status) return CK_EINVAL;
   return run_batches(G->t, keys, vals, n, status, views, kicks, retries, false,
                      (hipStream_t)stream, d_table, G->d_tdesc, false, true);
+}
+
+ck_status ck_group_export_stash(ck_group* G, uint32_t table, uint64_t* keys, uint64_t* vals,
+                                void* stream) {
+  if (!G) return CK_EINVAL;
+  return stash_export(G->t, table, keys, vals, stream);
 }
 
 ck_status ck_group_export_table(ck_group* G, uint32_t table, uint64_t* keys, uint64_t* vals,

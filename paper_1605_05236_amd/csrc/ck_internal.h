@@ -49,7 +49,9 @@ struct IMove {           // 8 bytes
   uint32_t sf;           // slot | flags << 8
 };
 
-enum : uint32_t { PL_FAIL = 0, PL_OK = 1, PL_EVICT = 2, PL_NOTFOUND = 3, PL_UPDATED = 4 };
+enum : uint32_t {
+  PL_FAIL = 0, PL_OK = 1, PL_EVICT = 2, PL_NOTFOUND = 3, PL_UPDATED = 4, PL_STASHED = 5
+};
 
 // Plan of one op of the sub-batch (32 bytes, one load in the commit kernel).
 // Plans of at most three moves that write only the op's own record keep them
@@ -72,6 +74,10 @@ constexpr uint32_t kHdrArena = 1u << 28;
 // Upsert of an absent key: the plan also holds a claim on the key's first bin
 // (which it may not write), so that two upserts of one new key conflict.
 constexpr uint32_t kHdrKeyClaim = 1u << 29;
+// The plan writes one stash entry, whose index (in the stash array of every
+// table) is the header's fourth word; it claims that entry like a bin.
+constexpr uint32_t kHdrStash = 1u << 30;
+constexpr uint32_t kMaxStash = 64;  // stash entries per table
 constexpr uint32_t kExtraInline = 2;  // inline moves beyond the first, per op
 
 // Lanes per op in the fresh planner: each lane holds B / lanes consecutive
@@ -115,18 +121,19 @@ struct Ctr {             // device counters of the round loop
 // of a statistics or lookup launch spread over separate lines instead of
 // serialising on one; readers sum the copies (`stored` included).
 constexpr int kStatStripes = 16;
+enum {
+  S_INS_OK, S_INS_FAIL, S_INS_ABORT, S_INS_BAD, S_VIEWS, S_VIEWS_ALL, S_KICKS, S_MAX_KICKS,
+  S_RETRIES, S_ROUNDS, S_TWINS, S_LOOKUPS, S_LOOKUP_HITS, S_LOOKUP_PROBES, S_DELETES,
+  S_DEL_FOUND, S_DEL_PROBES, S_DEL_RETRIES, S_STORED, S_INS_STASHED,
+  S_NUM  // the number of scalar counters
+};
 struct DevStatLine {
-  unsigned long long v[19];
-  unsigned long long pad[13];  // 256 bytes
+  unsigned long long v[S_NUM];
+  unsigned long long pad[32 - S_NUM];  // 256 bytes
   unsigned long long band[4][CK_BANDS];
 };
 struct DevStats {
   DevStatLine s[kStatStripes];
-};
-enum {
-  S_INS_OK, S_INS_FAIL, S_INS_ABORT, S_INS_BAD, S_VIEWS, S_VIEWS_ALL, S_KICKS, S_MAX_KICKS,
-  S_RETRIES, S_ROUNDS, S_TWINS, S_LOOKUPS, S_LOOKUP_HITS, S_LOOKUP_PROBES, S_DELETES,
-  S_DEL_FOUND, S_DEL_PROBES, S_DEL_RETRIES, S_STORED
 };
 
 // A table's bin range inside the bin array (a group of tables shares one).
@@ -144,6 +151,13 @@ struct Geo {
   uint32_t B, H, scheme;
   uint32_t ghost, balance, max_chain, max_search;
   uint64_t rng_seed;
+  // the stash (Sec. 2): stash_n entries per table, table t's at t * stash_n;
+  // a claim word per entry and a count of used entries per table
+  ulonglong2* stash;
+  unsigned long long* stash_owner;
+  uint32_t* stash_cnt;
+  uint32_t stash_n;
+  uint32_t stash_tables;
 };
 
 // Round-scratch pointers of one sub-batch.

@@ -125,6 +125,29 @@ __device__ __forceinline__ Tab tab_of(const Geo& g, const uint32_t* op_table, co
   return Tab{0u, g.n};
 }
 
+// ---------------------------------------------------------------------------
+// the stash (Sec. 2): stash_n entries per table, searched after the bins
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t table_of(const uint32_t* op_table, uint64_t i) {
+  return op_table ? op_table[i] : 0u;
+}
+
+// The entry of table t's stash that holds key x (not the empty key), or
+// kNone.  A group of W lanes searches it together: lane gl reads entries
+// gl, gl + W, ...; `vote` gives the group's ballot, bit k for its lane k.
+template <class Vote>
+__device__ __forceinline__ uint32_t stash_find(const Geo& g, uint32_t t, uint64_t x, int gl,
+                                               int W, Vote vote) {
+  if (g.stash_cnt[t] == 0) return kNone;
+  const uint32_t sb = t * g.stash_n;
+  for (uint32_t c = 0; c < g.stash_n; c += (uint32_t)W) {
+    const uint64_t k = c + gl < g.stash_n ? g.stash[sb + c + gl].x : kEmpty;
+    const uint64_t m = vote(k == x);
+    if (m) return sb + c + (uint32_t)(__ffsll((unsigned long long)m) - 1);
+  }
+  return kNone;
+}
+
 // Uniform choice in [0, m): draw t of op `op`; m == 1 consumes no draw.
 __device__ __forceinline__ uint32_t uniform_choice(const Geo& g, uint64_t op, uint32_t& draws,
                                                    uint32_t m) {
@@ -158,6 +181,14 @@ __global__ void k_init(Geo g) {
     g.meta[i] = 0u;
     g.owner[i] = ~0ull;
   }
+  const uint64_t nstash = (uint64_t)g.stash_tables * g.stash_n;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nstash; i += stride) {
+    g.stash[i] = make_ulonglong2(kEmpty, 0ull);
+    g.stash_owner[i] = ~0ull;
+  }
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+       i < (nstash ? g.stash_tables : 0u); i += stride)
+    g.stash_cnt[i] = 0u;
 }
 
 hipError_t launch_init(const Geo& g, hipStream_t s) {
@@ -251,6 +282,17 @@ __global__ __launch_bounds__(256) void k_lookup(Geo g, const uint64_t* __restric
           }
           hit = true;
           break;
+        }
+      }
+      if (!hit && g.stash_n) {  // then the stash, one more probe
+        ++probes;
+        const uint32_t e = stash_find(g, table_of(op_table, q), x, gl, LPP, [&](bool p) {
+          return (uint64_t)((__ballot(p) >> gshift) & gmask);
+        });
+        if (e != kNone) {
+          hit = true;
+          winner = 0;
+          val = g.stash[e].y;
         }
       }
     }
@@ -354,6 +396,22 @@ __device__ __forceinline__ void claim(const Geo& g, const Round& r, uint32_t bin
   atomicMin(&g.owner[bin], r.tag | (unsigned long long)i);
 }
 
+// A failed insert's key goes to the first free entry of its table's stash
+// (in the round's snapshot), if there is one; the entry is claimed like a bin.
+// Returns the entry's index in the stash array, or kNone.  One lane.
+__device__ uint32_t stash_take(const Geo& g, const Round& r, uint32_t i) {
+  if (g.stash_n == 0) return kNone;
+  const uint32_t t = table_of(r.op_table, i);
+  if (g.stash_cnt[t] >= g.stash_n) return kNone;
+  const uint32_t sb = t * g.stash_n;
+  for (uint32_t j = 0; j < g.stash_n; ++j)
+    if (g.stash[sb + j].x == kEmpty) {
+      atomicMin(&g.stash_owner[sb + j], r.tag | (unsigned long long)i);
+      return sb + j;
+    }
+  return kNone;
+}
+
 // ---------------------------------------------------------------------------
 // k_plan_fresh: B lanes per op, placement without eviction
 // ---------------------------------------------------------------------------
@@ -431,7 +489,7 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
     // one new key in a round the later one loses and then finds the key.
     const bool ups = r.upsert && active && !bad;
     bool updated = false;
-    uint32_t key_bin = 0;
+    uint32_t key_bin = 0, stash_e = kNone;
     if (ups) {
       uint32_t h[H];
       hash_key<H>(g, T, x, h);
@@ -453,6 +511,14 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
           views = (uint32_t)hi + 1;
           updated = true;
           break;
+        }
+      }
+      if (!updated && g.stash_n) {  // then the stash, one more view
+        stash_e = stash_find(g, table_of(r.op_table, i), x, G.sl, L,
+                             [&](bool p) { return (uint64_t)G.ballot(p); });
+        if (stash_e != kNone) {
+          views = (uint32_t)H + 1;
+          updated = true;
         }
       }
     }
@@ -538,10 +604,13 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
     }
     if (active && leader) {
       const bool key_claim = ups && !updated;
+      const bool in_stash = stash_e != kNone;
       const uint32_t st = bad ? PL_FAIL : (updated ? PL_UPDATED : (placed ? PL_OK : PL_EVICT));
-      ((uint4*)r.hdr)[2 * (size_t)i] =
-          make_uint4(hdr_pack(st, twins, nm) | (key_claim ? kHdrKeyClaim : 0u),
-                     views + (key_claim ? (uint32_t)H : 0u), b0, f0);
+      ((uint4*)r.hdr)[2 * (size_t)i] = make_uint4(
+          hdr_pack(st, twins, nm) | (key_claim ? kHdrKeyClaim : 0u) | (in_stash ? kHdrStash : 0u),
+          views + (key_claim ? (uint32_t)H + (g.stash_n ? 1u : 0u) : 0u), b0,
+          in_stash ? stash_e : f0);
+      if (in_stash) atomicMin(&g.stash_owner[stash_e], r.tag | (unsigned long long)i);
       if (placed || updated) {
         if (nm > 0) claim(g, r, b0, i);
         if (nm > 1) {
@@ -930,14 +999,16 @@ struct WalkPlanner {
       }
     }
     if (gl == 0) {
+      // a failed chain's key goes to the stash if it has room
+      const uint32_t se = status == PL_FAIL ? stash_take(g, r, i) : kNone;
       PlanHdr hd{};
       // an upsert's plan adds the presence check's views and its key claim
       // (made by the fresh planner)
-      hd.st = hdr_pack(status, status == PL_OK ? twins : 0, nm) | kHdrArena |
-              (r.upsert ? kHdrKeyClaim : 0u);
-      hd.views = views + (r.upsert ? (uint32_t)H : 0u);
+      hd.st = hdr_pack(se != kNone ? PL_STASHED : status, status == PL_OK ? twins : 0, nm) |
+              kHdrArena | (r.upsert ? kHdrKeyClaim : 0u) | (se != kNone ? kHdrStash : 0u);
+      hd.views = views + (r.upsert ? (uint32_t)H + (g.stash_n ? 1u : 0u) : 0u);
       hd.a = off;
-      hd.b = status == PL_OK ? kicks : 0;
+      hd.b = status == PL_OK ? kicks : (se != kNone ? se : 0u);
       hd.n_spawn = 0;
       hd.spawn_off = 0;
       r.hdr[i] = hd;
@@ -1717,12 +1788,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       }
     }
     if (have && gl == 0) {
+      // a failed search's key goes to the stash if it has room
+      const uint32_t se = found ? kNone : stash_take(g, r, i);
       PlanHdr hd{};
-      hd.st = hdr_pack(found ? PL_OK : PL_FAIL, twin, nm) | kHdrArena |
-              (r.upsert ? kHdrKeyClaim : 0u);
-      hd.views = views + (r.upsert ? (uint32_t)H : 0u);
+      hd.st = hdr_pack(found ? PL_OK : (se != kNone ? PL_STASHED : PL_FAIL), twin, nm) |
+              kHdrArena | (r.upsert ? kHdrKeyClaim : 0u) | (se != kNone ? kHdrStash : 0u);
+      hd.views = views + (r.upsert ? (uint32_t)H + (g.stash_n ? 1u : 0u) : 0u);
       hd.a = off;
-      hd.b = found ? depth : 0;
+      hd.b = found ? depth : (se != kNone ? se : 0u);
       hd.n_spawn = nsp;
       hd.spawn_off = soff;
       r.hdr[i] = hd;
@@ -1840,7 +1913,7 @@ __device__ __forceinline__ void delete_one(const Geo& g, const Round& r, const G
   const uint64_t x = r.keys[i];
   const bool leader = G.sl == 0;
   uint32_t mb[2], ms[2];
-  uint32_t nm = 0, probes = 0;
+  uint32_t nm = 0, probes = 0, se = kNone;
   uint32_t status = PL_NOTFOUND;
   if (x != kEmpty) {
     uint32_t h[H];
@@ -1868,12 +1941,19 @@ __device__ __forceinline__ void delete_one(const Geo& g, const Round& r, const G
         break;
       }
     }
+    if (status == PL_NOTFOUND && g.stash_n) {  // then the stash, one more probe
+      ++probes;
+      se = stash_find(g, table_of(r.op_table, i), x, G.sl, B,
+                      [&](bool p) { return (uint64_t)G.ballot(p); });
+      if (se != kNone) status = PL_OK;
+    }
   }
   if (!leader) return;
   const uint32_t fl = r.overwrite ? MV_VALUE : MV_CLEAR;
-  ((uint4*)r.hdr)[2 * (size_t)i] =
-      make_uint4(hdr_pack(x == kEmpty ? PL_FAIL : status, 0, nm), probes, nm > 0 ? mb[0] : 0u,
-                 nm > 0 ? (ms[0] | (fl << 8)) : 0u);
+  ((uint4*)r.hdr)[2 * (size_t)i] = make_uint4(
+      hdr_pack(x == kEmpty ? PL_FAIL : status, 0, nm) | (se != kNone ? kHdrStash : 0u), probes,
+      nm > 0 ? mb[0] : 0u, nm > 0 ? (ms[0] | (fl << 8)) : (se != kNone ? se : 0u));
+  if (se != kNone) atomicMin(&g.stash_owner[se], r.tag | (unsigned long long)i);
   if (nm > 0) claim(g, r, mb[0], i);
   if (nm > 1) {
     r.imv[(size_t)i * kExtraInline] = IMove{mb[1], ms[1] | (fl << 8)};
@@ -1951,7 +2031,7 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
     const uint32_t i = P.at(pos);
     // ---- decide ----
     uint32_t status = 0, twins = 0, nmv = 0, views = 0, off = 0, mv0_sf = 0, kicks = 0;
-    uint32_t n_spawn = 0, spawn_off = 0, lost = 0, retries = 0;
+    uint32_t n_spawn = 0, spawn_off = 0, lost = 0, retries = 0, se = kNone;
     uint64_t x = 0, xa = 0;
     bool live = false, inl = true, win = false, requeue = false, abort = false;
     // move j of the plan: bin, slot, flags and the record it writes
@@ -1993,14 +2073,15 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
         views = h0.y;
         off = h0.z;  // inline: the first move's bin; arena: the moves' offset
         mv0_sf = h0.w;
-        kicks = inl ? 0u : h0.w;
+        se = (h0.x & kHdrStash) ? h0.w : kNone;  // the stash entry the plan writes
+        kicks = (inl || se != kNone) ? 0u : h0.w;
         if (!inl) {
           const uint4 h1 = ((const uint4*)r.hdr)[2 * (size_t)i + 1];
           n_spawn = h1.x;
           spawn_off = h1.y;
         }
         x = r.keys[i];
-        xa = (inl && r.vals) ? load_aux(r.vals, i, g.B) : 0;
+        xa = ((inl || se != kNone) && r.vals) ? load_aux(r.vals, i, g.B) : 0;
         const unsigned long long me = r.tag | (unsigned long long)i;
         bool mine = true;
         for (uint32_t j = gl; j < nmv; j += CL) {
@@ -2014,6 +2095,7 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
           hash_key<1>(g, tab_of(g, r.op_table, r.tdesc, i), x, kb);
           if (g.owner[kb[0]] != me) mine = false;
         }
+        if (se != kNone && leader && g.stash_owner[se] != me) mine = false;
         win = ((__ballot(!mine) >> gshift) & ((1ull << CL) - 1)) == 0;
         if (!win && leader) {
           lost = r.op_lost[i] + views;
@@ -2060,12 +2142,26 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
           }
           if (fl & MV_HC) atomicAdd(mw, 1u << 24);
         }
+        if (se != kNone && leader) {  // the stash entry: cleared, a new value, or the key
+          ulonglong2* e = g.stash + se;
+          uint32_t* cnt = g.stash_cnt + se / g.stash_n;
+          if (r.is_delete && !r.overwrite) {
+            *e = make_ulonglong2(kEmpty, 0ull);
+            atomicSub(cnt, 1u);
+          } else if (r.is_delete || status == PL_UPDATED) {
+            e->y = xa;
+          } else {
+            *e = make_ulonglong2(x, xa);
+            atomicAdd(cnt, 1u);
+          }
+        }
         if (leader) {
           uint8_t st;
           if (x == kEmpty) st = CK_OP_BAD_KEY;
           else if (r.is_delete) st = status == PL_OK ? CK_OP_OK : CK_OP_NOT_FOUND;
           else if (status == PL_OK) st = CK_OP_OK;
-          else st = status == PL_UPDATED ? CK_OP_UPDATED : CK_OP_FAIL_CHAIN;
+          else if (status == PL_UPDATED) st = CK_OP_UPDATED;
+          else st = status == PL_STASHED ? CK_OP_STASHED : CK_OP_FAIL_CHAIN;
           r.status[i] = st;
           r.op_views[i] = views;
           if (kicks) r.op_kicks[i] = kicks;
@@ -2149,7 +2245,8 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_count(const uint8_t* statu
   uint32_t n = 0;
   for (uint32_t tile = t0; tile < t1; ++tile) {
     const uint64_t i = (uint64_t)tile * kStatBlock + threadIdx.x;
-    n += (i < m && status[i] == CK_OP_OK) ? 1u : 0u;
+    // every key the sub-batch adds to the table, placed or stashed
+    n += (i < m && (status[i] == CK_OP_OK || status[i] == CK_OP_STASHED)) ? 1u : 0u;
   }
   if (stats_closed_out(open, gate, unfinished, true)) return;
   n = (uint32_t)wave_sum(n);
@@ -2204,12 +2301,12 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
   if (t0 < t1) fetch(t0);
   if (stats_closed_out(open, gate, nullptr, false)) return;
   __shared__ unsigned long long hb[4][CK_BANDS];
-  __shared__ unsigned long long tot[11];
+  __shared__ unsigned long long tot[12];
   __shared__ uint32_t wsum[kStatBlock / 64];
   __shared__ uint64_t s_rank0;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int j = threadIdx.x; j < 4 * CK_BANDS; j += kStatBlock) hb[j / CK_BANDS][j % CK_BANDS] = 0;
-  if (threadIdx.x < 11) tot[threadIdx.x] = 0;
+  if (threadIdx.x < 12) tot[threadIdx.x] = 0;
   // successful inserts of the earlier workgroups (one wavefront sums them)
   if (wv == 0) {
     unsigned long long pre = 0;
@@ -2219,7 +2316,7 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
   }
   __syncthreads();
   unsigned long long a_ok = 0, a_fail = 0, a_abort = 0, a_bad = 0, a_views = 0, a_vall = 0,
-                     a_kicks = 0, a_maxk = 0, a_ret = 0, a_tw = 0;
+                     a_kicks = 0, a_maxk = 0, a_ret = 0, a_tw = 0, a_stash = 0;
   // per-lane sums of the current band, added to the workgroup histogram when
   // the band changes and at the end
   uint32_t cb = kNone;
@@ -2254,7 +2351,8 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
       if (tb + q >= t1) break;  // uniform
       const uint8_t s = sv[q];
       const bool ok = s == CK_OP_OK;
-      const uint64_t bal = __ballot(ok);
+      // the rank counts every key held: placed or stashed
+      const uint64_t bal = __ballot(ok || s == CK_OP_STASHED);
       const uint32_t before_in_wave = __popcll(bal & ((1ull << lane) - 1));
       if (lane == 0) wsum[wv] = __popcll(bal);
       __syncthreads();
@@ -2287,6 +2385,8 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
               a_kicks += o_kicks[q];
               a_maxk = o_kicks[q] > a_maxk ? o_kicks[q] : a_maxk;
               a_tw += o_twins[q];
+            } else if (s == CK_OP_STASHED) {  // a failed chain all the same
+              a_stash += 1;
             } else {
               a_fail += 1;
             }
@@ -2310,25 +2410,26 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_apply(
   a_ok = wave_sum(a_ok); a_fail = wave_sum(a_fail); a_abort = wave_sum(a_abort);
   a_bad = wave_sum(a_bad); a_views = wave_sum(a_views); a_vall = wave_sum(a_vall);
   a_kicks = wave_sum(a_kicks); a_maxk = wave_max(a_maxk); a_ret = wave_sum(a_ret);
-  a_tw = wave_sum(a_tw);
+  a_tw = wave_sum(a_tw); a_stash = wave_sum(a_stash);
   if (lane == 0) {
     atomicAdd(&tot[0], a_ok); atomicAdd(&tot[1], a_fail); atomicAdd(&tot[2], a_abort);
     atomicAdd(&tot[3], a_bad); atomicAdd(&tot[4], a_views); atomicAdd(&tot[5], a_vall);
     atomicAdd(&tot[6], a_kicks); atomicMax(&tot[7], a_maxk); atomicAdd(&tot[8], a_ret);
-    atomicAdd(&tot[9], a_tw);
+    atomicAdd(&tot[9], a_tw); atomicAdd(&tot[10], a_stash);
   }
   __syncthreads();
   DevStatLine& sl = st->s[blockIdx.x % kStatStripes];
-  if (threadIdx.x < 10) {
-    const int map[10] = {S_INS_OK, S_INS_FAIL, S_INS_ABORT, S_INS_BAD, S_VIEWS,
-                         S_VIEWS_ALL, S_KICKS, S_MAX_KICKS, S_RETRIES, S_TWINS};
+  if (threadIdx.x < 11) {
+    const int map[11] = {S_INS_OK, S_INS_FAIL, S_INS_ABORT, S_INS_BAD, S_VIEWS,
+                         S_VIEWS_ALL, S_KICKS, S_MAX_KICKS, S_RETRIES, S_TWINS,
+                         S_INS_STASHED};
     const int j = threadIdx.x;
     if (tot[j]) {
       if (j == 7) atomicMax(&sl.v[S_MAX_KICKS], tot[j]);
       else atomicAdd(&sl.v[map[j]], tot[j]);
     }
-    // `stored` grows by this workgroup's successful inserts
-    if (j == 0 && tot[0]) atomicAdd(&sl.v[S_STORED], tot[0]);
+    // `stored` grows by this workgroup's successful inserts, placed or stashed
+    if (j == 0 && tot[0] + tot[10]) atomicAdd(&sl.v[S_STORED], tot[0] + tot[10]);
   }
   for (int j = threadIdx.x; j < 4 * CK_BANDS; j += kStatBlock) {
     const unsigned long long v = hb[j / CK_BANDS][j % CK_BANDS];

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libck.so")
 
 SCHEMES = {"random_walk": 0, "bfs": 1, "sorted": 2, "queue": 3, "rattle": 4, "hybrid": 5}
-OP_NOT_FOUND, OP_OK, OP_FAIL_CHAIN, OP_ABORTED, OP_BAD_KEY, OP_UPDATED = range(6)
+OP_NOT_FOUND, OP_OK, OP_FAIL_CHAIN, OP_ABORTED, OP_BAD_KEY, OP_UPDATED, OP_STASHED = range(7)
 BANDS = 200
 EMPTY_KEY = 0xFFFFFFFFFFFFFFFF
 
@@ -31,14 +31,15 @@ class CkOptions(ctypes.Structure):
                 ("max_chain", ctypes.c_uint32), ("max_search", ctypes.c_uint32),
                 ("max_rounds", ctypes.c_uint32), ("batch_ops", ctypes.c_uint32),
                 ("hash_seed", ctypes.c_uint64), ("rng_seed", ctypes.c_uint64),
-                ("evict_wgs_per_cu", ctypes.c_uint32), ("enqueue_rounds", ctypes.c_uint32)]
+                ("evict_wgs_per_cu", ctypes.c_uint32), ("enqueue_rounds", ctypes.c_uint32),
+                ("stash", ctypes.c_uint32)]
 
 
 class CkStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in _SCALARS] + [
         ("band_inserts", ctypes.c_uint64 * BANDS), ("band_views", ctypes.c_uint64 * BANDS),
         ("band_kicks", ctypes.c_uint64 * BANDS), ("band_fails", ctypes.c_uint64 * BANDS),
-        ("arena_moves", ctypes.c_uint64)]
+        ("arena_moves", ctypes.c_uint64), ("inserts_stashed", ctypes.c_uint64)]
 
 
 class CkKernelTime(ctypes.Structure):
@@ -70,7 +71,8 @@ _lib = None
 
 EXPORTED = ["ck_default_options", "ck_storage_bytes", "ck_create", "ck_clear", "ck_insert", "ck_insert_ex",
             "ck_lookup", "ck_lookup_lpp", "ck_delete", "ck_overwrite", "ck_upsert",
-            "ck_stats_get", "ck_stats_reset",
+            "ck_stats_get", "ck_stats_reset", "ck_export_stash", "ck_import_stash",
+            "ck_group_export_stash",
             "ck_export", "ck_import", "ck_hash", "ck_insert_count", "ck_destroy", "ck_strerror",
             "ck_timing_enable", "ck_timing_get", "ck_group_storage_bytes", "ck_group_create",
             "ck_group_insert", "ck_group_lookup", "ck_group_delete", "ck_group_overwrite",
@@ -102,6 +104,9 @@ def load_library(path: str = LIB_PATH):
     L.ck_delete.argtypes = [vp, vp, u64, vp, vp]
     L.ck_overwrite.argtypes = [vp, vp, vp, u64, vp, vp]
     L.ck_upsert.argtypes = [vp, vp, vp, u64, vp, vp, vp, vp, vp]
+    L.ck_export_stash.argtypes = [vp, vp, vp, vp]
+    L.ck_import_stash.argtypes = [vp, vp, vp, vp]
+    L.ck_group_export_stash.argtypes = [vp, u32, vp, vp, vp]
     L.ck_stats_get.argtypes = [vp, ctypes.POINTER(CkStats), vp]
     L.ck_stats_reset.argtypes = [vp, vp]
     L.ck_export.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -132,7 +137,8 @@ def load_library(path: str = LIB_PATH):
     L.ck_strerror.restype = ctypes.c_char_p
     for f in ("ck_storage_bytes", "ck_create", "ck_clear", "ck_insert", "ck_insert_ex", "ck_lookup",
               "ck_lookup_lpp", "ck_delete", "ck_overwrite", "ck_upsert", "ck_stats_get",
-              "ck_stats_reset", "ck_export",
+              "ck_stats_reset", "ck_export", "ck_export_stash", "ck_import_stash",
+              "ck_group_export_stash",
               "ck_import", "ck_hash", "ck_destroy", "ck_timing_enable", "ck_timing_get",
               "ck_group_storage_bytes", "ck_group_create", "ck_group_insert", "ck_group_lookup",
               "ck_group_delete", "ck_group_overwrite", "ck_group_upsert",
@@ -182,10 +188,11 @@ class CuckooTable:
     def __init__(self, bins, slots_per_bin=4, d=2, scheme="random_walk", ghost=False,
                  load_balance=False, max_chain=500, max_search=500, max_rounds=0,
                  batch_ops=1 << 20, hash_seed=0, rng_seed=0, device="cuda", stream=None,
-                 evict_wgs_per_cu=0, enqueue_rounds=0):
+                 evict_wgs_per_cu=0, enqueue_rounds=0, stash=0):
         import torch
         L = load_library()
         self.n, self.B, self.H = int(bins), int(slots_per_bin), int(d)
+        self.stash = int(stash)
         self.device = torch.device(device)
         self.value_dtype = torch.int32 if self.B == 1 else torch.int64
         opt = CkOptions()
@@ -194,6 +201,7 @@ class CuckooTable:
         opt.max_chain, opt.max_search, opt.max_rounds = max_chain, max_search, max_rounds
         opt.batch_ops, opt.hash_seed, opt.rng_seed = batch_ops, hash_seed, rng_seed
         opt.evict_wgs_per_cu, opt.enqueue_rounds = evict_wgs_per_cu, enqueue_rounds
+        opt.stash = self.stash
         self.storage = torch.empty(storage_bytes(self.n, self.B, self.H), dtype=torch.uint8,
                                    device=self.device)
         h = ctypes.c_void_p()
@@ -285,6 +293,7 @@ class CuckooTable:
         for f in ("band_inserts", "band_views", "band_kicks", "band_fails"):
             out[f] = np.array(list(getattr(s, f)), dtype=np.uint64)
         out["arena_moves"] = int(s.arena_moves)
+        out["inserts_stashed"] = int(s.inserts_stashed)
         return out
 
     def reset_stats(self, stream=None):
@@ -298,7 +307,12 @@ class CuckooTable:
         meta = np.zeros(self.n, np.uint32)
         c = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
         _check(self._L.ck_export(self._h, c(keys), c(vals), c(rattle), c(meta), _stream(stream)))
-        return {"keys": keys, "vals": vals, "rattle": rattle, "meta": meta}
+        img = {"keys": keys, "vals": vals, "rattle": rattle, "meta": meta}
+        if self.stash:
+            sk, sv = np.zeros(self.stash, np.uint64), np.zeros(self.stash, np.uint64)
+            _check(self._L.ck_export_stash(self._h, c(sk), c(sv), _stream(stream)))
+            img["stash_keys"], img["stash_vals"] = sk, sv
+        return img
 
     def load(self, img, stream=None):
         c = lambda a: np.ascontiguousarray(a).ctypes.data_as(ctypes.c_void_p)  # noqa: E731
@@ -307,6 +321,10 @@ class CuckooTable:
                 np.ascontiguousarray(img["rattle"], np.uint16),
                 np.ascontiguousarray(img["meta"], np.uint32)]
         _check(self._L.ck_import(self._h, *[c(a) for a in arrs], _stream(stream)))
+        if self.stash:
+            _check(self._L.ck_import_stash(
+                self._h, c(np.ascontiguousarray(img["stash_keys"], np.uint64)),
+                c(np.ascontiguousarray(img["stash_vals"], np.uint64)), _stream(stream)))
 
     def timing(self, enable=None, stream=None):
         """Enable per-kernel event timing (True = every class, or a list of
@@ -332,13 +350,14 @@ class CuckooTable:
 
 
 def _options(ghost, load_balance, max_chain, max_search, max_rounds, batch_ops, hash_seed,
-             rng_seed, evict_wgs_per_cu=0, enqueue_rounds=0):
+             rng_seed, evict_wgs_per_cu=0, enqueue_rounds=0, stash=0):
     opt = CkOptions()
     load_library().ck_default_options(ctypes.byref(opt))
     opt.ghost, opt.load_balance = int(ghost), int(load_balance)
     opt.max_chain, opt.max_search, opt.max_rounds = max_chain, max_search, max_rounds
     opt.batch_ops, opt.hash_seed, opt.rng_seed = batch_ops, hash_seed, rng_seed
     opt.evict_wgs_per_cu, opt.enqueue_rounds = evict_wgs_per_cu, enqueue_rounds
+    opt.stash = stash
     return opt
 
 
@@ -356,9 +375,10 @@ class CuckooGroup:
     def __init__(self, bins, slots_per_bin=4, d=2, scheme="queue", ghost=False,
                  load_balance=False, max_chain=500, max_search=500, max_rounds=0,
                  batch_ops=1 << 20, hash_seed=0, rng_seed=0, device="cuda", stream=None,
-                 evict_wgs_per_cu=0, enqueue_rounds=0):
+                 evict_wgs_per_cu=0, enqueue_rounds=0, stash=0):
         import torch
         L = load_library()
+        self.stash = int(stash)
         self.bins = np.ascontiguousarray(bins, dtype=np.uint64)
         self.n_tables, self.B, self.H = int(self.bins.size), int(slots_per_bin), int(d)
         self.device = torch.device(device)
@@ -368,7 +388,7 @@ class CuckooGroup:
                                         self.B, self.H, ctypes.byref(size)))
         self.storage = torch.empty(int(size.value), dtype=torch.uint8, device=self.device)
         opt = _options(ghost, load_balance, max_chain, max_search, max_rounds, batch_ops,
-                       hash_seed, rng_seed, evict_wgs_per_cu, enqueue_rounds)
+                       hash_seed, rng_seed, evict_wgs_per_cu, enqueue_rounds, self.stash)
         h = ctypes.c_void_p()
         sch = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
         _check(L.ck_group_create(self.n_tables, self.bins.ctypes.data_as(ctypes.c_void_p),
@@ -458,12 +478,20 @@ class CuckooGroup:
         c = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
         _check(self._L.ck_group_export_table(self._h, int(table), c(keys), c(vals), c(rattle),
                                              c(meta), _stream(stream)))
-        return {"keys": keys, "vals": vals, "rattle": rattle, "meta": meta}
+        img = {"keys": keys, "vals": vals, "rattle": rattle, "meta": meta}
+        if self.stash:
+            sk, sv = np.zeros(self.stash, np.uint64), np.zeros(self.stash, np.uint64)
+            _check(self._L.ck_group_export_stash(self._h, int(table), c(sk), c(sv),
+                                                 _stream(stream)))
+            img["stash_keys"], img["stash_vals"] = sk, sv
+        return img
 
     def stats(self, stream=None) -> dict:
         st = CkStats()
         _check(self._L.ck_group_stats_get(self._h, ctypes.byref(st), _stream(stream)))
-        return {n: int(getattr(st, n)) for n in _SCALARS}
+        out = {n: int(getattr(st, n)) for n in _SCALARS}
+        out["inserts_stashed"] = int(st.inserts_stashed)
+        return out
 
     def timing(self, enable=None, stream=None):
         if enable is not None:

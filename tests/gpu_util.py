@@ -54,7 +54,10 @@ def gpu_overwrite(t, keys, vals):
 
 
 def assert_same_image(a, b, what=""):
-    for f in ("keys", "vals", "rattle", "meta"):
+    assert ("stash_keys" in a) == ("stash_keys" in b), f"{what}: one image has a stash"
+    for f in ("keys", "vals", "rattle", "meta", "stash_keys", "stash_vals"):
+        if f not in b:
+            continue
         if not np.array_equal(a[f], b[f]):
             bad = np.nonzero(a[f] != b[f])[0]
             raise AssertionError(f"{what}: {f} differs at {bad.size} entries, first {bad[:8]} "

@@ -139,3 +139,53 @@ def test_group_matches_tables_alone(scheme, B, d, ghost):
         checks.check_invariants(img, int(bins[t]), B, d, 111, ghost=ghost,
                                 rattle=scheme == "rattle")
     del torch
+
+
+@pytest.mark.parametrize("scheme,B,d", [("random_walk", 4, 2), ("bfs", 2, 2), ("rattle", 1, 3)])
+def test_group_stash_per_table(scheme, B, d):
+    # Each table of a group has its own stash (Sec. 2): small tables driven
+    # past their failure load give, table by table, what the oracle gives.
+    rng = np.random.default_rng(9)
+    nt = 12
+    bins = np.maximum(inputs.log_uniform_int(6, nt, 4, 7), 8)
+    chunk = 700
+    kw = dict(max_chain=4, max_search=8, stash=4)
+    g = make_group(bins, B, d, scheme, batch_ops=chunk, **kw)
+    orc = [oracle.OracleTable(int(n), B, d, scheme, batch_ops=1 << 30, hash_seed=111,
+                              rng_seed=222, **kw) for n in bins]
+    per_table = [inputs.target_count(int(n), B, 1.05) for n in bins]
+    keys, vals, tids = [], [], []
+    start = 0
+    for t, m in enumerate(per_table):
+        k, v = inputs.keys_values(41, m, start=start, value_bits=32 if B == 1 else 64)
+        start += m
+        keys.append(k)
+        vals.append(v)
+        tids.append(np.full(m, t, np.uint32))
+    keys, vals, tids = np.concatenate(keys), np.concatenate(vals), np.concatenate(tids)
+    perm = rng.permutation(keys.size)
+    keys, vals, tids = keys[perm], vals[perm], tids[perm]
+    base = g.insert_count
+    r = g.insert(dev(tids, "u32"), dev(keys, "u64"),
+                 dev(vals & 0xFFFFFFFF, "u32") if B == 1 else dev(vals, "u64"))
+    got = {k: v.cpu().numpy().view(np.uint8 if k == "status" else np.uint32) for k, v in r.items()}
+    for c0 in range(0, keys.size, chunk):
+        c1 = min(keys.size, c0 + chunk)
+        for t in range(nt):
+            pos = np.nonzero(tids[c0:c1] == t)[0] + c0
+            if pos.size == 0:
+                continue
+            ro = orc[t].insert(keys[pos], vals[pos], op_ids=base + pos)
+            for f in ("status", "views", "kicks", "retries"):
+                assert np.array_equal(got[f][pos].astype(np.int64), ro[f].astype(np.int64)), \
+                    (scheme, t, f)
+    assert (got["status"] == oracle.ST_STASHED).sum() > 0
+    for t in range(nt):
+        assert_same_image(g.export_table(t), orc[t].export(), f"{scheme} table {t}")
+    # every key held is found, stashed ones included
+    held = np.isin(got["status"], (oracle.ST_OK, oracle.ST_STASHED))
+    v, f = g.lookup(dev(tids[held], "u32"), dev(keys[held], "u64"))
+    v = v.cpu().numpy()
+    v = v.view(np.uint32).astype(np.uint64) if B == 1 else v.view(np.uint64)
+    mask = np.uint64(0xFFFFFFFF) if B == 1 else np.uint64(0xFFFFFFFFFFFFFFFF)
+    assert f.cpu().numpy().all() and np.array_equal(v, vals[held] & mask)

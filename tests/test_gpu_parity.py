@@ -176,6 +176,73 @@ def test_upsert_repeated_new_key_parity(scheme, B):
     assert_same_stats(g.stats(), o.stats(), f"{scheme} {B}")
 
 
+STASH_GEOMS = [("random_walk", 4, 2, False), ("bfs", 4, 2, True), ("sorted", 8, 2, False),
+               ("queue", 2, 2, False), ("rattle", 1, 3, False), ("hybrid", 4, 2, False),
+               ("random_walk", 1, 4, False)]
+
+
+@pytest.mark.parametrize("geom", STASH_GEOMS, ids=ident)
+@pytest.mark.parametrize("batch", [1, 300])
+def test_stash_parity(geom, batch):
+    # Short chain caps past the failure load, so chains fail and keys go to
+    # the stash (Sec. 2) until it is full; then deletes (stashed keys
+    # included), overwrites, upserts and more inserts, which refill freed
+    # entries.  Per-op results, the image with the stash, and the counters.
+    scheme, B, d, ghost = geom
+    n = 1 << 9
+    kw = dict(ghost=ghost, max_chain=6, max_search=12, batch_ops=batch, stash=16)
+    print(f"stash parity {geom} batch={batch}", flush=True)
+    g = gpu_table(n, B, d, scheme, seed=4, **kw)
+    o = oracle_table(n, B, d, scheme, seed=4, **kw)
+    keys, vals = keys_for(n, B, 1.3, seed=15)
+    rng = np.random.default_rng(4)
+    mask = np.uint64(0xFFFFFFFF) if B == 1 else np.uint64(0xFFFFFFFFFFFFFFFF)
+    held = []
+    pos = 0
+    full = n * B
+    for step in range(5):
+        m = int(0.9 * full) if step == 0 else full // 20
+        ks, vs = keys[pos:pos + m], vals[pos:pos + m]
+        pos += m
+        rg, ro = gpu_insert(g, ks, vs), o.insert(ks, vs)
+        assert_same_ops(rg, ro, f"{geom} step {step} insert")
+        held.extend(ks[np.isin(ro["status"], (1, 6))].tolist())
+        img = o.export()
+        assert_same_image(g.export(), img, f"{geom} step {step}")
+        sk = img["stash_keys"][img["stash_keys"] != inputs.EMPTY]
+        # deletes: some stashed keys, some placed ones, and absent keys
+        pick = np.concatenate([sk[::2], np.array(held, np.uint64)[rng.integers(0, len(held), 30)],
+                               keys[-5:]])
+        fg, fo = gpu_delete(g, pick), o.delete(pick)[0]
+        assert np.array_equal(fg, fo), f"{geom} step {step} delete"
+        gone = set(pick[fo == 1].tolist())
+        held = [k for k in held if k not in gone]
+        # overwrites and upserts of stashed, placed and absent keys
+        img = o.export()
+        sk = img["stash_keys"][img["stash_keys"] != inputs.EMPTY]
+        pick = np.concatenate([sk, np.array(held, np.uint64)[rng.integers(0, len(held), 20)],
+                               keys[-8:]])
+        nv = rng.integers(0, 1 << 63, pick.size, dtype=np.uint64) & mask
+        fg, fo = gpu_overwrite(g, pick, nv), o.overwrite(pick, nv)[0]
+        assert np.array_equal(fg, fo), f"{geom} step {step} overwrite"
+        up = np.concatenate([pick[::3], keys[pos:pos + 20], keys[pos:pos + 3]])
+        pos += 20
+        uv = rng.integers(0, 1 << 63, up.size, dtype=np.uint64) & mask
+        rg, ro = gpu_upsert(g, up, uv), o.upsert(up, uv)
+        assert_same_ops(rg, ro, f"{geom} step {step} upsert")
+        held.extend(up[np.isin(ro["status"], (1, 6))].tolist())
+        q = np.concatenate([np.array(held[:300], np.uint64), sk, keys[-30:]])
+        for lpp in (0, 1):
+            vg, fg = gpu_lookup(g, q, lpp)
+            vo, fo = o.lookup(q)
+            assert np.array_equal(fg, fo) and np.array_equal(vg, vo), f"{geom} lookup lpp={lpp}"
+        assert_same_image(g.export(), o.export(), f"{geom} step {step} after")
+    st = o.stats()
+    assert st["inserts_stashed"] > 0
+    assert_same_stats(g.stats(), st, f"{geom}")
+    checks.check_invariants(g.export(), n, B, d, 104, ghost=ghost, rattle=scheme == "rattle")
+
+
 @pytest.mark.parametrize("B,d", [(1, 2), (1, 3), (1, 4), (2, 2), (4, 2), (8, 2)])
 @pytest.mark.parametrize("lpp", [0, 1])
 def test_lookup_parity_on_imported_table(B, d, lpp):
