@@ -40,8 +40,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 # shapes, host loop); once that source changes the benchmark reports null
 # until the counters are taken again.
 MEASURED_EVICT_TRAFFIC = {
-    "sources_sha256": "a473900933a71fe5caa23907ebabd29ac52cc8684b08fbb1db07085710685d00",
-    "bytes_per_launch": 36658443,
+    "sources_sha256": "c6822e175c21e9bd40f4f58149888739cc6178e108b295d505e3a376e9e0213d",
+    "bytes_per_launch": 36663774,
     "profile": "profiles/evict_planners__fill95_2e24x8.md",
 }
 _SOURCES = ("ck_kernels.hip", "ck_api.hip", "ck_internal.h")
@@ -89,7 +89,8 @@ def parse():
                    help="first run three plain 256 MiB device copies (the yardstick "
                         "for rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     p.add_argument("--cpu-bins-log2", type=int, default=19)
-    p.add_argument("--workload", default="fill", choices=["fill", "group", "serve", "mixed", "dary"],
+    p.add_argument("--workload", default="fill",
+                   choices=["fill", "group", "serve", "mixed", "dary", "bias"],
                    help="fill: one 2^24 x 8 table (default); group: 4096 tables of "
                         "2^10..2^20 bins x 4 slots, batched vs per-request launches; "
                         "serve: the same tables behind the continuous-batching server, "
@@ -483,6 +484,50 @@ def run_dary(args):
         "by_case": res}), flush=True)
 
 
+def run_bias(args):
+    """Biased hashes (Sec. 9's open question): the fill of 2^22 bins x 4 slots
+    (two hash functions, 64-bit keys and values, sub-batches of 2^20) to 0.90
+    with random kicking, BFS, sorted search and queue-kicking, at bias levels
+    0 (uniform), 1 and 2.  Bins viewed per insert in the bands just below 0.80
+    and 0.90, failures and insert rates per case."""
+    import torch
+    from paper_1605_05236_amd import inputs
+    from paper_1605_05236_amd.table import CuckooTable
+    torch.cuda.set_device(0)
+    n, B, load = 1 << 22, 4, 0.90
+    m = inputs.target_count(n, B, load)
+    keys, vals = inputs.keys_values_torch(4, m)
+    res, total_ins, total_s = {}, 0, 0.0
+    for bias in (0, 1, 2):
+        for scheme in ("random_walk", "bfs", "sorted", "queue"):
+            t = CuckooTable(n, B, 2, scheme, max_chain=500, max_search=500, batch_ops=1 << 20,
+                            hash_seed=104, rng_seed=204, hash_bias=bias)
+            sec = _timed(lambda: t.insert(keys, vals, diagnostics=False))
+            st = t.stats()
+            bands = st["band_inserts"].astype(np.float64)
+            bv = st["band_views"].astype(np.float64)
+            out = {"inserts_per_s": m / sec, "seconds": sec,
+                   "failed_inserts": st["inserts_failed"], "stored": st["stored"]}
+            for edge in (0.80, 0.90):
+                top = int(np.floor(edge * 200 - 1e-9))
+                out[f"bins_viewed_per_insert_below_{edge:.2f}"] = (
+                    float(bv[top] / bands[top]) if bands[top] else None)
+            res[f"bias{bias}_{scheme}"] = out
+            total_ins += m
+            total_s += sec
+            print(f"# bias {bias} {scheme}: {out}", file=sys.stderr, flush=True)
+            t.close()
+    print(json.dumps({
+        "metric": "inserts/s and bins viewed per insert with biased hashes",
+        "value": total_ins / total_s, "unit": "inserts/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": total_s * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic (splitmix64 keys, seeded)",
+        "config": {"workload": "2^22 bins x 4 slots, 2 hash functions, fill to 0.90 in "
+                               "sub-batches of 2^20, hash bias levels 0, 1, 2",
+                   "schemes": ["random_walk", "bfs", "sorted", "queue"]},
+        "by_case": res}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -500,6 +545,9 @@ def main():
         return
     if args.workload == "dary":
         run_dary(args)
+        return
+    if args.workload == "bias":
+        run_bias(args)
         return
     import torch
     from paper_1605_05236_amd import inputs

@@ -109,6 +109,11 @@ typedef struct {
                                 in the first free entry (CK_OP_STASHED); lookups,
                                 deletes, overwrites and upserts search the stash
                                 after the key's bins, as one more probe */
+  uint32_t hash_bias;        /* 0: uniform hashes (Sec. 3).  1-4: biased hashes
+                                (Sec. 9): for each choice, w = mix64(a_i x + c_i)
+                                and, when the two low bits of w are below
+                                hash_bias, the bin is the lesser of the two
+                                draws', so low bins are favoured */
 } ck_options;
 
 /* Counters of one table since creation (or the last ck_stats_reset). */

@@ -519,6 +519,7 @@ static ck_status create_table(uint64_t bins, uint32_t B, uint32_t d, ck_scheme s
   if (o.batch_ops == 0 || o.batch_ops > (1u << 26)) return CK_EINVAL;
   if (o.max_chain > 2048 || o.max_search > 1024 || o.max_search < d) return CK_EINVAL;
   if (o.stash > kMaxStash) return CK_EINVAL;
+  if (o.hash_bias > 4) return CK_EINVAL;
   if (((uintptr_t)storage & 255) != 0) return CK_EINVAL;
   const Layout L = layout(bins, B);
   if (bytes < L.total) return CK_ENOMEM;
@@ -548,6 +549,7 @@ static ck_status create_table(uint64_t bins, uint32_t B, uint32_t d, ck_scheme s
   t->g.max_search = o.max_search;
   t->g.rng_seed = o.rng_seed;
   t->g.stash_n = o.stash;
+  t->g.hash_bias = o.hash_bias;
   t->g.stash_tables = n_tables;
   ck_status st = alloc_scratch(t);
   if (st != CK_OK) {
@@ -866,6 +868,14 @@ ck_status ck_hash(const ck_table* t, uint64_t key, uint64_t* out) {
   for (uint32_t i = 0; i < t->H; ++i) {
     uint64_t z = t->g.a[i] * key + t->g.c[i];
     uint64_t b = (uint64_t)(((unsigned __int128)z * t->bins) >> 64);
+    if (t->g.hash_bias) {  // as the kernels' hash_key
+      uint64_t w = z;
+      w = (w ^ (w >> 30)) * 0xBF58476D1CE4E5B9ull;
+      w = (w ^ (w >> 27)) * 0x94D049BB133111EBull;
+      w ^= w >> 31;
+      if ((w & 3) < t->g.hash_bias)
+        b = std::min<uint64_t>(b, (uint64_t)(((unsigned __int128)w * t->bins) >> 64));
+    }
     for (;;) {
       bool clash = false;
       for (uint32_t j = 0; j < i; ++j) clash |= out[j] == b;

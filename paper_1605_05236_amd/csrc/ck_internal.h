@@ -158,6 +158,7 @@ struct Geo {
   uint32_t* stash_cnt;
   uint32_t stash_n;
   uint32_t stash_tables;
+  uint32_t hash_bias;  // 0: uniform hashes; 1-4: biased
 };
 
 // Round-scratch pointers of one sub-batch.

@@ -40,13 +40,24 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 
 // h_i(x) = floor(((a_i x + c_i) mod 2^64) * n / 2^64), stepped past clashes,
 // in the bin range [t.base, t.base + t.n) of the key's table (a group of
-// tables shares one bin array; a single table has base 0).
-template <int H>
+// tables shares one bin array; a single table has base 0).  A biased hash of
+// level k (Sec. 9's open question) takes the lesser of that bin and the bin
+// of w = mix64(a_i x + c_i) when the two low bits of w are below k, so low
+// bins are favoured for a fraction k / 4 of the keys.
+// (Kernels instantiated for uniform hashes pass MayBias = false, which drops
+// the biased branch and its registers.)
+template <int H, bool MayBias = true>
 __device__ __forceinline__ void hash_key(const Geo& g, Tab t, uint64_t x, uint32_t* h) {
   const uint32_t end = t.base + t.n;
 #pragma unroll
   for (int i = 0; i < H; ++i) {
-    uint32_t b = t.base + (uint32_t)__umul64hi(g.a[i] * x + g.c[i], (uint64_t)t.n);
+    const uint64_t z = g.a[i] * x + g.c[i];
+    uint32_t b = t.base + (uint32_t)__umul64hi(z, (uint64_t)t.n);
+    if (MayBias && g.hash_bias) {
+      const uint64_t w = mix64(z);
+      if ((uint32_t)(w & 3) < g.hash_bias)
+        b = min(b, t.base + (uint32_t)__umul64hi(w, (uint64_t)t.n));
+    }
     for (;;) {
       bool clash = false;
 #pragma unroll
@@ -1147,7 +1158,9 @@ static size_t search_group_scratch_bytes(const Geo& g) {
 
 // At least four wavefronts per SIMD: the register budget that keeps 16
 // one-wavefront workgroups resident per CU.
-template <int B, int H, int O>
+// BIAS: an instance for biased hashes (the uniform one has no biased branch,
+// which would cost registers at this kernel's budget).
+template <int B, int H, int O, bool BIAS>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_plan_search(
     Geo g, Round r) {
   constexpr int W = kSearchW;
@@ -1245,7 +1258,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   auto fetch_roots = [&]() {
     if (i_nx == kNone) return;
     T_nx = tab_of(g, r.op_table, r.tdesc, i_nx);
-    hash_key<H>(g, T_nx, x_nx, h_nx);
+    hash_key<H, BIAS>(g, T_nx, x_nx, h_nx);
 #pragma unroll
     for (int t = 0; t < RBW; ++t) {
       const int e = gl + t * W;
@@ -1296,7 +1309,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
           if (q == j) hb = h[j];
         if (by_count) bk[t2] = min(15u, (rmeta[t2] >> 8) & 0xFu);
         uint32_t hv[H];
-        hash_key<H>(g, T, rkey[t2], hv);
+        hash_key<H, BIAS>(g, T, rkey[t2], hv);
         uint32_t o = 0;
 #pragma unroll
         for (int j = 0; j < H; ++j) {
@@ -1521,7 +1534,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
           const uint32_t cp = __shfl(c_u, gb + (int)(pu % W), 64);
           if (pu < G && ((RUNS >> pu) & 1ull)) {
             uint32_t hv[H];
-            hash_key<H>(g, T, sv[k].x, hv);
+            hash_key<H, BIAS>(g, T, sv[k].x, hv);
             cand(rp * B + ps) = hv[0] == cp ? hv[1] : hv[0];
           }
         }
@@ -1656,7 +1669,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
           const uint32_t run = nruns++;
           if (gl < B) {
             uint32_t hv[H];
-            hash_key<H>(g, T, vk, hv);
+            hash_key<H, BIAS>(g, T, vk, hv);
             uint32_t o = 0;
 #pragma unroll
             for (int q = 0; q < H; ++q)
@@ -1729,7 +1742,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       uint32_t tb = 0, tws = 0;
       if (twin) {  // the duplicate's twin, in the duplicate key's other bin
         uint32_t hd[2];
-        hash_key<2>(g, T, dk, hd);
+        hash_key<2, BIAS>(g, T, dk, hd);
         tb = hd[0] == term_c ? hd[1] : hd[0];
         uint64_t tk2 = kEmpty;
         if (gl < B) tk2 = g.slots[(uint64_t)tb * B + gl].x;
@@ -1831,13 +1844,25 @@ constexpr uint32_t kTailCommitBlocks = 1024;
 template <int B, int H>
 static void evict_go(const Geo& g, const Round& r, uint32_t grid, hipStream_t s) {
   const size_t lds = evict_lds_bytes(g);
-  if (g.scheme == CK_BFS)
-    hipLaunchKernelGGL((k_plan_search<B, H, kOrderFifo>), dim3(grid), dim3(64), lds, s, g, r);
-  else if (g.scheme == CK_SORTED)
-    hipLaunchKernelGGL((k_plan_search<B, H, kOrderCount>), dim3(grid), dim3(64), lds, s, g, r);
-  else if (g.scheme == CK_HYBRID)
-    hipLaunchKernelGGL((k_plan_search<B, H, kOrderDepthCount>), dim3(grid), dim3(64), lds, s, g,
+  if (is_search(g.scheme) && g.hash_bias) {
+    if (g.scheme == CK_BFS)
+      hipLaunchKernelGGL((k_plan_search<B, H, kOrderFifo, true>), dim3(grid), dim3(64), lds, s,
+                         g, r);
+    else if (g.scheme == CK_SORTED)
+      hipLaunchKernelGGL((k_plan_search<B, H, kOrderCount, true>), dim3(grid), dim3(64), lds, s,
+                         g, r);
+    else
+      hipLaunchKernelGGL((k_plan_search<B, H, kOrderDepthCount, true>), dim3(grid), dim3(64), lds,
+                         s, g, r);
+  } else if (g.scheme == CK_BFS)
+    hipLaunchKernelGGL((k_plan_search<B, H, kOrderFifo, false>), dim3(grid), dim3(64), lds, s, g,
                        r);
+  else if (g.scheme == CK_SORTED)
+    hipLaunchKernelGGL((k_plan_search<B, H, kOrderCount, false>), dim3(grid), dim3(64), lds, s, g,
+                       r);
+  else if (g.scheme == CK_HYBRID)
+    hipLaunchKernelGGL((k_plan_search<B, H, kOrderDepthCount, false>), dim3(grid), dim3(64), lds,
+                       s, g, r);
   else
     hipLaunchKernelGGL((k_plan_walk<B, H>), dim3(grid), dim3(64), lds, s, g, r);
 }
@@ -1866,15 +1891,16 @@ static void fresh_go(const Geo& g, const Round& r, hipStream_t s) {
 template <int B, int H>
 static void evict_occupancy(const Geo& g, int* per_cu) {
   const size_t lds = evict_lds_bytes(g);
+  // the uniform-hash instances (the biased ones have the same launch bounds)
   if (g.scheme == CK_BFS)
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_plan_search<B, H, kOrderFifo>, 64,
-                                                       lds);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        per_cu, k_plan_search<B, H, kOrderFifo, false>, 64, lds);
   else if (g.scheme == CK_SORTED)
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_plan_search<B, H, kOrderCount>, 64,
-                                                       lds);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        per_cu, k_plan_search<B, H, kOrderCount, false>, 64, lds);
   else if (g.scheme == CK_HYBRID)
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        per_cu, k_plan_search<B, H, kOrderDepthCount>, 64, lds);
+        per_cu, k_plan_search<B, H, kOrderDepthCount, false>, 64, lds);
   else
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_plan_walk<B, H>, 64, lds);
 }

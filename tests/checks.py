@@ -30,6 +30,13 @@ def hash_params(hash_seed: int, H: int = 4):
     return a, c
 
 
+def _mix_np(z: np.ndarray) -> np.ndarray:
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
 def _mulhi(z: np.ndarray, n: int) -> np.ndarray:
     assert n < (1 << 32)
     nn = np.uint64(n)
@@ -38,15 +45,21 @@ def _mulhi(z: np.ndarray, n: int) -> np.ndarray:
     return (hi * nn + ((lo * nn) >> np.uint64(32))) >> np.uint64(32)
 
 
-def bins_of(keys: np.ndarray, n: int, H: int, hash_seed: int) -> np.ndarray:
+def bins_of(keys: np.ndarray, n: int, H: int, hash_seed: int, hash_bias: int = 0) -> np.ndarray:
     """(len(keys), H) bin indices: floor(((a_i x + c_i) mod 2^64) n / 2^64),
-    stepped forward past earlier choices so the H bins are distinct."""
+    stepped forward past earlier choices so the H bins are distinct.  With a
+    bias level k, the lesser of that and the bin of w = mix64(a_i x + c_i)
+    when the two low bits of w are below k."""
     a, c = hash_params(hash_seed, H)
     keys = np.asarray(keys, dtype=np.uint64)
     out = np.zeros((keys.size, H), dtype=np.uint64)
     with np.errstate(over="ignore"):
         for i in range(H):
-            h = _mulhi(np.uint64(a[i]) * keys + np.uint64(c[i]), n)
+            z = np.uint64(a[i]) * keys + np.uint64(c[i])
+            h = _mulhi(z, n)
+            if hash_bias:
+                w = _mix_np(z)
+                h = np.where((w & np.uint64(3)) < np.uint64(hash_bias), np.minimum(h, _mulhi(w, n)), h)
             while True:
                 clash = np.zeros(keys.size, bool)
                 for j in range(i):
@@ -58,7 +71,7 @@ def bins_of(keys: np.ndarray, n: int, H: int, hash_seed: int) -> np.ndarray:
     return out
 
 
-def check_invariants(img, n, B, H, hash_seed, ghost=False, rattle=False):
+def check_invariants(img, n, B, H, hash_seed, ghost=False, rattle=False, hash_bias=0):
     """P1 placement, P2 uniqueness / ghost pairs.  Returns the stored key set."""
     keys, vals, meta = img["keys"], img["vals"], img["meta"]
     S = n * B
@@ -70,7 +83,7 @@ def check_invariants(img, n, B, H, hash_seed, ghost=False, rattle=False):
     assert not np.any(dupbit & ~occ), "duplicate mark on an empty slot"
     k = keys[occ]
     b = slot_bin[occ]
-    hb = bins_of(k, n, H, hash_seed)
+    hb = bins_of(k, n, H, hash_seed, hash_bias)
     assert np.all((hb == b[:, None]).any(axis=1)), "a key sits outside its bins"
     d = dupbit[occ]
     uk, counts = np.unique(k, return_counts=True)

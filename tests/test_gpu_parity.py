@@ -243,6 +243,33 @@ def test_stash_parity(geom, batch):
     checks.check_invariants(g.export(), n, B, d, 104, ghost=ghost, rattle=scheme == "rattle")
 
 
+@pytest.mark.parametrize("geom", [("random_walk", 4, 2, False), ("bfs", 8, 2, True),
+                                  ("sorted", 4, 2, False), ("queue", 4, 2, False),
+                                  ("rattle", 1, 3, False), ("hybrid", 1, 3, False)], ids=ident)
+@pytest.mark.parametrize("bias", [1, 2])
+def test_biased_hash_parity(geom, bias):
+    # Biased hashes (Sec. 9): the same fill, bin for bin, as the oracle, with
+    # the chain failures the bias brings at high load; the hash itself too.
+    scheme, B, d, ghost = geom
+    n = 1 << 11 if B > 1 else 1 << 12
+    kw = dict(ghost=ghost, max_chain=500, max_search=500, batch_ops=700, hash_bias=bias)
+    print(f"biased hash parity {geom} bias={bias}", flush=True)
+    g = gpu_table(n, B, d, scheme, seed=2, **kw)
+    o = oracle_table(n, B, d, scheme, seed=2, **kw)
+    keys, vals = keys_for(n, B, 0.93 if B > 1 else 0.85, seed=16)
+    for x in keys[:50].tolist():
+        assert g.hash(x) == o.hash(x)
+    rg, ro = gpu_insert(g, keys, vals), o.insert(keys, vals)
+    assert_same_ops(rg, ro, f"{geom} bias {bias}")
+    assert_same_image(g.export(), o.export(), f"{geom} bias {bias}")
+    assert_same_stats(g.stats(), o.stats(), f"{geom} bias {bias}")
+    ok = ro["status"] == 1
+    v, f = gpu_lookup(g, keys[ok])
+    assert f.all() and np.array_equal(v, vals[ok])
+    checks.check_invariants(g.export(), n, B, d, 102, ghost=ghost, rattle=scheme == "rattle",
+                            hash_bias=bias)
+
+
 @pytest.mark.parametrize("B,d", [(1, 2), (1, 3), (1, 4), (2, 2), (4, 2), (8, 2)])
 @pytest.mark.parametrize("lpp", [0, 1])
 def test_lookup_parity_on_imported_table(B, d, lpp):

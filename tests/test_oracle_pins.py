@@ -596,3 +596,45 @@ def test_round_mode_is_deterministic_and_valid():
         assert np.array_equal(imgs[0][0][f], imgs[1][0][f])
     assert imgs[0][1]["retries"].sum() > 0
     checks.check_invariants(imgs[0][0], 1 << 10, 4, 2, 101, ghost=True)
+
+
+# --------------------------------------------------------------------------- biased hashes (Sec. 9)
+@pytest.mark.parametrize("k", [1, 2, 4])
+def test_biased_hash_follows_its_distribution(k):
+    # Sec. 9 asks how the schemes fare with biased hashes.  A bias level k makes
+    # a fraction k/4 of the choices the lesser of two independent draws, so for
+    # n = 2^m the first choice h_0 lands on bin b with probability
+    #   (1 - k/4) / n + (k/4) (2 (n - b) - 1) / n^2
+    # (the minimum of two uniform draws on [0, n) exceeds b - 1 with
+    # probability ((n - b) / n)^2).  Chi-square against that law.
+    n = 1 << 8
+    t = make(n, 4, 2, hash_bias=k)
+    keys, _ = inputs.keys_values(61, 60000)
+    h0 = np.array([t.hash(x)[0] for x in keys.tolist()])
+    b = np.arange(n)
+    p = (1 - k / 4) / n + (k / 4) * (2 * (n - b) - 1) / n ** 2
+    assert abs(p.sum() - 1) < 1e-12
+    obs = np.bincount(h0, minlength=n)
+    exp = p * keys.size
+    chi2 = float(((obs - exp) ** 2 / exp).sum())
+    dof = n - 1
+    assert chi2 < dof + 6 * np.sqrt(2 * dof), chi2
+    # and the bias shows: the lowest eighth of the bins gets its share
+    lo = obs[: n // 8].sum() / keys.size
+    assert abs(lo - p[: n // 8].sum()) < 0.01
+
+
+def test_biased_hash_placement_and_dictionary():
+    # Keys still sit in their (biased) bins, and the table still answers like a
+    # dictionary; the placement check computes the biased bins independently.
+    for scheme, d, B in [("bfs", 2, 4), ("rattle", 3, 1), ("queue", 2, 4)]:
+        t = make(1 << 8, B, d, scheme, hash_bias=2, batch_ops=16, max_chain=1000)
+        m = inputs.target_count(t.n, B, 0.8)
+        k, v = inputs.keys_values(9, m, value_bits=32 if B == 1 else 64)
+        r = t.insert(k, v)
+        held = checks.check_invariants(t.export(), t.n, B, d, 101, rattle=scheme == "rattle",
+                                       hash_bias=2)
+        ok = np.isin(r["status"], HELD)
+        assert held == set(k[ok].tolist())
+        got, found = t.lookup(k[ok])
+        assert found.all()
