@@ -463,7 +463,9 @@ struct BinKeys {
   }
 };
 
-template <int B, int H>
+// EXT: the instance for upserts, stashes and biased hashes; the plain one
+// carries none of their code (the host picks by the table and the call).
+template <int B, int H, bool EXT>
 __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
   constexpr int L = fresh_lanes(B);
   using Keys = BinKeys<B, L>;
@@ -498,12 +500,12 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
     // one is inserted as below, having viewed all H bins, and its plan also
     // claims the key's first bin (kHdrKeyClaim), so that of two upserts of
     // one new key in a round the later one loses and then finds the key.
-    const bool ups = r.upsert && active && !bad;
+    const bool ups = EXT && r.upsert && active && !bad;
     bool updated = false;
     uint32_t key_bin = 0, stash_e = kNone;
     if (ups) {
       uint32_t h[H];
-      hash_key<H>(g, T, x, h);
+      hash_key<H, EXT>(g, T, x, h);
       key_bin = h[0];
 #pragma unroll
       for (int hi = 0; hi < H; ++hi) {
@@ -536,7 +538,7 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
     // rattle-kicking has no separate fresh phase: every op goes to the walk
     if (active && !bad && !updated && g.scheme != CK_RATTLE) {
       uint32_t h[H];
-      hash_key<H>(g, T, x, h);
+      hash_key<H, EXT>(g, T, x, h);
       if (g.ghost) {
         Keys s0, s1;
         s0.load(g, h[0], G.sl);
@@ -563,7 +565,7 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
             const uint32_t ds = ffs32(d0 ? d0 : d1);
             const uint64_t dk = w == 0 ? s0.at(G, ds) : s1.at(G, ds);
             uint32_t hd[2];
-            hash_key<2>(g, T, dk, hd);
+            hash_key<2, EXT>(g, T, dk, hd);
             const uint32_t tb = hd[0] == b ? hd[1] : hd[0];
             Keys ts;
             ts.load(g, tb, G.sl);
@@ -753,7 +755,7 @@ struct WalkLog {
   }
 };
 
-template <int B, int H>
+template <int B, int H, bool EXT>
 struct WalkPlanner {
   static constexpr int W = kWalkW;
   const Geo& g;
@@ -878,7 +880,7 @@ struct WalkPlanner {
   __device__ void replace_dup(uint32_t s, uint64_t k, uint64_t a, uint32_t flags) {
     const uint64_t dk = slot_key(s);
     uint32_t hd[2];
-    hash_key<2>(g, T, dk, hd);
+    hash_key<2, EXT>(g, T, dk, hd);
     const uint32_t here = vbin;
     const uint32_t tb = hd[0] == here ? hd[1] : hd[0];
     ulonglong2 ts = make_ulonglong2(kEmpty, 0ull);
@@ -919,7 +921,7 @@ struct WalkPlanner {
       ck = vk;
       ca = va;
       uint32_t hv[H];
-      hash_key<H>(g, T, ck, hv);
+      hash_key<H, EXT>(g, T, ck, hv);
       uint32_t oth[H];
       uint32_t no = 0;
       for (int q = 0; q < H; ++q)
@@ -950,7 +952,7 @@ struct WalkPlanner {
       ck = vk;
       ca = va;
       uint32_t hv[2];
-      hash_key<2>(g, T, ck, hv);
+      hash_key<2, EXT>(g, T, ck, hv);
       t = hv[0] == t ? hv[1] : hv[0];
       load(t, true);
       if (terminal()) {
@@ -967,7 +969,7 @@ struct WalkPlanner {
     for (;;) {
       if (tries == g.max_chain) return PL_FAIL;
       uint32_t hv[H];
-      hash_key<H>(g, T, ck, hv);
+      hash_key<H, EXT>(g, T, ck, hv);
       uint32_t rr = rattle_of(ca);
       const uint32_t b = hv[rr % H];
       rr = (rr + 1) & 0xFFFF;
@@ -1011,13 +1013,13 @@ struct WalkPlanner {
     }
     if (gl == 0) {
       // a failed chain's key goes to the stash if it has room
-      const uint32_t se = status == PL_FAIL ? stash_take(g, r, i) : kNone;
+      const uint32_t se = (EXT && status == PL_FAIL) ? stash_take(g, r, i) : kNone;
       PlanHdr hd{};
       // an upsert's plan adds the presence check's views and its key claim
       // (made by the fresh planner)
       hd.st = hdr_pack(se != kNone ? PL_STASHED : status, status == PL_OK ? twins : 0, nm) |
-              kHdrArena | (r.upsert ? kHdrKeyClaim : 0u) | (se != kNone ? kHdrStash : 0u);
-      hd.views = views + (r.upsert ? (uint32_t)H + (g.stash_n ? 1u : 0u) : 0u);
+              kHdrArena | ((EXT && r.upsert) ? kHdrKeyClaim : 0u) | (se != kNone ? kHdrStash : 0u);
+      hd.views = views + ((EXT && r.upsert) ? (uint32_t)H + (g.stash_n ? 1u : 0u) : 0u);
       hd.a = off;
       hd.b = status == PL_OK ? kicks : (se != kNone ? se : 0u);
       hd.n_spawn = 0;
@@ -1036,7 +1038,7 @@ static size_t walk_group_scratch_bytes(const Geo& g) {
   return ((size_t)(g.max_chain + 8) * 24 + 255) & ~(size_t)255;
 }
 
-template <int B, int H>
+template <int B, int H, bool EXT>
 __global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
   constexpr int W = kWalkW;
   constexpr int P = 64 / W;
@@ -1094,11 +1096,11 @@ __global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
     wave_sync();
     if (i != kNone) {
       const uint64_t xa = load_aux(r.vals, i, B);
-      WalkPlanner<B, H> Pl(g, r, L, cap);
+      WalkPlanner<B, H, EXT> Pl(g, r, L, cap);
       Pl.op = r.op_base + i;
       Pl.T = tab_of(g, r.op_table, r.tdesc, i);
       uint32_t h[H];
-      hash_key<H>(g, Pl.T, x, h);
+      hash_key<H, EXT>(g, Pl.T, x, h);
       uint32_t st;
       if (g.scheme == CK_RATTLE) st = Pl.rattle(x, xa);
       else if (g.scheme == CK_QUEUE) st = Pl.queue_kick(x, xa, h);
@@ -1158,9 +1160,9 @@ static size_t search_group_scratch_bytes(const Geo& g) {
 
 // At least four wavefronts per SIMD: the register budget that keeps 16
 // one-wavefront workgroups resident per CU.
-// BIAS: an instance for biased hashes (the uniform one has no biased branch,
-// which would cost registers at this kernel's budget).
-template <int B, int H, int O, bool BIAS>
+// EXT: the instance for upserts, stashes and biased hashes (the plain one has
+// none of their branches, which would cost registers at this kernel's budget).
+template <int B, int H, int O, bool EXT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_plan_search(
     Geo g, Round r) {
   constexpr int W = kSearchW;
@@ -1258,7 +1260,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   auto fetch_roots = [&]() {
     if (i_nx == kNone) return;
     T_nx = tab_of(g, r.op_table, r.tdesc, i_nx);
-    hash_key<H, BIAS>(g, T_nx, x_nx, h_nx);
+    hash_key<H, EXT>(g, T_nx, x_nx, h_nx);
 #pragma unroll
     for (int t = 0; t < RBW; ++t) {
       const int e = gl + t * W;
@@ -1309,7 +1311,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
           if (q == j) hb = h[j];
         if (by_count) bk[t2] = min(15u, (rmeta[t2] >> 8) & 0xFu);
         uint32_t hv[H];
-        hash_key<H, BIAS>(g, T, rkey[t2], hv);
+        hash_key<H, EXT>(g, T, rkey[t2], hv);
         uint32_t o = 0;
 #pragma unroll
         for (int j = 0; j < H; ++j) {
@@ -1534,7 +1536,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
           const uint32_t cp = __shfl(c_u, gb + (int)(pu % W), 64);
           if (pu < G && ((RUNS >> pu) & 1ull)) {
             uint32_t hv[H];
-            hash_key<H, BIAS>(g, T, sv[k].x, hv);
+            hash_key<H, EXT>(g, T, sv[k].x, hv);
             cand(rp * B + ps) = hv[0] == cp ? hv[1] : hv[0];
           }
         }
@@ -1669,7 +1671,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
           const uint32_t run = nruns++;
           if (gl < B) {
             uint32_t hv[H];
-            hash_key<H, BIAS>(g, T, vk, hv);
+            hash_key<H, EXT>(g, T, vk, hv);
             uint32_t o = 0;
 #pragma unroll
             for (int q = 0; q < H; ++q)
@@ -1742,7 +1744,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       uint32_t tb = 0, tws = 0;
       if (twin) {  // the duplicate's twin, in the duplicate key's other bin
         uint32_t hd[2];
-        hash_key<2, BIAS>(g, T, dk, hd);
+        hash_key<2, EXT>(g, T, dk, hd);
         tb = hd[0] == term_c ? hd[1] : hd[0];
         uint64_t tk2 = kEmpty;
         if (gl < B) tk2 = g.slots[(uint64_t)tb * B + gl].x;
@@ -1802,11 +1804,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     }
     if (have && gl == 0) {
       // a failed search's key goes to the stash if it has room
-      const uint32_t se = found ? kNone : stash_take(g, r, i);
+      const uint32_t se = (EXT && !found) ? stash_take(g, r, i) : kNone;
       PlanHdr hd{};
       hd.st = hdr_pack(found ? PL_OK : (se != kNone ? PL_STASHED : PL_FAIL), twin, nm) |
-              kHdrArena | (r.upsert ? kHdrKeyClaim : 0u) | (se != kNone ? kHdrStash : 0u);
-      hd.views = views + (r.upsert ? (uint32_t)H + (g.stash_n ? 1u : 0u) : 0u);
+              kHdrArena | ((EXT && r.upsert) ? kHdrKeyClaim : 0u) | (se != kNone ? kHdrStash : 0u);
+      hd.views = views + ((EXT && r.upsert) ? (uint32_t)H + (g.stash_n ? 1u : 0u) : 0u);
       hd.a = off;
       hd.b = found ? depth : (se != kNone ? se : 0u);
       hd.n_spawn = nsp;
@@ -1839,12 +1841,20 @@ size_t evict_wg_scratch_bytes(const Geo& g) {
 // is known only on the device: enough to fill the device, each taking as
 // many passes as the count needs.
 constexpr uint32_t kTailPlanBlocks = 2048;
+
+// Rounds that need the extended kernel instances: upserts, a stash (inserts,
+// deletes and overwrites search or fill it), or biased hashes.
+static bool extended(const Geo& g, const Round& r) {
+  return r.upsert || g.stash_n || g.hash_bias;
+}
 constexpr uint32_t kTailCommitBlocks = 1024;
 
 template <int B, int H>
 static void evict_go(const Geo& g, const Round& r, uint32_t grid, hipStream_t s) {
   const size_t lds = evict_lds_bytes(g);
-  if (is_search(g.scheme) && g.hash_bias) {
+  if (extended(g, r) && !is_search(g.scheme)) {
+    hipLaunchKernelGGL((k_plan_walk<B, H, true>), dim3(grid), dim3(64), lds, s, g, r);
+  } else if (extended(g, r)) {
     if (g.scheme == CK_BFS)
       hipLaunchKernelGGL((k_plan_search<B, H, kOrderFifo, true>), dim3(grid), dim3(64), lds, s,
                          g, r);
@@ -1864,7 +1874,7 @@ static void evict_go(const Geo& g, const Round& r, uint32_t grid, hipStream_t s)
     hipLaunchKernelGGL((k_plan_search<B, H, kOrderDepthCount, false>), dim3(grid), dim3(64), lds,
                        s, g, r);
   else
-    hipLaunchKernelGGL((k_plan_walk<B, H>), dim3(grid), dim3(64), lds, s, g, r);
+    hipLaunchKernelGGL((k_plan_walk<B, H, false>), dim3(grid), dim3(64), lds, s, g, r);
 }
 
 template <int B, int H>
@@ -1872,7 +1882,8 @@ static void fresh_go(const Geo& g, const Round& r, hipStream_t s) {
   const uint64_t threads = (uint64_t)r.npend * fresh_lanes(B);
   uint32_t grid = (uint32_t)((threads + 255) / 256);
   if (!r.first) grid = std::min(grid, kTailPlanBlocks);
-  hipLaunchKernelGGL((k_plan_fresh<B, H>), dim3(grid), dim3(256), 0, s, g, r);
+  if (extended(g, r)) hipLaunchKernelGGL((k_plan_fresh<B, H, true>), dim3(grid), dim3(256), 0, s, g, r);
+  else hipLaunchKernelGGL((k_plan_fresh<B, H, false>), dim3(grid), dim3(256), 0, s, g, r);
 }
 
 #define CK_DISPATCH(FN, ...)                                  \
@@ -1891,7 +1902,7 @@ static void fresh_go(const Geo& g, const Round& r, hipStream_t s) {
 template <int B, int H>
 static void evict_occupancy(const Geo& g, int* per_cu) {
   const size_t lds = evict_lds_bytes(g);
-  // the uniform-hash instances (the biased ones have the same launch bounds)
+  // the plain instances (the extended ones have the same launch bounds)
   if (g.scheme == CK_BFS)
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
         per_cu, k_plan_search<B, H, kOrderFifo, false>, 64, lds);
@@ -1902,7 +1913,7 @@ static void evict_occupancy(const Geo& g, int* per_cu) {
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
         per_cu, k_plan_search<B, H, kOrderDepthCount, false>, 64, lds);
   else
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_plan_walk<B, H>, 64, lds);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_plan_walk<B, H, false>, 64, lds);
 }
 
 // Eviction-planner workgroups that can be resident on one compute unit at
@@ -2039,6 +2050,7 @@ __device__ __forceinline__ void sc_increment(uint32_t* meta) {
 // Between them each wavefront lists its losers for the next round: the
 // atomic that reserves their list entries is issued before the writes and
 // its result is used after them, so its latency hides behind them.
+template <bool EXT>
 __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
   constexpr int CL = kCommitLanes;
   const int lane = threadIdx.x & 63;
@@ -2099,7 +2111,7 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
         views = h0.y;
         off = h0.z;  // inline: the first move's bin; arena: the moves' offset
         mv0_sf = h0.w;
-        se = (h0.x & kHdrStash) ? h0.w : kNone;  // the stash entry the plan writes
+        se = (EXT && (h0.x & kHdrStash)) ? h0.w : kNone;  // the stash entry the plan writes
         kicks = (inl || se != kNone) ? 0u : h0.w;
         if (!inl) {
           const uint4 h1 = ((const uint4*)r.hdr)[2 * (size_t)i + 1];
@@ -2116,12 +2128,12 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
           get(j, bin, slot, fl, k, a);
           if (g.owner[bin] != me) mine = false;
         }
-        if ((h0.x & kHdrKeyClaim) && leader) {  // an upsert's claim on its key's first bin
+        if (EXT && (h0.x & kHdrKeyClaim) && leader) {  // an upsert's claim on its key's first bin
           uint32_t kb[1];
-          hash_key<1>(g, tab_of(g, r.op_table, r.tdesc, i), x, kb);
+          hash_key<1, EXT>(g, tab_of(g, r.op_table, r.tdesc, i), x, kb);
           if (g.owner[kb[0]] != me) mine = false;
         }
-        if (se != kNone && leader && g.stash_owner[se] != me) mine = false;
+        if (EXT && se != kNone && leader && g.stash_owner[se] != me) mine = false;
         win = ((__ballot(!mine) >> gshift) & ((1ull << CL) - 1)) == 0;
         if (!win && leader) {
           lost = r.op_lost[i] + views;
@@ -2168,7 +2180,7 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
           }
           if (fl & MV_HC) atomicAdd(mw, 1u << 24);
         }
-        if (se != kNone && leader) {  // the stash entry: cleared, a new value, or the key
+        if (EXT && se != kNone && leader) {  // the stash entry: cleared, a new value, or the key
           ulonglong2* e = g.stash + se;
           uint32_t* cnt = g.stash_cnt + se / g.stash_n;
           if (r.is_delete && !r.overwrite) {
@@ -2215,7 +2227,8 @@ hipError_t launch_commit(const Geo& g, const Round& r, hipStream_t s) {
   if (r.npend == 0) return hipSuccess;
   uint32_t grid = (uint32_t)(((uint64_t)r.npend + kCommitOps - 1) / kCommitOps);
   if (!r.first) grid = std::min(grid, kTailCommitBlocks);
-  hipLaunchKernelGGL(k_commit, dim3(grid), dim3(256), 0, s, g, r);
+  if (extended(g, r)) hipLaunchKernelGGL(k_commit<true>, dim3(grid), dim3(256), 0, s, g, r);
+  else hipLaunchKernelGGL(k_commit<false>, dim3(grid), dim3(256), 0, s, g, r);
   return hipGetLastError();
 }
 
