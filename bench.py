@@ -40,8 +40,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 # shapes, host loop); once that source changes the benchmark reports null
 # until the counters are taken again.
 MEASURED_EVICT_TRAFFIC = {
-    "sources_sha256": "c6822e175c21e9bd40f4f58149888739cc6178e108b295d505e3a376e9e0213d",
-    "bytes_per_launch": 36663774,
+    "sources_sha256": "3832443820bac498d059dd0e3988d8ee1739faaa5a1d169dfb53af079a9521b6",
+    "bytes_per_launch": 36658470,
     "profile": "profiles/evict_planners__fill95_2e24x8.md",
 }
 _SOURCES = ("ck_kernels.hip", "ck_api.hip", "ck_internal.h")
