@@ -40,8 +40,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 # shapes, host loop); once that source changes the benchmark reports null
 # until the counters are taken again.
 MEASURED_EVICT_TRAFFIC = {
-    "sources_sha256": "3832443820bac498d059dd0e3988d8ee1739faaa5a1d169dfb53af079a9521b6",
-    "bytes_per_launch": 36658470,
+    "sources_sha256": "1833b354f1abc2216887acf13869cce2a415343d9c7e6747a009aa3e17de7ed5",
+    "bytes_per_launch": 36662140,
     "profile": "profiles/evict_planners__fill95_2e24x8.md",
 }
 _SOURCES = ("ck_kernels.hip", "ck_api.hip", "ck_internal.h")
@@ -90,7 +90,7 @@ def parse():
                         "for rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     p.add_argument("--cpu-bins-log2", type=int, default=19)
     p.add_argument("--workload", default="fill",
-                   choices=["fill", "group", "serve", "mixed", "dary", "bias"],
+                   choices=["fill", "group", "serve", "mixed", "dary", "bias", "stash"],
                    help="fill: one 2^24 x 8 table (default); group: 4096 tables of "
                         "2^10..2^20 bins x 4 slots, batched vs per-request launches; "
                         "serve: the same tables behind the continuous-batching server, "
@@ -528,6 +528,53 @@ def run_bias(args):
         "by_case": res}), flush=True)
 
 
+def run_stash(args):
+    """The stash (Sec. 2): a 2^22 x 4 table (two hash functions, 64-bit keys and
+    values, sub-batches of 2^20) filled to 0.97 by random kicking with chains
+    capped at 20 kicks, so chains fail near the top, without a stash and with
+    64 entries; then 2^24 lookups at 0.9 hits, whose misses also search the
+    stash when there is one."""
+    import torch
+    from paper_1605_05236_amd import inputs
+    from paper_1605_05236_amd.table import CuckooTable, as_device_keys
+    torch.cuda.set_device(0)
+    n, B, load = 1 << 22, 4, 0.97
+    m = inputs.target_count(n, B, load)
+    keys, vals = inputs.keys_values(5, m)
+    dkeys, dvals = as_device_keys(keys), as_device_keys(vals)
+    nq = 1 << 24
+    q, present = inputs.lookup_mix(305, keys, m, nq, 0.9, key_seed=5)
+    dq = as_device_keys(q)
+    res, total_ins, total_s = {}, 0, 0.0
+    for stash in (0, 64):
+        t = CuckooTable(n, B, 2, "random_walk", max_chain=20, batch_ops=1 << 20, hash_seed=105,
+                        rng_seed=205, stash=stash)
+        t.insert(dkeys, dvals, diagnostics=False)  # warm-up fill
+        t.clear()
+        sec = _timed(lambda: t.insert(dkeys, dvals, diagnostics=False))
+        st = t.stats()
+        t.lookup(dq)  # warm
+        lsec = _timed(lambda: t.lookup(dq))
+        out_v, found = t.lookup(dq)
+        res[f"stash{stash}"] = {
+            "inserts_per_s": m / sec, "lookups_per_s": nq / lsec,
+            "failed_inserts": st["inserts_failed"], "stashed_inserts": st["inserts_stashed"],
+            "lookup_hits": int(found.sum().item())}
+        total_ins += m
+        total_s += sec
+        print(f"# stash {stash}: {res[f'stash{stash}']}", file=sys.stderr, flush=True)
+        t.close()
+    print(json.dumps({
+        "metric": "inserts/s and lookups/s with and without a stash",
+        "value": total_ins / total_s, "unit": "inserts/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": total_s * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic (splitmix64 keys, seeded)",
+        "config": {"workload": "2^22 bins x 4 slots, 2 hash functions, random kicking with "
+                               "chains capped at 20, fill to 0.97 in sub-batches of 2^20, "
+                               "stash of 0 and 64 entries; 2^24 lookups at 0.9 hits"},
+        "by_case": res}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -548,6 +595,9 @@ def main():
         return
     if args.workload == "bias":
         run_bias(args)
+        return
+    if args.workload == "stash":
+        run_stash(args)
         return
     import torch
     from paper_1605_05236_amd import inputs

@@ -246,7 +246,8 @@ __device__ __forceinline__ void block_add2(unsigned long long a, unsigned long l
 // ---------------------------------------------------------------------------
 // lookup: LPP lanes per query, B/LPP slots per lane
 // ---------------------------------------------------------------------------
-template <int B, int LPP, int H>
+// EXT: the instance for tables with a stash or biased hashes.
+template <int B, int LPP, int H, bool EXT>
 __global__ __launch_bounds__(256) void k_lookup(Geo g, const uint64_t* __restrict__ keys,
                                                 uint64_t n, void* __restrict__ out,
                                                 uint8_t* __restrict__ found, DevStats* st,
@@ -269,7 +270,7 @@ __global__ __launch_bounds__(256) void k_lookup(Geo g, const uint64_t* __restric
     int winner = 0;
     if (x != kEmpty) {
       uint32_t h[H];
-      hash_key<H>(g, tab_of(g, op_table, tdesc, q), x, h);
+      hash_key<H, EXT>(g, tab_of(g, op_table, tdesc, q), x, h);
 #pragma unroll
       for (int hi = 0; hi < H; ++hi) {
         const ulonglong2* p = g.slots + (uint64_t)h[hi] * B + gl * SPL;
@@ -295,15 +296,48 @@ __global__ __launch_bounds__(256) void k_lookup(Geo g, const uint64_t* __restric
           break;
         }
       }
-      if (!hit && g.stash_n) {  // then the stash, one more probe
-        ++probes;
-        const uint32_t e = stash_find(g, table_of(op_table, q), x, gl, LPP, [&](bool p) {
-          return (uint64_t)((__ballot(p) >> gshift) & gmask);
-        });
-        if (e != kNone) {
-          hit = true;
-          winner = 0;
-          val = g.stash[e].y;
+    }
+    // Then the stash, one more probe for a query its bins did not answer.  A
+    // stash has at most 64 entries: each lane of the wavefront holds one key,
+    // and each unanswered query is compared with all of them in one ballot.
+    // A wavefront whose unanswered queries are of several tables (a group)
+    // searches per query group instead.
+    if (EXT && g.stash_n) {
+      const bool need = x != kEmpty && !hit;
+      if (need) ++probes;
+      const uint64_t needm = __ballot(need && gl == 0);
+      if (needm) {
+        const uint32_t t = need ? table_of(op_table, q) : 0u;
+        const uint32_t t0 = __shfl(t, __ffsll((unsigned long long)needm) - 1, 64);
+        if (__ballot(need && t != t0) == 0) {
+          if (g.stash_cnt[t0]) {
+            const uint32_t sb = t0 * g.stash_n;
+            const uint64_t ek = lane < (int)g.stash_n ? g.stash[sb + lane].x : kEmpty;
+            uint64_t rem = needm, got = 0, gv = 0;
+            while (rem) {  // wavefront-uniform
+              const int l = __ffsll((unsigned long long)rem) - 1;
+              const uint64_t mm = __ballot(ek == __shfl(x, l, 64));
+              if (mm) {
+                if (lane == l) gv = g.stash[sb + __ffsll((unsigned long long)mm) - 1].y;
+                got |= 1ull << l;
+              }
+              rem &= rem - 1;
+            }
+            if ((got >> gshift) & 1ull) {  // found by this query's group leader
+              hit = true;
+              winner = 0;
+              if (gl == 0) val = gv;
+            }
+          }
+        } else if (need) {
+          const uint32_t e = stash_find(g, t, x, gl, LPP, [&](bool p) {
+            return (uint64_t)((__ballot(p) >> gshift) & gmask);
+          });
+          if (e != kNone) {
+            hit = true;
+            winner = 0;
+            val = g.stash[e].y;
+          }
         }
       }
     }
@@ -326,8 +360,12 @@ static void lookup_go(const Geo& g, const uint64_t* keys, uint64_t n, void* out,
                       DevStats* st, const uint32_t* op_table, const uint2* tdesc, hipStream_t s) {
   const uint64_t blocks = (n * LPP + 255) / 256;
   const uint32_t grid = (uint32_t)std::min<uint64_t>(blocks, 8192);
-  hipLaunchKernelGGL((k_lookup<B, LPP, H>), dim3(grid), dim3(256), 0, s, g, keys, n, out, found,
-                     st, op_table, tdesc);
+  if (g.stash_n || g.hash_bias)
+    hipLaunchKernelGGL((k_lookup<B, LPP, H, true>), dim3(grid), dim3(256), 0, s, g, keys, n, out,
+                       found, st, op_table, tdesc);
+  else
+    hipLaunchKernelGGL((k_lookup<B, LPP, H, false>), dim3(grid), dim3(256), 0, s, g, keys, n, out,
+                       found, st, op_table, tdesc);
 }
 
 hipError_t launch_lookup(const Geo& g, const uint64_t* keys, uint64_t n, void* out,
