@@ -111,9 +111,10 @@ typedef struct {
                                 after the key's bins, as one more probe */
   uint32_t hash_bias;        /* 0: uniform hashes (Sec. 3).  1-4: biased hashes
                                 (Sec. 9): for each choice, w = mix64(a_i x + c_i)
-                                and, when the two low bits of w are below
-                                hash_bias, the bin is the lesser of the two
-                                draws', so low bins are favoured */
+                                (mix64: splitmix64's output function) and, when
+                                the two low bits of w are below hash_bias, the
+                                bin is the lesser of the bins of a_i x + c_i and
+                                of w, so low bins are favoured */
 } ck_options;
 
 /* Counters of one table since creation (or the last ck_stats_reset). */
@@ -124,7 +125,7 @@ typedef struct {
   uint64_t kicks, max_kicks, retries, rounds, twin_updates;
   uint64_t lookups, lookup_hits, lookup_probes;
   uint64_t deletes, deletes_found, delete_probes, delete_retries;
-  uint64_t stored;      /* distinct keys currently stored */
+  uint64_t stored;      /* distinct keys currently held, in bins or the stash */
   /* per 0.5 % density band: inserts, their bins viewed, kicks, failures;
      an op's density is the table's had its sub-batch been applied in op order */
   uint64_t band_inserts[CK_BANDS], band_views[CK_BANDS];
