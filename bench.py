@@ -40,7 +40,7 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 # shapes, host loop); once that source changes the benchmark reports null
 # until the counters are taken again.
 MEASURED_EVICT_TRAFFIC = {
-    "sources_sha256": "1833b354f1abc2216887acf13869cce2a415343d9c7e6747a009aa3e17de7ed5",
+    "sources_sha256": "9b1dfc36932f77ba36ffae35412e1c73c89522e39cffc8ecf9fbb9654eab068a",
     "bytes_per_launch": 36662140,
     "profile": "profiles/evict_planners__fill95_2e24x8.md",
 }

@@ -5,24 +5,29 @@
 //   k_lookup        lane group of LPP lanes per query; each probe loads one
 //                   bin as one coalesced 64/128-byte access and ballots for the
 //                   key (Sec. 1: the key is in one of its bins)
-//   k_plan_fresh    lane group of B lanes per pending insert: views the key's
-//                   bins and plans the placement when no kick-out is needed
-//                   (first fit, load balancing, ghost insertion, duplicate
-//                   reuse); every other op goes to its pass's region of the
-//                   evict list for an eviction planner
+//   k_plan_fresh    lane group of B/2 lanes per pending insert: views the
+//                   key's bins and plans the placement when no kick-out is
+//                   needed (first fit, load balancing, ghost insertion,
+//                   duplicate reuse); an upsert first looks for its key and,
+//                   if stored, plans the new value; every other op goes to its
+//                   wavefront's region of the evict list for an eviction planner
 //   k_plan_walk     eight walks per wavefront: random kicking, queue-kicking,
 //                   rattle-kicking; the chain is logged (LDS, then scratch)
 //                   and later bin reads see the chain's own earlier writes
-//   k_plan_search   four searches per wavefront: BFS and sorted search over
-//                   runs of B records, several frontier bins per load
-//   k_plan_delete   lane group per pending delete
+//   k_plan_search   four searches per wavefront: BFS, sorted search and their
+//                   hybrid over runs of B records, several frontier bins per
+//                   load
+//   k_plan_delete   lane group per pending delete or overwrite
 //   k_commit        2 lanes per plan: claim check, reverse-order chain write,
 //                   metadata atomics, spawn-count updates; the losers form
 //                   the next round's pending list
 //   k_stats_*       per-op counters -> totals and density bands
 //
 // Every planner reads the round-start snapshot only and claims each bin it
-// will write with a 64-bit atomicMin on the bin's claim word.
+// will write with a 64-bit atomicMin on the bin's claim word.  A failed insert
+// plan may claim a stash entry instead (Sec. 2).  The round kernels and the
+// lookup come in a plain instance and an extended one (upserts, a stash,
+// biased hashes).
 #include <hip/hip_runtime.h>
 
 #include "ck_internal.h"
