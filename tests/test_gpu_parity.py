@@ -270,6 +270,33 @@ def test_biased_hash_parity(geom, bias):
                             hash_bias=bias)
 
 
+@pytest.mark.parametrize("B,d,scheme", [(4, 2, "random_walk"), (1, 3, "rattle")])
+def test_stash_image_round_trip(B, d, scheme):
+    # A table with a full stash, built by the oracle alone, loaded into the
+    # library (ck_import then ck_import_stash): same image out, same answers,
+    # and the stashed keys count in `stored`.
+    n = 1 << 8
+    kw = dict(max_chain=4, max_search=8, stash=8)
+    o = oracle_table(n, B, d, scheme, seed=9, batch_ops=64, **kw)
+    keys, vals = keys_for(n, B, 1.1, seed=17)
+    ro = o.insert(keys, vals)
+    img = o.export()
+    assert (img["stash_keys"] != inputs.EMPTY).sum() == 8
+    g = gpu_table(n, B, d, scheme, seed=9, **kw)
+    g.load(img)
+    assert_same_image(g.export(), img, "round trip")
+    assert g.stats()["stored"] == o.stats()["stored"]
+    q = np.concatenate([keys, inputs.keys_values(18, 200)[0]])
+    for lpp in (0, 1):
+        vg, fg = gpu_lookup(g, q, lpp)
+        vo, fo = o.lookup(q)
+        assert np.array_equal(fg, fo) and np.array_equal(vg, vo)
+    held = keys[np.isin(ro["status"], (1, 6))]
+    d_ = np.concatenate([held[::3], img["stash_keys"][:4]])
+    assert np.array_equal(gpu_delete(g, d_), o.delete(d_)[0])
+    assert_same_image(g.export(), o.export(), "after deletes")
+
+
 @pytest.mark.parametrize("B,d", [(1, 2), (1, 3), (1, 4), (2, 2), (4, 2), (8, 2)])
 @pytest.mark.parametrize("lpp", [0, 1])
 def test_lookup_parity_on_imported_table(B, d, lpp):
