@@ -86,7 +86,8 @@ struct ck_table {
   // round scratch
   uint32_t batch_cap = 0;
   uint32_t* pend[2] = {nullptr, nullptr};
-  PlanHdr* hdr = nullptr;
+  uint4* hdr = nullptr;
+  uint2* hdr_spawn = nullptr;
   IMove* imv = nullptr;
   uint32_t* evict = nullptr;
   uint32_t* evict_cnt = nullptr;
@@ -162,6 +163,7 @@ void free_scratch(ck_table* t) {
   (void)hipFree(t->pend[0]);
   (void)hipFree(t->pend[1]);
   (void)hipFree(t->hdr);
+  (void)hipFree(t->hdr_spawn);
   (void)hipFree(t->imv);
   (void)hipFree(t->evict);
   (void)hipFree(t->evict_cnt);
@@ -205,6 +207,7 @@ ck_status alloc_scratch(ck_table* t) {
   HIP_TRY(dalloc(&t->pend[0], (size_t)kStripes * t->stripe_cap));
   HIP_TRY(dalloc(&t->pend[1], (size_t)kStripes * t->stripe_cap));
   HIP_TRY(dalloc(&t->hdr, m));
+  HIP_TRY(dalloc(&t->hdr_spawn, m));
   HIP_TRY(dalloc(&t->imv, (size_t)m * kExtraInline));
   // evict regions: one per fresh-planner wavefront (64 / lanes-per-op ops),
   // every wavefront of the last pass included
@@ -264,6 +267,7 @@ Round make_round(ck_table* t, const uint64_t* keys, const void* vals, uint8_t* s
   r.keys = keys;
   r.vals = vals;
   r.hdr = t->hdr;
+  r.hdr_spawn = t->hdr_spawn;
   r.imv = t->imv;
   r.evict = t->evict;
   r.evict_cnt = t->evict_cnt;

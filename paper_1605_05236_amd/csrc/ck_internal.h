@@ -53,23 +53,18 @@ enum : uint32_t {
   PL_FAIL = 0, PL_OK = 1, PL_EVICT = 2, PL_NOTFOUND = 3, PL_UPDATED = 4, PL_STASHED = 5
 };
 
-// Plan of one op of the sub-batch (32 bytes, one load in the commit kernel).
-// Plans of at most three moves that write only the op's own record keep them
-// inline: the first here, the others in the per-op inline array.
-// A plan's header, 32 bytes in two halves.  Inline plans (fresh placements,
-// deletes) are written and read as the first half only:
-//   {st, views, first move's bin, first move's slot | flags << 8}.
-// Arena plans (kick-out chains) set kHdrArena in st and use both halves:
-//   {st, views, arena offset of the moves, kicks}, {n_spawn, spawn_off, -, -}.
-struct PlanHdr {
-  uint32_t st;           // status | twins << 4 | n_moves << 8 | kHdrArena
-  uint32_t views;
-  uint32_t a;            // inline: first move's bin; arena: arena offset
-  uint32_t b;            // inline: first move's slot | flags << 8; arena: kicks
-  uint32_t n_spawn;      // arena plans: spawn list length (sorted search)
-  uint32_t spawn_off;    //              and its spawn arena offset
-  uint32_t pad[2];
-};
+// Plan of one op of the sub-batch: a 16-byte header (one load in the commit
+// kernel), in an array of its own so that the headers of consecutive ops fill
+// whole lines.  Plans of at most three moves that write only the op's own
+// record keep them inline: the first in the header, the others in the per-op
+// inline array.  The header is
+//   inline plans (fresh placements, deletes, overwrites):
+//     {st, views, first move's bin, first move's slot | flags << 8};
+//   arena plans (kick-out chains, kHdrArena set in st):
+//     {st, views, arena offset of the moves, kicks};
+// with st = status | twins << 4 | n_moves << 8 | flags (bits 28-30).  Arena
+// plans also have a spawn record {n_spawn, spawn_off} (sorted search: the
+// plan's spawn list in the spawn arena) in a second per-op array.
 constexpr uint32_t kHdrArena = 1u << 28;
 // Upsert of an absent key: the plan also holds a claim on the key's first bin
 // (which it may not write), so that two upserts of one new key conflict.
@@ -182,7 +177,8 @@ struct Round {
                              // opw = 64 / fresh_lanes(B)) puts its
                              // evict_cnt[u] ops at evict[u opw ...)
   uint32_t* evict_cnt;       // per fresh-planner wavefront
-  PlanHdr* hdr;
+  uint4* hdr;                // per op: the plan header
+  uint2* hdr_spawn;          // per op: arena plans' spawn record
   IMove* imv;                // kExtraInline per op
   Move* arena;
   uint32_t arena_cap;

@@ -662,7 +662,7 @@ __global__ __launch_bounds__(256) void k_plan_fresh(Geo g, Round r) {
       const bool key_claim = ups && !updated;
       const bool in_stash = stash_e != kNone;
       const uint32_t st = bad ? PL_FAIL : (updated ? PL_UPDATED : (placed ? PL_OK : PL_EVICT));
-      ((uint4*)r.hdr)[2 * (size_t)i] = make_uint4(
+      r.hdr[i] = make_uint4(
           hdr_pack(st, twins, nm) | (key_claim ? kHdrKeyClaim : 0u) | (in_stash ? kHdrStash : 0u),
           views + (key_claim ? (uint32_t)H + (g.stash_n ? 1u : 0u) : 0u), b0,
           in_stash ? stash_e : f0);
@@ -1057,17 +1057,14 @@ struct WalkPlanner {
     if (gl == 0) {
       // a failed chain's key goes to the stash if it has room
       const uint32_t se = (EXT && status == PL_FAIL) ? stash_take(g, r, i) : kNone;
-      PlanHdr hd{};
       // an upsert's plan adds the presence check's views and its key claim
       // (made by the fresh planner)
-      hd.st = hdr_pack(se != kNone ? PL_STASHED : status, status == PL_OK ? twins : 0, nm) |
-              kHdrArena | ((EXT && r.upsert) ? kHdrKeyClaim : 0u) | (se != kNone ? kHdrStash : 0u);
-      hd.views = views + ((EXT && r.upsert) ? (uint32_t)H + (g.stash_n ? 1u : 0u) : 0u);
-      hd.a = off;
-      hd.b = status == PL_OK ? kicks : (se != kNone ? se : 0u);
-      hd.n_spawn = 0;
-      hd.spawn_off = 0;
-      r.hdr[i] = hd;
+      r.hdr[i] = make_uint4(
+          hdr_pack(se != kNone ? PL_STASHED : status, status == PL_OK ? twins : 0, nm) |
+              kHdrArena | ((EXT && r.upsert) ? kHdrKeyClaim : 0u) | (se != kNone ? kHdrStash : 0u),
+          views + ((EXT && r.upsert) ? (uint32_t)H + (g.stash_n ? 1u : 0u) : 0u), off,
+          status == PL_OK ? kicks : (se != kNone ? se : 0u));
+      r.hdr_spawn[i] = make_uint2(0u, 0u);
       atomicAdd(wg_views, (unsigned long long)views);
     }
     wave_sync();
@@ -1848,15 +1845,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     if (have && gl == 0) {
       // a failed search's key goes to the stash if it has room
       const uint32_t se = (EXT && !found) ? stash_take(g, r, i) : kNone;
-      PlanHdr hd{};
-      hd.st = hdr_pack(found ? PL_OK : (se != kNone ? PL_STASHED : PL_FAIL), twin, nm) |
-              kHdrArena | ((EXT && r.upsert) ? kHdrKeyClaim : 0u) | (se != kNone ? kHdrStash : 0u);
-      hd.views = views + ((EXT && r.upsert) ? (uint32_t)H + (g.stash_n ? 1u : 0u) : 0u);
-      hd.a = off;
-      hd.b = found ? depth : (se != kNone ? se : 0u);
-      hd.n_spawn = nsp;
-      hd.spawn_off = soff;
-      r.hdr[i] = hd;
+      r.hdr[i] = make_uint4(
+          hdr_pack(found ? PL_OK : (se != kNone ? PL_STASHED : PL_FAIL), twin, nm) | kHdrArena |
+              ((EXT && r.upsert) ? kHdrKeyClaim : 0u) | (se != kNone ? kHdrStash : 0u),
+          views + ((EXT && r.upsert) ? (uint32_t)H + (g.stash_n ? 1u : 0u) : 0u), off,
+          found ? depth : (se != kNone ? se : 0u));
+      r.hdr_spawn[i] = make_uint2(nsp, soff);
       atomicAdd(&s_views, (unsigned long long)views);
     }
     wave_sync();
@@ -2030,7 +2024,7 @@ __device__ __forceinline__ void delete_one(const Geo& g, const Round& r, const G
   }
   if (!leader) return;
   const uint32_t fl = r.overwrite ? MV_VALUE : MV_CLEAR;
-  ((uint4*)r.hdr)[2 * (size_t)i] = make_uint4(
+  r.hdr[i] = make_uint4(
       hdr_pack(x == kEmpty ? PL_FAIL : status, 0, nm) | (se != kNone ? kHdrStash : 0u), probes,
       nm > 0 ? mb[0] : 0u, nm > 0 ? (ms[0] | (fl << 8)) : (se != kNone ? se : 0u));
   if (se != kNone) atomicMin(&g.stash_owner[se], r.tag | (unsigned long long)i);
@@ -2145,8 +2139,8 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
         requeue = true;
       } else {
         live = true;
-        // the header's first half; its second half only for arena plans
-        const uint4 h0 = ((const uint4*)r.hdr)[2 * (size_t)i];
+        // the header; the spawn record only for arena plans
+        const uint4 h0 = r.hdr[i];
         status = h0.x & 0xF;
         twins = (h0.x >> 4) & 0xF;
         nmv = (h0.x >> 8) & 0xFFFFF;
@@ -2157,7 +2151,7 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
         se = (EXT && (h0.x & kHdrStash)) ? h0.w : kNone;  // the stash entry the plan writes
         kicks = (inl || se != kNone) ? 0u : h0.w;
         if (!inl) {
-          const uint4 h1 = ((const uint4*)r.hdr)[2 * (size_t)i + 1];
+          const uint2 h1 = r.hdr_spawn[i];
           n_spawn = h1.x;
           spawn_off = h1.y;
         }
