@@ -219,3 +219,40 @@ def test_arena_growth_stays_bounded():
     _lookup_all(t, keys[ok], vals[ok])
     _absent(t, keys[~ok])
     assert checks.check_image_torch(t.export(), n, 1, d, 106) == int(ok.sum())
+
+
+def test_2e24x8_upsert_properties():
+    """The benchmark's table at 95% (queue-kicking), then one upsert call of
+    2^21 ops: 2^20 stored keys with new values interleaved with 2^20 absent
+    keys, the first 2^16 absent keys given twice more at the end.  A stored
+    key reports UPDATED, an absent key OK the first time and UPDATED after;
+    every key then holds the value of its last op, and nothing is stored twice."""
+    import torch
+    n, B = 1 << 24, 8
+    t = _table(n, B, 2, "queue", batch_ops=1 << 20, hash_seed=102, rng_seed=202)
+    m95 = inputs.target_count(n, B, 0.95)
+    keys, vals = inputs.keys_values_torch(2, m95)
+    st = t.insert(keys, vals, diagnostics=False)["status"]
+    assert bool((st == 1).all())
+    g = torch.Generator(device="cuda").manual_seed(403)
+    idx = torch.randperm(m95, generator=g, device="cuda")[: 1 << 20]
+    fresh, fresh_v = inputs.keys_values_torch(2, 1 << 20, start=m95)
+    new_v = torch.randint(0, 1 << 62, (1 << 20,), generator=g, device="cuda", dtype=torch.int64)
+    rep_v = torch.randint(0, 1 << 62, (1 << 16,), generator=g, device="cuda", dtype=torch.int64)
+    ups = torch.stack([keys[idx], fresh], dim=1).reshape(-1)
+    upv = torch.stack([new_v, fresh_v], dim=1).reshape(-1)
+    ups = torch.cat([ups, fresh[: 1 << 16]])
+    upv = torch.cat([upv, rep_v])
+    print(f"upsert {ups.numel()} ops at 95%", flush=True)
+    r = t.upsert(ups, upv, diagnostics=False)["status"]
+    head = r[: 1 << 21].reshape(-1, 2)
+    assert bool((head[:, 0] == 5).all()), "a stored key was not updated"
+    assert bool((head[:, 1] == 1).all()), "an absent key was not inserted"
+    assert bool((r[1 << 21:] == 5).all()), "a repeated new key was not updated"
+    final_v = fresh_v.clone()
+    final_v[: 1 << 16] = rep_v
+    _lookup_all(t, keys[idx], new_v)
+    _lookup_all(t, fresh, final_v)
+    stored = m95 + (1 << 20)
+    assert t.stats()["stored"] == stored
+    assert checks.check_image_torch(t.export(), n, B, 2, 102) == stored
