@@ -256,3 +256,33 @@ def test_2e24x8_upsert_properties():
     stored = m95 + (1 << 20)
     assert t.stats()["stored"] == stored
     assert checks.check_image_torch(t.export(), n, B, 2, 102) == stored
+
+
+def test_2e24x8_stash_properties():
+    """The benchmark's table filled to 98% by BFS with searches capped at 16
+    bins, so chains fail in the last sub-batches, with a 64-entry stash: 64
+    failures are stashed and found, the rest are absent, and the stash holds
+    no key that also sits in a bin."""
+    import torch
+    n, B = 1 << 24, 8
+    t = _table(n, B, 2, "bfs", max_search=16, batch_ops=1 << 20, hash_seed=102, rng_seed=202,
+               stash=64)
+    m = inputs.target_count(n, B, 0.98)
+    keys, vals = inputs.keys_values_torch(2, m)
+    print(f"fill to 98% with a stash ({m} keys)", flush=True)
+    st = t.insert(keys, vals, diagnostics=False)["status"]
+    n_ok, n_st, n_fail = (int((st == s).sum()) for s in (1, 6, 2))
+    assert n_ok + n_st + n_fail == m and n_fail > 0, (n_ok, n_st, n_fail)
+    assert n_st == 64
+    held = (st == 1) | (st == 6)
+    _lookup_all(t, keys[held], vals[held])
+    _absent(t, keys[st == 2])
+    assert t.stats()["stored"] == n_ok + n_st
+    assert t.stats()["inserts_stashed"] == 64
+    img = t.export()
+    assert checks.check_image_torch(img, n, B, 2, 102) == n_ok
+    sk = img["stash_keys"]
+    stashed = torch.from_numpy(sk.view(np.int64)).cuda()
+    assert bool((stashed != -1).all())
+    want = torch.sort(keys[st == 6]).values
+    assert bool((torch.sort(stashed).values == want).all())
