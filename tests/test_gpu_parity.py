@@ -319,8 +319,7 @@ def test_lookup_parity_on_imported_table(B, d, lpp):
 def test_edge_cases():
     g = gpu_table(64, 2, 2, "random_walk", seed=1, max_chain=0, batch_ops=16)
     o = oracle_table(64, 2, 2, "random_walk", seed=1, max_chain=0, batch_ops=16)
-    # empty batch
-    empty = np.zeros(0, np.uint64)
+    # a batch of one
     assert gpu_insert(g, np.array([5], np.uint64), np.array([6], np.uint64))["status"][0] == 1
     o.insert(np.array([5], np.uint64), np.array([6], np.uint64))
     # reserved key, cap of zero kicks (every eviction fails), ragged batch
@@ -331,14 +330,15 @@ def test_edge_cases():
     assert rg["status"][3] == 4 and (rg["status"] == 2).any()
     assert_same_image(g.export(), o.export(), "edge")
     assert_same_stats(g.stats(), o.stats(), "edge")
-    from paper_1605_05236_amd.table import CuckooTable
+    # empty batches of every call
     import torch
-    t = g
     z = torch.zeros(0, dtype=torch.int64, device="cuda")
-    assert t.insert(z, z)["status"].numel() == 0
-    assert t.lookup(z)[1].numel() == 0
-    assert t.delete(z).numel() == 0
-    del empty, CuckooTable
+    assert g.insert(z, z)["status"].numel() == 0
+    assert g.upsert(z, z)["status"].numel() == 0
+    assert g.lookup(z)[1].numel() == 0
+    assert g.delete(z).numel() == 0
+    assert g.overwrite(z, z).numel() == 0
+    assert_same_image(g.export(), o.export(), "after empty calls")
 
 
 @pytest.mark.parametrize("geom", [GEOMS[i] for i in (1, 4, 6, 10, 14, 17, 19)], ids=ident)
