@@ -67,3 +67,24 @@ def test_storage_bytes_and_geometry_checks(lib):
                          ctypes.byref(h)) == -1
     assert lib.ck_strerror(-1) == b"invalid argument"
     assert lib.ck_insert(None, None, None, 0, None, None) == -1
+
+
+def test_stash_and_bias_options_are_checked_before_device_work(lib):
+    from paper_1605_05236_amd import table
+    opt = table.CkOptions()
+    lib.ck_default_options(ctypes.byref(opt))
+    assert (opt.stash, opt.hash_bias) == (0, 0)  # no stash, uniform hashes
+    h = ctypes.c_void_p()
+    for field, bad in [("stash", 65), ("hash_bias", 5)]:
+        o = table.CkOptions()
+        lib.ck_default_options(ctypes.byref(o))
+        setattr(o, field, bad)
+        assert lib.ck_create(1 << 10, 4, 2, 0, ctypes.byref(o), ctypes.c_void_p(256), 1 << 20,
+                             None, ctypes.byref(h)) == -1, field
+    # the calls on a null handle are refused, whatever the size
+    assert lib.ck_upsert(None, None, None, 5, None, None, None, None, None) == -1
+    assert lib.ck_overwrite(None, None, None, 5, None, None) == -1
+    assert lib.ck_export_stash(None, None, None, None) == -1
+    assert lib.ck_import_stash(None, None, None, None) == -1
+    assert lib.ck_group_upsert(None, None, None, None, 5, None, None, None, None, None) == -1
+    assert lib.ck_group_export_stash(None, 0, None, None, None) == -1
