@@ -729,6 +729,20 @@ def main():
         bv95[s] = float(bvv[band] / max(1, bi[band]))
         cum[s] = st[s]["views"] / max(1, st[s]["inserts_ok"] + st[s]["inserts_failed"])
         fails[s] = st[s]["inserts_failed"]
+    # the whole insert path against the HBM roofline: per insert, its key and
+    # value in and status out (17 bytes), every bin viewed (line + 4-byte
+    # metadata word), and per record placed or moved one slot write (16) and
+    # one claim word (8)
+    ins_bytes, ins_total_bytes = {}, 0.0
+    for s in schemes:
+        done = max(1, st[s]["inserts_ok"] + st[s]["inserts_failed"])
+        kicks = st[s]["kicks"] / done
+        ins_bytes[s] = 17 + cum[s] * (B * 16 + 4) + (kicks + 1) * (16 + 8)
+        ins_total_bytes += ins_bytes[s] * m
+    ins_ach = ins_total_bytes / sum(fill.values()) / 1e9
+    insert_roof = {"bound": "hbm", "achieved": ins_ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                   "frac": ins_ach / PEAK_HBM_GBS, "bytes_per_insert": ins_bytes,
+                   "scope": "whole fill (all kernels), algorithmic bytes"}
     # lookup roofline: algorithmic bytes per query = key 8 + value 8 + found 1
     # + probes * 128-byte bin line (probes counted by the kernel itself)
     lt = tables[schemes[-1]].stats()
@@ -806,6 +820,7 @@ def main():
         "lookup_probes_per_query": probes_per_q,
         "roofline": roofline,
         "lookup_roofline": lookup_roof,
+        "insert_roofline": insert_roof,
         "kernel_ms_warmup_step": warm_ms,
         "dominant_kernel_class": dominant,
     }
