@@ -367,6 +367,15 @@ def test_enqueue_depth_parity(geom, depth):
     fg, fo = gpu_delete(g, pick), o.delete(pick)[0]
     assert np.array_equal(fg, fo), f"{geom} depth {depth} delete"
     assert_same_image(g.export(), o.export(), f"{geom} depth {depth} after deletes")
+    # upserts through the same gated re-enqueue path: the deleted half back,
+    # stored keys with new values, and new keys twice
+    nk, _ = keys_for(n, B, 0.02, seed=98)
+    up = np.concatenate([pick[: pick.size // 2], keys[:200], nk, nk[:50]])
+    uv = rng.integers(0, 1 << 63, up.size, dtype=np.uint64)
+    if B == 1:
+        uv &= np.uint64(0xFFFFFFFF)
+    assert_same_ops(gpu_upsert(g, up, uv), o.upsert(up, uv), f"{geom} depth {depth} upsert")
+    assert_same_image(g.export(), o.export(), f"{geom} depth {depth} after upserts")
     assert_same_stats(g.stats(), o.stats(), f"{geom} depth {depth}")
 
 
