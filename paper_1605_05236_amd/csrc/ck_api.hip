@@ -98,8 +98,8 @@ struct ck_table {
   uint32_t* op[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // views, lost, kicks, retries, twins
   unsigned long long* wg_views = nullptr;  // per eviction workgroup: bins viewed
   Ctr* ctr = nullptr;    // two sets: sub-batches alternate between them
-  Ctr* h_ctr = nullptr;  // pinned copies of the two sets
-  hipEvent_t ctr_ready[2] = {nullptr, nullptr};  // a set's copy has landed
+  HostSum* h_sum = nullptr;  // pinned: what the host needs of each set's sub-batch
+  hipEvent_t ctr_ready[2] = {nullptr, nullptr};  // a set's summary has landed
   void* wg_scratch = nullptr;
   uint32_t wg_bytes = 0;
   uint32_t evict_grid = 0;
@@ -171,7 +171,7 @@ void free_scratch(ck_table* t) {
   (void)hipFree(t->spawns);
   for (auto& p : t->op) (void)hipFree(p);
   (void)hipFree(t->ctr);
-  if (t->h_ctr) (void)hipHostFree(t->h_ctr);
+  if (t->h_sum) (void)hipHostFree(t->h_sum);
   for (auto& e : t->ctr_ready)
     if (e) (void)hipEventDestroy(e);
   (void)hipFree(t->wg_scratch);
@@ -226,7 +226,7 @@ ck_status alloc_scratch(ck_table* t) {
   HIP_TRY(dalloc(&t->spawns, t->spawn_cap));
   HIP_TRY(dalloc(&t->ctr, 2));
   HIP_TRY(hipMemset(t->ctr, 0, 2 * sizeof(Ctr)));
-  HIP_TRY(hipHostMalloc((void**)&t->h_ctr, 2 * sizeof(Ctr), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc((void**)&t->h_sum, 2 * sizeof(HostSum), hipHostMallocDefault));
   for (auto& e : t->ctr_ready) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   HIP_TRY(dalloc(&t->dstats, 1));
   HIP_TRY(hipMemset(t->dstats, 0, sizeof(DevStats)));
@@ -297,8 +297,9 @@ Round make_round(ck_table* t, const uint64_t* keys, const void* vals, uint8_t* s
 // device, so those rounds run capped grids that loop over whatever count
 // they find.  For a sub-batch the host enqueues as many rounds as the larger
 // of the last two insert sub-batches took (deletes: one more than the last
-// delete sub-batch), the statistics and a copy of its counters, and does so
-// one sub-batch ahead: sub-batch b + 1 is
+// delete sub-batch) and the statistics, whose first kernel writes the
+// host's summary of the sub-batch into pinned memory, and does so one
+// sub-batch ahead: sub-batch b + 1 is
 // enqueued before the host waits for b's counters.  Every kernel of b + 1
 // checks that b's last list came out empty (its gate) and otherwise does
 // nothing; the host then runs more rounds of b and enqueues b + 1 again.
@@ -307,12 +308,6 @@ Round make_round(ck_table* t, const uint64_t* keys, const void* vals, uint8_t* s
 // the next sub-batch's kernels read.  Sub-batches alternate between two sets
 // of round counters.
 constexpr uint32_t kMaxTailHint = 12;
-
-uint32_t list_count(const Ctr& c, int p) {
-  uint32_t n = 0;
-  for (uint32_t sg = 0; sg < kStripes; ++sg) n += c.cnt[p][sg * kStripeWords];
-  return n;
-}
 
 // One sub-batch in flight, as the host tracks it.
 struct Flight {
@@ -347,6 +342,7 @@ ck_status enqueue_rounds(ck_table* t, Flight& f, uint32_t K, bool first, const u
     r.first = first ? 1u : 0u;
     r.npend = (uint32_t)f.m;  // grid size; later rounds cap it
     r.ctr = c;
+    r.hsum = t->h_sum + f.set;
     r.gate = gate;
     r.pend = t->pend[f.cur];
     r.pcnt = first ? nullptr : c->cnt[f.cur];
@@ -377,11 +373,11 @@ ck_status enqueue_rounds(ck_table* t, Flight& f, uint32_t K, bool first, const u
     T.end(TK_COMMIT, ev, s);
     f.cur ^= 1;
   }
-  // the statistics (gated on this list and the gate), then the counters' copy
+  // the statistics (gated on this list and the gate); their first kernel
+  // writes the summary the host reads once this event has completed
   hipEvent_t ev = T.begin(s, TK_STATS);
   HIP_TRY(launch_batch_stats(r, f.m, f.slots, t->block_tmp, r.is_delete, c->cnt[f.cur], s));
   T.end(TK_STATS, ev, s);
-  HIP_TRY(hipMemcpyAsync(t->h_ctr + f.set, c, sizeof(Ctr), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipEventRecord(t->ctr_ready[f.set], s));
   return CK_OK;
 }
@@ -391,7 +387,7 @@ ck_status enqueue_rounds(ck_table* t, Flight& f, uint32_t K, bool first, const u
 ck_status settle(ck_table* t, Flight& f, hipStream_t s, bool* done) {
   HIP_TRY(hipEventSynchronize(t->ctr_ready[f.set]));
   t->timer.collect();
-  const Ctr& c = t->h_ctr[f.set];
+  const HostSum& c = t->h_sum[f.set];
   if (c.overflow || c.overflow_seen) {  // a void round: a larger arena for what follows
     ck_status st = grow_arena(t);
     if (st != CK_OK) return st;
@@ -400,7 +396,7 @@ ck_status settle(ck_table* t, Flight& f, hipStream_t s, bool* done) {
     // or each later look would grow the arena again
     HIP_TRY(hipMemsetAsync(&t->ctr[f.set].overflow, 0, 2 * sizeof(uint32_t), s));
   }
-  *done = list_count(c, f.cur) == 0;
+  *done = c.done != 0;
   if (*done) {
     if (!f.r.is_delete) t->rounds += c.rounds;
     if (!f.r.is_delete) t->tail_prev = t->tail_hint;

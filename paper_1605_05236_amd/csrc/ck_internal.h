@@ -111,6 +111,14 @@ struct Ctr {             // device counters of the round loop
   uint32_t cnt[2][kStripes * kStripeWords];  // segment counts of pending list p
 };
 
+// What the host needs of a sub-batch after its enqueued rounds, written by the
+// first statistics kernel straight into pinned host memory (no copy launch):
+// whether its last list came out empty, the arena-overflow flags and the
+// rounds that committed.
+struct HostSum {
+  uint32_t done, overflow, overflow_seen, rounds;
+};
+
 // Device accumulators (they mirror ck_stats), in kStatStripes copies:
 // workgroup w adds into copy w % kStatStripes, so the few adds per workgroup
 // of a statistics or lookup launch spread over separate lines instead of
@@ -202,6 +210,7 @@ struct Round {
   void* wg_scratch;          // per-workgroup scratch of the eviction planners
   uint32_t wg_scratch_bytes;
   DevStats* stats;
+  HostSum* hsum;             // pinned host memory of the sub-batch's counter set
 };
 
 // ---- launchers (ck_kernels.hip) ----

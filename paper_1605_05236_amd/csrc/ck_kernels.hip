@@ -2278,16 +2278,27 @@ constexpr int kStatBlock = 1024;
 // one before it has (its gate flag is set): the statistics kernels then leave
 // everything untouched.  One wavefront per workgroup reads the counts; every
 // thread of the workgroup calls it.  With `record`, workgroup 0 stores the
-// outcome in `unfinished` (the next sub-batch's gate).
+// outcome in `unfinished` (the next sub-batch's gate) and, when given, the
+// host's summary of the sub-batch in pinned memory.
 __device__ __forceinline__ bool stats_closed_out(const uint32_t* open, const uint32_t* gate,
-                                                 uint32_t* unfinished, bool record) {
+                                                 uint32_t* unfinished, bool record,
+                                                 const Ctr* c = nullptr,
+                                                 HostSum* hsum = nullptr) {
   __shared__ uint32_t s_open;
   if (threadIdx.x < 64) {
-    bool o = gate && *gate;
-    o = o || (open && list_open(open));
+    const bool own = open && list_open(open);  // all 64 lanes
+    const bool o = (gate && *gate) || own;
     if (threadIdx.x == 0) {
       s_open = o ? 1u : 0u;
-      if (record && blockIdx.x == 0) *unfinished = o ? 1u : 0u;
+      if (record && blockIdx.x == 0) {
+        *unfinished = o ? 1u : 0u;
+        if (hsum) {  // for the host, straight to pinned memory
+          hsum->done = own ? 0u : 1u;
+          hsum->overflow = c->overflow;
+          hsum->overflow_seen = c->overflow_seen;
+          hsum->rounds = c->rounds;
+        }
+      }
     }
   }
   __syncthreads();
@@ -2313,7 +2324,8 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_count(const uint8_t* statu
                                                             const DevStats* st,
                                                             const uint32_t* open,
                                                             const uint32_t* gate,
-                                                            uint32_t* unfinished) {
+                                                            uint32_t* unfinished, const Ctr* ctr,
+                                                            HostSum* hsum) {
   __shared__ uint32_t s_w[kStatBlock / 64];
   const StatSplit sp(m, gridDim.x);
   const uint32_t t0 = blockIdx.x * sp.per, t1 = min(sp.ntiles, t0 + sp.per);
@@ -2324,7 +2336,7 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_count(const uint8_t* statu
     // every key the sub-batch adds to the table, placed or stashed
     n += (i < m && (status[i] == CK_OP_OK || status[i] == CK_OP_STASHED)) ? 1u : 0u;
   }
-  if (stats_closed_out(open, gate, unfinished, true)) return;
+  if (stats_closed_out(open, gate, unfinished, true, ctr, hsum)) return;
   n = (uint32_t)wave_sum(n);
   if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = n;
   __syncthreads();
@@ -2520,8 +2532,9 @@ __global__ __launch_bounds__(kStatBlock) void k_stats_delete(const uint8_t* stat
                                                              DevStats* st, const uint32_t* open,
                                                              const uint32_t* gate,
                                                              uint32_t* unfinished,
-                                                             uint32_t count) {
-  if (stats_closed_out(open, gate, unfinished, true)) return;
+                                                             uint32_t count, const Ctr* ctr,
+                                                             HostSum* hsum) {
+  if (stats_closed_out(open, gate, unfinished, true, ctr, hsum)) return;
   if (!count) return;  // overwrites: no counters, only the completion flag
   unsigned long long d = 0, f = 0, p = 0, rt = 0;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
@@ -2553,13 +2566,13 @@ hipError_t launch_batch_stats(const Round& r, uint64_t m, uint64_t slots, uint32
   if (is_delete) {
     hipLaunchKernelGGL(k_stats_delete, dim3(std::min<uint32_t>(nb, 256)), dim3(kStatBlock), 0, s,
                        r.status, r.op_views, r.op_retries, m, r.stats, open, r.gate,
-                       &r.ctr->unfinished, r.overwrite ? 0u : 1u);
+                       &r.ctr->unfinished, r.overwrite ? 0u : 1u, r.ctr, r.hsum);
     return hipGetLastError();
   }
   uint64_t* stored_before = (uint64_t*)(block_tmp + ((nb + 63) & ~63u));
   const uint32_t grid = std::min<uint32_t>(nb, kStatMaxGrid);
   hipLaunchKernelGGL(k_stats_count, dim3(grid), dim3(kStatBlock), 0, s, r.status, m, block_tmp,
-                     stored_before, r.stats, open, r.gate, &r.ctr->unfinished);
+                     stored_before, r.stats, open, r.gate, &r.ctr->unfinished, r.ctr, r.hsum);
   hipLaunchKernelGGL(k_stats_apply, dim3(grid), dim3(kStatBlock), 0, s, r.status, r.op_views,
                      r.op_lost, r.op_kicks, r.op_retries, r.op_twins, m, block_tmp,
                      stored_before, slots, r.stats, open, r.gate);
