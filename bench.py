@@ -40,8 +40,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 # shapes, host loop); once that source changes the benchmark reports null
 # until the counters are taken again.
 MEASURED_EVICT_TRAFFIC = {
-    "sources_sha256": "fa52a55791d98ef2046503de061d12e83561fb38861698df404725fec8d12b0a",
-    "bytes_per_launch": 37307090,
+    "sources_sha256": "83185d040ca3469929c6b156d250964e07866049d9923c3807dac9310f13dd76",
+    "bytes_per_launch": 37302854,
     "profile": "profiles/evict_planners__fill95_2e24x8.md",
 }
 _SOURCES = ("ck_kernels.hip", "ck_api.hip", "ck_internal.h")
