@@ -711,6 +711,13 @@ def main():
     found = fout.cpu().numpy().astype(bool)
     assert np.array_equal(found, present), "lookup answers differ from the generated mix"
 
+    # after the timed region: the same steps with no kernel timing at all, to
+    # show what the two HIP events around every launch of the dominant class
+    # (which `roofline` needs) cost the fills
+    plain = [step(False, False) for _ in range(args.steps)]
+    plain_rate = len(schemes) * m / sum(float(np.mean([r["fill_s"][s] for r in plain]))
+                                        for s in schemes)
+
     fill = {s: float(np.mean([r["fill_s"][s] for r in results])) for s in schemes}
     lookup_s = float(np.mean([r["lookup_s"] for r in results]))
     delete_s = float(np.mean([r["delete_s"] for r in results]))
@@ -813,6 +820,7 @@ def main():
         "failed_inserts": fails,
         "rounds_per_sub_batch": rounds,
         "lost_rounds_per_insert": retries,
+        "inserts_per_s_without_kernel_events": plain_rate,
         "lookups_per_s": nq / lookup_s,
         "deletes_per_s": dels.size / delete_s,
         "overwrites_per_s": dels.size / overwrite_s,
