@@ -638,3 +638,20 @@ def test_biased_hash_placement_and_dictionary():
         assert held == set(k[ok].tolist())
         got, found = t.lookup(k[ok])
         assert found.all()
+
+
+def test_upsert_views_follow_the_presence_check():
+    # R17: an upsert views the key's bins in hash order until it finds the key
+    # (views = 1 + that bin's position); an absent key views all H bins, then
+    # places as an insert (into an empty table: its first bin, one more view).
+    t = make(1 << 8, 4, 2, "bfs", batch_ops=1)
+    keys, vals = inputs.keys_values(71, 300)
+    r = t.upsert(keys, vals)
+    assert np.all(r["status"] == oracle.ST_OK)
+    assert np.all(r["views"][:20] == 3)  # 2 (presence) + 1 (first fit into h_0)
+    img = t.export()
+    where = {int(k): b // 4 for b, k in enumerate(img["keys"].tolist()) if k != int(EMPTY)}
+    r2 = t.upsert(keys, vals ^ np.uint64(1))
+    assert np.all(r2["status"] == oracle.ST_UPDATED)
+    for x, v in zip(keys.tolist(), r2["views"].tolist()):
+        assert v == 1 + t.hash(x).index(where[x])
