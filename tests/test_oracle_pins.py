@@ -655,3 +655,27 @@ def test_upsert_views_follow_the_presence_check():
     assert np.all(r2["status"] == oracle.ST_UPDATED)
     for x, v in zip(keys.tolist(), r2["views"].tolist()):
         assert v == 1 + t.hash(x).index(where[x])
+
+
+def test_stash_lookup_probes():
+    # R18: a lookup probes the key's bins in hash order, then the stash as one
+    # more probe; counted from the image and the hash, independently.
+    t = make(1 << 6, 4, 2, "random_walk", batch_ops=1, max_chain=3, stash=8)
+    keys, vals = inputs.keys_values(73, 300)
+    t.insert(keys, vals)
+    img = t.export()
+    assert (img["stash_keys"] != EMPTY).sum() == 8
+    where = {int(k): b // 4 for b, k in enumerate(img["keys"].tolist()) if k != int(EMPTY)}
+    stashed = set(img["stash_keys"][img["stash_keys"] != EMPTY].tolist())
+    q = np.concatenate([keys, inputs.keys_values(74, 50)[0]])
+    before = t.stats()["lookup_probes"]
+    _, found = t.lookup(q)
+    expect = 0
+    for x, f in zip(q.tolist(), found.tolist()):
+        if x in where:
+            expect += 1 + t.hash(x).index(where[x])
+            assert f == 1
+        else:
+            expect += 2 + 1  # both bins, then the stash
+            assert f == (1 if x in stashed else 0)
+    assert t.stats()["lookup_probes"] - before == expect
