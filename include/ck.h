@@ -141,13 +141,18 @@ typedef struct {
    batch_ops 2^20, hash_seed 0, rng_seed 0. */
 void ck_default_options(ck_options* opt);
 
-/* Device bytes a table of this geometry needs (slots, per-bin metadata word,
-   per-bin claim word).  Errors: CK_EINVAL for an unsupported geometry. */
+/* Device bytes a table of this geometry needs: n bins of B slots (Sec. 1;
+   single-slot bins with d choices, Sec. 7), plus the per-bin metadata word
+   (duplicate marks of Sec. 4, spawn count of Sec. 5, hit counter of Sec. 6)
+   and the per-bin claim word (Sec. 8.2).  Pure host arithmetic, no device
+   call.  Errors: CK_EINVAL for an unsupported geometry or a null `out`. */
 ck_status ck_storage_bytes(uint64_t bins, uint32_t slots_per_bin, uint32_t d, size_t* out);
 
-/* Create a table in caller-owned device memory `d_storage` (>= storage bytes,
-   256-byte aligned; must outlive the table) and initialise it to empty on
-   `stream`.  Geometry: 1 <= bins < 2^32 and bins >= d; slots_per_bin in
+/* Create a table (Sec. 1: n bins of B slots, two hash functions; Sec. 7: d
+   hash functions over single-slot bins; the scheme is one of the kick-out
+   mechanisms of Secs. 1, 5, 6 and 7) in caller-owned device memory
+   `d_storage` (>= storage bytes, 256-byte aligned; must outlive the table)
+   and initialise it to empty on `stream`.  Geometry: 1 <= bins < 2^32 and bins >= d; slots_per_bin in
    {1, 2, 4, 8}; d in {2, 3, 4}; d > 2 needs slots_per_bin == 1; CK_RATTLE needs
    slots_per_bin == 1; CK_QUEUE and ghosts need d == 2.  The library allocates
    its own round scratch with hipMalloc (released by ck_destroy). */
@@ -156,7 +161,9 @@ ck_status ck_create(uint64_t bins, uint32_t slots_per_bin, uint32_t d, ck_scheme
                     void* stream, ck_table** out);
 
 /* Empty the table (every slot, metadata and claim word), zero its counters and
-   restart its insert-op count, on `stream`; storage and scratch are kept. */
+   restart its insert-op count, on `stream`; storage and scratch are kept.
+   After it the table is the empty table of Sec. 3's experiments (every
+   experiment fills from empty).  Errors: CK_EINVAL for a null handle. */
 ck_status ck_clear(ck_table* t, void* stream);
 
 /* Insert n keys with their values (8-byte values, 4-byte for single-slot
@@ -212,7 +219,11 @@ ck_status ck_upsert(ck_table* t, const uint64_t* d_keys, const void* d_vals, uin
                     uint8_t* d_status, uint32_t* d_views, uint32_t* d_kicks,
                     uint32_t* d_retries, void* stream);
 
-/* Copy the counters to host memory (synchronises `stream`). */
+/* Copy the counters to host memory (synchronises `stream`).  The counters are
+   the paper's cost measures: bins viewed per insertion by density (Sec. 3),
+   kick-out chain lengths (Sec. 5), failures, and the rounds lost to claims
+   (Sec. 8.2).  Errors: CK_EINVAL for a null handle or `h_out`; CK_EDEVICE when
+   the copy fails.  ck_stats_reset zeroes them (not `stored`). */
 ck_status ck_stats_get(ck_table* t, ck_stats* h_out, void* stream);
 ck_status ck_stats_reset(ck_table* t, void* stream);
 
@@ -243,8 +254,11 @@ ck_status ck_timing_enable(ck_table* t, uint32_t class_mask);
 /* Synchronises `stream`, then copies the timing gathered since enabling. */
 ck_status ck_timing_get(ck_table* t, ck_timing* h_out, void* stream);
 
-/* Canonical image of the table in host memory: per slot key, value (zero
-   extended for 32-bit values) and rattle counter; per bin the metadata word
+/* Canonical image of the table in host memory, the same layout the oracle
+   writes, so two images compare byte for byte: per slot key (Sec. 1), value
+   (zero extended for 32-bit values) and rattle counter (Sec. 7); per bin the
+   metadata word (duplicate marks, Sec. 4; spawn count, Sec. 5; hit counter,
+   Sec. 6)
      bits 0-7 duplicate marks, bits 8-11 spawn count, bits 24-31 hit counter.
    Arrays hold bins*slots_per_bin (keys, vals, rattle) and bins (meta)
    entries.  Export synchronises `stream`; import recomputes `stored`. */
@@ -261,17 +275,21 @@ ck_status ck_export_stash(ck_table* t, uint64_t* h_keys, uint64_t* h_vals, void*
 ck_status ck_import_stash(ck_table* t, const uint64_t* h_keys, const uint64_t* h_vals,
                           void* stream);
 
-/* Hash a key as the table does (the d bin indices, in order). */
+/* Hash a key as the table does: its d distinct bin indices h_0..h_{d-1}, in
+   order (Sec. 1, Sec. 7).  Host arithmetic, no device call. */
 ck_status ck_hash(const ck_table* t, uint64_t key, uint64_t* h_bins_out);
 
 /* Number of insert ops submitted so far (the id of the next insert op). */
 uint64_t ck_insert_count(const ck_table* t);
 
 /* Release the handle and the library's scratch; the caller's storage is not
-   freed.  Synchronises the device. */
+   freed.  Synchronises the device.  Not a paper operation: resource
+   management of the C ABI.  Errors: none (a null handle is ignored). */
 ck_status ck_destroy(ck_table* t);
 
 /* ---- groups: many independent tables of uneven sizes served together ----
+   Not a paper operation: the batched form of the calls above (the paper's
+   tables, Sec. 1, many at once), for callers that hold many small tables.
    A group holds n_tables tables (bins[i] bins each; same slots_per_bin, d,
    scheme and options) in one caller allocation.  Every op names its table
    (d_table[i] < n_tables); one call serves ops of any mix of tables with the

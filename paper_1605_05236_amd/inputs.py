@@ -52,18 +52,24 @@ def target_count(bins: int, slots_per_bin: int, load: float) -> int:
 
 
 def lookup_mix(seed: int, stored_keys: np.ndarray, absent_start: int, count: int,
-               hit_rate: float, key_seed: int):
+               hit_rate: float, key_seed: int, return_index: bool = False):
     """``count`` query keys: a ``hit_rate`` share drawn uniformly from
     ``stored_keys`` and the rest fresh (never inserted) keys from record index
     ``absent_start`` of the key stream ``key_seed``; shuffled together.
-    Returns (queries, expected_present)."""
+    Returns (queries, expected_present), and with ``return_index`` also each
+    query's index into ``stored_keys`` (-1 for an absent key), so a caller can
+    check returned values against the values it stored."""
     rng = np.random.default_rng(seed)
     n_hit = int(round(hit_rate * count))
-    hits = stored_keys[rng.integers(0, stored_keys.size, n_hit)]
+    src = rng.integers(0, stored_keys.size, n_hit)
+    hits = stored_keys[src]
     absent, _ = keys_values(key_seed, count - n_hit, start=absent_start)
     q = np.concatenate([hits, absent])
     present = np.concatenate([np.ones(n_hit, bool), np.zeros(count - n_hit, bool)])
     perm = rng.permutation(count)
+    if return_index:
+        idx = np.concatenate([src, np.full(count - n_hit, -1, np.int64)])
+        return q[perm], present[perm], idx[perm]
     return q[perm], present[perm]
 
 

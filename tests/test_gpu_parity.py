@@ -25,6 +25,7 @@ GEOMS = [
     ("random_walk", 1, 4, False, False),
     ("bfs", 4, 2, False, False),
     ("bfs", 8, 2, True, False),
+    ("bfs", 8, 2, False, False),
     ("bfs", 1, 4, False, False),
     ("sorted", 4, 2, False, False),
     ("sorted", 8, 2, False, False),
@@ -32,6 +33,7 @@ GEOMS = [
     ("sorted", 1, 3, False, False),
     ("queue", 4, 2, False, False),
     ("queue", 8, 2, True, False),
+    ("queue", 8, 2, False, False),
     ("queue", 2, 2, False, False),
     ("rattle", 1, 2, False, False),
     ("rattle", 1, 3, False, False),
