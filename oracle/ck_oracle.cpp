@@ -118,6 +118,11 @@ struct Table {
   std::vector<Slot> stash;      // the stash (Sec. 2): key kEmpty marks a free entry
   uint64_t insert_count = 0;    // global index of the next insert op
   Stats st;
+  // Optional record of every spawn-count increment (Sec. 5): the insert op
+  // whose plan spawned a record, and the bin the record sat in.  Plans that
+  // fail or lose a claim are recorded too, as their increments apply.
+  bool log_spawns = false;
+  std::vector<std::pair<uint64_t, uint64_t>> spawn_log;
 
   BinState bin(uint64_t b) const { return bins[b]; }
 
@@ -686,7 +691,10 @@ uint32_t run_rounds(Table& T, const std::vector<uint64_t>& ids, PlanFn plan_fn,
       }
     }
     for (auto& pl : plans)
-      for (uint64_t b : pl.spawns) T.bins[b].sc = (uint8_t)std::min(15, T.bins[b].sc + 1);
+      for (uint64_t b : pl.spawns) {
+        T.bins[b].sc = (uint8_t)std::min(15, T.bins[b].sc + 1);
+        if (T.log_spawns) T.spawn_log.push_back({pl.op, b});
+      }
     ++round;
     pending.swap(next);
   }
@@ -733,6 +741,25 @@ void* ck_oracle_create(uint64_t n, int B, int H, int scheme, int ghost, int load
 }
 
 void ck_oracle_destroy(void* t) { delete (Table*)t; }
+
+// Start (on != 0) or stop recording spawn-count increments; starting clears
+// the record.
+void ck_oracle_log_spawns(void* tp, int on) {
+  Table& T = *(Table*)tp;
+  T.log_spawns = on != 0;
+  if (T.log_spawns) T.spawn_log.clear();
+}
+
+// The recorded increments in the order they were applied: (insert op index,
+// bin) pairs, at most `cap` of them copied.  Returns how many were recorded.
+uint64_t ck_oracle_spawn_log(void* tp, uint64_t* ops, uint64_t* bins, uint64_t cap) {
+  Table& T = *(Table*)tp;
+  for (uint64_t k = 0; k < T.spawn_log.size() && k < cap; ++k) {
+    ops[k] = T.spawn_log[k].first;
+    bins[k] = T.spawn_log[k].second;
+  }
+  return T.spawn_log.size();
+}
 
 // Biased hashing of level k (0: uniform, up to 4), set on an empty table.
 int ck_oracle_set_hash_bias(void* tp, uint32_t k) {

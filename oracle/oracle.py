@@ -74,6 +74,9 @@ def lib():
         L.ck_oracle_import_stash.argtypes = [vp, vp, vp]
         L.ck_oracle_import.argtypes = [vp, vp, vp, vp, vp]
         L.ck_oracle_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
+        L.ck_oracle_log_spawns.argtypes = [vp, i32]
+        L.ck_oracle_spawn_log.argtypes = [vp, vp, vp, u64]
+        L.ck_oracle_spawn_log.restype = u64
         L.ck_oracle_insert_count.restype = u64
         L.ck_oracle_insert_count.argtypes = [vp]
         _lib = L
@@ -208,6 +211,18 @@ class OracleTable:
         for f in ("band_inserts", "band_views", "band_kicks", "band_fails"):
             out[f] = np.array(list(getattr(s, f)), dtype=np.uint64)
         return out
+
+    def log_spawns(self, on=True):
+        """Start (clearing it) or stop the record of spawn-count increments."""
+        lib().ck_oracle_log_spawns(self._t, int(bool(on)))
+
+    def spawn_log(self):
+        """(insert op index, bin) of every spawn-count increment recorded, in
+        the order applied."""
+        cnt = int(lib().ck_oracle_spawn_log(self._t, None, None, 0))
+        ops, bins = np.zeros(cnt, np.uint64), np.zeros(cnt, np.uint64)
+        lib().ck_oracle_spawn_log(self._t, _p(ops), _p(bins), cnt)
+        return ops, bins
 
     @property
     def insert_count(self) -> int:

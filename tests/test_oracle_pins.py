@@ -679,3 +679,234 @@ def test_stash_lookup_probes():
             expect += 2 + 1  # both bins, then the stash
             assert f == (1 if x in stashed else 0)
     assert t.stats()["lookup_probes"] - before == expect
+
+
+# --------------------------------------------------------------------------- hash test vector
+def test_hash_worked_vector():
+    # A fixed vector of the hash reading (multiply-shift with multipliers from
+    # splitmix64 of the hash seed, Sec. 1 / Sec. 3): hash seed 101 gives
+    # a_0, c_0, a_1, c_1 below, and the key 0x910a2dec89025cc1 (the first
+    # output of splitmix64 seeded with 1) lands in bins 13072 and 56838 of a
+    # 2^16-bin table.  The values were worked out once from the definition.
+    a, c = checks.hash_params(101, 2)
+    assert a == [0xD1024A5FAD64D717, 0x44C666B6B3E8BA5B]
+    assert c == [0x0466A7D0954B76A3, 0x8DF8FB6DA7904E2F]
+    assert int(inputs.splitmix64(1, 0, 1)[0]) == 0x910A2DEC89025CC1
+    t = make(1 << 16, B=4, d=2, seed=1)
+    assert t.hash(0x910A2DEC89025CC1) == [13072, 56838]
+
+
+# --------------------------------------------------------------------------- hand traces
+# Each trace below was worked out once by hand from the definitions: the
+# bins from the hash reading, the walk's choices from the counter-based draws
+# rand(op, t) = mix64(rng_seed ^ op * 0x9E3779B97F4A7C15 ^ (t + 1)) with a
+# choice among m options floor(rand * m / 2^64) (one draw per choice among
+# more than one option).  Keys k0, k1, ... are splitmix64(seed 9) outputs
+# 0, 2, 4, ... (values 1, 3, 5, ...).  Images are written bin by bin as key
+# indices, '-' for an empty slot.
+
+def _image_as_indices(img, keys, n, B):
+    idx = {int(k): i for i, k in enumerate(keys)}
+    out = []
+    for b in range(n):
+        row = []
+        for s in range(B):
+            k = img["keys"][b * B + s]
+            row.append("-" if k == EMPTY else idx[int(k)])
+        out.append(row)
+    return out
+
+
+def test_trace_random_walk_two_choice():
+    # Sec. 1 random kicking, n = 4 bins x 2 slots, first fit, hash seed 111,
+    # walk seed 211, serial.  Bins: k0 (1,3) k1 (1,2) k2 (0,1) k3 (1,2)
+    # k4 (1,3) k5 (1,2) k6 (1,0) k7 (0,1) k8 (2,1).
+    #   k0..k2 take the first bin (1 view each); k3, k4, k5 find bin 1 full and
+    #   take their second bin (2 views); k6 finds bin 1 full, takes bin 0.
+    #   k7: bins 0 and 1 full (2 views).  Draws of op 7 with m = 2: 0, 0, 0.
+    #     bin = h_0 = 0; slot 0 holds k2 -> k7 there (kick 1); k2's other bin
+    #     is 1, viewed (3), full; slot 0 holds k0 -> k2 there (kick 2); k0's
+    #     other bin is 3, viewed (4), slot 1 free -> k0 there.
+    #   k8 with chains capped at 3 kicks: bins 2 and 1 full (2 views).  Draws
+    #     of op 8: 1, 0, 1, 0.  bin = h_1 = 1, slot 0 (k2) -> kick 1, k2 to
+    #     bin 0 (view 3); slot 1 (k6) -> kick 2, k6 to bin 1 (view 4); slot 0
+    #     (k8 itself) -> kick 3, k8 to bin 2 (view 5), full: a fourth kick is
+    #     needed, so the insert fails and the table stays as it was.
+    keys, vals = inputs.keys_values(9, 9)
+    t = oracle.OracleTable(4, 2, 2, "random_walk", max_chain=3, batch_ops=1, hash_seed=111,
+                           rng_seed=211)
+    r = t.insert(keys[:8], vals[:8])
+    assert r["status"].tolist() == [1] * 8
+    assert r["views"].tolist() == [1, 1, 1, 2, 2, 2, 2, 4]
+    assert r["kicks"].tolist() == [0, 0, 0, 0, 0, 0, 0, 2]
+    want = [[7, 6], [2, 1], [3, 5], [4, 0]]
+    img = t.export()
+    assert _image_as_indices(img, keys, 4, 2) == want
+    r = t.insert(keys[8:9], vals[8:9])
+    assert r["status"].tolist() == [oracle.ST_FAIL] and r["views"].tolist() == [5]
+    img2 = t.export()
+    assert np.array_equal(img2["keys"], img["keys"]) and np.array_equal(img2["vals"], img["vals"])
+
+
+def test_trace_random_walk_three_choice():
+    # Sec. 1 random kicking with d = 3 single-slot bins (Sec. 7), n = 8, hash
+    # seed 119, walk seed 220, serial.  Bins: k0 (6,3,4) k1 (4,3,5) k2 (5,7,6)
+    # k3 (0,5,3) k4 (6,3,5) k5 (4,3,5).
+    #   k0..k3 take h_0 (1 view); k4 finds bin 6 full and takes bin 3 (2).
+    #   k5: bins 4, 3, 5 full (3 views).  Draws of op 5: 0x2ca5976bc2056795,
+    #     0x5b54018428757979, 0xcb3f699a9270e109, 0x462040449b6cdf82.
+    #     Among 3: 0 -> h_0 = 4, occupant k1; k5 there (kick 1).  k1's other
+    #     bins (3,5), among 2: 0 -> bin 3, viewed (4), holds k4; k1 there
+    #     (kick 2).  k4's other bins (6,5): 1 -> bin 5, viewed (5), holds k2;
+    #     k4 there (kick 3).  k2's other bins (7,6): 0 -> bin 7, viewed (6),
+    #     empty: k2 there.
+    keys, vals = inputs.keys_values(9, 6, value_bits=32)
+    t = oracle.OracleTable(8, 1, 3, "random_walk", max_chain=1000, batch_ops=1, hash_seed=119,
+                           rng_seed=220)
+    r = t.insert(keys, vals)
+    assert r["views"].tolist() == [1, 1, 1, 1, 2, 6]
+    assert r["kicks"].tolist() == [0, 0, 0, 0, 0, 3]
+    assert _image_as_indices(t.export(), keys, 8, 1) == [[3], ["-"], ["-"], [1], [5], [4], [0],
+                                                         [2]]
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_trace_rattle(d):
+    # Sec. 7 rattle-kicking (reading: one counter increment per try; the
+    # occupant keeps its bin on a tie).  A carried key (x, r) tries bin
+    # h_{r mod d}, then r += 1; into an empty bin it is stored with r; against
+    # an occupant (y, r_y) it takes the bin only if r > r_y, and y moves on.
+    if d == 2:
+        # n = 4, hash seed 128: k0 (1,2) k1 (3,0) k2 (2,3) k3 (3,2).
+        #   k0, k1, k2 store at h_0 with r = 1.  k3: bin 3 holds (k1,1), r = 1
+        #   is no larger; bin 2 holds (k2,1), r = 2 wins (kick 1); k2 (r 1)
+        #   tries its h_1 = 3 with r = 2, beats (k1,1) (kick 2); k1 (r 1)
+        #   tries h_1 = 0 with r = 2: empty.  4 views.
+        n, hs, m = 4, 128, 4
+        want_img = [[1], [0], [3], [2]]
+        want_r = [2, 1, 2, 2]
+        views, kicks = [1, 1, 1, 4], [0, 0, 0, 2]
+    else:
+        # n = 6, hash seed 113: k0 (2,3,1) k1 (4,3,1) k2 (5,3,4) k3 (3,4,2)
+        # k4 (2,3,4).  k0..k3 store at h_0 with r = 1.  k4: bin 2 holds
+        #   (k0,1), a tie; bin 3 holds (k3,1), r = 2 wins (kick 1); k3 tries
+        #   h_1 = 4 with r = 2, beats (k1,1) (kick 2); k1 tries h_1 = 3 with
+        #   r = 2 against (k4,2), a tie; then h_2 = 1 with r = 3: empty.
+        #   5 views.
+        n, hs, m = 6, 113, 5
+        want_img = [["-"], [1], [0], [4], [3], [2]]
+        want_r = [0, 3, 1, 2, 2, 1]
+        views, kicks = [1, 1, 1, 1, 5], [0, 0, 0, 0, 2]
+    keys, vals = inputs.keys_values(9, m, value_bits=32)
+    t = oracle.OracleTable(n, 1, d, "rattle", max_chain=40, batch_ops=1, hash_seed=hs)
+    r = t.insert(keys, vals)
+    assert r["views"].tolist() == views and r["kicks"].tolist() == kicks
+    img = t.export()
+    assert _image_as_indices(img, keys, n, 1) == want_img
+    assert img["rattle"].tolist() == want_r
+
+
+# --------------------------------------------------------------------------- spawn counts
+def _serial_with_images(t, keys, vals):
+    """Insert one key at a time; the image before each op and each op's result."""
+    before, res = [], []
+    for k, v in zip(keys, vals):
+        before.append(t.export())
+        res.append(t.insert(np.array([k], np.uint64), np.array([v], np.uint64)))
+    return before, {f: np.concatenate([r[f] for r in res]) for f in res[0]}
+
+
+@pytest.mark.parametrize("scheme,ghost", [("sorted", False), ("sorted", True), ("hybrid", False)])
+def test_spawn_counts_replayed_from_search_logs_serial(scheme, ghost):
+    # Sec. 5: a bin's spawn count is the number of times one of its records
+    # has been spawned during a search, kept in four bits (saturating at 15);
+    # sorted search spawns first the records of the bin with the smaller count.
+    # The oracle's record of spawns is replayed here, independently of its
+    # bookkeeping:
+    #  * the counts in the image equal min(15, spawns recorded per bin);
+    #  * with two hash functions every spawn views exactly one new bin, so an
+    #    op spawned views - 2 records (none when it placed without a search);
+    #  * every spawned record sat in a full bin (no free slot, with ghosts no
+    #    duplicate either) of the image before its op;
+    #  * a search's first spawn is from the key's bin with the smaller count
+    #    in that image (the first bin on a tie).
+    t = make(1 << 9, B=4, scheme=scheme, ghost=ghost, seed=41, batch_ops=1, max_search=200)
+    t.log_spawns()
+    m = inputs.target_count(t.n, t.B, 0.995)
+    keys, vals = inputs.keys_values(41, m)
+    before, r = _serial_with_images(t, keys, vals)
+    ops, bins = t.spawn_log()
+    img = t.export()
+    count = np.bincount(bins.astype(np.int64), minlength=t.n)
+    assert np.array_equal((img["meta"] >> 8) & 0xF, np.minimum(15, count))
+    assert count.max() > 15, "no bin reached saturation: the test needs a fuller table"
+    per_op = np.bincount(ops.astype(np.int64), minlength=m)
+    assert np.array_equal(per_op, np.maximum(0, r["views"].astype(np.int64) - 2))
+    hb = checks.bins_of(keys, t.n, 2, 141)
+    first = {}
+    for o, b in zip(ops.tolist(), bins.tolist()):
+        first.setdefault(o, b)
+        im = before[o]
+        occ = im["keys"][b * 4:(b + 1) * 4] != EMPTY
+        assert occ.all(), f"op {o} spawned a record of bin {b}, which had a free slot"
+        if ghost:
+            assert (im["meta"][b] & 0xF) == 0, f"op {o} spawned from a bin with a duplicate"
+    assert len(first) > 100
+    for o, b in first.items():
+        sc = (before[o]["meta"] >> 8) & 0xF
+        h0, h1 = int(hb[o, 0]), int(hb[o, 1])
+        assert b == (h0 if sc[h0] <= sc[h1] else h1), f"op {o}: first spawn from bin {b}"
+
+
+@pytest.mark.parametrize("scheme,batch", [("sorted", 37), ("hybrid", 200)])
+def test_spawn_counts_replayed_in_round_mode(scheme, batch):
+    # Round mode: every plan's spawns apply, including plans that lose a claim
+    # and plans that fail; the counts still equal the saturated replay.
+    t = make(1 << 8, B=4, scheme=scheme, seed=42, batch_ops=batch, max_search=40)
+    t.log_spawns()
+    _, _, r = fill(t, 0.99, seed=42)
+    ops, bins = t.spawn_log()
+    count = np.bincount(bins.astype(np.int64), minlength=t.n)
+    img = t.export()
+    assert np.array_equal((img["meta"] >> 8) & 0xF, np.minimum(15, count))
+    assert (r["retries"] > 0).any() and (r["status"] == oracle.ST_FAIL).any()
+
+
+# --------------------------------------------------------------------------- hit balancing
+def test_queue_load_and_hit_balancing_from_images():
+    # Sec. 6: queue-kicking views both bins; if either has room the record
+    # goes to the less full one (load balancing, the first on a tie), at its
+    # lowest free slot; if both are full it goes to the bin with the smaller
+    # hit counter (hit balancing, the first on a tie), into slot hc mod B,
+    # and every insertion into a bin advances its counter.  Checked op by op
+    # from the images alone (serial, no deletes, no ghosts).
+    B = 4
+    t = make(1 << 9, B=B, scheme="queue", seed=43, batch_ops=1, max_chain=500)
+    m = inputs.target_count(t.n, B, 0.99)
+    keys, vals = inputs.keys_values(43, m)
+    before, r = _serial_with_images(t, keys, vals)
+    before.append(t.export())
+    hb = checks.bins_of(keys, t.n, 2, 143)
+    n_hit = 0
+    for o in range(m):
+        if r["status"][o] != oracle.ST_OK:
+            continue
+        im, nx = before[o], before[o + 1]
+        h0, h1 = int(hb[o, 0]), int(hb[o, 1])
+        occ = [(im["keys"][b * B:(b + 1) * B] != EMPTY) for b in (h0, h1)]
+        hc = [int(im["meta"][b] >> 24) for b in (h0, h1)]
+        hc_after = [int(nx["meta"][b] >> 24) for b in (h0, h1)]
+        if not (occ[0].all() and occ[1].all()):
+            t_i = 0 if occ[0].sum() <= occ[1].sum() else 1
+            slot = int(np.argmin(occ[t_i]))
+            assert r["kicks"][o] == 0
+        else:
+            n_hit += 1
+            t_i = 0 if hc[0] <= hc[1] else 1
+            slot = hc[t_i] % B
+        tb = (h0, h1)[t_i]
+        adv = (hc_after[t_i] - hc[t_i]) % 256
+        assert adv >= 1, f"op {o}: the chosen bin's hit counter did not advance"
+        if adv == 1:  # the chain did not come back to the chosen bin
+            assert nx["keys"][tb * B + slot] == keys[o], f"op {o}: not in bin {tb} slot {slot}"
+    assert n_hit > 100
