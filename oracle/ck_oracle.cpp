@@ -100,6 +100,9 @@ struct Params {
   uint64_t hash_seed, rng_seed;
   uint32_t stash = 0;  // stash entries (Sec. 2); 0: no stash
   uint32_t hash_bias = 0;  // 0: uniform hashes; 1-4: biased (Sec. 9)
+  // BFS and sorted search spawning k records at a time (Sec. 5, Prefetching);
+  // 0: the one-at-a-time searches
+  uint32_t spawn_k = 0;
 };
 
 struct Stats {
@@ -441,6 +444,88 @@ struct Plan {
     }
   }
 
+  // ---- BFS and sorted search spawning k records at a time (Sec. 5) -------------
+  // Sec. 5 (Prefetching) lets sorted search spawn the k records with the
+  // smallest statistic at a time instead of one, so that their child bins can
+  // be fetched together; BFS is the same with the FIFO order.  Reading taken:
+  // the group is the first k records of the search order (across buckets);
+  // their candidate bins not yet visited are viewed together, record by
+  // record in group order, a view that would pass max_search ending the
+  // viewing; every record that viewed a bin is spawned.  If a viewed bin ends
+  // a chain, the first such bin in that order does (even when the cap cut the
+  // group short); otherwise a capped group fails the search, and an uncapped
+  // one lists every viewed bin as a new run, in that order.  With k = 1 this is
+  // the one-at-a-time search whenever a record has a single candidate (two
+  // hash functions).
+  void search_k(const Slot& x, const uint64_t* h, Order order, uint32_t k) {
+    if (place_fresh(x, h)) { status = ST_OK; return; }
+    std::vector<Entry> entries;
+    std::array<std::deque<int>, 16> bucket;  // FIFO per spawn count (BFS: one)
+    std::set<uint64_t> visited;
+    auto enqueue_bin = [&](uint64_t b, int parent, int depth) {
+      BinState s = read(b);
+      int key = order != BY_FIFO ? std::min<int>(15, s.sc) : 0;
+      for (int i = 0; i < T.p.B; ++i) {
+        entries.push_back({b, i, parent, depth});
+        bucket[key].push_back((int)entries.size() - 1);
+      }
+    };
+    for (int i = 0; i < T.p.H; ++i) {
+      visited.insert(h[i]);
+      enqueue_bin(h[i], -1, 0);
+    }
+    struct Viewed {
+      int e;          // the record whose candidate it is
+      uint64_t bin;
+      bool term;
+    };
+    for (;;) {
+      std::vector<int> group;
+      for (int b = 0; b < 16 && group.size() < k; ++b)
+        while (!bucket[b].empty() && group.size() < k) {
+          group.push_back(bucket[b].front());
+          bucket[b].pop_front();
+        }
+      if (group.empty()) { status = ST_FAIL; return; }  // nothing left to spawn
+      std::vector<Viewed> seen;
+      bool capped = false;
+      for (int e : group) {
+        const Entry en = entries[e];
+        const Slot rec = read(en.bin).s[en.slot];
+        bool spawned = false;
+        for (uint64_t child : others(rec.key, en.bin)) {
+          if (visited.count(child)) continue;
+          if (views == T.p.max_search) { capped = true; break; }
+          if (!spawned && order != BY_FIFO) spawns.push_back(en.bin);
+          spawned = true;
+          visited.insert(child);
+          seen.push_back({e, child, terminal(view(child))});
+        }
+        if (capped) break;
+      }
+      for (const Viewed& v : seen) {
+        if (!v.term) continue;
+        // Found: the record moves into the terminal bin, each record on its
+        // path moves one hop toward it, from the chain's end back (Sec. 8.2).
+        place_terminal(v.bin, read(entries[v.e].bin).s[entries[v.e].slot]);
+        ++kicks;
+        int cur = v.e;
+        while (entries[cur].parent >= 0) {
+          int par = entries[cur].parent;
+          put(entries[cur].bin, entries[cur].slot, read(entries[par].bin).s[entries[par].slot],
+              false);
+          ++kicks;
+          cur = par;
+        }
+        put(entries[cur].bin, entries[cur].slot, x, false);
+        status = ST_OK;
+        return;
+      }
+      if (capped) { status = ST_FAIL; return; }
+      for (const Viewed& v : seen) enqueue_bin(v.bin, v.e, entries[v.e].depth + 1);
+    }
+  }
+
   // ---- Rattle-kicking for d-ary tables with single-slot bins (Sec. 7) -----------
   // A key x carries a counter r(x), incremented on every try; it tries bin
   // h_{r mod d}.  Against an occupant y the larger counter keeps the bin (the
@@ -482,8 +567,14 @@ Plan plan_insert(const Table& T, uint64_t op, uint64_t key, uint64_t val) {
   T.hash(key, h);
   switch (T.p.scheme) {
     case RANDOM_WALK: pl.random_walk(x, h); break;
-    case BFS: pl.search(x, h, Plan::BY_FIFO); break;
-    case SORTED: pl.search(x, h, Plan::BY_COUNT); break;
+    case BFS:
+      if (T.p.spawn_k) pl.search_k(x, h, Plan::BY_FIFO, T.p.spawn_k);
+      else pl.search(x, h, Plan::BY_FIFO);
+      break;
+    case SORTED:
+      if (T.p.spawn_k) pl.search_k(x, h, Plan::BY_COUNT, T.p.spawn_k);
+      else pl.search(x, h, Plan::BY_COUNT);
+      break;
     case HYBRID: pl.search(x, h, Plan::BY_DEPTH_COUNT); break;
     case QUEUE: pl.queue_kick(x, h); break;
     case RATTLE: pl.rattle(x, h); break;
@@ -766,6 +857,16 @@ int ck_oracle_set_hash_bias(void* tp, uint32_t k) {
   Table& T = *(Table*)tp;
   if (k > 4) return -1;
   T.p.hash_bias = k;
+  return 0;
+}
+
+// BFS or sorted search spawning k records at a time (k >= 1; 0 restores the
+// one-at-a-time search), set on an empty table.
+int ck_oracle_set_spawn_k(void* tp, uint32_t k) {
+  Table& T = *(Table*)tp;
+  if (T.p.scheme != BFS && T.p.scheme != SORTED) return -1;
+  if (k > 64) return -1;
+  T.p.spawn_k = k;
   return 0;
 }
 

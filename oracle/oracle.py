@@ -74,6 +74,8 @@ def lib():
         L.ck_oracle_import_stash.argtypes = [vp, vp, vp]
         L.ck_oracle_import.argtypes = [vp, vp, vp, vp, vp]
         L.ck_oracle_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
+        L.ck_oracle_set_spawn_k.argtypes = [vp, u32]
+        L.ck_oracle_set_spawn_k.restype = i32
         L.ck_oracle_log_spawns.argtypes = [vp, i32]
         L.ck_oracle_spawn_log.argtypes = [vp, vp, vp, u64]
         L.ck_oracle_spawn_log.restype = u64
@@ -93,7 +95,7 @@ class OracleTable:
 
     def __init__(self, bins, slots_per_bin=4, d=2, scheme="random_walk", ghost=False,
                  load_balance=False, max_chain=500, max_search=500, max_rounds=0,
-                 batch_ops=1, hash_seed=0, rng_seed=0, stash=0, hash_bias=0):
+                 batch_ops=1, hash_seed=0, rng_seed=0, stash=0, hash_bias=0, spawn_k=0):
         self.n, self.B, self.H = int(bins), int(slots_per_bin), int(d)
         self.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
         self._t = lib().ck_oracle_create(self.n, self.B, self.H, self.scheme, int(ghost),
@@ -107,6 +109,10 @@ class OracleTable:
         self.hash_bias = int(hash_bias)
         if self.hash_bias and lib().ck_oracle_set_hash_bias(self._t, self.hash_bias) != 0:
             raise ValueError("oracle rejected the hash bias")
+        # BFS / sorted search spawning k records at a time (0: one at a time)
+        self.spawn_k = int(spawn_k)
+        if self.spawn_k and lib().ck_oracle_set_spawn_k(self._t, self.spawn_k) != 0:
+            raise ValueError("oracle rejected spawn_k")
 
     def __del__(self):
         if getattr(self, "_t", None):

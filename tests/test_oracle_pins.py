@@ -937,3 +937,87 @@ def test_footnote_kicks_per_bin_at_97():
     q = float(np.mean(per_bin["queue"]))
     assert 2.07 * 0.9 <= q <= 2.07 * 1.1, q
     assert np.mean(per_bin["walk"]) > 2 * 2.07 and np.mean(per_bin["walk_lb"]) > 2 * 2.07
+
+
+# --------------------------------------------------------------------------- k-at-a-time spawning
+@pytest.mark.parametrize("scheme", ["bfs", "sorted"])
+@pytest.mark.parametrize("ghost,batch", [(False, 1), (True, 1), (False, 61), (True, 200)])
+def test_spawn_k1_is_the_one_at_a_time_search(scheme, ghost, batch):
+    # Sec. 5 (Prefetching): spawning k records at a time with k = 1 is the
+    # search itself when a record has one candidate (two hash functions):
+    # same per-op results, image (spawn counts included) and counters.
+    kw = dict(ghost=ghost, batch_ops=batch, max_search=300)
+    a = make(1 << 10, 4, 2, scheme, seed=51, **kw)
+    b = make(1 << 10, 4, 2, scheme, seed=51, spawn_k=1, **kw)
+    keys, vals = inputs.keys_values(51, inputs.target_count(1 << 10, 4, 0.985))
+    ra, rb = a.insert(keys, vals), b.insert(keys, vals)
+    for f in ra:
+        assert np.array_equal(ra[f], rb[f]), f
+    ia, ib = a.export(), b.export()
+    for f in ("keys", "vals", "meta"):
+        assert np.array_equal(ia[f], ib[f]), f
+    assert a.stats()["views"] == b.stats()["views"]
+
+
+@pytest.mark.parametrize("scheme", ["bfs", "sorted"])
+@pytest.mark.parametrize("k", [2, 4, 8])
+@pytest.mark.parametrize("ghost,batch", [(False, 1), (True, 97)])
+def test_spawn_k_invariants_and_dictionary(scheme, k, ghost, batch):
+    # Spawning k at a time changes which chains are found, never their
+    # validity: placement and ghost-pair invariants, conservation, and
+    # lookups/deletes answering as a dictionary.
+    t = make(1 << 9, 4, 2, scheme, seed=52, ghost=ghost, batch_ops=batch, max_search=200,
+             spawn_k=k)
+    keys, vals, r = fill(t, 0.985, seed=52)
+    held = checks.check_invariants(t.export(), t.n, 4, 2, 152, ghost=ghost)
+    ok = r["status"] == oracle.ST_OK
+    assert held == set(keys[ok].tolist())
+    assert t.stats()["stored"] == int(ok.sum())
+    v, f = t.lookup(keys)
+    assert np.array_equal(f.astype(bool), ok) and np.array_equal(v[ok], vals[ok])
+    gone = keys[ok][::3]
+    fd, _ = t.delete(gone)
+    assert fd.all()
+    _, f2 = t.lookup(gone)
+    assert not f2.any()
+
+
+@pytest.mark.parametrize("k", [2, 3])
+@pytest.mark.parametrize("n,B", [(6, 1), (8, 2)])
+def test_bfs_spawn_k_chain_is_shortest(n, B, k):
+    # BFS spawning k records at a time still takes records in breadth-first
+    # order, so the first bin with room it views is at the least depth: its
+    # chains are the exhaustive minimum, as for BFS (Sec. 5).
+    checked = 0
+    for trial in range(60):
+        t = make(n, B, 2, "bfs", seed=trial, max_search=1000, spawn_k=k)
+        keys, vals = inputs.keys_values(1000 + trial, n * B + 4)
+        for i in range(keys.size):
+            h = t.hash(keys[i])
+            img = t.export()
+            kb = img["keys"].reshape(n, B)
+            full = all((kb[b] != EMPTY).all() for b in h)
+            r = t.insert(keys[i:i + 1], vals[i:i + 1])
+            if full:
+                want = brute_min_kicks(img, n, B, int(keys[i]), 100 + trial)
+                if want is None:
+                    assert r["status"][0] == oracle.ST_FAIL
+                else:
+                    assert r["status"][0] == oracle.ST_OK and r["kicks"][0] == want
+                checked += 1
+            if r["status"][0] != oracle.ST_OK:
+                break
+    assert checked > 50
+
+
+def test_spawn_k_views_between_sorted_and_bfs():
+    # Fig. 1 setup (2^13 x 4 to 97.5%, five tables): spawning k at a time
+    # fetches k records' children per step, so sorted search views more bins
+    # as k grows (the prefetching cost) yet stays well below BFS, whose views
+    # hardly move (it already spawns in order of age).
+    sv = {k: band_mean(run_fill(1 << 13, 4, 2, "sorted", 0.975, range(1, 6), spawn_k=k),
+                       194, 195) for k in (0, 2, 4, 8)}
+    bv = {k: band_mean(run_fill(1 << 13, 4, 2, "bfs", 0.975, range(1, 6), spawn_k=k),
+                       194, 195) for k in (0, 4)}
+    assert sv[0] < sv[2] < sv[4] < sv[8] < 0.6 * bv[0], (sv, bv)
+    assert abs(bv[4] - bv[0]) < 0.05 * bv[0], bv
