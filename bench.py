@@ -90,13 +90,16 @@ def parse():
                         "for rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     p.add_argument("--cpu-bins-log2", type=int, default=19)
     p.add_argument("--workload", default="fill",
-                   choices=["fill", "group", "serve", "mixed", "dary", "bias", "stash"],
+                   choices=["fill", "group", "serve", "mixed", "dary", "bias", "stash",
+                            "ceilings", "small"],
                    help="fill: one 2^24 x 8 table (default); group: 4096 tables of "
                         "2^10..2^20 bins x 4 slots, batched vs per-request launches; "
                         "serve: the same tables behind the continuous-batching server, "
                         "Poisson arrivals; mixed: steady-state lookups/inserts/deletes "
                         "with ghosts on a 2^25 x 4 table at 97%; dary: single-slot bins, "
-                        "d = 3 and 4, rattle vs random walk")
+                        "d = 3 and 4, rattle vs random walk; ceilings: random line "
+                        "gathers and 64-bit atomics over 2 GiB; small: the 2^16 x 4 "
+                        "random-walk table")
     p.add_argument("--mixed-steps", type=int, default=1024, help="mixed: steps of 2^18 ops")
     p.add_argument("--dary-schemes", default="rattle,random_walk", help="dary: schemes")
     p.add_argument("--rate", type=float, default=200_000.0, help="serve: requests per second")
@@ -109,27 +112,151 @@ def parse():
     return p.parse_args()
 
 
+def _cpu_model() -> dict:
+    """The host CPU's model name and logical core count (from /proc/cpuinfo)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cores": os.cpu_count()}
+
+
 def cpu_baseline(args, schemes):
-    """The oracle (serial, one core) on a bounded sample of the same workload."""
+    """The oracle (serial, one core) on a bounded sample of the same workload:
+    each scheme fills a 2^cpu_bins_log2 x B table to the load, then 2^20
+    lookups at the same hit rate run on the last table.  The process is
+    pinned to one core for the timing (the oracle is single-threaded)."""
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle
     from paper_1605_05236_amd import inputs
     n = 1 << args.cpu_bins_log2
     m = inputs.target_count(n, args.slots, args.load)
     keys, vals = inputs.keys_values(2, m)
-    t_ins = 0.0
-    total = 0
-    for s in schemes:
-        o = oracle.OracleTable(n, args.slots, 2, s, max_search=args.max_search, batch_ops=1,
-                               hash_seed=102, rng_seed=202)
+    q, _ = inputs.lookup_mix(302, keys, m, 1 << 20, args.hit_rate, key_seed=2)
+    cpu = _cpu_model()
+    old = os.sched_getaffinity(0)
+    core = min(old)
+    os.sched_setaffinity(0, {core})
+    try:
+        t_ins = 0.0
+        total = 0
+        for s in schemes:
+            o = oracle.OracleTable(n, args.slots, 2, s, max_search=args.max_search, batch_ops=1,
+                                   hash_seed=102, rng_seed=202)
+            t0 = time.perf_counter()
+            o.insert(keys, vals)
+            t_ins += time.perf_counter() - t0
+            total += m
         t0 = time.perf_counter()
-        o.insert(keys, vals)
-        t_ins += time.perf_counter() - t0
-        total += m
+        o.lookup(q)
+        t_look = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, old)
     return {"value": total / t_ins, "unit": "inserts/s", "cores": 1, "kind": "oracle",
-            "sample": f"serial oracle, schemes {','.join(schemes)}, each filling "
-                      f"2^{args.cpu_bins_log2} bins x {args.slots} slots to {args.load} "
-                      f"({m} inserts per scheme, same key stream), single thread"}
+            "lookups_per_s": q.size / t_look, "pinned_core": core,
+            "cpu_model": cpu["model"], "host_logical_cores": cpu["logical_cores"],
+            "sample": f"serial oracle (g++ -O2, one thread pinned to one core), schemes "
+                      f"{','.join(schemes)}, each filling 2^{args.cpu_bins_log2} bins x "
+                      f"{args.slots} slots to {args.load} ({m} inserts per scheme, same key "
+                      f"stream as the GPU); then {q.size} lookups at {args.hit_rate} hits on "
+                      f"the last table"}
+
+
+def measure_ceilings(gib=2, line_bytes=128, ops_log2=26, reps=5):
+    """The device's random-access ceilings: random whole-line gathers and random
+    64-bit atomicMin over a `gib` GiB buffer (best of `reps` launches each)."""
+    import ctypes
+    import torch
+    from paper_1605_05236_amd import build
+    if not os.path.exists(build.CEIL_LIB):
+        raise RuntimeError(f"{build.CEIL_LIB} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(build.CEIL_LIB)
+    vp, u64, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
+    L.ckc_gather_threads.restype = u64
+    L.ckc_gather.argtypes = [vp, u64, u32, u64, u64, vp, vp]
+    L.ckc_atomic_min.argtypes = [vp, u64, u64, u64, vp]
+    words = (gib << 30) // 8
+    buf = torch.randint(0, 1 << 62, (words,), dtype=torch.int64, device="cuda")
+    out = torch.empty(int(L.ckc_gather_threads()), dtype=torch.int64, device="cuda")
+    s = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(s.cuda_stream)
+    n = 1 << ops_log2
+    lines = (gib << 30) // line_bytes
+
+    def best(fn):
+        fn(0)
+        t = []
+        for r in range(reps):
+            t.append(_timed(lambda: fn(r + 1)))
+        return min(t)
+
+    def gather(seed):
+        assert L.ckc_gather(ctypes.c_void_p(buf.data_ptr()), lines, line_bytes, n, seed,
+                            ctypes.c_void_p(out.data_ptr()), sp) == 0
+
+    def amin(seed):
+        assert L.ckc_atomic_min(ctypes.c_void_p(buf.data_ptr()), words, n, seed, sp) == 0
+
+    tg = best(gather)
+    ta = best(amin)
+    del buf, out
+    torch.cuda.empty_cache()
+    return {"buffer_gib": gib, "ops": n,
+            "gather_line_bytes": line_bytes, "gather_lines_per_s": n / tg,
+            "gather_GBs": n * line_bytes / tg / 1e9,
+            "atomic_min_u64_per_s": n / ta,
+            "note": "random whole-line loads (lanes of a group load 16 bytes each) and random "
+                    "64-bit atomicMin, addresses drawn in-kernel; best of "
+                    f"{reps} launches after one warm-up"}
+
+
+def run_small(args):
+    """The single small table: 2^16 bins x 4 slots, two hash functions, random
+    walk capped at 500 kicks, filled to 0.95 in sub-batches of 2^12, then 2^16
+    lookups (half present, half absent).  4 MiB of slots: the table stays in
+    the 256 MiB last-level cache, so its HBM-roofline fraction can pass 1."""
+    import torch
+    from paper_1605_05236_amd import inputs
+    from paper_1605_05236_amd.table import CuckooTable, as_device_keys
+    n, B = 1 << 16, 4
+    m = inputs.target_count(n, B, 0.95)
+    keys, vals = inputs.keys_values(1, m)
+    dk, dv = as_device_keys(keys), as_device_keys(vals)
+    q, present, src = inputs.lookup_mix(301, keys, m, 1 << 16, 0.5, key_seed=1,
+                                        return_index=True)
+    dq = as_device_keys(q)
+    t = CuckooTable(n, B, 2, "random_walk", max_chain=500, batch_ops=1 << 12, hash_seed=101,
+                    rng_seed=201)
+    fills, looks = [], []
+    for r in range(4):
+        t.clear()
+        fills.append(_timed(lambda: t.insert(dk, dv, diagnostics=False)))
+        t.lookup(dq)
+        looks.append(_timed(lambda: t.lookup(dq)))
+    st = t.stats()
+    v, f = t.lookup(dq)
+    f = f.cpu().numpy().astype(bool)
+    v = v.cpu().numpy().view(np.uint64)
+    assert np.array_equal(f, present) and np.array_equal(v[present], vals[src[present]])
+    band = 189  # [94.5%, 95%)
+    fill_s, look_s = float(np.median(fills[1:])), float(np.median(looks[1:]))
+    probes = st["lookup_probes"] / max(1, st["lookups"])
+    bpq = 17 + probes * B * 16
+    return {"workload": "2^16 bins x 4 slots, 2 hash functions, random walk (max chain 500), "
+                        "fill to 0.95 in sub-batches of 2^12; 2^16 lookups at 0.5 hits",
+            "inserts_per_s": m / fill_s, "lookups_per_s": q.size / look_s,
+            "bins_viewed_per_insert_at_95": float(st["band_views"][band] /
+                                                  max(1, st["band_inserts"][band])),
+            "bins_viewed_per_insert_cumulative": st["views"] / max(1, st["inserts_ok"]),
+            "failed_inserts": st["inserts_failed"], "lookup_probes_per_query": probes,
+            "lookup_hbm_frac": q.size * bpq / look_s / 1e9 / PEAK_HBM_GBS,
+            "note": "cache-resident (4.5 MiB): the fraction is against HBM peak and may pass 1; "
+                    "times are medians of three repeats after one warm-up"}
 
 
 def _timed(fn):
@@ -599,6 +726,21 @@ def main():
     if args.workload == "stash":
         run_stash(args)
         return
+    if args.workload in ("ceilings", "small"):
+        import torch
+        torch.cuda.set_device(0)
+        if args.workload == "ceilings":
+            c = measure_ceilings()
+            line = {"metric": "random-access ceilings: line gathers/s and 64-bit atomicMin/s",
+                    "value": c["gather_lines_per_s"], "unit": "lines/s", "ceilings": c}
+        else:
+            c = run_small(args)
+            line = {"metric": "inserts/s and bins viewed per insert at 95% load, small table",
+                    "value": c["inserts_per_s"], "unit": "inserts/s", "small_table": c}
+        line.update({"n_gpus": 1, "higher_is_better": True, "dtype": "u64",
+                     "data": "synthetic"})
+        print(json.dumps(line), flush=True)
+        return
     import torch
     from paper_1605_05236_amd import inputs
     from paper_1605_05236_amd.table import CuckooTable, as_device_keys
@@ -609,11 +751,17 @@ def main():
     schemes = [s for s in args.schemes.split(",") if s]
     n, B = 1 << args.bins_log2, args.slots
     m = inputs.target_count(n, B, args.load)
+    # keys up to 98% load: the fills use the first m; after the timed steps each
+    # table is taken on from 95% to 98% (the top of the loads reported)
+    m_top = max(m, inputs.target_count(n, B, 0.98))
     t0 = time.time()
-    keys, vals = inputs.keys_values(2, m)
-    dkeys, dvals = as_device_keys(keys), as_device_keys(vals)
+    keys_all, vals_all = inputs.keys_values(2, m_top)
+    keys, vals = keys_all[:m], vals_all[:m]
+    dkeys_all, dvals_all = as_device_keys(keys_all), as_device_keys(vals_all)
+    dkeys, dvals = dkeys_all[:m], dvals_all[:m]
     nq = 1 << args.lookups_log2
-    q, present = inputs.lookup_mix(302, keys, m, nq, args.hit_rate, key_seed=2)
+    q, present, q_src = inputs.lookup_mix(302, keys, m, nq, args.hit_rate, key_seed=2,
+                                          return_index=True)
     dq = as_device_keys(q)
     rng = np.random.default_rng(402)
     dels = keys[rng.choice(m, 1 << args.deletes_log2, replace=False)]
@@ -707,9 +855,12 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
 
-    # correctness guard on the timed output: every probe answered as generated
+    # correctness guard on the timed output: every probe answered as generated,
+    # and every stored key's value is the one inserted
     found = fout.cpu().numpy().astype(bool)
     assert np.array_equal(found, present), "lookup answers differ from the generated mix"
+    got = vout.cpu().numpy().view(np.uint64)
+    assert np.array_equal(got[present], vals[q_src[present]]), "a lookup returned a wrong value"
 
     # after the timed region: the same steps with no kernel timing at all, to
     # show what the two HIP events around every launch of the dominant class
@@ -717,6 +868,38 @@ def main():
     plain = [step(False, False) for _ in range(args.steps)]
     plain_rate = len(schemes) * m / sum(float(np.mean([r["fill_s"][s] for r in plain]))
                                         for s in schemes)
+
+    # probes per lookup, counted by the lookup kernel (before the tables are
+    # refilled below)
+    lt = tables[schemes[-1]].stats()
+    probes_per_q = lt["lookup_probes"] / max(1, lt["lookups"])
+
+    # bins viewed per insert at each load of the configuration: the bands just
+    # below 0.90 and 0.95 come from the timed fills; for 0.98 each table is
+    # filled to 0.95 again (untimed) and taken on to 0.98 in one more call
+    by_load = {}
+    for lo in (0.90, args.load, 0.98):
+        by_load[f"{lo:.2f}"] = {}
+    top_rate = {}
+    for s in schemes:
+        t = tables[s]
+        t.timing(enable=False)
+        t.clear()
+        t.insert(dkeys, dvals, diagnostics=False)
+        st_lo = t.stats()
+        if m_top > m:
+            sec = _timed(lambda: t.insert(dkeys_all[m:], dvals_all[m:], diagnostics=False))
+            top_rate[s] = (m_top - m) / sec
+        st_hi = t.stats()
+        for lo in by_load:
+            band = int(round(float(lo) * 200)) - 1
+            src = st_lo if float(lo) <= args.load else st_hi
+            bi, bvv = src["band_inserts"][band], src["band_views"][band]
+            by_load[lo][s] = {"band": float(bvv / bi) if bi else None,
+                              "cumulative_to_here": float(
+                                  src["band_views"][:band + 1].sum() /
+                                  max(1, src["band_inserts"][:band + 1].sum())),
+                              "failed": int(src["band_fails"][:band + 1].sum())}
 
     fill = {s: float(np.mean([r["fill_s"][s] for r in results])) for s in schemes}
     lookup_s = float(np.mean([r["lookup_s"] for r in results]))
@@ -736,24 +919,39 @@ def main():
         bv95[s] = float(bvv[band] / max(1, bi[band]))
         cum[s] = st[s]["views"] / max(1, st[s]["inserts_ok"] + st[s]["inserts_failed"])
         fails[s] = st[s]["inserts_failed"]
-    # the whole insert path against the HBM roofline: per insert, its key and
-    # value in and status out (17 bytes), every bin viewed (line + 4-byte
-    # metadata word), and per record placed or moved one slot write (16) and
-    # one claim word (8)
-    ins_bytes, ins_total_bytes = {}, 0.0
+    # The whole insert path against the HBM roofline, under two byte models.
+    # Survey model (the primary figure): per insert 17 bytes of key, value and
+    # status; V bins viewed, each a whole line L; V_m of them also read the
+    # bin's metadata word, counted as a 64-byte line (sorted search and the
+    # hybrid read spawn counts, queue-kicking hit counters, ghosts duplicate
+    # marks); W = kicks + 1 bins written, each a line and its metadata line.
+    # Line-and-word model (the first one reported): a view is a line and a
+    # 4-byte word, a write a 16-byte slot and an 8-byte claim word.
+    L = B * 16
+
+    def reads_meta(s):
+        return s in ("sorted", "hybrid", "queue")
+
+    ins_bytes, ins_bytes_lw, ins_total, ins_total_lw = {}, {}, 0.0, 0.0
     for s in schemes:
         done = max(1, st[s]["inserts_ok"] + st[s]["inserts_failed"])
         kicks = st[s]["kicks"] / done
-        ins_bytes[s] = 17 + cum[s] * (B * 16 + 4) + (kicks + 1) * (16 + 8)
-        ins_total_bytes += ins_bytes[s] * m
-    ins_ach = ins_total_bytes / sum(fill.values()) / 1e9
+        vm = cum[s] if reads_meta(s) else 0.0
+        ins_bytes[s] = 17 + cum[s] * L + vm * 64 + (kicks + 1) * (L + 64)
+        ins_bytes_lw[s] = 17 + cum[s] * (L + 4) + (kicks + 1) * (16 + 8)
+        ins_total += ins_bytes[s] * m
+        ins_total_lw += ins_bytes_lw[s] * m
+    ins_ach = ins_total / sum(fill.values()) / 1e9
+    ins_ach_lw = ins_total_lw / sum(fill.values()) / 1e9
     insert_roof = {"bound": "hbm", "achieved": ins_ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                    "frac": ins_ach / PEAK_HBM_GBS, "bytes_per_insert": ins_bytes,
+                   "model": "17 + V*L + V_m*64 + W*(L+64) per insert",
+                   "line_and_word_model": {"achieved": ins_ach_lw, "frac": ins_ach_lw / PEAK_HBM_GBS,
+                                           "bytes_per_insert": ins_bytes_lw,
+                                           "model": "17 + V*(L+4) + W*(16+8) per insert"},
                    "scope": "whole fill (all kernels), algorithmic bytes"}
     # lookup roofline: algorithmic bytes per query = key 8 + value 8 + found 1
     # + probes * 128-byte bin line (probes counted by the kernel itself)
-    lt = tables[schemes[-1]].stats()
-    probes_per_q = lt["lookup_probes"] / max(1, lt["lookups"])
     bytes_per_q = 17 + probes_per_q * B * 16
     achieved = nq * bytes_per_q / lookup_s / 1e9
     lpp = args.lpp or B
@@ -761,7 +959,8 @@ def main():
                    "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                    "bytes_per_query": bytes_per_q}
     # the dominant kernel class, timed with HIP events over every timed step
-    kt_ms, kt_launch, evict_views = 0.0, 0, 0
+    kt_ms, kt_launch = 0.0, 0
+    views_by = {s: 0 for s in schemes}
     for r in results:
         if dominant == "lookup":
             kt_ms += r["lookup_timing"]["ms"]
@@ -771,15 +970,20 @@ def main():
             tm = r["timing"][s]
             kt_ms += tm[dominant]["ms"]
             kt_launch += tm[dominant]["launches"]
-            evict_views += tm["evict_views"]
+            views_by[s] += tm["evict_views"]
+    evict_views = sum(views_by.values())
     if dominant == "lookup":
         ach = nq * args.steps * bytes_per_q / (kt_ms / 1e3) / 1e9
         roofline = dict(lookup_roof, achieved=ach, frac=ach / PEAK_HBM_GBS, traffic=None)
     else:
-        # eviction planners: each bin viewed is one bin line (B x 16 bytes) plus
-        # its 4-byte metadata word; a launch's bytes are those of its plans' views
-        per_view = B * 16 + 4
-        ach = evict_views * per_view / (kt_ms / 1e3) / 1e9 if kt_ms else 0.0
+        # eviction planners: a bin viewed is one bin line (L bytes) and, for the
+        # schemes that read it, the bin's metadata word counted as a 64-byte
+        # line (survey model, the primary figure); the line-and-word model
+        # counts the word as 4 bytes.  A launch's bytes are its plans' views.
+        alg = sum(v * (L + (64 if reads_meta(s) else 0)) for s, v in views_by.items())
+        alg_lw = evict_views * (L + 4)
+        ach = alg / (kt_ms / 1e3) / 1e9 if kt_ms else 0.0
+        ach_lw = alg_lw / (kt_ms / 1e3) / 1e9 if kt_ms else 0.0
         traffic = None
         if MEASURED_EVICT_TRAFFIC["sources_sha256"] == _sources_sha256():
             traffic = MEASURED_EVICT_TRAFFIC["bytes_per_launch"]
@@ -788,10 +992,25 @@ def main():
                     "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": ach / PEAK_HBM_GBS, "traffic": traffic,
                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
-                    "algorithmic_bytes_per_launch": evict_views * per_view / max(1, kt_launch),
-                    "bytes_per_view": per_view, "views_per_step": evict_views / args.steps,
+                    "algorithmic_bytes_per_launch": alg / max(1, kt_launch),
+                    "model": "per view: L, plus 64 when the scheme reads the bin's metadata",
+                    "line_and_word_model": {"achieved": ach_lw, "frac": ach_lw / PEAK_HBM_GBS,
+                                            "algorithmic_bytes_per_launch":
+                                                alg_lw / max(1, kt_launch),
+                                            "bytes_per_view": L + 4},
+                    "views_per_step": evict_views / args.steps,
+                    "views_per_step_by_scheme": {s: v / args.steps for s, v in views_by.items()},
                     "launches_per_step": kt_launch / args.steps,
                     "avg_launch_us": kt_ms * 1e3 / max(1, kt_launch)}
+    ceilings = measure_ceilings()
+    lookup_roof["lines_per_s"] = nq * probes_per_q / lookup_s
+    lookup_roof["frac_of_gather_ceiling"] = lookup_roof["lines_per_s"] / \
+        ceilings["gather_lines_per_s"]
+    # claim atomics of the fills, a lower bound: every committed plan claimed
+    # each bin it writes (kicks + 1), and every lost round at least one
+    claims = sum((st[s]["inserts_ok"] + st[s]["kicks"]) + st[s]["retries"] for s in schemes)
+    claims_per_s = claims / sum(fill.values())
+    small = run_small(args)
     out = {
         "metric": "inserts/s & bins viewed/insert at 95% load; lookups/s vs HBM roofline",
         "value": ins_rate,
@@ -816,6 +1035,8 @@ def main():
                    "lookups": nq, "deletes": int(dels.size), "max_search": args.max_search},
         "inserts_per_s_by_scheme": {s: m / fill[s] for s in schemes},
         "bins_viewed_per_insert_at_95": bv95,
+        "bins_viewed_per_insert_by_load": by_load,
+        "inserts_per_s_95_to_98": top_rate,
         "bins_viewed_per_insert_cumulative": cum,
         "failed_inserts": fails,
         "rounds_per_sub_batch": rounds,
@@ -829,6 +1050,10 @@ def main():
         "roofline": roofline,
         "lookup_roofline": lookup_roof,
         "insert_roofline": insert_roof,
+        "ceilings": ceilings,
+        "claim_atomics_per_s_lower_bound": claims_per_s,
+        "claim_atomics_frac_of_ceiling": claims_per_s / ceilings["atomic_min_u64_per_s"],
+        "small_table": small,
         "kernel_ms_warmup_step": warm_ms,
         "dominant_kernel_class": dominant,
     }

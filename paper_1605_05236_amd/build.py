@@ -1,4 +1,5 @@
-"""Build libck.so (HIP, gfx950) in-tree with hipcc."""
+"""Build the HIP libraries (gfx950) in-tree with hipcc: libck.so (the tables)
+and libck_ceilings.so (the random-access ceilings the benchmark measures)."""
 from __future__ import annotations
 
 import os
@@ -8,7 +9,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libck.so")
+CEIL_LIB = os.path.join(HERE, "libck_ceilings.so")
 SOURCES = ["ck_kernels.hip", "ck_api.hip"]
+CEIL_SOURCES = ["ceilings.hip"]
 HEADERS = ["ck_internal.h", os.path.join("..", "..", "include", "ck.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -19,24 +22,29 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Wall", "-Wno-unused-function"]
 
 
-def build(verbose: bool = False) -> str:
+def _link(sources, lib, verbose):
     objs = []
-    for src in SOURCES:
+    for src in sources:
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
         cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     for o in objs:
         os.remove(o)
-    return LIB
+    return lib
+
+
+def build(verbose: bool = False) -> str:
+    _link(CEIL_SOURCES, CEIL_LIB, verbose)
+    return _link(SOURCES, LIB, verbose)
 
 
 if __name__ == "__main__":
