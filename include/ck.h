@@ -195,6 +195,24 @@ ck_status ck_lookup_lpp(ck_table* t, const uint64_t* d_keys, uint64_t n, void* d
 ck_status ck_delete(ck_table* t, const uint64_t* d_keys, uint64_t n, uint8_t* d_found,
                     void* stream);
 
+/* For callers that cannot allocate device memory (serving loops and harnesses
+   that forbid hipMalloc after set-up): ck_delete, with every round scratch
+   array (pending lists, plan headers, inline moves, per-op counters, round
+   counters, statistics staging) carved from one fixed array of
+   CK_NOALLOC_SCRATCH_BYTES that the library holds per device (until the
+   process ends) instead of the table's own scratch.  It calls no hipMalloc,
+   hipFree or allocating routine; its results (d_found, the table, every
+   counter) equal ck_delete's for the same table and keys.  A sub-batch
+   (min(n, batch_ops) ops) may hold at most CK_NOALLOC_MAX_OPS ops, else
+   CK_EINVAL before any device work.  Every call on one device shares that
+   device's array: calls that overlap on one device (other streams, other host
+   threads) race and must not be made; consecutive calls are safe, since each
+   returns with its work complete.  Kernel-class timing is not recorded. */
+#define CK_NOALLOC_MAX_OPS 65536u
+#define CK_NOALLOC_SCRATCH_BYTES (5u << 20)
+ck_status ck_delete_noalloc(ck_table* t, const uint64_t* d_keys, uint64_t n, uint8_t* d_found,
+                            void* stream);
+
 /* Overwrite (Sec. 1: constant-time overwrites): a stored key gets the new
    value (8 bytes, or 4 for single-slot bins) in every slot holding it; its
    key, ghost mark and rattle counter stay.  An absent key is not inserted.

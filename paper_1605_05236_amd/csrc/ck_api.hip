@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -116,9 +117,51 @@ struct ck_table {
   Timer timer;
 };
 
+// The round scratch one call runs on: the table's own arrays (allocated at
+// create; the plan arena grows when a round runs out), or a fixed set carved
+// from the library's static array, which never grows.
+struct Scratch {
+  uint32_t* pend[2];
+  uint4* hdr;
+  uint2* hdr_spawn;
+  IMove* imv;
+  uint32_t* evict;
+  uint32_t* evict_cnt;
+  Move* arena;
+  uint32_t arena_cap;
+  uint32_t* spawns;
+  uint32_t spawn_cap;
+  uint32_t* op[5];
+  Ctr* ctr;
+  uint32_t* block_tmp;
+  uint32_t stripe_cap;
+  bool fixed;  // no growth: an overflowing round is an error
+};
+
 namespace {
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Scratch own_scratch(const ck_table* t) {
+  Scratch x{};
+  x.pend[0] = t->pend[0];
+  x.pend[1] = t->pend[1];
+  x.hdr = t->hdr;
+  x.hdr_spawn = t->hdr_spawn;
+  x.imv = t->imv;
+  x.evict = t->evict;
+  x.evict_cnt = t->evict_cnt;
+  x.arena = t->arena;
+  x.arena_cap = t->arena_cap;
+  x.spawns = t->spawns;
+  x.spawn_cap = t->spawn_cap;
+  for (int k = 0; k < 5; ++k) x.op[k] = t->op[k];
+  x.ctr = t->ctr;
+  x.block_tmp = t->block_tmp;
+  x.stripe_cap = t->stripe_cap;
+  x.fixed = false;
+  return x;
+}
 
 // splitmix64 (Steele, Lea, Flood): derives the hash multipliers from the seed.
 uint64_t sm_next(uint64_t& s) {
@@ -258,24 +301,24 @@ ck_status grow_arena(ck_table* t) {
   return CK_OK;
 }
 
-Round make_round(ck_table* t, const uint64_t* keys, const void* vals, uint8_t* status,
-                 uint32_t** ops, uint64_t op_base, bool is_delete, const uint32_t* op_table,
-                 const uint2* tdesc) {
+Round make_round(ck_table* t, const Scratch& x, const uint64_t* keys, const void* vals,
+                 uint8_t* status, uint32_t** ops, uint64_t op_base, bool is_delete,
+                 const uint32_t* op_table, const uint2* tdesc) {
   Round r{};
   r.op_table = op_table;
   r.tdesc = tdesc;
   r.keys = keys;
   r.vals = vals;
-  r.hdr = t->hdr;
-  r.hdr_spawn = t->hdr_spawn;
-  r.imv = t->imv;
-  r.evict = t->evict;
-  r.evict_cnt = t->evict_cnt;
-  r.arena = t->arena;
-  r.arena_cap = t->arena_cap;
-  r.spawns = t->spawns;
-  r.spawn_cap = t->spawn_cap;
-  r.ctr = t->ctr;
+  r.hdr = x.hdr;
+  r.hdr_spawn = x.hdr_spawn;
+  r.imv = x.imv;
+  r.evict = x.evict;
+  r.evict_cnt = x.evict_cnt;
+  r.arena = x.arena;
+  r.arena_cap = x.arena_cap;
+  r.spawns = x.spawns;
+  r.spawn_cap = x.spawn_cap;
+  r.ctr = x.ctr;
   r.op_base = op_base;
   r.status = status;
   r.op_views = ops[0];
@@ -317,13 +360,20 @@ struct Flight {
   int cur = 0;          // list parity its next round reads
   uint64_t guard = 0;   // rounds left before the loop counts as stuck
   bool live = false;
+  const Scratch* fixed = nullptr;  // the call's fixed scratch, or null: the table's own
 };
+
+// The scratch a sub-batch runs on, read afresh (the table's arena may have grown).
+Scratch scratch_of(const ck_table* t, const Flight& f) {
+  return f.fixed ? *f.fixed : own_scratch(t);
+}
 
 ck_status enqueue_rounds(ck_table* t, Flight& f, uint32_t K, bool first, const uint32_t* gate,
                          hipStream_t s) {
   Timer& T = t->timer;
   Round& r = f.r;
-  Ctr* c = t->ctr + f.set;
+  const Scratch x = scratch_of(t, f);
+  Ctr* c = x.ctr + f.set;
   if (first) f.cur = 0;
   for (uint32_t k = 0; k < K; ++k) {
     // The lowest pending op always commits, so m rounds suffice; arena growth
@@ -344,15 +394,15 @@ ck_status enqueue_rounds(ck_table* t, Flight& f, uint32_t K, bool first, const u
     r.ctr = c;
     r.hsum = t->h_sum + f.set;
     r.gate = gate;
-    r.pend = t->pend[f.cur];
+    r.pend = x.pend[f.cur];
     r.pcnt = first ? nullptr : c->cnt[f.cur];
-    r.next = t->pend[f.cur ^ 1];
+    r.next = x.pend[f.cur ^ 1];
     r.next_cnt = c->cnt[f.cur ^ 1];
-    r.stripe_cap = t->stripe_cap;
-    r.arena = t->arena;
-    r.arena_cap = t->arena_cap;
-    r.spawns = t->spawns;
-    r.spawn_cap = t->spawn_cap;
+    r.stripe_cap = x.stripe_cap;
+    r.arena = x.arena;
+    r.arena_cap = x.arena_cap;
+    r.spawns = x.spawns;
+    r.spawn_cap = x.spawn_cap;
     first = false;
     hipEvent_t ev;
     if (r.is_delete) {
@@ -376,7 +426,7 @@ ck_status enqueue_rounds(ck_table* t, Flight& f, uint32_t K, bool first, const u
   // the statistics (gated on this list and the gate); their first kernel
   // writes the summary the host reads once this event has completed
   hipEvent_t ev = T.begin(s, TK_STATS);
-  HIP_TRY(launch_batch_stats(r, f.m, f.slots, t->block_tmp, r.is_delete, c->cnt[f.cur], s));
+  HIP_TRY(launch_batch_stats(r, f.m, f.slots, x.block_tmp, r.is_delete, c->cnt[f.cur], s));
   T.end(TK_STATS, ev, s);
   HIP_TRY(hipEventRecord(t->ctr_ready[f.set], s));
   return CK_OK;
@@ -389,6 +439,7 @@ ck_status settle(ck_table* t, Flight& f, hipStream_t s, bool* done) {
   t->timer.collect();
   const HostSum& c = t->h_sum[f.set];
   if (c.overflow || c.overflow_seen) {  // a void round: a larger arena for what follows
+    if (f.fixed) return CK_ENOMEM;     // fixed scratch never grows
     ck_status st = grow_arena(t);
     if (st != CK_OK) return st;
     // the flags are seen: clear them before any later round of this
@@ -423,18 +474,20 @@ ck_status run_batches(ck_table* t, const uint64_t* keys, const void* vals, uint6
                       uint8_t* status, uint32_t* views, uint32_t* kicks, uint32_t* retries,
                       bool is_delete, hipStream_t s, const uint32_t* op_table = nullptr,
                       const uint2* tdesc = nullptr, bool overwrite = false,
-                      bool upsert = false) {
+                      bool upsert = false, const Scratch* fixed = nullptr) {
   const uint32_t vb = t->B == 1 ? 4 : 8;
+  const Scratch x = fixed ? *fixed : own_scratch(t);
   const uint64_t slots = t->bins * t->B;
   Flight prev;
   int set = 0;
   for (uint64_t b0 = 0; b0 < n; b0 += t->opt.batch_ops) {
     const uint64_t m = std::min<uint64_t>(t->opt.batch_ops, n - b0);
-    uint32_t* ops[5] = {views ? views + b0 : t->op[0], t->op[1],
-                        kicks ? kicks + b0 : t->op[2], retries ? retries + b0 : t->op[3],
-                        t->op[4]};
+    uint32_t* ops[5] = {views ? views + b0 : x.op[0], x.op[1],
+                        kicks ? kicks + b0 : x.op[2], retries ? retries + b0 : x.op[3],
+                        x.op[4]};
     Flight f;
-    f.r = make_round(t, keys + b0, vals ? (const char*)vals + b0 * vb : nullptr, status + b0, ops,
+    f.fixed = fixed;
+    f.r = make_round(t, x, keys + b0, vals ? (const char*)vals + b0 * vb : nullptr, status + b0, ops,
                      t->insert_count + b0, is_delete, op_table ? op_table + b0 : nullptr, tdesc);
     f.r.overwrite = overwrite ? 1u : 0u;
     f.r.upsert = upsert ? 1u : 0u;
@@ -448,7 +501,7 @@ ck_status run_batches(ck_table* t, const uint64_t* keys, const void* vals, uint6
                            ? t->opt.enqueue_rounds
                            : (is_delete ? t->tail_hint_del + 1
                                         : std::max(t->tail_hint, t->tail_prev));
-    const uint32_t* gate = prev.live ? &t->ctr[prev.set].unfinished : nullptr;
+    const uint32_t* gate = prev.live ? &x.ctr[prev.set].unfinished : nullptr;
     ck_status st = enqueue_rounds(t, f, K, true, gate, s);
     if (st != CK_OK) return st;
     if (prev.live) {
@@ -627,6 +680,106 @@ ck_status ck_delete(ck_table* t, const uint64_t* keys, uint64_t n, uint8_t* foun
   if (!keys || !found) return CK_EINVAL;
   return run_batches(t, keys, nullptr, n, found, nullptr, nullptr, nullptr, true,
                      (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// The no-allocation delete: the round scratch of ck_delete carved from one
+// fixed device array instead of the table's own scratch.
+// ---------------------------------------------------------------------------
+// Every GPU the library runs on holds its own copy of this array until the
+// process ends.  Host code never passes the array's name to a kernel or a
+// runtime call (on the host it is only a stand-in for the symbol): it uses the
+// device address that hipGetSymbolAddress returns, looked up once per device
+// with that device current.
+static __device__ __align__(256) unsigned char scratch[CK_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The fixed array's device address on the current device (looked up on the
+// first call there).
+ck_status scratch_base(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return CK_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return CK_EDEVICE;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return CK_OK;
+}
+
+// The delete path's round scratch for sub-batches of up to M ops, carved in
+// 256-byte aligned pieces from `base` (or only sized, when base is null):
+// two pending lists, plan headers, inline moves, five per-op counters, two
+// round-counter sets and the statistics' staging.  Deletes write inline plans
+// only, so no plan arena, spawn arena or evict list is carved.  Returns the
+// bytes used.
+size_t carve_delete_scratch(unsigned char* base, uint32_t M, Scratch* x) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = base ? (void*)(base + off) : nullptr;
+    off += align256(std::max<size_t>(bytes, 1));
+    return p;
+  };
+  Scratch v{};
+  v.stripe_cap = stripe_capacity(M);
+  for (int k = 0; k < 2; ++k)
+    v.pend[k] = (uint32_t*)take((size_t)kStripes * v.stripe_cap * sizeof(uint32_t));
+  v.hdr = (uint4*)take((size_t)M * sizeof(uint4));
+  v.hdr_spawn = (uint2*)take((size_t)M * sizeof(uint2));
+  v.imv = (IMove*)take((size_t)M * kExtraInline * sizeof(IMove));
+  for (int k = 0; k < 5; ++k) v.op[k] = (uint32_t*)take((size_t)M * sizeof(uint32_t));
+  v.ctr = (Ctr*)take(2 * sizeof(Ctr));
+  const uint32_t nb = (M + 1023) / 1024;
+  v.block_tmp = (uint32_t*)take((((nb + 63) & ~63u) + 16) * sizeof(uint32_t));
+  v.evict = v.evict_cnt = v.spawns = nullptr;
+  v.arena = nullptr;
+  v.arena_cap = v.spawn_cap = 0;
+  v.fixed = true;
+  if (x) *x = v;
+  return off;
+}
+
+}  // namespace
+
+extern "C" {
+
+ck_status ck_delete_noalloc(ck_table* t, const uint64_t* keys, uint64_t n, uint8_t* found,
+                            void* stream) {
+  static_assert(sizeof(scratch) == CK_NOALLOC_SCRATCH_BYTES, "scratch size");
+  if (!t) return CK_EINVAL;
+  if (n == 0) return CK_OK;
+  if (!keys || !found) return CK_EINVAL;
+  // the largest sub-batch of this call must fit the fixed scratch
+  if (std::min<uint64_t>(n, t->opt.batch_ops) > CK_NOALLOC_MAX_OPS) return CK_EINVAL;
+  if (carve_delete_scratch(nullptr, CK_NOALLOC_MAX_OPS, nullptr) > CK_NOALLOC_SCRATCH_BYTES)
+    return CK_EUNSUPPORTED;
+  void* base = nullptr;
+  ck_status st = scratch_base(&base);
+  if (st != CK_OK) return st;
+  Scratch x;
+  carve_delete_scratch((unsigned char*)base, CK_NOALLOC_MAX_OPS, &x);
+  hipStream_t s = (hipStream_t)stream;
+  // the array keeps the last call's contents: the round counters start at
+  // zero (cleared by a small fill kernel rather than a memset)
+  HIP_TRY(launch_fill_u32((uint32_t*)x.ctr, 0u, 2 * sizeof(Ctr) / sizeof(uint32_t), s));
+  // kernel-class timing creates events on demand: off for this call
+  const bool timing = t->timer.on;
+  t->timer.on = false;
+  st = run_batches(t, keys, nullptr, n, found, nullptr, nullptr, nullptr, true, s, nullptr,
+                   nullptr, false, false, &x);
+  t->timer.on = timing;
+  return st;
 }
 
 ck_status ck_overwrite(ck_table* t, const uint64_t* keys, const void* vals, uint64_t n,

@@ -232,5 +232,7 @@ size_t evict_lds_bytes(const Geo& g);
 int evict_resident_per_cu(const Geo& g);
 size_t evict_wg_scratch_bytes(const Geo& g);
 hipError_t launch_export_meta(const Geo& g, hipStream_t s);
+// p[0..count) = value (a small fill kernel; no memset node)
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s);
 
 }  // namespace ck

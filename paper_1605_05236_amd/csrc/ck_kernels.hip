@@ -186,6 +186,22 @@ __device__ __forceinline__ uint64_t with_rattle(uint64_t aux, uint32_t r) {
 }
 
 // ---------------------------------------------------------------------------
+// fill
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u32(uint32_t* p, uint32_t value, uint64_t count) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+    p[i] = value;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((count + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(256), 0, s, p, value, (uint64_t)count);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // init
 // ---------------------------------------------------------------------------
 __global__ void k_init(Geo g) {

@@ -70,7 +70,8 @@ class CkError(RuntimeError):
 _lib = None
 
 EXPORTED = ["ck_default_options", "ck_storage_bytes", "ck_create", "ck_clear", "ck_insert", "ck_insert_ex",
-            "ck_lookup", "ck_lookup_lpp", "ck_delete", "ck_overwrite", "ck_upsert",
+            "ck_lookup", "ck_lookup_lpp", "ck_delete", "ck_delete_noalloc", "ck_overwrite",
+            "ck_upsert",
             "ck_stats_get", "ck_stats_reset", "ck_export_stash", "ck_import_stash",
             "ck_group_export_stash",
             "ck_export", "ck_import", "ck_hash", "ck_insert_count", "ck_destroy", "ck_strerror",
@@ -102,6 +103,7 @@ def load_library(path: str = LIB_PATH):
     L.ck_lookup.argtypes = [vp, vp, u64, vp, vp, vp]
     L.ck_lookup_lpp.argtypes = [vp, vp, u64, vp, vp, u32, vp]
     L.ck_delete.argtypes = [vp, vp, u64, vp, vp]
+    L.ck_delete_noalloc.argtypes = [vp, vp, u64, vp, vp]
     L.ck_overwrite.argtypes = [vp, vp, vp, u64, vp, vp]
     L.ck_upsert.argtypes = [vp, vp, vp, u64, vp, vp, vp, vp, vp]
     L.ck_export_stash.argtypes = [vp, vp, vp, vp]
@@ -136,7 +138,7 @@ def load_library(path: str = LIB_PATH):
     L.ck_strerror.argtypes = [i32]
     L.ck_strerror.restype = ctypes.c_char_p
     for f in ("ck_storage_bytes", "ck_create", "ck_clear", "ck_insert", "ck_insert_ex", "ck_lookup",
-              "ck_lookup_lpp", "ck_delete", "ck_overwrite", "ck_upsert", "ck_stats_get",
+              "ck_lookup_lpp", "ck_delete", "ck_delete_noalloc", "ck_overwrite", "ck_upsert", "ck_stats_get",
               "ck_stats_reset", "ck_export", "ck_export_stash", "ck_import_stash",
               "ck_group_export_stash",
               "ck_import", "ck_hash", "ck_destroy", "ck_timing_enable", "ck_timing_get",
@@ -258,6 +260,15 @@ class CuckooTable:
         found = torch.empty(keys.numel(), dtype=torch.uint8, device=self.device)
         _check(self._L.ck_delete(self._h, _ptr(keys), keys.numel(), _ptr(found),
                                  _stream(stream)))
+        return found
+
+    def delete_noalloc(self, keys, stream=None):
+        """As delete, with the round scratch taken from the library's fixed
+        per-device array (ck_delete_noalloc): no device allocation."""
+        import torch
+        found = torch.empty(keys.numel(), dtype=torch.uint8, device=self.device)
+        _check(self._L.ck_delete_noalloc(self._h, _ptr(keys), keys.numel(), _ptr(found),
+                                         _stream(stream)))
         return found
 
     def overwrite(self, keys, vals, stream=None):

@@ -88,3 +88,7 @@ def test_stash_and_bias_options_are_checked_before_device_work(lib):
     assert lib.ck_import_stash(None, None, None, None) == -1
     assert lib.ck_group_upsert(None, None, None, None, 5, None, None, None, None, None) == -1
     assert lib.ck_group_export_stash(None, 0, None, None, None) == -1
+
+
+def test_noalloc_delete_refuses_a_null_handle(lib):
+    assert lib.ck_delete_noalloc(None, None, 5, None, None) == -1
