@@ -115,6 +115,14 @@ typedef struct {
                                 the two low bits of w are below hash_bias, the
                                 bin is the lesser of the bins of a_i x + c_i and
                                 of w, so low bins are favoured */
+  uint32_t spawn_k;          /* 0 or 1: searches spawn one record at a time.
+                                k >= 2 (CK_BFS and CK_SORTED, d == 2,
+                                slots_per_bin 4 or 8, k <= 32 / slots_per_bin):
+                                the search spawns the k records at the front of
+                                its order together and views their candidate
+                                bins at once (Sec. 5, Prefetching); the first
+                                bin with room among them ends the chain.  Results
+                                depend on k */
 } ck_options;
 
 /* Counters of one table since creation (or the last ck_stats_reset). */
@@ -302,7 +310,7 @@ uint64_t ck_insert_count(const ck_table* t);
 
 /* Release the handle and the library's scratch; the caller's storage is not
    freed.  Synchronises the device.  Not a paper operation: resource
-   management of the C ABI.  Errors: none (a null handle is ignored). */
+   management of the C ABI.  Errors: CK_EINVAL for a null handle. */
 ck_status ck_destroy(ck_table* t);
 
 /* ---- groups: many independent tables of uneven sizes served together ----

@@ -573,6 +573,11 @@ static ck_status create_table(uint64_t bins, uint32_t B, uint32_t d, ck_scheme s
   if (o.max_chain > 2048 || o.max_search > 1024 || o.max_search < d) return CK_EINVAL;
   if (o.stash > kMaxStash) return CK_EINVAL;
   if (o.hash_bias > 4) return CK_EINVAL;
+  if (o.spawn_k > 1) {  // k-at-a-time spawning: the group step of the two-choice searches
+    if (scheme != CK_BFS && scheme != CK_SORTED) return CK_EUNSUPPORTED;
+    if (d != 2 || (B != 4 && B != 8)) return CK_EUNSUPPORTED;
+    if (o.spawn_k > 32 / B) return CK_EINVAL;
+  }
   if (((uintptr_t)storage & 255) != 0) return CK_EINVAL;
   const Layout L = layout(bins, B);
   if (bytes < L.total) return CK_ENOMEM;
@@ -603,6 +608,7 @@ static ck_status create_table(uint64_t bins, uint32_t B, uint32_t d, ck_scheme s
   t->g.rng_seed = o.rng_seed;
   t->g.stash_n = o.stash;
   t->g.hash_bias = o.hash_bias;
+  t->g.spawn_k = o.spawn_k > 1 ? o.spawn_k : 0;
   t->g.stash_tables = n_tables;
   ck_status st = alloc_scratch(t);
   if (st != CK_OK) {

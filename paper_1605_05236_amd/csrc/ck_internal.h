@@ -162,6 +162,7 @@ struct Geo {
   uint32_t stash_n;
   uint32_t stash_tables;
   uint32_t hash_bias;  // 0: uniform hashes; 1-4: biased
+  uint32_t spawn_k;    // > 1: BFS / sorted search spawn this many records at a time
 };
 
 // Round-scratch pointers of one sub-batch.

@@ -1280,6 +1280,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   constexpr bool by_count = O != kOrderFifo;
   constexpr bool hybrid = O == kOrderDepthCount;
   const bool need_meta = by_count || g.ghost;
+  // k-at-a-time spawning (two-choice bins of 4 or 8 slots): a group is the
+  // next spawn_k records in search order, across buckets, all spawned
+  constexpr bool kable = C == 1 && B >= 4 && !hybrid;
+  const bool kmode = kable && g.spawn_k > 1;
+  const uint32_t glim = kmode ? g.spawn_k * C : G;  // units of one group
   if (lane == 0) {
     region_init(win, r.arena_cap);
     region_init(win + 2, r.spawn_cap);
@@ -1438,7 +1443,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       if (!by_count) {
         const uint32_t tail = nruns * B;
         if (head == tail) break;
-        const uint32_t nrec = min(G / C, tail - head);
+        const uint32_t nrec = min(glim / C, tail - head);
         nu = nrec * C;
 #pragma unroll
         for (int t = 0; t < UW; ++t) {
@@ -1462,9 +1467,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
           bmask = nbmask;
           nbmask = 0;
         }
-        const int kb2 = __ffs(bmask) - 1;
+        int kb2 = __ffs(bmask) - 1;
         uint32_t e = bhead[kb2];
-        while (e != kNone && nu + C <= G) {
+        uint32_t bm = bmask;
+        for (;;) {
+          if (e == kNone) {  // k at a time: on to the next bucket
+            if (!kmode) break;
+            bm &= ~(1u << kb2);
+            if (bm == 0) break;
+            kb2 = __ffs(bm) - 1;
+            e = bhead[kb2];
+            continue;
+          }
+          if (nu + C > glim) break;
 #pragma unroll
           for (uint32_t j = 0; j < C; ++j)
 #pragma unroll
@@ -1557,14 +1572,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const uint32_t avail = g.max_search - views;
         const uint64_t TERM = gballot(nv && term);
         // (the hybrid's new runs are one depth down: never ahead of this group)
-        const uint64_t LOW = (by_count && !hybrid) ? gballot(nv && !term && b2 < kb_now) : 0ull;
+        const uint64_t LOW =
+            (by_count && !hybrid && !kmode) ? gballot(nv && !term && b2 < kb_now) : 0ull;
         const uint64_t CAP = gballot(nv && rank == avail);
         const uint32_t t_term = TERM ? (uint32_t)__ffsll((unsigned long long)TERM) - 1 : 64u;
         const uint32_t t_low = LOW ? (uint32_t)__ffsll((unsigned long long)LOW) - 1 : 64u;
         const uint32_t t_cap = CAP ? (uint32_t)__ffsll((unsigned long long)CAP) - 1 : 64u;
         uint32_t cut = nu;
         bool capped = false;
-        if (t_cap <= t_term && t_cap <= t_low && t_cap < 64u) {
+        if (kmode) {
+          // spawned together: every record of the group views its candidate
+          // (up to the cap); the first bin with room among them ends the chain
+          if (t_cap < 64u) cut = t_cap;
+          found = t_term < cut;
+          capped = t_cap < 64u && !found;
+        } else if (t_cap <= t_term && t_cap <= t_low && t_cap < 64u) {
           cut = t_cap;
           capped = true;
         } else if (t_term < t_low) {
@@ -1612,22 +1634,33 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         if (!by_count) {
           head += cut;
         } else {
-          uint32_t eh = bhead[kb_now];
-          for (uint32_t q = 0; q < cut && eh != kNone; ++q) {
-            if (((eh + 1) & (B - 1)) != 0) {
-              eh = eh + 1;
-            } else {
-              const uint32_t nr = rnext_at(eh / B);
-              eh = nr == kNone ? kNone : nr * B;
+          // the group's records leave the front of the buckets: the first
+          // `cut` records of the lowest bucket, or (k at a time, when the
+          // search goes on) all nu records, lowest bucket first
+          uint32_t left = kmode ? ((found || capped) ? 0u : nu) : cut;
+          bool first_pass = true;
+          while (left || first_pass) {
+            first_pass = false;
+            const uint32_t kbp = kmode ? (uint32_t)(__ffs(bmask) - 1) : kb_now;
+            if (kmode && bmask == 0) break;
+            uint32_t eh = bhead[kbp];
+            for (; left && eh != kNone; --left) {
+              if (((eh + 1) & (B - 1)) != 0) {
+                eh = eh + 1;
+              } else {
+                const uint32_t nr = rnext_at(eh / B);
+                eh = nr == kNone ? kNone : nr * B;
+              }
             }
+            wave_sync();
+            if (gl == 0) {
+              bhead[kbp] = eh;
+              if (eh == kNone) btail[kbp] = kNone;
+            }
+            if (eh == kNone) bmask &= ~(1u << kbp);
+            wave_sync();
+            if (!kmode) break;
           }
-          wave_sync();
-          if (gl == 0) {
-            bhead[kb_now] = eh;
-            if (eh == kNone) btail[kb_now] = kNone;
-          }
-          if (eh == kNone) bmask &= ~(1u << kb_now);
-          wave_sync();
           uint64_t rr = RUNS;
           while (rr) {
             const uint32_t v = (uint32_t)__ffsll((unsigned long long)rr) - 1;

@@ -32,7 +32,8 @@ class CkOptions(ctypes.Structure):
                 ("max_rounds", ctypes.c_uint32), ("batch_ops", ctypes.c_uint32),
                 ("hash_seed", ctypes.c_uint64), ("rng_seed", ctypes.c_uint64),
                 ("evict_wgs_per_cu", ctypes.c_uint32), ("enqueue_rounds", ctypes.c_uint32),
-                ("stash", ctypes.c_uint32), ("hash_bias", ctypes.c_uint32)]
+                ("stash", ctypes.c_uint32), ("hash_bias", ctypes.c_uint32),
+                ("spawn_k", ctypes.c_uint32)]
 
 
 class CkStats(ctypes.Structure):
@@ -190,7 +191,7 @@ class CuckooTable:
     def __init__(self, bins, slots_per_bin=4, d=2, scheme="random_walk", ghost=False,
                  load_balance=False, max_chain=500, max_search=500, max_rounds=0,
                  batch_ops=1 << 20, hash_seed=0, rng_seed=0, device="cuda", stream=None,
-                 evict_wgs_per_cu=0, enqueue_rounds=0, stash=0, hash_bias=0):
+                 evict_wgs_per_cu=0, enqueue_rounds=0, stash=0, hash_bias=0, spawn_k=0):
         import torch
         L = load_library()
         self.n, self.B, self.H = int(bins), int(slots_per_bin), int(d)
@@ -204,6 +205,7 @@ class CuckooTable:
         opt.batch_ops, opt.hash_seed, opt.rng_seed = batch_ops, hash_seed, rng_seed
         opt.evict_wgs_per_cu, opt.enqueue_rounds = evict_wgs_per_cu, enqueue_rounds
         opt.stash, opt.hash_bias = self.stash, int(hash_bias)
+        opt.spawn_k = int(spawn_k)
         self.storage = torch.empty(storage_bytes(self.n, self.B, self.H), dtype=torch.uint8,
                                    device=self.device)
         h = ctypes.c_void_p()
@@ -361,7 +363,7 @@ class CuckooTable:
 
 
 def _options(ghost, load_balance, max_chain, max_search, max_rounds, batch_ops, hash_seed,
-             rng_seed, evict_wgs_per_cu=0, enqueue_rounds=0, stash=0, hash_bias=0):
+             rng_seed, evict_wgs_per_cu=0, enqueue_rounds=0, stash=0, hash_bias=0, spawn_k=0):
     opt = CkOptions()
     load_library().ck_default_options(ctypes.byref(opt))
     opt.ghost, opt.load_balance = int(ghost), int(load_balance)
@@ -369,6 +371,7 @@ def _options(ghost, load_balance, max_chain, max_search, max_rounds, batch_ops, 
     opt.batch_ops, opt.hash_seed, opt.rng_seed = batch_ops, hash_seed, rng_seed
     opt.evict_wgs_per_cu, opt.enqueue_rounds = evict_wgs_per_cu, enqueue_rounds
     opt.stash, opt.hash_bias = stash, hash_bias
+    opt.spawn_k = spawn_k
     return opt
 
 
@@ -386,7 +389,7 @@ class CuckooGroup:
     def __init__(self, bins, slots_per_bin=4, d=2, scheme="queue", ghost=False,
                  load_balance=False, max_chain=500, max_search=500, max_rounds=0,
                  batch_ops=1 << 20, hash_seed=0, rng_seed=0, device="cuda", stream=None,
-                 evict_wgs_per_cu=0, enqueue_rounds=0, stash=0, hash_bias=0):
+                 evict_wgs_per_cu=0, enqueue_rounds=0, stash=0, hash_bias=0, spawn_k=0):
         import torch
         L = load_library()
         self.stash = int(stash)
@@ -400,7 +403,7 @@ class CuckooGroup:
         self.storage = torch.empty(int(size.value), dtype=torch.uint8, device=self.device)
         opt = _options(ghost, load_balance, max_chain, max_search, max_rounds, batch_ops,
                        hash_seed, rng_seed, evict_wgs_per_cu, enqueue_rounds, self.stash,
-                       int(hash_bias))
+                       int(hash_bias), int(spawn_k))
         h = ctypes.c_void_p()
         sch = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
         _check(L.ck_group_create(self.n_tables, self.bins.ctypes.data_as(ctypes.c_void_p),

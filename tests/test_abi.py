@@ -90,5 +90,17 @@ def test_stash_and_bias_options_are_checked_before_device_work(lib):
     assert lib.ck_group_export_stash(None, 0, None, None, None) == -1
 
 
-def test_noalloc_delete_refuses_a_null_handle(lib):
+def test_spawn_k_option_is_checked_before_device_work(lib):
+    # k-at-a-time spawning: BFS (1) and sorted search (2) only, two hash
+    # functions, 4- or 8-slot bins, k <= 32 / slots_per_bin
+    from paper_1605_05236_amd import table
+    h = ctypes.c_void_p()
+    for bins, B, d, scheme, k, want in [(1 << 10, 8, 2, 2, 5, -1), (1 << 10, 4, 2, 1, 9, -1),
+                                        (1 << 10, 4, 2, 0, 2, -5), (1 << 10, 4, 2, 5, 2, -5),
+                                        (1 << 10, 2, 2, 2, 2, -5), (1 << 10, 1, 3, 1, 2, -5)]:
+        o = table.CkOptions()
+        lib.ck_default_options(ctypes.byref(o))
+        o.spawn_k = k
+        assert lib.ck_create(bins, B, d, scheme, ctypes.byref(o), ctypes.c_void_p(256), 1 << 30,
+                             None, ctypes.byref(h)) == want, (B, d, scheme, k)
     assert lib.ck_delete_noalloc(None, None, 5, None, None) == -1
