@@ -2118,15 +2118,30 @@ hipError_t launch_plan_delete(const Geo& g, const Round& r, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // commit: kCommitLanes lanes per plan
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void sc_increment(uint32_t* meta) {
-  uint32_t old = __hip_atomic_load(meta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  for (;;) {
-    const uint32_t sc = (old >> 8) & 0xFu;
-    if (sc >= 15) return;
-    const uint32_t nw = (old & ~0xF00u) | ((sc + 1) << 8);
-    const uint32_t seen = atomicCAS(meta, old, nw);
-    if (seen == old) return;
-    old = seen;
+// Spawn counts (Sec. 5) of one plan: +1 for each listed bin, saturating at
+// 15.  One returning add per increment, four in flight per lane; an add that
+// found the count already at 15 or more is taken back.  While the kernel
+// runs the field may read above 15 (even carry into the byte above it,
+// which only queue-kicking's hit counter uses, and queue-kicking keeps no
+// spawn counts), but the adds that are kept never take it past 15 and every
+// other add is undone, so when the kernel ends the field holds
+// min(15, before + increments) whatever the interleaving.  Nothing reads the
+// spawn counts during the commit kernel.
+__device__ __forceinline__ void sc_increments(uint32_t* meta, const uint32_t* bins, uint32_t n,
+                                              uint32_t first, uint32_t step) {
+  for (uint32_t j0 = first; j0 < n; j0 += 4 * step) {
+    uint32_t b[4], old[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t j = j0 + (uint32_t)u * step;
+      b[u] = j < n ? bins[j] : kNone;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (b[u] != kNone) old[u] = atomicAdd(meta + b[u], 1u << 8);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (b[u] != kNone && (old[u] >> 8) >= 15u) atomicSub(meta + b[u], 1u << 8);
   }
 }
 
@@ -2300,7 +2315,7 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
         }
       }
       // spawn counts (Sec. 5) of every plan, committed or not, saturating at 15
-      for (uint32_t j = gl; j < n_spawn; j += CL) sc_increment(g.meta + r.spawns[spawn_off + j]);
+      if (n_spawn) sc_increments(g.meta, r.spawns + spawn_off, n_spawn, (uint32_t)gl, CL);
     }
     if (nrq) {
       base = __shfl(base, 0, 64);
