@@ -191,7 +191,13 @@ struct Plan {
 
   Plan(const Table& t, uint64_t op_) : T(t), op(op_) {}
 
+  // Transactions (Sec. 8) record every bin whose contents a plan reads: its
+  // read set, claimed like the write set.
+  bool track_reads = false;
+  mutable std::set<uint64_t> reads;
+
   BinState read(uint64_t b) const {
+    if (track_reads) reads.insert(b);
     auto it = draft.find(b);
     return it != draft.end() ? it->second : T.bin(b);
   }
@@ -719,6 +725,97 @@ Plan plan_upsert(const Table& T, uint64_t op, uint64_t key, uint64_t val) {
   return pl;
 }
 
+// ---- Transactions (Sec. 8) --------------------------------------------------------
+// A transaction is a run of operations -- lookups, inserts, deletes and
+// overwrites -- applied atomically.  Reading taken (the round form of Sec. 8's
+// plan / lock-and-verify / apply stages): in a round every pending
+// transaction plans all its operations in order against the round-start
+// snapshot, each one seeing the writes of the earlier ones (the plan's draft,
+// which plays the part of Stage 1's deferred edits).  An insert runs the
+// table's scheme whole, kick-out chain included, inside that draft; an insert
+// whose chain fails leaves the draft as it was before it.  The transaction's
+// read set (every bin whose contents it read: probes, views, the bins of its
+// chains) and write set (every bin it writes) are both claimed with its index,
+// the lowest index winning a bin, as claim flags do; a transaction that owns
+// every bin of both sets commits all its writes, the others plan again next
+// round (whole), and max_rounds turns a persistent loser into an abort.
+// Winners' read and write sets are pairwise disjoint, so the committed
+// transactions are equivalent to running them one at a time, round by round
+// and within a round in index order: the table is transactional in Sec. 8's
+// sense.  The random walk's choices of an insert are keyed by the insert's
+// index in the call's operations.
+enum TxnOp { TX_LOOKUP = 0, TX_INSERT = 1, TX_DELETE = 2, TX_OVERWRITE = 3 };
+
+struct TxnResult {
+  std::vector<uint8_t> status;  // per op of the transaction
+  std::vector<uint64_t> value;  // lookups that hit
+};
+
+// Find key x through the plan's draft: (bin, slot) or bin kEmpty.
+static std::pair<uint64_t, int> txn_find(Plan& pl, uint64_t x, const uint64_t* h) {
+  for (int i = 0; i < pl.T.p.H; ++i) {
+    BinState s = pl.read(h[i]);
+    for (int j = 0; j < pl.T.p.B; ++j)
+      if (s.s[j].key == x) return {h[i], j};
+  }
+  return {kEmpty, -1};
+}
+
+Plan plan_txn(const Table& T, const uint8_t* kind, const uint64_t* keys, const uint64_t* vals,
+              uint64_t o0, uint64_t o1, uint64_t op_base, TxnResult* out) {
+  Plan pl(T, 0);
+  pl.track_reads = true;
+  out->status.assign(o1 - o0, ST_NOT_FOUND);
+  out->value.assign(o1 - o0, 0);
+  for (uint64_t j = o0; j < o1; ++j) {
+    const uint64_t x = keys[j];
+    uint8_t& st = out->status[j - o0];
+    if (x == kEmpty) { st = ST_BAD_KEY; continue; }
+    uint64_t h[4];
+    T.hash(x, h);
+    if (kind[j] == TX_LOOKUP) {
+      auto f = txn_find(pl, x, h);
+      if (f.second >= 0) {
+        st = ST_OK;
+        out->value[j - o0] = pl.read(f.first).s[f.second].val;
+      }
+    } else if (kind[j] == TX_DELETE) {
+      auto f = txn_find(pl, x, h);
+      if (f.second >= 0) {
+        BinState& w = pl.write(f.first);
+        w.s[f.second] = Slot();
+        w.dup &= (uint8_t)~(1u << f.second);
+        st = ST_OK;
+      }
+    } else if (kind[j] == TX_OVERWRITE) {
+      auto f = txn_find(pl, x, h);
+      if (f.second >= 0) {
+        pl.write(f.first).s[f.second].val = T.p.B == 1 ? (vals[j] & 0xFFFFFFFFull) : vals[j];
+        st = ST_OK;
+      }
+    } else {  // insert (the key is assumed absent, Sec. 3)
+      const auto saved = pl.draft;
+      pl.op = op_base + j;
+      pl.draws = 0;
+      pl.status = ST_FAIL;
+      Slot r;
+      r.key = x;
+      r.val = vals[j];
+      switch (T.p.scheme) {
+        case RANDOM_WALK: pl.random_walk(r, h); break;
+        case BFS: pl.search(r, h, Plan::BY_FIFO); break;
+        case SORTED: pl.search(r, h, Plan::BY_COUNT); break;
+        case HYBRID: pl.search(r, h, Plan::BY_DEPTH_COUNT); break;
+        case QUEUE: pl.queue_kick(r, h); break;
+        case RATTLE: pl.rattle(r, h); break;
+      }
+      st = (uint8_t)pl.status;
+      if (pl.status != ST_OK) pl.draft = saved;  // a failed insert writes nothing
+    }
+  }
+  return pl;
+}
+
 // ---- Deterministic phased rounds ------------------------------------------------
 // Every pending op plans against the same snapshot; each plan claims the bins
 // it writes, lowest op index winning a bin; a plan that owns all its bins is
@@ -1075,6 +1172,95 @@ void ck_oracle_overwrite(void* tp, const uint64_t* keys, const uint64_t* vals, u
       retries[b0 + i] = res[i].retries;
     }
   }
+}
+
+// Transactional batch (Sec. 8): n_txn transactions, transaction t being the
+// operations [txn_off[t], txn_off[t + 1]) of kind / keys / vals (kinds: 0
+// lookup, 1 insert, 2 delete, 3 overwrite), applied in sub-batches of
+// batch_ops transactions by the transaction rounds above.  Per op: status
+// (lookup / delete / overwrite: found or not; insert: OK or FAIL; ABORTED for
+// every op of an aborted transaction; BAD_KEY) and the value of a lookup
+// that hit.  Per transaction: the round (within its sub-batch, from 0) in
+// which it committed, and the rounds it lost.  Tables with ghosts or a stash
+// are refused (-1); so are upserts, by having no kind for them.
+int ck_oracle_txn(void* tp, const uint8_t* kind, const uint64_t* keys, const uint64_t* vals,
+                  const uint64_t* txn_off, uint64_t n_txn, uint8_t* status, uint64_t* vals_out,
+                  uint32_t* txn_round, uint32_t* txn_retries) {
+  Table& T = *(Table*)tp;
+  if (T.p.ghost || !T.stash.empty()) return -1;
+  const uint64_t op_base = T.insert_count;
+  for (uint64_t t0 = 0; t0 < n_txn; t0 += T.p.batch_ops) {
+    const uint64_t m = std::min<uint64_t>(T.p.batch_ops, n_txn - t0);
+    std::vector<uint64_t> pending;
+    for (uint64_t i = 0; i < m; ++i) pending.push_back(i);
+    std::vector<uint32_t> retries(m, 0);
+    uint32_t round = 0;
+    while (!pending.empty()) {
+      std::vector<Plan> plans;
+      std::vector<TxnResult> outs(pending.size());
+      plans.reserve(pending.size());
+      for (size_t k = 0; k < pending.size(); ++k) {
+        const uint64_t t = t0 + pending[k];
+        plans.push_back(plan_txn(T, kind, keys, vals, txn_off[t], txn_off[t + 1], op_base,
+                                 &outs[k]));
+      }
+      std::map<uint64_t, uint64_t> owner;  // bin -> lowest transaction claiming it
+      auto take = [&](uint64_t b, uint64_t i) {
+        auto it = owner.find(b);
+        if (it == owner.end() || i < it->second) owner[b] = i;
+      };
+      for (size_t k = 0; k < plans.size(); ++k) {
+        for (auto& kv : plans[k].draft) take(kv.first, pending[k]);
+        for (uint64_t b : plans[k].reads) take(b, pending[k]);
+      }
+      std::vector<uint64_t> next;
+      for (size_t k = 0; k < plans.size(); ++k) {
+        const uint64_t i = pending[k], t = t0 + i;
+        bool wins = true;
+        for (auto& kv : plans[k].draft)
+          if (owner[kv.first] != i) wins = false;
+        for (uint64_t b : plans[k].reads)
+          if (owner[b] != i) wins = false;
+        const uint64_t o0 = txn_off[t], o1 = txn_off[t + 1];
+        if (wins) {
+          for (auto& kv : plans[k].draft) {
+            BinState nb = kv.second;
+            nb.sc = T.bins[kv.first].sc;  // spawn counts are merged below
+            T.bins[kv.first] = nb;
+          }
+          for (uint64_t j = o0; j < o1; ++j) {
+            status[j] = outs[k].status[j - o0];
+            vals_out[j] = outs[k].value[j - o0];
+            if (status[j] == ST_OK && kind[j] == TX_INSERT) { ++T.st.stored; ++T.st.inserts_ok; }
+            if (status[j] == ST_FAIL) ++T.st.inserts_failed;
+            if (status[j] == ST_OK && kind[j] == TX_DELETE) { --T.st.stored; ++T.st.deletes_found; }
+          }
+          txn_round[t] = round;
+          txn_retries[t] = retries[i];
+        } else if (T.p.max_rounds && ++retries[i] >= T.p.max_rounds) {
+          for (uint64_t j = o0; j < o1; ++j) {
+            status[j] = ST_ABORTED;
+            vals_out[j] = 0;
+          }
+          txn_round[t] = round;
+          txn_retries[t] = retries[i];
+        } else {
+          if (!T.p.max_rounds) ++retries[i];
+          next.push_back(i);
+        }
+      }
+      for (auto& pl : plans)
+        for (uint64_t b : pl.spawns) {
+          T.bins[b].sc = (uint8_t)std::min(15, T.bins[b].sc + 1);
+          if (T.log_spawns) T.spawn_log.push_back({pl.op, b});
+        }
+      ++round;
+      pending.swap(next);
+    }
+    T.st.rounds += round;
+  }
+  T.insert_count += txn_off[n_txn] - txn_off[0];
+  return 0;
 }
 
 // Canonical image of the table: keys and values per slot, rattle counters

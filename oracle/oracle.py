@@ -74,6 +74,8 @@ def lib():
         L.ck_oracle_import_stash.argtypes = [vp, vp, vp]
         L.ck_oracle_import.argtypes = [vp, vp, vp, vp, vp]
         L.ck_oracle_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
+        L.ck_oracle_txn.argtypes = [vp, vp, vp, vp, vp, u64, vp, vp, vp, vp]
+        L.ck_oracle_txn.restype = i32
         L.ck_oracle_set_spawn_k.argtypes = [vp, u32]
         L.ck_oracle_set_spawn_k.restype = i32
         L.ck_oracle_log_spawns.argtypes = [vp, i32]
@@ -217,6 +219,25 @@ class OracleTable:
         for f in ("band_inserts", "band_views", "band_kicks", "band_fails"):
             out[f] = np.array(list(getattr(s, f)), dtype=np.uint64)
         return out
+
+    def transactions(self, kinds, keys, vals, txn_off):
+        """Transactional batch (Sec. 8): transaction t is ops
+        [txn_off[t], txn_off[t+1]) (kinds 0 lookup, 1 insert, 2 delete, 3
+        overwrite).  Returns per-op status and value, and per-transaction
+        commit round and lost rounds."""
+        kinds = np.ascontiguousarray(kinds, dtype=np.uint8)
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        vals = np.ascontiguousarray(vals, dtype=np.uint64)
+        off = np.ascontiguousarray(txn_off, dtype=np.uint64)
+        nt = off.size - 1
+        status = np.zeros(keys.size, np.uint8)
+        vout = np.zeros(keys.size, np.uint64)
+        rnd = np.zeros(nt, np.uint32)
+        ret = np.zeros(nt, np.uint32)
+        if lib().ck_oracle_txn(self._t, _p(kinds), _p(keys), _p(vals), _p(off), nt, _p(status),
+                               _p(vout), _p(rnd), _p(ret)) != 0:
+            raise ValueError("transactions need a table without ghosts or a stash")
+        return {"status": status, "value": vout, "round": rnd, "retries": ret}
 
     def log_spawns(self, on=True):
         """Start (clearing it) or stop the record of spawn-count increments."""
