@@ -103,6 +103,10 @@ struct Params {
   // BFS and sorted search spawning k records at a time (Sec. 5, Prefetching);
   // 0: the one-at-a-time searches
   uint32_t spawn_k = 0;
+  // transactions: a plan that reads or writes more distinct bins than this
+  // aborts (its claims and writes would not fit a bounded per-transaction
+  // record)
+  uint32_t txn_bins = 256;
 };
 
 struct Stats {
@@ -967,6 +971,14 @@ int ck_oracle_set_spawn_k(void* tp, uint32_t k) {
   return 0;
 }
 
+// The bound on the distinct bins one transaction's plan may touch (>= 1).
+int ck_oracle_set_txn_bins(void* tp, uint32_t bins) {
+  Table& T = *(Table*)tp;
+  if (bins == 0) return -1;
+  T.p.txn_bins = bins;
+  return 0;
+}
+
 // Give an empty table a stash of `entries` entries (at most kMaxStash).
 int ck_oracle_set_stash(void* tp, uint32_t entries) {
   Table& T = *(Table*)tp;
@@ -1209,14 +1221,22 @@ int ck_oracle_txn(void* tp, const uint8_t* kind, const uint64_t* keys, const uin
         auto it = owner.find(b);
         if (it == owner.end() || i < it->second) owner[b] = i;
       };
+      // a plan that touched more than txn_bins distinct bins aborts: no claims
+      std::vector<bool> too_big(plans.size(), false);
       for (size_t k = 0; k < plans.size(); ++k) {
+        std::set<uint64_t> touched(plans[k].reads);
+        for (auto& kv : plans[k].draft) touched.insert(kv.first);
+        too_big[k] = touched.size() > T.p.txn_bins;
+      }
+      for (size_t k = 0; k < plans.size(); ++k) {
+        if (too_big[k]) continue;
         for (auto& kv : plans[k].draft) take(kv.first, pending[k]);
         for (uint64_t b : plans[k].reads) take(b, pending[k]);
       }
       std::vector<uint64_t> next;
       for (size_t k = 0; k < plans.size(); ++k) {
         const uint64_t i = pending[k], t = t0 + i;
-        bool wins = true;
+        bool wins = !too_big[k];
         for (auto& kv : plans[k].draft)
           if (owner[kv.first] != i) wins = false;
         for (uint64_t b : plans[k].reads)
@@ -1237,7 +1257,7 @@ int ck_oracle_txn(void* tp, const uint8_t* kind, const uint64_t* keys, const uin
           }
           txn_round[t] = round;
           txn_retries[t] = retries[i];
-        } else if (T.p.max_rounds && ++retries[i] >= T.p.max_rounds) {
+        } else if (too_big[k] || (T.p.max_rounds && ++retries[i] >= T.p.max_rounds)) {
           for (uint64_t j = o0; j < o1; ++j) {
             status[j] = ST_ABORTED;
             vals_out[j] = 0;

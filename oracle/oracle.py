@@ -76,6 +76,8 @@ def lib():
         L.ck_oracle_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
         L.ck_oracle_txn.argtypes = [vp, vp, vp, vp, vp, u64, vp, vp, vp, vp]
         L.ck_oracle_txn.restype = i32
+        L.ck_oracle_set_txn_bins.argtypes = [vp, u32]
+        L.ck_oracle_set_txn_bins.restype = i32
         L.ck_oracle_set_spawn_k.argtypes = [vp, u32]
         L.ck_oracle_set_spawn_k.restype = i32
         L.ck_oracle_log_spawns.argtypes = [vp, i32]
@@ -219,6 +221,12 @@ class OracleTable:
         for f in ("band_inserts", "band_views", "band_kicks", "band_fails"):
             out[f] = np.array(list(getattr(s, f)), dtype=np.uint64)
         return out
+
+    def set_txn_bins(self, bins):
+        """Bound on the distinct bins a transaction's plan may touch (default
+        256); a larger plan aborts."""
+        if lib().ck_oracle_set_txn_bins(self._t, int(bins)) != 0:
+            raise ValueError("bad bound")
 
     def transactions(self, kinds, keys, vals, txn_off):
         """Transactional batch (Sec. 8): transaction t is ops

@@ -124,6 +124,20 @@ def test_aborted_transactions_leave_no_trace():
     assert table_dict(t) == replay(kinds, keys, vals, off, res, 100)
 
 
+def test_transactions_touching_too_many_bins_abort():
+    # A plan that touches more distinct bins than the bound aborts whole (its
+    # ops report ABORTED, nothing of it is applied); the rest stay serializable.
+    n, B = 1 << 6, 4
+    kinds, keys, vals, off = workload(75, 120, int(0.97 * n * B), max_ops=6, p_insert=0.8)
+    t = oracle.OracleTable(n, B, 2, "random_walk", batch_ops=16, hash_seed=175, rng_seed=275)
+    t.set_txn_bins(6)
+    res = t.transactions(kinds, keys, vals, off)
+    aborted = [i for i in range(off.size - 1)
+               if (res["status"][int(off[i]):int(off[i + 1])] == oracle.ST_ABORTED).all()]
+    assert 0 < len(aborted) < off.size - 1
+    assert table_dict(t) == replay(kinds, keys, vals, off, res, 16)
+
+
 @pytest.mark.parametrize("scheme", ["random_walk", "sorted", "queue"])
 def test_one_op_transactions_are_the_plain_calls(scheme):
     # Serially, a transaction of one operation is that operation (Sec. 1):
@@ -135,6 +149,7 @@ def test_one_op_transactions_are_the_plain_calls(scheme):
     kw = dict(batch_ops=1, hash_seed=173, rng_seed=273)
     a = oracle.OracleTable(n, B, 2, scheme, **kw)
     b = oracle.OracleTable(n, B, 2, scheme, **kw)
+    b.set_txn_bins(1 << 20)  # no transaction is cut off by its bin count here
     ra = a.insert(keys, vals)
     rb = b.transactions(np.full(m, INSERT, np.uint8), keys, vals, np.arange(m + 1))
     assert np.array_equal(ra["status"], rb["status"])
