@@ -801,6 +801,8 @@ Plan plan_txn(const Table& T, const uint8_t* kind, const uint64_t* keys, const u
       const auto saved = pl.draft;
       pl.op = op_base + j;
       pl.draws = 0;
+      pl.kicks = 0;  // the chain and search caps are per insert
+      pl.views = 0;
       pl.status = ST_FAIL;
       Slot r;
       r.key = x;
