@@ -82,6 +82,9 @@ def parse():
     p.add_argument("--hit-rate", type=float, default=0.9)
     p.add_argument("--deletes-log2", type=int, default=20)
     p.add_argument("--max-search", type=int, default=500)
+    p.add_argument("--spawn-k", type=int, default=0,
+                   help="fill: BFS and sorted search spawn this many records at a time "
+                        "(Sec. 5, Prefetching; 0 = one at a time)")
     p.add_argument("--lpp", type=int, default=0,
                    help="lookup lanes per probe (1 or slots per bin; 0 = slots per bin)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -442,7 +445,10 @@ def run_serve(args):
                                                    else "all arriving at once"),
                    "scheme": args.group_scheme, "max_batch_ops": args.max_batch_ops},
         "latency": summ, "batches": res.stats["batches"], "wrong_answers": wrong,
-        "host_issue_s": res.stats["host_issue_s"], "device_wait_s": res.stats["device_wait_s"],
+        "host_issue_s": res.stats["host_issue_s"],
+        "host_issue_frac_of_span": res.stats["host_issue_s"] / summ["span_s"] if summ["span_s"] else None,
+        "host_slot_wait_s": res.stats["host_slot_wait_s"],
+        "device_calls_s": res.stats["device_calls_s"],
         "offered_ops_per_s": nops / float(arrivals[-1]) if arrivals[-1] > 0 else None,
     }
     print(json.dumps(out), flush=True)
@@ -780,7 +786,8 @@ def main():
     print(f"# inputs ready in {time.time() - t0:.1f}s: {m} inserts, {nq} lookups, "
           f"{dels.size} deletes", file=sys.stderr, flush=True)
     tables = {s: CuckooTable(n, B, 2, s, max_search=args.max_search,
-                             batch_ops=1 << args.batch_log2, hash_seed=102, rng_seed=202)
+                             batch_ops=1 << args.batch_log2, hash_seed=102, rng_seed=202,
+                             spawn_k=args.spawn_k if s in ("bfs", "sorted") else 0)
               for s in schemes}
     stream = torch.cuda.current_stream()
     vout = torch.empty(nq, dtype=torch.int64, device="cuda")
@@ -1032,7 +1039,8 @@ def main():
                                f"stored keys, 2^{args.deletes_log2 + 1} upserts (half stored, "
                                f"half absent), then deletes of the stored keys",
                    "bins": n, "slots_per_bin": B, "inserts_per_fill": m,
-                   "lookups": nq, "deletes": int(dels.size), "max_search": args.max_search},
+                   "lookups": nq, "deletes": int(dels.size), "max_search": args.max_search,
+                   "spawn_k": args.spawn_k},
         "inserts_per_s_by_scheme": {s: m / fill[s] for s in schemes},
         "bins_viewed_per_insert_at_95": bv95,
         "bins_viewed_per_insert_by_load": by_load,

@@ -5,8 +5,11 @@ time, open loop.  Their payloads sit back to back in host memory in arrival
 order (a receive buffer), so every arrival range is one contiguous copy.
 
 * Upload: at the top of every loop iteration the newly arrived range of keys
-  and values is copied to the device on a copy stream; the batch's kernels
-  wait for it by event, so the copy overlaps the host's batch selection.
+  and values is copied to the device on the marshalling stream.
+* Overlap: batch b + 1 is selected and marshalled (on the marshalling
+  stream, by the calling thread) while batch b's table calls run on the
+  compute stream (driven by a worker thread); up to `depth` batches are in
+  flight, each with its own gather buffers.
 * Batching: each batch takes, per table, the longest run of consecutive
   requests of one kind at the head of that table's queue (coalescing them).
   A table thus contributes one kind per batch, so running a batch's lookups,
@@ -230,11 +233,10 @@ class Server:
     def _take(self, rs, pending):
         return take_batch(rs.kind, rs.table, rs.n, pending, self.max_batch_ops)
 
-    def _execute(self, rs, taken, dev, cursor, aoff, staging):
-        """Run one batch; answers go to [cursor, ...) of the answer buffers in
-        batch order.  Returns the new cursor."""
-        import torch
-        d_keys, d_vals, d_flag, d_val = dev
+    def _plan(self, rs, taken, cursor, aoff):
+        """A batch's launch groups: (kind, slab, requests, answer offset, ops) per
+        kind (lookups, deletes, inserts, in that order) and slab; every
+        request's answers get the next range of the answer buffers."""
         kinds = rs.kind[taken]
         slabs = self.slab_of(rs.table[taken])
         groups = []
@@ -247,14 +249,24 @@ class Server:
                 if tot:
                     groups.append((kind, int(s), sel, cursor, tot))
                     cursor += tot
-        if not groups:
-            return cursor
-        # segment arrays of every group (lengths, receive offsets, table ids)
-        # in one pinned buffer, one asynchronous copy
+        return groups, cursor
+
+    def _marshal(self, rs, groups, slot, d_keys, d_vals):
+        """Gather a batch's keys, values and table ids from the device copy of
+        the receive buffer into the slot's buffers (segment lists go up in one
+        pinned copy).  Enqueued on the current stream."""
+        import torch
         m = sum(g[2].size for g in groups)
-        if staging[0] is None or staging[0].numel() < 3 * m:
-            staging[0] = torch.empty(max(3 * m, 1 << 14), dtype=torch.int64, pin_memory=True)
-        h = staging[0].numpy()
+        if slot["staging"] is None or slot["staging"].numel() < 3 * m:
+            slot["staging"] = torch.empty(max(3 * m, 1 << 14), dtype=torch.int64,
+                                          pin_memory=True)
+        tot_all = sum(g[4] for g in groups)
+        if slot["keys"] is None or slot["keys"].numel() < tot_all:
+            size = max(tot_all, self.max_batch_ops, 1 << 16)
+            slot["keys"] = torch.empty(size, dtype=torch.int64, device=self.device)
+            slot["vals"] = torch.empty(size, dtype=torch.int64, device=self.device)
+            slot["tids"] = torch.empty(size, dtype=torch.int32, device=self.device)
+        h = slot["staging"].numpy()
         o = 0
         for kind, s, sel, c0, tot in groups:
             k = sel.size
@@ -262,8 +274,8 @@ class Server:
             h[o + k:o + 2 * k] = rs.off[sel]
             h[o + 2 * k:o + 3 * k] = rs.table[sel] - s * self.slab_tables
             o += 3 * k
-        dh = staging[0][:3 * m].to(self.device, non_blocking=True)
-        o = 0
+        dh = slot["staging"][:3 * m].to(self.device, non_blocking=True)
+        o = b = 0
         for kind, s, sel, c0, tot in groups:
             k = sel.size
             dln, dsrc, dtab = dh[o:o + k], dh[o + k:o + 2 * k], dh[o + 2 * k:o + 3 * k]
@@ -272,23 +284,45 @@ class Server:
                                           output_size=tot)
             first = torch.cumsum(dln, 0) - dln
             pos = torch.arange(tot, device=self.device) - first[seg] + dsrc[seg]
-            tids = dtab[seg].to(torch.int32)
+            torch.index_select(d_keys, 0, pos, out=slot["keys"][b:b + tot])
+            if kind == INSERT:
+                torch.index_select(d_vals, 0, pos, out=slot["vals"][b:b + tot])
+            slot["tids"][b:b + tot].copy_(dtab[seg])
+            b += tot
+
+    def _execute(self, groups, slot, d_flag, d_val, stream):
+        """The table calls of one marshalled batch, on `stream` (lookups first,
+        then deletes, then inserts: each table's FIFO order)."""
+        b = 0
+        for kind, s, sel, c0, tot in groups:
             g = self.slabs[s]
-            keys = d_keys[pos]
+            keys, tids = slot["keys"][b:b + tot], slot["tids"][b:b + tot]
             c1 = c0 + tot
             if kind == LOOKUP:
                 g.lookup(tids, keys, lanes_per_probe=self.lpp, out=d_val[c0:c1],
-                         found=d_flag[c0:c1])
+                         found=d_flag[c0:c1], stream=stream)
             elif kind == DELETE:
-                d_flag[c0:c1].copy_(g.delete(tids, keys))
+                d_flag[c0:c1].copy_(g.delete(tids, keys, stream=stream))
             else:
-                d_flag[c0:c1].copy_(g.insert(tids, keys, d_vals[pos], diagnostics=False)["status"])
-        return cursor
+                d_flag[c0:c1].copy_(g.insert(tids, keys, slot["vals"][b:b + tot],
+                                             diagnostics=False, stream=stream)["status"])
+            b += tot
 
     # ---- the request loop --------------------------------------------------
-    def run(self, rs: RequestSet) -> Results:
+    def run(self, rs: RequestSet, depth: int = 2) -> Results:
         """Serve the request set, each request becoming visible at its arrival
-        time (seconds from the start of the call)."""
+        time (seconds from the start of the call).
+
+        Two threads and two streams keep up to `depth` batches in flight.  The
+        calling thread uploads arrivals, selects batch b + 1 and marshals it on
+        the marshalling stream (gathers into one of `depth` buffer slots) while
+        batch b's table calls run on the compute stream, driven by a worker
+        thread (the table calls return once their rounds are done).  The
+        worker runs batches in selection order, so every table's requests keep
+        their FIFO order; a batch's answers go back to host memory with one copy
+        on the compute stream, and its requests complete when that copy has."""
+        import queue
+        import threading
         import torch
         R = len(rs)
         total = int(rs.off[-1])
@@ -300,65 +334,128 @@ class Server:
         d_val = torch.zeros(cap, dtype=torch.int64, device=dev)
         h_flag = torch.zeros(cap, dtype=torch.uint8, pin_memory=True)
         h_val = torch.zeros(cap, dtype=torch.int64, pin_memory=True)
+        torch.cuda.current_stream(dev).synchronize()  # the buffers exist before other streams use them
         done = np.full(R, np.nan)
         aoff = np.zeros(R, np.int64)
-        comp = torch.cuda.current_stream(dev)
-        copy_stream = torch.cuda.Stream(dev)
-        staging = [None]
+        comp = torch.cuda.Stream(dev)   # table calls and answer copies (worker)
+        prep = torch.cuda.Stream(dev)   # uploads and marshalling (calling thread)
+        free = queue.Queue()
+        # each slot's buffers exist before the clock starts (a warm server)
+        size = max(self.max_batch_ops, 1 << 16)
+        for _ in range(max(1, depth)):
+            free.put({"staging": torch.empty(3 << 16, dtype=torch.int64, pin_memory=True),
+                      "keys": torch.empty(size, dtype=torch.int64, device=dev),
+                      "vals": torch.empty(size, dtype=torch.int64, device=dev),
+                      "tids": torch.empty(size, dtype=torch.int32, device=dev)})
+        torch.cuda.current_stream(dev).synchronize()
+        work = queue.Queue()
+        failure = []
+        busy = [0.0]
+        ready_evt = threading.Event()
+        start = 0.0
+
+        def worker():
+            try:
+                torch.cuda.set_device(dev)
+                with torch.cuda.stream(comp):
+                    ready_evt.set()
+                    while True:
+                        item = work.get()
+                        if item is None:
+                            return
+                        slot, groups, taken, ready, c0, c1 = item
+                        t0 = time.perf_counter()
+                        comp.wait_event(ready)
+                        self._execute(groups, slot, d_flag, d_val, comp)
+                        if c1 > c0:
+                            h_flag[c0:c1].copy_(d_flag[c0:c1], non_blocking=True)
+                            h_val[c0:c1].copy_(d_val[c0:c1], non_blocking=True)
+                        fin = torch.cuda.Event()
+                        fin.record(comp)
+                        fin.synchronize()
+                        done[taken] = time.perf_counter() - start
+                        busy[0] += time.perf_counter() - t0
+                        free.put(slot)
+            except BaseException as e:  # surfaced by the calling thread
+                failure.append(e)
+                ready_evt.set()
+                free.put(None)
+
+        # the two threads hand the interpreter lock back and forth at every
+        # call; the default 5 ms switch interval would make the calling thread
+        # wait for the worker's Python steps (and the other way round)
+        import sys
+        old_switch = sys.getswitchinterval()
+        sys.setswitchinterval(5e-5)
+        th = threading.Thread(target=worker, daemon=True)
+        th.start()
+        ready_evt.wait()
+        start = time.perf_counter()
         up = 0  # requests uploaded
-        ev = None  # event after the last upload
         pending = np.empty(0, np.int64)
         admitted = np.zeros(len(self.slabs), bool)
         batches = ops = cursor = 0
         host_s = wait_s = 0.0
-        start = time.perf_counter()
-        while True:
-            now = time.perf_counter() - start
-            a = int(np.searchsorted(rs.arrival, now, side="right"))
-            if a > up:
-                o0, o1 = int(rs.off[up]), int(rs.off[a])
-                with torch.cuda.stream(copy_stream):
+        try:
+            while not failure:
+                now = time.perf_counter() - start
+                a = int(np.searchsorted(rs.arrival, now, side="right"))
+                if a > up:
+                    new = np.arange(up, a, dtype=np.int64)
+                    sl = self.slab_of(rs.table[new])
+                    fresh = False
+                    for s in np.unique(sl):
+                        if self.slabs[s] is None:
+                            admitted[s] = self._admit_slab(int(s))
+                            fresh |= bool(admitted[s])
+                        else:
+                            admitted[s] = True
+                    if fresh:  # a new slab's initialisation is done before any stream uses it
+                        torch.cuda.current_stream(dev).synchronize()
+                    o0, o1 = int(rs.off[up]), int(rs.off[a])
                     if o1 > o0:
-                        d_keys[o0:o1].copy_(rs.keys[o0:o1], non_blocking=True)
-                        d_vals[o0:o1].copy_(rs.vals[o0:o1], non_blocking=True)
-                    ev = torch.cuda.Event()
-                    ev.record(copy_stream)
-                new = np.arange(up, a, dtype=np.int64)
-                up = a
-                sl = self.slab_of(rs.table[new])
-                for s in np.unique(sl):
-                    admitted[s] = self._admit_slab(int(s))
-                ok = admitted[sl]
-                self.stats["deferred"] += int((~ok).sum())
-                pending = np.concatenate([pending, new[ok]])
-            if pending.size == 0:
-                if up == R:
+                        with torch.cuda.stream(prep):
+                            d_keys[o0:o1].copy_(rs.keys[o0:o1], non_blocking=True)
+                            d_vals[o0:o1].copy_(rs.vals[o0:o1], non_blocking=True)
+                    up = a
+                    ok = admitted[sl]
+                    self.stats["deferred"] += int((~ok).sum())
+                    pending = np.concatenate([pending, new[ok]])
+                if pending.size == 0:
+                    if up == R:
+                        break
+                    time.sleep(min(max(rs.arrival[up] - now, 0.0), 0.0005))
+                    continue
+                t0 = time.perf_counter()
+                slot = free.get()  # at most `depth` batches in flight
+                if slot is None:
                     break
-                time.sleep(min(max(rs.arrival[up] - now, 0.0), 0.0005))
-                continue
-            t0 = time.perf_counter()
-            taken, pending = self._take(rs, pending)
-            comp.wait_event(ev)
-            c0 = cursor
-            cursor = self._execute(rs, taken, (d_keys, d_vals, d_flag, d_val), cursor, aoff,
-                                   staging)
-            if cursor > c0:
-                h_flag[c0:cursor].copy_(d_flag[c0:cursor], non_blocking=True)
-                h_val[c0:cursor].copy_(d_val[c0:cursor], non_blocking=True)
-            t1 = time.perf_counter()
-            comp.synchronize()
-            t2 = time.perf_counter()
-            host_s += t1 - t0
-            wait_s += t2 - t1
-            done[taken] = t2 - start
-            batches += 1
-            ops += int(rs.n[taken].sum())
-        copy_stream.synchronize()  # uploads of never-served requests end here
+                t1 = time.perf_counter()
+                taken, pending = self._take(rs, pending)
+                c0 = cursor
+                groups, cursor = self._plan(rs, taken, cursor, aoff)
+                with torch.cuda.stream(prep):
+                    self._marshal(rs, groups, slot, d_keys, d_vals)
+                    ready = torch.cuda.Event()
+                    ready.record(prep)
+                work.put((slot, groups, taken, ready, c0, cursor))
+                t2 = time.perf_counter()
+                wait_s += t1 - t0
+                host_s += t2 - t1
+                batches += 1
+                ops += int(rs.n[taken].sum())
+        finally:
+            work.put(None)
+            th.join()
+            sys.setswitchinterval(old_switch)
+            prep.synchronize()  # uploads of never-served requests end here
+        if failure:
+            raise failure[0]
         self.stats["batches"] += batches
         self.stats["ops"] += ops
         return Results(rs, done, aoff, h_flag.numpy()[:total], h_val.numpy()[:total],
                        {"batches": batches, "ops": ops, "host_issue_s": host_s,
-                        "device_wait_s": wait_s})
+                        "host_slot_wait_s": wait_s, "device_calls_s": busy[0]})
 
     def close(self):
         for s in range(len(self.slabs)):
