@@ -94,7 +94,7 @@ def parse():
     p.add_argument("--cpu-bins-log2", type=int, default=19)
     p.add_argument("--workload", default="fill",
                    choices=["fill", "group", "serve", "mixed", "dary", "bias", "stash",
-                            "ceilings", "small"],
+                            "ceilings", "small", "txn"],
                    help="fill: one 2^24 x 8 table (default); group: 4096 tables of "
                         "2^10..2^20 bins x 4 slots, batched vs per-request launches; "
                         "serve: the same tables behind the continuous-batching server, "
@@ -104,6 +104,7 @@ def parse():
                         "gathers and 64-bit atomics over 2 GiB; small: the 2^16 x 4 "
                         "random-walk table")
     p.add_argument("--mixed-steps", type=int, default=1024, help="mixed: steps of 2^18 ops")
+    p.add_argument("--txn-ops", type=int, default=100, help="txn: operations per transaction")
     p.add_argument("--dary-schemes", default="rattle,random_walk", help="dary: schemes")
     p.add_argument("--rate", type=float, default=200_000.0, help="serve: requests per second")
     p.add_argument("--max-batch-ops", type=int, default=1 << 22, help="serve: ops per batch cap")
@@ -661,6 +662,81 @@ def run_bias(args):
         "by_case": res}), flush=True)
 
 
+def run_txn(args):
+    """Transactional batches (Sec. 8): a 2^20 x 8 table (random kicking with
+    load balancing, as in the paper's transactional experiments) prefilled to
+    0.5, then transactions of --txn-ops operations in the paper's two mixes
+    (inserts : deletes : overwrites : reads = 1:0:1:1, delete-light, and
+    2:1:2:2, delete-heavy) until 0.9 load; reads, deletes and overwrites pick
+    uniformly among the keys inserted so far (stored or since deleted)."""
+    import torch
+    from paper_1605_05236_amd import inputs
+    from paper_1605_05236_amd.table import CuckooTable, as_device_keys
+    torch.cuda.set_device(0)
+    n, B = 1 << 20, 8
+    out = {}
+    total_ops, total_s = 0, 0.0
+    for name, ratio in (("delete_light", (1, 0, 1, 1)), ("delete_heavy", (2, 1, 2, 2))):
+        t = CuckooTable(n, B, 2, "random_walk", load_balance=True, max_chain=500,
+                        batch_ops=1 << 14, hash_seed=106, rng_seed=206)
+        m0 = inputs.target_count(n, B, 0.5)
+        pk, pv = inputs.keys_values(6, m0)
+        t.insert(as_device_keys(pk), as_device_keys(pv), diagnostics=False)
+        # enough ops that the inserts (net of deletes) bring the load to 0.9
+        net = (ratio[0] - ratio[1]) / sum(ratio)
+        nops = int((inputs.target_count(n, B, 0.9) - m0) / net)
+        nops -= nops % args.txn_ops
+        rng = np.random.default_rng(306)
+        kind = rng.choice(4, nops, p=np.array([ratio[3], ratio[0], ratio[1], ratio[2]]) /
+                          sum(ratio)).astype(np.uint8)  # 0 read, 1 insert, 2 delete, 3 overwrite
+        ins = kind == 1
+        nins = int(ins.sum())
+        fk, fv = inputs.keys_values(6, nins, start=m0)
+        keys = np.empty(nops, np.uint64)
+        vals = rng.integers(0, 1 << 63, nops, dtype=np.uint64)
+        keys[ins] = fk
+        vals[ins] = fv
+        # the others: a uniform pick among the keys inserted before them
+        before = np.cumsum(ins) - ins  # inserts earlier in the stream
+        pool = np.concatenate([pk, fk])
+        pick = (rng.random(nops) * (m0 + before)).astype(np.int64)
+        keys[~ins] = pool[pick[~ins]]
+        off = np.arange(0, nops + 1, args.txn_ops, dtype=np.int32)
+        dk, dv = as_device_keys(keys), as_device_keys(vals)
+        dkind = torch.from_numpy(kind).cuda()
+        doff = torch.from_numpy(off).cuda()
+        before_stats = t.stats()
+        sec = _timed(lambda: out.setdefault(name + "_res", t.transact(dkind, dk, dv, doff)))
+        r = out.pop(name + "_res")
+        st = r["status"].cpu().numpy()
+        rounds = r["round"].cpu().numpy()
+        after = t.stats()
+        ntx = off.size - 1
+        aborted = int((st[off[:-1]] == 3).sum())
+        out[name] = {"transactions": ntx, "ops": nops, "transactions_per_s": ntx / sec,
+                     "ops_per_s": nops / sec, "seconds": sec,
+                     "aborted_transactions": aborted,
+                     "mean_commit_round": float(rounds.mean()),
+                     "transactions_committed_after_losing_a_round": int((rounds > 0).sum()),
+                     "rounds": after["rounds"] - before_stats["rounds"],
+                     "load_after": after["stored"] / (n * B),
+                     "failed_inserts": after["inserts_failed"] - before_stats["inserts_failed"]}
+        total_ops += nops
+        total_s += sec
+        print(f"# txn {name}: {out[name]}", file=sys.stderr, flush=True)
+        t.close()
+    print(json.dumps({
+        "metric": "transactional batches: transactions/s, ops/s, rounds lost and aborts",
+        "value": total_ops / total_s, "unit": "ops/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": total_s * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic (splitmix64 keys, seeded)",
+        "config": {"workload": f"2^20 bins x 8 slots, random kicking with load balancing, "
+                               f"prefilled to 0.5, transactions of {args.txn_ops} ops to 0.9 "
+                               "load, mixes 1:0:1:1 and 2:1:2:2 (insert:delete:overwrite:read), "
+                               "sub-batches of 2^14 transactions"},
+        "by_mix": out}), flush=True)
+
+
 def run_stash(args):
     """The stash (Sec. 2): a 2^22 x 4 table (two hash functions, 64-bit keys and
     values, sub-batches of 2^20) filled to 0.97 by random kicking with chains
@@ -731,6 +807,9 @@ def main():
         return
     if args.workload == "stash":
         run_stash(args)
+        return
+    if args.workload == "txn":
+        run_txn(args)
         return
     if args.workload in ("ceilings", "small"):
         import torch

@@ -245,6 +245,37 @@ ck_status ck_upsert(ck_table* t, const uint64_t* d_keys, const void* d_vals, uin
                     uint8_t* d_status, uint32_t* d_views, uint32_t* d_kicks,
                     uint32_t* d_retries, void* stream);
 
+/* Transactional batch (Sec. 8): n_txn transactions, transaction t being the
+   operations [d_txn_off[t], d_txn_off[t + 1]) of d_kind / d_keys / d_vals
+   (d_txn_off holds n_txn + 1 increasing indices; kinds CK_TXN_*; values are
+   read for inserts and overwrites).  Each transaction is applied atomically:
+   its operations run in order, each seeing the earlier ones' writes (an
+   insert runs the table's kick-out walk, chain included), and the table ends
+   as if the committed transactions had run one at a time (Sec. 8's
+   transactional correctness).  Transactions run in sub-batches in rounds:
+   every pending transaction plans against the round's snapshot and claims
+   every bin it reads or writes (its read and write sets, the claim flags of
+   Sec. 8.2; the smallest transaction index wins a bin); one that owns all its
+   bins commits, the others plan again next round.  A transaction whose plan
+   would touch more than CK_TXN_MAX_BINS bins, or that loses max_rounds rounds
+   (when set), aborts.  Per op, d_status: lookups, deletes and overwrites
+   CK_OP_OK (found) or CK_OP_NOT_FOUND; inserts CK_OP_OK or CK_OP_FAIL_CHAIN;
+   every op of an aborted transaction CK_OP_ABORTED; CK_OP_BAD_KEY for the
+   reserved key.  d_vals_out[j]: a lookup's value (0 otherwise).
+   d_txn_round[t]: the round (within its sub-batch, from 0) in which t
+   committed or aborted.  Inserted keys must be absent and inserted once.
+   Tables: CK_RANDOM_WALK or CK_QUEUE, d == 2, slots_per_bin 2, 4 or 8, no
+   ghosts, no stash, uniform hashes; else CK_EUNSUPPORTED.  The library
+   allocates the transactions' scratch (per lane of a sub-batch of at most
+   2^14 transactions: CK_TXN_MAX_BINS bins and an undo log of max_chain + 2
+   records) on the first call.  Synchronises `stream` once per round. */
+enum { CK_TXN_LOOKUP = 0, CK_TXN_INSERT = 1, CK_TXN_DELETE = 2, CK_TXN_OVERWRITE = 3 };
+#define CK_TXN_MAX_BINS 512u
+ck_status ck_transact(ck_table* t, const uint8_t* d_kind, const uint64_t* d_keys,
+                      const uint64_t* d_vals, const uint32_t* d_txn_off, uint32_t n_txn,
+                      uint8_t* d_status, uint64_t* d_vals_out, uint32_t* d_txn_round,
+                      void* stream);
+
 /* Copy the counters to host memory (synchronises `stream`).  The counters are
    the paper's cost measures: bins viewed per insertion by density (Sec. 3),
    kick-out chain lengths (Sec. 5), failures, and the rounds lost to claims

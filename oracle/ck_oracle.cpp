@@ -106,7 +106,7 @@ struct Params {
   // transactions: a plan that reads or writes more distinct bins than this
   // aborts (its claims and writes would not fit a bounded per-transaction
   // record)
-  uint32_t txn_bins = 256;
+  uint32_t txn_bins = 512;
 };
 
 struct Stats {

@@ -224,7 +224,7 @@ class OracleTable:
 
     def set_txn_bins(self, bins):
         """Bound on the distinct bins a transaction's plan may touch (default
-        256); a larger plan aborts."""
+        512, as the GPU library); a larger plan aborts."""
         if lib().ck_oracle_set_txn_bins(self._t, int(bins)) != 0:
             raise ValueError("bad bound")
 

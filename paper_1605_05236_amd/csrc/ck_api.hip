@@ -115,6 +115,13 @@ struct ck_table {
   // host-side counters
   uint64_t rounds = 0, lookups = 0;
   Timer timer;
+  // transactional batches: per-lane scratch and lists, allocated on first use
+  char* txn_scratch = nullptr;
+  uint32_t txn_cap = 0;
+  uint32_t* txn_list[2] = {nullptr, nullptr};
+  uint32_t* txn_nob = nullptr;
+  uint32_t* txn_lost = nullptr;
+  uint32_t* txn_cnt = nullptr;
 };
 
 // The round scratch one call runs on: the table's own arrays (allocated at
@@ -224,6 +231,12 @@ void free_scratch(ck_table* t) {
   (void)hipFree(t->g.stash);
   (void)hipFree(t->g.stash_owner);
   (void)hipFree(t->g.stash_cnt);
+  (void)hipFree(t->txn_scratch);
+  (void)hipFree(t->txn_list[0]);
+  (void)hipFree(t->txn_list[1]);
+  (void)hipFree(t->txn_nob);
+  (void)hipFree(t->txn_lost);
+  (void)hipFree(t->txn_cnt);
 }
 
 ck_status alloc_scratch(ck_table* t) {
@@ -786,6 +799,97 @@ ck_status ck_delete_noalloc(ck_table* t, const uint64_t* keys, uint64_t n, uint8
                    nullptr, false, false, &x);
   t->timer.on = timing;
   return st;
+}
+
+// Transactional batches (Sec. 8): per sub-batch of transactions, rounds of
+// a planning launch and a commit launch, each one lane per pending
+// transaction, until none is pending; the host reads the pending count
+// after every round.
+ck_status ck_transact(ck_table* t, const uint8_t* kind, const uint64_t* keys,
+                      const uint64_t* vals, const uint32_t* off, uint32_t n_txn, uint8_t* status,
+                      uint64_t* vals_out, uint32_t* txn_round, void* stream) {
+  if (!t) return CK_EINVAL;
+  if (n_txn == 0) return CK_OK;
+  if (!kind || !keys || !vals || !off || !status || !vals_out || !txn_round) return CK_EINVAL;
+  if ((t->scheme != CK_RANDOM_WALK && t->scheme != CK_QUEUE) || t->H != 2 ||
+      (t->B != 2 && t->B != 4 && t->B != 8) || t->opt.ghost || t->g.stash_n || t->g.hash_bias ||
+      t->g.stash_tables != 1)
+    return CK_EUNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t ends[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(&ends[0], off, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&ends[1], off + n_txn, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (ends[1] < ends[0]) return CK_EINVAL;
+  const uint32_t cap = std::min<uint32_t>(t->opt.batch_ops, 1u << 14);
+  const size_t lane = txn_lane_bytes(t->g);
+  if (t->txn_cap < cap) {
+    (void)hipFree(t->txn_scratch);
+    for (auto& l : t->txn_list) (void)hipFree(l);
+    (void)hipFree(t->txn_nob);
+    (void)hipFree(t->txn_lost);
+    (void)hipFree(t->txn_cnt);
+    t->txn_cap = 0;
+    HIP_TRY(dalloc(&t->txn_scratch, (size_t)cap * lane));
+    for (auto& l : t->txn_list) HIP_TRY(dalloc(&l, cap));
+    HIP_TRY(dalloc(&t->txn_nob, cap));
+    HIP_TRY(dalloc(&t->txn_lost, cap));
+    HIP_TRY(dalloc(&t->txn_cnt, 1));
+    t->txn_cap = cap;
+  }
+  const uint64_t op_base = t->insert_count;
+  for (uint32_t t0 = 0; t0 < n_txn; t0 += cap) {
+    const uint32_t m = std::min<uint32_t>(cap, n_txn - t0);
+    HIP_TRY(launch_fill_u32(t->txn_lost, 0u, m, s));
+    TxnRound r{};
+    r.kind = kind;
+    r.keys = keys;
+    r.vals = vals;
+    r.off = off;
+    r.t0 = t0;
+    r.pend = nullptr;  // round 0: every transaction of the sub-batch, in order
+    r.npend = m;
+    r.next_cnt = t->txn_cnt;
+    r.status = status;
+    r.vout = vals_out;
+    r.txn_round = txn_round;
+    r.lost = t->txn_lost;
+    r.nob = t->txn_nob;
+    r.max_rounds = t->opt.max_rounds;
+    r.op_base = op_base;
+    r.scratch = t->txn_scratch;
+    r.lane_bytes = (uint32_t)lane;
+    r.undo_cap = txn_undo_cap(t->g);
+    r.stats = t->dstats;
+    uint32_t round = 0;
+    int cur = 0;
+    while (r.npend) {
+      // the smallest pending transaction commits or aborts every round
+      if (round > m + 64) return CK_EDEVICE;
+      ++t->epoch;
+      if (t->epoch == 0) {  // claim tags wrapped: reset every claim word
+        HIP_TRY(hipMemsetAsync(t->g.owner, 0xFF, (size_t)t->bins * 8, s));
+        t->epoch = 1;
+      }
+      r.tag = (unsigned long long)(~t->epoch) << 32;
+      r.round = round;
+      r.next = t->txn_list[cur];
+      HIP_TRY(launch_fill_u32(t->txn_cnt, 0u, 1, s));
+      HIP_TRY(launch_txn(t->g, r, false, s));
+      HIP_TRY(launch_txn(t->g, r, true, s));
+      uint32_t n_next = 0;
+      HIP_TRY(hipMemcpyAsync(&n_next, t->txn_cnt, 4, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      if (n_next > r.npend) return CK_EDEVICE;
+      r.pend = t->txn_list[cur];
+      r.npend = n_next;
+      cur ^= 1;
+      ++round;
+    }
+    t->rounds += round;
+  }
+  t->insert_count += ends[1] - ends[0];
+  return CK_OK;
 }
 
 ck_status ck_overwrite(ck_table* t, const uint64_t* keys, const void* vals, uint64_t n,

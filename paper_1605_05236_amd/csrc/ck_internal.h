@@ -214,6 +214,34 @@ struct Round {
   HostSum* hsum;             // pinned host memory of the sub-batch's counter set
 };
 
+// One round of a transactional batch (Sec. 8): the pending transactions of a
+// sub-batch, one lane each.
+constexpr uint32_t kTxnBins = CK_TXN_MAX_BINS;  // bins one transaction's plan may touch
+enum : uint32_t { TXN_LOOKUP = CK_TXN_LOOKUP, TXN_INSERT = CK_TXN_INSERT,
+                  TXN_DELETE = CK_TXN_DELETE, TXN_OVERWRITE = CK_TXN_OVERWRITE };
+struct TxnRound {
+  const uint8_t* kind;       // per op
+  const uint64_t* keys;
+  const uint64_t* vals;
+  const uint32_t* off;       // transaction t: ops [off[t], off[t + 1])
+  uint32_t t0;               // first transaction of the sub-batch
+  const uint32_t* pend;      // pending transactions (within the sub-batch); null: 0..npend-1
+  uint32_t npend;
+  uint32_t* next;            // the transactions that go again, and their count
+  uint32_t* next_cnt;
+  uint8_t* status;           // per op
+  uint64_t* vout;            // per op: a lookup's value
+  uint32_t* txn_round;       // per transaction: the round it committed or aborted in
+  uint32_t* lost;            // per transaction of the sub-batch: rounds lost
+  uint32_t* nob;             // per pending position: overlay entries, kNone: too many bins
+  uint32_t round, max_rounds;
+  uint64_t op_base;          // the insert-op index of op 0 (random walk draws)
+  unsigned long long tag;    // (~epoch) << 32
+  char* scratch;             // per pending position: lane_bytes of overlay and undo log
+  uint32_t lane_bytes, undo_cap;
+  DevStats* stats;
+};
+
 // ---- launchers (ck_kernels.hip) ----
 hipError_t launch_init(const Geo& g, hipStream_t s);
 hipError_t launch_lookup(const Geo& g, const uint64_t* keys, uint64_t n, void* vals_out,
@@ -233,6 +261,9 @@ size_t evict_lds_bytes(const Geo& g);
 int evict_resident_per_cu(const Geo& g);
 size_t evict_wg_scratch_bytes(const Geo& g);
 hipError_t launch_export_meta(const Geo& g, hipStream_t s);
+size_t txn_lane_bytes(const Geo& g);
+uint32_t txn_undo_cap(const Geo& g);
+hipError_t launch_txn(const Geo& g, const TxnRound& r, bool commit, hipStream_t s);
 // p[0..count) = value (a small fill kernel; no memset node)
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s);
 

@@ -2643,4 +2643,307 @@ hipError_t launch_batch_stats(const Round& r, uint64_t m, uint64_t slots, uint32
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// transactional batches (Sec. 8): one lane per transaction
+// ---------------------------------------------------------------------------
+// A lane plans its transaction's operations in order against the round-start
+// table through a private overlay in scratch: every bin the plan has touched
+// (read or written), each a copy of the bin's slots and metadata word, so
+// that later operations see the earlier ones' writes.  The overlay is the
+// transaction's read set and write set at once: every bin in it is claimed
+// with the transaction's index (the smallest index wins a bin), and a
+// transaction that owns all of them commits by writing back the bins it
+// changed; the others plan again next round.  An insert runs the table's
+// walk (random kicking, or queue-kicking with its hit counters) inside the
+// overlay, kick-out chain included; a failed insert is undone from a log of
+// the slots and words it overwrote (the bins it read stay in the overlay,
+// and so in the read set).  A plan that would touch more than kTxnBins bins
+// aborts.
+
+template <int B>
+struct TxnLane {
+  const Geo* g;
+  uint32_t* bins;    // [kTxnBins]
+  uint32_t* meta;    // [kTxnBins]
+  uint32_t* dirty;   // [kTxnBins]: 1 once written
+  ulonglong2* slots; // [kTxnBins * B]
+  uint32_t* uent;    // undo log of the current insert: entry, slot,
+  uint32_t* uslot;   // previous slot contents and word
+  ulonglong2* uold;
+  uint32_t* umeta;
+  uint32_t n = 0, nu = 0;
+  bool big = false;
+
+  __device__ void init(const Geo& geo, char* base, uint32_t undo_cap) {
+    g = &geo;
+    bins = (uint32_t*)base;
+    meta = bins + kTxnBins;
+    dirty = meta + kTxnBins;
+    slots = (ulonglong2*)(dirty + kTxnBins);
+    uent = (uint32_t*)(slots + (size_t)kTxnBins * B);
+    uslot = uent + undo_cap;
+    umeta = uslot + undo_cap;
+    uold = (ulonglong2*)(umeta + undo_cap);  // undo_cap is a multiple of 4: 16-byte aligned
+  }
+  // Overlay entry of bin b, copied from the table on first touch; kNone
+  // (and big) when the overlay is full.
+  __device__ uint32_t touch(uint32_t b) {
+    for (uint32_t e = 0; e < n; ++e)
+      if (bins[e] == b) return e;
+    if (n == kTxnBins) {
+      big = true;
+      return kNone;
+    }
+    bins[n] = b;
+    meta[n] = g->meta[b];
+    dirty[n] = 0;
+#pragma unroll
+    for (int s = 0; s < B; ++s) slots[(size_t)n * B + s] = g->slots[(uint64_t)b * B + s];
+    return n++;
+  }
+  __device__ int first_empty(uint32_t e) const {
+#pragma unroll
+    for (int s = 0; s < B; ++s)
+      if (slots[(size_t)e * B + s].x == kEmpty) return s;
+    return -1;
+  }
+  __device__ int occupancy(uint32_t e) const {
+    int o = 0;
+#pragma unroll
+    for (int s = 0; s < B; ++s) o += slots[(size_t)e * B + s].x != kEmpty;
+    return o;
+  }
+  // slot s of entry e gets rec (an insertion: queue-kicking counts it)
+  __device__ void put(uint32_t e, int s, ulonglong2 rec, bool log) {
+    ulonglong2& sl = slots[(size_t)e * B + s];
+    if (log) {
+      uent[nu] = e;
+      uslot[nu] = (uint32_t)s;
+      uold[nu] = sl;
+      umeta[nu] = meta[e];
+      ++nu;
+    }
+    sl = rec;
+    dirty[e] = 1;
+    if (g->scheme == CK_QUEUE) meta[e] += 1u << 24;
+  }
+  __device__ void undo() {
+    while (nu) {
+      --nu;
+      slots[(size_t)uent[nu] * B + uslot[nu]] = uold[nu];
+      meta[uent[nu]] = umeta[nu];
+    }
+  }
+  // the entry and slot holding key x among its bins (h in hash order)
+  __device__ bool find(uint64_t x, const uint32_t* h, uint32_t& e, int& s) {
+    for (int i = 0; i < 2; ++i) {
+      e = touch(h[i]);
+      if (big) return false;
+#pragma unroll
+      for (int q = 0; q < B; ++q)
+        if (slots[(size_t)e * B + q].x == x) {
+          s = q;
+          return true;
+        }
+    }
+    return false;
+  }
+  // Insert x (absent) by the table's walk; PL_OK or PL_FAIL (a failed
+  // insert leaves the overlay's contents as they were).
+  __device__ uint32_t insert(ulonglong2 x, uint64_t op, const uint32_t* h) {
+    nu = 0;
+    uint32_t draws = 0, kicks = 0;
+    const bool queue = g->scheme == CK_QUEUE;
+    uint32_t e0 = kNone, e1 = kNone;
+    if (g->balance || queue) {  // load balancing (Sec. 2; always for queue-kicking)
+      e0 = touch(h[0]);
+      if (big) return PL_FAIL;
+      e1 = touch(h[1]);
+      if (big) return PL_FAIL;
+      const int o0 = occupancy(e0), o1 = occupancy(e1);
+      if (o0 < B || o1 < B) {
+        const uint32_t t = o0 <= o1 ? e0 : e1;
+        put(t, first_empty(t), x, false);
+        return PL_OK;
+      }
+    } else {  // first fit (Sec. 1)
+      e0 = touch(h[0]);
+      if (big) return PL_FAIL;
+      int fe = first_empty(e0);
+      if (fe >= 0) {
+        put(e0, fe, x, false);
+        return PL_OK;
+      }
+      e1 = touch(h[1]);
+      if (big) return PL_FAIL;
+      fe = first_empty(e1);
+      if (fe >= 0) {
+        put(e1, fe, x, false);
+        return PL_OK;
+      }
+    }
+    // kick-out walk: hit balancing picks the bin (queue), else a random one
+    uint32_t cur;
+    if (queue) cur = (meta[e0] >> 24) <= (meta[e1] >> 24) ? e0 : e1;
+    else cur = uniform_choice(*g, op, draws, 2) == 0 ? e0 : e1;
+    ulonglong2 carry = x;
+    for (;;) {
+      if (kicks == g->max_chain) {
+        undo();
+        return PL_FAIL;
+      }
+      const int s = queue ? (int)((meta[cur] >> 24) % B) : (int)uniform_choice(*g, op, draws, B);
+      const ulonglong2 victim = slots[(size_t)cur * B + s];
+      put(cur, s, carry, true);
+      ++kicks;
+      carry = victim;
+      uint32_t hv[2];
+      hash_key<2, false>(*g, Tab{0u, g->n}, carry.x, hv);
+      const uint32_t nb = hv[0] == bins[cur] ? hv[1] : hv[0];
+      cur = touch(nb);
+      if (big) {
+        undo();
+        return PL_FAIL;
+      }
+      const int fe = first_empty(cur);
+      if (fe >= 0) {
+        put(cur, fe, carry, true);
+        return PL_OK;
+      }
+    }
+  }
+};
+
+template <int B>
+__global__ __launch_bounds__(256) void k_plan_txn(Geo g, TxnRound r) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= r.npend) return;
+  const uint32_t i = r.pend ? r.pend[p] : p;  // the transaction, within the sub-batch
+  const uint32_t t = r.t0 + i;
+  TxnLane<B> L;
+  L.init(g, r.scratch + (size_t)p * r.lane_bytes, r.undo_cap);
+  const uint32_t o0 = r.off[t], o1 = r.off[t + 1];
+  for (uint32_t j = o0; j < o1 && !L.big; ++j) {
+    const uint64_t x = r.keys[j];
+    uint8_t st = CK_OP_NOT_FOUND;
+    uint64_t v = 0;
+    if (x == kEmpty) {
+      st = CK_OP_BAD_KEY;
+    } else {
+      uint32_t h[2];
+      hash_key<2, false>(g, Tab{0u, g.n}, x, h);
+      const uint32_t kd = r.kind[j];
+      uint32_t e = 0;
+      int s = 0;
+      if (kd == TXN_INSERT) {
+        st = L.insert(make_ulonglong2(x, r.vals[j]), r.op_base + j, h) == PL_OK ? CK_OP_OK
+                                                                             : CK_OP_FAIL_CHAIN;
+      } else if (L.find(x, h, e, s)) {
+        st = CK_OP_OK;
+        ulonglong2& sl = L.slots[(size_t)e * B + s];
+        if (kd == TXN_LOOKUP) {
+          v = sl.y;
+        } else if (kd == TXN_DELETE) {
+          sl = make_ulonglong2(kEmpty, 0ull);
+          L.dirty[e] = 1;
+        } else {  // overwrite
+          sl.y = r.vals[j];
+          L.dirty[e] = 1;
+        }
+      }
+    }
+    r.status[j] = st;
+    r.vout[j] = v;
+  }
+  if (L.big) {  // too many bins: the transaction aborts, claiming nothing
+    r.nob[p] = kNone;
+    return;
+  }
+  r.nob[p] = L.n;
+  const unsigned long long me = r.tag | (unsigned long long)i;
+  for (uint32_t e = 0; e < L.n; ++e) atomicMin(&g.owner[L.bins[e]], me);
+}
+
+template <int B>
+__global__ __launch_bounds__(256) void k_commit_txn(Geo g, TxnRound r) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= r.npend) return;
+  const uint32_t i = r.pend ? r.pend[p] : p;
+  const uint32_t t = r.t0 + i;
+  const uint32_t o0 = r.off[t], o1 = r.off[t + 1];
+  const uint32_t n = r.nob[p];
+  TxnLane<B> L;
+  L.init(g, r.scratch + (size_t)p * r.lane_bytes, r.undo_cap);
+  bool win = n != kNone;
+  const unsigned long long me = r.tag | (unsigned long long)i;
+  for (uint32_t e = 0; win && e < n; ++e) win = g.owner[L.bins[e]] == me;
+  bool abort = n == kNone;
+  if (!win && !abort) {
+    const uint32_t lost = ++r.lost[i];
+    abort = r.max_rounds && lost >= r.max_rounds;
+  }
+  if (win) {
+    for (uint32_t e = 0; e < n; ++e) {
+      if (!L.dirty[e]) continue;
+      const uint32_t b = L.bins[e];
+#pragma unroll
+      for (int s = 0; s < B; ++s) g.slots[(uint64_t)b * B + s] = L.slots[(size_t)e * B + s];
+      g.meta[b] = L.meta[e];
+    }
+    unsigned long long ok = 0, fail = 0, del = 0;
+    for (uint32_t j = o0; j < o1; ++j) {
+      const uint8_t st = r.status[j];
+      const uint32_t kd = r.kind[j];
+      ok += kd == TXN_INSERT && st == CK_OP_OK;
+      fail += kd == TXN_INSERT && st == CK_OP_FAIL_CHAIN;
+      del += kd == TXN_DELETE && st == CK_OP_OK;
+    }
+    DevStatLine& sl = r.stats->s[blockIdx.x % kStatStripes];
+    if (ok) atomicAdd(&sl.v[S_INS_OK], ok);
+    if (fail) atomicAdd(&sl.v[S_INS_FAIL], fail);
+    if (del) atomicAdd(&sl.v[S_DEL_FOUND], del);
+    if (ok != del) atomicAdd(&sl.v[S_STORED], ok - del);
+    r.txn_round[t] = r.round;
+  } else if (abort) {
+    for (uint32_t j = o0; j < o1; ++j) {
+      r.status[j] = CK_OP_ABORTED;
+      r.vout[j] = 0;
+    }
+    r.txn_round[t] = r.round;
+  } else {
+    const uint32_t q = atomicAdd(r.next_cnt, 1u);
+    r.next[q] = i;
+  }
+}
+
+// Undo-log records per lane: every kick of an insert's walk and its final
+// placement, rounded up to a multiple of 4.
+uint32_t txn_undo_cap(const Geo& g) { return (g.max_chain + 2 + 3) & ~3u; }
+
+// Scratch bytes of one lane: bins, words and dirty flags (4 bytes each per
+// entry), the entries' slots, and the undo log (entry, slot, word, old slot).
+size_t txn_lane_bytes(const Geo& g) {
+  const size_t uc = txn_undo_cap(g);
+  const size_t b = (size_t)kTxnBins * 12 + (size_t)kTxnBins * g.B * 16 + uc * 12 + uc * 16;
+  return (b + 255) & ~(size_t)255;
+}
+
+template <int B>
+static void txn_go(const Geo& g, const TxnRound& r, bool commit, hipStream_t s) {
+  const uint32_t grid = (r.npend + 255) / 256;
+  if (commit) hipLaunchKernelGGL(k_commit_txn<B>, dim3(grid), dim3(256), 0, s, g, r);
+  else hipLaunchKernelGGL(k_plan_txn<B>, dim3(grid), dim3(256), 0, s, g, r);
+}
+
+hipError_t launch_txn(const Geo& g, const TxnRound& r, bool commit, hipStream_t s) {
+  if (r.npend == 0) return hipSuccess;
+  switch (g.B) {
+    case 2: txn_go<2>(g, r, commit, s); break;
+    case 4: txn_go<4>(g, r, commit, s); break;
+    case 8: txn_go<8>(g, r, commit, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace ck

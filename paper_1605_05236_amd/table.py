@@ -72,7 +72,7 @@ _lib = None
 
 EXPORTED = ["ck_default_options", "ck_storage_bytes", "ck_create", "ck_clear", "ck_insert", "ck_insert_ex",
             "ck_lookup", "ck_lookup_lpp", "ck_delete", "ck_delete_noalloc", "ck_overwrite",
-            "ck_upsert",
+            "ck_upsert", "ck_transact",
             "ck_stats_get", "ck_stats_reset", "ck_export_stash", "ck_import_stash",
             "ck_group_export_stash",
             "ck_export", "ck_import", "ck_hash", "ck_insert_count", "ck_destroy", "ck_strerror",
@@ -105,6 +105,7 @@ def load_library(path: str = LIB_PATH):
     L.ck_lookup_lpp.argtypes = [vp, vp, u64, vp, vp, u32, vp]
     L.ck_delete.argtypes = [vp, vp, u64, vp, vp]
     L.ck_delete_noalloc.argtypes = [vp, vp, u64, vp, vp]
+    L.ck_transact.argtypes = [vp, vp, vp, vp, vp, u32, vp, vp, vp, vp]
     L.ck_overwrite.argtypes = [vp, vp, vp, u64, vp, vp]
     L.ck_upsert.argtypes = [vp, vp, vp, u64, vp, vp, vp, vp, vp]
     L.ck_export_stash.argtypes = [vp, vp, vp, vp]
@@ -139,7 +140,7 @@ def load_library(path: str = LIB_PATH):
     L.ck_strerror.argtypes = [i32]
     L.ck_strerror.restype = ctypes.c_char_p
     for f in ("ck_storage_bytes", "ck_create", "ck_clear", "ck_insert", "ck_insert_ex", "ck_lookup",
-              "ck_lookup_lpp", "ck_delete", "ck_delete_noalloc", "ck_overwrite", "ck_upsert", "ck_stats_get",
+              "ck_lookup_lpp", "ck_delete", "ck_delete_noalloc", "ck_transact", "ck_overwrite", "ck_upsert", "ck_stats_get",
               "ck_stats_reset", "ck_export", "ck_export_stash", "ck_import_stash",
               "ck_group_export_stash",
               "ck_import", "ck_hash", "ck_destroy", "ck_timing_enable", "ck_timing_get",
@@ -272,6 +273,21 @@ class CuckooTable:
         _check(self._L.ck_delete_noalloc(self._h, _ptr(keys), keys.numel(), _ptr(found),
                                          _stream(stream)))
         return found
+
+    def transact(self, kinds, keys, vals, txn_off, stream=None):
+        """Transactional batch (ck_transact, Sec. 8): uint8 kinds (0 lookup,
+        1 insert, 2 delete, 3 overwrite), int64 keys and values, int32
+        transaction offsets (n_txn + 1) on the device.  Returns per-op status
+        and value, and per-transaction commit round."""
+        import torch
+        n = keys.numel()
+        nt = txn_off.numel() - 1
+        status = torch.empty(n, dtype=torch.uint8, device=self.device)
+        vout = torch.empty(n, dtype=torch.int64, device=self.device)
+        rnd = torch.empty(max(nt, 1), dtype=torch.int32, device=self.device)
+        _check(self._L.ck_transact(self._h, _ptr(kinds), _ptr(keys), _ptr(vals), _ptr(txn_off),
+                                   nt, _ptr(status), _ptr(vout), _ptr(rnd), _stream(stream)))
+        return {"status": status, "value": vout, "round": rnd[:nt]}
 
     def overwrite(self, keys, vals, stream=None):
         """New values for stored keys (absent keys are reported, not inserted)."""
