@@ -263,6 +263,23 @@ def run_small(args):
                     "times are medians of three repeats after one warm-up"}
 
 
+def _profiler_ns():
+    """The profiler's clock in ns when the program runs under rocprofv3 (its
+    SDK is then loaded in this process), else None.  The fill workload prints
+    its timed region in this clock, so a kernel trace of the same command can
+    be cut to that region."""
+    import ctypes
+    for name in ("librocprofiler-sdk.so.1", "librocprofiler-sdk.so"):
+        try:
+            lib = ctypes.CDLL(name, mode=os.RTLD_NOLOAD | os.RTLD_LAZY)
+        except OSError:
+            continue
+        ts = ctypes.c_uint64(0)
+        if lib.rocprofiler_get_timestamp(ctypes.byref(ts)) == 0:
+            return int(ts.value)
+    return None
+
+
 def _timed(fn):
     import torch
     s = torch.cuda.current_stream()
@@ -941,6 +958,7 @@ def main():
             dominant = max(warm_ms, key=warm_ms.get)
         print(f"# warmup {w} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    p_start = _profiler_ns()
     t_start = time.perf_counter()
     results = []
     for k in range(args.steps):
@@ -951,6 +969,9 @@ def main():
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    p_end = _profiler_ns()
+    if p_start is not None and p_end is not None:
+        print(f"# profiler window ns: {p_start} {p_end}", file=sys.stderr, flush=True)
 
     # correctness guard on the timed output: every probe answered as generated,
     # and every stored key's value is the one inserted

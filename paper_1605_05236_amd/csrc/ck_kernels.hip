@@ -1197,17 +1197,25 @@ constexpr uint32_t kRootParent = 0xFFFFFFFFu;
 constexpr uint32_t kSearchLdsRuns = 128;
 constexpr int kSearchW = 16;  // lanes per search
 constexpr int kSearchLoads = 2;  // bin slots per lane in one group load
+// BFS over bins of 8 slots or more loads twice as deep: FIFO order never
+// abandons a fetched group (only the terminal bin ends one early), so deeper
+// loads hide more latency, while the spawn-count orders would discard them
+// whenever a new run goes to a lower bucket, and would spill registers.
+constexpr int kSearchLoadsFifo8 = 4;
 
 size_t search_runs(const Geo& g) { return (size_t)g.max_search + 8 + g.H; }
 // search orders: BFS (FIFO), sorted search (spawn count), their hybrid
 // (depth, then spawn count)
 constexpr int kOrderFifo = 0, kOrderCount = 1, kOrderDepthCount = 2;
+// Candidate words (a listed record's other bins) of one search kept in LDS;
+// the rest (long searches only) go to workgroup scratch.
+constexpr uint32_t kCandLds = 128;
 // LDS words of one search group: run bins, parents and links (kSearchLdsRuns
 // each), then bucket heads and tails, and the hybrid's next-depth heads and
-// tails (16 each).  The kernel's group stride and the launch's size both
-// come from here.
+// tails (16 each), then the first kCandLds candidate words.  The kernel's
+// group stride and the launch's size both come from here.
 __host__ __device__ constexpr uint32_t search_group_lds_words() {
-  return 3 * kSearchLdsRuns + 4 * 16;
+  return 3 * kSearchLdsRuns + 4 * 16 + kCandLds;
 }
 static size_t search_group_scratch_bytes(const Geo& g) {
   const size_t RC = search_runs(g);
@@ -1224,7 +1232,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   constexpr int W = kSearchW;
   constexpr int P = 64 / W;       // searches per wavefront
   constexpr uint32_t C = H - 1;   // candidates per record
-  constexpr int KW = kSearchLoads;          // bin slots each lane loads per group load
+  // bin slots each lane loads per group load
+  constexpr int KW = (B >= 8 && O == kOrderFifo) ? kSearchLoadsFifo8 : kSearchLoads;
   constexpr uint32_t G = KW * W / B;        // bins per group load
   constexpr int UW = (int)((G + W - 1) / W);  // group units per lane
   constexpr uint32_t RB = H * B;  // root records
@@ -1248,7 +1257,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   uint32_t* btail = bhead + 16;   // last run of each bucket
   uint32_t* nhead = btail + 16;   // the hybrid: the next depth's buckets
   uint32_t* ntail = nhead + 16;
-  static_assert(3 * RL + 4 * 16 <= search_group_lds_words(), "search group LDS layout");
+  uint32_t* candL = ntail + 16;   // candidate words 0 .. kCandLds - 1
+  static_assert(3 * RL + 4 * 16 + kCandLds <= search_group_lds_words(),
+                "search group LDS layout");
   // the group's scratch: one workgroup-uniform base plus a per-group word
   // offset, so the arrays cost one register, not a pointer each
   uint32_t* const wsb = (uint32_t*)((char*)r.wg_scratch + (size_t)blockIdx.x * r.wg_scratch_bytes);
@@ -1258,7 +1269,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   const uint32_t o_rbin = o_path + RC;  // runs >= RL
   const uint32_t o_rpar = o_rbin + RC;
   const uint32_t o_rnext = o_rpar + RC;
-  auto cand = [&](uint32_t j) -> uint32_t& { return wsb[go + j]; };
+  auto cand = [&](uint32_t j) -> uint32_t& { return j < kCandLds ? candL[j] : wsb[go + j]; };
   auto spl = [&](uint32_t j) -> uint32_t& { return wsb[go + o_spl + j]; };
   auto path = [&](uint32_t j) -> uint32_t& { return wsb[go + o_path + j]; };
   auto rbinG = [&](uint32_t j) -> uint32_t& { return wsb[go + o_rbin + j]; };

@@ -15,6 +15,13 @@
 * --group NAME=REGEX: one more line per group of kernels taken together (for
   example the planners that share one role): launches, average duration, and
   HBM bytes per launch averaged over the group's launches.
+* --trace-log / --fetch-log / --write-log: the stderr of each profiled run.
+  When it holds the benchmark's `# profiler window ns: A B` line (its timed
+  region, in the profiler's clock), that run's kernels are cut to the ones
+  that started and ended inside the window.  A counter database whose
+  dispatches carry no timestamps is cut to the dispatch ids of the trace's
+  window instead (the runs dispatch the same sequence: give every run
+  --pmc-calibration), and the kernel names at those ids are checked.
 """
 from __future__ import annotations
 
@@ -25,33 +32,68 @@ import sqlite3
 
 
 def _short(name: str) -> str:
+    name = name.replace("(anonymous namespace)::", "")
     return name.split("(")[0].replace("void ", "").strip()
 
 
-def kernel_times(db: str) -> dict:
-    """kernel -> [calls, total microseconds]."""
+def window(log):
+    """(start, end) ns of the benchmark's timed region from a run's log, or None."""
+    if not log:
+        return None
+    found = None
+    with open(log, errors="replace") as fh:
+        for line in fh:
+            m = re.search(r"# profiler window ns: (\d+) (\d+)", line)
+            if m:
+                found = (int(m.group(1)), int(m.group(2)))
+    if found is None:
+        raise SystemExit(f"{log}: no profiler window line")
+    return found
+
+
+def kernel_times(db: str, win=None):
+    """(kernel -> [calls, total microseconds], {dispatch id: kernel}) of the
+    dispatches inside `win` (all when None)."""
     out = collections.defaultdict(lambda: [0, 0.0])
+    ids = {}
     con = sqlite3.connect(db)
-    for name, s, e in con.execute("select name, start, end from kernels"):
+    for name, s, e, d in con.execute("select name, start, end, dispatch_id from kernels"):
+        if win is not None and not (s >= win[0] and e <= win[1]):
+            continue
         k = _short(name)
         out[k][0] += 1
         out[k][1] += (e - s) / 1e3
-    return dict(out)
+        ids[d] = k
+    return dict(out), ids
 
 
-def counter_totals(db: str, counter: str):
-    """(kernel -> [dispatches, KiB total], [(dispatch id, kernel, KiB)])."""
-    out = collections.defaultdict(lambda: [0, 0.0])
+def counter_totals(db: str, counter: str, win=None, trace_ids=None):
+    """(kernel -> [dispatches, KiB total], [(dispatch id, kernel, KiB)], how):
+    all rows, or those inside `win` by their own timestamps, or (when the
+    database holds none) those at the dispatch ids of the trace's window."""
     rows = []
     con = sqlite3.connect(db)
-    for name, v, d in con.execute(
-            "select kernel_name, value, dispatch_id from counters_collection "
+    for name, v, d, s, e in con.execute(
+            "select kernel_name, value, dispatch_id, start, end from counters_collection "
             "where counter_name = ? order by dispatch_id", (counter,)):
-        k = _short(name)
+        rows.append((d, _short(name), v, s, e))
+    how = "all dispatches"
+    keep = rows
+    if win is not None and any(s for _, _, _, s, _ in rows):
+        keep = [r for r in rows if r[3] >= win[0] and r[4] <= win[1]]
+        how = "own timed window"
+    elif trace_ids is not None:
+        keep = [r for r in rows if r[0] in trace_ids]
+        bad = sum(1 for r in keep if trace_ids[r[0]] != r[1])
+        if bad or len(keep) != len(trace_ids):
+            raise SystemExit(f"{db}: dispatch sequence differs from the trace's "
+                             f"({bad} names differ, {len(keep)} of {len(trace_ids)} ids found)")
+        how = "dispatch ids of the trace's window"
+    out = collections.defaultdict(lambda: [0, 0.0])
+    for d, k, v, _, _ in keep:
         out[k][0] += 1
         out[k][1] += v
-        rows.append((d, k, v))
-    return dict(out), rows
+    return dict(out), [(d, k, v) for d, k, v, _, _ in rows], how
 
 
 def calibration(write_rows, fetch_rows, kib: float):
@@ -75,15 +117,23 @@ def main():
     ap.add_argument("--calibration-kib", type=float, default=262144.0)
     ap.add_argument("--top", type=int, default=25)
     ap.add_argument("--group", action="append", default=[])
+    ap.add_argument("--trace-log")
+    ap.add_argument("--fetch-log")
+    ap.add_argument("--write-log")
     a = ap.parse_args()
-    t = kernel_times(a.trace)
+    tw = window(a.trace_log)
+    t, ids = kernel_times(a.trace, tw)
+    if tw is not None:
+        print(f"trace cut to the timed window: {sum(v[0] for v in t.values())} dispatches")
     f = w = None
     if a.fetch and a.write:
-        f, frows = counter_totals(a.fetch, "FETCH_SIZE")
-        w, wrows = counter_totals(a.write, "WRITE_SIZE")
+        tid = ids if tw is not None else None
+        f, frows, fhow = counter_totals(a.fetch, "FETCH_SIZE", window(a.fetch_log), tid)
+        w, wrows, whow = counter_totals(a.write, "WRITE_SIZE", window(a.write_log), tid)
         cf, cw = calibration(wrows, frows, a.calibration_kib)
         print(f"calibration: FETCH_SIZE x{cf:.3f}, WRITE_SIZE x{cw:.3f} "
               f"(plain copy of {a.calibration_kib / 1024:.0f} MiB)")
+        print(f"counter dispatches: FETCH_SIZE {fhow}, WRITE_SIZE {whow}")
     pat = re.compile(a.kernels)
     total = sum(v[1] for v in t.values())
     hdr = f"| kernel | calls | total ms | avg us | % time |"
