@@ -36,12 +36,12 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 # per launch in the default fill workload: FETCH_SIZE + WRITE_SIZE from two
 # rocprofv3 --pmc runs of this benchmark (--steps 1 --warmup 1
 # --pmc-calibration), each scaled by its reading for a plain 256 MiB device
-# copy.  It describes the library source it was taken on (kernels, launch
+# copy, over the launches of the timed step (the class the benchmark times).  It describes the library source it was taken on (kernels, launch
 # shapes, host loop); once that source changes the benchmark reports null
 # until the counters are taken again.
 MEASURED_EVICT_TRAFFIC = {
-    "sources_sha256": "83185d040ca3469929c6b156d250964e07866049d9923c3807dac9310f13dd76",
-    "bytes_per_launch": 36039455,
+    "sources_sha256": "d00b40e0e7543032ea8905508aa83c350343a4c92ee74709bde5f606e4691913",
+    "bytes_per_launch": 34966071,
     "profile": "profiles/evict_planners__fill95_2e24x8.md",
 }
 _SOURCES = ("ck_kernels.hip", "ck_api.hip", "ck_internal.h")
