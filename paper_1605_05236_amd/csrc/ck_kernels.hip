@@ -268,13 +268,24 @@ __device__ __forceinline__ void block_add2(unsigned long long a, unsigned long l
 // lookup: LPP lanes per query, B/LPP slots per lane
 // ---------------------------------------------------------------------------
 // EXT: the instance for tables with a stash or biased hashes.
+// A lane group takes QL queries per pass (two where a lane holds at most two
+// slots of a bin): their keys, hashes and probes of the same hash function
+// are issued together, so twice the line loads are in flight per wavefront
+// for the same bytes (the second probe is still issued only for a query the
+// first did not answer).
+template <int B, int LPP>
+__host__ __device__ constexpr int lookup_queries_per_group() {
+  return B / LPP <= 2 ? 2 : 1;
+}
 template <int B, int LPP, int H, bool EXT>
 __global__ __launch_bounds__(256) void k_lookup(Geo g, const uint64_t* __restrict__ keys,
                                                 uint64_t n, void* __restrict__ out,
                                                 uint8_t* __restrict__ found, DevStats* st,
                                                 const uint32_t* op_table, const uint2* tdesc) {
   constexpr int SPL = B / LPP;
-  constexpr int QPB = 256 / LPP;  // queries per block and iteration
+  constexpr int QL = lookup_queries_per_group<B, LPP>();
+  constexpr int GPB = 256 / LPP;   // lane groups per block
+  constexpr int QPB = GPB * QL;    // queries per block and pass
   const int lane = threadIdx.x & 63;
   const int gl = lane % LPP;
   const int gshift = lane - gl;
@@ -282,39 +293,60 @@ __global__ __launch_bounds__(256) void k_lookup(Geo g, const uint64_t* __restric
   unsigned long long probes_acc = 0, hits_acc = 0;
   for (uint64_t base = (uint64_t)blockIdx.x * QPB; base < n;
        base += (uint64_t)gridDim.x * QPB) {
-    const uint64_t q = base + threadIdx.x / LPP;
-    const bool active = q < n;
-    const uint64_t x = active ? keys[q] : kEmpty;
-    uint32_t probes = 0;
-    bool hit = false;
-    uint64_t val = 0;
-    int winner = 0;
-    if (x != kEmpty) {
-      uint32_t h[H];
-      hash_key<H, EXT>(g, tab_of(g, op_table, tdesc, q), x, h);
+    // query u of this group: base + u GPB + group index (each u a coalesced run)
+    uint64_t qv[QL], x[QL], val[QL];
+    bool active[QL], hit[QL];
+    uint32_t probes[QL], h[QL][H];
+    int winner[QL];
 #pragma unroll
-      for (int hi = 0; hi < H; ++hi) {
-        const ulonglong2* p = g.slots + (uint64_t)h[hi] * B + gl * SPL;
-        ulonglong2 sl[SPL];
+    for (int u = 0; u < QL; ++u) {
+      qv[u] = base + (uint64_t)u * GPB + threadIdx.x / LPP;
+      active[u] = qv[u] < n;
+      x[u] = active[u] ? keys[qv[u]] : kEmpty;
+      probes[u] = 0;
+      hit[u] = false;
+      val[u] = 0;
+      winner[u] = 0;
+    }
 #pragma unroll
-        for (int k = 0; k < SPL; ++k) sl[k] = p[k];
-        ++probes;
+    for (int u = 0; u < QL; ++u) {
+#pragma unroll
+      for (int hi = 0; hi < H; ++hi) h[u][hi] = 0;
+      if (x[u] != kEmpty) hash_key<H, EXT>(g, tab_of(g, op_table, tdesc, qv[u]), x[u], h[u]);
+    }
+#pragma unroll
+    for (int hi = 0; hi < H; ++hi) {
+      // the probes of hash function hi of every query not yet answered
+      bool want[QL];
+      ulonglong2 sl[QL][SPL];
+#pragma unroll
+      for (int u = 0; u < QL; ++u) {
+        want[u] = x[u] != kEmpty && !hit[u];
+        if (want[u]) {
+          const ulonglong2* p = g.slots + (uint64_t)h[u][hi] * B + gl * SPL;
+#pragma unroll
+          for (int k = 0; k < SPL; ++k) sl[u][k] = p[k];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < QL; ++u) {
+        if (!want[u]) continue;  // uniform within the query's lane group
+        ++probes[u];
         int mk = -1;
 #pragma unroll
         for (int k = SPL - 1; k >= 0; --k)
-          if (sl[k].x == x) mk = k;
+          if (sl[u][k].x == x[u]) mk = k;
         const uint64_t m = (__ballot(mk >= 0) >> gshift) & gmask;
         if (m) {
-          winner = __ffsll((unsigned long long)m) - 1;
-          if (gl == winner) {
+          winner[u] = __ffsll((unsigned long long)m) - 1;
+          if (gl == winner[u]) {
             uint64_t v = 0;
 #pragma unroll
             for (int k = 0; k < SPL; ++k)
-              if (k == mk) v = sl[k].y;
-            val = v;
+              if (k == mk) v = sl[u][k].y;
+            val[u] = v;
           }
-          hit = true;
-          break;
+          hit[u] = true;
         }
       }
     }
@@ -324,52 +356,58 @@ __global__ __launch_bounds__(256) void k_lookup(Geo g, const uint64_t* __restric
     // A wavefront whose unanswered queries are of several tables (a group)
     // searches per query group instead.
     if (EXT && g.stash_n) {
-      const bool need = x != kEmpty && !hit;
-      if (need) ++probes;
-      const uint64_t needm = __ballot(need && gl == 0);
-      if (needm) {
-        const uint32_t t = need ? table_of(op_table, q) : 0u;
-        const uint32_t t0 = __shfl(t, __ffsll((unsigned long long)needm) - 1, 64);
-        if (__ballot(need && t != t0) == 0) {
-          if (g.stash_cnt[t0]) {
-            const uint32_t sb = t0 * g.stash_n;
-            const uint64_t ek = lane < (int)g.stash_n ? g.stash[sb + lane].x : kEmpty;
-            uint64_t rem = needm, got = 0, gv = 0;
-            while (rem) {  // wavefront-uniform
-              const int l = __ffsll((unsigned long long)rem) - 1;
-              const uint64_t mm = __ballot(ek == __shfl(x, l, 64));
-              if (mm) {
-                if (lane == l) gv = g.stash[sb + __ffsll((unsigned long long)mm) - 1].y;
-                got |= 1ull << l;
+#pragma unroll
+      for (int u = 0; u < QL; ++u) {  // every lane of the wavefront takes each pass
+        const bool need = x[u] != kEmpty && !hit[u];
+        if (need) ++probes[u];
+        const uint64_t needm = __ballot(need && gl == 0);
+        if (needm) {
+          const uint32_t t = need ? table_of(op_table, qv[u]) : 0u;
+          const uint32_t t0 = __shfl(t, __ffsll((unsigned long long)needm) - 1, 64);
+          if (__ballot(need && t != t0) == 0) {
+            if (g.stash_cnt[t0]) {
+              const uint32_t sb = t0 * g.stash_n;
+              const uint64_t ek = lane < (int)g.stash_n ? g.stash[sb + lane].x : kEmpty;
+              uint64_t rem = needm, got = 0, gv = 0;
+              while (rem) {  // wavefront-uniform
+                const int l = __ffsll((unsigned long long)rem) - 1;
+                const uint64_t mm = __ballot(ek == __shfl(x[u], l, 64));
+                if (mm) {
+                  if (lane == l) gv = g.stash[sb + __ffsll((unsigned long long)mm) - 1].y;
+                  got |= 1ull << l;
+                }
+                rem &= rem - 1;
               }
-              rem &= rem - 1;
+              if ((got >> gshift) & 1ull) {  // found by this query's group leader
+                hit[u] = true;
+                winner[u] = 0;
+                if (gl == 0) val[u] = gv;
+              }
             }
-            if ((got >> gshift) & 1ull) {  // found by this query's group leader
-              hit = true;
-              winner = 0;
-              if (gl == 0) val = gv;
+          } else if (need) {
+            const uint32_t e = stash_find(g, t, x[u], gl, LPP, [&](bool p) {
+              return (uint64_t)((__ballot(p) >> gshift) & gmask);
+            });
+            if (e != kNone) {
+              hit[u] = true;
+              winner[u] = 0;
+              val[u] = g.stash[e].y;
             }
-          }
-        } else if (need) {
-          const uint32_t e = stash_find(g, t, x, gl, LPP, [&](bool p) {
-            return (uint64_t)((__ballot(p) >> gshift) & gmask);
-          });
-          if (e != kNone) {
-            hit = true;
-            winner = 0;
-            val = g.stash[e].y;
           }
         }
       }
     }
-    if (active && gl == winner) {
-      if (B == 1) ((uint32_t*)out)[q] = (uint32_t)val;
-      else ((uint64_t*)out)[q] = val;
-      found[q] = hit ? 1 : 0;
-    }
-    if (active && gl == 0) {
-      probes_acc += probes;
-      hits_acc += hit ? 1 : 0;
+#pragma unroll
+    for (int u = 0; u < QL; ++u) {
+      if (active[u] && gl == winner[u]) {
+        if (B == 1) ((uint32_t*)out)[qv[u]] = (uint32_t)val[u];
+        else ((uint64_t*)out)[qv[u]] = val[u];
+        found[qv[u]] = hit[u] ? 1 : 0;
+      }
+      if (active[u] && gl == 0) {
+        probes_acc += probes[u];
+        hits_acc += hit[u] ? 1 : 0;
+      }
     }
   }
   DevStatLine& sl = st->s[blockIdx.x % kStatStripes];
@@ -379,7 +417,8 @@ __global__ __launch_bounds__(256) void k_lookup(Geo g, const uint64_t* __restric
 template <int B, int LPP, int H>
 static void lookup_go(const Geo& g, const uint64_t* keys, uint64_t n, void* out, uint8_t* found,
                       DevStats* st, const uint32_t* op_table, const uint2* tdesc, hipStream_t s) {
-  const uint64_t blocks = (n * LPP + 255) / 256;
+  const uint64_t blocks = (n * LPP + 256 * lookup_queries_per_group<B, LPP>() - 1) /
+                          (256 * lookup_queries_per_group<B, LPP>());
   const uint32_t grid = (uint32_t)std::min<uint64_t>(blocks, 8192);
   if (g.stash_n || g.hash_bias)
     hipLaunchKernelGGL((k_lookup<B, LPP, H, true>), dim3(grid), dim3(256), 0, s, g, keys, n, out,
