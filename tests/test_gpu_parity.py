@@ -318,6 +318,35 @@ def test_lookup_parity_on_imported_table(B, d, lpp):
     assert g.stats()["lookup_probes"] == o.stats()["lookup_probes"]
 
 
+@pytest.mark.parametrize("B,d,lpp", [(8, 2, 0), (8, 2, 1), (4, 2, 0), (2, 2, 0), (2, 2, 1),
+                                     (1, 3, 0)])
+def test_lookup_ragged_counts(B, d, lpp):
+    # query counts around the lookup kernel's pass sizes (a lane group takes one
+    # or two queries per pass; 256-thread blocks; at most 8192 blocks, so the
+    # largest counts take a second, partial grid-stride pass)
+    n = 1 << 10
+    scheme = "random_walk" if B > 1 else "rattle"
+    o = oracle_table(n, B, d, scheme, seed=9, max_chain=1000)
+    keys, vals = keys_for(n, B, 0.85 if B > 1 else 0.8, seed=19)
+    o.insert(keys, vals)
+    g = gpu_table(n, B, d, scheme, seed=9)
+    g.load(o.export())
+    pool, _ = inputs.lookup_mix(21, keys, keys.size, 1 << 16, 0.5, key_seed=19)
+    lanes = B if lpp == 0 else 1
+    per_block = 256 // lanes * (2 if B // lanes <= 2 else 1)
+    counts = sorted({1, 31, 32, 33, 63, 64, 65, per_block - 1, per_block, per_block + 1,
+                     8192 * per_block + 77})
+    for c in counts:
+        print(f"lookup B={B} d={d} lpp={lpp} count={c}", flush=True)
+        q = np.resize(pool, c)
+        vg, fg = gpu_lookup(g, q, lpp)
+        vo, fo = o.lookup(q)
+        assert np.array_equal(fg, fo), c
+        assert np.array_equal(vg, vo), c
+    assert g.stats()["lookup_probes"] == o.stats()["lookup_probes"]
+    assert g.stats()["lookup_hits"] == o.stats()["lookup_hits"]
+
+
 def test_edge_cases():
     g = gpu_table(64, 2, 2, "random_walk", seed=1, max_chain=0, batch_ops=16)
     o = oracle_table(64, 2, 2, "random_walk", seed=1, max_chain=0, batch_ops=16)
