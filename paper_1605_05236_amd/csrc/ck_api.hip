@@ -286,8 +286,7 @@ ck_status alloc_scratch(ck_table* t) {
   for (auto& e : t->ctr_ready) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   HIP_TRY(dalloc(&t->dstats, 1));
   HIP_TRY(hipMemset(t->dstats, 0, sizeof(DevStats)));
-  const uint32_t nb = (m + 1023) / 1024;
-  HIP_TRY(dalloc(&t->block_tmp, ((nb + 63) & ~63u) + 16));
+  HIP_TRY(dalloc(&t->block_tmp, stats_tmp_words(m)));
   // the stash: entries, their claim words, and a count per table
   if (t->g.stash_n) {
     const size_t ns = (size_t)t->g.stash_tables * t->g.stash_n;
@@ -759,8 +758,7 @@ size_t carve_delete_scratch(unsigned char* base, uint32_t M, Scratch* x) {
   v.imv = (IMove*)take((size_t)M * kExtraInline * sizeof(IMove));
   for (int k = 0; k < 5; ++k) v.op[k] = (uint32_t*)take((size_t)M * sizeof(uint32_t));
   v.ctr = (Ctr*)take(2 * sizeof(Ctr));
-  const uint32_t nb = (M + 1023) / 1024;
-  v.block_tmp = (uint32_t*)take((((nb + 63) & ~63u) + 16) * sizeof(uint32_t));
+  v.block_tmp = (uint32_t*)take(stats_tmp_words(M) * sizeof(uint32_t));
   v.evict = v.evict_cnt = v.spawns = nullptr;
   v.arena = nullptr;
   v.arena_cap = v.spawn_cap = 0;

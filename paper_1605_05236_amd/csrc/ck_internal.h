@@ -257,6 +257,8 @@ hipError_t launch_commit(const Geo& g, const Round& r, hipStream_t s);
 // The first statistics kernel records the outcome in r.ctr->unfinished.
 hipError_t launch_batch_stats(const Round& r, uint64_t m, uint64_t slots, uint32_t* block_tmp,
                               uint32_t is_delete, const uint32_t* open, hipStream_t s);
+// 32-bit words of `block_tmp` that the statistics of a sub-batch of m ops use.
+size_t stats_tmp_words(uint64_t m);
 size_t evict_lds_bytes(const Geo& g);
 int evict_resident_per_cu(const Geo& g);
 size_t evict_wg_scratch_bytes(const Geo& g);
