@@ -40,8 +40,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 # shapes, host loop); once that source changes the benchmark reports null
 # until the counters are taken again.
 MEASURED_EVICT_TRAFFIC = {
-    "sources_sha256": "90e3608c7a20fbbe9a4c56b8d92dc3e08aad851df145cc42cd063c5f5a4a7110",
-    "bytes_per_launch": 34970257,
+    "sources_sha256": "6990d9e80d44eab54d3761f7b2d906d5d2223f92c4762c7670981d7b9d4f1d16",
+    "bytes_per_launch": 34974269,
     "profile": "profiles/evict_planners__fill95_2e24x8.md",
 }
 _SOURCES = ("ck_kernels.hip", "ck_api.hip", "ck_internal.h")
