@@ -111,6 +111,8 @@ def parse():
     p.add_argument("--tables", type=int, default=4096)
     p.add_argument("--requests", type=int, default=8192)
     p.add_argument("--per-request-sample", type=int, default=512)
+    p.add_argument("--cpu-table-stride", type=int, default=4,
+                   help="group: the all-cores oracle baseline takes every k-th table")
     p.add_argument("--group-scheme", default="queue")
     p.add_argument("--tune", action="store_true", help="autotune the group's knobs first")
     return p.parse_args()
@@ -169,6 +171,91 @@ def cpu_baseline(args, schemes):
                       f"{args.slots} slots to {args.load} ({m} inserts per scheme, same key "
                       f"stream as the GPU); then {q.size} lookups at {args.hit_rate} hits on "
                       f"the last table"}
+
+
+def group_cpu_baseline(args, bins, rs, reqs, key_seed, B):
+    """The oracle (serial mode) for many tables on every host core this
+    process may use, up to 16: one thread per core, each pinned, over a sample
+    of the tables (every --cpu-table-stride-th).  Each thread prefills its
+    tables to half load and builds their requests' keys (untimed), waits for
+    the others, then runs every request of the stream to its tables, a table's
+    ops by kind in the order the GPU runs them (lookups, deletes, inserts).
+    The oracle's C calls release the interpreter lock, so the threads run in
+    parallel; the rate is the sample's ops over the slowest thread's time."""
+    import threading
+    import torch
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import oracle
+    from paper_1605_05236_amd import inputs
+    cores = sorted(os.sched_getaffinity(0))[:16]
+    nw = len(cores)
+    stride = max(1, args.cpu_table_stride)
+    sample = [t for t in range(len(bins)) if t % stride == 0]
+    per = {t: {0: [], 1: [], 2: []} for t in sample}
+    for kind, t, rec in reqs:
+        if t in per:
+            per[t][kind].append(rec)
+    pre_start, pre = rs.prefill_records()
+    # largest tables first, dealt round robin: similar prefill and op counts per thread
+    order = sorted(sample, key=lambda t: -int(bins[t]))
+    shares = [order[w::nw] for w in range(nw)]
+    barrier = threading.Barrier(nw)
+    out = [None] * nw
+
+    def keys_of(rec):
+        k, v = inputs.keys_at_torch(key_seed, torch.from_numpy(rec))
+        return k.numpy().view(np.uint64), v.numpy().view(np.uint64)
+
+    def work(w):
+        os.sched_setaffinity(0, {cores[w]})  # this thread only
+        tabs = []
+        try:
+            for t in shares[w]:
+                o = oracle.OracleTable(int(bins[t]), B, 2, args.group_scheme, batch_ops=1,
+                                       hash_seed=105, rng_seed=205)
+                k, v = inputs.keys_values(key_seed, int(pre[t]), start=int(pre_start[t]))
+                o.insert(k, v)
+                calls = []
+                for kind in (0, 2, 1):
+                    if per[t][kind]:
+                        calls.append((kind,) + keys_of(np.concatenate(per[t][kind])))
+                tabs.append((o, calls))
+        finally:
+            barrier.wait()
+        ops = 0
+        t0 = time.perf_counter()
+        for o, calls in tabs:
+            for kind, k, v in calls:
+                if kind == 0:
+                    o.lookup(k)
+                elif kind == 2:
+                    o.delete(k)
+                else:
+                    o.insert(k, v)
+                ops += k.size
+        out[w] = (ops, time.perf_counter() - t0)
+
+    old = os.sched_getaffinity(0)
+    threads = [threading.Thread(target=work, args=(w,)) for w in range(nw)]
+    try:
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
+    finally:
+        os.sched_setaffinity(0, old)
+    if any(o is None for o in out):
+        raise RuntimeError("a baseline thread failed")
+    ops = sum(o for o, _ in out)
+    span = max(s for _, s in out)
+    cpu = _cpu_model()
+    return {"value": ops / span, "unit": "ops/s", "cores": nw, "kind": "oracle",
+            "cpu_model": cpu["model"], "host_logical_cores": cpu["logical_cores"],
+            "thread_seconds": [round(s, 4) for _, s in out],
+            "sample": f"serial oracle (g++ -O2), one thread pinned per core on {nw} cores, "
+                      f"every {stride}th table ({len(sample)} tables, "
+                      f"{int(sum(int(bins[t]) for t in sample))} bins x {B} slots) prefilled "
+                      f"to 0.5 untimed, then the stream's {ops} ops to those tables"}
 
 
 def measure_ceilings(gib=2, line_bytes=128, ops_log2=26, reps=5):
@@ -397,6 +484,10 @@ def run_group(args):
         "per_request_sample": {"requests": len(more), "ops": int(more_ops)},
         "speedup_batched_vs_per_request": batched / per_req,
     }
+    if not args.no_cpu_baseline:
+        print("# group cpu baseline (oracle, all cores)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = group_cpu_baseline(args, bins, rs, reqs[:len(reqs) - len(more)],
+                                                 seed, B)
     print(json.dumps(out), flush=True)
 
 
