@@ -576,6 +576,8 @@ def run_mixed(args):
     from paper_1605_05236_amd import inputs
     from paper_1605_05236_amd.table import CuckooTable
     torch.cuda.set_device(0)
+    if args.pmc_calibration:
+        pmc_calibration_copies()
     n, B, seed = 1 << 25, 4, 4
     step_ops = 1 << 18
     steps = args.mixed_steps
@@ -645,12 +647,19 @@ def run_mixed(args):
             dfound.add_((t.delete(dk[s]) == 1).sum())
             iok.add_((t.insert(ik[s], iv[s], diagnostics=False)["status"] == 1).sum())
 
+    p_start = _profiler_ns()
     sec = _timed(run)
+    p_end = _profiler_ns()
+    if p_start is not None and p_end is not None:
+        print(f"# profiler window ns: {p_start} {p_end}", file=sys.stderr, flush=True)
     after = t.stats()
     ops = steps * step_ops
     diff = {f: after[f] - before[f] for f in ("inserts_ok", "inserts_failed", "inserts_aborted",
                                               "retries", "delete_retries", "twin_updates",
-                                              "kicks", "rounds")}
+                                              "kicks", "rounds", "lookups", "lookup_probes")}
+    # algorithmic bytes of one step's lookup launch: key, value and found flag
+    # per query, plus one 64-byte bin line per probe
+    ppq = diff["lookup_probes"] / max(1, diff["lookups"])
     out = {
         "metric": "steady-state ops/s (lookup/insert/delete mix) with abort and retry counts",
         "value": ops / sec, "unit": "ops/s", "n_gpus": 1, "steps": steps, "warmup": 0,
@@ -667,6 +676,8 @@ def run_mixed(args):
         "aborts_per_insert": diff["inserts_aborted"] / (steps * n_ins),
         "lost_rounds_per_insert": diff["retries"] / (steps * n_ins),
         "delete_retries_per_delete": diff["delete_retries"] / (steps * n_del),
+        "lookup_probes_per_query": ppq,
+        "lookup_algorithmic_bytes_per_launch": n_look * (17 + ppq * B * 16),
     }
     print(json.dumps(out), flush=True)
 
