@@ -2201,6 +2201,14 @@ __device__ __forceinline__ void sc_increments(uint32_t* meta, const uint32_t* bi
 // Between them each wavefront lists its losers for the next round: the
 // atomic that reserves their list entries is issued before the writes and
 // its result is used after them, so its latency hides behind them.
+// Moves each commit lane fetches before it checks them (kCommitAhead) or
+// writes them (kCommitAheadApply).  Four checks in flight took the mixed
+// steady state (chains of 23 kicks on average at 97%) from 104 to 115 M
+// ops/s; prefetching writes too cost the plain kernel a wavefront per SIMD,
+// which the first rounds' one-move plans pay for.
+constexpr int kCommitAhead = 4;
+constexpr int kCommitAheadApply = 1;
+constexpr uint32_t kMvSkip = 0x100;  // beyond the 8 flag bits: no move here
 template <bool EXT>
 __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
   constexpr int CL = kCommitLanes;
@@ -2272,12 +2280,24 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
         x = r.keys[i];
         xa = ((inl || se != kNone) && r.vals) ? load_aux(r.vals, i, g.B) : 0;
         const unsigned long long me = r.tag | (unsigned long long)i;
+        // kCommitAhead moves per lane in flight: a long chain's claim checks
+        // are not one dependent load after another
         bool mine = true;
-        for (uint32_t j = gl; j < nmv; j += CL) {
-          uint32_t bin, slot, fl;
-          uint64_t k, a;
-          get(j, bin, slot, fl, k, a);
-          if (g.owner[bin] != me) mine = false;
+        for (uint32_t j0 = gl; j0 < nmv; j0 += CL * kCommitAhead) {
+          uint32_t bn[kCommitAhead];
+#pragma unroll
+          for (int u = 0; u < kCommitAhead; ++u) {
+            const uint32_t j = j0 + (uint32_t)u * CL;
+            bn[u] = kNone;
+            if (j < nmv) {
+              uint32_t slot, fl;
+              uint64_t k, a;
+              get(j, bn[u], slot, fl, k, a);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kCommitAhead; ++u)
+            if (bn[u] != kNone && g.owner[bn[u]] != me) mine = false;
         }
         if (EXT && (h0.x & kHdrKeyClaim) && leader) {  // an upsert's claim on its key's first bin
           uint32_t kb[1];
@@ -2305,31 +2325,40 @@ __global__ __launch_bounds__(256) void k_commit(Geo g, Round r) {
     // ---- apply ----
     if (live) {
       if (win) {
-        // chain written from its end backwards (Sec. 8.2 system-transaction order)
-        for (int top = (int)nmv - 1; top >= 0; top -= CL) {
-          const int j = top - gl;
-          if (j < 0) continue;
-          uint32_t bin, slot, fl;
-          uint64_t k, a;
-          get((uint32_t)j, bin, slot, fl, k, a);
-          uint32_t* mw = g.meta + bin;
-          if (fl & MV_DUPCLR) {
-            atomicAnd(mw, ~(1u << slot));
-            continue;
+        // chain written from its end backwards (Sec. 8.2 system-transaction
+        // order); each lane fetches its next kCommitAheadApply moves, then writes
+        // them in the same order
+        for (int top = (int)nmv - 1; top >= 0; top -= CL * kCommitAheadApply) {
+          uint32_t bin[kCommitAheadApply], slot[kCommitAheadApply], fl[kCommitAheadApply];
+          uint64_t k[kCommitAheadApply], a[kCommitAheadApply];
+#pragma unroll
+          for (int u = 0; u < kCommitAheadApply; ++u) {
+            const int j = top - u * CL - gl;
+            fl[u] = kMvSkip;
+            if (j >= 0) get((uint32_t)j, bin[u], slot[u], fl[u], k[u], a[u]);
           }
-          if (fl & MV_VALUE) {  // overwrite: the value word only
-            unsigned long long* vw = &g.slots[(uint64_t)bin * g.B + slot].y;
-            if (g.B == 1) *(uint32_t*)vw = (uint32_t)a;  // the rattle counter above stays
-            else *vw = a;
-          } else if (!(fl & MV_SUPERSEDED)) {
-            g.slots[(uint64_t)bin * g.B + slot] =
-                (fl & MV_CLEAR) ? make_ulonglong2(kEmpty, 0ull) : make_ulonglong2(k, a);
-            if (g.ghost) {
-              if (fl & MV_DUP) atomicOr(mw, 1u << slot);
-              else atomicAnd(mw, ~(1u << slot));
+#pragma unroll
+          for (int u = 0; u < kCommitAheadApply; ++u) {
+            if (fl[u] & kMvSkip) continue;
+            uint32_t* mw = g.meta + bin[u];
+            if (fl[u] & MV_DUPCLR) {
+              atomicAnd(mw, ~(1u << slot[u]));
+              continue;
             }
+            if (fl[u] & MV_VALUE) {  // overwrite: the value word only
+              unsigned long long* vw = &g.slots[(uint64_t)bin[u] * g.B + slot[u]].y;
+              if (g.B == 1) *(uint32_t*)vw = (uint32_t)a[u];  // the rattle counter above stays
+              else *vw = a[u];
+            } else if (!(fl[u] & MV_SUPERSEDED)) {
+              g.slots[(uint64_t)bin[u] * g.B + slot[u]] =
+                  (fl[u] & MV_CLEAR) ? make_ulonglong2(kEmpty, 0ull) : make_ulonglong2(k[u], a[u]);
+              if (g.ghost) {
+                if (fl[u] & MV_DUP) atomicOr(mw, 1u << slot[u]);
+                else atomicAnd(mw, ~(1u << slot[u]));
+              }
+            }
+            if (fl[u] & MV_HC) atomicAdd(mw, 1u << 24);
           }
-          if (fl & MV_HC) atomicAdd(mw, 1u << 24);
         }
         if (EXT && se != kNone && leader) {  // the stash entry: cleared, a new value, or the key
           ulonglong2* e = g.stash + se;
