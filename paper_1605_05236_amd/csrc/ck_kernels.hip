@@ -824,8 +824,14 @@ __device__ __forceinline__ uint32_t region_take(uint32_t* win, uint32_t n, Ctr* 
 
 // A walk's move log: entries < kWalkLdsLog in LDS, the rest in scratch, and
 // a filter of the bins it wrote (one bit per bin hash; a view of a bin whose
-// bit is clear has nothing to overlay).
-constexpr uint32_t kWalkMapWords = 64;  // 2048 bits
+// bit is clear has nothing to overlay).  2048 bits, or 8192 for random
+// kicking in single-slot bins, whose walks run to a thousand kicks: there a
+// filter half full sent every other view through a scan of the whole log.
+constexpr uint32_t kWalkMapWords = 64;       // 2048 bits
+constexpr uint32_t kWalkMapWordsLong = 256;  // 8192 bits
+__host__ __device__ __forceinline__ uint32_t walk_map_words(const Geo& g) {
+  return (g.scheme == CK_RANDOM_WALK && g.B == 1) ? kWalkMapWordsLong : kWalkMapWords;
+}
 struct WalkLog {
   uint64_t* key;    // LDS, kWalkLdsLog each
   uint64_t* aux;
@@ -833,7 +839,8 @@ struct WalkLog {
   uint32_t* sf;     // slot | flags << 8
   int* last;        // LDS [8]
   uint32_t* misc;   // LDS [8]: 0 hc adds
-  uint32_t* wmap;   // LDS [kWalkMapWords]
+  uint32_t* wmap;   // LDS [walk_map_words]
+  uint32_t mshift;  // 32 - log2(filter bits)
   uint64_t* gkey;   // scratch, indexed from 0 (entries < kWalkLdsLog unused)
   uint64_t* gaux;
   uint32_t* gbin;
@@ -842,7 +849,7 @@ struct WalkLog {
   __device__ __forceinline__ uint64_t& a(uint32_t j) const { return j < kWalkLdsLog ? aux[j] : gaux[j]; }
   __device__ __forceinline__ uint32_t& b(uint32_t j) const { return j < kWalkLdsLog ? bin[j] : gbin[j]; }
   __device__ __forceinline__ uint32_t& f(uint32_t j) const { return j < kWalkLdsLog ? sf[j] : gsf[j]; }
-  __device__ static __forceinline__ uint32_t mbit(uint32_t b) { return (b * 0x9E3779B1u) >> 21; }
+  __device__ __forceinline__ uint32_t mbit(uint32_t b) const { return (b * 0x9E3779B1u) >> mshift; }
   __device__ __forceinline__ bool maybe_written(uint32_t b) const {
     const uint32_t h = mbit(b);
     return (wmap[h >> 5] >> (h & 31)) & 1u;
@@ -1126,8 +1133,8 @@ struct WalkPlanner {
   }
 };
 
-__host__ __device__ constexpr size_t walk_group_lds_bytes() {
-  return kWalkLdsLog * 24 + 16 * 4 + kWalkMapWords * 4;
+__host__ __device__ inline size_t walk_group_lds_bytes(const Geo& g) {
+  return kWalkLdsLog * 24 + 16 * 4 + walk_map_words(g) * 4;
 }
 static size_t walk_group_scratch_bytes(const Geo& g) {
   return ((size_t)(g.max_chain + 8) * 24 + 255) & ~(size_t)255;
@@ -1143,9 +1150,10 @@ __global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
   const int lane = threadIdx.x;
   const int gi = lane / W;
   const uint32_t cap = g.max_chain + 8;
+  const uint32_t mwords = walk_map_words(g);
   WalkLog L;
   {
-    char* base = (char*)lds64 + (size_t)gi * walk_group_lds_bytes();
+    char* base = (char*)lds64 + (size_t)gi * walk_group_lds_bytes(g);
     L.key = (uint64_t*)base;
     L.aux = L.key + kWalkLdsLog;
     L.bin = (uint32_t*)(L.aux + kWalkLdsLog);
@@ -1153,6 +1161,7 @@ __global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
     L.last = (int*)(L.sf + kWalkLdsLog);
     L.misc = (uint32_t*)(L.last + 8);
     L.wmap = L.misc + 8;
+    L.mshift = mwords == kWalkMapWordsLong ? 19u : 21u;
     char* sc = (char*)r.wg_scratch + (size_t)blockIdx.x * r.wg_scratch_bytes +
                (size_t)gi * (r.wg_scratch_bytes / P);
     L.gkey = (uint64_t*)sc;
@@ -1187,7 +1196,7 @@ __global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
     const uint64_t x = x_nx;
     i_nx = batch_item(kb + P);
     if (i_nx != kNone) x_nx = r.keys[i_nx];
-    for (uint32_t j = lane % W; j < kWalkMapWords; j += W) L.wmap[j] = 0;
+    for (uint32_t j = lane % W; j < mwords; j += W) L.wmap[j] = 0;
     wave_sync();
     if (i != kNone) {
       const uint64_t xa = load_aux(r.vals, i, B);
@@ -1964,7 +1973,7 @@ static bool is_search(uint32_t scheme) {
 size_t evict_lds_bytes(const Geo& g) {
   if (is_search(g.scheme))
     return (64 / kSearchW) * search_group_lds_words() * 4 + 64;
-  return (64 / kWalkW) * walk_group_lds_bytes() + 64;
+  return (64 / kWalkW) * walk_group_lds_bytes(g) + 64;
 }
 
 size_t evict_wg_scratch_bytes(const Geo& g) {
