@@ -112,6 +112,10 @@ struct ck_table {
   uint32_t tail_hint = 2;
   uint32_t tail_prev = 2;
   uint32_t tail_hint_del = 1;
+  // upserts keep their own history: their key claims make them take more
+  // rounds than the table's plain inserts
+  uint32_t tail_hint_ups = 2;
+  uint32_t tail_prev_ups = 2;
   // host-side counters
   uint64_t rounds = 0, lookups = 0;
   Timer timer;
@@ -461,10 +465,18 @@ ck_status settle(ck_table* t, Flight& f, hipStream_t s, bool* done) {
   }
   *done = c.done != 0;
   if (*done) {
-    if (!f.r.is_delete) t->rounds += c.rounds;
-    if (!f.r.is_delete) t->tail_prev = t->tail_hint;
-    (f.r.is_delete ? t->tail_hint_del : t->tail_hint) =
-        std::min(kMaxTailHint, std::max<uint32_t>(1, c.rounds));
+    const uint32_t hint = std::min(kMaxTailHint, std::max<uint32_t>(1, c.rounds));
+    if (f.r.is_delete) {
+      t->tail_hint_del = hint;
+    } else if (f.r.upsert) {
+      t->rounds += c.rounds;
+      t->tail_prev_ups = t->tail_hint_ups;
+      t->tail_hint_ups = hint;
+    } else {
+      t->rounds += c.rounds;
+      t->tail_prev = t->tail_hint;
+      t->tail_hint = hint;
+    }
   }
   return CK_OK;
 }
@@ -509,10 +521,10 @@ ck_status run_batches(ck_table* t, const uint64_t* keys, const void* vals, uint6
     f.guard = 2 * m + 64;
     f.live = true;
     set ^= 1;
-    const uint32_t K = t->opt.enqueue_rounds
-                           ? t->opt.enqueue_rounds
-                           : (is_delete ? t->tail_hint_del + 1
-                                        : std::max(t->tail_hint, t->tail_prev));
+    const uint32_t K = t->opt.enqueue_rounds ? t->opt.enqueue_rounds
+                       : is_delete           ? t->tail_hint_del + 1
+                       : upsert              ? std::max(t->tail_hint_ups, t->tail_prev_ups)
+                                             : std::max(t->tail_hint, t->tail_prev);
     const uint32_t* gate = prev.live ? &x.ctr[prev.set].unfinished : nullptr;
     ck_status st = enqueue_rounds(t, f, K, true, gate, s);
     if (st != CK_OK) return st;
