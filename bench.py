@@ -1140,12 +1140,12 @@ def main():
         cum[s] = st[s]["views"] / max(1, st[s]["inserts_ok"] + st[s]["inserts_failed"])
         fails[s] = st[s]["inserts_failed"]
     # The whole insert path against the HBM roofline, under two byte models.
-    # Survey model (the primary figure): per insert 17 bytes of key, value and
+    # Line model (the primary figure): per insert 17 bytes of key, value and
     # status; V bins viewed, each a whole line L; V_m of them also read the
     # bin's metadata word, counted as a 64-byte line (sorted search and the
     # hybrid read spawn counts, queue-kicking hit counters, ghosts duplicate
     # marks); W = kicks + 1 bins written, each a line and its metadata line.
-    # Line-and-word model (the first one reported): a view is a line and a
+    # Line-and-word model (the secondary figure): a view is a line and a
     # 4-byte word, a write a 16-byte slot and an 8-byte claim word.
     L = B * 16
 
@@ -1198,7 +1198,7 @@ def main():
     else:
         # eviction planners: a bin viewed is one bin line (L bytes) and, for the
         # schemes that read it, the bin's metadata word counted as a 64-byte
-        # line (survey model, the primary figure); the line-and-word model
+        # line (the line model, the primary figure); the line-and-word model
         # counts the word as 4 bytes.  A launch's bytes are its plans' views.
         alg = sum(v * (L + (64 if reads_meta(s) else 0)) for s, v in views_by.items())
         alg_lw = evict_views * (L + 4)
