@@ -829,6 +829,10 @@ __device__ __forceinline__ uint32_t region_take(uint32_t* win, uint32_t n, Ctr* 
 // filter half full sent every other view through a scan of the whole log.
 constexpr uint32_t kWalkMapWords = 64;       // 2048 bits
 constexpr uint32_t kWalkMapWordsLong = 256;  // 8192 bits
+// Those long walks also keep a second filter of 65536 bits (another hash of
+// the bin) in their scratch, read only when the first one's bit is set: a
+// whole-log scan then happens about once in 500 views instead of once in 8.
+constexpr uint32_t kWalkMap2Words = 2048;
 __host__ __device__ __forceinline__ uint32_t walk_map_words(const Geo& g) {
   return (g.scheme == CK_RANDOM_WALK && g.B == 1) ? kWalkMapWordsLong : kWalkMapWords;
 }
@@ -841,6 +845,7 @@ struct WalkLog {
   uint32_t* misc;   // LDS [8]: 0 hc adds
   uint32_t* wmap;   // LDS [walk_map_words]
   uint32_t mshift;  // 32 - log2(filter bits)
+  uint32_t* gmap2;  // scratch [kWalkMap2Words], the second filter, or null
   uint64_t* gkey;   // scratch, indexed from 0 (entries < kWalkLdsLog unused)
   uint64_t* gaux;
   uint32_t* gbin;
@@ -850,13 +855,21 @@ struct WalkLog {
   __device__ __forceinline__ uint32_t& b(uint32_t j) const { return j < kWalkLdsLog ? bin[j] : gbin[j]; }
   __device__ __forceinline__ uint32_t& f(uint32_t j) const { return j < kWalkLdsLog ? sf[j] : gsf[j]; }
   __device__ __forceinline__ uint32_t mbit(uint32_t b) const { return (b * 0x9E3779B1u) >> mshift; }
+  __device__ static __forceinline__ uint32_t mbit2(uint32_t b) { return (b * 0x85EBCA6Bu) >> 16; }
   __device__ __forceinline__ bool maybe_written(uint32_t b) const {
     const uint32_t h = mbit(b);
-    return (wmap[h >> 5] >> (h & 31)) & 1u;
+    if (!((wmap[h >> 5] >> (h & 31)) & 1u)) return false;
+    if (!gmap2) return true;
+    const uint32_t h2 = mbit2(b);
+    return (gmap2[h2 >> 5] >> (h2 & 31)) & 1u;
   }
   __device__ __forceinline__ void mark(uint32_t b) const {  // one lane
     const uint32_t h = mbit(b);
     wmap[h >> 5] |= 1u << (h & 31);
+    if (gmap2) {
+      const uint32_t h2 = mbit2(b);
+      atomicOr(&gmap2[h2 >> 5], 1u << (h2 & 31));
+    }
   }
 };
 
@@ -1137,7 +1150,8 @@ __host__ __device__ inline size_t walk_group_lds_bytes(const Geo& g) {
   return kWalkLdsLog * 24 + 16 * 4 + walk_map_words(g) * 4;
 }
 static size_t walk_group_scratch_bytes(const Geo& g) {
-  return ((size_t)(g.max_chain + 8) * 24 + 255) & ~(size_t)255;
+  const size_t map2 = walk_map_words(g) == kWalkMapWordsLong ? kWalkMap2Words * 4 : 0;
+  return ((size_t)(g.max_chain + 8) * 24 + map2 + 255) & ~(size_t)255;
 }
 
 template <int B, int H, bool EXT>
@@ -1168,6 +1182,7 @@ __global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
     L.gaux = L.gkey + cap;
     L.gbin = (uint32_t*)(L.gaux + cap);
     L.gsf = L.gbin + cap;
+    L.gmap2 = mwords == kWalkMapWordsLong ? L.gsf + cap : nullptr;
   }
   if (lane == 0) {
     region_init(win, r.arena_cap);
@@ -1197,6 +1212,8 @@ __global__ __launch_bounds__(64) void k_plan_walk(Geo g, Round r) {
     i_nx = batch_item(kb + P);
     if (i_nx != kNone) x_nx = r.keys[i_nx];
     for (uint32_t j = lane % W; j < mwords; j += W) L.wmap[j] = 0;
+    if (L.gmap2)
+      for (uint32_t j = lane % W; j < kWalkMap2Words; j += W) L.gmap2[j] = 0;
     wave_sync();
     if (i != kNone) {
       const uint64_t xa = load_aux(r.vals, i, B);
