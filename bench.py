@@ -40,8 +40,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 # shapes, host loop); once that source changes the benchmark reports null
 # until the counters are taken again.
 MEASURED_EVICT_TRAFFIC = {
-    "sources_sha256": "7078f7cb2624d463fd77d2855dcfa5de561e10a1b0a2f76dd7054608f1929257",
-    "bytes_per_launch": 34970877,
+    "sources_sha256": "f6f24c022b8b0bef9d2f3e10bab2d3ab49f32bb69b82d03505a0be48b6d0edbe",
+    "bytes_per_launch": 35111708,
     "profile": "profiles/evict_planners__fill95_2e24x8.md",
 }
 _SOURCES = ("ck_kernels.hip", "ck_api.hip", "ck_internal.h")
