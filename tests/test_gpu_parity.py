@@ -21,6 +21,7 @@ GEOMS = [
     ("random_walk", 4, 2, True, False),
     ("random_walk", 8, 2, False, True),
     ("random_walk", 2, 2, False, False),
+    ("random_walk", 1, 2, False, False),
     ("random_walk", 1, 3, False, False),
     ("random_walk", 1, 4, False, False),
     ("bfs", 4, 2, False, False),
@@ -71,7 +72,7 @@ def test_fill_parity(geom, batch):
     assert f.all() and np.array_equal(v, vals[ok])
 
 
-MIXED = [GEOMS[i] for i in (0, 1, 4, 6, 9, 11, 13, 14, 17, 20)]
+MIXED = [GEOMS[i] for i in (0, 1, 5, 7, 10, 12, 14, 15, 18, 21)]
 
 
 @pytest.mark.parametrize("geom", MIXED, ids=ident)
@@ -372,7 +373,7 @@ def test_edge_cases():
     assert_same_image(g.export(), o.export(), "after empty calls")
 
 
-@pytest.mark.parametrize("geom", [GEOMS[i] for i in (1, 4, 6, 10, 14, 17, 19)], ids=ident)
+@pytest.mark.parametrize("geom", [GEOMS[i] for i in (1, 5, 7, 11, 15, 18, 20)], ids=ident)
 @pytest.mark.parametrize("depth", [1, 3])
 def test_enqueue_depth_parity(geom, depth):
     """How many rounds the host enqueues per sub-batch before it looks at the
