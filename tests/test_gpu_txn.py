@@ -9,6 +9,7 @@ import pytest
 
 from gpu_util import assert_same_image, assert_same_stats, gpu_insert, gpu_table, keys_for, \
     oracle_table, to_dev
+from paper_1605_05236_amd import inputs
 from test_oracle_txn import replay, table_dict, workload
 
 pytestmark = pytest.mark.gpu
@@ -55,6 +56,44 @@ def test_transactions_parity(case, batch):
     assert table_dict(o) == d
     if batch > 1:
         assert (o.stats()["rounds"] > 4)
+
+
+def bench_like_workload(seed, n_txn, stored, ops=16):
+    """Transactions shaped like the transaction benchmark's: `ops` ops each,
+    inserts : deletes : overwrites : reads = 2:1:2:2, inserts of fresh keys,
+    the other kinds on keys drawn uniformly from `stored` (present or, once
+    deleted, absent)."""
+    rng = np.random.default_rng(seed)
+    m = n_txn * ops
+    kinds = rng.choice(np.array([1, 1, 2, 3, 3, 0, 0], np.uint8), m)
+    fresh, fvals = inputs.keys_values(seed + 1000, int((kinds == 1).sum()))
+    keys = stored[rng.integers(0, stored.size, m)]
+    keys[kinds == 1] = fresh
+    vals = rng.integers(0, 1 << 63, m, dtype=np.uint64)
+    vals[kinds == 1] = fvals
+    off = np.arange(0, m + 1, ops, dtype=np.uint64)
+    return kinds, keys, vals, off
+
+
+def test_transactions_at_the_benchmark_call_shape():
+    """2^14 transactions of 16 ops in one call (one sub-batch of the per-call
+    cap), random kicking with load balancing on 8-slot bins prefilled to half
+    load: the shape the transaction benchmark runs, on a smaller table (the
+    oracle takes about 20 s)."""
+    n, B = 1 << 19, 8
+    kw = dict(load_balance=True, batch_ops=1 << 14, max_chain=500)
+    g = gpu_table(n, B, 2, "random_walk", seed=87, **kw)
+    o = oracle_table(n, B, 2, "random_walk", seed=87, **kw)
+    pk, pv = keys_for(n, B, 0.5, seed=187)
+    assert np.array_equal(gpu_insert(g, pk, pv)["status"], o.insert(pk, pv)["status"])
+    kinds, keys, vals, off = bench_like_workload(88, 1 << 14, pk)
+    print(f"transactions at call shape: {off.size - 1} transactions, {keys.size} ops", flush=True)
+    ro = run_both(g, o, kinds, keys, vals, off)
+    d = replay(kinds, keys, vals, off, ro, 1 << 14, dict(zip(pk.tolist(), pv.tolist())))
+    assert_same_image(g.export(), o.export(), "call shape")
+    assert_same_stats(g.stats(), o.stats(), "call shape")
+    assert table_dict(o) == d
+    assert (ro["round"] > 0).any()  # some transactions lost rounds to others
 
 
 def test_transactions_abort_paths_parity():
