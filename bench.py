@@ -704,10 +704,18 @@ def run_dary(args):
             t = CuckooTable(n, 1, d, scheme, max_chain=1000, batch_ops=1 << 20, hash_seed=103,
                             rng_seed=203)
             done, out = 0, {}
+            st0 = t.stats()
             for load in loads:
                 m = inputs.target_count(n, 1, load)
                 sec = _timed(lambda: t.insert(keys[done:m], vals[done:m], diagnostics=False))
                 st = t.stats()
+                # d-ary byte model: 17 bytes in and out per insert, plus one
+                # access granule per bin viewed and per bin written (kicks + 1);
+                # G = 64 bytes, the line a 16-byte slot access fetches
+                v_leg = st["views"] - st0["views"]
+                w_leg = (st["kicks"] - st0["kicks"]) + (st["inserts_ok"] - st0["inserts_ok"])
+                alg = 17 * (m - done) + 64 * (v_leg + w_leg)
+                st0 = st
                 bands = st["band_inserts"].astype(np.float64)
                 bv = st["band_views"].astype(np.float64)
                 top = int(np.floor(load * 200 - 1e-9))  # the band just below `load`
@@ -717,7 +725,12 @@ def run_dary(args):
                     "bins_viewed_per_insert_cumulative": float(st["views"] / max(st["inserts_ok"]
                                                                               + st["inserts_failed"], 1)),
                     "failed_inserts": st["inserts_failed"], "stored": st["stored"],
-                    "rounds": st["rounds"], "lost_rounds": st["retries"]}
+                    "rounds": st["rounds"], "lost_rounds": st["retries"],
+                    "algorithmic_bytes_per_insert": alg / max(m - done, 1),
+                    "roofline": {"bound": "hbm", "achieved": alg / sec / 1e9,
+                                 "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                 "frac": alg / sec / 1e9 / PEAK_HBM_GBS,
+                                 "model": "17 + 64 (V + W) per insert, G = 64"}}
                 total_ins += m - done
                 total_s += sec
                 done = m
